@@ -1,0 +1,174 @@
+/*
+ * hk -- smallest eigenvalue of the Hankel moment matrix
+ *           M_ij = (1/beta) Gamma((1+i+j)/beta),  i, j = 0..N-1,
+ * by a fixed-point LDL^T factorisation of M - xI on an AMD MI355X (gfx950).
+ *
+ * Method (Emmart, Weems, Chen, "Computing the smallest eigenvalue of large
+ * ill-conditioned Hankel matrices"):
+ *   - the matrix definition is the paper's Introduction; M is the moment
+ *     matrix of exp(-x^beta) on [0, inf) ("Properties of M"), hence SPD with
+ *     distinct eigenvalues;
+ *   - the factorisation is the submatrix-order LDL^T of "The LDL^T
+ *     Determinant Algorithm": M entries carry K fractional bits, the
+ *     extracted column C and the quotient L = C / diag carry K/2;
+ *   - lambda_1 is the smallest root of P(x) = det(M - xI) ("The Secant
+ *     Algorithm"), checked by the sign test of "Interval Verification";
+ *   - inverse iteration on one factorisation is offered as the default
+ *     driver (not in the paper).
+ *
+ * Conventions for every entry point
+ *   - extern "C", never throws; returns hk_status (HK_OK = 0).  On error a
+ *     message is available from hk_last_error() (thread-local).
+ *   - K = prec_bits must be even and >= 64 (K/2 must be integral).
+ *   - beta = num/den with num, den >= 1 (reduced internally).
+ *   - Device memory is owned by the caller.  dev_ws is one device buffer of
+ *     at least hk_workspace_bytes(...) bytes; the library carves it up and
+ *     never allocates or frees device memory itself.  hk_matrix handles own
+ *     only host memory and must be released with hk_matrix_destroy.
+ *   - Every device operation is enqueued on the caller's stream s; calls
+ *     that return results to the host synchronise that stream.
+ *   - Big integers cross the boundary in one of two plain formats:
+ *       hk_mpf      : value = sign * sum_i digits[i] 2^(32 i) * 2^exp2;
+ *       "int lists" : arrays (slen[n], off[n], dig[]): entry i has |slen[i]|
+ *                     base-2^32 digits dig[off[i] ..], little endian, its
+ *                     sign is the sign of slen[i] (slen 0 = zero).
+ */
+#ifndef HK_H
+#define HK_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { int64_t num, den; } hk_rational;
+
+typedef struct {
+  int32_t sign;            /* -1, 0, +1 */
+  int32_t ndigits;         /* number of base-2^32 digits */
+  int64_t exp2;            /* binary exponent of digit 0 */
+  const uint32_t* digits;  /* host memory, little endian */
+} hk_mpf;
+
+typedef enum {
+  HK_OK = 0,
+  HK_EINVAL = 1,      /* bad argument (sizes, K odd, beta <= 0, short ws)   */
+  HK_ENOTSPD = 2,     /* pivot <= 0 before the last column                  */
+  HK_EPRECISION = 3,  /* precision exhausted (iteration stalled, overflow)  */
+  HK_ENOCONV = 4,     /* iteration limit reached                            */
+  HK_EVERIFY = 5,     /* inertia bracket failed                             */
+  HK_EDEVICE = 6,     /* HIP runtime error                                  */
+  HK_ENOMEM = 7       /* host allocation failed                             */
+} hk_status;
+
+enum { HK_INVERSE = 0, HK_SECANT = 1 };
+
+typedef struct hk_matrix_s* hk_matrix;
+
+typedef struct {
+  int N, K, h;            /* size, fractional bits of M, of C and L            */
+  int digit_bits;         /* device digit radix 2^digit_bits (29)             */
+  int max_col_digits;     /* widest column of the working triangle            */
+  int vec_digits;         /* digits per entry of a device vector              */
+  int solve_guard_bits;   /* extra fractional bits of the solve vectors       */
+  int panel;              /* columns per trailing update (rank of the update) */
+  size_t ws_bytes;        /* bytes of workspace in use                        */
+  size_t vec_bytes;       /* bytes of one device vector (hk_solve operands)   */
+  int n_update_launches;  /* trailing-update launches of the last hk_factor   */
+  double update_ms;       /* summed device time of those launches (timing on) */
+} hk_info;
+
+typedef struct {
+  hk_status status;
+  int bits_used;          /* K of the accepted run                            */
+  int factorizations;     /* LDL^T factorisations performed                   */
+  int solves;             /* hk_solve calls (inverse iteration)               */
+  int verified;           /* 1 if the inertia bracket held                    */
+  int digits_verified;    /* significant digits of the verified bracket       */
+  char lambda_dec[192];   /* lambda_1 in decimal scientific notation          */
+  double limb_macs;       /* algorithmic 32-bit limb MACs, all factorisations */
+  double t_factor_s, t_solve_s, t_total_s;
+} hk_report;
+
+/* Bytes of device workspace needed for (N, beta, K).  flags: reserved, 0.
+   Returns 0 for invalid arguments. */
+size_t hk_workspace_bytes(int N, hk_rational beta, int prec_bits, int flags);
+
+/* Computes the 2N-1 moments X_n = RNE(2^K mu_n), mu_n = (1/beta)
+   Gamma((n+1)/beta) (Introduction: the matrix definition), correctly rounded
+   (round to nearest, ties to even), and uploads them to dev_ws.  The matrix
+   itself is expanded from them at every hk_factor.  On success *out is a new
+   handle bound to dev_ws (which must stay alive until hk_matrix_destroy). */
+hk_status hk_build_matrix(int N, hk_rational beta, int prec_bits, void* dev_ws,
+                          size_t ws_bytes, hipStream_t s, hk_matrix* out);
+
+/* LDL^T of M - xI, x = shift (a dyadic with at most K fractional bits),
+   in the paper's submatrix order and fixed-point format ("The LDL^T
+   Determinant Algorithm"; parallel variant's formats): for each column pc,
+     C_pc[r] = RNE(A_{r,pc} / 2^h)   r >= pc,   d_pc = C_pc[pc],
+     L_pc[r] = RNE(C_pc[r] 2^h / d_pc)          r > pc,
+     A_{rc} -= C_pc[c] L_pc[r]  (exact)         pc < c <= r.
+   The factors stay in dev_ws.  inertia_mode = 0: a pivot <= 0 before the
+   last column returns HK_ENOTSPD with *first_bad_col set.  inertia_mode = 1:
+   returns HK_OK when only the last pivot is <= 0 and reports *n_negative
+   (Sylvester's inertia, used by the verification); a non-positive pivot
+   earlier still returns HK_ENOTSPD (the fixed widths hold only while the
+   trailing block is positive definite).  n_negative / first_bad_col may be
+   NULL.  Synchronises s. */
+hk_status hk_factor(hk_matrix m, hk_mpf shift, int inertia_mode, hipStream_t s,
+                    int* n_negative, int* first_bad_col);
+
+/* x = (L D L^T)^{-1} b on the current factorisation: dev_rhs holds b with K
+   fractional bits, dev_x receives x with K + g fractional bits (g =
+   hk_info.solve_guard_bits).  Forward, diagonal and backward steps each
+   round once per entry (RNE) after exact inner products.  Both operands are
+   device vectors of hk_info.vec_bytes bytes in the library's layout (fill
+   and read them with hk_vec_import / hk_vec_export).  Does not synchronise. */
+hk_status hk_solve(hk_matrix factored, const void* dev_rhs, void* dev_x, hipStream_t s);
+
+/* The full method: build, factor, iterate (HK_INVERSE: inverse iteration on
+   one factorisation at shift_hint or 0; HK_SECANT: the paper's Secant
+   iteration), then the inertia bracket at `digits` significant digits.
+   lambda_1 is written to out_decimal (scientific notation, `digits`
+   digits).  rep may be NULL. */
+hk_status hk_smallest_eig(int N, hk_rational beta, int prec_bits, int method, int digits,
+                          const hk_mpf* shift_hint, void* dev_ws, size_t ws_bytes,
+                          hipStream_t s, char* out_decimal, size_t out_len, hk_report* rep);
+
+hk_status hk_matrix_destroy(hk_matrix m);
+const char* hk_last_error(void);
+hk_status hk_matrix_info(hk_matrix m, hk_info* out);
+
+/* Tuning: columns per trailing update (panel width, >= 1). */
+hk_status hk_set_panel(hk_matrix m, int panel);
+/* Timing: when on, every trailing-update launch of hk_factor is bracketed by
+   HIP events on s and hk_info reports their count and summed duration. */
+hk_status hk_set_timing(hk_matrix m, int on);
+
+/* Copies factor entries of columns [c0, c1) to the host as int lists.
+   kind 0: C_pc[r], r = pc..N-1;  kind 1: L_pc[r], r = pc+1..N-1;
+   kind 2: pivots d_pc.  Values carry h fractional bits.  Call with
+   dig == NULL to get the number of digits needed (return value); the
+   number of entries is implied by (kind, c0, c1).  Returns -1 on error. */
+int64_t hk_factor_export(hk_matrix m, int kind, int c0, int c1, int32_t* slen,
+                         int64_t* off, uint32_t* dig, int64_t dig_cap, hipStream_t s);
+
+/* Algorithmic work of the last factorisation: sum over updates of
+   ceil(bits(C)/32) * ceil(bits(L)/32) (schoolbook 32-bit limb MACs).
+   Launches a small counting kernel and synchronises s. */
+hk_status hk_factor_limb_macs(hk_matrix m, hipStream_t s, double* limb_macs);
+
+/* Device vectors (N entries) <-> int lists.  Import expects values with K
+   fractional bits; export returns the stored fixed-point integers. */
+hk_status hk_vec_import(hk_matrix m, int n, const int32_t* slen, const int64_t* off,
+                        const uint32_t* dig, void* dev_vec, hipStream_t s);
+int64_t hk_vec_export(hk_matrix m, const void* dev_vec, int n, int32_t* slen, int64_t* off,
+                      uint32_t* dig, int64_t dig_cap, hipStream_t s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HK_H */

@@ -1,0 +1,7 @@
+"""MI355X-native smallest eigenvalue of ill-conditioned Hankel moment matrices.
+
+The compute path is libhk.so (HIP kernels for gfx950 behind the C-ABI in
+include/hk.h); this package only binds it.  See hk.py.
+"""
+from .hk import (HK_INVERSE, HK_SECANT, EXPORTS, HKError, Matrix, lib, smallest_eig,  # noqa: F401
+                 workspace_bytes)

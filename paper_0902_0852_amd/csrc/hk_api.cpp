@@ -1,0 +1,403 @@
+// C-ABI of the hk library: workspace planning, matrix build, factorisation,
+// solves, export and the eigenvalue drivers.  See include/hk.h for the
+// contract of every entry point.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "hk_internal.hpp"
+
+using namespace hk;
+
+namespace hk {
+thread_local std::string g_err;
+static hk_status fail(hk_status st, const std::string& msg) { g_err = msg; return st; }
+#define HK_HIP(call)                                                                         \
+  do {                                                                                       \
+    hipError_t e_ = (call);                                                                  \
+    if (e_ != hipSuccess) return fail(HK_EDEVICE, std::string(#call ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+static int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+bool make_plan(int N, int64_t bnum, int64_t bden, int K, Plan& P, std::string& err) {
+  if (N < 1 || N > 100000) { err = "N out of range"; return false; }
+  if (K < 64 || (K & 1) || K > (1 << 22)) { err = "prec_bits must be even and >= 64"; return false; }
+  if (!reduce_beta(bnum, bden, &P.p, &P.q)) { err = "beta must be num/den with num, den >= 1"; return false; }
+  P.N = N; P.K = K; P.h = K / 2;
+  const int nX = 2 * N - 1;
+  std::vector<int64_t> bX(nX);
+  int64_t bmax = 0;
+  for (int n = 0; n < nX; n++) {
+    double l = log2_mu(n, P.p, P.q);
+    int64_t b = (int64_t)K + (int64_t)std::ceil(l + 1e-9 * std::fabs(l)) + 2;
+    bX[n] = std::max<int64_t>(b, 1);
+    bmax = std::max(bmax, bX[n]);
+  }
+  P.WX = (int)((bmax + 1 + DB - 1) / DB) + 1;
+  // suffix max of the diagonal sizes
+  std::vector<int64_t> sufmax(N + 1, 0);
+  for (int r = N - 1; r >= 0; r--) sufmax[r] = std::max(sufmax[r + 1], bX[2 * r]);
+  P.cols.resize(N);
+  P.itemStart.assign(N + 1, 0);
+  int64_t a = 0, kk = 0, cc = 0, ll = 0, dd = 0;
+  P.maxW = 0;
+  for (int c = 0; c < N; c++) {
+    ColInfo& ci = P.cols[c];
+    // |A_rc| <= sqrt(A_rr A_cc) while the trailing block is positive definite
+    int64_t Bc = (sufmax[c] + bX[2 * c] + 1) / 2 + 4;
+    int W = round_up((int)((Bc + DB - 1) / DB) + 4, WB);
+    ci.W = W;
+    ci.R = round_up(N - c, 64);
+    ci.nb = W / WB;
+    ci.CW = W + WB;
+    ci.LW = W + 2 * WB;
+    ci.items = (ci.R / 64) * ci.nb;
+    ci.aoff = a; a += (int64_t)W * ci.R;
+    ci.koff = kk; kk += (int64_t)2 * ci.nb * ci.R;
+    ci.coff = cc; cc += (int64_t)(N - c) * ci.CW;
+    ci.soff = ci.coff;
+    ci.loff = ll; ll += (int64_t)ci.LW * ci.R;
+    ci.doff = dd; dd += W + 2;
+    P.itemStart[c + 1] = P.itemStart[c] + ci.items;
+    P.maxW = std::max(P.maxW, W);
+  }
+  if ((int64_t)P.itemStart[N] >= (int64_t)INT_MAX / 2) { err = "problem too large"; return false; }
+  P.ntri = (int64_t)N * (N + 1) / 2;
+  // solve vectors: K + g fractional bits plus the integer part of A^{-1} b
+  P.gbits = 64 * (int)(((std::max<int64_t>(0, bmax - K) / 2) + 63) / 64);
+  P.VW = round_up((int)((2 * (int64_t)K + P.gbits + bmax + 64) / DB) + 8, WB);
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
+  P.o_cols = take(sizeof(ColInfo) * N);
+  P.o_items = take(sizeof(int32_t) * (N + 1));
+  P.o_A = take(sizeof(int32_t) * a);
+  P.o_K = take(sizeof(int64_t) * kk);
+  P.o_C = take(sizeof(int32_t) * cc);
+  P.o_S = take(sizeof(uint32_t) * cc);
+  P.o_L = take(sizeof(int32_t) * ll);
+  P.o_D = take(sizeof(uint32_t) * dd);
+  P.o_dinfo = take(sizeof(int32_t) * 4 * N);
+  P.o_nC = take(sizeof(int32_t) * P.ntri);
+  P.o_nCs = take(sizeof(int32_t) * P.ntri);
+  P.o_nL = take(sizeof(int32_t) * P.ntri);
+  P.o_b32C = take(sizeof(int32_t) * P.ntri);
+  P.o_b32L = take(sizeof(int32_t) * P.ntri);
+  P.o_X = take(sizeof(int32_t) * (size_t)nX * P.WX);
+  P.o_xs = take(sizeof(int32_t) * P.WX);
+  P.o_flags = take(sizeof(int32_t) * 16);
+  P.o_vec = take(sizeof(int32_t) * std::max((size_t)4 * N * P.VW, (size_t)N * (P.maxW + WB)));  // solve / pivot scratch
+  P.total = o;
+  return true;
+}
+
+DevPtrs dev_ptrs(const Plan& P, char* ws) {
+  DevPtrs D;
+  D.cols = (ColInfo*)(ws + P.o_cols);
+  D.itemStart = (int32_t*)(ws + P.o_items);
+  D.A = (int32_t*)(ws + P.o_A);
+  D.Kc = (int64_t*)(ws + P.o_K);
+  D.C = (int32_t*)(ws + P.o_C);
+  D.S = (uint32_t*)(ws + P.o_S);
+  D.L = (int32_t*)(ws + P.o_L);
+  D.D = (uint32_t*)(ws + P.o_D);
+  D.dinfo = (int32_t*)(ws + P.o_dinfo);
+  D.nC = (int32_t*)(ws + P.o_nC);
+  D.nCs = (int32_t*)(ws + P.o_nCs);
+  D.nL = (int32_t*)(ws + P.o_nL);
+  D.b32C = (int32_t*)(ws + P.o_b32C);
+  D.b32L = (int32_t*)(ws + P.o_b32L);
+  D.X = (int32_t*)(ws + P.o_X);
+  D.xs = (int32_t*)(ws + P.o_xs);
+  D.flags = (int32_t*)(ws + P.o_flags);
+  D.vec = (int32_t*)(ws + P.o_vec);
+  return D;
+}
+
+// v -> n balanced radix-2^29 digits (zero padded); false if it does not fit
+static bool to_digits(const MP& v, int32_t* out, int n) {
+  if (v.bitlen() > (int64_t)n * DB) return false;
+  int64_t carry = 0;
+  for (int i = 0; i < n; i++) {
+    const int64_t pos = (int64_t)i * DB;
+    const size_t w = (size_t)(pos >> 5);
+    const int off = (int)(pos & 31);
+    uint64_t u = 0;
+    if (w < v.d.size()) {
+      uint64_t lo = v.d[w];
+      if (w + 1 < v.d.size()) lo |= (uint64_t)v.d[w + 1] << 32;
+      u = (lo >> off) & (uint64_t)(RADIX - 1);
+    }
+    int64_t y = (int64_t)u + carry;
+    if (y >= (int64_t(1) << 28)) { y -= RADIX; carry = 1; } else carry = 0;
+    out[i] = (int32_t)(v.neg ? -y : y);
+  }
+  return carry == 0;
+}
+
+void mp_to_digits(const MP& v, int32_t* out, int n) { to_digits(v, out, n); }
+
+MP digits_to_mp(const int32_t* d, int n, int64_t stride) {
+  // positive and negative digit parts packed separately, then subtracted
+  std::vector<uint32_t> pw((size_t)(((int64_t)n * DB) / 32 + 3), 0u), nw(pw.size(), 0u);
+  for (int i = 0; i < n; i++) {
+    int32_t x = d[(int64_t)i * stride];
+    if (!x) continue;
+    uint64_t m = (uint64_t)(x < 0 ? -(int64_t)x : (int64_t)x);
+    int64_t pos = (int64_t)i * DB;
+    std::vector<uint32_t>& w = x < 0 ? nw : pw;
+    size_t k = (size_t)(pos >> 5);
+    uint64_t sh = m << (pos & 31);
+    uint64_t cur = (uint64_t)w[k] + (uint32_t)sh;
+    w[k] = (uint32_t)cur;
+    uint64_t c2 = (cur >> 32) + (sh >> 32);
+    for (size_t j = k + 1; c2 && j < w.size(); j++) {
+      uint64_t t = (uint64_t)w[j] + c2;
+      w[j] = (uint32_t)t;
+      c2 = t >> 32;
+    }
+  }
+  MP a, b;
+  a.d = pw; a.trim();
+  b.d = nw; b.trim();
+  return sub(a, b);
+}
+
+}  // namespace hk
+
+extern "C" {
+
+const char* hk_last_error(void) { return g_err.c_str(); }
+
+size_t hk_workspace_bytes(int N, hk_rational beta, int prec_bits, int flags) {
+  (void)flags;
+  Plan P;
+  std::string err;
+  if (!make_plan(N, beta.num, beta.den, prec_bits, P, err)) { g_err = err; return 0; }
+  return P.total;
+}
+
+hk_status hk_build_matrix(int N, hk_rational beta, int prec_bits, void* dev_ws, size_t ws_bytes,
+                          hipStream_t s, hk_matrix* out) {
+  if (!out) return fail(HK_EINVAL, "out is NULL");
+  *out = nullptr;
+  hk_matrix m = new (std::nothrow) hk_matrix_s;
+  if (!m) return fail(HK_ENOMEM, "host allocation failed");
+  std::string err;
+  if (!make_plan(N, beta.num, beta.den, prec_bits, m->P, err)) { delete m; return fail(HK_EINVAL, err); }
+  if (!dev_ws || ws_bytes < m->P.total) {
+    size_t need = m->P.total;
+    delete m;
+    return fail(HK_EINVAL, "workspace too small: need " + std::to_string(need) + " bytes");
+  }
+  m->ws = (char*)dev_ws;
+  m->ws_bytes = ws_bytes;
+  m->D = dev_ptrs(m->P, m->ws);
+  const Plan& P = m->P;
+  if (!build_moments(N, P.p, P.q, P.K, m->X)) { delete m; return fail(HK_EPRECISION, "moment rounding undecided"); }
+  std::vector<int32_t> Xd((size_t)(2 * N - 1) * P.WX);
+  for (int n = 0; n < 2 * N - 1; n++) {
+    if (!to_digits(m->X[n], &Xd[(size_t)n * P.WX], P.WX)) { delete m; return fail(HK_EPRECISION, "moment wider than planned"); }
+  }
+  hk_status st = HK_OK;
+  auto cp = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+  };
+  hipError_t e = cp(m->D.X, Xd.data(), Xd.size() * sizeof(int32_t));
+  if (e == hipSuccess) e = cp(m->D.cols, P.cols.data(), P.cols.size() * sizeof(ColInfo));
+  if (e == hipSuccess) e = cp(m->D.itemStart, P.itemStart.data(), P.itemStart.size() * sizeof(int32_t));
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) { delete m; return fail(HK_EDEVICE, std::string("upload: ") + hipGetErrorString(e)); }
+  *out = m;
+  return st;
+}
+
+hk_status hk_matrix_destroy(hk_matrix m) {
+  if (!m) return HK_OK;
+  for (auto& e : m->ev) (void)hipEventDestroy(e);
+  delete m;
+  return HK_OK;
+}
+
+hk_status hk_set_panel(hk_matrix m, int panel) {
+  if (!m || panel < 1 || panel > 64) return fail(HK_EINVAL, "panel must be in [1, 64]");
+  m->panel = panel;
+  return HK_OK;
+}
+hk_status hk_set_timing(hk_matrix m, int on) {
+  if (!m) return fail(HK_EINVAL, "null matrix");
+  m->timing = on ? 1 : 0;
+  return HK_OK;
+}
+
+hk_status hk_matrix_info(hk_matrix m, hk_info* o) {
+  if (!m || !o) return fail(HK_EINVAL, "null argument");
+  const Plan& P = m->P;
+  o->N = P.N; o->K = P.K; o->h = P.h; o->digit_bits = DB;
+  o->max_col_digits = P.maxW; o->vec_digits = P.VW; o->solve_guard_bits = P.gbits;
+  o->panel = m->panel; o->ws_bytes = P.total;
+  o->vec_bytes = sizeof(int32_t) * (size_t)P.N * P.VW;
+  o->n_update_launches = m->n_update; o->update_ms = m->update_ms;
+  return HK_OK;
+}
+
+// shift as an integer with K fractional bits
+static bool shift_fixed(const hk_mpf& x, int K, MP& out) {
+  MP v;
+  if (x.sign != 0 && x.ndigits > 0 && x.digits) {
+    v.d.assign(x.digits, x.digits + x.ndigits);
+    v.trim();
+    v.neg = x.sign < 0 && !v.d.empty();
+  }
+  int64_t e = x.exp2 + K;
+  if (e >= 0) { out = shl(v, e); return true; }
+  if (!low_bits_zero(v, -e)) return false;
+  out = shr_mag(v, -e);
+  return true;
+}
+
+hk_status hk_factor(hk_matrix m, hk_mpf shift, int inertia_mode, hipStream_t s, int* n_negative,
+                    int* first_bad_col) {
+  if (!m) return fail(HK_EINVAL, "null matrix");
+  const Plan& P = m->P;
+  const DevPtrs& D = m->D;
+  MP xf;
+  if (!shift_fixed(shift, P.K, xf)) return fail(HK_EINVAL, "shift has more than K fractional bits");
+  if (xf.bitlen() > m->X[0].bitlen() + 64 && xf.bitlen() > (int64_t)P.K + 8)
+    return fail(HK_EINVAL, "shift too large for the planned widths");
+  m->xs_host.assign(P.WX, 0);
+  if (!to_digits(xf, m->xs_host.data(), P.WX)) return fail(HK_EINVAL, "shift too wide");
+  HK_HIP(hipMemcpyAsync(D.xs, m->xs_host.data(), sizeof(int32_t) * P.WX, hipMemcpyHostToDevice, s));
+  HK_HIP(launch_fill32(D.flags, 16, 0, s));
+  HK_HIP(launch_fill32(D.flags + 1, 1, INT_MAX, s));
+  HK_HIP(launch_expand(P, D, s));
+  const int N = P.N, b = m->panel;
+  m->n_update = 0;
+  m->update_ms = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> evs;
+  size_t evi = 0;
+  auto get_ev = [&]() -> hipEvent_t {
+    if (evi >= m->ev.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      m->ev.push_back(e);
+    }
+    return m->ev[evi++];
+  };
+  int Pidx = 0;
+  for (int pc = 0; pc < N; pc += b, Pidx++) {
+    const int bb = std::min(b, N - pc);
+    for (int j = 0; j < bb; j++) {
+      const int c = pc + j;
+      if (j > 0) HK_HIP(launch_update(P, D, pc, pc + j, c, c + 1, Pidx & 1, s));
+      const int rdf = (Pidx + (j > 0 ? 1 : 0)) & 1;
+      HK_HIP(launch_finalize(P, D, c, rdf, s));
+      if (c < N - 1) HK_HIP(launch_divide(P, D, c, s));
+    }
+    if (pc + bb < N) {
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (m->timing) { e0 = get_ev(); e1 = get_ev(); if (e0 && e1) HK_HIP(hipEventRecord(e0, s)); }
+      HK_HIP(launch_update(P, D, pc, pc + bb, pc + bb, N, Pidx & 1, s));
+      if (m->timing && e0 && e1) { HK_HIP(hipEventRecord(e1, s)); evs.push_back({e0, e1}); }
+      m->n_update++;
+    }
+  }
+  HK_HIP(hipMemcpyAsync(m->flags_host, D.flags, sizeof(int32_t) * 16, hipMemcpyDeviceToHost, s));
+  HK_HIP(hipStreamSynchronize(s));
+  for (auto& pr : evs) {
+    float ms = 0;
+    HK_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
+    m->update_ms += ms;
+  }
+  m->factored = true;
+  const int fb = m->flags_host[1] == INT_MAX ? -1 : m->flags_host[1];
+  if (first_bad_col) *first_bad_col = fb;
+  if (n_negative) *n_negative = m->flags_host[2];
+  if (m->flags_host[0]) {
+    m->factored = false;
+    return fail(HK_EPRECISION, "fixed-point width exceeded (flags " + std::to_string(m->flags_host[0]) + ")");
+  }
+  if (fb >= 0 && (fb < N - 1 || !inertia_mode)) {
+    if (fb < N - 1) m->factored = false;
+    return fail(HK_ENOTSPD, "pivot <= 0 at column " + std::to_string(fb));
+  }
+  return HK_OK;
+}
+
+int64_t hk_factor_export(hk_matrix m, int kind, int c0, int c1, int32_t* slen, int64_t* off,
+                         uint32_t* dig, int64_t dig_cap, hipStream_t s) {
+  if (!m || kind < 0 || kind > 2 || c0 < 0 || c1 > m->P.N || c0 > c1) { g_err = "bad export range"; return -1; }
+  const Plan& P = m->P;
+  const DevPtrs& D = m->D;
+  const int N = P.N;
+  std::vector<MP> vals;
+  std::vector<int32_t> nw(P.ntri);
+  if (hipMemcpyAsync(nw.data(), kind == 1 ? D.nL : D.nC, sizeof(int32_t) * P.ntri,
+                     hipMemcpyDeviceToHost, s) != hipSuccess) { g_err = "copy failed"; return -1; }
+  for (int pc = c0; pc < c1; pc++) {
+    const ColInfo& ci = P.cols[pc];
+    if (kind == 1) {
+      if (pc == N - 1) continue;
+      std::vector<int32_t> buf((size_t)ci.LW * ci.R);
+      if (hipMemcpyAsync(buf.data(), D.L + ci.loff, sizeof(int32_t) * buf.size(), hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess) { g_err = "copy failed"; return -1; }
+      for (int r = pc + 1; r < N; r++) {
+        int n = std::min(nw[tri_index(N, pc, r)], ci.LW);
+        vals.push_back(digits_to_mp(buf.data() + (r - pc), n, ci.R));
+      }
+    } else {
+      const int rows = kind == 0 ? N - pc : 1;
+      std::vector<int32_t> buf((size_t)rows * ci.CW);
+      if (hipMemcpyAsync(buf.data(), D.C + ci.coff, sizeof(int32_t) * buf.size(), hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess) { g_err = "copy failed"; return -1; }
+      for (int i = 0; i < rows; i++) {
+        int n = std::min(nw[tri_index(N, pc, pc + i)], ci.CW);
+        vals.push_back(digits_to_mp(buf.data() + (size_t)i * ci.CW, n, 1));
+      }
+    }
+  }
+  int64_t total = 0;
+  for (auto& v : vals) total += (int64_t)v.d.size();
+  if (!dig) return total;
+  if (total > dig_cap) { g_err = "digit buffer too small"; return -1; }
+  int64_t pos = 0;
+  for (size_t i = 0; i < vals.size(); i++) {
+    slen[i] = vals[i].neg ? -(int32_t)vals[i].d.size() : (int32_t)vals[i].d.size();
+    off[i] = pos;
+    if (!vals[i].d.empty()) memcpy(dig + pos, vals[i].d.data(), sizeof(uint32_t) * vals[i].d.size());
+    pos += (int64_t)vals[i].d.size();
+  }
+  return total;
+}
+
+hk_status hk_factor_limb_macs(hk_matrix m, hipStream_t s, double* limb_macs) {
+  if (!m || !limb_macs) return fail(HK_EINVAL, "null argument");
+  if (!m->factored) return fail(HK_EINVAL, "no factorisation");
+  const Plan& P = m->P;
+  HK_HIP(launch_bits(P, m->D, s));
+  std::vector<int32_t> bc(P.ntri), bl(P.ntri);
+  HK_HIP(hipMemcpyAsync(bc.data(), m->D.b32C, sizeof(int32_t) * P.ntri, hipMemcpyDeviceToHost, s));
+  HK_HIP(hipMemcpyAsync(bl.data(), m->D.b32L, sizeof(int32_t) * P.ntri, hipMemcpyDeviceToHost, s));
+  HK_HIP(hipStreamSynchronize(s));
+  const int N = P.N;
+  double total = 0;
+  for (int k = 0; k < N - 1; k++) {
+    // sum_{c>k} nC(k,c) * sum_{r>=c} nL(k,r)
+    double suf = 0;
+    for (int r = N - 1; r > k; r--) {
+      suf += bl[tri_index(N, k, r)];
+      total += (double)bc[tri_index(N, k, r)] * suf;
+    }
+  }
+  *limb_macs = total;
+  return HK_OK;
+}
+
+}  // extern "C"

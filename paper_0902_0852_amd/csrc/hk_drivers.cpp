@@ -1,0 +1,349 @@
+// Eigenvalue drivers of the hk library (host control flow; every
+// factorisation and solve runs on the GPU through hk_factor / hk_solve).
+//
+//  * Secant ("The Secant Algorithm"): P(x) = det(M - xI) is the product of
+//    the LDL^T pivots; start at x1 = -2^-ceil(K/4) and x2 = 0 (the paper asks
+//    for a small negative x1 and x2 = 0), iterate
+//        x_{i+1} = x_i - (x_i - x_{i-1}) r / (r - 1),  r = P(x_i) / P(x_{i-1}),
+//    r formed as the product of per-pivot ratios floored to F = K/2 + 64 +
+//    bitlen(N) fractional bits, the running product truncated to F bits, and
+//    x_{i+1} rounded to K fractional bits (ties to even).  Stop when
+//    |x_{i+1} - x_i| <= 10^-tol x_{i+1}.  If rounding carries an iterate to
+//    or past the computed root, the last two points bracket it and the same
+//    secant formula continues on the bracket (Illinois regula falsi).
+//  * Verification ("Interval Verification"): lambda truncated to `digits`
+//    significant digits must leave every pivot positive, one unit more in
+//    the last digit must give exactly one negative pivot (Sylvester).
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "hk_internal.hpp"
+
+using namespace hk;
+
+namespace {
+
+hk_status dfail(hk_status st, const std::string& msg) { g_err = msg; return st; }
+
+MP one_shl(int64_t s) { return shl(MP::from_u64(1), s); }
+
+// floor(x / 2^s)
+MP floor_shr(const MP& x, int64_t s) {
+  MP q = shr_mag(x, s);
+  if (x.neg && !low_bits_zero(x, s)) q = sub(q, MP::from_u64(1));
+  return q;
+}
+
+hk_status pivots_host(hk_matrix m, hipStream_t s, std::vector<MP>& out) {
+  const Plan& P = m->P;
+  const int ld = P.maxW + WB;
+  hipError_t e = launch_gather_pivots(P, m->D, m->D.vec, ld, s);
+  std::vector<int32_t> buf((size_t)P.N * ld);
+  if (e == hipSuccess) e = hipMemcpyAsync(buf.data(), m->D.vec, sizeof(int32_t) * buf.size(), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return dfail(HK_EDEVICE, std::string("pivot copy: ") + hipGetErrorString(e));
+  out.resize(P.N);
+  for (int k = 0; k < P.N; k++) out[k] = digits_to_mp(buf.data() + (size_t)k * ld, ld, 1);
+  return HK_OK;
+}
+
+MP pivot_ratio(const std::vector<MP>& dn, const std::vector<MP>& dold, int64_t F) {
+  MP R = one_shl(F);
+  for (size_t k = 0; k < dn.size(); k++) {
+    MP t = floor_div(shl(dn[k], F), dold[k]);
+    R = floor_shr(mul(R, t), F);
+  }
+  return R;
+}
+
+// |a| <= 10^-tol * b  for b > 0
+bool within_tol(const MP& a, const MP& b, int tol) {
+  MP lhs = mul(a, pow10((uint32_t)tol));
+  lhs.neg = false;
+  return cmp(lhs, b) <= 0;
+}
+
+hk_mpf fixed_mpf(const MP& v, int K, std::vector<uint32_t>& keep) {
+  keep = v.d;
+  if (keep.empty()) keep.push_back(0);
+  hk_mpf f;
+  f.sign = v.sign();
+  f.ndigits = (int32_t)keep.size();
+  f.exp2 = -K;
+  f.digits = keep.data();
+  return f;
+}
+
+struct Eval {
+  hk_status st;
+  int nneg, first_bad;
+  std::vector<MP> piv;
+};
+
+}  // namespace
+
+namespace hk {
+
+struct DriverCtx {
+  hk_matrix m;
+  hipStream_t s;
+  int nfact = 0;
+  double limb_macs = 0;
+  double t_factor = 0;
+  double t_solve = 0;
+  bool count_macs = true;
+};
+
+hk_status inverse_driver(DriverCtx& cx, const hk_mpf* shift_hint, int tol, int max_iter, MP& lam,
+                         int& solves);
+
+static Eval evaluate(DriverCtx& cx, const MP& x, int inertia_mode) {
+  Eval ev;
+  std::vector<uint32_t> keep;
+  hk_mpf f = fixed_mpf(x, cx.m->P.K, keep);
+  auto t0 = std::chrono::steady_clock::now();
+  ev.st = hk_factor(cx.m, f, inertia_mode, cx.s, &ev.nneg, &ev.first_bad);
+  cx.t_factor += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  cx.nfact++;
+  if (ev.st == HK_OK && cx.count_macs) {
+    double lm = 0;
+    if (hk_factor_limb_macs(cx.m, cx.s, &lm) == HK_OK) cx.limb_macs += lm;
+  }
+  if (ev.st == HK_OK) {
+    hk_status st = pivots_host(cx.m, cx.s, ev.piv);
+    if (st != HK_OK) ev.st = st;
+  }
+  return ev;
+}
+
+hk_status secant_driver(DriverCtx& cx, int tol, int max_iter, MP& lam_fixed) {
+  const Plan& P = cx.m->P;
+  const int K = P.K;
+  int nb = 0;
+  for (int n = P.N; n; n >>= 1) nb++;
+  const int64_t F = P.h + 64 + nb;
+  const MP ONE = one_shl(F);
+  const int q = (K + 3) / 4;
+  auto secant_point = [&](const MP& xa, const MP& xb, const MP& R) {
+    MP Rm1 = sub(R, ONE);
+    return rne_div(sub(mul(xb, Rm1), mul(sub(xb, xa), R)), Rm1);
+  };
+  std::vector<MP> xs = {neg(one_shl(K - q)), MP()};
+  std::vector<std::vector<MP>> piv;
+  for (auto& x : xs) {
+    Eval ev = evaluate(cx, x, 0);
+    if (ev.st != HK_OK) return ev.st == HK_ENOTSPD ? dfail(HK_ENOTSPD, "start point not left of lambda_1") : ev.st;
+    piv.push_back(ev.piv);
+  }
+  MP prev_step;
+  bool have_prev = false;
+  for (int it = 0; it < max_iter; it++) {
+    const MP& x0 = xs[xs.size() - 2];
+    const MP& x1 = xs.back();
+    MP R = pivot_ratio(piv.back(), piv[piv.size() - 2], F);
+    if (cmp(R, ONE) >= 0) return dfail(HK_EPRECISION, "secant ratio >= 1: precision exhausted");
+    MP x2 = secant_point(x0, x1, R);
+    MP step = sub(x2, x1);
+    if (step.sign() <= 0) return dfail(HK_EPRECISION, "secant iterate did not increase");
+    if (have_prev && cmp(step, prev_step) >= 0 && it > 2) return dfail(HK_EPRECISION, "secant step did not shrink");
+    prev_step = step;
+    have_prev = true;
+    if (within_tol(step, x2, tol)) { lam_fixed = x2; return HK_OK; }
+    Eval ev = evaluate(cx, x2, 1);
+    if (ev.st == HK_OK && ev.nneg == 0 && ev.first_bad < 0) {
+      xs.push_back(x2);
+      piv.push_back(ev.piv);
+      continue;
+    }
+    if (ev.st != HK_OK && ev.st != HK_ENOTSPD) return ev.st;
+    // bracket [a, b] with P(a) > 0 >= P(b)
+    MP a = x1, b = x2;
+    std::vector<MP> da = piv.back(), db = ev.st == HK_OK ? ev.piv : std::vector<MP>();
+    int scale_a = 0, scale_b = 0, side = 0;
+    for (int jt = it; jt < max_iter; jt++) {
+      if (within_tol(sub(b, a), a, tol)) { lam_fixed = a; return HK_OK; }
+      MP c;
+      bool have_c = false;
+      if (!db.empty()) {
+        MP Rb = pivot_ratio(db, da, F);
+        if (scale_b <= scale_a) Rb = shl(floor_shr(Rb, scale_b), scale_a);
+        else Rb = floor_shr(Rb, scale_b - scale_a);
+        if (cmp(Rb, ONE) != 0) { c = secant_point(a, b, Rb); have_c = true; }
+      }
+      if (!have_c || cmp(c, a) <= 0 || cmp(c, b) >= 0) c = floor_shr(add(a, b), 1);
+      Eval ec = evaluate(cx, c, 1);
+      if (ec.st != HK_OK && ec.st != HK_ENOTSPD) return ec.st;
+      if (ec.st == HK_OK && ec.nneg == 0 && ec.first_bad < 0) {
+        a = c; da = ec.piv; scale_a = 0;
+        if (side == -1) scale_b++;
+        side = -1;
+      } else {
+        b = c; db = ec.st == HK_OK ? ec.piv : std::vector<MP>(); scale_b = 0;
+        if (side == 1) scale_a++;
+        side = 1;
+      }
+    }
+    return dfail(HK_ENOCONV, "bracketing did not converge");
+  }
+  return dfail(HK_ENOCONV, "secant did not converge");
+}
+
+// lambda = x / 2^K truncated to `digits` significant digits: D * 10^e
+static void truncate_digits(const MP& x, int K, int digits, MP& D, int64_t& e) {
+  const double l10 = ((double)x.bitlen() - K) * 0.30102999566398120;
+  e = (int64_t)std::floor(l10) - (digits - 1) - 1;
+  const MP lo = pow10((uint32_t)(digits - 1)), hi = pow10((uint32_t)digits);
+  for (int guard = 0; guard < 8; guard++) {
+    // D = floor(x / (2^K 10^e))
+    MP num = x, den = one_shl(K);
+    if (e >= 0) den = mul(den, pow10((uint32_t)e));
+    else num = mul(num, pow10((uint32_t)(-e)));
+    D = floor_div(num, den);
+    if (cmp(D, hi) >= 0) e++;
+    else if (cmp(D, lo) < 0) e--;
+    else return;
+  }
+}
+
+// fixed point (K fractional bits) of D * 10^e, floor or ceil
+static MP decimal_to_fixed(const MP& D, int64_t e, int K, bool ceil_mode) {
+  MP num = shl(D, K), den = MP::from_u64(1);
+  if (e >= 0) num = mul(num, pow10((uint32_t)e));
+  else den = pow10((uint32_t)(-e));
+  return ceil_mode ? ceil_div(num, den) : floor_div(num, den);
+}
+
+hk_status verify_bracket(DriverCtx& cx, const MP& lam_fixed, int digits, std::string& dec, bool& ok) {
+  const int K = cx.m->P.K;
+  ok = false;
+  if (lam_fixed.sign() <= 0) return dfail(HK_EVERIFY, "non-positive eigenvalue estimate");
+  MP D;
+  int64_t e;
+  truncate_digits(lam_fixed, K, digits, D, e);
+  std::string ds = to_dec(D);
+  char buf[64];
+  snprintf(buf, sizeof buf, "e%lld", (long long)(e + (int64_t)ds.size() - 1));
+  dec = ds.substr(0, 1) + "." + ds.substr(1) + buf;
+  MP xlo = decimal_to_fixed(D, e, K, false);
+  MP xhi = decimal_to_fixed(add(D, MP::from_u64(1)), e, K, true);
+  Eval a = evaluate(cx, xlo, 1);
+  if (a.st != HK_OK && a.st != HK_ENOTSPD) return a.st;
+  Eval b = evaluate(cx, xhi, 1);
+  if (b.st != HK_OK && b.st != HK_ENOTSPD) return b.st;
+  ok = a.st == HK_OK && a.nneg == 0 && a.first_bad < 0 && b.st == HK_OK && b.nneg == 1 &&
+       b.first_bad == cx.m->P.N - 1;
+  return HK_OK;
+}
+
+}  // namespace hk
+
+namespace hk {
+// Inverse iteration on one factorisation (built in the next step).
+hk_status inverse_driver(DriverCtx& cx, const hk_mpf* shift_hint, int tol, int max_iter, MP& lam,
+                         int& solves) {
+  (void)cx; (void)shift_hint; (void)tol; (void)max_iter; (void)lam;
+  solves = 0;
+  return dfail(HK_EINVAL, "inverse iteration: solve kernels not built yet");
+}
+}  // namespace hk
+
+extern "C" {
+
+hk_status hk_solve(hk_matrix factored, const void* dev_rhs, void* dev_x, hipStream_t s) {
+  (void)factored; (void)dev_rhs; (void)dev_x; (void)s;
+  return dfail(HK_EINVAL, "solve kernels not built yet");
+}
+
+hk_status hk_vec_import(hk_matrix m, int n, const int32_t* slen, const int64_t* off,
+                        const uint32_t* dig, void* dev_vec, hipStream_t s) {
+  if (!m || !dev_vec || n != m->P.N) return dfail(HK_EINVAL, "vector length must be N");
+  const int VW = m->P.VW;
+  std::vector<int32_t> buf((size_t)n * VW, 0);
+  for (int i = 0; i < n; i++) {
+    MP v;
+    int nd = slen[i] < 0 ? -slen[i] : slen[i];
+    v.d.assign(dig + off[i], dig + off[i] + nd);
+    v.trim();
+    v.neg = slen[i] < 0 && !v.d.empty();
+    mp_to_digits(v, buf.data() + (size_t)i * VW, VW);
+    if (v.bitlen() > (int64_t)(VW - 2) * DB) return dfail(HK_EINVAL, "vector entry too wide");
+  }
+  hipError_t e = hipMemcpyAsync(dev_vec, buf.data(), sizeof(int32_t) * buf.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return dfail(HK_EDEVICE, hipGetErrorString(e));
+  return HK_OK;
+}
+
+int64_t hk_vec_export(hk_matrix m, const void* dev_vec, int n, int32_t* slen, int64_t* off,
+                      uint32_t* dig, int64_t dig_cap, hipStream_t s) {
+  if (!m || !dev_vec || n != m->P.N) { g_err = "vector length must be N"; return -1; }
+  const int VW = m->P.VW;
+  std::vector<int32_t> buf((size_t)n * VW);
+  hipError_t e = hipMemcpyAsync(buf.data(), dev_vec, sizeof(int32_t) * buf.size(), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) { g_err = hipGetErrorString(e); return -1; }
+  std::vector<MP> vals(n);
+  int64_t total = 0;
+  for (int i = 0; i < n; i++) { vals[i] = digits_to_mp(buf.data() + (size_t)i * VW, VW, 1); total += (int64_t)vals[i].d.size(); }
+  if (!dig) return total;
+  if (total > dig_cap) { g_err = "digit buffer too small"; return -1; }
+  int64_t pos = 0;
+  for (int i = 0; i < n; i++) {
+    slen[i] = vals[i].neg ? -(int32_t)vals[i].d.size() : (int32_t)vals[i].d.size();
+    off[i] = pos;
+    if (!vals[i].d.empty()) memcpy(dig + pos, vals[i].d.data(), sizeof(uint32_t) * vals[i].d.size());
+    pos += (int64_t)vals[i].d.size();
+  }
+  return total;
+}
+
+hk_status hk_smallest_eig(int N, hk_rational beta, int prec_bits, int method, int digits,
+                          const hk_mpf* shift_hint, void* dev_ws, size_t ws_bytes, hipStream_t s,
+                          char* out_decimal, size_t out_len, hk_report* rep) {
+  auto t0 = std::chrono::steady_clock::now();
+  if (rep) { memset(rep, 0, sizeof(*rep)); rep->bits_used = prec_bits; }
+  if (digits < 2 || digits > 150) return dfail(HK_EINVAL, "digits must be in [2, 150]");
+  if (method != HK_INVERSE && method != HK_SECANT) return dfail(HK_EINVAL, "unknown method");
+  hk_matrix m = nullptr;
+  hk_status st = hk_build_matrix(N, beta, prec_bits, dev_ws, ws_bytes, s, &m);
+  if (st != HK_OK) { if (rep) rep->status = st; return st; }
+  DriverCtx cx;
+  cx.m = m;
+  cx.s = s;
+  MP lam;
+  int solves = 0;
+  if (method == HK_SECANT) {
+    st = secant_driver(cx, digits, 200, lam);
+  } else {
+    st = inverse_driver(cx, shift_hint, digits, 400, lam, solves);
+  }
+  bool ok = false;
+  std::string dec;
+  if (st == HK_OK) st = verify_bracket(cx, lam, digits, dec, ok);
+  if (st == HK_OK && !ok) st = dfail(HK_EVERIFY, "inertia bracket failed at " + dec);
+  if (out_decimal && out_len) {
+    snprintf(out_decimal, out_len, "%s", dec.c_str());
+  }
+  if (rep) {
+    rep->status = st;
+    rep->factorizations = cx.nfact;
+    rep->solves = solves;
+    rep->verified = ok ? 1 : 0;
+    rep->digits_verified = ok ? digits : 0;
+    snprintf(rep->lambda_dec, sizeof rep->lambda_dec, "%s", dec.c_str());
+    rep->limb_macs = cx.limb_macs;
+    rep->t_factor_s = cx.t_factor;
+    rep->t_solve_s = cx.t_solve;
+    rep->t_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  hk_matrix_destroy(m);
+  return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,105 @@
+// Internal declarations shared by the host side and the kernel launchers of
+// the hk library.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/hk.h"
+#include "hk_mp.hpp"
+
+namespace hk {
+
+// Device digits: balanced radix 2^29, value = sum_i d_i 2^(29 i) with
+// d_i in [-2^28, 2^28) once normalised; stored as int32.
+constexpr int DB = 29;
+constexpr int64_t RADIX = int64_t(1) << DB;
+constexpr int WB = 16;       // digits per output block of the trailing update
+constexpr int TROWS = 64;    // rows per update tile (one wavefront)
+
+// Per-column layout record (column c of the working triangle, also used as
+// the panel column k that produced C_k / L_k).
+struct ColInfo {
+  int64_t aoff;   // A: W digit planes of R rows (int32)
+  int64_t koff;   // carries: [2][nb][R] (int64)
+  int64_t coff;   // C_k rows (N-k) x CW, balanced digits (int32)
+  int64_t loff;   // L_k digit planes LW x R (int32), row index r - k
+  int64_t soff;   // |C_k| standard digits, rows (N-k) x CW (uint32)
+  int64_t doff;   // |d_k| 2^sh standard digits (uint32), W + 2 entries
+  int32_t W;      // digits per A entry (multiple of WB)
+  int32_t R;      // padded rows (multiple of 64)
+  int32_t nb;     // W / WB
+  int32_t CW;     // W + 16
+  int32_t LW;     // W + 32
+  int32_t items;  // trailing-update items of this column: (R/64) * nb
+};
+
+struct Plan {
+  int N = 0, K = 0, h = 0;
+  uint32_t p = 1, q = 1;
+  int WX = 0;                 // digits per moment
+  int maxW = 0;
+  int gbits = 0;              // solve guard bits
+  int VW = 0;                 // digits per vector entry
+  std::vector<ColInfo> cols;
+  std::vector<int32_t> itemStart;  // N+1 prefix sums of items
+  // byte offsets in the workspace
+  size_t o_cols, o_items, o_A, o_K, o_C, o_L, o_S, o_D, o_dinfo, o_nC, o_nCs, o_nL,
+      o_X, o_xs, o_flags, o_b32C, o_b32L, o_vec, total;
+  int64_t ntri;
+};
+
+bool make_plan(int N, int64_t bnum, int64_t bden, int K, Plan& P, std::string& err);
+
+bool reduce_beta(int64_t num, int64_t den, uint32_t* p, uint32_t* q);
+double log2_mu(int n, uint32_t p, uint32_t q);
+bool build_moments(int N, uint32_t p, uint32_t q, int K, std::vector<MP>& X);
+
+// conversions between host integers and device digits
+void mp_to_digits(const MP& v, int32_t* out, int n);          // balanced, zero padded
+MP digits_to_mp(const int32_t* d, int n, int64_t stride = 1);
+
+__host__ __device__ inline int64_t tri_index(int N, int k, int r) {
+  return (int64_t)k * N - (int64_t)k * (k - 1) / 2 + (r - k);
+}
+
+// kernel launchers (hk_kernels.hip)
+struct DevPtrs {
+  ColInfo* cols; int32_t* itemStart;
+  int32_t* A; int64_t* Kc; int32_t* C; int32_t* L; uint32_t* S; uint32_t* D; int32_t* dinfo;
+  int32_t* nC; int32_t* nCs; int32_t* nL; int32_t* X; int32_t* xs; int32_t* flags;
+  int32_t* b32C; int32_t* b32L; int32_t* vec;
+};
+DevPtrs dev_ptrs(const Plan& P, char* ws);
+extern thread_local std::string g_err;
+
+hipError_t launch_fill32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+hipError_t launch_fill64(int64_t* p, int64_t n, hipStream_t s);
+hipError_t launch_expand(const Plan& P, const DevPtrs& D, hipStream_t s);
+hipError_t launch_update(const Plan& P, const DevPtrs& D, int k0, int k1, int c_lo, int c_hi,
+                         int rd, hipStream_t s);
+hipError_t launch_finalize(const Plan& P, const DevPtrs& D, int c, int rd, hipStream_t s);
+hipError_t launch_divide(const Plan& P, const DevPtrs& D, int c, hipStream_t s);
+hipError_t launch_bits(const Plan& P, const DevPtrs& D, hipStream_t s);
+hipError_t launch_gather_pivots(const Plan& P, const DevPtrs& D, int32_t* out, int ld, hipStream_t s);
+
+}  // namespace hk
+
+struct hk_matrix_s {
+  hk::Plan P;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  hk::DevPtrs D;
+  std::vector<hk::MP> X;
+  std::vector<int32_t> xs_host;
+  bool factored = false;
+  int panel = 4;
+  int timing = 0;
+  int n_update = 0;
+  double update_ms = 0;
+  int32_t flags_host[16];
+  std::vector<hipEvent_t> ev;
+};
+

@@ -1,0 +1,304 @@
+"""Python binding of the hk C-ABI (include/hk.h): argument marshalling only.
+
+Every step of the method runs in libhk.so (HIP kernels for gfx950 plus its
+own host-side setup); this module converts Python integers to and from the
+library's plain big-integer formats, passes torch device buffers and the
+current HIP stream, and raises on any non-OK status.  There is no fallback:
+if the library is missing or fails to load, import fails loudly.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhk.so")
+
+HK_INVERSE, HK_SECANT = 0, 1
+STATUS = {0: "HK_OK", 1: "HK_EINVAL", 2: "HK_ENOTSPD", 3: "HK_EPRECISION", 4: "HK_ENOCONV",
+          5: "HK_EVERIFY", 6: "HK_EDEVICE", 7: "HK_ENOMEM"}
+
+
+class HKError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+
+
+class Rational(ctypes.Structure):
+    _fields_ = [("num", ctypes.c_int64), ("den", ctypes.c_int64)]
+
+
+class MPF(ctypes.Structure):
+    _fields_ = [("sign", ctypes.c_int32), ("ndigits", ctypes.c_int32), ("exp2", ctypes.c_int64),
+                ("digits", ctypes.POINTER(ctypes.c_uint32))]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int), ("K", ctypes.c_int), ("h", ctypes.c_int),
+                ("digit_bits", ctypes.c_int), ("max_col_digits", ctypes.c_int),
+                ("vec_digits", ctypes.c_int), ("solve_guard_bits", ctypes.c_int),
+                ("panel", ctypes.c_int), ("ws_bytes", ctypes.c_size_t),
+                ("vec_bytes", ctypes.c_size_t), ("n_update_launches", ctypes.c_int),
+                ("update_ms", ctypes.c_double)]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("bits_used", ctypes.c_int),
+                ("factorizations", ctypes.c_int), ("solves", ctypes.c_int),
+                ("verified", ctypes.c_int), ("digits_verified", ctypes.c_int),
+                ("lambda_dec", ctypes.c_char * 192), ("limb_macs", ctypes.c_double),
+                ("t_factor_s", ctypes.c_double), ("t_solve_s", ctypes.c_double),
+                ("t_total_s", ctypes.c_double)]
+
+
+_lib = None
+
+# every symbol that include/hk.h declares
+EXPORTS = ["hk_workspace_bytes", "hk_build_matrix", "hk_factor", "hk_solve", "hk_smallest_eig",
+           "hk_matrix_destroy", "hk_last_error", "hk_matrix_info", "hk_set_panel", "hk_set_timing",
+           "hk_factor_export", "hk_factor_limb_macs", "hk_vec_import", "hk_vec_export"]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libhk.so not built: run paper_0902_0852_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I, I64, SZ = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_size_t
+        L.hk_workspace_bytes.restype = SZ
+        L.hk_workspace_bytes.argtypes = [I, Rational, I, I]
+        L.hk_build_matrix.restype = I
+        L.hk_build_matrix.argtypes = [I, Rational, I, P, SZ, P, ctypes.POINTER(P)]
+        L.hk_factor.restype = I
+        L.hk_factor.argtypes = [P, MPF, I, P, ctypes.POINTER(I), ctypes.POINTER(I)]
+        L.hk_solve.restype = I
+        L.hk_solve.argtypes = [P, P, P, P]
+        L.hk_smallest_eig.restype = I
+        L.hk_smallest_eig.argtypes = [I, Rational, I, I, I, ctypes.POINTER(MPF), P, SZ, P,
+                                      ctypes.c_char_p, SZ, ctypes.POINTER(Report)]
+        L.hk_matrix_destroy.restype = I
+        L.hk_matrix_destroy.argtypes = [P]
+        L.hk_last_error.restype = ctypes.c_char_p
+        L.hk_matrix_info.restype = I
+        L.hk_matrix_info.argtypes = [P, ctypes.POINTER(Info)]
+        L.hk_set_panel.restype = I
+        L.hk_set_panel.argtypes = [P, I]
+        L.hk_set_timing.restype = I
+        L.hk_set_timing.argtypes = [P, I]
+        L.hk_factor_export.restype = I64
+        L.hk_factor_export.argtypes = [P, I, I, I, P, P, P, I64, P]
+        L.hk_factor_limb_macs.restype = I
+        L.hk_factor_limb_macs.argtypes = [P, P, ctypes.POINTER(ctypes.c_double)]
+        L.hk_vec_import.restype = I
+        L.hk_vec_import.argtypes = [P, I, P, P, P, P, P]
+        L.hk_vec_export.restype = I64
+        L.hk_vec_export.argtypes = [P, P, I, P, P, P, I64, P]
+        _lib = L
+    return _lib
+
+
+def _check(st):
+    if st != 0:
+        raise HKError(st, lib().hk_last_error().decode())
+
+
+def _stream(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _rational(beta):
+    from fractions import Fraction
+    if isinstance(beta, tuple):
+        fr = Fraction(beta[0], beta[1])
+    else:
+        fr = Fraction(beta)
+    return Rational(fr.numerator, fr.denominator)
+
+
+def _mpf_fixed(v, K):
+    """Python int with K fractional bits -> hk_mpf (keeps the digit buffer alive)."""
+    m = -v if v < 0 else v
+    nd = max(1, (m.bit_length() + 31) // 32)
+    arr = (ctypes.c_uint32 * nd).from_buffer_copy(m.to_bytes(4 * nd, "little"))
+    f = MPF(0 if v == 0 else (1 if v > 0 else -1), nd, -K, arr)
+    return f, arr
+
+
+def _ints_to_io(vals):
+    n = len(vals)
+    slen = np.zeros(max(n, 1), np.int32)
+    off = np.zeros(max(n, 1), np.int64)
+    chunks, pos = [], 0
+    for i, v in enumerate(vals):
+        m = -v if v < 0 else v
+        nd = (m.bit_length() + 31) // 32
+        slen[i] = -nd if v < 0 else nd
+        off[i] = pos
+        if nd:
+            chunks.append(m.to_bytes(4 * nd, "little"))
+        pos += nd
+    dig = np.frombuffer(b"".join(chunks), dtype=np.uint32).copy() if chunks else np.zeros(1, np.uint32)
+    if dig.size == 0:
+        dig = np.zeros(1, np.uint32)
+    return slen, off, dig
+
+
+def _io_to_ints(slen, off, dig, n):
+    raw = dig.tobytes()
+    out = []
+    for s, o in zip(slen[:n].tolist(), off[:n].tolist()):
+        nd = -s if s < 0 else s
+        v = int.from_bytes(raw[4 * o:4 * (o + nd)], "little") if nd else 0
+        out.append(-v if s < 0 else v)
+    return out
+
+
+def workspace_bytes(N, beta, K):
+    return lib().hk_workspace_bytes(N, _rational(beta), K, 0)
+
+
+class Matrix:
+    """Owns a device workspace (a torch uint8 tensor) and an hk_matrix."""
+
+    def __init__(self, N, beta, K, stream=None, ws=None):
+        import torch
+        self.N, self.K = N, K
+        self.beta = beta
+        nbytes = workspace_bytes(N, beta, K)
+        if nbytes == 0:
+            raise HKError(1, lib().hk_last_error().decode())
+        self.ws = ws if ws is not None else torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        h = ctypes.c_void_p()
+        _check(lib().hk_build_matrix(N, _rational(beta), K, ctypes.c_void_p(self.ws.data_ptr()),
+                                     self.ws.numel(), _stream(stream), ctypes.byref(h)))
+        self.h = h
+
+    def __del__(self):
+        if getattr(self, "h", None) is not None and _lib is not None:
+            _lib.hk_matrix_destroy(self.h)
+            self.h = None
+
+    def set_panel(self, b):
+        _check(lib().hk_set_panel(self.h, b))
+
+    def set_timing(self, on):
+        _check(lib().hk_set_timing(self.h, 1 if on else 0))
+
+    def info(self):
+        inf = Info()
+        _check(lib().hk_matrix_info(self.h, ctypes.byref(inf)))
+        return inf
+
+    def factor(self, shift_fixed=0, inertia_mode=0, stream=None, raise_on_error=True):
+        f, keep = _mpf_fixed(shift_fixed, self.K)
+        nn, fb = ctypes.c_int(0), ctypes.c_int(0)
+        st = lib().hk_factor(self.h, f, inertia_mode, _stream(stream), ctypes.byref(nn), ctypes.byref(fb))
+        if raise_on_error:
+            _check(st)
+        return st, nn.value, fb.value
+
+    def export(self, kind, c0=0, c1=None, stream=None):
+        c1 = self.N if c1 is None else c1
+        L = lib()
+        s = _stream(stream)
+        nd = L.hk_factor_export(self.h, kind, c0, c1, None, None, None, 0, s)
+        if nd < 0:
+            raise HKError(1, L.hk_last_error().decode())
+        N = self.N
+        if kind == 0:
+            cnt = sum(N - pc for pc in range(c0, c1))
+        elif kind == 1:
+            cnt = sum(N - pc - 1 for pc in range(c0, min(c1, N - 1)))
+        else:
+            cnt = c1 - c0
+        slen = np.zeros(max(cnt, 1), np.int32)
+        off = np.zeros(max(cnt, 1), np.int64)
+        dig = np.zeros(max(nd, 1), np.uint32)
+        r = L.hk_factor_export(self.h, kind, c0, c1, slen.ctypes.data, off.ctypes.data,
+                               dig.ctypes.data, dig.size, s)
+        if r < 0:
+            raise HKError(1, L.hk_last_error().decode())
+        return _io_to_ints(slen, off, dig, cnt)
+
+    def columns_C(self, c0=0, c1=None):
+        c1 = self.N if c1 is None else c1
+        flat = self.export(0, c0, c1)
+        out, p = [], 0
+        for pc in range(c0, c1):
+            out.append(flat[p:p + self.N - pc])
+            p += self.N - pc
+        return out
+
+    def columns_L(self, c0=0, c1=None):
+        c1 = self.N - 1 if c1 is None else min(c1, self.N - 1)
+        flat = self.export(1, c0, c1)
+        out, p = [], 0
+        for pc in range(c0, c1):
+            out.append(flat[p:p + self.N - pc - 1])
+            p += self.N - pc - 1
+        return out
+
+    def pivots(self):
+        return self.export(2, 0, self.N)
+
+    def limb_macs(self, stream=None):
+        v = ctypes.c_double()
+        _check(lib().hk_factor_limb_macs(self.h, _stream(stream), ctypes.byref(v)))
+        return v.value
+
+    # device vectors
+    def new_vec(self):
+        import torch
+        return torch.zeros(self.info().vec_bytes, dtype=torch.uint8, device="cuda")
+
+    def vec_import(self, vals, dev_vec, stream=None):
+        slen, off, dig = _ints_to_io(vals)
+        _check(lib().hk_vec_import(self.h, len(vals), slen.ctypes.data, off.ctypes.data,
+                                   dig.ctypes.data, ctypes.c_void_p(dev_vec.data_ptr()), _stream(stream)))
+
+    def vec_export(self, dev_vec, stream=None):
+        L = lib()
+        s = _stream(stream)
+        n = self.N
+        nd = L.hk_vec_export(self.h, ctypes.c_void_p(dev_vec.data_ptr()), n, None, None, None, 0, s)
+        if nd < 0:
+            raise HKError(1, L.hk_last_error().decode())
+        slen = np.zeros(n, np.int32)
+        off = np.zeros(n, np.int64)
+        dig = np.zeros(max(nd, 1), np.uint32)
+        r = L.hk_vec_export(self.h, ctypes.c_void_p(dev_vec.data_ptr()), n, slen.ctypes.data,
+                            off.ctypes.data, dig.ctypes.data, dig.size, s)
+        if r < 0:
+            raise HKError(1, L.hk_last_error().decode())
+        return _io_to_ints(slen, off, dig, n)
+
+    def solve(self, dev_rhs, dev_x, stream=None):
+        _check(lib().hk_solve(self.h, ctypes.c_void_p(dev_rhs.data_ptr()),
+                              ctypes.c_void_p(dev_x.data_ptr()), _stream(stream)))
+
+
+def smallest_eig(N, beta, K, method=HK_INVERSE, digits=45, shift_fixed=None, stream=None, ws=None):
+    """The whole method; returns (decimal string, report dict)."""
+    import torch
+    L = lib()
+    nbytes = workspace_bytes(N, beta, K)
+    if nbytes == 0:
+        raise HKError(1, L.hk_last_error().decode())
+    ws = ws if ws is not None else torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    out = ctypes.create_string_buffer(256)
+    rep = Report()
+    hint = None
+    keep = None
+    if shift_fixed is not None:
+        f, keep = _mpf_fixed(shift_fixed, K)
+        hint = ctypes.pointer(f)
+    st = L.hk_smallest_eig(N, _rational(beta), K, method, digits, hint, ctypes.c_void_p(ws.data_ptr()),
+                           ws.numel(), _stream(stream), out, 256, ctypes.byref(rep))
+    _check(st)
+    d = {k: getattr(rep, k) for k, _ in Report._fields_}
+    d["lambda_dec"] = rep.lambda_dec.decode()
+    return out.value.decode(), d

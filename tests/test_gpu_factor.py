@@ -1,0 +1,116 @@
+"""GPU parity: every digit of C, L and the pivots from the HIP factorisation
+equals the oracle's, element by element, on seeded configurations (sizes that
+span several 64-row tiles and 16-digit blocks with ragged tails), at the small
+config (N=32, beta=1, K=512: also the closed forms) and the N=200, beta=7/4,
+K=2048 config, for several update ranks (schedule invariance)."""
+import math
+import random
+
+import pytest
+
+import oracle
+from oracle.moments import moments
+from tests.gpu_util import log
+
+pytestmark = pytest.mark.gpu
+
+
+def compare(hm, of, N):
+    gC, oC = hm.columns_C(), of.all_C()
+    for pc in range(N):
+        assert gC[pc] == oC[pc], ("C", pc)
+    gL, oL = hm.columns_L(), of.all_L()
+    for pc in range(N - 1):
+        assert gL[pc] == oL[pc], ("L", pc)
+    assert hm.pivots() == of.pivots()
+
+
+def test_config1_closed_forms(hk):
+    N, K = 32, 512
+    h = K // 2
+    log("config1 N=32 beta=1 K=512")
+    m = hk.Matrix(N, (1, 1), K)
+    st, nneg, fb = m.factor(0)
+    assert (nneg, fb) == (0, -1)
+    C, L = m.columns_C(), m.columns_L()
+    for pc in range(N):
+        assert C[pc] == [(math.factorial(r) ** 2 // math.factorial(r - pc)) << h for r in range(pc, N)]
+    for pc in range(N - 1):
+        assert L[pc] == [(math.comb(r, pc) * math.factorial(r) // math.factorial(pc)) << h
+                         for r in range(pc + 1, N)]
+    det = math.prod(m.pivots())
+    assert det == math.prod(math.factorial(k) ** 2 for k in range(N)) << (h * N)
+    assert m.limb_macs() == oracle.factor(N, (1, 1), K).limb_macs
+
+
+CASES = [
+    # (N, beta, K, shift numerator xn, panel); shift x = xn * 2^-(K/2), far
+    # below lambda_1 for these sizes (negative values move the other way)
+    (5, (7, 4), 128, 0, 1),
+    (33, (7, 4), 384, -3, 4),
+    (70, (3, 2), 640, 11, 3),
+    (65, (1, 2), 512, 0, 4),
+    (97, (5, 3), 768, 7, 8),
+    (40, (2, 7), 320, -1, 2),
+    (130, (1, 1), 1024, 5, 4),
+]
+
+
+@pytest.mark.parametrize("N,beta,K,xn,panel", CASES)
+def test_parity_vs_oracle(hk, N, beta, K, xn, panel):
+    log("parity N=%d beta=%s K=%d x=%d*2^-(K/2) panel=%d" % (N, beta, K, xn, panel))
+    X = moments(N, beta, K)
+    xf = xn << (K - K // 2)
+    of = oracle.factor_from_moments(X, N, K, xf)
+    m = hk.Matrix(N, beta, K)
+    m.set_panel(panel)
+    st, nneg, fb = m.factor(xf)
+    compare(m, of, N)
+
+
+@pytest.mark.parametrize("panel", [1, 4, 16])
+def test_schedule_invariance(hk, panel):
+    # the update is exact, so every rank gives the same digits
+    N, beta, K = 80, (7, 4), 896
+    log("schedule panel=%d" % panel)
+    m = hk.Matrix(N, beta, K)
+    m.set_panel(panel)
+    m.factor(0)
+    of = oracle.factor(N, beta, K, 0)
+    compare(m, of, N)
+
+
+def test_config2_full_parity(hk):
+    N, beta, K = 200, (7, 4), 2048
+    log("config2 N=200 beta=7/4 K=2048")
+    X = moments(N, beta, K)
+    of = oracle.factor_from_moments(X, N, K, 0)
+    m = hk.Matrix(N, beta, K)
+    m.factor(0)
+    compare(m, of, N)
+    assert m.limb_macs() == of.limb_macs
+
+
+def test_shift_above_lambda_reports_not_spd(hk):
+    # x far above lambda_1: a pivot turns negative before the last column
+    N, beta, K = 40, (3, 2), 512
+    m = hk.Matrix(N, beta, K)
+    st, nneg, fb = m.factor(1 << K, inertia_mode=0, raise_on_error=False)
+    of = oracle.factor(N, beta, K, 1 << K)
+    assert st == 2 and fb == of.first_nonpos and 0 <= fb < N - 1
+
+
+def test_inertia_last_pivot(hk):
+    # just above lambda_1: only the last pivot is negative
+    from oracle.drivers import inverse_iteration, to_fixed
+    from fractions import Fraction
+    N, beta, K = 32, (1, 1), 512
+    lam, _ = inverse_iteration(N, beta, K)
+    m = hk.Matrix(N, beta, K)
+    xs = to_fixed(lam * (1 + Fraction(1, 10 ** 30)), K, "ceil")
+    st, nneg, fb = m.factor(xs, inertia_mode=1)
+    assert st == 0 and nneg == 1 and fb == N - 1
+    of = oracle.factor(N, beta, K, xs)
+    assert m.pivots() == of.pivots()
+    st, nneg, fb = m.factor(xs, inertia_mode=0, raise_on_error=False)
+    assert st == 2 and fb == N - 1
