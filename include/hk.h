@@ -65,6 +65,9 @@ typedef enum {
 } hk_status;
 
 enum { HK_INVERSE = 0, HK_SECANT = 1 };
+/* flags or-ed into the method argument of hk_smallest_eig */
+enum { HK_FLAG_NO_WORK_COUNT = 0x100,   /* skip the limb-MAC count (report 0)    */
+       HK_FLAG_TIME_UPDATES = 0x200 };  /* time every trailing-update launch      */
 
 typedef struct hk_matrix_s* hk_matrix;
 
@@ -77,7 +80,7 @@ typedef struct {
   int panel;              /* columns per trailing update (rank of the update) */
   size_t ws_bytes;        /* bytes of workspace in use                        */
   size_t vec_bytes;       /* bytes of one device vector (hk_solve operands)   */
-  int n_update_launches;  /* trailing-update launches of the last hk_factor   */
+  int n_update_launches;  /* update-kernel launches of the last hk_factor     */
   double update_ms;       /* summed device time of those launches (timing on) */
 } hk_info;
 
@@ -91,6 +94,8 @@ typedef struct {
   char lambda_dec[192];   /* lambda_1 in decimal scientific notation          */
   double limb_macs;       /* algorithmic 32-bit limb MACs, all factorisations */
   double t_factor_s, t_solve_s, t_total_s;
+  int update_launches;    /* update-kernel launches (HK_FLAG_TIME_UPDATES)    */
+  double update_ms;       /* their summed device time                         */
 } hk_report;
 
 /* Bytes of device workspace needed for (N, beta, K).  flags: reserved, 0.
@@ -126,7 +131,8 @@ hk_status hk_factor(hk_matrix m, hk_mpf shift, int inertia_mode, hipStream_t s,
    hk_info.solve_guard_bits).  Forward, diagonal and backward steps each
    round once per entry (RNE) after exact inner products.  Both operands are
    device vectors of hk_info.vec_bytes bytes in the library's layout (fill
-   and read them with hk_vec_import / hk_vec_export).  Does not synchronise. */
+   and read them with hk_vec_import / hk_vec_export).  Synchronises s and
+   returns HK_EPRECISION if an intermediate exceeded the planned widths. */
 hk_status hk_solve(hk_matrix factored, const void* dev_rhs, void* dev_x, hipStream_t s);
 
 /* The full method: build, factor, iterate (HK_INVERSE: inverse iteration on
@@ -144,8 +150,9 @@ hk_status hk_matrix_info(hk_matrix m, hk_info* out);
 
 /* Tuning: columns per trailing update (panel width, >= 1). */
 hk_status hk_set_panel(hk_matrix m, int panel);
-/* Timing: when on, every trailing-update launch of hk_factor is bracketed by
-   HIP events on s and hk_info reports their count and summed duration. */
+/* Timing: when on, every launch of the update kernel in hk_factor (the
+   in-panel and the trailing ones) is bracketed by HIP events on s and
+   hk_info reports their count and summed duration. */
 hk_status hk_set_timing(hk_matrix m, int on);
 
 /* Copies factor entries of columns [c0, c1) to the host as int lists.

@@ -70,10 +70,25 @@ bool make_plan(int N, int64_t bnum, int64_t bden, int K, Plan& P, std::string& e
     P.maxW = std::max(P.maxW, W);
   }
   if ((int64_t)P.itemStart[N] >= (int64_t)INT_MAX / 2) { err = "problem too large"; return false; }
+  // L^T rows (backward solves): row r holds L_c[r], c < r
+  P.LWT = P.maxW + 2 * WB;
+  int64_t lt = 0;
+  for (int r = 0; r < N; r++) {
+    ColInfo& ci = P.cols[r];
+    ci.PT = std::max(64, round_up(r, 64));
+    ci.ltoff = lt;
+    lt += (int64_t)P.LWT * ci.PT;
+  }
   P.ntri = (int64_t)N * (N + 1) / 2;
   // solve vectors: K + g fractional bits plus the integer part of A^{-1} b
   P.gbits = 64 * (int)(((std::max<int64_t>(0, bmax - K) / 2) + 63) / 64);
-  P.VW = round_up((int)((2 * (int64_t)K + P.gbits + bmax + 64) / DB) + 8, WB);
+  // |z| <= N sqrt(A_ii / lambda_1), |w|, |y| <= N / lambda_1 with lambda_1 >= 2^-K
+  {
+    const int64_t vb = std::max<int64_t>(3 * (int64_t)K / 2 + 2 * P.gbits, 2 * (int64_t)K + P.gbits) + 96;
+    P.VW = round_up((int)((vb + DB - 1) / DB) + 4, WB);
+  }
+  P.VA = round_up(P.VW + P.maxW + 2 * WB + (P.h + DB - 1) / DB + 6, WB);
+  P.Npad = round_up(N, 64);
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
   P.o_cols = take(sizeof(ColInfo) * N);
@@ -93,7 +108,18 @@ bool make_plan(int N, int64_t bnum, int64_t bden, int K, Plan& P, std::string& e
   P.o_X = take(sizeof(int32_t) * (size_t)nX * P.WX);
   P.o_xs = take(sizeof(int32_t) * P.WX);
   P.o_flags = take(sizeof(int32_t) * 16);
-  P.o_vec = take(sizeof(int32_t) * std::max((size_t)4 * N * P.VW, (size_t)N * (P.maxW + WB)));  // solve / pivot scratch
+  P.o_vec = take(sizeof(int32_t) * (size_t)N * (P.maxW + WB));  // pivot gather
+  P.o_LT = take(sizeof(int32_t) * lt);
+  P.o_acc = take(sizeof(int32_t) * (size_t)P.VA * P.Npad);
+  P.o_kca = take(sizeof(int64_t) * (size_t)2 * (P.VA / WB) * P.Npad);
+  P.o_ub = take(sizeof(int32_t) * (size_t)N * P.VW);
+  P.o_us = take(sizeof(uint32_t) * (size_t)N * P.VW);
+  P.o_wb = take(sizeof(int32_t) * (size_t)N * P.VW);
+  P.o_nU = take(sizeof(int32_t) * N);
+  P.o_nUs = take(sizeof(int32_t) * N);
+  P.o_dv1 = take(sizeof(int32_t) * (size_t)N * P.VW);
+  P.o_dv2 = take(sizeof(int32_t) * (size_t)N * P.VW);
+  P.o_md = take(sizeof(uint32_t) * (size_t)(P.VW + 4));
   P.total = o;
   return true;
 }
@@ -118,6 +144,17 @@ DevPtrs dev_ptrs(const Plan& P, char* ws) {
   D.xs = (int32_t*)(ws + P.o_xs);
   D.flags = (int32_t*)(ws + P.o_flags);
   D.vec = (int32_t*)(ws + P.o_vec);
+  D.LT = (int32_t*)(ws + P.o_LT);
+  D.acc = (int32_t*)(ws + P.o_acc);
+  D.kca = (int64_t*)(ws + P.o_kca);
+  D.ub = (int32_t*)(ws + P.o_ub);
+  D.us = (uint32_t*)(ws + P.o_us);
+  D.wb = (int32_t*)(ws + P.o_wb);
+  D.nU = (int32_t*)(ws + P.o_nU);
+  D.nUs = (int32_t*)(ws + P.o_nUs);
+  D.dv1 = (int32_t*)(ws + P.o_dv1);
+  D.dv2 = (int32_t*)(ws + P.o_dv2);
+  D.md = (uint32_t*)(ws + P.o_md);
   return D;
 }
 
@@ -202,6 +239,13 @@ hk_status hk_build_matrix(int N, hk_rational beta, int prec_bits, void* dev_ws, 
   m->D = dev_ptrs(m->P, m->ws);
   const Plan& P = m->P;
   if (!build_moments(N, P.p, P.q, P.K, m->X)) { delete m; return fail(HK_EPRECISION, "moment rounding undecided"); }
+  {
+    // solve guard bits: half the bit length of the largest moment's integer
+    // part, rounded up to a multiple of 64
+    const int64_t top = std::max<int64_t>(0, m->X[2 * N - 2].bitlen() - P.K);
+    m->gbits = 64 * (int)((top / 2 + 63) / 64);
+    if (m->gbits > P.gbits) { delete m; return fail(HK_EPRECISION, "moment wider than planned"); }
+  }
   std::vector<int32_t> Xd((size_t)(2 * N - 1) * P.WX);
   for (int n = 0; n < 2 * N - 1; n++) {
     if (!to_digits(m->X[n], &Xd[(size_t)n * P.WX], P.WX)) { delete m; return fail(HK_EPRECISION, "moment wider than planned"); }
@@ -241,7 +285,7 @@ hk_status hk_matrix_info(hk_matrix m, hk_info* o) {
   if (!m || !o) return fail(HK_EINVAL, "null argument");
   const Plan& P = m->P;
   o->N = P.N; o->K = P.K; o->h = P.h; o->digit_bits = DB;
-  o->max_col_digits = P.maxW; o->vec_digits = P.VW; o->solve_guard_bits = P.gbits;
+  o->max_col_digits = P.maxW; o->vec_digits = P.VW; o->solve_guard_bits = m->gbits;
   o->panel = m->panel; o->ws_bytes = P.total;
   o->vec_bytes = sizeof(int32_t) * (size_t)P.N * P.VW;
   o->n_update_launches = m->n_update; o->update_ms = m->update_ms;
@@ -296,7 +340,13 @@ hk_status hk_factor(hk_matrix m, hk_mpf shift, int inertia_mode, hipStream_t s, 
     const int bb = std::min(b, N - pc);
     for (int j = 0; j < bb; j++) {
       const int c = pc + j;
-      if (j > 0) HK_HIP(launch_update(P, D, pc, pc + j, c, c + 1, Pidx & 1, s));
+      if (j > 0) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (m->timing) { e0 = get_ev(); e1 = get_ev(); if (e0 && e1) HK_HIP(hipEventRecord(e0, s)); }
+        HK_HIP(launch_update(P, D, pc, pc + j, c, c + 1, Pidx & 1, s));
+        if (m->timing && e0 && e1) { HK_HIP(hipEventRecord(e1, s)); evs.push_back({e0, e1}); }
+        m->n_update++;
+      }
       const int rdf = (Pidx + (j > 0 ? 1 : 0)) & 1;
       HK_HIP(launch_finalize(P, D, c, rdf, s));
       if (c < N - 1) HK_HIP(launch_divide(P, D, c, s));

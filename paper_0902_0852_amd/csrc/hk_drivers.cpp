@@ -98,6 +98,8 @@ struct DriverCtx {
   double t_factor = 0;
   double t_solve = 0;
   bool count_macs = true;
+  int upd_launches = 0;
+  double upd_ms = 0;
 };
 
 hk_status inverse_driver(DriverCtx& cx, const hk_mpf* shift_hint, int tol, int max_iter, MP& lam,
@@ -111,6 +113,10 @@ static Eval evaluate(DriverCtx& cx, const MP& x, int inertia_mode) {
   ev.st = hk_factor(cx.m, f, inertia_mode, cx.s, &ev.nneg, &ev.first_bad);
   cx.t_factor += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   cx.nfact++;
+  {
+    hk_info inf;
+    if (hk_matrix_info(cx.m, &inf) == HK_OK) { cx.upd_launches += inf.n_update_launches; cx.upd_ms += inf.update_ms; }
+  }
   if (ev.st == HK_OK && cx.count_macs) {
     double lm = 0;
     if (hk_factor_limb_macs(cx.m, cx.s, &lm) == HK_OK) cx.limb_macs += lm;
@@ -244,20 +250,151 @@ hk_status verify_bracket(DriverCtx& cx, const MP& lam_fixed, int digits, std::st
 }  // namespace hk
 
 namespace hk {
-// Inverse iteration on one factorisation (built in the next step).
+
+// device vector (N rows of VW balanced digits) -> host integers
+static hk_status vec_to_host(hk_matrix m, const int32_t* dev, hipStream_t s, std::vector<MP>& out) {
+  const Plan& P = m->P;
+  std::vector<int32_t> buf((size_t)P.N * P.VW);
+  hipError_t e = hipMemcpyAsync(buf.data(), dev, sizeof(int32_t) * buf.size(), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return dfail(HK_EDEVICE, hipGetErrorString(e));
+  out.resize(P.N);
+  for (int i = 0; i < P.N; i++) out[i] = digits_to_mp(buf.data() + (size_t)i * P.VW, P.VW, 1);
+  return HK_OK;
+}
+
+// Inverse iteration (not in the paper): one factorisation of M - sigma I,
+// then y = (M - sigma I)^{-1} v on the GPU, lambda = sigma + <v,v>/<v,y> from
+// exact integer dots, v <- RNE(y 2^K / max|y|) on the GPU; v0 = all ones.
+// Stops when |lambda_k - lambda_{k-1}| <= 10^-tol lambda_k.  A shift hint
+// that is not below lambda_1 (a pivot <= 0) is halved up to three times,
+// then 0 is used.
 hk_status inverse_driver(DriverCtx& cx, const hk_mpf* shift_hint, int tol, int max_iter, MP& lam,
                          int& solves) {
-  (void)cx; (void)shift_hint; (void)tol; (void)max_iter; (void)lam;
+  hk_matrix m = cx.m;
+  const Plan& P = m->P;
+  const int K = P.K, N = P.N;
   solves = 0;
-  return dfail(HK_EINVAL, "inverse iteration: solve kernels not built yet");
+  MP sigma;
+  if (shift_hint) {
+    MP v;
+    if (shift_hint->sign != 0 && shift_hint->ndigits > 0) {
+      v.d.assign(shift_hint->digits, shift_hint->digits + shift_hint->ndigits);
+      v.trim();
+      v.neg = shift_hint->sign < 0 && !v.d.empty();
+    }
+    const int64_t e = shift_hint->exp2 + K;
+    sigma = e >= 0 ? shl(v, e) : floor_shr(v, -e);
+  }
+  for (int attempt = 0;; attempt++) {
+    Eval ev = evaluate(cx, sigma, 0);
+    if (ev.st == HK_OK) break;
+    if (ev.st != HK_ENOTSPD || sigma.is_zero()) return ev.st;
+    sigma = attempt < 3 ? floor_shr(sigma, 1) : MP();
+  }
+  const int g = m->gbits;
+  // v0 = 1 (K fractional bits)
+  std::vector<MP> v(N, one_shl(K));
+  {
+    std::vector<int32_t> buf((size_t)N * P.VW, 0);
+    for (int i = 0; i < N; i++) mp_to_digits(v[i], buf.data() + (size_t)i * P.VW, P.VW);
+    hipError_t e = hipMemcpyAsync(m->D.dv1, buf.data(), sizeof(int32_t) * buf.size(), hipMemcpyHostToDevice, cx.s);
+    if (e == hipSuccess) e = hipStreamSynchronize(cx.s);
+    if (e != hipSuccess) return dfail(HK_EDEVICE, hipGetErrorString(e));
+  }
+  const int64_t F = 2 * (int64_t)K + 64;   // fixed-point bits of the lambda iterates
+  MP lam_prev;
+  bool have_prev = false;
+  std::vector<MP> y;
+  for (int it = 0; it < max_iter; it++) {
+    auto t0 = std::chrono::steady_clock::now();
+    hk_status st = hk_solve(m, m->D.dv1, m->D.dv2, cx.s);
+    solves++;
+    if (st != HK_OK) return st;
+    st = vec_to_host(m, m->D.dv2, cx.s, y);
+    cx.t_solve += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (st != HK_OK) return st;
+    MP vy, vv;
+    for (int i = 0; i < N; i++) { vy = add(vy, mul(v[i], y[i])); vv = add(vv, mul(v[i], v[i])); }
+    if (vy.sign() <= 0) return dfail(HK_EPRECISION, "non-positive Rayleigh quotient");
+    // lambda 2^F = sigma 2^(F-K) + vv 2^(g+F) / vy
+    MP lamF = add(shl(sigma, F - K), floor_div(shl(vv, g + F), vy));
+    if (have_prev && within_tol(sub(lamF, lam_prev), lamF, tol)) {
+      lam = rne_shr(lamF, F - K);
+      return HK_OK;
+    }
+    lam_prev = lamF;
+    have_prev = true;
+    // v <- RNE(y 2^K / max|y|) on the GPU (standard digits of |y| are in us)
+    size_t imax = 0;
+    for (int i = 1; i < N; i++) if (cmp_mag(y[i], y[imax]) > 0) imax = i;
+    MP mag = y[imax];
+    mag.neg = false;
+    if (mag.is_zero()) return dfail(HK_EPRECISION, "zero iterate");
+    const int64_t bl = mag.bitlen();
+    const int sh = (int)((DB - (bl % DB)) % DB);     // top digit gets bit 28 set
+    MP msh = shl(mag, sh);
+    const int nd = (int)((msh.bitlen() + DB - 1) / DB);
+    std::vector<uint32_t> md(nd);
+    for (int i = 0; i < nd; i++) {
+      const int64_t pos = (int64_t)i * DB;
+      const size_t w = (size_t)(pos >> 5);
+      uint64_t lo = w < msh.d.size() ? msh.d[w] : 0;
+      if (w + 1 < msh.d.size()) lo |= (uint64_t)msh.d[w + 1] << 32;
+      md[i] = (uint32_t)((lo >> (pos & 31)) & (RADIX - 1));
+    }
+    hipError_t e = hipMemcpyAsync(m->D.md, md.data(), sizeof(uint32_t) * nd, hipMemcpyHostToDevice, cx.s);
+    if (e == hipSuccess) e = launch_vscale(P, m->D, m->D.md, nd, sh, m->D.dv1, cx.s);
+    if (e != hipSuccess) return dfail(HK_EDEVICE, hipGetErrorString(e));
+    st = vec_to_host(m, m->D.dv1, cx.s, v);
+    if (st != HK_OK) return st;
+  }
+  return dfail(HK_ENOCONV, "inverse iteration did not converge");
 }
+
 }  // namespace hk
 
 extern "C" {
 
-hk_status hk_solve(hk_matrix factored, const void* dev_rhs, void* dev_x, hipStream_t s) {
-  (void)factored; (void)dev_rhs; (void)dev_x; (void)s;
-  return dfail(HK_EINVAL, "solve kernels not built yet");
+hk_status hk_solve(hk_matrix m, const void* dev_rhs, void* dev_x, hipStream_t s) {
+  if (!m || !dev_rhs || !dev_x) return dfail(HK_EINVAL, "null argument");
+  if (!m->factored) return dfail(HK_EINVAL, "no valid factorisation");
+  const Plan& P = m->P;
+  const DevPtrs& D = m->D;
+  const int N = P.N, h = P.h, b = m->panel;
+  hipError_t e = launch_fill32(D.flags, 16, 0, s);
+  // forward: acc = b 2^(h+g); z_k = RNE(acc_k / 2^h) column by column
+  if (e == hipSuccess) e = launch_vinit(P, D, (const int32_t*)dev_rhs, h + m->gbits, s);
+  int Pidx = 0;
+  for (int k0 = 0; k0 < N && e == hipSuccess; k0 += b, Pidx++) {
+    const int bb = std::min(b, N - k0);
+    for (int j = 0; j < bb && e == hipSuccess; j++) {
+      const int k = k0 + j;
+      if (j > 0) e = launch_vupdate(P, D, 0, k0, k, k, k + 1, Pidx & 1, s);
+      if (e == hipSuccess) e = launch_vfinalize(P, D, k, (Pidx + (j > 0 ? 1 : 0)) & 1, nullptr, s);
+    }
+    if (e == hipSuccess && k0 + bb < N) e = launch_vupdate(P, D, 0, k0, k0 + bb, k0 + bb, N, Pidx & 1, s);
+  }
+  // diagonal: w_k = RNE(z_k 2^h / d_k)
+  if (e == hipSuccess) e = launch_vdivide(P, D, s);
+  // backward: acc = w 2^h; y_k = RNE(acc_k / 2^h), last row first
+  if (e == hipSuccess) e = launch_vinit(P, D, D.wb, h, s);
+  Pidx = 0;
+  for (int k_hi = N; k_hi > 0 && e == hipSuccess; k_hi -= b, Pidx++) {
+    const int k_lo = std::max(0, k_hi - b);
+    for (int j = 0; j < k_hi - k_lo && e == hipSuccess; j++) {
+      const int k = k_hi - 1 - j;
+      if (j > 0) e = launch_vupdate(P, D, 1, k + 1, k_hi, k, k + 1, Pidx & 1, s);
+      if (e == hipSuccess) e = launch_vfinalize(P, D, k, (Pidx + (j > 0 ? 1 : 0)) & 1, (int32_t*)dev_x, s);
+    }
+    if (e == hipSuccess && k_lo > 0) e = launch_vupdate(P, D, 1, k_lo, k_hi, 0, k_lo, Pidx & 1, s);
+  }
+  int32_t fl[16];
+  if (e == hipSuccess) e = hipMemcpyAsync(fl, D.flags, sizeof fl, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return dfail(HK_EDEVICE, std::string("solve: ") + hipGetErrorString(e));
+  if (fl[0]) return dfail(HK_EPRECISION, "solve: fixed-point width exceeded (flags " + std::to_string(fl[0]) + ")");
+  return HK_OK;
 }
 
 hk_status hk_vec_import(hk_matrix m, int n, const int32_t* slen, const int64_t* off,
@@ -309,6 +446,8 @@ hk_status hk_smallest_eig(int N, hk_rational beta, int prec_bits, int method, in
   auto t0 = std::chrono::steady_clock::now();
   if (rep) { memset(rep, 0, sizeof(*rep)); rep->bits_used = prec_bits; }
   if (digits < 2 || digits > 150) return dfail(HK_EINVAL, "digits must be in [2, 150]");
+  const int flags = method & ~0xff;
+  method &= 0xff;
   if (method != HK_INVERSE && method != HK_SECANT) return dfail(HK_EINVAL, "unknown method");
   hk_matrix m = nullptr;
   hk_status st = hk_build_matrix(N, beta, prec_bits, dev_ws, ws_bytes, s, &m);
@@ -316,6 +455,8 @@ hk_status hk_smallest_eig(int N, hk_rational beta, int prec_bits, int method, in
   DriverCtx cx;
   cx.m = m;
   cx.s = s;
+  cx.count_macs = !(flags & HK_FLAG_NO_WORK_COUNT);
+  if (flags & HK_FLAG_TIME_UPDATES) hk_set_timing(m, 1);
   MP lam;
   int solves = 0;
   if (method == HK_SECANT) {
@@ -341,6 +482,8 @@ hk_status hk_smallest_eig(int N, hk_rational beta, int prec_bits, int method, in
     rep->t_factor_s = cx.t_factor;
     rep->t_solve_s = cx.t_solve;
     rep->t_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    rep->update_launches = cx.upd_launches;
+    rep->update_ms = cx.upd_ms;
   }
   hk_matrix_destroy(m);
   return st;

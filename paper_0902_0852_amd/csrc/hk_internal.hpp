@@ -34,6 +34,9 @@ struct ColInfo {
   int32_t CW;     // W + 16
   int32_t LW;     // W + 32
   int32_t items;  // trailing-update items of this column: (R/64) * nb
+  int64_t ltoff;  // L^T row: entries L_c[r] for c < r, digit planes LWT x PT (int32)
+  int32_t PT;     // rows of the L^T planes: r rounded up to 64 (>= 64)
+  int32_t pad;
 };
 
 struct Plan {
@@ -43,11 +46,15 @@ struct Plan {
   int maxW = 0;
   int gbits = 0;              // solve guard bits
   int VW = 0;                 // digits per vector entry
+  int VA = 0;                 // digits per solve accumulator (multiple of WB)
+  int Npad = 0;               // N rounded up to 64
+  int LWT = 0;                // digit planes of the L^T rows
   std::vector<ColInfo> cols;
   std::vector<int32_t> itemStart;  // N+1 prefix sums of items
   // byte offsets in the workspace
   size_t o_cols, o_items, o_A, o_K, o_C, o_L, o_S, o_D, o_dinfo, o_nC, o_nCs, o_nL,
-      o_X, o_xs, o_flags, o_b32C, o_b32L, o_vec, total;
+      o_X, o_xs, o_flags, o_b32C, o_b32L, o_vec, o_LT, o_acc, o_kca, o_ub, o_us, o_wb, o_nU,
+      o_nUs, o_dv1, o_dv2, o_md, total;
   int64_t ntri;
 };
 
@@ -71,6 +78,8 @@ struct DevPtrs {
   int32_t* A; int64_t* Kc; int32_t* C; int32_t* L; uint32_t* S; uint32_t* D; int32_t* dinfo;
   int32_t* nC; int32_t* nCs; int32_t* nL; int32_t* X; int32_t* xs; int32_t* flags;
   int32_t* b32C; int32_t* b32L; int32_t* vec;
+  int32_t* LT; int32_t* acc; int64_t* kca; int32_t* ub; uint32_t* us; int32_t* wb;
+  int32_t* nU; int32_t* nUs; int32_t* dv1; int32_t* dv2; uint32_t* md;
 };
 DevPtrs dev_ptrs(const Plan& P, char* ws);
 extern thread_local std::string g_err;
@@ -83,6 +92,14 @@ hipError_t launch_update(const Plan& P, const DevPtrs& D, int k0, int k1, int c_
 hipError_t launch_finalize(const Plan& P, const DevPtrs& D, int c, int rd, hipStream_t s);
 hipError_t launch_divide(const Plan& P, const DevPtrs& D, int c, hipStream_t s);
 hipError_t launch_bits(const Plan& P, const DevPtrs& D, hipStream_t s);
+hipError_t launch_vinit(const Plan& P, const DevPtrs& D, const int32_t* src, int Sbits, hipStream_t s);
+hipError_t launch_vupdate(const Plan& P, const DevPtrs& D, int bwd, int k0, int k1, int i_lo,
+                          int i_hi, int rd, hipStream_t s);
+hipError_t launch_vfinalize(const Plan& P, const DevPtrs& D, int k, int rd, int32_t* out,
+                            hipStream_t s);
+hipError_t launch_vdivide(const Plan& P, const DevPtrs& D, hipStream_t s);
+hipError_t launch_vscale(const Plan& P, const DevPtrs& D, const uint32_t* md, int nd, int sh,
+                         int32_t* out, hipStream_t s);
 hipError_t launch_gather_pivots(const Plan& P, const DevPtrs& D, int32_t* out, int ld, hipStream_t s);
 
 }  // namespace hk
@@ -100,6 +117,7 @@ struct hk_matrix_s {
   int n_update = 0;
   double update_ms = 0;
   int32_t flags_host[16];
+  int gbits = 0;            // solve guard bits from the actual largest moment
   std::vector<hipEvent_t> ev;
 };
 

@@ -33,6 +33,10 @@ __device__ __forceinline__ int wave_max(int v) {
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// wavefront-uniform operand digits are read through the constant address
+// space so that they arrive by scalar loads into SGPRs
+typedef const __attribute__((address_space(4))) int32_t cint32_t;
+
 __global__ void k_fill32(int32_t* __restrict__ p, int64_t n, int32_t v) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -90,11 +94,80 @@ __device__ __forceinline__ void renorm(int64_t* acc) {
   }
 }
 
+// Accumulate sum_{k} C_k * L_k into the 16 output columns of block q:
+// C_k (uniform: wavefront-shared digits Cp[0..nC), zero padded to a multiple
+// of 16) times L_k (per lane: digit j at Lbase[j * P + lo], zero padded by
+// >= 30 digits), product scanning through a 31-digit sliding register window.
+// L digits come by buffer loads: the digit-plane offset j P is a scalar
+// operand, the lane offset lo a vector one, and the region size bounds every
+// access (a load outside it returns 0).
+__device__ __forceinline__ void accum_block(int64_t* acc, int& cnt, const int32_t* Cp, int nC,
+                                            const int32_t* Lbase, int64_t nbytes, int lo, int P,
+                                            int nL, int q) {
+  const int u_lo = max(0, q - (nC + WB - 1) / WB + 1);
+  const int u_hi = min(q, (nL + WB - 2) / WB);
+  if (nC <= 0 || nL <= 0 || u_lo > u_hi) return;
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)Lbase, (short)0, (int)min(nbytes, (int64_t)0x7fffffff), 0x00020000);
+  const int vo = lo * 4;
+  const int pb = P * 4;
+  int32_t D[WB], U[WB], Cd[WB];
+  if (u_lo == 0) {
+#pragma unroll
+    for (int e = 0; e < WB; e++) D[e] = 0;
+  } else {
+#pragma unroll
+    for (int e = 0; e < WB; e++)
+      D[e] = __builtin_amdgcn_raw_buffer_load_b32(rs, vo, (WB * u_lo - WB + e) * pb, 0);
+  }
+  for (int u = u_lo; u <= u_hi; u += 2) {
+#pragma unroll
+    for (int e = 0; e < WB; e++) U[e] = __builtin_amdgcn_raw_buffer_load_b32(rs, vo, (WB * u + e) * pb, 0);
+    {
+      const cint32_t* cp = (const cint32_t*)(Cp + WB * (q - u));
+#pragma unroll
+      for (int e = 0; e < WB; e++) Cd[e] = cp[e];
+    }
+    mac_block(acc, Cd, D, U);
+    cnt += WB;
+    if (cnt >= 96) { renorm(acc); cnt = 0; }
+    if (u + 1 > u_hi) break;
+#pragma unroll
+    for (int e = 0; e < WB; e++)
+      D[e] = __builtin_amdgcn_raw_buffer_load_b32(rs, vo, (WB * (u + 1) + e) * pb, 0);
+    {
+      const cint32_t* cp = (const cint32_t*)(Cp + WB * (q - u - 1));
+#pragma unroll
+      for (int e = 0; e < WB; e++) Cd[e] = cp[e];
+    }
+    mac_block(acc, Cd, U, D);
+    cnt += WB;
+    if (cnt >= 96) { renorm(acc); cnt = 0; }
+  }
+}
+
+// A's 16 digits of block q (stride as) -= acc, with the pending carry into
+// this block (kin, NULL for block 0) folded in; the carry out goes to kout
+// (NULL for the top block, where it must vanish).
+__device__ __forceinline__ void apply_block(const int64_t* acc, int32_t* Ap, int64_t as,
+                                            const int64_t* kin, int64_t* kout, int32_t* flags) {
+  int64_t v = kin ? *kin : 0;
+#pragma unroll
+  for (int m = 0; m < WB; m++) {
+    v += (int64_t)Ap[(int64_t)m * as] - acc[m];
+    const int32_t d = balanced29(v);
+    Ap[(int64_t)m * as] = d;
+    v = (v - d) >> DB;
+  }
+  v -= acc[WB];
+  if (kout) *kout = v;
+  else if (v != 0) atomicOr(&flags[0], 1);
+}
+
 // Rank-(k1-k0) update of columns [c_lo, c_hi):
 //   A_rc -= sum_{k0 <= k < k1} C_k[c] L_k[r]      (exact)
 // One wavefront per (column, 64-row tile, 16-digit output block).  C_k[c]
-// digits are wavefront-uniform (scalar loads, SGPR operands of the MACs);
-// L_k[r] digits are per lane and slide through a 31-digit register window.
+// digits are wavefront-uniform; L_k[r] digits are per lane.
 __global__ void __launch_bounds__(256) k_update(const ColInfo* __restrict__ cols,
                                                 const int32_t* __restrict__ itemStart,
                                                 int32_t* __restrict__ A, int64_t* __restrict__ Kc,
@@ -128,72 +201,126 @@ __global__ void __launch_bounds__(256) k_update(const ColInfo* __restrict__ cols
 #pragma unroll
   for (int m = 0; m <= WB; m++) acc[m] = 0;
   int cnt = 0;
-
   for (int k = k0; k < k1; k++) {
     const ColInfo kk = cols[k];
     const int nC = min(uni(nCw[tri_index(N, k, c)]), kk.CW - WB);
     const int nLl = active ? nLw[tri_index(N, k, rr)] : 0;
     const int nL = min(uni(wave_max(nLl)), kk.LW - 2 * WB);
-    const int u_lo = max(0, q - (nC + WB - 1) / WB + 1);
-    const int u_hi = min(q, (nL + WB - 2) / WB);
-    if (nC == 0 || nL == 0 || u_lo > u_hi) continue;
-    const int32_t* Cp = Cb + kk.coff + (int64_t)(c - k) * kk.CW;
-    const int32_t* Lp = Lb + kk.loff + (rr - k);
-    const int64_t P = kk.R;
-    int32_t D[WB], U[WB], Cd[WB];
-    if (u_lo == 0) {
-#pragma unroll
-      for (int e = 0; e < WB; e++) D[e] = 0;
-    } else {
-#pragma unroll
-      for (int e = 0; e < WB; e++) D[e] = Lp[(int64_t)(WB * u_lo - WB + e) * P];
-    }
-    for (int u = u_lo; u <= u_hi; u += 2) {
-#pragma unroll
-      for (int e = 0; e < WB; e++) U[e] = Lp[(int64_t)(WB * u + e) * P];
-      {
-        const int32_t* cp = Cp + WB * (q - u);
-#pragma unroll
-        for (int e = 0; e < WB; e++) Cd[e] = cp[e];
-      }
-      mac_block(acc, Cd, D, U);
-      cnt += WB;
-      if (cnt >= 96) { renorm(acc); cnt = 0; }
-      if (u + 1 > u_hi) break;
-#pragma unroll
-      for (int e = 0; e < WB; e++) D[e] = Lp[(int64_t)(WB * (u + 1) + e) * P];
-      {
-        const int32_t* cp = Cp + WB * (q - u - 1);
-#pragma unroll
-        for (int e = 0; e < WB; e++) Cd[e] = cp[e];
-      }
-      mac_block(acc, Cd, U, D);
-      cnt += WB;
-      if (cnt >= 96) { renorm(acc); cnt = 0; }
-    }
+    accum_block(acc, cnt, Cb + kk.coff + (int64_t)(c - k) * kk.CW, nC, Lb + kk.loff,
+                (int64_t)kk.LW * kk.R * 4, rr - k, kk.R, nL, q);
   }
   if (!active) return;
   const int lr = r - c;
   int64_t* Kcol = Kc + cc.koff;
-  int64_t v = 0;
-  if (q > 0) v = Kcol[((int64_t)rd * cc.nb + q) * cc.R + lr];
-  int32_t* Ap = A + cc.aoff + (int64_t)(WB * q) * cc.R + lr;
-#pragma unroll
-  for (int m = 0; m < WB; m++) {
-    v += (int64_t)Ap[(int64_t)m * cc.R] - acc[m];
-    const int32_t d = balanced29(v);
-    Ap[(int64_t)m * cc.R] = d;
-    v = (v - d) >> DB;
-  }
-  v -= acc[WB];
-  if (q + 1 < cc.nb) Kcol[((int64_t)(rd ^ 1) * cc.nb + q + 1) * cc.R + lr] = v;
-  else if (v != 0) atomicOr(&flags[0], 1);
+  apply_block(acc, A + cc.aoff + (int64_t)(WB * q) * cc.R + lr, cc.R,
+              q > 0 ? Kcol + ((int64_t)rd * cc.nb + q) * cc.R + lr : nullptr,
+              q + 1 < cc.nb ? Kcol + ((int64_t)(rd ^ 1) * cc.nb + q + 1) * cc.R + lr : nullptr, flags);
 }
 
-// Column c after all its updates: normalise A_rc (folding pending block
-// carries of buffer rd), C = RNE(A / 2^h), written as balanced digits (for
-// the update) and as standard magnitude digits (for the division); the pivot
-// row also stores |d| 2^sh normalised for the division.  One thread per row.
+struct FinOut {
+  int nbal;       // balanced digits of the result (top nonzero + 1)
+  int nstd;       // standard digits of |result|
+  int neg;        // sign of the result
+  int bits;       // bit length of |result|
+  uint32_t topv;  // top standard digit
+};
+
+// Value = sum_s A[s as] 2^(29 s) + sum_{q >= 1} K[q ks] 2^(29 16 q) (lazy
+// digits with pending block carries, W a multiple of 16).  Writes RNE(value /
+// 2^h) as balanced digits to Cr[0..cap) and as standard digits of its
+// magnitude to Sr[0..cap) (both zero filled).  One thread; digits are read in
+// blocks of 16 so that the loads of a block are in flight together.  Pass 1
+// finds the sign, pass 2 repeats the carry chain and streams the magnitude
+// through the rounding shift.
+__device__ FinOut finalize_entry(const int32_t* Ap, int64_t as, int W, const int64_t* Kp, int64_t ks,
+                                 int h, int32_t* Cr, uint32_t* Sr, int cap, int32_t* flags) {
+  const int nbk = W / WB;
+  int64_t v = 0;
+  int topneg = 0;
+  for (int q = 0; q < nbk; q++) {
+    int32_t a[WB];
+#pragma unroll
+    for (int m = 0; m < WB; m++) a[m] = Ap[(int64_t)(q * WB + m) * as];
+    if (q > 0) v += Kp[(int64_t)q * ks];
+#pragma unroll
+    for (int m = 0; m < WB; m++) {
+      v += a[m];
+      const int32_t d = balanced29(v);
+      v = (v - d) >> DB;
+      if (d != 0) topneg = d < 0;
+    }
+  }
+  if (v != 0) atomicOr(&flags[0], 2);
+  const bool neg = topneg != 0;
+  const int hq = h / DB, hb = h % DB;
+  const int hbit_digit = (h - 1) / DB, hbit = (h - 1) % DB;
+  int64_t bor = 0, rc = 0, bc = 0;
+  int half = 0, sticky = 0, nout = 0, ctop = -1, stop = -1;
+  uint32_t prev = 0, stopv = 0;
+  auto put = [&](uint32_t so) {
+    if (nout >= cap) {
+      if (so) atomicOr(&flags[0], 16);
+      return;
+    }
+    Sr[nout] = so;
+    if (so) { stop = nout; stopv = so; }
+    int64_t y = (int64_t)so + bc;
+    if (y >= (int64_t(1) << 28)) { y -= RADIX; bc = 1; } else bc = 0;
+    const int32_t bd = (int32_t)(neg ? -y : y);
+    Cr[nout] = bd;
+    if (bd) ctop = nout;
+    nout++;
+  };
+  auto feed = [&](int s, uint32_t u) {
+    if (s == hbit_digit) {
+      half = (u >> hbit) & 1;
+      if (hbit > 0 && (u & ((1u << hbit) - 1))) sticky = 1;
+    } else if (s < hbit_digit && u) {
+      sticky = 1;
+    }
+    if (s > hq) {
+      const uint32_t o = (prev >> hb) | (hb ? ((u << (DB - hb)) & (uint32_t)(RADIX - 1)) : 0u);
+      if (s == hq + 1) rc = (half && (sticky || (o & 1))) ? 1 : 0;
+      const int64_t x = (int64_t)o + rc;
+      rc = x >> DB;
+      put((uint32_t)(x & (RADIX - 1)));
+    }
+    prev = u;
+  };
+  v = 0;
+  for (int q = 0; q < nbk; q++) {
+    int32_t a[WB];
+#pragma unroll
+    for (int m = 0; m < WB; m++) a[m] = Ap[(int64_t)(q * WB + m) * as];
+    if (q > 0) v += Kp[(int64_t)q * ks];
+    for (int m = 0; m < WB; m++) {
+      v += a[m];
+      const int32_t d = balanced29(v);
+      v = (v - d) >> DB;
+      const int64_t x = (int64_t)(neg ? -d : d) + bor;
+      bor = x >> DB;
+      feed(q * WB + m, (uint32_t)(x & (RADIX - 1)));
+    }
+  }
+  feed(W, 0u);
+  if (rc) put((uint32_t)rc);
+  if (bc) {
+    if (nout < cap) { Sr[nout] = 0; Cr[nout] = neg ? -1 : 1; ctop = nout; nout++; }
+    else atomicOr(&flags[0], 16);
+  }
+  for (int i = nout; i < cap; i++) { Cr[i] = 0; Sr[i] = 0; }
+  FinOut f;
+  f.nbal = ctop + 1;
+  f.nstd = stop + 1;
+  f.neg = neg ? 1 : 0;
+  f.bits = stop < 0 ? 0 : DB * stop + (32 - __clz(stopv));
+  f.topv = stopv;
+  return f;
+}
+
+// Column c after all its updates: C = RNE(A / 2^h) for every row (balanced
+// digits for the update, standard magnitude digits for the division); the
+// pivot row also stores |d| 2^sh normalised for the division.
 __global__ void __launch_bounds__(64) k_finalize(const ColInfo* __restrict__ cols, int N, int c,
                                                  int rd, int h, int32_t* __restrict__ A,
                                                  const int64_t* __restrict__ Kc,
@@ -205,119 +332,31 @@ __global__ void __launch_bounds__(64) k_finalize(const ColInfo* __restrict__ col
   if (r >= N) return;
   const ColInfo cc = cols[c];
   const int lr = r - c;
-  const int W = cc.W;
-  int32_t* Ap = A + cc.aoff + lr;
-  const int64_t* Kcol = Kc + cc.koff;
-  // pass 1: balanced normalisation in place
-  int64_t v = 0;
-  int top = -1;
-  for (int s = 0; s < W; s++) {
-    if (s > 0 && (s % WB) == 0) v += Kcol[((int64_t)rd * cc.nb + s / WB) * cc.R + lr];
-    v += Ap[(int64_t)s * cc.R];
-    const int32_t d = balanced29(v);
-    Ap[(int64_t)s * cc.R] = d;
-    v = (v - d) >> DB;
-    if (d != 0) top = s;
-  }
-  if (v != 0) atomicOr(&flags[0], 2);
-  const bool neg = top >= 0 && Ap[(int64_t)top * cc.R] < 0;
-  // pass 2: |A| as standard digits, streamed through the RNE shift by h bits
-  const int hq = h / DB, hb = h % DB;
-  const int hbit_digit = (h - 1) / DB, hbit = (h - 1) % DB;
-  int64_t bor = 0;              // carry while converting balanced -> standard
-  int half = 0, sticky = 0;
-  uint32_t prev = 0;            // standard digit s-1 (for the shifted output)
-  int64_t rc = 0;               // RNE increment carry through the output
-  int64_t bc = 0;               // balanced conversion carry of the output
-  int nout = 0;
-  const int64_t CW = cc.CW;
-  int32_t* Crow = Cb + cc.coff + (int64_t)lr * CW;
-  uint32_t* Srow = S + cc.soff + (int64_t)lr * CW;
-  int ctop = -1, stop = -1;
-  uint32_t stopv = 0;
-  bool inc = false;
-  auto emit = [&](uint32_t o) {
-    // o: output standard digit before the RNE increment
-    if (nout == 0) {
-      inc = half && (sticky || (o & 1));
-      rc = inc ? 1 : 0;
-    }
-    int64_t x = (int64_t)o + rc;
-    uint32_t so = (uint32_t)(x & (RADIX - 1));
-    rc = x >> DB;
-    Srow[nout] = so;
-    if (so) { stop = nout; stopv = so; }
-    int64_t y = (int64_t)so + bc;
-    if (y >= (int64_t(1) << 28)) { y -= RADIX; bc = 1; } else bc = 0;
-    const int32_t bd = (int32_t)(neg ? -y : y);
-    Crow[nout] = bd;
-    if (bd) ctop = nout;
-    nout++;
-  };
-  for (int s = 0; s <= W; s++) {
-    uint32_t u = 0;
-    if (s < W) {
-      int64_t a = Ap[(int64_t)s * cc.R];
-      int64_t x = (neg ? -a : a) + bor;
-      u = (uint32_t)(x & (RADIX - 1));
-      bor = x >> DB;
-    }
-    if (s == hbit_digit) {
-      half = (u >> hbit) & 1;
-      if (hbit > 0 && (u & ((1u << hbit) - 1))) sticky = 1;
-    } else if (s < hbit_digit && u) {
-      sticky = 1;
-    }
-    if (s > hq) emit((prev >> hb) | (hb ? ((u << (DB - hb)) & (uint32_t)(RADIX - 1)) : 0u));
-    prev = u;
-  }
-  // flush: the increment carry and the balanced carry may add digits
-  if (rc || bc) {
-    int64_t x = rc;
-    rc = 0;
-    uint32_t so = (uint32_t)x;
-    if (nout < CW) {
-      Srow[nout] = so;
-      if (so) { stop = nout; stopv = so; }
-      int64_t y = (int64_t)so + bc;
-      if (y >= (int64_t(1) << 28)) { y -= RADIX; bc = 1; } else bc = 0;
-      const int32_t bd = (int32_t)(neg ? -y : y);
-      Crow[nout] = bd;
-      if (bd) ctop = nout;
-      nout++;
-    }
-    if (bc && nout < CW) {
-      Srow[nout] = 0;
-      Crow[nout] = neg ? -1 : 1;
-      ctop = nout;
-      nout++;
-    }
-  }
-  for (int i = nout; i < CW; i++) { Crow[i] = 0; Srow[i] = 0; }
+  uint32_t* Srow = S + cc.soff + (int64_t)lr * cc.CW;
+  const FinOut f = finalize_entry(A + cc.aoff + lr, cc.R, cc.W,
+                                  Kc + cc.koff + (int64_t)rd * cc.nb * cc.R + lr, cc.R, h,
+                                  Cb + cc.coff + (int64_t)lr * cc.CW, Srow, cc.CW, flags);
   const int64_t ti = tri_index(N, c, r);
-  nCw[ti] = ctop + 1;
-  nCs[ti] = stop + 1;
-  const int bits = stop < 0 ? 0 : DB * stop + (32 - __clz(stopv));
-  b32C[ti] = (bits + 31) / 32;
+  nCw[ti] = f.nbal;
+  nCs[ti] = f.neg ? -f.nstd : f.nstd;
+  b32C[ti] = (f.bits + 31) / 32;
   if (r == c) {
-    // pivot: d_c = C_c[c]
-    if (stop < 0 || neg) {
+    if (f.nstd == 0 || f.neg) {
       atomicMin(&flags[1], c);
-      if (stop >= 0 && neg) atomicAdd(&flags[2], 1);
+      if (f.nstd > 0 && f.neg) atomicAdd(&flags[2], 1);
     }
-    if (stop >= 0) {
-      // |d| shifted left so that its top digit has bit 28 set
-      const int sh = 28 - (31 - __clz(stopv));
+    if (f.nstd > 0) {
+      const int sh = 28 - (31 - __clz(f.topv));
       uint32_t* Dp = Dd + cc.doff;
       uint32_t carry = 0;
-      for (int i = 0; i <= stop; i++) {
-        uint64_t x = ((uint64_t)Srow[i] << sh) | carry;
+      for (int i = 0; i < f.nstd; i++) {
+        const uint64_t x = ((uint64_t)Srow[i] << sh) | carry;
         Dp[i] = (uint32_t)(x & (RADIX - 1));
         carry = (uint32_t)(x >> DB);
       }
-      dinfo[4 * c] = stop + 1;
+      dinfo[4 * c] = f.nstd;
       dinfo[4 * c + 1] = sh;
-      dinfo[4 * c + 2] = neg ? 1 : 0;
+      dinfo[4 * c + 2] = f.neg;
     } else {
       dinfo[4 * c] = 0;
       dinfo[4 * c + 1] = 0;
@@ -326,67 +365,43 @@ __global__ void __launch_bounds__(64) k_finalize(const ColInfo* __restrict__ col
   }
 }
 
-// L_c[r] = RNE(C_c[r] 2^h / d_c) for one row per 64-lane workgroup: schoolbook
-// long division in radix 2^29 with a lazily normalised int64 remainder in
-// LDS.  Each quotient digit is estimated from the top three remainder digits
-// against the top three divisor digits in float64 (error < 1/2 + 2^-20), so
-// quotient digits are signed and the remainder stays within (1/2 + eps) d;
-// the final remainder decides the rounding (ties to even).
-__global__ void __launch_bounds__(64) k_divide(const ColInfo* __restrict__ cols, int N, int c,
-                                               int h, const uint32_t* __restrict__ S,
-                                               const uint32_t* __restrict__ Dd,
-                                               const int32_t* __restrict__ dinfo,
-                                               const int32_t* __restrict__ Cb,
-                                               const int32_t* __restrict__ nCs,
-                                               int32_t* __restrict__ Lb, int32_t* __restrict__ nLw,
-                                               int32_t* __restrict__ flags) {
-  extern __shared__ int64_t smem[];
-  const int r = c + 1 + blockIdx.x;
+// out = RNE(+-|num| 2^h / |d|) for one 64-lane workgroup: schoolbook long
+// division in radix 2^29 with a lazily normalised int64 remainder in LDS.
+// num: standard digits Sr[0..ns) of its magnitude, sign negN; divisor:
+// standard digits Dp[0..nd) of |d| 2^sh (top digit >= 2^28), sign negd.  Each
+// quotient digit is estimated from the top three remainder digits against the
+// top three divisor digits in float64 (error < 1/2 + 2^-20), so quotient
+// digits are signed and the remainder stays within (1/2 + eps) |d|; the final
+// remainder decides the rounding (ties to even).  Writes `cap` balanced
+// digits to out[j * os] (zero filled) and returns the digit count.
+__device__ int divide_entry(int64_t* smem, const uint32_t* Sr, int ns, int negN,
+                            const uint32_t* Dp, int nd, int sh, int negd, int h, int32_t* out,
+                            int64_t os, int cap, int32_t* out2, int64_t os2, int32_t* flags) {
   const int lane = threadIdx.x;
-  const ColInfo cc = cols[c];
-  const int nd = dinfo[4 * c], sh = dinfo[4 * c + 1], negd = dinfo[4 * c + 2];
-  const int64_t ti = tri_index(N, c, r);
-  const int ns = nCs[ti];
-  const int lr = r - c;
-  int32_t* Lp = Lb + cc.loff + lr;
-  const int64_t P = cc.R;
-  const int LW = cc.LW;
-  // sign of C_c[r]: top balanced digit
-  const int32_t* Crow = Cb + cc.coff + (int64_t)lr * cc.CW;
-  if (nd == 0) {  // zero pivot: nothing to divide by
-    for (int j = lane; j < LW; j += 64) Lp[(int64_t)j * P] = 0;
-    if (lane == 0) { nLw[ti] = 0; atomicOr(&flags[0], 4); }
-    return;
+  if (nd == 0) {
+    for (int j = lane; j < cap; j += 64) { out[(int64_t)j * os] = 0; if (out2) out2[(int64_t)j * os2] = 0; }
+    if (lane == 0) atomicOr(&flags[0], 4);
+    return 0;
   }
   const int Sbits = h + sh, Sq = Sbits / DB, Sb = Sbits % DB;
   const int nu = ns == 0 ? 0 : Sq + ns + 1;
-  if (nu < nd) {  // quotient below 2/2^29: rounds to zero
-    for (int j = lane; j < LW; j += 64) Lp[(int64_t)j * P] = 0;
-    if (lane == 0) nLw[ti] = 0;
-    return;
+  if (nu < nd) {  // quotient below 2 / 2^29: rounds to zero
+    for (int j = lane; j < cap; j += 64) { out[(int64_t)j * os] = 0; if (out2) out2[(int64_t)j * os2] = 0; }
+    return 0;
   }
   int64_t* rem = smem;                       // nu + 3
   int64_t* dd = rem + (nu + 3);              // nd + 1 (dd[nd] = 0)
   int64_t* qd = dd + (nd + 1);               // nu - nd + 2
-  __shared__ int64_t qslot;
-  __shared__ int negC;
-  const uint32_t* Srow = S + cc.soff + (int64_t)lr * cc.CW;
-  const uint32_t* Dp = Dd + cc.doff;
   for (int i = lane; i <= nd; i += 64) dd[i] = i < nd ? (int64_t)Dp[i] : 0;
   for (int s = lane; s < nu + 3; s += 64) {
     int64_t x = 0;
     if (s >= Sq && s < nu) {
-      const int i = s - Sq;  // source digit index of the shifted value
-      uint64_t a = i < ns ? (uint64_t)Srow[i] : 0;
-      uint64_t b = (i >= 1 && i - 1 < ns) ? (uint64_t)Srow[i - 1] : 0;
+      const int i = s - Sq;
+      const uint64_t a = i < ns ? (uint64_t)Sr[i] : 0;
+      const uint64_t b = (i >= 1 && i - 1 < ns) ? (uint64_t)Sr[i - 1] : 0;
       x = (int64_t)(((a << Sb) | (Sb ? (b >> (DB - Sb)) : 0)) & (RADIX - 1));
     }
     rem[s] = x;
-  }
-  if (lane == 0) {
-    int t = -1;
-    for (int i = cc.CW - 1; i >= 0; i--) if (Crow[i] != 0) { t = i; break; }
-    negC = (t >= 0 && Crow[t] < 0) ? 1 : 0;
   }
   const int jmax = nu - nd;
   for (int j = lane; j <= jmax + 1; j += 64) qd[j] = 0;
@@ -394,61 +409,77 @@ __global__ void __launch_bounds__(64) k_divide(const ColInfo* __restrict__ cols,
   const double R = (double)RADIX;
   const double D3 = (double)dd[nd - 1] * R * R + (nd >= 2 ? (double)dd[nd - 2] * R : 0.0) +
                     (nd >= 3 ? (double)dd[nd - 3] : 0.0);
+  const int64_t d1 = dd[nd - 1], d2 = nd >= 2 ? dd[nd - 2] : 0;
+  // The top of the remainder window, positions t-2 .. t+1 (t = j + nd), is
+  // kept in registers of every lane (w0 .. w3, identical in all lanes); the
+  // digits below t-2 live in LDS and take the bulk of each subtraction.
+  int t = jmax + nd;
+  int64_t w0 = t - 2 >= 0 ? rem[t - 2] : 0, w1 = rem[t - 1], w2 = rem[t], w3 = rem[t + 1];
   int since = 0;
   for (int j = jmax; j >= 0; j--) {
-    if (lane == 0) {
-      const int t = j + nd;
-      rem[t] += rem[t + 1] << DB;
-      rem[t + 1] = 0;
-      for (int s = t - 2; s < t; s++) {
-        if (s < 0) continue;
-        int64_t cy = rem[s] >> DB;
-        rem[s] -= cy << DB;
-        rem[s + 1] += cy;
-      }
-      const double T = (double)rem[t] * R * R + (t >= 1 ? (double)rem[t - 1] * R : 0.0) +
-                       (t >= 2 ? (double)rem[t - 2] : 0.0);
-      const int64_t qq = (int64_t)rint(T * R / D3);
-      qd[j] = qq;
-      qslot = qq;
-    }
-    __syncthreads();
-    const int64_t qq = qslot;
+    t = j + nd;
+    w2 += w3 << DB;
+    w3 = 0;
+    int64_t cy = w0 >> DB;
+    w0 -= cy << DB;
+    w1 += cy;
+    cy = w1 >> DB;
+    w1 -= cy << DB;
+    w2 += cy;
+    const double T = (double)w2 * R * R + (double)w1 * R + (double)w0;
+    const int64_t qq = (int64_t)rint(T * R / D3);
+    if (lane == 0) qd[j] = qq;
+    w1 -= qq * d1;
+    w0 -= qq * d2;
     if (qq != 0)
-      for (int i = lane; i < nd; i += 64) rem[j + i] -= qq * dd[i];
+      for (int i = lane; i < nd - 2; i += 64) rem[j + i] -= qq * dd[i];
     __syncthreads();
+    if (j == 0) break;
     if (++since == 12) {
       since = 0;
-      for (int s = j + lane; s < j + nd - 1; s += 64) {
+      // one carry step on the LDS digits that stay below the next window
+      for (int s = j - 1 + lane; s <= t - 5; s += 64) {
         const int64_t x = rem[s];
-        const int64_t cy = x >> DB;
-        if (cy) {
-          atomicAdd((unsigned long long*)&rem[s], (unsigned long long)(-(cy << DB)));
-          atomicAdd((unsigned long long*)&rem[s + 1], (unsigned long long)cy);
+        const int64_t c2 = x >> DB;
+        if (c2) {
+          atomicAdd((unsigned long long*)&rem[s], (unsigned long long)(-(c2 << DB)));
+          atomicAdd((unsigned long long*)&rem[s + 1], (unsigned long long)c2);
         }
       }
       __syncthreads();
     }
+    // slide the window down by one position
+    w3 = w2;
+    w2 = w1;
+    w1 = w0;
+    w0 = t - 3 >= 0 ? rem[t - 3] : 0;
   }
-  // rounding decision from the final remainder Rem = window [0, nd]
+  // final remainder: window back to LDS (positions nd-2 .. nd+1)
+  if (lane == 0) {
+    if (nd - 2 >= 0) rem[nd - 2] = w0;
+    rem[nd - 1] = w1;
+    rem[nd] = w2;
+    rem[nd + 1] = w3;
+  }
+  __syncthreads();
   if (lane == 0) {
     rem[nd] += rem[nd + 1] << DB;
     rem[nd + 1] = 0;
     for (int s = nd - 2; s < nd; s++) {
       if (s < 0) continue;
-      int64_t cy = rem[s] >> DB;
+      const int64_t cy = rem[s] >> DB;
       rem[s] -= cy << DB;
       rem[s + 1] += cy;
     }
     const double T = (double)rem[nd] * R * R + (nd >= 1 ? (double)rem[nd - 1] * R : 0.0) +
                      (nd >= 2 ? (double)rem[nd - 2] : 0.0);
-    const double f = T * R / D3;   // Rem / d'
+    const double f = T * R / D3;   // remainder / divisor
     int adj = 0;
     const double af = fabs(f);
     if (fabs(2.0 * af - 1.0) > 1e-6) {
       adj = af > 0.5 ? (f > 0 ? 1 : -1) : 0;
     } else {
-      // exact comparison of 2 Rem with +d' and -d'
+      // exact comparison of 2 rem with +d and -d
       int64_t v1 = 0, v2 = 0;
       int nz1 = 0, nz2 = 0;
       for (int s = 0; s <= nd + 1; s++) {
@@ -474,26 +505,192 @@ __global__ void __launch_bounds__(64) k_divide(const ColInfo* __restrict__ cols,
   // quotient digits -> balanced digits (one carry step suffices: |q| <= 2^30)
   const int nq = jmax + 2;
   int mytop = -1;
-  const int sgn = (negC ^ negd) ? -1 : 1;
-  for (int j = lane; j < LW; j += 64) {
-    int64_t out = 0;
+  const int sgn = (negN ^ negd) ? -1 : 1;
+  for (int j = lane; j < cap; j += 64) {
+    int64_t o = 0;
     if (j < nq) {
       const int64_t x = j <= jmax ? qd[j] : 0;
-      out = balanced29(x);
+      o = balanced29(x);
       if (j >= 1 && j - 1 <= jmax) {
         const int64_t y = qd[j - 1];
-        out += (y - balanced29(y)) >> DB;
+        o += (y - balanced29(y)) >> DB;
       }
     }
-    const int32_t o = (int32_t)(sgn * out);
-    Lp[(int64_t)j * P] = o;
-    if (o != 0) mytop = j;
+    const int32_t od = (int32_t)(sgn * o);
+    out[(int64_t)j * os] = od;
+    if (out2) out2[(int64_t)j * os2] = od;
+    if (od != 0) mytop = j;
   }
-  const int t = wave_max(mytop);
-  if (lane == 0) {
-    nLw[ti] = t + 1;
-    if (t + 1 > LW - 32) atomicOr(&flags[0], 8);
+  if (nq > cap && lane == 0) {
+    for (int j = cap; j < nq; j++) {
+      const int64_t x = j <= jmax ? qd[j] : 0;
+      int64_t o = balanced29(x);
+      if (j - 1 <= jmax) { const int64_t y = qd[j - 1]; o += (y - balanced29(y)) >> DB; }
+      if (o != 0) atomicOr(&flags[0], 8);
+    }
   }
+  return wave_max(mytop) + 1;
+}
+
+// L_c[r] = RNE(C_c[r] 2^h / d_c), one row per 64-lane workgroup; written in
+// the column layout (for the trailing update and forward solves) and in the
+// row layout L^T (for backward solves).
+__global__ void __launch_bounds__(64) k_divide(const ColInfo* __restrict__ cols, int N, int c,
+                                               int h, const uint32_t* __restrict__ S,
+                                               const uint32_t* __restrict__ Dd,
+                                               const int32_t* __restrict__ dinfo,
+                                               const int32_t* __restrict__ nCs,
+                                               int32_t* __restrict__ Lb, int32_t* __restrict__ LTb,
+                                               int32_t* __restrict__ nLw, int32_t* __restrict__ flags) {
+  extern __shared__ int64_t smem[];
+  const int r = c + 1 + blockIdx.x;
+  const ColInfo cc = cols[c];
+  const ColInfo cr = cols[r];
+  const int64_t ti = tri_index(N, c, r);
+  const int nsg = nCs[ti];
+  const int lr = r - c;
+  const int n = divide_entry(smem, S + cc.soff + (int64_t)lr * cc.CW, nsg < 0 ? -nsg : nsg, nsg < 0,
+                             Dd + cc.doff, dinfo[4 * c], dinfo[4 * c + 1], dinfo[4 * c + 2], h,
+                             Lb + cc.loff + lr, cc.R, cc.LW, LTb + cr.ltoff + c, cr.PT, flags);
+  if (threadIdx.x == 0) {
+    nLw[ti] = n;
+    if (n > cc.LW - 2 * WB) atomicOr(&flags[0], 8);
+  }
+}
+
+// v_i = RNE(y_i 2^K / m) with the common divisor m (standard digits of m 2^sh
+// in md[0..nd)); y_i as standard magnitude digits (us rows, signed nUs)
+__global__ void __launch_bounds__(64) k_vscale(int K, const uint32_t* __restrict__ us,
+                                               const int32_t* __restrict__ nUs, int VW,
+                                               const uint32_t* __restrict__ md, int nd, int sh,
+                                               int32_t* __restrict__ out, int32_t* __restrict__ flags) {
+  extern __shared__ int64_t smem[];
+  const int i = blockIdx.x;
+  const int nsg = nUs[i];
+  divide_entry(smem, us + (int64_t)i * VW, nsg < 0 ? -nsg : nsg, nsg < 0, md, nd, sh, 0, K,
+               out + (int64_t)i * VW, 1, VW, nullptr, 0, flags);
+}
+
+// ---------------------------------------------------------------- solves
+// Accumulators of a vector: VA digit planes of Npad rows (value of row i =
+// sum_s acc[s Npad + i] 2^(29 s) plus pending block carries), the same lazy
+// format and double-buffered carries as the matrix columns.
+
+// acc_i = src_i * 2^Sbits (src: N rows of VW balanced digits); carries cleared
+__global__ void k_vinit(int32_t* __restrict__ acc, int64_t* __restrict__ kc,
+                        const int32_t* __restrict__ src, int N, int Npad, int VA, int nbA, int VW,
+                        int Sbits) {
+  const int Sq = Sbits / DB, Sb = Sbits % DB;
+  const int64_t n = (int64_t)VA * Npad;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int s = (int)(idx / Npad), i = (int)(idx - (int64_t)s * Npad);
+    int64_t v = 0;
+    if (i < N) {
+      const int j = s - Sq;
+      if (j >= 0 && j < VW) v += (((int64_t)src[(int64_t)i * VW + j]) << Sb) & (RADIX - 1);
+      if (j - 1 >= 0 && j - 1 < VW) v += (((int64_t)src[(int64_t)i * VW + j - 1]) << Sb) >> DB;
+    }
+    acc[idx] = (int32_t)v;
+  }
+  const int64_t nk = (int64_t)2 * nbA * Npad;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < nk;
+       idx += (int64_t)gridDim.x * blockDim.x)
+    kc[idx] = 0;
+}
+
+// acc_i -= sum_{k0 <= k < k1} V_k[i] u_k for rows i in [i_lo, i_hi):
+//   forward (bwd = 0): V_k[i] = L_k[i] (column layout), rows i > k;
+//   backward (bwd = 1): V_k[i] = L_i[k] (row layout L^T), rows i < k.
+// u_k (uniform): row k of ub (VW balanced digits, nU[k] used).
+__global__ void __launch_bounds__(256) k_vupdate(const ColInfo* __restrict__ cols, int N, int bwd,
+                                                 int k0, int k1, int i_lo, int i_hi, int rd,
+                                                 int32_t* __restrict__ acc, int64_t* __restrict__ kc,
+                                                 int Npad, int nbA, const int32_t* __restrict__ ub,
+                                                 const int32_t* __restrict__ nU, int VW,
+                                                 const int32_t* __restrict__ Lb,
+                                                 const int32_t* __restrict__ LTb,
+                                                 const int32_t* __restrict__ nLw, int LWT,
+                                                 int32_t* __restrict__ flags) {
+  const int wave = uni(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int T = (i_hi - i_lo + 63) / 64;
+  const int it = blockIdx.x * 4 + wave;
+  if (it >= T * nbA) return;
+  const int q = uni(it / T);
+  const int t = uni(it - q * T);
+  const int i = i_lo + 64 * t + lane;
+  const bool active = i < i_hi;
+  const int ii = active ? i : i_hi - 1;
+  int64_t a[WB + 1];
+#pragma unroll
+  for (int m = 0; m <= WB; m++) a[m] = 0;
+  int cnt = 0;
+  for (int k = k0; k < k1; k++) {
+    const int nC = min(uni(nU[k]), VW - WB);
+    int nLl, lo, cap, P;
+    const int32_t* Lp;
+    int64_t nbytes;
+    const ColInfo kk = cols[k];
+    if (!bwd) {
+      nLl = active ? nLw[tri_index(N, k, ii)] : 0;
+      Lp = Lb + kk.loff;
+      nbytes = (int64_t)kk.LW * kk.R * 4;
+      lo = ii - k;
+      P = kk.R;
+      cap = kk.LW;
+    } else {
+      nLl = active ? nLw[tri_index(N, ii, k)] : 0;
+      Lp = LTb + kk.ltoff;
+      nbytes = (int64_t)LWT * kk.PT * 4;
+      lo = ii;
+      P = kk.PT;
+      cap = cols[ii].LW;
+    }
+    const int nL = min(uni(wave_max(min(nLl, cap - 2 * WB))), LWT - 2 * WB);
+    accum_block(a, cnt, ub + (int64_t)k * VW, nC, Lp, nbytes, lo, P, nL, q);
+  }
+  if (!active) return;
+  apply_block(a, acc + (int64_t)(WB * q) * Npad + i, Npad,
+              q > 0 ? kc + ((int64_t)rd * nbA + q) * Npad + i : nullptr,
+              q + 1 < nbA ? kc + ((int64_t)(rd ^ 1) * nbA + q + 1) * Npad + i : nullptr, flags);
+}
+
+// u_k = RNE(acc_k / 2^h) -> ub row k (balanced) and us row k (standard
+// magnitude), widths nU[k] and signed nUs[k]; optionally copied to out row k.
+__global__ void __launch_bounds__(64) k_vfinalize(int k, int rd, int h, int32_t* __restrict__ acc,
+                                                  const int64_t* __restrict__ kc, int Npad, int VA,
+                                                  int nbA, int32_t* __restrict__ ub,
+                                                  uint32_t* __restrict__ us, int32_t* __restrict__ nU,
+                                                  int32_t* __restrict__ nUs, int VW,
+                                                  int32_t* __restrict__ out,
+                                                  int32_t* __restrict__ flags) {
+  if (threadIdx.x == 0) {
+    const FinOut f = finalize_entry(acc + k, Npad, VA, kc + (int64_t)rd * nbA * Npad + k, Npad, h,
+                                    ub + (int64_t)k * VW, us + (int64_t)k * VW, VW, flags);
+    nU[k] = f.nbal;
+    nUs[k] = f.neg ? -f.nstd : f.nstd;
+    if (f.nbal > VW - WB) atomicOr(&flags[0], 32);
+  }
+  if (out) {
+    __syncthreads();
+    for (int j = threadIdx.x; j < VW; j += 64) out[(int64_t)k * VW + j] = ub[(int64_t)k * VW + j];
+  }
+}
+
+// w_k = RNE(z_k 2^h / d_k) for every k (one 64-lane workgroup each)
+__global__ void __launch_bounds__(64) k_vdivide(const ColInfo* __restrict__ cols, int h,
+                                                const uint32_t* __restrict__ us,
+                                                const int32_t* __restrict__ nUs,
+                                                const uint32_t* __restrict__ Dd,
+                                                const int32_t* __restrict__ dinfo, int VW,
+                                                int32_t* __restrict__ wb, int32_t* __restrict__ flags) {
+  extern __shared__ int64_t smem[];
+  const int k = blockIdx.x;
+  const int nsg = nUs[k];
+  divide_entry(smem, us + (int64_t)k * VW, nsg < 0 ? -nsg : nsg, nsg < 0, Dd + cols[k].doff,
+               dinfo[4 * k], dinfo[4 * k + 1], dinfo[4 * k + 2], h, wb + (int64_t)k * VW, 1, VW,
+               nullptr, 0, flags);
 }
 
 // exact ceil(bits/32) of every L entry (for the algorithmic work count)
@@ -576,16 +773,51 @@ hipError_t launch_finalize(const Plan& P, const DevPtrs& D, int c, int rd, hipSt
                      D.A, D.Kc, D.C, D.S, D.D, D.dinfo, D.nC, D.nCs, D.b32C, D.flags);
   return hipGetLastError();
 }
+// LDS of divide_entry: remainder nu + 3, divisor nd + 1, quotient nu - nd + 2
+static size_t divide_shm(int h, int num_cap, int den_cap) {
+  const int Sq = (h + 28) / DB + 1;
+  const int nu_max = Sq + num_cap + 1;
+  return sizeof(int64_t) * (size_t)((nu_max + 3) + (den_cap + 3) + (nu_max + 3));
+}
 hipError_t launch_divide(const Plan& P, const DevPtrs& D, int c, hipStream_t s) {
   const int rows = P.N - c - 1;
   if (rows <= 0) return hipSuccess;
   const ColInfo& cc = P.cols[c];
-  // rem: nu + 3 with nu <= Sq + CW + 1; dd: W + 2; qd: nu + 2
-  const int Sq = (P.h + 28) / DB + 1;
-  const int nu_max = Sq + cc.CW + 1;
-  const size_t shm = sizeof(int64_t) * (size_t)((nu_max + 3) + (cc.W + 3) + (nu_max + 3));
-  hipLaunchKernelGGL(k_divide, dim3(rows), dim3(64), shm, s, D.cols, P.N, c, P.h, D.S, D.D,
-                     D.dinfo, D.C, D.nCs, D.L, D.nL, D.flags);
+  hipLaunchKernelGGL(k_divide, dim3(rows), dim3(64), divide_shm(P.h, cc.CW, cc.W + 2), s, D.cols,
+                     P.N, c, P.h, D.S, D.D, D.dinfo, D.nCs, D.L, D.LT, D.nL, D.flags);
+  return hipGetLastError();
+}
+hipError_t launch_vinit(const Plan& P, const DevPtrs& D, const int32_t* src, int Sbits, hipStream_t s) {
+  const int64_t n = (int64_t)P.VA * P.Npad;
+  hipLaunchKernelGGL(k_vinit, dim3(blocks_for(n, 256)), dim3(256), 0, s, D.acc, D.kca, src, P.N,
+                     P.Npad, P.VA, P.VA / WB, P.VW, Sbits);
+  return hipGetLastError();
+}
+hipError_t launch_vupdate(const Plan& P, const DevPtrs& D, int bwd, int k0, int k1, int i_lo,
+                          int i_hi, int rd, hipStream_t s) {
+  if (i_hi <= i_lo || k1 <= k0) return hipSuccess;
+  const int T = (i_hi - i_lo + 63) / 64;
+  const int64_t items = (int64_t)T * (P.VA / WB);
+  hipLaunchKernelGGL(k_vupdate, dim3((int)((items + 3) / 4)), dim3(256), 0, s, D.cols, P.N, bwd, k0,
+                     k1, i_lo, i_hi, rd, D.acc, D.kca, P.Npad, P.VA / WB, D.ub, D.nU, P.VW, D.L, D.LT,
+                     D.nL, P.LWT, D.flags);
+  return hipGetLastError();
+}
+hipError_t launch_vfinalize(const Plan& P, const DevPtrs& D, int k, int rd, int32_t* out,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_vfinalize, dim3(1), dim3(64), 0, s, k, rd, P.h, D.acc, D.kca, P.Npad, P.VA,
+                     P.VA / WB, D.ub, D.us, D.nU, D.nUs, P.VW, out, D.flags);
+  return hipGetLastError();
+}
+hipError_t launch_vdivide(const Plan& P, const DevPtrs& D, hipStream_t s) {
+  hipLaunchKernelGGL(k_vdivide, dim3(P.N), dim3(64), divide_shm(P.h, P.VW, P.maxW + 2), s, D.cols,
+                     P.h, D.us, D.nUs, D.D, D.dinfo, P.VW, D.wb, D.flags);
+  return hipGetLastError();
+}
+hipError_t launch_vscale(const Plan& P, const DevPtrs& D, const uint32_t* md, int nd, int sh,
+                         int32_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_vscale, dim3(P.N), dim3(64), divide_shm(P.K, P.VW, nd + 2), s, P.K, D.us,
+                     D.nUs, P.VW, md, nd, sh, out, D.flags);
   return hipGetLastError();
 }
 hipError_t launch_gather_pivots(const Plan& P, const DevPtrs& D, int32_t* out, int ld,

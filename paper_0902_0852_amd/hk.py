@@ -15,6 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhk.so")
 
 HK_INVERSE, HK_SECANT = 0, 1
+HK_FLAG_NO_WORK_COUNT, HK_FLAG_TIME_UPDATES = 0x100, 0x200
 STATUS = {0: "HK_OK", 1: "HK_EINVAL", 2: "HK_ENOTSPD", 3: "HK_EPRECISION", 4: "HK_ENOCONV",
           5: "HK_EVERIFY", 6: "HK_EDEVICE", 7: "HK_ENOMEM"}
 
@@ -49,7 +50,8 @@ class Report(ctypes.Structure):
                 ("verified", ctypes.c_int), ("digits_verified", ctypes.c_int),
                 ("lambda_dec", ctypes.c_char * 192), ("limb_macs", ctypes.c_double),
                 ("t_factor_s", ctypes.c_double), ("t_solve_s", ctypes.c_double),
-                ("t_total_s", ctypes.c_double)]
+                ("t_total_s", ctypes.c_double), ("update_launches", ctypes.c_int),
+                ("update_ms", ctypes.c_double)]
 
 
 _lib = None
@@ -281,7 +283,8 @@ class Matrix:
                               ctypes.c_void_p(dev_x.data_ptr()), _stream(stream)))
 
 
-def smallest_eig(N, beta, K, method=HK_INVERSE, digits=45, shift_fixed=None, stream=None, ws=None):
+def smallest_eig(N, beta, K, method=HK_INVERSE, digits=45, shift_fixed=None, stream=None, ws=None,
+                 flags=0):
     """The whole method; returns (decimal string, report dict)."""
     import torch
     L = lib()
@@ -296,7 +299,7 @@ def smallest_eig(N, beta, K, method=HK_INVERSE, digits=45, shift_fixed=None, str
     if shift_fixed is not None:
         f, keep = _mpf_fixed(shift_fixed, K)
         hint = ctypes.pointer(f)
-    st = L.hk_smallest_eig(N, _rational(beta), K, method, digits, hint, ctypes.c_void_p(ws.data_ptr()),
+    st = L.hk_smallest_eig(N, _rational(beta), K, method | flags, digits, hint, ctypes.c_void_p(ws.data_ptr()),
                            ws.numel(), _stream(stream), out, 256, ctypes.byref(rep))
     _check(st)
     d = {k: getattr(rep, k) for k, _ in Report._fields_}
