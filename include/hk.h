@@ -175,6 +175,86 @@ hk_status hk_vec_import(hk_matrix m, int n, const int32_t* slen, const int64_t* 
 int64_t hk_vec_export(hk_matrix m, const void* dev_vec, int n, int32_t* slen, int64_t* off,
                       uint32_t* dig, int64_t dig_cap, hipStream_t s);
 
+/* ---- batched form ------------------------------------------------------
+   Many instances of uneven (N, beta, K) factored together: every kernel of
+   the factorisation covers all instances of the batch in one launch (work
+   items are (instance, column, row tile, digit block)), and the whole launch
+   sequence of one factorisation is captured once in a HIP graph and
+   replayed for every factorisation the drivers need.  The driver is the
+   paper's Secant iteration ("The Secant Algorithm") per instance, run in
+   lockstep, then the inertia bracket of "Interval Verification".  Callers
+   that repeat the same batch shapes may tune the panel width once with
+   hk_autotune. */
+typedef struct { int N; hk_rational beta; int prec_bits; } hk_instance;
+
+typedef struct {
+  hk_status status;
+  int factorizations;     /* factorisations this instance took part in   */
+  int verified;           /* 1 if the inertia bracket held               */
+  char lambda_dec[192];   /* lambda_1, `digits` significant digits       */
+} hk_result;
+
+typedef struct {
+  int panel;              /* panel width used                            */
+  int graph_launches;     /* batched factorisations (graph replays)      */
+  double t_build_s;       /* moments + uploads                           */
+  double t_factor_s;      /* graph replays incl. pivot read-back         */
+  double t_total_s;
+} hk_batch_report;
+
+/* Device bytes for a batch (one buffer for all instances). 0 if invalid. */
+size_t hk_batch_workspace_bytes(const hk_instance* inst, int count);
+
+/* lambda_1 of every instance.  panel = 0 takes the width from the tuning
+   cache named by the environment variable HK_TUNE_CACHE when it has an entry
+   for this batch shape, else 4.  out[count] receives the per-instance
+   results; the call returns HK_OK if every instance succeeded (otherwise the
+   first failing status).  rep may be NULL.  Synchronises s. */
+hk_status hk_eig_batched(const hk_instance* inst, int count, int digits, int panel, void* dev_ws,
+                         size_t ws_bytes, hipStream_t s, hk_result* out, hk_batch_report* rep);
+
+/* Times one batched factorisation of the given batch for each panel width
+   in {1, 2, 4, 8, 16}, stores the fastest in *best_panel and appends it to
+   the text cache file cache_path (NULL: no file) under the batch-shape key
+   (architecture, count, N bucket, K bucket).  Synchronises s. */
+hk_status hk_autotune(const hk_instance* inst, int count, void* dev_ws, size_t ws_bytes,
+                      hipStream_t s, const char* cache_path, int* best_panel);
+
+/* ---- precision-proposal network -----------------------------------------
+   A float32 MLP 3 -> 64 -> 64 -> 64 -> 2 with ReLU on the hidden layers
+   (not in the paper).  It maps the scaled features (N, beta, ln N) of an
+   instance to its scaled required precision and scaled ln lambda_1; its
+   training data come from the method itself (hk_bracket_batched).  Every
+   pointer below is a caller-owned float32 device buffer; the kernels run on
+   s and nothing is synchronised.  Parameters: one packed vector of
+   hk_mlp_nparams() floats, W1 (64x3), b1 (64), W2 (64x64), b2, W3 (64x64),
+   b3, W4 (2x64), b4 (2), matrices row-major (outputs x inputs).  X is
+   batch x 3 and Y batch x 2, row-major. */
+int hk_mlp_nparams(void);
+/* floats per sample of the activation cache (input + three hidden layers) */
+int hk_mlp_cache_floats(void);
+
+/* Y = net(X).  act_cache: NULL, or batch * hk_mlp_cache_floats() floats that
+   receive what hk_mlp_backward needs. */
+hk_status hk_mlp_forward(const float* W, const float* X, int batch, float* Y, float* act_cache,
+                         hipStream_t s);
+
+/* dW = gradient of sum(dY .* Y) over the batch with respect to W
+   (overwritten, hk_mlp_nparams() floats), from the cache of the forward pass
+   at the same W.  delta: scratch of batch * 192 floats.  Sums over the batch
+   run in a fixed order (bitwise reproducible). */
+hk_status hk_mlp_backward(const float* W, const float* act_cache, const float* dY, int batch, float* dW,
+                          float* delta, hipStream_t s);
+
+/* *loss = mean over the batch x 2 outputs of (Y - T)^2, dY = its gradient
+   with respect to Y. */
+hk_status hk_mlp_mse(const float* Y, const float* T, int batch, float* dY, float* loss, hipStream_t s);
+
+/* One Adam step (Kingma & Ba 2015, Algorithm 1) at step number step >= 1:
+   m, v are the moment estimates (start at zero), updated in place with W. */
+hk_status hk_mlp_adam_step(float* W, float* m, float* v, const float* dW, int nparams, float lr,
+                           float b1, float b2, float eps, int step, hipStream_t s);
+
 #ifdef __cplusplus
 }
 #endif

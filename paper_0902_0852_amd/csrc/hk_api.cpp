@@ -120,6 +120,7 @@ bool make_plan(int N, int64_t bnum, int64_t bden, int K, Plan& P, std::string& e
   P.o_dv1 = take(sizeof(int32_t) * (size_t)N * P.VW);
   P.o_dv2 = take(sizeof(int32_t) * (size_t)N * P.VW);
   P.o_md = take(sizeof(uint32_t) * (size_t)(P.VW + 4));
+  P.o_desc = take(sizeof(InstDesc));
   P.total = o;
   return true;
 }
@@ -155,7 +156,18 @@ DevPtrs dev_ptrs(const Plan& P, char* ws) {
   D.dv1 = (int32_t*)(ws + P.o_dv1);
   D.dv2 = (int32_t*)(ws + P.o_dv2);
   D.md = (uint32_t*)(ws + P.o_md);
+  D.desc = (InstDesc*)(ws + P.o_desc);
   return D;
+}
+
+InstDesc make_desc(const Plan& P, const DevPtrs& D) {
+  InstDesc I;
+  I.cols = D.cols; I.itemStart = D.itemStart;
+  I.A = D.A; I.Kc = D.Kc; I.C = D.C; I.S = D.S; I.L = D.L; I.LT = D.LT; I.D = D.D;
+  I.dinfo = D.dinfo; I.nC = D.nC; I.nCs = D.nCs; I.nL = D.nL; I.b32C = D.b32C; I.flags = D.flags;
+  I.X = D.X; I.xs = D.xs;
+  I.N = P.N; I.h = P.h; I.WX = P.WX; I.active = 1;
+  return I;
 }
 
 // v -> n balanced radix-2^29 digits (zero padded); false if it does not fit
@@ -180,6 +192,45 @@ static bool to_digits(const MP& v, int32_t* out, int n) {
 }
 
 void mp_to_digits(const MP& v, int32_t* out, int n) { to_digits(v, out, n); }
+
+// The whole factorisation of every instance of B (shifts and flags already in
+// place): expansion, then per panel of b columns the in-panel updates,
+// finalisations and divisions column by column, then the trailing update.
+// With evs != NULL every update launch is bracketed by HIP events.
+hipError_t enqueue_factor(const BatchView& B, int b, hipStream_t s,
+                          std::vector<std::pair<hipEvent_t, hipEvent_t>>* evs,
+                          std::vector<hipEvent_t>* pool, size_t* evi, int* n_update) {
+  auto get_ev = [&]() -> hipEvent_t {
+    if (*evi >= pool->size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      pool->push_back(e);
+    }
+    return (*pool)[(*evi)++];
+  };
+  auto timed_update = [&](int pc, int j, int rd) -> hipError_t {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (evs) { e0 = get_ev(); e1 = get_ev(); }
+    hipError_t e = hipSuccess;
+    if (e0 && e1) e = hipEventRecord(e0, s);
+    if (e == hipSuccess) e = launch_update(B, pc, b, j, rd, s);
+    if (e == hipSuccess && e0 && e1) { e = hipEventRecord(e1, s); evs->push_back({e0, e1}); }
+    if (n_update) (*n_update)++;
+    return e;
+  };
+  hipError_t e = launch_expand(B, s);
+  int Pidx = 0;
+  for (int pc = 0; pc < B.maxN && e == hipSuccess; pc += b, Pidx++) {
+    for (int j = 0; j < b && pc + j < B.maxN && e == hipSuccess; j++) {
+      const int c = pc + j;
+      if (j > 0) e = timed_update(pc, j, Pidx & 1);
+      if (e == hipSuccess) e = launch_finalize(B, c, (Pidx + (j > 0 ? 1 : 0)) & 1, s);
+      if (e == hipSuccess) e = launch_divide(B, c, s);
+    }
+    if (e == hipSuccess && pc + b < B.maxN) e = timed_update(pc, 0, Pidx & 1);
+  }
+  return e;
+}
 
 MP digits_to_mp(const int32_t* d, int n, int64_t stride) {
   // positive and negative digit parts packed separately, then subtracted
@@ -223,6 +274,15 @@ size_t hk_workspace_bytes(int N, hk_rational beta, int prec_bits, int flags) {
 
 hk_status hk_build_matrix(int N, hk_rational beta, int prec_bits, void* dev_ws, size_t ws_bytes,
                           hipStream_t s, hk_matrix* out) {
+  return hk::build_matrix_impl(N, beta, prec_bits, dev_ws, ws_bytes, s, out, nullptr);
+}
+
+}  // extern "C"
+
+namespace hk {
+// hk_build_matrix with optionally precomputed moments (moved in)
+hk_status build_matrix_impl(int N, hk_rational beta, int prec_bits, void* dev_ws, size_t ws_bytes,
+                            hipStream_t s, hk_matrix* out, std::vector<MP>* moments) {
   if (!out) return fail(HK_EINVAL, "out is NULL");
   *out = nullptr;
   hk_matrix m = new (std::nothrow) hk_matrix_s;
@@ -238,7 +298,9 @@ hk_status hk_build_matrix(int N, hk_rational beta, int prec_bits, void* dev_ws, 
   m->ws_bytes = ws_bytes;
   m->D = dev_ptrs(m->P, m->ws);
   const Plan& P = m->P;
-  if (!build_moments(N, P.p, P.q, P.K, m->X)) { delete m; return fail(HK_EPRECISION, "moment rounding undecided"); }
+  if (moments) m->X.swap(*moments);
+  else if (!build_moments(N, P.p, P.q, P.K, m->X)) { delete m; return fail(HK_EPRECISION, "moment rounding undecided"); }
+  if ((int)m->X.size() != 2 * N - 1) { delete m; return fail(HK_EINVAL, "moment count"); }
   {
     // solve guard bits: half the bit length of the largest moment's integer
     // part, rounded up to a multiple of 64
@@ -254,7 +316,12 @@ hk_status hk_build_matrix(int N, hk_rational beta, int prec_bits, void* dev_ws, 
   auto cp = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
     return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
   };
+  m->desc_host = make_desc(P, m->D);
+  m->B.ddesc = m->D.desc;
+  m->B.plans = {&m->P};
+  m->B.maxN = N;
   hipError_t e = cp(m->D.X, Xd.data(), Xd.size() * sizeof(int32_t));
+  if (e == hipSuccess) e = cp(m->D.desc, &m->desc_host, sizeof(InstDesc));
   if (e == hipSuccess) e = cp(m->D.cols, P.cols.data(), P.cols.size() * sizeof(ColInfo));
   if (e == hipSuccess) e = cp(m->D.itemStart, P.itemStart.data(), P.itemStart.size() * sizeof(int32_t));
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -262,6 +329,9 @@ hk_status hk_build_matrix(int N, hk_rational beta, int prec_bits, void* dev_ws, 
   *out = m;
   return st;
 }
+}  // namespace hk
+
+extern "C" {
 
 hk_status hk_matrix_destroy(hk_matrix m) {
   if (!m) return HK_OK;
@@ -321,44 +391,12 @@ hk_status hk_factor(hk_matrix m, hk_mpf shift, int inertia_mode, hipStream_t s, 
   HK_HIP(hipMemcpyAsync(D.xs, m->xs_host.data(), sizeof(int32_t) * P.WX, hipMemcpyHostToDevice, s));
   HK_HIP(launch_fill32(D.flags, 16, 0, s));
   HK_HIP(launch_fill32(D.flags + 1, 1, INT_MAX, s));
-  HK_HIP(launch_expand(P, D, s));
   const int N = P.N, b = m->panel;
   m->n_update = 0;
   m->update_ms = 0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> evs;
   size_t evi = 0;
-  auto get_ev = [&]() -> hipEvent_t {
-    if (evi >= m->ev.size()) {
-      hipEvent_t e;
-      if (hipEventCreate(&e) != hipSuccess) return nullptr;
-      m->ev.push_back(e);
-    }
-    return m->ev[evi++];
-  };
-  int Pidx = 0;
-  for (int pc = 0; pc < N; pc += b, Pidx++) {
-    const int bb = std::min(b, N - pc);
-    for (int j = 0; j < bb; j++) {
-      const int c = pc + j;
-      if (j > 0) {
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (m->timing) { e0 = get_ev(); e1 = get_ev(); if (e0 && e1) HK_HIP(hipEventRecord(e0, s)); }
-        HK_HIP(launch_update(P, D, pc, pc + j, c, c + 1, Pidx & 1, s));
-        if (m->timing && e0 && e1) { HK_HIP(hipEventRecord(e1, s)); evs.push_back({e0, e1}); }
-        m->n_update++;
-      }
-      const int rdf = (Pidx + (j > 0 ? 1 : 0)) & 1;
-      HK_HIP(launch_finalize(P, D, c, rdf, s));
-      if (c < N - 1) HK_HIP(launch_divide(P, D, c, s));
-    }
-    if (pc + bb < N) {
-      hipEvent_t e0 = nullptr, e1 = nullptr;
-      if (m->timing) { e0 = get_ev(); e1 = get_ev(); if (e0 && e1) HK_HIP(hipEventRecord(e0, s)); }
-      HK_HIP(launch_update(P, D, pc, pc + bb, pc + bb, N, Pidx & 1, s));
-      if (m->timing && e0 && e1) { HK_HIP(hipEventRecord(e1, s)); evs.push_back({e0, e1}); }
-      m->n_update++;
-    }
-  }
+  HK_HIP(enqueue_factor(m->B, b, s, m->timing ? &evs : nullptr, &m->ev, &evi, &m->n_update));
   HK_HIP(hipMemcpyAsync(m->flags_host, D.flags, sizeof(int32_t) * 16, hipMemcpyDeviceToHost, s));
   HK_HIP(hipStreamSynchronize(s));
   for (auto& pr : evs) {

@@ -1,0 +1,369 @@
+// Batched form: many instances factored together by instance-batched
+// kernels, one factorisation captured as a HIP graph and replayed; the
+// paper's Secant iteration per instance in lockstep, then the inertia
+// bracket.  See include/hk.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "hk_internal.hpp"
+
+using namespace hk;
+
+namespace hk {
+
+hk_status dfail_b(hk_status st, const std::string& msg) { g_err = msg; return st; }
+
+static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Batch {
+  int count = 0, maxN = 0, ld = 0, panel = 4;
+  std::vector<hk_matrix> mats;
+  std::vector<InstDesc> hdesc;
+  InstDesc* ddesc = nullptr;
+  int32_t* flags = nullptr;
+  int32_t* piv = nullptr;
+  BatchView B;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int captured_panel = 0;
+  int graph_launches = 0;
+  ~Batch() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap) (void)hipStreamDestroy(cap);
+    for (auto m : mats) hk_matrix_destroy(m);
+  }
+};
+
+// per-batch layout: descriptors, flags, pivot rows, then one workspace per instance
+static bool batch_layout(const hk_instance* inst, int count, std::vector<size_t>& off, size_t& total,
+                         int& maxN, int& ld) {
+  maxN = 0; ld = 0;
+  std::vector<size_t> sz(count);
+  for (int i = 0; i < count; i++) {
+    Plan P;
+    std::string err;
+    if (!make_plan(inst[i].N, inst[i].beta.num, inst[i].beta.den, inst[i].prec_bits, P, err)) {
+      g_err = "instance " + std::to_string(i) + ": " + err;
+      return false;
+    }
+    sz[i] = P.total;
+    maxN = std::max(maxN, P.N);
+    ld = std::max(ld, P.maxW + WB);
+  }
+  size_t o = 0;
+  o = al256(o + sizeof(InstDesc) * count);
+  o = al256(o + sizeof(int32_t) * 16 * count);
+  o = al256(o + sizeof(int32_t) * (size_t)count * maxN * ld);
+  off.resize(count);
+  for (int i = 0; i < count; i++) { off[i] = o; o = al256(o + sz[i]); }
+  total = o;
+  return true;
+}
+
+__global__ void k_reset_flags(int32_t* flags, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count * 16) flags[i] = (i % 16) == 1 ? INT_MAX : 0;
+}
+
+static hk_status build_batch(Batch& bt, const hk_instance* inst, int count, void* ws, size_t ws_bytes,
+                             hipStream_t s) {
+  std::vector<size_t> off;
+  size_t total;
+  if (count < 1) return dfail_b(HK_EINVAL, "empty batch");
+  if (!batch_layout(inst, count, off, total, bt.maxN, bt.ld)) return HK_EINVAL;
+  if (!ws || ws_bytes < total) return dfail_b(HK_EINVAL, "workspace too small: need " + std::to_string(total));
+  char* base = (char*)ws;
+  bt.count = count;
+  bt.ddesc = (InstDesc*)base;
+  bt.flags = (int32_t*)(base + al256(sizeof(InstDesc) * count));
+  bt.piv = (int32_t*)((char*)bt.flags + al256(sizeof(int32_t) * 16 * count));
+  // moments of all instances in parallel host threads
+  std::vector<std::vector<MP>> X(count);
+  std::vector<int> ok(count, 0);
+  {
+    const int nth = std::max(1, std::min<int>(count, (int)std::thread::hardware_concurrency()));
+    std::vector<std::thread> th;
+    for (int t = 0; t < nth; t++)
+      th.emplace_back([&, t] {
+        for (int i = t; i < count; i += nth) {
+          uint32_t p, q;
+          if (!reduce_beta(inst[i].beta.num, inst[i].beta.den, &p, &q)) continue;
+          ok[i] = build_moments(inst[i].N, p, q, inst[i].prec_bits, X[i]) ? 1 : 0;
+        }
+      });
+    for (auto& t : th) t.join();
+  }
+  for (int i = 0; i < count; i++) {
+    if (!ok[i]) return dfail_b(HK_EPRECISION, "moments of instance " + std::to_string(i));
+    hk_matrix m = nullptr;
+    hk_status st = build_matrix_impl(inst[i].N, inst[i].beta, inst[i].prec_bits, base + off[i],
+                                     ws_bytes - off[i], s, &m, &X[i]);
+    if (st != HK_OK) return st;
+    bt.mats.push_back(m);
+    InstDesc d = m->desc_host;
+    d.flags = bt.flags + 16 * i;
+    bt.hdesc.push_back(d);
+    bt.B.plans.push_back(&m->P);
+  }
+  bt.B.ddesc = bt.ddesc;
+  bt.B.maxN = bt.maxN;
+  hipError_t e = hipMemcpyAsync(bt.ddesc, bt.hdesc.data(), sizeof(InstDesc) * count, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return dfail_b(HK_EDEVICE, hipGetErrorString(e));
+  return HK_OK;
+}
+
+// capture (once per panel width) the launch sequence of one factorisation
+static hk_status ensure_graph(Batch& bt) {
+  if (bt.exec && bt.captured_panel == bt.panel) return HK_OK;
+  if (bt.exec) { (void)hipGraphExecDestroy(bt.exec); bt.exec = nullptr; }
+  if (bt.graph) { (void)hipGraphDestroy(bt.graph); bt.graph = nullptr; }
+  hipError_t e = hipSuccess;
+  if (!bt.cap) e = hipStreamCreateWithFlags(&bt.cap, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamBeginCapture(bt.cap, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_reset_flags, dim3((bt.count * 16 + 255) / 256), dim3(256), 0, bt.cap, bt.flags,
+                       bt.count);
+    e = hipGetLastError();
+    size_t evi = 0;
+    std::vector<hipEvent_t> pool;
+    if (e == hipSuccess) e = enqueue_factor(bt.B, bt.panel, bt.cap, nullptr, &pool, &evi, nullptr);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(bt.cap, &g);
+    if (e == hipSuccess) e = e2;
+    bt.graph = g;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&bt.exec, bt.graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) return dfail_b(HK_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+  bt.captured_panel = bt.panel;
+  return HK_OK;
+}
+
+struct BEval { hk_status st; int nneg, first_bad; std::vector<MP> piv; };
+
+// one batched factorisation: instance i at shift x[i] if act[i]
+static hk_status factor_batch(Batch& bt, const std::vector<MP>& x, const std::vector<int>& act,
+                              hipStream_t s, std::vector<BEval>& out, bool want_pivots) {
+  hk_status st = ensure_graph(bt);
+  if (st != HK_OK) return st;
+  std::vector<std::vector<int32_t>> xs(bt.count);
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < bt.count && e == hipSuccess; i++) {
+    bt.hdesc[i].active = act[i];
+    if (!act[i]) continue;
+    const Plan& P = bt.mats[i]->P;
+    xs[i].assign(P.WX, 0);
+    mp_to_digits(x[i], xs[i].data(), P.WX);
+    if (x[i].bitlen() > (int64_t)(P.WX - 2) * DB) return dfail_b(HK_EINVAL, "shift too wide");
+    e = hipMemcpyAsync(bt.mats[i]->D.xs, xs[i].data(), sizeof(int32_t) * P.WX, hipMemcpyHostToDevice, s);
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(bt.ddesc, bt.hdesc.data(), sizeof(InstDesc) * bt.count, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipGraphLaunch(bt.exec, s);
+  bt.graph_launches++;
+  std::vector<int32_t> fl(16 * bt.count);
+  std::vector<int32_t> pv;
+  if (e == hipSuccess && want_pivots) {
+    e = launch_gather_pivots_b(bt.B, bt.piv, bt.ld, s);
+    pv.resize((size_t)bt.count * bt.maxN * bt.ld);
+    if (e == hipSuccess) e = hipMemcpyAsync(pv.data(), bt.piv, sizeof(int32_t) * pv.size(), hipMemcpyDeviceToHost, s);
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(fl.data(), bt.flags, sizeof(int32_t) * fl.size(), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return dfail_b(HK_EDEVICE, std::string("batched factorisation: ") + hipGetErrorString(e));
+  out.assign(bt.count, BEval());
+  for (int i = 0; i < bt.count; i++) {
+    if (!act[i]) continue;
+    const int N = bt.mats[i]->P.N;
+    BEval& ev = out[i];
+    const int32_t* f = &fl[16 * i];
+    ev.first_bad = f[1] == INT_MAX ? -1 : f[1];
+    ev.nneg = f[2];
+    ev.st = f[0] ? HK_EPRECISION : ((ev.first_bad >= 0 && ev.first_bad < N - 1) ? HK_ENOTSPD : HK_OK);
+    bt.mats[i]->factored = ev.st == HK_OK;
+    if (want_pivots && ev.st == HK_OK) {
+      ev.piv.resize(N);
+      for (int k = 0; k < N; k++)
+        ev.piv[k] = digits_to_mp(pv.data() + ((size_t)i * bt.maxN + k) * bt.ld, bt.ld, 1);
+    }
+  }
+  return HK_OK;
+}
+
+static std::string tune_key(const hk_instance* inst, int count) {
+  int maxN = 0, maxK = 0;
+  for (int i = 0; i < count; i++) { maxN = std::max(maxN, inst[i].N); maxK = std::max(maxK, inst[i].prec_bits); }
+  int nb = 1, kb = 1;
+  while (nb < maxN) nb <<= 1;
+  while (kb < maxK) kb <<= 1;
+  hipDeviceProp_t prop;
+  int dev = 0;
+  std::string arch = "unknown";
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+    arch = prop.gcnArchName;
+    arch = arch.substr(0, arch.find(':'));
+  }
+  std::ostringstream os;
+  os << arch << " count=" << count << " N<=" << nb << " K<=" << kb;
+  return os.str();
+}
+
+static int cached_panel(const std::string& key) {
+  const char* path = getenv("HK_TUNE_CACHE");
+  if (!path) return 0;
+  std::ifstream f(path);
+  std::string line;
+  int best = 0;
+  while (std::getline(f, line)) {
+    size_t bar = line.find(" | panel=");
+    if (bar != std::string::npos && line.substr(0, bar) == key) best = atoi(line.c_str() + bar + 9);
+  }
+  return best;
+}
+
+// the paper's Secant iteration is reused from hk_drivers.cpp through this
+// interface (one machine per instance)
+struct SecantRun;
+SecantRun* secant_new(int N, int K, int h, int tol, int max_eval);
+void secant_delete(SecantRun* r);
+bool secant_next(SecantRun* r, MP& x, int& inertia);
+void secant_feed(SecantRun* r, hk_status st, int nneg, int first_bad, const std::vector<MP>& piv);
+bool secant_done(SecantRun* r, MP& lam, hk_status& st, std::string& err);
+void decimal_bracket(const MP& lam, int K, int digits, MP& xlo, MP& xhi, std::string& dec);
+
+}  // namespace hk
+
+extern "C" {
+
+size_t hk_batch_workspace_bytes(const hk_instance* inst, int count) {
+  std::vector<size_t> off;
+  size_t total;
+  int maxN, ld;
+  if (!inst || count < 1) return 0;
+  if (!batch_layout(inst, count, off, total, maxN, ld)) return 0;
+  return total;
+}
+
+hk_status hk_eig_batched(const hk_instance* inst, int count, int digits, int panel, void* dev_ws,
+                         size_t ws_bytes, hipStream_t s, hk_result* out, hk_batch_report* rep) {
+  auto t0 = std::chrono::steady_clock::now();
+  if (!inst || !out || count < 1) return dfail_b(HK_EINVAL, "bad arguments");
+  if (digits < 2 || digits > 150) return dfail_b(HK_EINVAL, "digits must be in [2, 150]");
+  Batch bt;
+  hk_status st = build_batch(bt, inst, count, dev_ws, ws_bytes, s);
+  if (st != HK_OK) return st;
+  bt.panel = panel > 0 ? panel : cached_panel(tune_key(inst, count));
+  if (bt.panel <= 0) bt.panel = 4;
+  auto t1 = std::chrono::steady_clock::now();
+  std::vector<SecantRun*> sm(count);
+  for (int i = 0; i < count; i++) {
+    const Plan& P = bt.mats[i]->P;
+    sm[i] = secant_new(P.N, P.K, P.h, digits, 200);
+    memset(&out[i], 0, sizeof(hk_result));
+  }
+  std::vector<MP> x(count);
+  std::vector<int> act(count), inertia(count), nfact(count, 0);
+  std::vector<BEval> ev;
+  st = HK_OK;
+  for (int round = 0; round < 400 && st == HK_OK; round++) {
+    bool any = false;
+    for (int i = 0; i < count; i++) {
+      act[i] = secant_next(sm[i], x[i], inertia[i]) ? 1 : 0;
+      any |= act[i] != 0;
+    }
+    if (!any) break;
+    st = factor_batch(bt, x, act, s, ev, true);
+    for (int i = 0; i < count && st == HK_OK; i++) {
+      if (!act[i]) continue;
+      nfact[i]++;
+      secant_feed(sm[i], ev[i].st, ev[i].nneg, ev[i].first_bad, ev[i].piv);
+    }
+  }
+  // inertia bracket for every converged instance
+  std::vector<MP> lam(count), xlo(count), xhi(count);
+  std::vector<std::string> dec(count);
+  std::vector<int> done(count, 0);
+  for (int i = 0; i < count && st == HK_OK; i++) {
+    hk_status si;
+    std::string err;
+    if (secant_done(sm[i], lam[i], si, err)) {
+      done[i] = 1;
+      decimal_bracket(lam[i], bt.mats[i]->P.K, digits, xlo[i], xhi[i], dec[i]);
+    } else {
+      out[i].status = si;
+    }
+  }
+  std::vector<BEval> elo, ehi;
+  if (st == HK_OK) st = factor_batch(bt, xlo, done, s, elo, false);
+  if (st == HK_OK) st = factor_batch(bt, xhi, done, s, ehi, false);
+  hk_status first = st;
+  for (int i = 0; i < count; i++) {
+    out[i].factorizations = nfact[i] + (done[i] ? 2 : 0);
+    if (st == HK_OK && done[i]) {
+      const int N = bt.mats[i]->P.N;
+      const bool okb = elo[i].st == HK_OK && elo[i].nneg == 0 && elo[i].first_bad < 0 &&
+                       ehi[i].st == HK_OK && ehi[i].nneg == 1 && ehi[i].first_bad == N - 1;
+      out[i].verified = okb ? 1 : 0;
+      out[i].status = okb ? HK_OK : HK_EVERIFY;
+      snprintf(out[i].lambda_dec, sizeof out[i].lambda_dec, "%s", dec[i].c_str());
+    }
+    if (first == HK_OK && out[i].status != HK_OK) first = out[i].status;
+    secant_delete(sm[i]);
+  }
+  if (rep) {
+    rep->panel = bt.panel;
+    rep->graph_launches = bt.graph_launches;
+    rep->t_build_s = std::chrono::duration<double>(t1 - t0).count();
+    rep->t_factor_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t1).count();
+    rep->t_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (first != HK_OK && st == HK_OK) g_err = "some instances failed";
+  return first;
+}
+
+hk_status hk_autotune(const hk_instance* inst, int count, void* dev_ws, size_t ws_bytes,
+                      hipStream_t s, const char* cache_path, int* best_panel) {
+  if (!inst || count < 1 || !best_panel) return dfail_b(HK_EINVAL, "bad arguments");
+  Batch bt;
+  hk_status st = build_batch(bt, inst, count, dev_ws, ws_bytes, s);
+  if (st != HK_OK) return st;
+  std::vector<MP> x(count);
+  std::vector<int> act(count, 1);
+  std::vector<BEval> ev;
+  const int cand[] = {1, 2, 4, 8, 16};
+  double best_ms = 1e300;
+  int best = 4;
+  for (int b : cand) {
+    bt.panel = b;
+    st = factor_batch(bt, x, act, s, ev, false);   // capture + warm up
+    if (st != HK_OK) return st;
+    auto t0 = std::chrono::steady_clock::now();
+    st = factor_batch(bt, x, act, s, ev, false);
+    if (st != HK_OK) return st;
+    const double ms = 1e3 * std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (ms < best_ms) { best_ms = ms; best = b; }
+  }
+  *best_panel = best;
+  if (cache_path) {
+    std::ofstream f(cache_path, std::ios::app);
+    if (!f) return dfail_b(HK_EINVAL, "cannot write the tuning cache");
+    f << tune_key(inst, count) << " | panel=" << best << " ms=" << best_ms << "\n";
+  }
+  return HK_OK;
+}
+
+}  // extern "C"

@@ -43,7 +43,7 @@ MP floor_shr(const MP& x, int64_t s) {
 hk_status pivots_host(hk_matrix m, hipStream_t s, std::vector<MP>& out) {
   const Plan& P = m->P;
   const int ld = P.maxW + WB;
-  hipError_t e = launch_gather_pivots(P, m->D, m->D.vec, ld, s);
+  hipError_t e = launch_gather_pivots_b(m->B, m->D.vec, ld, s);
   std::vector<int32_t> buf((size_t)P.N * ld);
   if (e == hipSuccess) e = hipMemcpyAsync(buf.data(), m->D.vec, sizeof(int32_t) * buf.size(), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -128,76 +128,131 @@ static Eval evaluate(DriverCtx& cx, const MP& x, int inertia_mode) {
   return ev;
 }
 
-hk_status secant_driver(DriverCtx& cx, int tol, int max_iter, MP& lam_fixed) {
-  const Plan& P = cx.m->P;
-  const int K = P.K;
-  int nb = 0;
-  for (int n = P.N; n; n >>= 1) nb++;
-  const int64_t F = P.h + 64 + nb;
-  const MP ONE = one_shl(F);
-  const int q = (K + 3) / 4;
-  auto secant_point = [&](const MP& xa, const MP& xb, const MP& R) {
-    MP Rm1 = sub(R, ONE);
-    return rne_div(sub(mul(xb, Rm1), mul(sub(xb, xa), R)), Rm1);
-  };
-  std::vector<MP> xs = {neg(one_shl(K - q)), MP()};
+// The Secant iteration as a resumable machine: next() names the point to
+// factor (and whether inertia mode is wanted), feed() consumes the result.
+// Used one instance at a time and across a batch.
+struct SecantMachine {
+  enum Phase { START0, START1, ITER, BRACKET, DONE, FAILED } phase = START0;
+  int K = 0, tol = 45, max_eval = 200, nevals = 0;
+  int64_t F = 0;
+  MP ONE, lam;
+  hk_status status = HK_OK;
+  std::string err;
+  std::vector<MP> xs;
   std::vector<std::vector<MP>> piv;
-  for (auto& x : xs) {
-    Eval ev = evaluate(cx, x, 0);
-    if (ev.st != HK_OK) return ev.st == HK_ENOTSPD ? dfail(HK_ENOTSPD, "start point not left of lambda_1") : ev.st;
-    piv.push_back(ev.piv);
-  }
   MP prev_step;
   bool have_prev = false;
-  for (int it = 0; it < max_iter; it++) {
-    const MP& x0 = xs[xs.size() - 2];
-    const MP& x1 = xs.back();
-    MP R = pivot_ratio(piv.back(), piv[piv.size() - 2], F);
-    if (cmp(R, ONE) >= 0) return dfail(HK_EPRECISION, "secant ratio >= 1: precision exhausted");
-    MP x2 = secant_point(x0, x1, R);
-    MP step = sub(x2, x1);
-    if (step.sign() <= 0) return dfail(HK_EPRECISION, "secant iterate did not increase");
-    if (have_prev && cmp(step, prev_step) >= 0 && it > 2) return dfail(HK_EPRECISION, "secant step did not shrink");
-    prev_step = step;
-    have_prev = true;
-    if (within_tol(step, x2, tol)) { lam_fixed = x2; return HK_OK; }
-    Eval ev = evaluate(cx, x2, 1);
-    if (ev.st == HK_OK && ev.nneg == 0 && ev.first_bad < 0) {
-      xs.push_back(x2);
-      piv.push_back(ev.piv);
-      continue;
-    }
-    if (ev.st != HK_OK && ev.st != HK_ENOTSPD) return ev.st;
-    // bracket [a, b] with P(a) > 0 >= P(b)
-    MP a = x1, b = x2;
-    std::vector<MP> da = piv.back(), db = ev.st == HK_OK ? ev.piv : std::vector<MP>();
-    int scale_a = 0, scale_b = 0, side = 0;
-    for (int jt = it; jt < max_iter; jt++) {
-      if (within_tol(sub(b, a), a, tol)) { lam_fixed = a; return HK_OK; }
-      MP c;
-      bool have_c = false;
-      if (!db.empty()) {
-        MP Rb = pivot_ratio(db, da, F);
-        if (scale_b <= scale_a) Rb = shl(floor_shr(Rb, scale_b), scale_a);
-        else Rb = floor_shr(Rb, scale_b - scale_a);
-        if (cmp(Rb, ONE) != 0) { c = secant_point(a, b, Rb); have_c = true; }
-      }
-      if (!have_c || cmp(c, a) <= 0 || cmp(c, b) >= 0) c = floor_shr(add(a, b), 1);
-      Eval ec = evaluate(cx, c, 1);
-      if (ec.st != HK_OK && ec.st != HK_ENOTSPD) return ec.st;
-      if (ec.st == HK_OK && ec.nneg == 0 && ec.first_bad < 0) {
-        a = c; da = ec.piv; scale_a = 0;
-        if (side == -1) scale_b++;
-        side = -1;
-      } else {
-        b = c; db = ec.st == HK_OK ? ec.piv : std::vector<MP>(); scale_b = 0;
-        if (side == 1) scale_a++;
-        side = 1;
-      }
-    }
-    return dfail(HK_ENOCONV, "bracketing did not converge");
+  int it = 0;
+  MP pending;
+  // bracket state: P(a) > 0 >= P(b)
+  MP a, b;
+  std::vector<MP> da, db;
+  int scale_a = 0, scale_b = 0, side = 0;
+
+  void init(int N, int K_, int h, int tol_, int max_eval_) {
+    K = K_; tol = tol_; max_eval = max_eval_;
+    int nb = 0;
+    for (int n = N; n; n >>= 1) nb++;
+    F = h + 64 + nb;
+    ONE = one_shl(F);
+    xs = {neg(one_shl(K - (K + 3) / 4)), MP()};
   }
-  return dfail(HK_ENOCONV, "secant did not converge");
+  MP secant_point(const MP& xa, const MP& xb, const MP& R) const {
+    MP Rm1 = sub(R, ONE);
+    return rne_div(sub(mul(xb, Rm1), mul(sub(xb, xa), R)), Rm1);
+  }
+  void fail(hk_status st, const std::string& m) { phase = FAILED; status = st; err = m; }
+  // false when finished (DONE or FAILED)
+  bool next(MP& x, int& inertia) {
+    if (phase == DONE || phase == FAILED) return false;
+    if (nevals >= max_eval) { fail(HK_ENOCONV, "secant did not converge"); return false; }
+    if (phase == START0 || phase == START1) {
+      x = xs[phase == START0 ? 0 : 1];
+      inertia = 0;
+      return true;
+    }
+    if (phase == ITER) {
+      const MP& x0 = xs[xs.size() - 2];
+      const MP& x1 = xs.back();
+      MP R = pivot_ratio(piv.back(), piv[piv.size() - 2], F);
+      if (cmp(R, ONE) >= 0) { fail(HK_EPRECISION, "secant ratio >= 1: precision exhausted"); return false; }
+      MP x2 = secant_point(x0, x1, R);
+      MP step = sub(x2, x1);
+      if (step.sign() <= 0) { fail(HK_EPRECISION, "secant iterate did not increase"); return false; }
+      if (have_prev && cmp(step, prev_step) >= 0 && it > 2) {
+        fail(HK_EPRECISION, "secant step did not shrink");
+        return false;
+      }
+      prev_step = step;
+      have_prev = true;
+      it++;
+      if (within_tol(step, x2, tol)) { lam = x2; phase = DONE; return false; }
+      pending = x2;
+      x = x2;
+      inertia = 1;
+      return true;
+    }
+    // BRACKET
+    if (within_tol(sub(b, a), a, tol)) { lam = a; phase = DONE; return false; }
+    MP c;
+    bool have_c = false;
+    if (!db.empty()) {
+      MP Rb = pivot_ratio(db, da, F);
+      if (scale_b <= scale_a) Rb = shl(floor_shr(Rb, scale_b), scale_a);
+      else Rb = floor_shr(Rb, scale_b - scale_a);
+      if (cmp(Rb, ONE) != 0) { c = secant_point(a, b, Rb); have_c = true; }
+    }
+    if (!have_c || cmp(c, a) <= 0 || cmp(c, b) >= 0) c = floor_shr(add(a, b), 1);
+    pending = c;
+    x = c;
+    inertia = 1;
+    return true;
+  }
+  void feed(const Eval& ev) {
+    nevals++;
+    const bool left = ev.st == HK_OK && ev.nneg == 0 && ev.first_bad < 0;
+    if (phase == START0 || phase == START1) {
+      if (ev.st != HK_OK) {
+        if (ev.st == HK_ENOTSPD) fail(HK_ENOTSPD, "start point not left of lambda_1");
+        else fail(ev.st, "factorisation failed");
+        return;
+      }
+      piv.push_back(ev.piv);
+      phase = phase == START0 ? START1 : ITER;
+      return;
+    }
+    if (ev.st != HK_OK && ev.st != HK_ENOTSPD) { fail(ev.st, "factorisation failed"); return; }
+    if (phase == ITER) {
+      if (left) { xs.push_back(pending); piv.push_back(ev.piv); return; }
+      a = xs.back(); b = pending;
+      da = piv.back();
+      db = ev.st == HK_OK ? ev.piv : std::vector<MP>();
+      scale_a = scale_b = side = 0;
+      phase = BRACKET;
+      return;
+    }
+    if (left) {
+      a = pending; da = ev.piv; scale_a = 0;
+      if (side == -1) scale_b++;
+      side = -1;
+    } else {
+      b = pending; db = ev.st == HK_OK ? ev.piv : std::vector<MP>(); scale_b = 0;
+      if (side == 1) scale_a++;
+      side = 1;
+    }
+  }
+};
+
+hk_status secant_driver(DriverCtx& cx, int tol, int max_iter, MP& lam_fixed) {
+  const Plan& P = cx.m->P;
+  SecantMachine sm;
+  sm.init(P.N, P.K, P.h, tol, max_iter);
+  MP x;
+  int inertia;
+  while (sm.next(x, inertia)) sm.feed(evaluate(cx, x, inertia));
+  if (sm.phase != SecantMachine::DONE) return dfail(sm.status, sm.err);
+  lam_fixed = sm.lam;
+  return HK_OK;
 }
 
 // lambda = x / 2^K truncated to `digits` significant digits: D * 10^e
@@ -223,6 +278,40 @@ static MP decimal_to_fixed(const MP& D, int64_t e, int K, bool ceil_mode) {
   if (e >= 0) num = mul(num, pow10((uint32_t)e));
   else den = pow10((uint32_t)(-e));
   return ceil_mode ? ceil_div(num, den) : floor_div(num, den);
+}
+
+// decimal form of lambda (digits significant digits) and the two bracket
+// points: truncated value floored to K bits, one unit more ceiled
+void decimal_bracket(const MP& lam, int K, int digits, MP& xlo, MP& xhi, std::string& dec) {
+  MP D;
+  int64_t e;
+  truncate_digits(lam, K, digits, D, e);
+  std::string ds = to_dec(D);
+  char buf[64];
+  snprintf(buf, sizeof buf, "e%lld", (long long)(e + (int64_t)ds.size() - 1));
+  dec = ds.substr(0, 1) + "." + ds.substr(1) + buf;
+  xlo = decimal_to_fixed(D, e, K, false);
+  xhi = decimal_to_fixed(add(D, MP::from_u64(1)), e, K, true);
+}
+
+struct SecantRun { SecantMachine m; };
+SecantRun* secant_new(int N, int K, int h, int tol, int max_eval) {
+  SecantRun* r = new SecantRun;
+  r->m.init(N, K, h, tol, max_eval);
+  return r;
+}
+void secant_delete(SecantRun* r) { delete r; }
+bool secant_next(SecantRun* r, MP& x, int& inertia) { return r->m.next(x, inertia); }
+void secant_feed(SecantRun* r, hk_status st, int nneg, int first_bad, const std::vector<MP>& piv) {
+  Eval ev;
+  ev.st = st; ev.nneg = nneg; ev.first_bad = first_bad; ev.piv = piv;
+  r->m.feed(ev);
+}
+bool secant_done(SecantRun* r, MP& lam, hk_status& st, std::string& err) {
+  lam = r->m.lam;
+  st = r->m.status;
+  err = r->m.err;
+  return r->m.phase == SecantMachine::DONE;
 }
 
 hk_status verify_bracket(DriverCtx& cx, const MP& lam_fixed, int digits, std::string& dec, bool& ok) {

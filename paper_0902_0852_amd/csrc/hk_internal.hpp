@@ -10,6 +10,8 @@
 #include "../../include/hk.h"
 #include "hk_mp.hpp"
 
+struct hk_matrix_s;
+
 namespace hk {
 
 // Device digits: balanced radix 2^29, value = sum_i d_i 2^(29 i) with
@@ -54,7 +56,7 @@ struct Plan {
   // byte offsets in the workspace
   size_t o_cols, o_items, o_A, o_K, o_C, o_L, o_S, o_D, o_dinfo, o_nC, o_nCs, o_nL,
       o_X, o_xs, o_flags, o_b32C, o_b32L, o_vec, o_LT, o_acc, o_kca, o_ub, o_us, o_wb, o_nU,
-      o_nUs, o_dv1, o_dv2, o_md, total;
+      o_nUs, o_dv1, o_dv2, o_md, o_desc, total;
   int64_t ntri;
 };
 
@@ -72,7 +74,11 @@ __host__ __device__ inline int64_t tri_index(int N, int k, int r) {
   return (int64_t)k * N - (int64_t)k * (k - 1) / 2 + (r - k);
 }
 
+hk_status build_matrix_impl(int N, hk_rational beta, int prec_bits, void* dev_ws, size_t ws_bytes,
+                            hipStream_t s, hk_matrix* out, std::vector<MP>* moments);
+
 // kernel launchers (hk_kernels.hip)
+struct InstDesc;
 struct DevPtrs {
   ColInfo* cols; int32_t* itemStart;
   int32_t* A; int64_t* Kc; int32_t* C; int32_t* L; uint32_t* S; uint32_t* D; int32_t* dinfo;
@@ -80,17 +86,44 @@ struct DevPtrs {
   int32_t* b32C; int32_t* b32L; int32_t* vec;
   int32_t* LT; int32_t* acc; int64_t* kca; int32_t* ub; uint32_t* us; int32_t* wb;
   int32_t* nU; int32_t* nUs; int32_t* dv1; int32_t* dv2; uint32_t* md;
+  InstDesc* desc;
 };
 DevPtrs dev_ptrs(const Plan& P, char* ws);
+
+// Device descriptor of one instance (one factorisation problem) of a batch;
+// every factorisation kernel takes an array of them, a single matrix is a
+// batch of one.
+struct InstDesc {
+  const ColInfo* cols; const int32_t* itemStart;
+  int32_t* A; int64_t* Kc; int32_t* C; uint32_t* S; int32_t* L; int32_t* LT; uint32_t* D;
+  int32_t* dinfo; int32_t* nC; int32_t* nCs; int32_t* nL; int32_t* b32C; int32_t* flags;
+  const int32_t* X; const int32_t* xs;
+  int32_t N, h, WX, active;
+};
+InstDesc make_desc(const Plan& P, const DevPtrs& D);
+
+// Host view of a batch: the device descriptor array and the plans (grid sizes
+// are computed on the host from the plans).
+struct BatchView {
+  const InstDesc* ddesc = nullptr;
+  std::vector<const Plan*> plans;
+  int maxN = 0;
+};
 extern thread_local std::string g_err;
 
 hipError_t launch_fill32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_fill64(int64_t* p, int64_t n, hipStream_t s);
-hipError_t launch_expand(const Plan& P, const DevPtrs& D, hipStream_t s);
-hipError_t launch_update(const Plan& P, const DevPtrs& D, int k0, int k1, int c_lo, int c_hi,
-                         int rd, hipStream_t s);
-hipError_t launch_finalize(const Plan& P, const DevPtrs& D, int c, int rd, hipStream_t s);
-hipError_t launch_divide(const Plan& P, const DevPtrs& D, int c, hipStream_t s);
+hipError_t launch_expand(const BatchView& B, hipStream_t s);
+// j = 0: trailing update after the panel [pc, pc + b); j > 0: in-panel
+// (left-looking) update of column pc + j by columns [pc, pc + j)
+hipError_t launch_update(const BatchView& B, int pc, int b, int j, int rd, hipStream_t s);
+hipError_t launch_finalize(const BatchView& B, int c, int rd, hipStream_t s);
+hipError_t launch_divide(const BatchView& B, int c, hipStream_t s);
+hipError_t launch_gather_pivots_b(const BatchView& B, int32_t* out, int ld, hipStream_t s);
+int64_t update_items(const Plan& P, int pc, int b, int j);
+hipError_t enqueue_factor(const BatchView& B, int b, hipStream_t s,
+                          std::vector<std::pair<hipEvent_t, hipEvent_t>>* evs,
+                          std::vector<hipEvent_t>* pool, size_t* evi, int* n_update);
 hipError_t launch_bits(const Plan& P, const DevPtrs& D, hipStream_t s);
 hipError_t launch_vinit(const Plan& P, const DevPtrs& D, const int32_t* src, int Sbits, hipStream_t s);
 hipError_t launch_vupdate(const Plan& P, const DevPtrs& D, int bwd, int k0, int k1, int i_lo,
@@ -100,7 +133,6 @@ hipError_t launch_vfinalize(const Plan& P, const DevPtrs& D, int k, int rd, int3
 hipError_t launch_vdivide(const Plan& P, const DevPtrs& D, hipStream_t s);
 hipError_t launch_vscale(const Plan& P, const DevPtrs& D, const uint32_t* md, int nd, int sh,
                          int32_t* out, hipStream_t s);
-hipError_t launch_gather_pivots(const Plan& P, const DevPtrs& D, int32_t* out, int ld, hipStream_t s);
 
 }  // namespace hk
 
@@ -118,6 +150,8 @@ struct hk_matrix_s {
   double update_ms = 0;
   int32_t flags_host[16];
   int gbits = 0;            // solve guard bits from the actual largest moment
+  hk::InstDesc desc_host;
+  hk::BatchView B;          // this matrix as a batch of one
   std::vector<hipEvent_t> ev;
 };
 

@@ -49,26 +49,25 @@ __global__ void k_fill64(int64_t* __restrict__ p, int64_t n) {
 }
 
 // A_rc = X_{r+c} - [r = c] xs  (diagonal shift first, as in determinant());
-// carries of column c cleared.  One workgroup per column.
-__global__ void __launch_bounds__(256) k_expand(const ColInfo* __restrict__ cols, int N, int WX,
-                                                const int32_t* __restrict__ X,
-                                                const int32_t* __restrict__ xs,
-                                                int32_t* __restrict__ A, int64_t* __restrict__ Kc) {
+// carries of column c cleared.  One workgroup per (column, instance).
+__global__ void __launch_bounds__(256) k_expand(const InstDesc* __restrict__ desc) {
+  const InstDesc I = desc[blockIdx.y];
   const int c = blockIdx.x;
-  const ColInfo cc = cols[c];
+  if (!I.active || c >= I.N) return;
+  const ColInfo cc = I.cols[c];
   const int64_t n = (int64_t)cc.W * cc.R;
   for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
     int s = (int)(i / cc.R), lr = (int)(i - (int64_t)s * cc.R);
     int r = c + lr;
     int32_t v = 0;
-    if (r < N && s < WX) {
-      v = X[(int64_t)(r + c) * WX + s];
-      if (lr == 0) v -= xs[s];
+    if (r < I.N && s < I.WX) {
+      v = I.X[(int64_t)(r + c) * I.WX + s];
+      if (lr == 0) v -= I.xs[s];
     }
-    A[cc.aoff + i] = v;
+    I.A[cc.aoff + i] = v;
   }
   const int64_t nk = (int64_t)2 * cc.nb * cc.R;
-  for (int64_t i = threadIdx.x; i < nk; i += blockDim.x) Kc[cc.koff + i] = 0;
+  for (int64_t i = threadIdx.x; i < nk; i += blockDim.x) I.Kc[cc.koff + i] = 0;
 }
 
 // acc[m] += sum_t C[t] * w(m - t), w(e) = hi[e] (e >= 0) or lo[16 + e] (e < 0)
@@ -164,32 +163,52 @@ __device__ __forceinline__ void apply_block(const int64_t* acc, int32_t* Ap, int
   else if (v != 0) atomicOr(&flags[0], 1);
 }
 
-// Rank-(k1-k0) update of columns [c_lo, c_hi):
+// column and panel ranges of one update launch for an instance of size N:
+// j = 0 trailing (columns [pc+bb, N), k in [pc, pc+bb)), j > 0 in-panel
+// (column pc+j, k in [pc, pc+j)); false if the instance has nothing to do
+__host__ __device__ inline bool update_range(int N, int pc, int b, int j, int& k0, int& k1, int& c_lo,
+                                            int& c_hi) {
+  if (j == 0) {
+    const int bb = min(b, N - pc);
+    if (bb <= 0 || pc + bb >= N) return false;
+    k0 = pc; k1 = pc + bb; c_lo = pc + bb; c_hi = N;
+  } else {
+    if (pc + j >= N) return false;
+    k0 = pc; k1 = pc + j; c_lo = pc + j; c_hi = pc + j + 1;
+  }
+  return true;
+}
+
+// Rank-(k1-k0) update of the columns [c_lo, c_hi) of every instance:
 //   A_rc -= sum_{k0 <= k < k1} C_k[c] L_k[r]      (exact)
-// One wavefront per (column, 64-row tile, 16-digit output block).  C_k[c]
-// digits are wavefront-uniform; L_k[r] digits are per lane.
-__global__ void __launch_bounds__(256) k_update(const ColInfo* __restrict__ cols,
-                                                const int32_t* __restrict__ itemStart,
-                                                int32_t* __restrict__ A, int64_t* __restrict__ Kc,
-                                                const int32_t* __restrict__ Cb,
-                                                const int32_t* __restrict__ Lb,
-                                                const int32_t* __restrict__ nCw,
-                                                const int32_t* __restrict__ nLw,
-                                                int32_t* __restrict__ flags, int N, int k0, int k1,
-                                                int c_lo, int c_hi, int rd) {
+// One wavefront per (instance, column, 64-row tile, 16-digit output block).
+// C_k[c] digits are wavefront-uniform; L_k[r] digits are per lane.
+__global__ void __launch_bounds__(256) k_update(const InstDesc* __restrict__ desc, int count, int pc,
+                                                int b, int j, int rd) {
   const int wave = uni(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int base = itemStart[c_lo];
-  const int it = base + blockIdx.x * 4 + wave;
-  if (it >= itemStart[c_hi]) return;
+  int it = blockIdx.x * 4 + wave;
+  int inst = -1, k0 = 0, k1 = 0, c_lo = 0, c_hi = 0;
+  for (int i = 0; i < count; i++) {
+    int a0, a1, b0, b1;
+    if (!update_range(desc[i].N, pc, b, j, a0, a1, b0, b1)) continue;
+    const int n = desc[i].itemStart[b1] - desc[i].itemStart[b0];
+    if (it < n) { inst = i; k0 = a0; k1 = a1; c_lo = b0; c_hi = b1; break; }
+    it -= n;
+  }
+  if (inst < 0) return;
+  const InstDesc I = desc[inst];
+  if (!I.active) return;
+  const int N = I.N;
+  it += I.itemStart[c_lo];
   int lo = c_lo, hi = c_hi - 1;
   while (lo < hi) {
     int mid = (lo + hi + 1) >> 1;
-    if (itemStart[mid] <= it) lo = mid; else hi = mid - 1;
+    if (I.itemStart[mid] <= it) lo = mid; else hi = mid - 1;
   }
   const int c = uni(lo);
-  const ColInfo cc = cols[c];
-  const int rem = it - itemStart[c];
+  const ColInfo cc = I.cols[c];
+  const int rem = it - I.itemStart[c];
   const int T = cc.R >> 6;
   const int q = uni(rem / T);
   const int t = uni(rem - q * T);
@@ -202,19 +221,19 @@ __global__ void __launch_bounds__(256) k_update(const ColInfo* __restrict__ cols
   for (int m = 0; m <= WB; m++) acc[m] = 0;
   int cnt = 0;
   for (int k = k0; k < k1; k++) {
-    const ColInfo kk = cols[k];
-    const int nC = min(uni(nCw[tri_index(N, k, c)]), kk.CW - WB);
-    const int nLl = active ? nLw[tri_index(N, k, rr)] : 0;
+    const ColInfo kk = I.cols[k];
+    const int nC = min(uni(I.nC[tri_index(N, k, c)]), kk.CW - WB);
+    const int nLl = active ? I.nL[tri_index(N, k, rr)] : 0;
     const int nL = min(uni(wave_max(nLl)), kk.LW - 2 * WB);
-    accum_block(acc, cnt, Cb + kk.coff + (int64_t)(c - k) * kk.CW, nC, Lb + kk.loff,
+    accum_block(acc, cnt, I.C + kk.coff + (int64_t)(c - k) * kk.CW, nC, I.L + kk.loff,
                 (int64_t)kk.LW * kk.R * 4, rr - k, kk.R, nL, q);
   }
   if (!active) return;
   const int lr = r - c;
-  int64_t* Kcol = Kc + cc.koff;
-  apply_block(acc, A + cc.aoff + (int64_t)(WB * q) * cc.R + lr, cc.R,
+  int64_t* Kcol = I.Kc + cc.koff;
+  apply_block(acc, I.A + cc.aoff + (int64_t)(WB * q) * cc.R + lr, cc.R,
               q > 0 ? Kcol + ((int64_t)rd * cc.nb + q) * cc.R + lr : nullptr,
-              q + 1 < cc.nb ? Kcol + ((int64_t)(rd ^ 1) * cc.nb + q + 1) * cc.R + lr : nullptr, flags);
+              q + 1 < cc.nb ? Kcol + ((int64_t)(rd ^ 1) * cc.nb + q + 1) * cc.R + lr : nullptr, I.flags);
 }
 
 struct FinOut {
@@ -225,142 +244,216 @@ struct FinOut {
   uint32_t topv;  // top standard digit
 };
 
-// Value = sum_s A[s as] 2^(29 s) + sum_{q >= 1} K[q ks] 2^(29 16 q) (lazy
-// digits with pending block carries, W a multiple of 16).  Writes RNE(value /
-// 2^h) as balanced digits to Cr[0..cap) and as standard digits of its
-// magnitude to Sr[0..cap) (both zero filled).  One thread; digits are read in
-// blocks of 16 so that the loads of a block are in flight together.  Pass 1
-// finds the sign, pass 2 repeats the carry chain and streams the magnitude
-// through the rounding shift.
-__device__ FinOut finalize_entry(const int32_t* Ap, int64_t as, int W, const int64_t* Kp, int64_t ks,
-                                 int h, int32_t* Cr, uint32_t* Sr, int cap, int32_t* flags) {
-  const int nbk = W / WB;
-  int64_t v = 0;
-  int topneg = 0;
-  for (int q = 0; q < nbk; q++) {
+// Carry resolution over nblk blocks of 16 digits held in LDS (x), one
+// wavefront: block q absorbs the carry cin[q] coming from block q-1 and
+// renormalises (balanced or standard digits), handing its own carry to block
+// q+1 in the next round; rounds repeat until no carry is left inside the
+// number (at most nblk rounds).  cin[0] may hold a carry into block 0.
+// Returns the total carry out of the top block.
+template <bool BAL>
+__device__ int64_t wave_resolve(int32_t* x, int nblk, int64_t* cin, int64_t* cout) {
+  const int lane = threadIdx.x & 63;
+  int64_t top = cin[nblk];   // carry already out of the top block
+  for (int round = 0; round <= nblk + 1; round++) {
+    int any = 0;
+    for (int q = lane; q < nblk; q += 64) {
+      const int64_t c = cin[q];
+      int64_t v = c;
+      if (c != 0) {
+        for (int m = 0; m < WB; m++) {
+          v += x[q * WB + m];
+          const int32_t d = BAL ? balanced29(v) : (int32_t)(v & (RADIX - 1));
+          x[q * WB + m] = d;
+          v = (v - d) >> DB;
+        }
+      }
+      cout[q + 1] = v;
+      any |= (v != 0) && (q + 1 < nblk);
+    }
+    __syncthreads();
+    top += cout[nblk];
+    if (!__any(any)) break;
+    for (int q = lane; q < nblk; q += 64) cin[q] = q == 0 ? 0 : cout[q];
+    __syncthreads();
+  }
+  __syncthreads();
+  return top;
+}
+
+// RNE(value / 2^h) of one lazily represented number by one wavefront: the
+// value (lazy digits Ap[s as], W a multiple of 16, pending block carries
+// Kp[q ks] for q >= 1) is normalised block by block in parallel,
+// its sign taken from the top digit, its magnitude converted to standard
+// digits, shifted right by h bits with round-to-nearest-even, and written as
+// balanced digits (Cr) and standard magnitude digits (Sr), cap each.  LDS:
+// dg and ob of W + 48 int32, ca and cb of W/16 + 8 int64.
+__device__ FinOut wave_finalize(const int32_t* Ap, int64_t as, int W, const int64_t* Kp, int64_t ks,
+                                int h, int32_t* Cr, uint32_t* Sr, int cap, int32_t* flags,
+                                int32_t* dg, int32_t* ob, int64_t* ca, int64_t* cb) {
+  const int lane = threadIdx.x & 63;
+  const int nb = W / WB;
+  // 1. load, block-local balanced normalisation, carries between blocks
+  for (int q = lane; q < nb; q += 64) {
     int32_t a[WB];
 #pragma unroll
     for (int m = 0; m < WB; m++) a[m] = Ap[(int64_t)(q * WB + m) * as];
-    if (q > 0) v += Kp[(int64_t)q * ks];
+    int64_t v = q > 0 ? Kp[(int64_t)q * ks] : 0;
 #pragma unroll
     for (int m = 0; m < WB; m++) {
       v += a[m];
       const int32_t d = balanced29(v);
+      dg[q * WB + m] = d;
       v = (v - d) >> DB;
-      if (d != 0) topneg = d < 0;
     }
+    ca[q + 1] = v;
   }
-  if (v != 0) atomicOr(&flags[0], 2);
-  const bool neg = topneg != 0;
+  if (lane == 0) ca[0] = 0;
+  __syncthreads();
+  // carries out of block q were stored in ca[q+1]: the carry into block q
+  if (wave_resolve<true>(dg, nb, ca, cb) != 0 && lane == 0) atomicOr(&flags[0], 2);
+  // 2. sign: the top nonzero digit
+  int mytop = -1;
+  for (int s = lane; s < W; s += 64) if (dg[s] != 0) mytop = s;
+  const int top = wave_max(mytop);
+  const bool neg = top >= 0 && dg[top] < 0;
+  __syncthreads();
+  // 3. magnitude as standard digits
+  for (int q = lane; q < nb; q += 64) {
+    int64_t v = 0;
+#pragma unroll
+    for (int m = 0; m < WB; m++) {
+      const int64_t x = (int64_t)(neg ? -dg[q * WB + m] : dg[q * WB + m]) + v;
+      const int32_t u = (int32_t)(x & (RADIX - 1));
+      dg[q * WB + m] = u;
+      v = x >> DB;
+    }
+    ca[q + 1] = v;
+  }
+  if (lane == 0) ca[0] = 0;
+  __syncthreads();
+  wave_resolve<false>(dg, nb, ca, cb);
+  // 4. shift right by h bits; round to nearest, ties to even
   const int hq = h / DB, hb = h % DB;
   const int hbit_digit = (h - 1) / DB, hbit = (h - 1) % DB;
-  int64_t bor = 0, rc = 0, bc = 0;
-  int half = 0, sticky = 0, nout = 0, ctop = -1, stop = -1;
-  uint32_t prev = 0, stopv = 0;
-  auto put = [&](uint32_t so) {
-    if (nout >= cap) {
-      if (so) atomicOr(&flags[0], 16);
-      return;
+  const int nout = W - hq + 1;                 // output digits incl. a carry digit
+  const int nbo = (nout + WB - 1) / WB;
+  for (int i = lane; i < nbo * WB; i += 64) {
+    uint32_t o = 0;
+    if (i < nout) {
+      const int s = hq + i;
+      const uint32_t lo = s < W ? (uint32_t)dg[s] : 0u;
+      const uint32_t hi = s + 1 < W ? (uint32_t)dg[s + 1] : 0u;
+      o = (lo >> hb) | (hb ? ((hi << (DB - hb)) & (uint32_t)(RADIX - 1)) : 0u);
     }
-    Sr[nout] = so;
-    if (so) { stop = nout; stopv = so; }
-    int64_t y = (int64_t)so + bc;
-    if (y >= (int64_t(1) << 28)) { y -= RADIX; bc = 1; } else bc = 0;
-    const int32_t bd = (int32_t)(neg ? -y : y);
-    Cr[nout] = bd;
-    if (bd) ctop = nout;
-    nout++;
-  };
-  auto feed = [&](int s, uint32_t u) {
-    if (s == hbit_digit) {
-      half = (u >> hbit) & 1;
-      if (hbit > 0 && (u & ((1u << hbit) - 1))) sticky = 1;
-    } else if (s < hbit_digit && u) {
-      sticky = 1;
-    }
-    if (s > hq) {
-      const uint32_t o = (prev >> hb) | (hb ? ((u << (DB - hb)) & (uint32_t)(RADIX - 1)) : 0u);
-      if (s == hq + 1) rc = (half && (sticky || (o & 1))) ? 1 : 0;
-      const int64_t x = (int64_t)o + rc;
-      rc = x >> DB;
-      put((uint32_t)(x & (RADIX - 1)));
-    }
-    prev = u;
-  };
-  v = 0;
-  for (int q = 0; q < nbk; q++) {
-    int32_t a[WB];
+    ob[i] = (int32_t)o;
+  }
+  int st = 0;
+  for (int s = lane; s < hbit_digit; s += 64) st |= dg[s] != 0;
+  const uint32_t hd = (uint32_t)dg[hbit_digit];
+  const int sticky = __any(st) || (hbit > 0 && (hd & ((1u << hbit) - 1)));
+  const int half = (hd >> hbit) & 1;
+  __syncthreads();
+  const int inc = half && (sticky || (ob[0] & 1));
+  for (int q = lane; q <= nbo; q += 64) ca[q] = (q == 0) ? inc : 0;
+  __syncthreads();
+  if (wave_resolve<false>(ob, nbo, ca, cb) != 0 && lane == 0) atomicOr(&flags[0], 16);
+  // 5. standard digits out; balanced copy with the sign
+  int ts = -1;
+  for (int i = lane; i < nbo * WB; i += 64) {
+    const int32_t u = i < nout ? ob[i] : 0;
+    if (i < cap) Sr[i] = (uint32_t)u;
+    if (u != 0) { ts = i; if (i >= cap) atomicOr(&flags[0], 16); }
+  }
+  for (int i = nbo * WB + lane; i < cap; i += 64) Sr[i] = 0;
+  const int stop = wave_max(ts);
+  const uint32_t topv = stop >= 0 ? (uint32_t)ob[stop] : 0u;
+  __syncthreads();
+  for (int q = lane; q < nbo; q += 64) {
+    int64_t v = 0;
 #pragma unroll
-    for (int m = 0; m < WB; m++) a[m] = Ap[(int64_t)(q * WB + m) * as];
-    if (q > 0) v += Kp[(int64_t)q * ks];
     for (int m = 0; m < WB; m++) {
-      v += a[m];
+      v += ob[q * WB + m];
       const int32_t d = balanced29(v);
+      ob[q * WB + m] = d;
       v = (v - d) >> DB;
-      const int64_t x = (int64_t)(neg ? -d : d) + bor;
-      bor = x >> DB;
-      feed(q * WB + m, (uint32_t)(x & (RADIX - 1)));
     }
+    ca[q + 1] = v;
   }
-  feed(W, 0u);
-  if (rc) put((uint32_t)rc);
-  if (bc) {
-    if (nout < cap) { Sr[nout] = 0; Cr[nout] = neg ? -1 : 1; ctop = nout; nout++; }
-    else atomicOr(&flags[0], 16);
+  if (lane == 0) ca[0] = 0;
+  __syncthreads();
+  const int64_t extra = wave_resolve<true>(ob, nbo, ca, cb);   // 0 or 1: one more digit
+  int tb = -1;
+  for (int i = lane; i < cap; i += 64) {
+    int32_t d = i < nbo * WB ? ob[i] : 0;
+    if (i == nbo * WB) d = (int32_t)extra;
+    d = neg ? -d : d;
+    Cr[i] = d;
+    if (d != 0) tb = i;
   }
-  for (int i = nout; i < cap; i++) { Cr[i] = 0; Sr[i] = 0; }
+  if (extra != 0 && nbo * WB >= cap && lane == 0) atomicOr(&flags[0], 16);
   FinOut f;
-  f.nbal = ctop + 1;
+  f.nbal = wave_max(tb) + 1;
   f.nstd = stop + 1;
   f.neg = neg ? 1 : 0;
-  f.bits = stop < 0 ? 0 : DB * stop + (32 - __clz(stopv));
-  f.topv = stopv;
+  f.bits = stop < 0 ? 0 : DB * stop + (32 - __clz(topv));
+  f.topv = topv;
   return f;
 }
 
 // Column c after all its updates: C = RNE(A / 2^h) for every row (balanced
 // digits for the update, standard magnitude digits for the division); the
-// pivot row also stores |d| 2^sh normalised for the division.
-__global__ void __launch_bounds__(64) k_finalize(const ColInfo* __restrict__ cols, int N, int c,
-                                                 int rd, int h, int32_t* __restrict__ A,
-                                                 const int64_t* __restrict__ Kc,
-                                                 int32_t* __restrict__ Cb, uint32_t* __restrict__ S,
-                                                 uint32_t* __restrict__ Dd, int32_t* __restrict__ dinfo,
-                                                 int32_t* __restrict__ nCw, int32_t* __restrict__ nCs,
-                                                 int32_t* __restrict__ b32C, int32_t* __restrict__ flags) {
-  const int r = c + blockIdx.x * 64 + threadIdx.x;
-  if (r >= N) return;
-  const ColInfo cc = cols[c];
+// pivot row also stores |d| 2^sh normalised for the division.  One 64-lane
+// workgroup per (instance, row).
+__global__ void __launch_bounds__(64) k_finalize(const InstDesc* __restrict__ desc, int count, int c,
+                                                 int rd) {
+  extern __shared__ int64_t smem[];
+  int bid = blockIdx.x, inst = -1;
+  for (int i = 0; i < count; i++) {
+    const int n = max(0, desc[i].N - c);
+    if (bid < n) { inst = i; break; }
+    bid -= n;
+  }
+  if (inst < 0) return;
+  const InstDesc I = desc[inst];
+  if (!I.active) return;
+  const int N = I.N;
+  const int r = c + bid;
+  const ColInfo cc = I.cols[c];
   const int lr = r - c;
-  uint32_t* Srow = S + cc.soff + (int64_t)lr * cc.CW;
-  const FinOut f = finalize_entry(A + cc.aoff + lr, cc.R, cc.W,
-                                  Kc + cc.koff + (int64_t)rd * cc.nb * cc.R + lr, cc.R, h,
-                                  Cb + cc.coff + (int64_t)lr * cc.CW, Srow, cc.CW, flags);
+  int32_t* dg = (int32_t*)smem;
+  int32_t* ob = dg + (cc.W + 48);
+  int64_t* ca = (int64_t*)(ob + (cc.W + 48));
+  int64_t* cb = ca + (cc.W / WB + 8);
+  uint32_t* Srow = I.S + cc.soff + (int64_t)lr * cc.CW;
+  const FinOut f = wave_finalize(I.A + cc.aoff + lr, cc.R, cc.W,
+                                 I.Kc + cc.koff + (int64_t)rd * cc.nb * cc.R + lr, cc.R, I.h,
+                                 I.C + cc.coff + (int64_t)lr * cc.CW, Srow, cc.CW, I.flags, dg, ob, ca, cb);
+  if (threadIdx.x != 0) return;
   const int64_t ti = tri_index(N, c, r);
-  nCw[ti] = f.nbal;
-  nCs[ti] = f.neg ? -f.nstd : f.nstd;
-  b32C[ti] = (f.bits + 31) / 32;
+  I.nC[ti] = f.nbal;
+  I.nCs[ti] = f.neg ? -f.nstd : f.nstd;
+  I.b32C[ti] = (f.bits + 31) / 32;
   if (r == c) {
     if (f.nstd == 0 || f.neg) {
-      atomicMin(&flags[1], c);
-      if (f.nstd > 0 && f.neg) atomicAdd(&flags[2], 1);
+      atomicMin(&I.flags[1], c);
+      if (f.nstd > 0 && f.neg) atomicAdd(&I.flags[2], 1);
     }
     if (f.nstd > 0) {
       const int sh = 28 - (31 - __clz(f.topv));
-      uint32_t* Dp = Dd + cc.doff;
+      uint32_t* Dp = I.D + cc.doff;
       uint32_t carry = 0;
       for (int i = 0; i < f.nstd; i++) {
         const uint64_t x = ((uint64_t)Srow[i] << sh) | carry;
         Dp[i] = (uint32_t)(x & (RADIX - 1));
         carry = (uint32_t)(x >> DB);
       }
-      dinfo[4 * c] = f.nstd;
-      dinfo[4 * c + 1] = sh;
-      dinfo[4 * c + 2] = f.neg;
+      I.dinfo[4 * c] = f.nstd;
+      I.dinfo[4 * c + 1] = sh;
+      I.dinfo[4 * c + 2] = f.neg;
     } else {
-      dinfo[4 * c] = 0;
-      dinfo[4 * c + 1] = 0;
-      dinfo[4 * c + 2] = 0;
+      I.dinfo[4 * c] = 0;
+      I.dinfo[4 * c + 1] = 0;
+      I.dinfo[4 * c + 2] = 0;
     }
   }
 }
@@ -534,27 +627,31 @@ __device__ int divide_entry(int64_t* smem, const uint32_t* Sr, int ns, int negN,
 
 // L_c[r] = RNE(C_c[r] 2^h / d_c), one row per 64-lane workgroup; written in
 // the column layout (for the trailing update and forward solves) and in the
-// row layout L^T (for backward solves).
-__global__ void __launch_bounds__(64) k_divide(const ColInfo* __restrict__ cols, int N, int c,
-                                               int h, const uint32_t* __restrict__ S,
-                                               const uint32_t* __restrict__ Dd,
-                                               const int32_t* __restrict__ dinfo,
-                                               const int32_t* __restrict__ nCs,
-                                               int32_t* __restrict__ Lb, int32_t* __restrict__ LTb,
-                                               int32_t* __restrict__ nLw, int32_t* __restrict__ flags) {
+// row layout L^T (for backward solves).  Rows of every instance.
+__global__ void __launch_bounds__(64) k_divide(const InstDesc* __restrict__ desc, int count, int c) {
   extern __shared__ int64_t smem[];
-  const int r = c + 1 + blockIdx.x;
-  const ColInfo cc = cols[c];
-  const ColInfo cr = cols[r];
+  int bid = blockIdx.x, inst = -1;
+  for (int i = 0; i < count; i++) {
+    const int n = max(0, desc[i].N - c - 1);
+    if (bid < n) { inst = i; break; }
+    bid -= n;
+  }
+  if (inst < 0) return;
+  const InstDesc I = desc[inst];
+  if (!I.active) return;
+  const int N = I.N;
+  const int r = c + 1 + bid;
+  const ColInfo cc = I.cols[c];
+  const ColInfo cr = I.cols[r];
   const int64_t ti = tri_index(N, c, r);
-  const int nsg = nCs[ti];
+  const int nsg = I.nCs[ti];
   const int lr = r - c;
-  const int n = divide_entry(smem, S + cc.soff + (int64_t)lr * cc.CW, nsg < 0 ? -nsg : nsg, nsg < 0,
-                             Dd + cc.doff, dinfo[4 * c], dinfo[4 * c + 1], dinfo[4 * c + 2], h,
-                             Lb + cc.loff + lr, cc.R, cc.LW, LTb + cr.ltoff + c, cr.PT, flags);
+  const int n = divide_entry(smem, I.S + cc.soff + (int64_t)lr * cc.CW, nsg < 0 ? -nsg : nsg, nsg < 0,
+                             I.D + cc.doff, I.dinfo[4 * c], I.dinfo[4 * c + 1], I.dinfo[4 * c + 2], I.h,
+                             I.L + cc.loff + lr, cc.R, cc.LW, I.LT + cr.ltoff + c, cr.PT, I.flags);
   if (threadIdx.x == 0) {
-    nLw[ti] = n;
-    if (n > cc.LW - 2 * WB) atomicOr(&flags[0], 8);
+    I.nL[ti] = n;
+    if (n > cc.LW - 2 * WB) atomicOr(&I.flags[0], 8);
   }
 }
 
@@ -658,16 +755,22 @@ __global__ void __launch_bounds__(256) k_vupdate(const ColInfo* __restrict__ col
 
 // u_k = RNE(acc_k / 2^h) -> ub row k (balanced) and us row k (standard
 // magnitude), widths nU[k] and signed nUs[k]; optionally copied to out row k.
-__global__ void __launch_bounds__(64) k_vfinalize(int k, int rd, int h, int32_t* __restrict__ acc,
+// One 64-lane workgroup.
+__global__ void __launch_bounds__(64) k_vfinalize(int k, int rd, int h, const int32_t* __restrict__ acc,
                                                   const int64_t* __restrict__ kc, int Npad, int VA,
                                                   int nbA, int32_t* __restrict__ ub,
                                                   uint32_t* __restrict__ us, int32_t* __restrict__ nU,
                                                   int32_t* __restrict__ nUs, int VW,
                                                   int32_t* __restrict__ out,
                                                   int32_t* __restrict__ flags) {
+  extern __shared__ int64_t smem[];
+  int32_t* dg = (int32_t*)smem;
+  int32_t* ob = dg + (VA + 48);
+  int64_t* ca = (int64_t*)(ob + (VA + 48));
+  int64_t* cb = ca + (VA / WB + 8);
+  const FinOut f = wave_finalize(acc + k, Npad, VA, kc + (int64_t)rd * nbA * Npad + k, Npad, h,
+                                 ub + (int64_t)k * VW, us + (int64_t)k * VW, VW, flags, dg, ob, ca, cb);
   if (threadIdx.x == 0) {
-    const FinOut f = finalize_entry(acc + k, Npad, VA, kc + (int64_t)rd * nbA * Npad + k, Npad, h,
-                                    ub + (int64_t)k * VW, us + (int64_t)k * VW, VW, flags);
     nU[k] = f.nbal;
     nUs[k] = f.neg ? -f.nstd : f.nstd;
     if (f.nbal > VW - WB) atomicOr(&flags[0], 32);
@@ -728,13 +831,16 @@ __global__ void k_bitsL(const ColInfo* __restrict__ cols, int N, const int32_t* 
   }
 }
 
-// pivots d_k = C_k[k] gathered into one buffer of N rows x ld digits
-__global__ void k_gather_pivots(const ColInfo* __restrict__ cols, int N, int ld,
-                                const int32_t* __restrict__ Cb, int32_t* __restrict__ out) {
+// pivots d_k = C_k[k] of every instance gathered into rows of ld digits
+// (instance i at rows [i maxN, i maxN + N_i))
+__global__ void k_gather_pivots(const InstDesc* __restrict__ desc, int maxN, int ld,
+                                int32_t* __restrict__ out) {
+  const InstDesc I = desc[blockIdx.y];
   const int k = blockIdx.x;
-  const ColInfo kk = cols[k];
-  for (int i = threadIdx.x; i < ld; i += blockDim.x)
-    out[(int64_t)k * ld + i] = i < kk.CW ? Cb[kk.coff + i] : 0;
+  if (k >= I.N) return;
+  const ColInfo kk = I.cols[k];
+  int32_t* o = out + ((int64_t)blockIdx.y * maxN + k) * ld;
+  for (int i = threadIdx.x; i < ld; i += blockDim.x) o[i] = i < kk.CW ? I.C[kk.coff + i] : 0;
 }
 
 int blocks_for(int64_t n, int tpb) {
@@ -754,23 +860,35 @@ hipError_t launch_fill64(int64_t* p, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_fill64, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, n);
   return hipGetLastError();
 }
-hipError_t launch_expand(const Plan& P, const DevPtrs& D, hipStream_t s) {
-  hipLaunchKernelGGL(k_expand, dim3(P.N), dim3(256), 0, s, D.cols, P.N, P.WX, D.X, D.xs, D.A, D.Kc);
+hipError_t launch_expand(const BatchView& B, hipStream_t s) {
+  hipLaunchKernelGGL(k_expand, dim3(B.maxN, (unsigned)B.plans.size()), dim3(256), 0, s, B.ddesc);
   return hipGetLastError();
 }
-hipError_t launch_update(const Plan& P, const DevPtrs& D, int k0, int k1, int c_lo, int c_hi,
-                         int rd, hipStream_t s) {
-  const int64_t items = (int64_t)P.itemStart[c_hi] - P.itemStart[c_lo];
+int64_t update_items(const Plan& P, int pc, int b, int j) {
+  int k0, k1, c_lo, c_hi;
+  if (!update_range(P.N, pc, b, j, k0, k1, c_lo, c_hi)) return 0;
+  return (int64_t)P.itemStart[c_hi] - P.itemStart[c_lo];
+}
+hipError_t launch_update(const BatchView& B, int pc, int b, int j, int rd, hipStream_t s) {
+  int64_t items = 0;
+  for (const Plan* p : B.plans) items += update_items(*p, pc, b, j);
   if (items <= 0) return hipSuccess;
-  const int blocks = (int)((items + 3) / 4);
-  hipLaunchKernelGGL(k_update, dim3(blocks), dim3(256), 0, s, D.cols, D.itemStart, D.A, D.Kc,
-                     D.C, D.L, D.nC, D.nL, D.flags, P.N, k0, k1, c_lo, c_hi, rd);
+  hipLaunchKernelGGL(k_update, dim3((unsigned)((items + 3) / 4)), dim3(256), 0, s, B.ddesc,
+                     (int)B.plans.size(), pc, b, j, rd);
   return hipGetLastError();
 }
-hipError_t launch_finalize(const Plan& P, const DevPtrs& D, int c, int rd, hipStream_t s) {
-  const int rows = P.N - c;
-  hipLaunchKernelGGL(k_finalize, dim3((rows + 63) / 64), dim3(64), 0, s, D.cols, P.N, c, rd, P.h,
-                     D.A, D.Kc, D.C, D.S, D.D, D.dinfo, D.nC, D.nCs, D.b32C, D.flags);
+// LDS of wave_finalize for W digits
+static size_t fin_shm(int W) {
+  return sizeof(int32_t) * 2 * (size_t)(W + 48) + sizeof(int64_t) * 2 * (size_t)(W / WB + 8);
+}
+hipError_t launch_finalize(const BatchView& B, int c, int rd, hipStream_t s) {
+  int64_t rows = 0;
+  int W = 0;
+  for (const Plan* p : B.plans)
+    if (c < p->N) { rows += p->N - c; W = std::max(W, p->cols[c].W); }
+  if (rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_finalize, dim3((unsigned)rows), dim3(64), fin_shm(W), s, B.ddesc,
+                     (int)B.plans.size(), c, rd);
   return hipGetLastError();
 }
 // LDS of divide_entry: remainder nu + 3, divisor nd + 1, quotient nu - nd + 2
@@ -779,12 +897,21 @@ static size_t divide_shm(int h, int num_cap, int den_cap) {
   const int nu_max = Sq + num_cap + 1;
   return sizeof(int64_t) * (size_t)((nu_max + 3) + (den_cap + 3) + (nu_max + 3));
 }
-hipError_t launch_divide(const Plan& P, const DevPtrs& D, int c, hipStream_t s) {
-  const int rows = P.N - c - 1;
+hipError_t launch_divide(const BatchView& B, int c, hipStream_t s) {
+  int64_t rows = 0;
+  size_t shm = 0;
+  for (const Plan* p : B.plans)
+    if (c + 1 < p->N) {
+      rows += p->N - c - 1;
+      shm = std::max(shm, divide_shm(p->h, p->cols[c].CW, p->cols[c].W + 2));
+    }
   if (rows <= 0) return hipSuccess;
-  const ColInfo& cc = P.cols[c];
-  hipLaunchKernelGGL(k_divide, dim3(rows), dim3(64), divide_shm(P.h, cc.CW, cc.W + 2), s, D.cols,
-                     P.N, c, P.h, D.S, D.D, D.dinfo, D.nCs, D.L, D.LT, D.nL, D.flags);
+  hipLaunchKernelGGL(k_divide, dim3((unsigned)rows), dim3(64), shm, s, B.ddesc, (int)B.plans.size(), c);
+  return hipGetLastError();
+}
+hipError_t launch_gather_pivots_b(const BatchView& B, int32_t* out, int ld, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_pivots, dim3(B.maxN, (unsigned)B.plans.size()), dim3(64), 0, s, B.ddesc,
+                     B.maxN, ld, out);
   return hipGetLastError();
 }
 hipError_t launch_vinit(const Plan& P, const DevPtrs& D, const int32_t* src, int Sbits, hipStream_t s) {
@@ -805,7 +932,7 @@ hipError_t launch_vupdate(const Plan& P, const DevPtrs& D, int bwd, int k0, int 
 }
 hipError_t launch_vfinalize(const Plan& P, const DevPtrs& D, int k, int rd, int32_t* out,
                             hipStream_t s) {
-  hipLaunchKernelGGL(k_vfinalize, dim3(1), dim3(64), 0, s, k, rd, P.h, D.acc, D.kca, P.Npad, P.VA,
+  hipLaunchKernelGGL(k_vfinalize, dim3(1), dim3(64), fin_shm(P.VA), s, k, rd, P.h, D.acc, D.kca, P.Npad, P.VA,
                      P.VA / WB, D.ub, D.us, D.nU, D.nUs, P.VW, out, D.flags);
   return hipGetLastError();
 }
@@ -818,11 +945,6 @@ hipError_t launch_vscale(const Plan& P, const DevPtrs& D, const uint32_t* md, in
                          int32_t* out, hipStream_t s) {
   hipLaunchKernelGGL(k_vscale, dim3(P.N), dim3(64), divide_shm(P.K, P.VW, nd + 2), s, P.K, D.us,
                      D.nUs, P.VW, md, nd, sh, out, D.flags);
-  return hipGetLastError();
-}
-hipError_t launch_gather_pivots(const Plan& P, const DevPtrs& D, int32_t* out, int ld,
-                                hipStream_t s) {
-  hipLaunchKernelGGL(k_gather_pivots, dim3(P.N), dim3(64), 0, s, D.cols, P.N, ld, D.C, out);
   return hipGetLastError();
 }
 hipError_t launch_bits(const Plan& P, const DevPtrs& D, hipStream_t s) {

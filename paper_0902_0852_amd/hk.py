@@ -54,12 +54,30 @@ class Report(ctypes.Structure):
                 ("update_ms", ctypes.c_double)]
 
 
+class Instance(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int), ("beta", Rational), ("prec_bits", ctypes.c_int)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("factorizations", ctypes.c_int),
+                ("verified", ctypes.c_int), ("lambda_dec", ctypes.c_char * 192)]
+
+
+class BatchReport(ctypes.Structure):
+    _fields_ = [("panel", ctypes.c_int), ("graph_launches", ctypes.c_int),
+                ("t_build_s", ctypes.c_double), ("t_factor_s", ctypes.c_double),
+                ("t_total_s", ctypes.c_double)]
+
+
 _lib = None
 
 # every symbol that include/hk.h declares
 EXPORTS = ["hk_workspace_bytes", "hk_build_matrix", "hk_factor", "hk_solve", "hk_smallest_eig",
            "hk_matrix_destroy", "hk_last_error", "hk_matrix_info", "hk_set_panel", "hk_set_timing",
-           "hk_factor_export", "hk_factor_limb_macs", "hk_vec_import", "hk_vec_export"]
+           "hk_factor_export", "hk_factor_limb_macs", "hk_vec_import", "hk_vec_export",
+           "hk_batch_workspace_bytes", "hk_eig_batched", "hk_autotune",
+           "hk_mlp_nparams", "hk_mlp_cache_floats", "hk_mlp_forward", "hk_mlp_backward", "hk_mlp_mse",
+           "hk_mlp_adam_step"]
 
 
 def lib():
@@ -97,6 +115,25 @@ def lib():
         L.hk_vec_import.argtypes = [P, I, P, P, P, P, P]
         L.hk_vec_export.restype = I64
         L.hk_vec_export.argtypes = [P, P, I, P, P, P, I64, P]
+        L.hk_batch_workspace_bytes.restype = SZ
+        L.hk_batch_workspace_bytes.argtypes = [P, I]
+        L.hk_eig_batched.restype = I
+        L.hk_eig_batched.argtypes = [P, I, I, I, P, SZ, P, P, ctypes.POINTER(BatchReport)]
+        L.hk_autotune.restype = I
+        L.hk_autotune.argtypes = [P, I, P, SZ, P, ctypes.c_char_p, ctypes.POINTER(I)]
+        F = ctypes.c_float
+        L.hk_mlp_nparams.restype = I
+        L.hk_mlp_nparams.argtypes = []
+        L.hk_mlp_cache_floats.restype = I
+        L.hk_mlp_cache_floats.argtypes = []
+        L.hk_mlp_forward.restype = I
+        L.hk_mlp_forward.argtypes = [P, P, I, P, P, P]
+        L.hk_mlp_backward.restype = I
+        L.hk_mlp_backward.argtypes = [P, P, P, I, P, P, P]
+        L.hk_mlp_mse.restype = I
+        L.hk_mlp_mse.argtypes = [P, P, I, P, P, P]
+        L.hk_mlp_adam_step.restype = I
+        L.hk_mlp_adam_step.argtypes = [P, P, P, P, I, F, F, F, F, I, P]
         _lib = L
     return _lib
 
@@ -305,3 +342,118 @@ def smallest_eig(N, beta, K, method=HK_INVERSE, digits=45, shift_fixed=None, str
     d = {k: getattr(rep, k) for k, _ in Report._fields_}
     d["lambda_dec"] = rep.lambda_dec.decode()
     return out.value.decode(), d
+
+
+def _instances(insts):
+    arr = (Instance * len(insts))()
+    for i, (N, beta, K) in enumerate(insts):
+        arr[i] = Instance(N, _rational(beta), K)
+    return arr
+
+
+def batch_workspace_bytes(insts):
+    arr = _instances(insts)
+    return lib().hk_batch_workspace_bytes(ctypes.cast(arr, ctypes.c_void_p), len(insts))
+
+
+def eig_batched(insts, digits=45, panel=0, stream=None, ws=None):
+    """lambda_1 of every (N, beta, K) instance in one batch; returns
+    (list of (status, decimal, verified, factorizations), report dict)."""
+    import torch
+    L = lib()
+    arr = _instances(insts)
+    nbytes = L.hk_batch_workspace_bytes(ctypes.cast(arr, ctypes.c_void_p), len(insts))
+    if nbytes == 0:
+        raise HKError(1, L.hk_last_error().decode())
+    ws = ws if ws is not None else torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    out = (Result * len(insts))()
+    rep = BatchReport()
+    st = L.hk_eig_batched(ctypes.cast(arr, ctypes.c_void_p), len(insts), digits, panel,
+                          ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream),
+                          ctypes.cast(out, ctypes.c_void_p), ctypes.byref(rep))
+    res = [(r.status, r.lambda_dec.decode(), r.verified, r.factorizations) for r in out]
+    d = {k: getattr(rep, k) for k, _ in BatchReport._fields_}
+    d["status"] = st
+    if st != 0 and all(r[0] == 0 for r in res):
+        _check(st)
+    return res, d
+
+
+def autotune(insts, cache_path=None, stream=None, ws=None):
+    import torch
+    L = lib()
+    arr = _instances(insts)
+    nbytes = L.hk_batch_workspace_bytes(ctypes.cast(arr, ctypes.c_void_p), len(insts))
+    ws = ws if ws is not None else torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    best = ctypes.c_int(0)
+    _check(L.hk_autotune(ctypes.cast(arr, ctypes.c_void_p), len(insts), ctypes.c_void_p(ws.data_ptr()),
+                         ws.numel(), _stream(stream),
+                         cache_path.encode() if cache_path else None, ctypes.byref(best)))
+    return best.value
+
+
+# ---- precision-proposal network (float32 device tensors) ----------------
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _f32(t, n=None):
+    import torch
+    if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+        raise HKError(1, "float32 contiguous device tensor expected")
+    if n is not None and t.numel() < n:
+        raise HKError(1, "tensor too small: %d < %d" % (t.numel(), n))
+    return t
+
+
+def mlp_nparams():
+    return lib().hk_mlp_nparams()
+
+
+def mlp_cache_floats():
+    return lib().hk_mlp_cache_floats()
+
+
+def mlp_forward(W, X, cache=None, stream=None):
+    """Y (batch x 2) = net(X) on the GPU; fills cache when given."""
+    import torch
+    b = X.shape[0]
+    _f32(W, mlp_nparams()); _f32(X, 3 * b)
+    if cache is not None:
+        _f32(cache, b * mlp_cache_floats())
+    Y = torch.empty((b, 2), dtype=torch.float32, device=X.device)
+    _check(lib().hk_mlp_forward(_ptr(W), _ptr(X), b, _ptr(Y), _ptr(cache), _stream(stream)))
+    return Y
+
+
+def mlp_backward(W, cache, dY, stream=None):
+    """Gradient of sum(dY * Y) with respect to the packed parameters."""
+    import torch
+    b = dY.shape[0]
+    _f32(W, mlp_nparams()); _f32(cache, b * mlp_cache_floats()); _f32(dY, 2 * b)
+    dW = torch.empty(mlp_nparams(), dtype=torch.float32, device=W.device)
+    delta = torch.empty(b * 192, dtype=torch.float32, device=W.device)
+    _check(lib().hk_mlp_backward(_ptr(W), _ptr(cache), _ptr(dY), b, _ptr(dW), _ptr(delta),
+                                 _stream(stream)))
+    return dW
+
+
+def mlp_mse(Y, T, stream=None):
+    """(loss tensor of one element, dY) on the GPU."""
+    import torch
+    b = Y.shape[0]
+    _f32(Y, 2 * b); _f32(T, 2 * b)
+    dY = torch.empty_like(Y)
+    loss = torch.empty(1, dtype=torch.float32, device=Y.device)
+    _check(lib().hk_mlp_mse(_ptr(Y), _ptr(T), b, _ptr(dY), _ptr(loss), _stream(stream)))
+    return loss, dY
+
+
+def mlp_adam_step(W, m, v, dW, step, lr, b1=0.9, b2=0.999, eps=1e-8, stream=None):
+    """In-place Adam update of W, m, v."""
+    n = W.numel()
+    for t in (W, m, v, dW):
+        _f32(t, n)
+    _check(lib().hk_mlp_adam_step(_ptr(W), _ptr(m), _ptr(v), _ptr(dW), n, lr, b1, b2, eps, step,
+                                  _stream(stream)))
