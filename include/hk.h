@@ -191,7 +191,12 @@ typedef struct {
   hk_status status;
   int factorizations;     /* factorisations this instance took part in   */
   int verified;           /* 1 if the inertia bracket held               */
-  char lambda_dec[192];   /* lambda_1, `digits` significant digits       */
+  char lambda_dec[192];   /* lambda_1 in decimal scientific notation     */
+  int bits_used;          /* K of the returned value                     */
+  int solves;             /* hk_solve calls (inverse iteration)          */
+  int path;               /* 0: plain method, checked by the inertia
+                             bracket; 1: learned proposal, accepted by the
+                             rerun at +25% bits (hk_eig_learned)         */
 } hk_result;
 
 typedef struct {
@@ -254,6 +259,54 @@ hk_status hk_mlp_mse(const float* Y, const float* T, int batch, float* dY, float
    m, v are the moment estimates (start at zero), updated in place with W. */
 hk_status hk_mlp_adam_step(float* W, float* m, float* v, const float* dW, int nparams, float lr,
                            float b1, float b2, float eps, int step, hipStream_t s);
+
+/* ---- learned precision and shift ----------------------------------------
+   Scaling of the network's inputs and outputs and the two validation
+   statistics the proposal uses. */
+typedef struct {
+  float in_mean[3], in_scale[3];    /* features (N, beta, ln N): (x - mean) / scale   */
+  float out_mean[2], out_scale[2];  /* outputs: y * scale + mean = (bits, ln lambda_1) */
+  float bits_margin;                /* proposed bits = predicted bits * margin        */
+  float rmse_ln_lambda;             /* validation RMSE of the predicted ln lambda_1   */
+} hk_mlp_meta;
+
+/* Proposals for count instances: bits_hat[i] = predicted bits x margin,
+   rounded up to a multiple of 32 (>= 64); ln_sigma_hat[i] = predicted
+   ln lambda_1 - 3 RMSE.  W: trained parameters (device); dev_io: device
+   scratch of 5 * count floats.  Synchronises s. */
+hk_status hk_mlp_propose(const float* W, const hk_mlp_meta* meta, const hk_instance* inst, int count,
+                         float* dev_io, hipStream_t s, int* bits_hat, double* ln_sigma_hat);
+
+/* The inertia bracket of "Interval Verification" for many instances at
+   once: lambda_dec[i] (decimal scientific notation) truncated to `digits`
+   significant digits, floored to K_i bits, must leave every pivot of
+   M - xI positive, and one unit more in the last digit (ceiled) must give
+   exactly one negative pivot, in instance i's own precision K_i =
+   inst[i].prec_bits.  ok[i] = 1 when both hold.  Two batched
+   factorisations; dev_ws of hk_batch_workspace_bytes(inst, count) bytes.
+   Used to find the bits an instance needs.  Synchronises s. */
+hk_status hk_bracket_batched(const hk_instance* inst, int count, const char* const* lambda_dec, int digits,
+                             int panel, void* dev_ws, size_t ws_bytes, hipStream_t s, int* ok);
+
+/* Device bytes hk_eig_learned needs for these instances and proposals. */
+size_t hk_learned_workspace_bytes(const hk_instance* inst, int count, const int* bits_hat);
+
+/* lambda_1 of every instance with proposed precisions and shifts (not in
+   the paper).  For instance i with b = bits_hat[i] and sigma =
+   exp(ln_sigma_hat[i]): M - sigma I is factored at b and at ceil(1.25 b)
+   bits (all instances and both precisions in one batched factorisation;
+   a pivot <= 0 halves sigma, at most three times, then sigma = 0), inverse
+   iteration runs on each factorisation, and lambda(1.25 b) is accepted
+   when it agrees with lambda(b) to 10^-digits relative (out[i].path = 1).
+   Otherwise the precision rises by 1.25 at most twice more, each level
+   compared with the one before; when nothing agrees, or the next level
+   would exceed inst[i].prec_bits, the plain method runs at
+   inst[i].prec_bits (inverse iteration from 0 and the inertia bracket,
+   out[i].path = 0).  lambda_dec carries digits + 5 significant digits.
+   rep may be NULL.  Synchronises s. */
+hk_status hk_eig_learned(const hk_instance* inst, int count, const int* bits_hat, const double* ln_sigma_hat,
+                         int digits, int panel, void* dev_ws, size_t ws_bytes, hipStream_t s, hk_result* out,
+                         hk_batch_report* rep);
 
 #ifdef __cplusplus
 }

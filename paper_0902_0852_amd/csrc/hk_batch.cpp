@@ -17,7 +17,7 @@
 #include <thread>
 #include <vector>
 
-#include "hk_internal.hpp"
+#include "hk_batch.hpp"
 
 using namespace hk;
 
@@ -27,26 +27,12 @@ hk_status dfail_b(hk_status st, const std::string& msg) { g_err = msg; return st
 
 static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-struct Batch {
-  int count = 0, maxN = 0, ld = 0, panel = 4;
-  std::vector<hk_matrix> mats;
-  std::vector<InstDesc> hdesc;
-  InstDesc* ddesc = nullptr;
-  int32_t* flags = nullptr;
-  int32_t* piv = nullptr;
-  BatchView B;
-  hipStream_t cap = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  int captured_panel = 0;
-  int graph_launches = 0;
-  ~Batch() {
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
-    if (cap) (void)hipStreamDestroy(cap);
-    for (auto m : mats) hk_matrix_destroy(m);
-  }
-};
+Batch::~Batch() {
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (cap) (void)hipStreamDestroy(cap);
+  for (auto m : mats) hk_matrix_destroy(m);
+}
 
 // per-batch layout: descriptors, flags, pivot rows, then one workspace per instance
 static bool batch_layout(const hk_instance* inst, int count, std::vector<size_t>& off, size_t& total,
@@ -79,8 +65,8 @@ __global__ void k_reset_flags(int32_t* flags, int count) {
   if (i < count * 16) flags[i] = (i % 16) == 1 ? INT_MAX : 0;
 }
 
-static hk_status build_batch(Batch& bt, const hk_instance* inst, int count, void* ws, size_t ws_bytes,
-                             hipStream_t s) {
+hk_status build_batch(Batch& bt, const hk_instance* inst, int count, void* ws, size_t ws_bytes,
+                      hipStream_t s) {
   std::vector<size_t> off;
   size_t total;
   if (count < 1) return dfail_b(HK_EINVAL, "empty batch");
@@ -153,11 +139,8 @@ static hk_status ensure_graph(Batch& bt) {
   return HK_OK;
 }
 
-struct BEval { hk_status st; int nneg, first_bad; std::vector<MP> piv; };
-
-// one batched factorisation: instance i at shift x[i] if act[i]
-static hk_status factor_batch(Batch& bt, const std::vector<MP>& x, const std::vector<int>& act,
-                              hipStream_t s, std::vector<BEval>& out, bool want_pivots) {
+hk_status factor_batch(Batch& bt, const std::vector<MP>& x, const std::vector<int>& act, hipStream_t s,
+                       std::vector<BEval>& out, bool want_pivots) {
   hk_status st = ensure_graph(bt);
   if (st != HK_OK) return st;
   std::vector<std::vector<int32_t>> xs(bt.count);
@@ -243,13 +226,8 @@ void secant_delete(SecantRun* r);
 bool secant_next(SecantRun* r, MP& x, int& inertia);
 void secant_feed(SecantRun* r, hk_status st, int nneg, int first_bad, const std::vector<MP>& piv);
 bool secant_done(SecantRun* r, MP& lam, hk_status& st, std::string& err);
-void decimal_bracket(const MP& lam, int K, int digits, MP& xlo, MP& xhi, std::string& dec);
 
-}  // namespace hk
-
-extern "C" {
-
-size_t hk_batch_workspace_bytes(const hk_instance* inst, int count) {
+size_t batch_bytes(const hk_instance* inst, int count) {
   std::vector<size_t> off;
   size_t total;
   int maxN, ld;
@@ -257,6 +235,14 @@ size_t hk_batch_workspace_bytes(const hk_instance* inst, int count) {
   if (!batch_layout(inst, count, off, total, maxN, ld)) return 0;
   return total;
 }
+
+int tuned_panel(const hk_instance* inst, int count) { return cached_panel(tune_key(inst, count)); }
+
+}  // namespace hk
+
+extern "C" {
+
+size_t hk_batch_workspace_bytes(const hk_instance* inst, int count) { return batch_bytes(inst, count); }
 
 hk_status hk_eig_batched(const hk_instance* inst, int count, int digits, int panel, void* dev_ws,
                          size_t ws_bytes, hipStream_t s, hk_result* out, hk_batch_report* rep) {
@@ -266,7 +252,7 @@ hk_status hk_eig_batched(const hk_instance* inst, int count, int digits, int pan
   Batch bt;
   hk_status st = build_batch(bt, inst, count, dev_ws, ws_bytes, s);
   if (st != HK_OK) return st;
-  bt.panel = panel > 0 ? panel : cached_panel(tune_key(inst, count));
+  bt.panel = panel > 0 ? panel : tuned_panel(inst, count);
   if (bt.panel <= 0) bt.panel = 4;
   auto t1 = std::chrono::steady_clock::now();
   std::vector<SecantRun*> sm(count);
@@ -313,6 +299,8 @@ hk_status hk_eig_batched(const hk_instance* inst, int count, int digits, int pan
   hk_status first = st;
   for (int i = 0; i < count; i++) {
     out[i].factorizations = nfact[i] + (done[i] ? 2 : 0);
+    out[i].bits_used = bt.mats[i]->P.K;
+    out[i].path = 0;
     if (st == HK_OK && done[i]) {
       const int N = bt.mats[i]->P.N;
       const bool okb = elo[i].st == HK_OK && elo[i].nneg == 0 && elo[i].first_bad < 0 &&

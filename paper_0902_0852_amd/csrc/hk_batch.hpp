@@ -1,0 +1,58 @@
+// The batch object shared by the batched drivers: every instance's workspace
+// inside one caller buffer, the device descriptor array, per-instance status
+// flags and pivot rows, and the captured graph of one factorisation.
+#pragma once
+#include <string>
+#include <vector>
+
+#include "hk_internal.hpp"
+
+namespace hk {
+
+struct Batch {
+  int count = 0, maxN = 0, ld = 0, panel = 4;
+  std::vector<hk_matrix> mats;
+  std::vector<InstDesc> hdesc;
+  InstDesc* ddesc = nullptr;
+  int32_t* flags = nullptr;
+  int32_t* piv = nullptr;
+  BatchView B;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int captured_panel = 0;
+  int graph_launches = 0;
+  Batch() = default;
+  Batch(const Batch&) = delete;
+  Batch& operator=(const Batch&) = delete;
+  ~Batch();
+};
+
+// outcome of one instance in a batched factorisation
+struct BEval { hk_status st; int nneg, first_bad; std::vector<MP> piv; };
+
+// Lays the batch out in ws (moments on the host, then uploads).
+hk_status build_batch(Batch& bt, const hk_instance* inst, int count, void* ws, size_t ws_bytes,
+                      hipStream_t s);
+// One batched factorisation: instance i at shift x[i] (K_i fractional bits)
+// when act[i] != 0, replayed from the captured graph; synchronises s.
+hk_status factor_batch(Batch& bt, const std::vector<MP>& x, const std::vector<int>& act, hipStream_t s,
+                       std::vector<BEval>& out, bool want_pivots);
+// bytes of the batch layout (0 and g_err set if an instance is invalid)
+size_t batch_bytes(const hk_instance* inst, int count);
+// panel width from the tuning cache (HK_TUNE_CACHE) for this batch shape, else 0
+int tuned_panel(const hk_instance* inst, int count);
+
+// shared with the single-instance drivers (hk_drivers.cpp)
+void decimal_bracket(const MP& lam, int K, int digits, MP& xlo, MP& xhi, std::string& dec);
+bool parse_decimal(const char* s, int digits, MP& D, int64_t& e);
+MP decimal_to_fixed(const MP& D, int64_t e, int K, bool ceil_mode);
+std::string decimal_string(const MP& lam, int K, int digits);
+// |a - b| <= 10^-tol |b| for values with the same number of fractional bits
+bool agree(const MP& a, const MP& b, int tol);
+// inverse iteration on the current factorisation of m, which was taken at
+// shift sigma (K fractional bits); lam gets K fractional bits
+hk_status inverse_iterate(hk_matrix m, hipStream_t s, const MP& sigma, int tol, int max_iter, MP& lam,
+                          int& solves, double& t_solve);
+
+}  // namespace hk

@@ -19,11 +19,12 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
 
-#include "hk_internal.hpp"
+#include "hk_batch.hpp"
 
 using namespace hk;
 
@@ -273,7 +274,7 @@ static void truncate_digits(const MP& x, int K, int digits, MP& D, int64_t& e) {
 }
 
 // fixed point (K fractional bits) of D * 10^e, floor or ceil
-static MP decimal_to_fixed(const MP& D, int64_t e, int K, bool ceil_mode) {
+MP decimal_to_fixed(const MP& D, int64_t e, int K, bool ceil_mode) {
   MP num = shl(D, K), den = MP::from_u64(1);
   if (e >= 0) num = mul(num, pow10((uint32_t)e));
   else den = pow10((uint32_t)(-e));
@@ -292,6 +293,50 @@ void decimal_bracket(const MP& lam, int K, int digits, MP& xlo, MP& xhi, std::st
   dec = ds.substr(0, 1) + "." + ds.substr(1) + buf;
   xlo = decimal_to_fixed(D, e, K, false);
   xhi = decimal_to_fixed(add(D, MP::from_u64(1)), e, K, true);
+}
+
+// "d.ddd...e[+-]x" -> its first `digits` significant digits D and e with
+// value D * 10^e (truncated); false on a malformed or non-positive string
+bool parse_decimal(const char* str, int digits, MP& D, int64_t& e) {
+  if (!str || digits < 1) return false;
+  std::string ds;
+  int64_t exp10 = 0, point = -1;
+  const char* p = str;
+  for (; *p && *p != 'e' && *p != 'E'; p++) {
+    if (*p == '.') { if (point >= 0) return false; point = (int64_t)ds.size(); continue; }
+    if (*p < '0' || *p > '9') return false;
+    ds.push_back(*p);
+  }
+  if (*p) {
+    char* end = nullptr;
+    exp10 = strtoll(p + 1, &end, 10);
+    if (!end || *end) return false;
+  }
+  if (point < 0) point = (int64_t)ds.size();
+  size_t lead = ds.find_first_not_of('0');
+  if (lead == std::string::npos) return false;
+  // value = 0.ds * 10^(point + exp10) with ds starting at its first nonzero digit
+  const int64_t mag = point - (int64_t)lead + exp10;   // value in [10^(mag-1), 10^mag)
+  ds = ds.substr(lead);
+  if ((int)ds.size() > digits) ds.resize(digits);
+  while ((int)ds.size() < digits) ds.push_back('0');
+  D = MP();
+  for (char c : ds) D = add(mul_small(D, 10), MP::from_u64((uint64_t)(c - '0')));
+  e = mag - digits;
+  return true;
+}
+
+std::string decimal_string(const MP& lam, int K, int digits) {
+  MP xlo, xhi;
+  std::string dec;
+  decimal_bracket(lam, K, digits, xlo, xhi, dec);
+  return dec;
+}
+
+bool agree(const MP& a, const MP& b, int tol) {
+  MP bb = b;
+  bb.neg = false;
+  return within_tol(sub(a, b), bb, tol);
 }
 
 struct SecantRun { SecantMachine m; };
@@ -360,9 +405,7 @@ static hk_status vec_to_host(hk_matrix m, const int32_t* dev, hipStream_t s, std
 // then 0 is used.
 hk_status inverse_driver(DriverCtx& cx, const hk_mpf* shift_hint, int tol, int max_iter, MP& lam,
                          int& solves) {
-  hk_matrix m = cx.m;
-  const Plan& P = m->P;
-  const int K = P.K, N = P.N;
+  const int K = cx.m->P.K;
   solves = 0;
   MP sigma;
   if (shift_hint) {
@@ -381,36 +424,64 @@ hk_status inverse_driver(DriverCtx& cx, const hk_mpf* shift_hint, int tol, int m
     if (ev.st != HK_ENOTSPD || sigma.is_zero()) return ev.st;
     sigma = attempt < 3 ? floor_shr(sigma, 1) : MP();
   }
+  return inverse_iterate(cx.m, cx.s, sigma, tol, max_iter, lam, solves, cx.t_solve);
+}
+
+// The iteration proper on a factorisation of M - sigma I.  Besides the
+// tolerance test it stops, returning the last estimate, once the change of
+// the estimate has fallen below 10^-(tol/2) of it and then fails to shrink
+// twice in a row: the iterates have reached the rounding floor of the
+// fixed-point solve at this K.
+hk_status inverse_iterate(hk_matrix m, hipStream_t s, const MP& sigma, int tol, int max_iter, MP& lam,
+                          int& solves, double& t_solve) {
+  const Plan& P = m->P;
+  const int K = P.K, N = P.N;
+  solves = 0;
   const int g = m->gbits;
   // v0 = 1 (K fractional bits)
   std::vector<MP> v(N, one_shl(K));
   {
     std::vector<int32_t> buf((size_t)N * P.VW, 0);
     for (int i = 0; i < N; i++) mp_to_digits(v[i], buf.data() + (size_t)i * P.VW, P.VW);
-    hipError_t e = hipMemcpyAsync(m->D.dv1, buf.data(), sizeof(int32_t) * buf.size(), hipMemcpyHostToDevice, cx.s);
-    if (e == hipSuccess) e = hipStreamSynchronize(cx.s);
+    hipError_t e = hipMemcpyAsync(m->D.dv1, buf.data(), sizeof(int32_t) * buf.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return dfail(HK_EDEVICE, hipGetErrorString(e));
   }
   const int64_t F = 2 * (int64_t)K + 64;   // fixed-point bits of the lambda iterates
-  MP lam_prev;
-  bool have_prev = false;
+  MP lam_prev, step_prev;
+  bool have_prev = false, have_step = false;
+  int no_shrink = 0;
   std::vector<MP> y;
   for (int it = 0; it < max_iter; it++) {
     auto t0 = std::chrono::steady_clock::now();
-    hk_status st = hk_solve(m, m->D.dv1, m->D.dv2, cx.s);
+    hk_status st = hk_solve(m, m->D.dv1, m->D.dv2, s);
     solves++;
     if (st != HK_OK) return st;
-    st = vec_to_host(m, m->D.dv2, cx.s, y);
-    cx.t_solve += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    st = vec_to_host(m, m->D.dv2, s, y);
+    t_solve += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (st != HK_OK) return st;
     MP vy, vv;
     for (int i = 0; i < N; i++) { vy = add(vy, mul(v[i], y[i])); vv = add(vv, mul(v[i], v[i])); }
     if (vy.sign() <= 0) return dfail(HK_EPRECISION, "non-positive Rayleigh quotient");
     // lambda 2^F = sigma 2^(F-K) + vv 2^(g+F) / vy
     MP lamF = add(shl(sigma, F - K), floor_div(shl(vv, g + F), vy));
-    if (have_prev && within_tol(sub(lamF, lam_prev), lamF, tol)) {
-      lam = rne_shr(lamF, F - K);
-      return HK_OK;
+    if (have_prev) {
+      MP step = sub(lamF, lam_prev);
+      step.neg = false;
+      if (within_tol(step, lamF, tol)) {
+        lam = rne_shr(lamF, F - K);
+        return HK_OK;
+      }
+      if (have_step && within_tol(step, lamF, tol / 2) && cmp(step, step_prev) >= 0) {
+        if (++no_shrink >= 2) {
+          lam = rne_shr(lamF, F - K);
+          return HK_OK;
+        }
+      } else {
+        no_shrink = 0;
+      }
+      step_prev = step;
+      have_step = true;
     }
     lam_prev = lamF;
     have_prev = true;
@@ -432,10 +503,10 @@ hk_status inverse_driver(DriverCtx& cx, const hk_mpf* shift_hint, int tol, int m
       if (w + 1 < msh.d.size()) lo |= (uint64_t)msh.d[w + 1] << 32;
       md[i] = (uint32_t)((lo >> (pos & 31)) & (RADIX - 1));
     }
-    hipError_t e = hipMemcpyAsync(m->D.md, md.data(), sizeof(uint32_t) * nd, hipMemcpyHostToDevice, cx.s);
-    if (e == hipSuccess) e = launch_vscale(P, m->D, m->D.md, nd, sh, m->D.dv1, cx.s);
+    hipError_t e = hipMemcpyAsync(m->D.md, md.data(), sizeof(uint32_t) * nd, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_vscale(P, m->D, m->D.md, nd, sh, m->D.dv1, s);
     if (e != hipSuccess) return dfail(HK_EDEVICE, hipGetErrorString(e));
-    st = vec_to_host(m, m->D.dv1, cx.s, v);
+    st = vec_to_host(m, m->D.dv1, s, v);
     if (st != HK_OK) return st;
   }
   return dfail(HK_ENOCONV, "inverse iteration did not converge");
@@ -454,8 +525,16 @@ hk_status hk_solve(hk_matrix m, const void* dev_rhs, void* dev_x, hipStream_t s)
   hipError_t e = launch_fill32(D.flags, 16, 0, s);
   // forward: acc = b 2^(h+g); z_k = RNE(acc_k / 2^h) column by column
   if (e == hipSuccess) e = launch_vinit(P, D, (const int32_t*)dev_rhs, h + m->gbits, s);
+  static const bool stepwise = getenv("HK_SOLVE_STEPWISE") != nullptr;
+  if (!stepwise) {
+    // one launch per sweep
+    if (e == hipSuccess) e = launch_vsweep(P, D, 0, b, nullptr, s);
+    if (e == hipSuccess) e = launch_vdivide(P, D, s);
+    if (e == hipSuccess) e = launch_vinit(P, D, D.wb, h, s);
+    if (e == hipSuccess) e = launch_vsweep(P, D, 1, b, (int32_t*)dev_x, s);
+  }
   int Pidx = 0;
-  for (int k0 = 0; k0 < N && e == hipSuccess; k0 += b, Pidx++) {
+  for (int k0 = 0; k0 < N && e == hipSuccess && stepwise; k0 += b, Pidx++) {
     const int bb = std::min(b, N - k0);
     for (int j = 0; j < bb && e == hipSuccess; j++) {
       const int k = k0 + j;
@@ -465,11 +544,11 @@ hk_status hk_solve(hk_matrix m, const void* dev_rhs, void* dev_x, hipStream_t s)
     if (e == hipSuccess && k0 + bb < N) e = launch_vupdate(P, D, 0, k0, k0 + bb, k0 + bb, N, Pidx & 1, s);
   }
   // diagonal: w_k = RNE(z_k 2^h / d_k)
-  if (e == hipSuccess) e = launch_vdivide(P, D, s);
+  if (e == hipSuccess && stepwise) e = launch_vdivide(P, D, s);
   // backward: acc = w 2^h; y_k = RNE(acc_k / 2^h), last row first
-  if (e == hipSuccess) e = launch_vinit(P, D, D.wb, h, s);
+  if (e == hipSuccess && stepwise) e = launch_vinit(P, D, D.wb, h, s);
   Pidx = 0;
-  for (int k_hi = N; k_hi > 0 && e == hipSuccess; k_hi -= b, Pidx++) {
+  for (int k_hi = N; k_hi > 0 && e == hipSuccess && stepwise; k_hi -= b, Pidx++) {
     const int k_lo = std::max(0, k_hi - b);
     for (int j = 0; j < k_hi - k_lo && e == hipSuccess; j++) {
       const int k = k_hi - 1 - j;

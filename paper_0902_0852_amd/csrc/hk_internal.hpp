@@ -131,6 +131,8 @@ hipError_t launch_vupdate(const Plan& P, const DevPtrs& D, int bwd, int k0, int 
 hipError_t launch_vfinalize(const Plan& P, const DevPtrs& D, int k, int rd, int32_t* out,
                             hipStream_t s);
 hipError_t launch_vdivide(const Plan& P, const DevPtrs& D, hipStream_t s);
+// the whole forward (bwd = 0) or backward (bwd = 1) sweep of a solve in one launch
+hipError_t launch_vsweep(const Plan& P, const DevPtrs& D, int bwd, int panel, int32_t* out, hipStream_t s);
 hipError_t launch_vscale(const Plan& P, const DevPtrs& D, const uint32_t* md, int nd, int sh,
                          int32_t* out, hipStream_t s);
 

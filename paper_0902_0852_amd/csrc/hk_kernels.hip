@@ -244,13 +244,28 @@ struct FinOut {
   uint32_t topv;  // top standard digit
 };
 
+// LDS ordering among the lanes of the one wavefront that runs a
+// wave_resolve / wave_finalize: a workgroup barrier when that wavefront is the
+// whole workgroup (BLK), else a wavefront-scope fence and wave barrier, so
+// that other wavefronts of a larger workgroup need not take part.
+template <bool BLK>
+__device__ __forceinline__ void lds_sync() {
+  if constexpr (BLK) {
+    __syncthreads();
+  } else {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
 // Carry resolution over nblk blocks of 16 digits held in LDS (x), one
 // wavefront: block q absorbs the carry cin[q] coming from block q-1 and
 // renormalises (balanced or standard digits), handing its own carry to block
 // q+1 in the next round; rounds repeat until no carry is left inside the
 // number (at most nblk rounds).  cin[0] may hold a carry into block 0.
 // Returns the total carry out of the top block.
-template <bool BAL>
+template <bool BAL, bool BLK = true>
 __device__ int64_t wave_resolve(int32_t* x, int nblk, int64_t* cin, int64_t* cout) {
   const int lane = threadIdx.x & 63;
   int64_t top = cin[nblk];   // carry already out of the top block
@@ -270,13 +285,13 @@ __device__ int64_t wave_resolve(int32_t* x, int nblk, int64_t* cin, int64_t* cou
       cout[q + 1] = v;
       any |= (v != 0) && (q + 1 < nblk);
     }
-    __syncthreads();
+    lds_sync<BLK>();
     top += cout[nblk];
     if (!__any(any)) break;
     for (int q = lane; q < nblk; q += 64) cin[q] = q == 0 ? 0 : cout[q];
-    __syncthreads();
+    lds_sync<BLK>();
   }
-  __syncthreads();
+  lds_sync<BLK>();
   return top;
 }
 
@@ -287,6 +302,7 @@ __device__ int64_t wave_resolve(int32_t* x, int nblk, int64_t* cin, int64_t* cou
 // digits, shifted right by h bits with round-to-nearest-even, and written as
 // balanced digits (Cr) and standard magnitude digits (Sr), cap each.  LDS:
 // dg and ob of W + 48 int32, ca and cb of W/16 + 8 int64.
+template <bool BLK = true>
 __device__ FinOut wave_finalize(const int32_t* Ap, int64_t as, int W, const int64_t* Kp, int64_t ks,
                                 int h, int32_t* Cr, uint32_t* Sr, int cap, int32_t* flags,
                                 int32_t* dg, int32_t* ob, int64_t* ca, int64_t* cb) {
@@ -308,15 +324,15 @@ __device__ FinOut wave_finalize(const int32_t* Ap, int64_t as, int W, const int6
     ca[q + 1] = v;
   }
   if (lane == 0) ca[0] = 0;
-  __syncthreads();
+  lds_sync<BLK>();
   // carries out of block q were stored in ca[q+1]: the carry into block q
-  if (wave_resolve<true>(dg, nb, ca, cb) != 0 && lane == 0) atomicOr(&flags[0], 2);
+  if (wave_resolve<true, BLK>(dg, nb, ca, cb) != 0 && lane == 0) atomicOr(&flags[0], 2);
   // 2. sign: the top nonzero digit
   int mytop = -1;
   for (int s = lane; s < W; s += 64) if (dg[s] != 0) mytop = s;
   const int top = wave_max(mytop);
   const bool neg = top >= 0 && dg[top] < 0;
-  __syncthreads();
+  lds_sync<BLK>();
   // 3. magnitude as standard digits
   for (int q = lane; q < nb; q += 64) {
     int64_t v = 0;
@@ -330,8 +346,8 @@ __device__ FinOut wave_finalize(const int32_t* Ap, int64_t as, int W, const int6
     ca[q + 1] = v;
   }
   if (lane == 0) ca[0] = 0;
-  __syncthreads();
-  wave_resolve<false>(dg, nb, ca, cb);
+  lds_sync<BLK>();
+  wave_resolve<false, BLK>(dg, nb, ca, cb);
   // 4. shift right by h bits; round to nearest, ties to even
   const int hq = h / DB, hb = h % DB;
   const int hbit_digit = (h - 1) / DB, hbit = (h - 1) % DB;
@@ -352,11 +368,11 @@ __device__ FinOut wave_finalize(const int32_t* Ap, int64_t as, int W, const int6
   const uint32_t hd = (uint32_t)dg[hbit_digit];
   const int sticky = __any(st) || (hbit > 0 && (hd & ((1u << hbit) - 1)));
   const int half = (hd >> hbit) & 1;
-  __syncthreads();
+  lds_sync<BLK>();
   const int inc = half && (sticky || (ob[0] & 1));
   for (int q = lane; q <= nbo; q += 64) ca[q] = (q == 0) ? inc : 0;
-  __syncthreads();
-  if (wave_resolve<false>(ob, nbo, ca, cb) != 0 && lane == 0) atomicOr(&flags[0], 16);
+  lds_sync<BLK>();
+  if (wave_resolve<false, BLK>(ob, nbo, ca, cb) != 0 && lane == 0) atomicOr(&flags[0], 16);
   // 5. standard digits out; balanced copy with the sign
   int ts = -1;
   for (int i = lane; i < nbo * WB; i += 64) {
@@ -367,7 +383,7 @@ __device__ FinOut wave_finalize(const int32_t* Ap, int64_t as, int W, const int6
   for (int i = nbo * WB + lane; i < cap; i += 64) Sr[i] = 0;
   const int stop = wave_max(ts);
   const uint32_t topv = stop >= 0 ? (uint32_t)ob[stop] : 0u;
-  __syncthreads();
+  lds_sync<BLK>();
   for (int q = lane; q < nbo; q += 64) {
     int64_t v = 0;
 #pragma unroll
@@ -380,8 +396,8 @@ __device__ FinOut wave_finalize(const int32_t* Ap, int64_t as, int W, const int6
     ca[q + 1] = v;
   }
   if (lane == 0) ca[0] = 0;
-  __syncthreads();
-  const int64_t extra = wave_resolve<true>(ob, nbo, ca, cb);   // 0 or 1: one more digit
+  lds_sync<BLK>();
+  const int64_t extra = wave_resolve<true, BLK>(ob, nbo, ca, cb);   // 0 or 1: one more digit
   int tb = -1;
   for (int i = lane; i < cap; i += 64) {
     int32_t d = i < nbo * WB ? ob[i] : 0;
@@ -699,21 +715,19 @@ __global__ void k_vinit(int32_t* __restrict__ acc, int64_t* __restrict__ kc,
 // acc_i -= sum_{k0 <= k < k1} V_k[i] u_k for rows i in [i_lo, i_hi):
 //   forward (bwd = 0): V_k[i] = L_k[i] (column layout), rows i > k;
 //   backward (bwd = 1): V_k[i] = L_i[k] (row layout L^T), rows i < k.
-// u_k (uniform): row k of ub (VW balanced digits, nU[k] used).
-__global__ void __launch_bounds__(256) k_vupdate(const ColInfo* __restrict__ cols, int N, int bwd,
-                                                 int k0, int k1, int i_lo, int i_hi, int rd,
-                                                 int32_t* __restrict__ acc, int64_t* __restrict__ kc,
-                                                 int Npad, int nbA, const int32_t* __restrict__ ub,
-                                                 const int32_t* __restrict__ nU, int VW,
-                                                 const int32_t* __restrict__ Lb,
-                                                 const int32_t* __restrict__ LTb,
-                                                 const int32_t* __restrict__ nLw, int LWT,
-                                                 int32_t* __restrict__ flags) {
-  const int wave = uni(threadIdx.x >> 6);
+// u_k (uniform): row k of ub (VW balanced digits, nU[k] used).  Work item
+// `it` of T * nbA (T row tiles of 64, nbA digit blocks) for one wavefront.
+__device__ __forceinline__ void vupdate_item(const ColInfo* __restrict__ cols, int N, int bwd, int k0,
+                                             int k1, int i_lo, int i_hi, int rd, int it,
+                                             int32_t* __restrict__ acc, int64_t* __restrict__ kc,
+                                             int Npad, int nbA, const int32_t* __restrict__ ub,
+                                             const int32_t* __restrict__ nU, int VW,
+                                             const int32_t* __restrict__ Lb,
+                                             const int32_t* __restrict__ LTb,
+                                             const int32_t* __restrict__ nLw, int LWT,
+                                             int32_t* __restrict__ flags) {
   const int lane = threadIdx.x & 63;
   const int T = (i_hi - i_lo + 63) / 64;
-  const int it = blockIdx.x * 4 + wave;
-  if (it >= T * nbA) return;
   const int q = uni(it / T);
   const int t = uni(it - q * T);
   const int i = i_lo + 64 * t + lane;
@@ -753,6 +767,23 @@ __global__ void __launch_bounds__(256) k_vupdate(const ColInfo* __restrict__ col
               q + 1 < nbA ? kc + ((int64_t)(rd ^ 1) * nbA + q + 1) * Npad + i : nullptr, flags);
 }
 
+__global__ void __launch_bounds__(256) k_vupdate(const ColInfo* __restrict__ cols, int N, int bwd,
+                                                 int k0, int k1, int i_lo, int i_hi, int rd,
+                                                 int32_t* __restrict__ acc, int64_t* __restrict__ kc,
+                                                 int Npad, int nbA, const int32_t* __restrict__ ub,
+                                                 const int32_t* __restrict__ nU, int VW,
+                                                 const int32_t* __restrict__ Lb,
+                                                 const int32_t* __restrict__ LTb,
+                                                 const int32_t* __restrict__ nLw, int LWT,
+                                                 int32_t* __restrict__ flags) {
+  const int wave = uni(threadIdx.x >> 6);
+  const int T = (i_hi - i_lo + 63) / 64;
+  const int it = blockIdx.x * 4 + wave;
+  if (it >= T * nbA) return;
+  vupdate_item(cols, N, bwd, k0, k1, i_lo, i_hi, rd, it, acc, kc, Npad, nbA, ub, nU, VW, Lb, LTb, nLw, LWT,
+               flags);
+}
+
 // u_k = RNE(acc_k / 2^h) -> ub row k (balanced) and us row k (standard
 // magnitude), widths nU[k] and signed nUs[k]; optionally copied to out row k.
 // One 64-lane workgroup.
@@ -778,6 +809,87 @@ __global__ void __launch_bounds__(64) k_vfinalize(int k, int rd, int h, const in
   if (out) {
     __syncthreads();
     for (int j = threadIdx.x; j < VW; j += 64) out[(int64_t)k * VW + j] = ub[(int64_t)k * VW + j];
+  }
+}
+
+// Whole forward (bwd = 0) or backward (bwd = 1) substitution of a solve in
+// one launch: one workgroup walks the columns with the same panel schedule,
+// carry parities and arithmetic as the per-step launches (k_vupdate,
+// k_vfinalize), the stages separated by workgroup barriers.  Wavefront 0
+// finalises u_k while the others wait; every wavefront takes update items.
+struct SweepArgs {
+  const ColInfo* cols;
+  int N, Npad, VA, nbA, VW, LWT, h, bwd, panel;
+  int32_t* acc; int64_t* kc; int32_t* ub; uint32_t* us; int32_t* nU; int32_t* nUs;
+  const int32_t* L; const int32_t* LT; const int32_t* nL; int32_t* out; int32_t* flags;
+};
+
+__device__ void sweep_finalize(const SweepArgs& a, int k, int rd, int64_t* smem) {
+  int32_t* dg = (int32_t*)smem;
+  int32_t* ob = dg + (a.VA + 48);
+  int64_t* ca = (int64_t*)(ob + (a.VA + 48));
+  int64_t* cb = ca + (a.VA / WB + 8);
+  const FinOut f = wave_finalize<false>(a.acc + k, a.Npad, a.VA, a.kc + (int64_t)rd * a.nbA * a.Npad + k,
+                                        a.Npad, a.h, a.ub + (int64_t)k * a.VW, a.us + (int64_t)k * a.VW, a.VW,
+                                        a.flags, dg, ob, ca, cb);
+  if ((threadIdx.x & 63) == 0) {
+    a.nU[k] = f.nbal;
+    a.nUs[k] = f.neg ? -f.nstd : f.nstd;
+    if (f.nbal > a.VW - WB) atomicOr(&a.flags[0], 32);
+  }
+  // each lane copies the digits it wrote itself
+  if (a.out)
+    for (int j = threadIdx.x & 63; j < a.VW; j += 64) a.out[(int64_t)k * a.VW + j] = a.ub[(int64_t)k * a.VW + j];
+}
+
+__device__ __forceinline__ void sweep_update(const SweepArgs& a, int k0, int k1, int i_lo, int i_hi, int rd) {
+  if (i_hi <= i_lo || k1 <= k0) return;
+  const int wave = uni(threadIdx.x >> 6), nw = blockDim.x >> 6;
+  const int items = ((i_hi - i_lo + 63) / 64) * a.nbA;
+  for (int it = wave; it < items; it += nw)
+    vupdate_item(a.cols, a.N, a.bwd, k0, k1, i_lo, i_hi, rd, it, a.acc, a.kc, a.Npad, a.nbA, a.ub, a.nU, a.VW,
+                 a.L, a.LT, a.nL, a.LWT, a.flags);
+}
+
+__global__ void __launch_bounds__(512) k_vsweep(SweepArgs a) {
+  extern __shared__ int64_t smem[];
+  const int wave = uni(threadIdx.x >> 6);
+  const int N = a.N, b = a.panel;
+  int P = 0;
+  if (!a.bwd) {
+    for (int k0 = 0; k0 < N; k0 += b, P++) {
+      const int bb = min(b, N - k0);
+      for (int j = 0; j < bb; j++) {
+        const int k = k0 + j;
+        if (j > 0) {
+          sweep_update(a, k0, k, k, k + 1, P & 1);
+          __syncthreads();
+        }
+        if (wave == 0) sweep_finalize(a, k, (P + (j > 0 ? 1 : 0)) & 1, smem);
+        __syncthreads();
+      }
+      if (k0 + bb < N) {
+        sweep_update(a, k0, k0 + bb, k0 + bb, N, P & 1);
+        __syncthreads();
+      }
+    }
+  } else {
+    for (int k_hi = N; k_hi > 0; k_hi -= b, P++) {
+      const int k_lo = max(0, k_hi - b);
+      for (int j = 0; j < k_hi - k_lo; j++) {
+        const int k = k_hi - 1 - j;
+        if (j > 0) {
+          sweep_update(a, k + 1, k_hi, k, k + 1, P & 1);
+          __syncthreads();
+        }
+        if (wave == 0) sweep_finalize(a, k, (P + (j > 0 ? 1 : 0)) & 1, smem);
+        __syncthreads();
+      }
+      if (k_lo > 0) {
+        sweep_update(a, k_lo, k_hi, 0, k_lo, P & 1);
+        __syncthreads();
+      }
+    }
   }
 }
 
@@ -934,6 +1046,15 @@ hipError_t launch_vfinalize(const Plan& P, const DevPtrs& D, int k, int rd, int3
                             hipStream_t s) {
   hipLaunchKernelGGL(k_vfinalize, dim3(1), dim3(64), fin_shm(P.VA), s, k, rd, P.h, D.acc, D.kca, P.Npad, P.VA,
                      P.VA / WB, D.ub, D.us, D.nU, D.nUs, P.VW, out, D.flags);
+  return hipGetLastError();
+}
+hipError_t launch_vsweep(const Plan& P, const DevPtrs& D, int bwd, int panel, int32_t* out, hipStream_t s) {
+  SweepArgs a;
+  a.cols = D.cols; a.N = P.N; a.Npad = P.Npad; a.VA = P.VA; a.nbA = P.VA / WB; a.VW = P.VW; a.LWT = P.LWT;
+  a.h = P.h; a.bwd = bwd; a.panel = panel < 1 ? 1 : panel;
+  a.acc = D.acc; a.kc = D.kca; a.ub = D.ub; a.us = D.us; a.nU = D.nU; a.nUs = D.nUs;
+  a.L = D.L; a.LT = D.LT; a.nL = D.nL; a.out = out; a.flags = D.flags;
+  hipLaunchKernelGGL(k_vsweep, dim3(1), dim3(512), fin_shm(P.VA), s, a);
   return hipGetLastError();
 }
 hipError_t launch_vdivide(const Plan& P, const DevPtrs& D, hipStream_t s) {

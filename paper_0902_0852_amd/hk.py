@@ -60,7 +60,14 @@ class Instance(ctypes.Structure):
 
 class Result(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("factorizations", ctypes.c_int),
-                ("verified", ctypes.c_int), ("lambda_dec", ctypes.c_char * 192)]
+                ("verified", ctypes.c_int), ("lambda_dec", ctypes.c_char * 192),
+                ("bits_used", ctypes.c_int), ("solves", ctypes.c_int), ("path", ctypes.c_int)]
+
+
+class MlpMeta(ctypes.Structure):
+    _fields_ = [("in_mean", ctypes.c_float * 3), ("in_scale", ctypes.c_float * 3),
+                ("out_mean", ctypes.c_float * 2), ("out_scale", ctypes.c_float * 2),
+                ("bits_margin", ctypes.c_float), ("rmse_ln_lambda", ctypes.c_float)]
 
 
 class BatchReport(ctypes.Structure):
@@ -77,7 +84,8 @@ EXPORTS = ["hk_workspace_bytes", "hk_build_matrix", "hk_factor", "hk_solve", "hk
            "hk_factor_export", "hk_factor_limb_macs", "hk_vec_import", "hk_vec_export",
            "hk_batch_workspace_bytes", "hk_eig_batched", "hk_autotune",
            "hk_mlp_nparams", "hk_mlp_cache_floats", "hk_mlp_forward", "hk_mlp_backward", "hk_mlp_mse",
-           "hk_mlp_adam_step"]
+           "hk_mlp_adam_step", "hk_mlp_propose", "hk_bracket_batched", "hk_learned_workspace_bytes",
+           "hk_eig_learned"]
 
 
 def lib():
@@ -134,6 +142,14 @@ def lib():
         L.hk_mlp_mse.argtypes = [P, P, I, P, P, P]
         L.hk_mlp_adam_step.restype = I
         L.hk_mlp_adam_step.argtypes = [P, P, P, P, I, F, F, F, F, I, P]
+        L.hk_mlp_propose.restype = I
+        L.hk_mlp_propose.argtypes = [P, ctypes.POINTER(MlpMeta), P, I, P, P, P, P]
+        L.hk_bracket_batched.restype = I
+        L.hk_bracket_batched.argtypes = [P, I, P, I, I, P, SZ, P, P]
+        L.hk_learned_workspace_bytes.restype = SZ
+        L.hk_learned_workspace_bytes.argtypes = [P, I, P]
+        L.hk_eig_learned.restype = I
+        L.hk_eig_learned.argtypes = [P, I, P, P, I, I, P, SZ, P, P, ctypes.POINTER(BatchReport)]
         _lib = L
     return _lib
 
@@ -373,6 +389,7 @@ def eig_batched(insts, digits=45, panel=0, stream=None, ws=None):
                           ctypes.cast(out, ctypes.c_void_p), ctypes.byref(rep))
     res = [(r.status, r.lambda_dec.decode(), r.verified, r.factorizations) for r in out]
     d = {k: getattr(rep, k) for k, _ in BatchReport._fields_}
+    d["bits_used"] = [r.bits_used for r in out]
     d["status"] = st
     if st != 0 and all(r[0] == 0 for r in res):
         _check(st)
@@ -457,3 +474,75 @@ def mlp_adam_step(W, m, v, dW, step, lr, b1=0.9, b2=0.999, eps=1e-8, stream=None
         _f32(t, n)
     _check(lib().hk_mlp_adam_step(_ptr(W), _ptr(m), _ptr(v), _ptr(dW), n, lr, b1, b2, eps, step,
                                   _stream(stream)))
+
+
+# ---- learned precision and shift -----------------------------------------
+
+def bracket_batched(insts, lambdas, digits=41, panel=0, stream=None, ws=None):
+    """Per instance: does its own precision's factorisation bracket lambda
+    (decimal string) at `digits` significant digits?  List of bools."""
+    import torch
+    L = lib()
+    arr = _instances(insts)
+    nbytes = L.hk_batch_workspace_bytes(ctypes.cast(arr, ctypes.c_void_p), len(insts))
+    if nbytes == 0:
+        raise HKError(1, L.hk_last_error().decode())
+    ws = ws if ws is not None and ws.numel() >= nbytes else torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    decs = (ctypes.c_char_p * len(insts))(*[d.encode() for d in lambdas])
+    ok = (ctypes.c_int * len(insts))()
+    _check(L.hk_bracket_batched(ctypes.cast(arr, ctypes.c_void_p), len(insts), ctypes.cast(decs, ctypes.c_void_p),
+                                digits, panel, ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream),
+                                ctypes.cast(ok, ctypes.c_void_p)))
+    return [bool(v) for v in ok]
+
+
+def mlp_meta(in_mean, in_scale, out_mean, out_scale, bits_margin, rmse_ln_lambda):
+    m = MlpMeta()
+    for k in range(3):
+        m.in_mean[k], m.in_scale[k] = in_mean[k], in_scale[k]
+    for k in range(2):
+        m.out_mean[k], m.out_scale[k] = out_mean[k], out_scale[k]
+    m.bits_margin, m.rmse_ln_lambda = bits_margin, rmse_ln_lambda
+    return m
+
+
+def mlp_propose(W, meta, insts, stream=None):
+    """(bits_hat list, ln_sigma_hat list) from the network W (device float32)."""
+    import torch
+    n = len(insts)
+    arr = _instances([(N, beta, 0) for N, beta in insts])
+    io = torch.empty(5 * n, dtype=torch.float32, device=W.device)
+    bits = (ctypes.c_int * n)()
+    lns = (ctypes.c_double * n)()
+    _check(lib().hk_mlp_propose(_ptr(_f32(W, mlp_nparams())), ctypes.byref(meta), ctypes.cast(arr, ctypes.c_void_p),
+                                n, _ptr(io), _stream(stream), ctypes.cast(bits, ctypes.c_void_p),
+                                ctypes.cast(lns, ctypes.c_void_p)))
+    return list(bits), list(lns)
+
+
+def eig_learned(insts, bits_hat, ln_sigma_hat, digits=40, panel=0, stream=None, ws=None):
+    """lambda_1 of every (N, beta, K_plain) instance from proposed bits and
+    shifts; returns (list of result dicts, report dict)."""
+    import torch
+    L = lib()
+    n = len(insts)
+    arr = _instances(insts)
+    bits = (ctypes.c_int * n)(*[int(b) for b in bits_hat])
+    lns = (ctypes.c_double * n)(*[float(x) for x in ln_sigma_hat])
+    nbytes = L.hk_learned_workspace_bytes(ctypes.cast(arr, ctypes.c_void_p), n, ctypes.cast(bits, ctypes.c_void_p))
+    if nbytes == 0:
+        raise HKError(1, L.hk_last_error().decode())
+    ws = ws if ws is not None and ws.numel() >= nbytes else torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    out = (Result * n)()
+    rep = BatchReport()
+    st = L.hk_eig_learned(ctypes.cast(arr, ctypes.c_void_p), n, ctypes.cast(bits, ctypes.c_void_p),
+                          ctypes.cast(lns, ctypes.c_void_p), digits, panel, ctypes.c_void_p(ws.data_ptr()),
+                          ws.numel(), _stream(stream), ctypes.cast(out, ctypes.c_void_p), ctypes.byref(rep))
+    res = [{"status": r.status, "lambda_dec": r.lambda_dec.decode(), "verified": r.verified,
+            "factorizations": r.factorizations, "bits_used": r.bits_used, "solves": r.solves,
+            "path": r.path} for r in out]
+    d = {k: getattr(rep, k) for k, _ in BatchReport._fields_}
+    d["status"] = st
+    if st != 0 and all(r["status"] == 0 for r in res):
+        _check(st)
+    return res, d

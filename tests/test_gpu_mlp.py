@@ -106,10 +106,13 @@ def test_adam_step_matches_reference(hk):
     m = np.zeros(n)
     v = np.zeros(n)
     W, md, vd = _dev(theta), torch.zeros(n, device="cuda"), torch.zeros(n, device="cuda")
+    # the kernel takes float32 hyper-parameters: give the reference the same values
+    f32 = lambda x: float(np.float32(x))
+    lr, b1, b2, eps = f32(1e-2), f32(0.9), f32(0.999), f32(1e-8)
     for step in range(1, 6):
         g = rng.normal(size=n).astype(np.float32).astype(np.float64)
-        theta, m, v = mlp.adam_step(theta, m, v, g, step, lr=1e-2)
-        hk.mlp_adam_step(W, md, vd, _dev(g), step, 1e-2)
+        theta, m, v = mlp.adam_step(theta, m, v, g, step, lr=lr, b1=b1, b2=b2, eps=eps)
+        hk.mlp_adam_step(W, md, vd, _dev(g), step, lr, b1, b2, eps)
         torch.cuda.synchronize()
         np.testing.assert_allclose(md.cpu().numpy(), m, rtol=1e-5, atol=1e-7)
         np.testing.assert_allclose(vd.cpu().numpy(), v, rtol=1e-5, atol=1e-9)
