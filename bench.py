@@ -32,6 +32,30 @@ CONFIGS = {
 }
 PEAK_INT_MUL = 256 * 64 * 2.4e9       # one 32x32 multiply per lane per clock
 HBM_PEAK = 8.0e12
+HERE = os.path.dirname(os.path.abspath(__file__))
+PROFILE_TAG = {"c2": "N200_beta7-4_K2048", "c3b1": "N500_beta1_K6144"}
+
+
+def measured_traffic(cfg_name):
+    """HBM bytes per k_update launch from the committed rocprofv3 counter
+    summary of this workload, or None when there is none or the kernel
+    source has changed since the counters were taken."""
+    import hashlib
+    import re
+    tag = PROFILE_TAG.get(cfg_name)
+    if tag is None:
+        return None, None
+    path = os.path.join(HERE, "profiles", "k_update_%s_secant.txt" % tag)
+    try:
+        txt = open(path).read()
+    except OSError:
+        return None, None
+    src = open(os.path.join(HERE, "paper_0902_0852_amd", "csrc", "hk_kernels.hip"), "rb").read()
+    m = re.search(r"sha256 ([0-9a-f]{16})", txt)
+    t = re.search(r"traffic_bytes_per_launch=(\d+)", txt)
+    if not m or not t or m.group(1) != hashlib.sha256(src).hexdigest()[:16]:
+        return None, os.path.relpath(path, HERE)
+    return int(t.group(1)), os.path.relpath(path, HERE)
 
 
 def log(msg):
@@ -69,6 +93,59 @@ def cpu_baseline(cfg, method, budget_s=20.0):
             "lambda_per_s": n / dt}
 
 
+def learned_gain(args):
+    """Batched + learned form against the batched plain form on the same
+    held-out instances: lambda_1 instances per second at 1e-40 agreement."""
+    import torch
+    import paper_0902_0852_amd as hk
+    from paper_0902_0852_amd import learned
+    from fractions import Fraction
+    model = learned.load_model(args.model) if args.model else learned.load_model()
+    insts = learned.sample_instances(args.instances, args.seed, args.n_lo, args.n_hi)
+    plain = [(N, b, learned.plain_bits(N)) for N, b in insts]
+    # warm-up on a small batch of the same kind (graph capture, code load)
+    hk.eig_batched(plain[:2], digits=45)
+    learned.smallest_eig_learned(model, plain[:2])
+    torch.cuda.synchronize()
+    t0 = time.time()
+    res_p, rep_p = hk.eig_batched(plain, digits=45)
+    torch.cuda.synchronize()
+    t_plain = time.time() - t0
+    t0 = time.time()
+    res_l, rep_l, bits, lns = learned.smallest_eig_learned(model, plain)
+    torch.cuda.synchronize()
+    t_learned = time.time() - t0
+
+    def val(dec):
+        m, e = dec.split("e")
+        return Fraction(m) * Fraction(10) ** int(e)
+    agree = 0
+    for (st, dec, ver, nf), r in zip(res_p, res_l):
+        if st == 0 and r["status"] == 0:
+            a, b = val(dec), val(r["lambda_dec"])
+            agree += abs(a - b) <= Fraction(1, 10 ** 40) * abs(a)
+    n = len(insts)
+    out = {
+        "metric": "lambda_1 instances/s at 1e-40 agreement, batched + learned precision vs batched plain "
+                  "fixed precision",
+        "value": n / t_learned, "unit": "instances/s", "n_gpus": 1, "higher_is_better": True,
+        "data": "synthetic", "dtype": "int32 (method), float32 (network)",
+        "config": {"workload": "%d held-out instances, seed %d, N uniform in [%d, %d], beta = p/q, p, q in 1..8, "
+                               "beta in [1/2, 3]; plain precision 1024 + 20.48 (N - 50) bits" %
+                               (n, args.seed, args.n_lo, args.n_hi)},
+        "plain_instances_per_s": n / t_plain, "speedup": t_plain / t_learned,
+        "t_plain_s": t_plain, "t_learned_s": t_learned,
+        "accepted_learned": sum(r["path"] == 1 for r in res_l), "fallback_plain": sum(r["path"] == 0 for r in res_l),
+        "agree_1e-40": agree,
+        "mean_bits_plain": sum(k for _, _, k in plain) / n, "mean_bits_proposed": sum(bits) / n,
+        "mean_bits_used": sum(r["bits_used"] for r in res_l) / n,
+        "factorizations_plain": sum(nf for _, _, _, nf in res_p),
+        "factorizations_learned": sum(r["factorizations"] for r in res_l),
+        "solves_learned": sum(r["solves"] for r in res_l),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,11 +154,21 @@ def main():
     ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
     ap.add_argument("--method", default="secant", choices=["secant", "inverse"])
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--mode", default="plain", choices=["plain", "learned"],
+                    help="learned: batched + learned form against the batched plain form")
+    ap.add_argument("--model", default=None, help="network file (default: the package's trained one)")
+    ap.add_argument("--instances", type=int, default=32)
+    ap.add_argument("--seed", type=int, default=4242)
+    ap.add_argument("--n-lo", type=int, default=100)
+    ap.add_argument("--n-hi", type=int, default=250)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the method has no multi-GPU path in this "
               "build (one instance per GPU shards trivially; see DESIGN.md).", file=sys.stderr)
         sys.exit(2)
+    if args.mode == "learned":
+        learned_gain(args)
+        return
     import torch
     import paper_0902_0852_amd as hk
     cfg = CONFIGS[args.config]
@@ -109,6 +196,7 @@ def main():
     ms_step = 1e3 * dt / args.steps
     value = macs_per_step * args.steps / dt
     achieved = macs_per_step * args.steps / (upd_ms * 1e-3) if upd_ms > 0 else 0.0
+    traffic, traffic_src = measured_traffic(args.config)
     out = {
         "metric": "multiprecision limb-MACs/s (whole job) and % int-mul peak of the update kernel; "
                   "lambda_min solves/s at 1e-40 rel",
@@ -127,7 +215,9 @@ def main():
                      "avg_launch_us": 1e3 * upd_ms / max(upd_n, 1),
                      "limb_macs_per_launch": macs_per_step / max(upd_n // args.steps, 1),
                      "share_of_step": (upd_ms / args.steps) / ms_step,
-                     "traffic": None},
+                     "traffic": traffic, "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + "
+                                                          "WRITE_SIZE, copy-calibrated)",
+                     "traffic_source": traffic_src},
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, args.method)
