@@ -106,7 +106,9 @@ size_t hk_workspace_bytes(int N, hk_rational beta, int prec_bits, int flags);
    Gamma((n+1)/beta) (Introduction: the matrix definition), correctly rounded
    (round to nearest, ties to even), and uploads them to dev_ws.  The matrix
    itself is expanded from them at every hk_factor.  On success *out is a new
-   handle bound to dev_ws (which must stay alive until hk_matrix_destroy). */
+   handle bound to dev_ws (which must stay alive until hk_matrix_destroy).
+   Its panel width is 4, or the one hk_autotune stored for this shape in the
+   tuning cache named by the environment variable HK_TUNE_CACHE. */
 hk_status hk_build_matrix(int N, hk_rational beta, int prec_bits, void* dev_ws,
                           size_t ws_bytes, hipStream_t s, hk_matrix* out);
 

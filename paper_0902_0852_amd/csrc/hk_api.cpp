@@ -120,6 +120,8 @@ bool make_plan(int N, int64_t bnum, int64_t bden, int K, Plan& P, std::string& e
   P.o_dv1 = take(sizeof(int32_t) * (size_t)N * P.VW);
   P.o_dv2 = take(sizeof(int32_t) * (size_t)N * P.VW);
   P.o_md = take(sizeof(uint32_t) * (size_t)(P.VW + 4));
+  P.o_mdinfo = take(sizeof(int32_t) * 4);
+  P.o_dots = take(sizeof(int64_t) * 4 * (size_t)(2 * P.VW + 8));
   P.o_desc = take(sizeof(InstDesc));
   P.total = o;
   return true;
@@ -156,6 +158,8 @@ DevPtrs dev_ptrs(const Plan& P, char* ws) {
   D.dv1 = (int32_t*)(ws + P.o_dv1);
   D.dv2 = (int32_t*)(ws + P.o_dv2);
   D.md = (uint32_t*)(ws + P.o_md);
+  D.mdinfo = (int32_t*)(ws + P.o_mdinfo);
+  D.dots = (int64_t*)(ws + P.o_dots);
   D.desc = (InstDesc*)(ws + P.o_desc);
   return D;
 }
@@ -274,7 +278,14 @@ size_t hk_workspace_bytes(int N, hk_rational beta, int prec_bits, int flags) {
 
 hk_status hk_build_matrix(int N, hk_rational beta, int prec_bits, void* dev_ws, size_t ws_bytes,
                           hipStream_t s, hk_matrix* out) {
-  return hk::build_matrix_impl(N, beta, prec_bits, dev_ws, ws_bytes, s, out, nullptr);
+  const hk_status st = hk::build_matrix_impl(N, beta, prec_bits, dev_ws, ws_bytes, s, out, nullptr);
+  if (st == HK_OK) {
+    // a panel width tuned for this shape (hk_autotune, cache named by HK_TUNE_CACHE)
+    const hk_instance one = {N, beta, prec_bits};
+    const int p = hk::tuned_panel(&one, 1);
+    if (p > 0) (*out)->panel = p;
+  }
+  return st;
 }
 
 }  // extern "C"
@@ -336,6 +347,9 @@ extern "C" {
 hk_status hk_matrix_destroy(hk_matrix m) {
   if (!m) return HK_OK;
   for (auto& e : m->ev) (void)hipEventDestroy(e);
+  if (m->gexec) (void)hipGraphExecDestroy(m->gexec);
+  if (m->graph) (void)hipGraphDestroy(m->graph);
+  if (m->gcap) (void)hipStreamDestroy(m->gcap);
   delete m;
   return HK_OK;
 }
@@ -389,14 +403,37 @@ hk_status hk_factor(hk_matrix m, hk_mpf shift, int inertia_mode, hipStream_t s, 
   m->xs_host.assign(P.WX, 0);
   if (!to_digits(xf, m->xs_host.data(), P.WX)) return fail(HK_EINVAL, "shift too wide");
   HK_HIP(hipMemcpyAsync(D.xs, m->xs_host.data(), sizeof(int32_t) * P.WX, hipMemcpyHostToDevice, s));
-  HK_HIP(launch_fill32(D.flags, 16, 0, s));
-  HK_HIP(launch_fill32(D.flags + 1, 1, INT_MAX, s));
   const int N = P.N, b = m->panel;
   m->n_update = 0;
   m->update_ms = 0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> evs;
-  size_t evi = 0;
-  HK_HIP(enqueue_factor(m->B, b, s, m->timing ? &evs : nullptr, &m->ev, &evi, &m->n_update));
+  if (m->timing) {
+    size_t evi = 0;
+    HK_HIP(launch_fill32(D.flags, 16, 0, s));
+    HK_HIP(launch_fill32(D.flags + 1, 1, INT_MAX, s));
+    HK_HIP(enqueue_factor(m->B, b, s, &evs, &m->ev, &evi, &m->n_update));
+  } else {
+    if (!m->gexec || m->gpanel != b) {
+      if (m->gexec) { (void)hipGraphExecDestroy(m->gexec); m->gexec = nullptr; }
+      if (m->graph) { (void)hipGraphDestroy(m->graph); m->graph = nullptr; }
+      if (!m->gcap) HK_HIP(hipStreamCreateWithFlags(&m->gcap, hipStreamNonBlocking));
+      HK_HIP(hipStreamBeginCapture(m->gcap, hipStreamCaptureModeThreadLocal));
+      int nu = 0;
+      hipError_t e = launch_fill32(D.flags, 16, 0, m->gcap);
+      if (e == hipSuccess) e = launch_fill32(D.flags + 1, 1, INT_MAX, m->gcap);
+      if (e == hipSuccess) e = enqueue_factor(m->B, b, m->gcap, nullptr, nullptr, nullptr, &nu);
+      hipGraph_t g = nullptr;
+      const hipError_t e2 = hipStreamEndCapture(m->gcap, &g);
+      m->graph = g;
+      if (e == hipSuccess) e = e2;
+      if (e == hipSuccess) e = hipGraphInstantiate(&m->gexec, m->graph, nullptr, nullptr, 0);
+      if (e != hipSuccess) return fail(HK_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+      m->gpanel = b;
+      m->g_nupdate = nu;
+    }
+    HK_HIP(hipGraphLaunch(m->gexec, s));
+    m->n_update = m->g_nupdate;
+  }
   HK_HIP(hipMemcpyAsync(m->flags_host, D.flags, sizeof(int32_t) * 16, hipMemcpyDeviceToHost, s));
   HK_HIP(hipStreamSynchronize(s));
   for (auto& pr : evs) {

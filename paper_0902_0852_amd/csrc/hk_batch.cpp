@@ -54,6 +54,7 @@ static bool batch_layout(const hk_instance* inst, int count, std::vector<size_t>
   o = al256(o + sizeof(InstDesc) * count);
   o = al256(o + sizeof(int32_t) * 16 * count);
   o = al256(o + sizeof(int32_t) * (size_t)count * maxN * ld);
+  o = al256(o + sizeof(SweepArgs) * count);
   off.resize(count);
   for (int i = 0; i < count; i++) { off[i] = o; o = al256(o + sz[i]); }
   total = o;
@@ -77,6 +78,7 @@ hk_status build_batch(Batch& bt, const hk_instance* inst, int count, void* ws, s
   bt.ddesc = (InstDesc*)base;
   bt.flags = (int32_t*)(base + al256(sizeof(InstDesc) * count));
   bt.piv = (int32_t*)((char*)bt.flags + al256(sizeof(int32_t) * 16 * count));
+  bt.sargs = (SweepArgs*)((char*)bt.piv + al256(sizeof(int32_t) * (size_t)count * bt.maxN * bt.ld));
   // moments of all instances in parallel host threads
   std::vector<std::vector<MP>> X(count);
   std::vector<int> ok(count, 0);

@@ -16,6 +16,7 @@ struct Batch {
   InstDesc* ddesc = nullptr;
   int32_t* flags = nullptr;
   int32_t* piv = nullptr;
+  SweepArgs* sargs = nullptr;   // per-instance solve arguments (batched inverse iteration)
   BatchView B;
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
@@ -40,8 +41,6 @@ hk_status factor_batch(Batch& bt, const std::vector<MP>& x, const std::vector<in
                        std::vector<BEval>& out, bool want_pivots);
 // bytes of the batch layout (0 and g_err set if an instance is invalid)
 size_t batch_bytes(const hk_instance* inst, int count);
-// panel width from the tuning cache (HK_TUNE_CACHE) for this batch shape, else 0
-int tuned_panel(const hk_instance* inst, int count);
 
 // shared with the single-instance drivers (hk_drivers.cpp)
 void decimal_bracket(const MP& lam, int K, int digits, MP& xlo, MP& xhi, std::string& dec);
@@ -50,6 +49,13 @@ MP decimal_to_fixed(const MP& D, int64_t e, int K, bool ceil_mode);
 std::string decimal_string(const MP& lam, int K, int digits);
 // |a - b| <= 10^-tol |b| for values with the same number of fractional bits
 bool agree(const MP& a, const MP& b, int tol);
+// Inverse iteration of every active instance of bt on its current
+// factorisation (taken at sigma[i], K_i fractional bits), all instances
+// stepped together (hk_binverse.cpp); lam[i] gets K_i fractional bits,
+// st[i] the instance's outcome, iters[i] its solves.
+hk_status batch_inverse(Batch& bt, const std::vector<MP>& sigma, const std::vector<int>& act, int tol,
+                        int max_iter, hipStream_t s, std::vector<MP>& lam, std::vector<hk_status>& st,
+                        std::vector<int>& iters, double& t_solve);
 // inverse iteration on the current factorisation of m, which was taken at
 // shift sigma (K fractional bits); lam gets K fractional bits
 hk_status inverse_iterate(hk_matrix m, hipStream_t s, const MP& sigma, int tol, int max_iter, MP& lam,

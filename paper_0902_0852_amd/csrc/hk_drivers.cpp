@@ -525,7 +525,9 @@ hk_status hk_solve(hk_matrix m, const void* dev_rhs, void* dev_x, hipStream_t s)
   hipError_t e = launch_fill32(D.flags, 16, 0, s);
   // forward: acc = b 2^(h+g); z_k = RNE(acc_k / 2^h) column by column
   if (e == hipSuccess) e = launch_vinit(P, D, (const int32_t*)dev_rhs, h + m->gbits, s);
-  static const bool stepwise = getenv("HK_SOLVE_STEPWISE") != nullptr;
+  // one launch per column step across the chip (default: lowest latency for
+  // one instance), or one single-workgroup launch per sweep (HK_SOLVE_FUSED)
+  static const bool stepwise = getenv("HK_SOLVE_FUSED") == nullptr;
   if (!stepwise) {
     // one launch per sweep
     if (e == hipSuccess) e = launch_vsweep(P, D, 0, b, nullptr, s);

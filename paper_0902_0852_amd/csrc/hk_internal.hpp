@@ -56,11 +56,13 @@ struct Plan {
   // byte offsets in the workspace
   size_t o_cols, o_items, o_A, o_K, o_C, o_L, o_S, o_D, o_dinfo, o_nC, o_nCs, o_nL,
       o_X, o_xs, o_flags, o_b32C, o_b32L, o_vec, o_LT, o_acc, o_kca, o_ub, o_us, o_wb, o_nU,
-      o_nUs, o_dv1, o_dv2, o_md, o_desc, total;
+      o_nUs, o_dv1, o_dv2, o_md, o_mdinfo, o_dots, o_desc, total;
   int64_t ntri;
 };
 
 bool make_plan(int N, int64_t bnum, int64_t bden, int K, Plan& P, std::string& err);
+// panel width from the tuning cache (HK_TUNE_CACHE) for this batch shape, else 0
+int tuned_panel(const hk_instance* inst, int count);
 
 bool reduce_beta(int64_t num, int64_t den, uint32_t* p, uint32_t* q);
 double log2_mu(int n, uint32_t p, uint32_t q);
@@ -86,6 +88,7 @@ struct DevPtrs {
   int32_t* b32C; int32_t* b32L; int32_t* vec;
   int32_t* LT; int32_t* acc; int64_t* kca; int32_t* ub; uint32_t* us; int32_t* wb;
   int32_t* nU; int32_t* nUs; int32_t* dv1; int32_t* dv2; uint32_t* md;
+  int32_t* mdinfo; int64_t* dots;
   InstDesc* desc;
 };
 DevPtrs dev_ptrs(const Plan& P, char* ws);
@@ -133,6 +136,35 @@ hipError_t launch_vfinalize(const Plan& P, const DevPtrs& D, int k, int rd, int3
 hipError_t launch_vdivide(const Plan& P, const DevPtrs& D, hipStream_t s);
 // the whole forward (bwd = 0) or backward (bwd = 1) sweep of a solve in one launch
 hipError_t launch_vsweep(const Plan& P, const DevPtrs& D, int bwd, int panel, int32_t* out, hipStream_t s);
+
+// Everything the solve and inverse-iteration kernels need of one instance;
+// the batched launches take a device array of these (one per instance).
+struct SweepArgs {
+  const ColInfo* cols;
+  int N, Npad, VA, nbA, VW, LWT, h, bwd, panel, gbits, K, pad;
+  int32_t* acc; int64_t* kc; int32_t* ub; uint32_t* us; int32_t* nU; int32_t* nUs;
+  const int32_t* L; const int32_t* LT; const int32_t* nL; int32_t* out; int32_t* flags;
+  int32_t* v; int32_t* y; int32_t* wb; const uint32_t* Dd; const int32_t* dinfo;
+  int64_t* dots; uint32_t* md; int32_t* mdinfo;
+};
+SweepArgs make_sweep_args(const Plan& P, const DevPtrs& D, int panel, int gbits);
+// launch shapes of a batch (maxima over its instances)
+struct SweepShape { int count = 0, maxN = 0, maxVA = 0, maxVW = 0; int64_t maxVAN = 0;
+                    size_t shm_div = 0, shm_scale = 0; };
+SweepShape sweep_shape(const std::vector<const Plan*>& plans);
+// Batched inverse-iteration steps (hk_kernels.hip):
+//   vinit_b  stage 0: acc = v 2^(h+g); stage 1: acc = w 2^h
+//   vsweep_b forward (bwd 0) or backward (bwd 1, y rows out) sweep, one workgroup per instance
+//   vdivide_b w = RNE(z 2^h / d) per row
+//   vdots_b  exact <v, y> and <v, v> as lazy int64 digits (dots)
+//   vmax_b   the row of largest |y|: its magnitude normalised (md, mdinfo = nd, sh, row)
+//   vscale_b v = RNE(y 2^K / max|y|)
+hipError_t launch_vinit_b(const SweepArgs* args, const SweepShape& sh, int stage, hipStream_t s);
+hipError_t launch_vsweep_b(const SweepArgs* args, const SweepShape& sh, int bwd, hipStream_t s);
+hipError_t launch_vdivide_b(const SweepArgs* args, const SweepShape& sh, hipStream_t s);
+hipError_t launch_vdots_b(const SweepArgs* args, const SweepShape& sh, hipStream_t s);
+hipError_t launch_vmax_b(const SweepArgs* args, const SweepShape& sh, hipStream_t s);
+hipError_t launch_vscale_b(const SweepArgs* args, const SweepShape& sh, hipStream_t s);
 hipError_t launch_vscale(const Plan& P, const DevPtrs& D, const uint32_t* md, int nd, int sh,
                          int32_t* out, hipStream_t s);
 
@@ -155,5 +187,11 @@ struct hk_matrix_s {
   hk::InstDesc desc_host;
   hk::BatchView B;          // this matrix as a batch of one
   std::vector<hipEvent_t> ev;
+  // the launch sequence of one factorisation, captured once per panel width
+  // and replayed by hk_factor when per-launch timing is off
+  hipStream_t gcap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int gpanel = 0, g_nupdate = 0;
 };
 

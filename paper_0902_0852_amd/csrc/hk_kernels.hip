@@ -15,6 +15,8 @@
 // each item normalises its 16 digits and hands its carry to block q+1
 // through a double-buffered int64 carry plane (read buffer rd, write rd^1),
 // so no atomics and no cross-item ordering are needed.
+#include <cstring>
+
 #include "hk_internal.hpp"
 
 namespace hk {
@@ -36,6 +38,26 @@ __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlan
 // wavefront-uniform operand digits are read through the constant address
 // space so that they arrive by scalar loads into SGPRs
 typedef const __attribute__((address_space(4))) int32_t cint32_t;
+
+// a pointer every lane holds the same value of, moved into SGPRs
+template <typename T>
+__device__ __forceinline__ T* uptr(T* p) {
+  const uint64_t v = (uint64_t)p;
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+  return (T*)(((uint64_t)hi << 32) | lo);
+}
+// a read-only object at a wavefront-uniform address, by scalar loads
+template <typename T>
+__device__ __forceinline__ T sload(const T* p) {
+  static_assert(sizeof(T) % 4 == 0, "whole words");
+  typedef const __attribute__((address_space(4))) uint32_t cword;
+  const cword* q = (const cword*)uptr(p);
+  union { T t; uint32_t w[sizeof(T) / 4]; } u;
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); i++) u.w[i] = q[i];
+  return u.t;
+}
 
 __global__ void k_fill32(int32_t* __restrict__ p, int64_t n, int32_t v) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
@@ -191,23 +213,26 @@ __global__ void __launch_bounds__(256) k_update(const InstDesc* __restrict__ des
   int inst = -1, k0 = 0, k1 = 0, c_lo = 0, c_hi = 0;
   for (int i = 0; i < count; i++) {
     int a0, a1, b0, b1;
-    if (!update_range(desc[i].N, pc, b, j, a0, a1, b0, b1)) continue;
-    const int n = desc[i].itemStart[b1] - desc[i].itemStart[b0];
+    const int Ni = sload(&desc[i].N);
+    if (!update_range(Ni, pc, b, j, a0, a1, b0, b1)) continue;
+    const int32_t* is = sload(&desc[i].itemStart);
+    const int n = sload(is + b1) - sload(is + b0);
     if (it < n) { inst = i; k0 = a0; k1 = a1; c_lo = b0; c_hi = b1; break; }
     it -= n;
   }
+  inst = uni(inst);
   if (inst < 0) return;
-  const InstDesc I = desc[inst];
+  const InstDesc I = sload(desc + inst);
   if (!I.active) return;
   const int N = I.N;
-  it += I.itemStart[c_lo];
+  it += sload(I.itemStart + c_lo);
   int lo = c_lo, hi = c_hi - 1;
   while (lo < hi) {
     int mid = (lo + hi + 1) >> 1;
-    if (I.itemStart[mid] <= it) lo = mid; else hi = mid - 1;
+    if (sload(I.itemStart + mid) <= it) lo = mid; else hi = mid - 1;
   }
   const int c = uni(lo);
-  const ColInfo cc = I.cols[c];
+  const ColInfo cc = sload(I.cols + c);
   const int rem = it - I.itemStart[c];
   const int T = cc.R >> 6;
   const int q = uni(rem / T);
@@ -221,11 +246,11 @@ __global__ void __launch_bounds__(256) k_update(const InstDesc* __restrict__ des
   for (int m = 0; m <= WB; m++) acc[m] = 0;
   int cnt = 0;
   for (int k = k0; k < k1; k++) {
-    const ColInfo kk = I.cols[k];
-    const int nC = min(uni(I.nC[tri_index(N, k, c)]), kk.CW - WB);
+    const ColInfo kk = sload(I.cols + k);
+    const int nC = min(sload(I.nC + tri_index(N, k, c)), kk.CW - WB);
     const int nLl = active ? I.nL[tri_index(N, k, rr)] : 0;
     const int nL = min(uni(wave_max(nLl)), kk.LW - 2 * WB);
-    accum_block(acc, cnt, I.C + kk.coff + (int64_t)(c - k) * kk.CW, nC, I.L + kk.loff,
+    accum_block(acc, cnt, uptr(I.C + kk.coff + (int64_t)(c - k) * kk.CW), nC, uptr(I.L + kk.loff),
                 (int64_t)kk.LW * kk.R * 4, rr - k, kk.R, nL, q);
   }
   if (!active) return;
@@ -525,6 +550,7 @@ __device__ int divide_entry(int64_t* smem, const uint32_t* Sr, int ns, int negN,
   int t = jmax + nd;
   int64_t w0 = t - 2 >= 0 ? rem[t - 2] : 0, w1 = rem[t - 1], w2 = rem[t], w3 = rem[t + 1];
   int since = 0;
+  const double invD = R / D3;   // quotient estimates by one multiply
   for (int j = jmax; j >= 0; j--) {
     t = j + nd;
     w2 += w3 << DB;
@@ -536,12 +562,14 @@ __device__ int divide_entry(int64_t* smem, const uint32_t* Sr, int ns, int negN,
     w1 -= cy << DB;
     w2 += cy;
     const double T = (double)w2 * R * R + (double)w1 * R + (double)w0;
-    const int64_t qq = (int64_t)rint(T * R / D3);
+    const int64_t qq = (int64_t)rint(T * invD);
     if (lane == 0) qd[j] = qq;
     w1 -= qq * d1;
     w0 -= qq * d2;
+    // |qq| < 2^30 and divisor digits < 2^29: one 32 x 32 -> 64 multiply each
+    const int32_t q32 = (int32_t)qq;
     if (qq != 0)
-      for (int i = lane; i < nd - 2; i += 64) rem[j + i] -= qq * dd[i];
+      for (int i = lane; i < nd - 2; i += 64) rem[j + i] -= (int64_t)q32 * (int64_t)(int32_t)dd[i];
     __syncthreads();
     if (j == 0) break;
     if (++since == 12) {
@@ -817,13 +845,6 @@ __global__ void __launch_bounds__(64) k_vfinalize(int k, int rd, int h, const in
 // carry parities and arithmetic as the per-step launches (k_vupdate,
 // k_vfinalize), the stages separated by workgroup barriers.  Wavefront 0
 // finalises u_k while the others wait; every wavefront takes update items.
-struct SweepArgs {
-  const ColInfo* cols;
-  int N, Npad, VA, nbA, VW, LWT, h, bwd, panel;
-  int32_t* acc; int64_t* kc; int32_t* ub; uint32_t* us; int32_t* nU; int32_t* nUs;
-  const int32_t* L; const int32_t* LT; const int32_t* nL; int32_t* out; int32_t* flags;
-};
-
 __device__ void sweep_finalize(const SweepArgs& a, int k, int rd, int64_t* smem) {
   int32_t* dg = (int32_t*)smem;
   int32_t* ob = dg + (a.VA + 48);
@@ -851,8 +872,7 @@ __device__ __forceinline__ void sweep_update(const SweepArgs& a, int k0, int k1,
                  a.L, a.LT, a.nL, a.LWT, a.flags);
 }
 
-__global__ void __launch_bounds__(512) k_vsweep(SweepArgs a) {
-  extern __shared__ int64_t smem[];
+__device__ void sweep_body(const SweepArgs& a, int64_t* smem) {
   const int wave = uni(threadIdx.x >> 6);
   const int N = a.N, b = a.panel;
   int P = 0;
@@ -891,6 +911,176 @@ __global__ void __launch_bounds__(512) k_vsweep(SweepArgs a) {
       }
     }
   }
+}
+
+__global__ void __launch_bounds__(512) k_vsweep(SweepArgs a) {
+  extern __shared__ int64_t smem[];
+  sweep_body(a, smem);
+}
+
+// ---------------------------------------------- batched inverse iteration
+// One SweepArgs per instance; blockIdx.y (or blockIdx.x for one-workgroup
+// kernels) selects the instance.
+
+__global__ void __launch_bounds__(512) k_vsweep_b(const SweepArgs* __restrict__ args, int bwd) {
+  extern __shared__ int64_t smem[];
+  SweepArgs a = args[blockIdx.x];
+  a.bwd = bwd;
+  a.out = bwd ? a.y : nullptr;
+  sweep_body(a, smem);
+}
+
+__global__ void __launch_bounds__(256) k_vinit_b(const SweepArgs* __restrict__ args, int stage) {
+  const SweepArgs& a = args[blockIdx.y];
+  const int32_t* src = stage == 0 ? a.v : a.wb;
+  const int Sbits = stage == 0 ? a.h + a.gbits : a.h;
+  const int Sq = Sbits / DB, Sb = Sbits % DB;
+  const int64_t n = (int64_t)a.VA * a.Npad;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int s = (int)(idx / a.Npad), i = (int)(idx - (int64_t)s * a.Npad);
+    int64_t v = 0;
+    if (i < a.N) {
+      const int j = s - Sq;
+      if (j >= 0 && j < a.VW) v += (((int64_t)src[(int64_t)i * a.VW + j]) << Sb) & (RADIX - 1);
+      if (j - 1 >= 0 && j - 1 < a.VW) v += (((int64_t)src[(int64_t)i * a.VW + j - 1]) << Sb) >> DB;
+    }
+    a.acc[idx] = (int32_t)v;
+  }
+  const int64_t nk = (int64_t)2 * a.nbA * a.Npad;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < nk;
+       idx += (int64_t)gridDim.x * blockDim.x)
+    a.kc[idx] = 0;
+}
+
+__global__ void __launch_bounds__(64) k_vdivide_b(const SweepArgs* __restrict__ args) {
+  extern __shared__ int64_t smem[];
+  const SweepArgs& a = args[blockIdx.y];
+  const int k = blockIdx.x;
+  if (k >= a.N) return;
+  const int nsg = a.nUs[k];
+  divide_entry(smem, a.us + (int64_t)k * a.VW, nsg < 0 ? -nsg : nsg, nsg < 0, a.Dd + a.cols[k].doff,
+                   a.dinfo[4 * k], a.dinfo[4 * k + 1], a.dinfo[4 * k + 2], a.h, a.wb + (int64_t)k * a.VW, 1,
+                   a.VW, nullptr, 0, a.flags);
+}
+
+// <v, y> (which = 0) and <v, v> (which = 1) exactly: thread t owns output
+// digit positions p = t, t + 256, ... and sums v_i[a] y_i[p - a] over rows i
+// and digits a in int64, moving everything above 29 bits into a second
+// accumulator every 64 products.  Rows are staged in LDS (v_i broadcast,
+// y_i read at consecutive addresses).  Written as two lazy int64 digit rows,
+// dots[which][0][p] (low parts, position p) and dots[which][1][p] (high
+// parts of position p - 1): value = sum over both rows of d_p 2^(29 p).
+// LDS: 2 VW int32.
+__global__ void __launch_bounds__(256) k_vdots_b(const SweepArgs* __restrict__ args) {
+  extern __shared__ int64_t smem[];
+  const SweepArgs& a = args[blockIdx.x];
+  const int which = blockIdx.y;
+  const int32_t* V = a.v;
+  const int32_t* Y = which == 0 ? a.y : a.v;
+  const int VW = a.VW, np = VW + 4;     // 2 np = 2 VW + 8 entries per row
+  int64_t* lo_row = a.dots + (int64_t)which * 2 * (2 * np);
+  int64_t* hi_row = lo_row + 2 * np;
+  int32_t* vs = (int32_t*)smem;
+  int32_t* ys = vs + VW;
+  constexpr int PT = 4;                  // output positions per thread and pass
+  for (int p = threadIdx.x; p < 2 * np; p += blockDim.x) {
+    if (p >= 2 * VW) lo_row[p] = 0;
+    if (p == 0 || p > 2 * VW) hi_row[p] = 0;
+  }
+  for (int base = 0; base < 2 * VW; base += PT * 256) {
+    int64_t lo[PT], hi[PT];
+    int cnt[PT];
+#pragma unroll
+    for (int u = 0; u < PT; u++) { lo[u] = 0; hi[u] = 0; cnt[u] = 0; }
+    for (int i = 0; i < a.N; i++) {
+      __syncthreads();
+      for (int d = threadIdx.x; d < VW; d += blockDim.x) {
+        vs[d] = V[(int64_t)i * VW + d];
+        ys[d] = Y[(int64_t)i * VW + d];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < PT; u++) {
+        const int p = base + threadIdx.x + 256 * u;
+        if (p < 2 * VW) {
+          const int a_lo = max(0, p - VW + 1), a_hi = min(p, VW - 1);
+          for (int d = a_lo; d <= a_hi; d++) {
+            lo[u] += (int64_t)vs[d] * (int64_t)ys[p - d];
+            if (++cnt[u] == 64) {
+              cnt[u] = 0;
+              hi[u] += lo[u] >> DB;
+              lo[u] &= RADIX - 1;
+            }
+          }
+        }
+      }
+    }
+    // lo belongs to position p, hi to position p + 1
+#pragma unroll
+    for (int u = 0; u < PT; u++) {
+      const int p = base + threadIdx.x + 256 * u;
+      if (p < 2 * VW) {
+        lo_row[p] = lo[u];
+        hi_row[p + 1] = hi[u];
+      }
+    }
+  }
+}
+
+// the row of largest |y| (standard magnitude digits us, signed counts nUs):
+// per lane the best of its rows, then a tournament over the wavefront;
+// its magnitude shifted so that the top digit has bit 28 set goes to md, and
+// mdinfo = {digits, shift, row}
+__device__ __forceinline__ int cmp_mag_rows(const uint32_t* us, const int32_t* nUs, int VW, int i, int j) {
+  const int ni = abs(nUs[i]), nj = abs(nUs[j]);
+  if (ni != nj) return ni > nj ? 1 : -1;
+  for (int d = ni - 1; d >= 0; d--) {
+    const uint32_t x = us[(int64_t)i * VW + d], y = us[(int64_t)j * VW + d];
+    if (x != y) return x > y ? 1 : -1;
+  }
+  return 0;
+}
+
+__global__ void __launch_bounds__(64) k_vmax_b(const SweepArgs* __restrict__ args) {
+  const SweepArgs& a = args[blockIdx.x];
+  const int lane = threadIdx.x;
+  int best = -1;
+  for (int i = lane; i < a.N; i += 64)
+    if (best < 0 || cmp_mag_rows(a.us, a.nUs, a.VW, i, best) > 0) best = i;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int other = __shfl_xor(best, o, 64);
+    if (other >= 0 && (best < 0 || cmp_mag_rows(a.us, a.nUs, a.VW, other, best) > 0 ||
+                       (cmp_mag_rows(a.us, a.nUs, a.VW, other, best) == 0 && other < best)))
+      best = other;
+  }
+  if (lane != 0) return;
+  const int nstd = best >= 0 ? abs(a.nUs[best]) : 0;
+  if (nstd == 0) {
+    a.mdinfo[0] = 0; a.mdinfo[1] = 0; a.mdinfo[2] = best;
+    return;
+  }
+  const uint32_t* row = a.us + (int64_t)best * a.VW;
+  const int sh = 28 - (31 - __clz(row[nstd - 1]));
+  uint32_t carry = 0;
+  for (int d = 0; d < nstd; d++) {
+    const uint64_t x = ((uint64_t)row[d] << sh) | carry;
+    a.md[d] = (uint32_t)(x & (RADIX - 1));
+    carry = (uint32_t)(x >> DB);
+  }
+  a.mdinfo[0] = nstd;
+  a.mdinfo[1] = sh;
+  a.mdinfo[2] = best;
+}
+
+__global__ void __launch_bounds__(64) k_vscale_b(const SweepArgs* __restrict__ args) {
+  extern __shared__ int64_t smem[];
+  const SweepArgs& a = args[blockIdx.y];
+  const int i = blockIdx.x;
+  if (i >= a.N) return;
+  const int nsg = a.nUs[i];
+  divide_entry(smem, a.us + (int64_t)i * a.VW, nsg < 0 ? -nsg : nsg, nsg < 0, a.md, a.mdinfo[0],
+                   a.mdinfo[1], 0, a.K, a.v + (int64_t)i * a.VW, 1, a.VW, nullptr, 0, a.flags);
 }
 
 // w_k = RNE(z_k 2^h / d_k) for every k (one 64-lane workgroup each)
@@ -1048,24 +1238,71 @@ hipError_t launch_vfinalize(const Plan& P, const DevPtrs& D, int k, int rd, int3
                      P.VA / WB, D.ub, D.us, D.nU, D.nUs, P.VW, out, D.flags);
   return hipGetLastError();
 }
-hipError_t launch_vsweep(const Plan& P, const DevPtrs& D, int bwd, int panel, int32_t* out, hipStream_t s) {
+SweepArgs make_sweep_args(const Plan& P, const DevPtrs& D, int panel, int gbits) {
   SweepArgs a;
+  memset(&a, 0, sizeof a);
   a.cols = D.cols; a.N = P.N; a.Npad = P.Npad; a.VA = P.VA; a.nbA = P.VA / WB; a.VW = P.VW; a.LWT = P.LWT;
-  a.h = P.h; a.bwd = bwd; a.panel = panel < 1 ? 1 : panel;
+  a.h = P.h; a.bwd = 0; a.panel = panel < 1 ? 1 : panel; a.gbits = gbits; a.K = P.K;
   a.acc = D.acc; a.kc = D.kca; a.ub = D.ub; a.us = D.us; a.nU = D.nU; a.nUs = D.nUs;
-  a.L = D.L; a.LT = D.LT; a.nL = D.nL; a.out = out; a.flags = D.flags;
+  a.L = D.L; a.LT = D.LT; a.nL = D.nL; a.out = nullptr; a.flags = D.flags;
+  a.v = D.dv1; a.y = D.dv2; a.wb = D.wb; a.Dd = D.D; a.dinfo = D.dinfo;
+  a.dots = D.dots; a.md = D.md; a.mdinfo = D.mdinfo;
+  return a;
+}
+hipError_t launch_vsweep(const Plan& P, const DevPtrs& D, int bwd, int panel, int32_t* out, hipStream_t s) {
+  SweepArgs a = make_sweep_args(P, D, panel, 0);
+  a.bwd = bwd;
+  a.out = out;
   hipLaunchKernelGGL(k_vsweep, dim3(1), dim3(512), fin_shm(P.VA), s, a);
   return hipGetLastError();
 }
+SweepShape sweep_shape(const std::vector<const Plan*>& plans) {
+  SweepShape sh;
+  sh.count = (int)plans.size();
+  for (const Plan* p : plans) {
+    sh.maxN = std::max(sh.maxN, p->N);
+    sh.maxVA = std::max(sh.maxVA, p->VA);
+    sh.maxVW = std::max(sh.maxVW, p->VW);
+    sh.maxVAN = std::max(sh.maxVAN, (int64_t)p->VA * p->Npad);
+    sh.shm_div = std::max(sh.shm_div, divide_shm(p->h, p->VW, p->maxW + 2));
+    sh.shm_scale = std::max(sh.shm_scale, divide_shm(p->K, p->VW, p->VW + 2));
+  }
+  return sh;
+}
+hipError_t launch_vinit_b(const SweepArgs* args, const SweepShape& sh, int stage, hipStream_t s) {
+  const unsigned bx = (unsigned)std::min<int64_t>(blocks_for(sh.maxVAN, 256), 1024);
+  hipLaunchKernelGGL(k_vinit_b, dim3(bx, sh.count), dim3(256), 0, s, args, stage);
+  return hipGetLastError();
+}
+hipError_t launch_vsweep_b(const SweepArgs* args, const SweepShape& sh, int bwd, hipStream_t s) {
+  hipLaunchKernelGGL(k_vsweep_b, dim3(sh.count), dim3(512), fin_shm(sh.maxVA), s, args, bwd);
+  return hipGetLastError();
+}
+hipError_t launch_vdivide_b(const SweepArgs* args, const SweepShape& sh, hipStream_t s) {
+  hipLaunchKernelGGL(k_vdivide_b, dim3(sh.maxN, sh.count), dim3(64), sh.shm_div, s, args);
+  return hipGetLastError();
+}
+hipError_t launch_vdots_b(const SweepArgs* args, const SweepShape& sh, hipStream_t s) {
+  hipLaunchKernelGGL(k_vdots_b, dim3(sh.count, 2), dim3(256), sizeof(int32_t) * 2 * sh.maxVW, s, args);
+  return hipGetLastError();
+}
+hipError_t launch_vmax_b(const SweepArgs* args, const SweepShape& sh, hipStream_t s) {
+  hipLaunchKernelGGL(k_vmax_b, dim3(sh.count), dim3(64), 0, s, args);
+  return hipGetLastError();
+}
+hipError_t launch_vscale_b(const SweepArgs* args, const SweepShape& sh, hipStream_t s) {
+  hipLaunchKernelGGL(k_vscale_b, dim3(sh.maxN, sh.count), dim3(64), sh.shm_scale, s, args);
+  return hipGetLastError();
+}
 hipError_t launch_vdivide(const Plan& P, const DevPtrs& D, hipStream_t s) {
-  hipLaunchKernelGGL(k_vdivide, dim3(P.N), dim3(64), divide_shm(P.h, P.VW, P.maxW + 2), s, D.cols,
-                     P.h, D.us, D.nUs, D.D, D.dinfo, P.VW, D.wb, D.flags);
+  hipLaunchKernelGGL(k_vdivide, dim3(P.N), dim3(64), divide_shm(P.h, P.VW, P.maxW + 2), s, D.cols, P.h, D.us,
+                     D.nUs, D.D, D.dinfo, P.VW, D.wb, D.flags);
   return hipGetLastError();
 }
 hipError_t launch_vscale(const Plan& P, const DevPtrs& D, const uint32_t* md, int nd, int sh,
                          int32_t* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_vscale, dim3(P.N), dim3(64), divide_shm(P.K, P.VW, nd + 2), s, P.K, D.us,
-                     D.nUs, P.VW, md, nd, sh, out, D.flags);
+  hipLaunchKernelGGL(k_vscale, dim3(P.N), dim3(64), divide_shm(P.K, P.VW, nd + 2), s, P.K, D.us, D.nUs, P.VW,
+                     md, nd, sh, out, D.flags);
   return hipGetLastError();
 }
 hipError_t launch_bits(const Plan& P, const DevPtrs& D, hipStream_t s) {

@@ -102,12 +102,23 @@ hk_status run_entries(std::vector<Entry>& E, const hk_instance* inst, int digits
     if (!again) break;
   }
   graph_launches += bt.graph_launches;
-  // factor_batch left each factor in place, marked factored when it succeeded
+  // factor_batch left each factor in place; inverse iteration on all of them
+  std::vector<int> ok(n, 0);
   for (int j = 0; j < n; j++) {
     E[j].sigma = x[j];
-    if (E[j].st != HK_OK) continue;
-    double ts = 0;
-    E[j].st = inverse_iterate(bt.mats[j], s, x[j], digits + 1, 80, E[j].lam, E[j].solves, ts);
+    ok[j] = E[j].st == HK_OK;
+  }
+  std::vector<MP> lam;
+  std::vector<hk_status> ist;
+  std::vector<int> iters;
+  double ts = 0;
+  st = batch_inverse(bt, x, ok, digits + 1, 80, s, lam, ist, iters, ts);
+  if (st != HK_OK) return st;
+  for (int j = 0; j < n; j++) {
+    if (!ok[j]) continue;
+    E[j].st = ist[j];
+    E[j].lam = lam[j];
+    E[j].solves = iters[j];
   }
   return HK_OK;
 }

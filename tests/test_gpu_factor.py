@@ -114,3 +114,26 @@ def test_inertia_last_pivot(hk):
     assert m.pivots() == of.pivots()
     st, nneg, fb = m.factor(xs, inertia_mode=0, raise_on_error=False)
     assert st == 2 and fb == N - 1
+
+
+def test_graph_replays_equal_eager_and_oracle(hk):
+    """hk_factor replays one captured HIP graph per panel width when per-launch
+    timing is off: several replays at alternating shifts, with eager (timed,
+    stream-launched) factorisations and host work in between, each equal to
+    the oracle digit for digit."""
+    N, beta, K = 70, (3, 2), 640
+    h = K // 2
+    X = moments(N, beta, K)
+    shifts = [5 << (K - h), 0, 5 << (K - h), 17 << (K - h)]
+    ref = {x: oracle.factor_from_moments(X, N, K, x) for x in set(shifts)}
+    m = hk.Matrix(N, beta, K)
+    for rep, x in enumerate(shifts):
+        for timing in (0, 1, 0):
+            log("graph replay %d timing %d shift %d" % (rep, timing, x))
+            m.set_timing(timing)
+            m.factor(x)
+            compare(m, ref[x], N)
+    m.set_timing(0)
+    m.set_panel(2)          # recapture at another width
+    m.factor(shifts[0])
+    compare(m, ref[shifts[0]], N)
