@@ -108,11 +108,11 @@ def learned_gain(args):
     learned.smallest_eig_learned(model, plain[:2])
     torch.cuda.synchronize()
     t0 = time.time()
-    res_p, rep_p = hk.eig_batched(plain, digits=45)
+    res_p, rep_p = hk.eig_batched(plain, digits=45, panel=args.panel)
     torch.cuda.synchronize()
     t_plain = time.time() - t0
     t0 = time.time()
-    res_l, rep_l, bits, lns = learned.smallest_eig_learned(model, plain)
+    res_l, rep_l, bits, lns = learned.smallest_eig_learned(model, plain, panel=args.panel)
     torch.cuda.synchronize()
     t_learned = time.time() - t0
 
@@ -142,6 +142,7 @@ def learned_gain(args):
         "factorizations_plain": sum(nf for _, _, _, nf in res_p),
         "factorizations_learned": sum(r["factorizations"] for r in res_l),
         "solves_learned": sum(r["solves"] for r in res_l),
+        "panel": args.panel,
     }
     print(json.dumps(out), flush=True)
 
@@ -161,6 +162,7 @@ def main():
     ap.add_argument("--seed", type=int, default=4242)
     ap.add_argument("--n-lo", type=int, default=100)
     ap.add_argument("--n-hi", type=int, default=250)
+    ap.add_argument("--panel", type=int, default=0, help="learned mode: panel width (0: tuned or 4)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the method has no multi-GPU path in this "

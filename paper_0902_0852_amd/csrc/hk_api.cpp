@@ -121,7 +121,7 @@ bool make_plan(int N, int64_t bnum, int64_t bden, int K, Plan& P, std::string& e
   P.o_dv2 = take(sizeof(int32_t) * (size_t)N * P.VW);
   P.o_md = take(sizeof(uint32_t) * (size_t)(P.VW + 4));
   P.o_mdinfo = take(sizeof(int32_t) * 4);
-  P.o_dots = take(sizeof(int64_t) * 4 * (size_t)(2 * P.VW + 8));
+  P.o_dots = take(sizeof(int64_t) * 4 * DOT_PARTS * (size_t)(2 * P.VW + 8));
   P.o_desc = take(sizeof(InstDesc));
   P.total = o;
   return true;

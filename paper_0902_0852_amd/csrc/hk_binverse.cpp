@@ -1,14 +1,16 @@
 // Inverse iteration for every instance of a batch at once (not in the
 // paper): each instance on its own factorisation of M - sigma I, all of them
-// stepped together.  One iteration is eight launches for the whole batch:
-// right-hand side into the accumulators, forward sweep (one workgroup per
-// instance), diagonal division, second initialisation, backward sweep,
-// the exact dots <v,y> and <v,v>, the row of largest |y|, and
-// v <- RNE(y 2^K / max|y|).  The host reads the dots, forms
+// stepped together.  One iteration (right-hand side into the accumulators,
+// forward substitution column by column, diagonal division, second
+// initialisation, backward substitution, the exact dots <v,y> and <v,v>, the
+// row of largest |y|, v <- RNE(y 2^K / max|y|)) is a fixed launch sequence
+// in which every launch covers all instances; it is captured once as a HIP
+// graph and replayed.  The host reads the dots, forms
 // lambda = sigma + <v,v> 2^g / <v,y> per instance and stops an instance by
 // the same rules as the single-instance iteration.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cstring>
 #include <string>
@@ -49,6 +51,51 @@ MP lazy64_to_mp(const int64_t* d, int n) {
   return sub(a, b);
 }
 
+// one inverse-iteration step for every instance, in launch order: right-hand
+// side, forward sweep column by column, diagonal, second right-hand side,
+// backward sweep, dots, largest row, normalisation
+hipError_t enqueue_iteration(const SweepArgs* da, const SweepShape& sh, int b, hipStream_t s) {
+  const int N = sh.maxN;
+  hipError_t e = launch_vinit_b(da, sh, 0, s);
+  int P = 0;
+  for (int k0 = 0; k0 < N && e == hipSuccess; k0 += b, P++) {
+    const int bb = std::min(b, N - k0);
+    for (int j = 0; j < bb && e == hipSuccess; j++) {
+      const int k = k0 + j;
+      if (j > 0) e = launch_vupdate_b(da, sh, 0, k0, k, k, k + 1, P & 1, s);
+      if (e == hipSuccess) e = launch_vfinalize_b(da, sh, k, (P + (j > 0 ? 1 : 0)) & 1, 0, s);
+    }
+    if (e == hipSuccess && k0 + bb < N) e = launch_vupdate_b(da, sh, 0, k0, k0 + bb, k0 + bb, -1, P & 1, s);
+  }
+  if (e == hipSuccess) e = launch_vdivide_b(da, sh, s);
+  if (e == hipSuccess) e = launch_vinit_b(da, sh, 1, s);
+  P = 0;
+  for (int k_hi = N; k_hi > 0 && e == hipSuccess; k_hi -= b, P++) {
+    const int k_lo = std::max(0, k_hi - b);
+    for (int j = 0; j < k_hi - k_lo && e == hipSuccess; j++) {
+      const int k = k_hi - 1 - j;
+      if (j > 0) e = launch_vupdate_b(da, sh, 1, k + 1, k_hi, k, k + 1, P & 1, s);
+      if (e == hipSuccess) e = launch_vfinalize_b(da, sh, k, (P + (j > 0 ? 1 : 0)) & 1, 1, s);
+    }
+    if (e == hipSuccess && k_lo > 0) e = launch_vupdate_b(da, sh, 1, k_lo, k_hi, 0, k_lo, P & 1, s);
+  }
+  if (e == hipSuccess) e = launch_vdots_b(da, sh, s);
+  if (e == hipSuccess) e = launch_vmax_b(da, sh, s);
+  if (e == hipSuccess) e = launch_vscale_b(da, sh, s);
+  return e;
+}
+
+struct GraphHolder {
+  hipStream_t cap = nullptr;
+  hipGraph_t g = nullptr;
+  hipGraphExec_t x = nullptr;
+  ~GraphHolder() {
+    if (x) (void)hipGraphExecDestroy(x);
+    if (g) (void)hipGraphDestroy(g);
+    if (cap) (void)hipStreamDestroy(cap);
+  }
+};
+
 }  // namespace
 
 hk_status batch_inverse(Batch& bt, const std::vector<MP>& sigma, const std::vector<int>& act, int tol,
@@ -62,7 +109,7 @@ hk_status batch_inverse(Batch& bt, const std::vector<MP>& sigma, const std::vect
   std::vector<const Plan*> plans;
   for (int i = 0; i < count; i++) {
     hk_matrix m = bt.mats[i];
-    ha[i] = make_sweep_args(m->P, m->D, m->panel, m->gbits);
+    ha[i] = make_sweep_args(m->P, m->D, bt.panel, m->gbits);
     if (!act[i]) ha[i].N = 0;     // nothing to do for this instance
     plans.push_back(&m->P);
   }
@@ -82,6 +129,17 @@ hk_status batch_inverse(Batch& bt, const std::vector<MP>& sigma, const std::vect
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return bfail(HK_EDEVICE, std::string("batched inverse setup: ") + hipGetErrorString(e));
   const SweepArgs* da = bt.sargs;
+  // one iteration of the whole batch, captured once and replayed
+  GraphHolder gh;
+  e = hipStreamCreateWithFlags(&gh.cap, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamBeginCapture(gh.cap, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    hipError_t ec = enqueue_iteration(da, sh, std::max(1, bt.panel), gh.cap);
+    const hipError_t e2 = hipStreamEndCapture(gh.cap, &gh.g);
+    e = ec != hipSuccess ? ec : e2;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&gh.x, gh.g, nullptr, nullptr, 0);
+  if (e != hipSuccess) return bfail(HK_EDEVICE, std::string("batched inverse graph: ") + hipGetErrorString(e));
   std::vector<std::vector<int64_t>> dots(count);
   std::vector<std::vector<int32_t>> fl(count, std::vector<int32_t>(16, 0));
   std::vector<MP> lam_prev(count), step_prev(count);
@@ -90,18 +148,11 @@ hk_status batch_inverse(Batch& bt, const std::vector<MP>& sigma, const std::vect
   for (int i = 0; i < count; i++) if (act[i]) { open[i] = 1; n_open++; }
   for (int it = 0; it < max_iter && n_open > 0; it++) {
     auto t0 = std::chrono::steady_clock::now();
-    e = launch_vinit_b(da, sh, 0, s);
-    if (e == hipSuccess) e = launch_vsweep_b(da, sh, 0, s);
-    if (e == hipSuccess) e = launch_vdivide_b(da, sh, s);
-    if (e == hipSuccess) e = launch_vinit_b(da, sh, 1, s);
-    if (e == hipSuccess) e = launch_vsweep_b(da, sh, 1, s);
-    if (e == hipSuccess) e = launch_vdots_b(da, sh, s);
-    if (e == hipSuccess) e = launch_vmax_b(da, sh, s);
-    if (e == hipSuccess) e = launch_vscale_b(da, sh, s);
+    e = hipGraphLaunch(gh.x, s);
     for (int i = 0; i < count && e == hipSuccess; i++) {
       if (!open[i]) continue;
       const Plan& P = bt.mats[i]->P;
-      dots[i].resize((size_t)4 * (2 * P.VW + 8));
+      dots[i].resize((size_t)4 * DOT_PARTS * (2 * P.VW + 8));
       e = hipMemcpyAsync(dots[i].data(), bt.mats[i]->D.dots, sizeof(int64_t) * dots[i].size(),
                          hipMemcpyDeviceToHost, s);
       if (e == hipSuccess)
@@ -118,9 +169,12 @@ hk_status batch_inverse(Batch& bt, const std::vector<MP>& sigma, const std::vect
       auto close = [&](hk_status r) { st[i] = r; open[i] = 0; n_open--; };
       if (fl[i][0]) { close(HK_EPRECISION); continue; }
       const int np = 2 * P.VW + 8;
-      // each dot is a row of low parts plus a row of high parts
-      const MP vy = add(lazy64_to_mp(dots[i].data(), np), lazy64_to_mp(dots[i].data() + np, np));
-      const MP vv = add(lazy64_to_mp(dots[i].data() + 2 * np, np), lazy64_to_mp(dots[i].data() + 3 * np, np));
+      // each dot: DOT_PARTS parts of a row of low parts and a row of high parts
+      MP vy, vv;
+      for (int r = 0; r < 2 * DOT_PARTS; r++) {
+        vy = add(vy, lazy64_to_mp(dots[i].data() + (size_t)r * np, np));
+        vv = add(vv, lazy64_to_mp(dots[i].data() + (size_t)(2 * DOT_PARTS + r) * np, np));
+      }
       if (vy.sign() <= 0) { close(HK_EPRECISION); continue; }
       const int64_t F = 2 * (int64_t)K + 64;
       const MP lamF = add(shl(sigma[i], F - K), floor_div(shl(vv, g + F), vy));

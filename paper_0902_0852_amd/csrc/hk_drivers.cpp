@@ -525,18 +525,8 @@ hk_status hk_solve(hk_matrix m, const void* dev_rhs, void* dev_x, hipStream_t s)
   hipError_t e = launch_fill32(D.flags, 16, 0, s);
   // forward: acc = b 2^(h+g); z_k = RNE(acc_k / 2^h) column by column
   if (e == hipSuccess) e = launch_vinit(P, D, (const int32_t*)dev_rhs, h + m->gbits, s);
-  // one launch per column step across the chip (default: lowest latency for
-  // one instance), or one single-workgroup launch per sweep (HK_SOLVE_FUSED)
-  static const bool stepwise = getenv("HK_SOLVE_FUSED") == nullptr;
-  if (!stepwise) {
-    // one launch per sweep
-    if (e == hipSuccess) e = launch_vsweep(P, D, 0, b, nullptr, s);
-    if (e == hipSuccess) e = launch_vdivide(P, D, s);
-    if (e == hipSuccess) e = launch_vinit(P, D, D.wb, h, s);
-    if (e == hipSuccess) e = launch_vsweep(P, D, 1, b, (int32_t*)dev_x, s);
-  }
   int Pidx = 0;
-  for (int k0 = 0; k0 < N && e == hipSuccess && stepwise; k0 += b, Pidx++) {
+  for (int k0 = 0; k0 < N && e == hipSuccess; k0 += b, Pidx++) {
     const int bb = std::min(b, N - k0);
     for (int j = 0; j < bb && e == hipSuccess; j++) {
       const int k = k0 + j;
@@ -546,11 +536,11 @@ hk_status hk_solve(hk_matrix m, const void* dev_rhs, void* dev_x, hipStream_t s)
     if (e == hipSuccess && k0 + bb < N) e = launch_vupdate(P, D, 0, k0, k0 + bb, k0 + bb, N, Pidx & 1, s);
   }
   // diagonal: w_k = RNE(z_k 2^h / d_k)
-  if (e == hipSuccess && stepwise) e = launch_vdivide(P, D, s);
+  if (e == hipSuccess) e = launch_vdivide(P, D, s);
   // backward: acc = w 2^h; y_k = RNE(acc_k / 2^h), last row first
-  if (e == hipSuccess && stepwise) e = launch_vinit(P, D, D.wb, h, s);
+  if (e == hipSuccess) e = launch_vinit(P, D, D.wb, h, s);
   Pidx = 0;
-  for (int k_hi = N; k_hi > 0 && e == hipSuccess && stepwise; k_hi -= b, Pidx++) {
+  for (int k_hi = N; k_hi > 0 && e == hipSuccess; k_hi -= b, Pidx++) {
     const int k_lo = std::max(0, k_hi - b);
     for (int j = 0; j < k_hi - k_lo && e == hipSuccess; j++) {
       const int k = k_hi - 1 - j;

@@ -20,6 +20,7 @@ constexpr int DB = 29;
 constexpr int64_t RADIX = int64_t(1) << DB;
 constexpr int WB = 16;       // digits per output block of the trailing update
 constexpr int TROWS = 64;    // rows per update tile (one wavefront)
+constexpr int DOT_PARTS = 8; // workgroups per exact dot product (batched inverse iteration)
 
 // Per-column layout record (column c of the working triangle, also used as
 // the panel column k that produced C_k / L_k).
@@ -134,8 +135,6 @@ hipError_t launch_vupdate(const Plan& P, const DevPtrs& D, int bwd, int k0, int 
 hipError_t launch_vfinalize(const Plan& P, const DevPtrs& D, int k, int rd, int32_t* out,
                             hipStream_t s);
 hipError_t launch_vdivide(const Plan& P, const DevPtrs& D, hipStream_t s);
-// the whole forward (bwd = 0) or backward (bwd = 1) sweep of a solve in one launch
-hipError_t launch_vsweep(const Plan& P, const DevPtrs& D, int bwd, int panel, int32_t* out, hipStream_t s);
 
 // Everything the solve and inverse-iteration kernels need of one instance;
 // the batched launches take a device array of these (one per instance).
@@ -154,13 +153,15 @@ struct SweepShape { int count = 0, maxN = 0, maxVA = 0, maxVW = 0; int64_t maxVA
 SweepShape sweep_shape(const std::vector<const Plan*>& plans);
 // Batched inverse-iteration steps (hk_kernels.hip):
 //   vinit_b  stage 0: acc = v 2^(h+g); stage 1: acc = w 2^h
-//   vsweep_b forward (bwd 0) or backward (bwd 1, y rows out) sweep, one workgroup per instance
+//   vupdate_b, vfinalize_b  one column step of the forward (bwd 0) or backward (bwd 1) substitution
 //   vdivide_b w = RNE(z 2^h / d) per row
 //   vdots_b  exact <v, y> and <v, v> as lazy int64 digits (dots)
 //   vmax_b   the row of largest |y|: its magnitude normalised (md, mdinfo = nd, sh, row)
 //   vscale_b v = RNE(y 2^K / max|y|)
 hipError_t launch_vinit_b(const SweepArgs* args, const SweepShape& sh, int stage, hipStream_t s);
-hipError_t launch_vsweep_b(const SweepArgs* args, const SweepShape& sh, int bwd, hipStream_t s);
+hipError_t launch_vupdate_b(const SweepArgs* args, const SweepShape& sh, int bwd, int k0, int k1, int i_lo,
+                            int i_hi, int rd, hipStream_t s);
+hipError_t launch_vfinalize_b(const SweepArgs* args, const SweepShape& sh, int k, int rd, int bwd, hipStream_t s);
 hipError_t launch_vdivide_b(const SweepArgs* args, const SweepShape& sh, hipStream_t s);
 hipError_t launch_vdots_b(const SweepArgs* args, const SweepShape& sh, hipStream_t s);
 hipError_t launch_vmax_b(const SweepArgs* args, const SweepShape& sh, hipStream_t s);

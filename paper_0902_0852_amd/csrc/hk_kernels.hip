@@ -840,11 +840,8 @@ __global__ void __launch_bounds__(64) k_vfinalize(int k, int rd, int h, const in
   }
 }
 
-// Whole forward (bwd = 0) or backward (bwd = 1) substitution of a solve in
-// one launch: one workgroup walks the columns with the same panel schedule,
-// carry parities and arithmetic as the per-step launches (k_vupdate,
-// k_vfinalize), the stages separated by workgroup barriers.  Wavefront 0
-// finalises u_k while the others wait; every wavefront takes update items.
+// u_k = RNE(acc_k / 2^h) of one instance by one wavefront (the batched
+// solves), with the counts and the optional copy of k_vfinalize.
 __device__ void sweep_finalize(const SweepArgs& a, int k, int rd, int64_t* smem) {
   int32_t* dg = (int32_t*)smem;
   int32_t* ob = dg + (a.VA + 48);
@@ -863,72 +860,9 @@ __device__ void sweep_finalize(const SweepArgs& a, int k, int rd, int64_t* smem)
     for (int j = threadIdx.x & 63; j < a.VW; j += 64) a.out[(int64_t)k * a.VW + j] = a.ub[(int64_t)k * a.VW + j];
 }
 
-__device__ __forceinline__ void sweep_update(const SweepArgs& a, int k0, int k1, int i_lo, int i_hi, int rd) {
-  if (i_hi <= i_lo || k1 <= k0) return;
-  const int wave = uni(threadIdx.x >> 6), nw = blockDim.x >> 6;
-  const int items = ((i_hi - i_lo + 63) / 64) * a.nbA;
-  for (int it = wave; it < items; it += nw)
-    vupdate_item(a.cols, a.N, a.bwd, k0, k1, i_lo, i_hi, rd, it, a.acc, a.kc, a.Npad, a.nbA, a.ub, a.nU, a.VW,
-                 a.L, a.LT, a.nL, a.LWT, a.flags);
-}
-
-__device__ void sweep_body(const SweepArgs& a, int64_t* smem) {
-  const int wave = uni(threadIdx.x >> 6);
-  const int N = a.N, b = a.panel;
-  int P = 0;
-  if (!a.bwd) {
-    for (int k0 = 0; k0 < N; k0 += b, P++) {
-      const int bb = min(b, N - k0);
-      for (int j = 0; j < bb; j++) {
-        const int k = k0 + j;
-        if (j > 0) {
-          sweep_update(a, k0, k, k, k + 1, P & 1);
-          __syncthreads();
-        }
-        if (wave == 0) sweep_finalize(a, k, (P + (j > 0 ? 1 : 0)) & 1, smem);
-        __syncthreads();
-      }
-      if (k0 + bb < N) {
-        sweep_update(a, k0, k0 + bb, k0 + bb, N, P & 1);
-        __syncthreads();
-      }
-    }
-  } else {
-    for (int k_hi = N; k_hi > 0; k_hi -= b, P++) {
-      const int k_lo = max(0, k_hi - b);
-      for (int j = 0; j < k_hi - k_lo; j++) {
-        const int k = k_hi - 1 - j;
-        if (j > 0) {
-          sweep_update(a, k + 1, k_hi, k, k + 1, P & 1);
-          __syncthreads();
-        }
-        if (wave == 0) sweep_finalize(a, k, (P + (j > 0 ? 1 : 0)) & 1, smem);
-        __syncthreads();
-      }
-      if (k_lo > 0) {
-        sweep_update(a, k_lo, k_hi, 0, k_lo, P & 1);
-        __syncthreads();
-      }
-    }
-  }
-}
-
-__global__ void __launch_bounds__(512) k_vsweep(SweepArgs a) {
-  extern __shared__ int64_t smem[];
-  sweep_body(a, smem);
-}
-
 // ---------------------------------------------- batched inverse iteration
 // One SweepArgs per instance; blockIdx.y (or blockIdx.x for one-workgroup
 // kernels) selects the instance.
-
-__global__ void __launch_bounds__(512) k_vsweep_b(const SweepArgs* __restrict__ args, int bwd) {
-  extern __shared__ int64_t smem[];
-  SweepArgs a = args[blockIdx.x];
-  a.bwd = bwd;
-  a.out = bwd ? a.y : nullptr;
-  sweep_body(a, smem);
-}
 
 __global__ void __launch_bounds__(256) k_vinit_b(const SweepArgs* __restrict__ args, int stage) {
   const SweepArgs& a = args[blockIdx.y];
@@ -964,8 +898,38 @@ __global__ void __launch_bounds__(64) k_vdivide_b(const SweepArgs* __restrict__ 
                    a.VW, nullptr, 0, a.flags);
 }
 
-// <v, y> (which = 0) and <v, v> (which = 1) exactly: thread t owns output
-// digit positions p = t, t + 256, ... and sums v_i[a] y_i[p - a] over rows i
+// One column step of the solves for every instance of a batch (blockIdx.y):
+// the update of rows [i_lo, i_hi) (i_hi < 0: the instance's N) by columns
+// [k0, k1), both clipped to the instance's N, with the item layout of
+// k_vupdate.
+__global__ void __launch_bounds__(256) k_vupdate_b(const SweepArgs* __restrict__ args, int bwd, int k0, int k1,
+                                                   int i_lo, int i_hi, int rd) {
+  const SweepArgs& a = args[blockIdx.y];
+  const int N = a.N;
+  const int k1e = min(k1, N), ihe = i_hi < 0 ? N : min(i_hi, N);
+  if (k1e <= k0 || ihe <= i_lo) return;
+  const int wave = uni(threadIdx.x >> 6);
+  const int T = (ihe - i_lo + 63) / 64;
+  const int it = blockIdx.x * 4 + wave;
+  if (it >= T * a.nbA) return;
+  vupdate_item(a.cols, N, bwd, k0, k1e, i_lo, ihe, rd, it, a.acc, a.kc, a.Npad, a.nbA, a.ub, a.nU, a.VW, a.L,
+               a.LT, a.nL, a.LWT, a.flags);
+}
+
+// u_k = RNE(acc_k / 2^h) for every instance (blockIdx.x) with k < N; the
+// backward sweep also copies it to y
+__global__ void __launch_bounds__(64) k_vfinalize_b(const SweepArgs* __restrict__ args, int k, int rd, int bwd) {
+  extern __shared__ int64_t smem[];
+  SweepArgs a = args[blockIdx.x];
+  if (k >= a.N) return;
+  a.out = bwd ? a.y : nullptr;
+  sweep_finalize(a, k, rd, smem);
+}
+
+// <v, y> (which = 0) and <v, v> (which = 1) exactly, split over DOT_PARTS
+// workgroups per dot (each a subset of the rows; the host adds the parts):
+// thread t owns output digit positions p = t, t + 256, ... and sums
+// v_i[a] y_i[p - a] over its rows i
 // and digits a in int64, moving everything above 29 bits into a second
 // accumulator every 64 products.  Rows are staged in LDS (v_i broadcast,
 // y_i read at consecutive addresses).  Written as two lazy int64 digit rows,
@@ -975,11 +939,12 @@ __global__ void __launch_bounds__(64) k_vdivide_b(const SweepArgs* __restrict__ 
 __global__ void __launch_bounds__(256) k_vdots_b(const SweepArgs* __restrict__ args) {
   extern __shared__ int64_t smem[];
   const SweepArgs& a = args[blockIdx.x];
-  const int which = blockIdx.y;
+  const int which = blockIdx.y;       // 0: <v, y>, 1: <v, v>
+  const int part = blockIdx.z;        // rows i = part, part + DOT_PARTS, ...
   const int32_t* V = a.v;
   const int32_t* Y = which == 0 ? a.y : a.v;
   const int VW = a.VW, np = VW + 4;     // 2 np = 2 VW + 8 entries per row
-  int64_t* lo_row = a.dots + (int64_t)which * 2 * (2 * np);
+  int64_t* lo_row = a.dots + ((int64_t)which * DOT_PARTS + part) * 2 * (2 * np);
   int64_t* hi_row = lo_row + 2 * np;
   int32_t* vs = (int32_t*)smem;
   int32_t* ys = vs + VW;
@@ -993,7 +958,7 @@ __global__ void __launch_bounds__(256) k_vdots_b(const SweepArgs* __restrict__ a
     int cnt[PT];
 #pragma unroll
     for (int u = 0; u < PT; u++) { lo[u] = 0; hi[u] = 0; cnt[u] = 0; }
-    for (int i = 0; i < a.N; i++) {
+    for (int i = part; i < a.N; i += DOT_PARTS) {
       __syncthreads();
       for (int d = threadIdx.x; d < VW; d += blockDim.x) {
         vs[d] = V[(int64_t)i * VW + d];
@@ -1249,13 +1214,6 @@ SweepArgs make_sweep_args(const Plan& P, const DevPtrs& D, int panel, int gbits)
   a.dots = D.dots; a.md = D.md; a.mdinfo = D.mdinfo;
   return a;
 }
-hipError_t launch_vsweep(const Plan& P, const DevPtrs& D, int bwd, int panel, int32_t* out, hipStream_t s) {
-  SweepArgs a = make_sweep_args(P, D, panel, 0);
-  a.bwd = bwd;
-  a.out = out;
-  hipLaunchKernelGGL(k_vsweep, dim3(1), dim3(512), fin_shm(P.VA), s, a);
-  return hipGetLastError();
-}
 SweepShape sweep_shape(const std::vector<const Plan*>& plans) {
   SweepShape sh;
   sh.count = (int)plans.size();
@@ -1274,8 +1232,18 @@ hipError_t launch_vinit_b(const SweepArgs* args, const SweepShape& sh, int stage
   hipLaunchKernelGGL(k_vinit_b, dim3(bx, sh.count), dim3(256), 0, s, args, stage);
   return hipGetLastError();
 }
-hipError_t launch_vsweep_b(const SweepArgs* args, const SweepShape& sh, int bwd, hipStream_t s) {
-  hipLaunchKernelGGL(k_vsweep_b, dim3(sh.count), dim3(512), fin_shm(sh.maxVA), s, args, bwd);
+hipError_t launch_vupdate_b(const SweepArgs* args, const SweepShape& sh, int bwd, int k0, int k1, int i_lo,
+                            int i_hi, int rd, hipStream_t s) {
+  // rows of the widest instance bound the item count
+  const int rows = (i_hi < 0 ? sh.maxN : std::min(i_hi, sh.maxN)) - i_lo;
+  if (rows <= 0 || k1 <= k0) return hipSuccess;
+  const int64_t items = (int64_t)((rows + 63) / 64) * (sh.maxVA / WB);
+  hipLaunchKernelGGL(k_vupdate_b, dim3((unsigned)((items + 3) / 4), sh.count), dim3(256), 0, s, args, bwd, k0, k1,
+                     i_lo, i_hi, rd);
+  return hipGetLastError();
+}
+hipError_t launch_vfinalize_b(const SweepArgs* args, const SweepShape& sh, int k, int rd, int bwd, hipStream_t s) {
+  hipLaunchKernelGGL(k_vfinalize_b, dim3(sh.count), dim3(64), fin_shm(sh.maxVA), s, args, k, rd, bwd);
   return hipGetLastError();
 }
 hipError_t launch_vdivide_b(const SweepArgs* args, const SweepShape& sh, hipStream_t s) {
@@ -1283,7 +1251,7 @@ hipError_t launch_vdivide_b(const SweepArgs* args, const SweepShape& sh, hipStre
   return hipGetLastError();
 }
 hipError_t launch_vdots_b(const SweepArgs* args, const SweepShape& sh, hipStream_t s) {
-  hipLaunchKernelGGL(k_vdots_b, dim3(sh.count, 2), dim3(256), sizeof(int32_t) * 2 * sh.maxVW, s, args);
+  hipLaunchKernelGGL(k_vdots_b, dim3(sh.count, 2, DOT_PARTS), dim3(256), sizeof(int32_t) * 2 * sh.maxVW, s, args);
   return hipGetLastError();
 }
 hipError_t launch_vmax_b(const SweepArgs* args, const SweepShape& sh, hipStream_t s) {
