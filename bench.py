@@ -29,6 +29,7 @@ CONFIGS = {
     "c3b2": dict(N=500, beta=(2, 1), K=6144, desc="N=500 beta=2 K=6144"),
     "c3b32": dict(N=500, beta=(3, 2), K=6144, desc="N=500 beta=3/2 K=6144"),
     "c3b12": dict(N=500, beta=(1, 2), K=6144, desc="N=500 beta=1/2 K=6144"),
+    "c5": dict(N=1500, beta=(3, 2), K=24576, desc="N=1500 beta=3/2 K=24576"),
 }
 PEAK_INT_MUL = 256 * 64 * 2.4e9       # one 32x32 multiply per lane per clock
 HBM_PEAK = 8.0e12
@@ -101,14 +102,29 @@ def learned_gain(args):
     from paper_0902_0852_amd import learned
     from fractions import Fraction
     model = learned.load_model(args.model) if args.model else learned.load_model()
-    insts = learned.sample_instances(args.instances, args.seed, args.n_lo, args.n_hi)
-    plain = [(N, b, learned.plain_bits(N)) for N, b in insts]
-    # warm-up on a small batch of the same kind (graph capture, code load)
-    hk.eig_batched(plain[:2], digits=45)
-    learned.smallest_eig_learned(model, plain[:2])
+    single = args.config == "c5"
+    if single:
+        # one large instance: the plain form is inverse iteration from 0 at the
+        # fixed precision plus the inertia bracket (the faster plain driver)
+        cfg = CONFIGS["c5"]
+        insts = [(cfg["N"], cfg["beta"])]
+        plain = [(cfg["N"], cfg["beta"], cfg["K"])]
+    else:
+        insts = learned.sample_instances(args.instances, args.seed, args.n_lo, args.n_hi)
+        plain = [(N, b, learned.plain_bits(N)) for N, b in insts]
+        # warm-up on a small batch of the same kind (graph capture, code load)
+        hk.eig_batched(plain[:2], digits=45)
+        learned.smallest_eig_learned(model, plain[:2])
     torch.cuda.synchronize()
     t0 = time.time()
-    res_p, rep_p = hk.eig_batched(plain, digits=45, panel=args.panel)
+    if single:
+        N, beta, K = plain[0]
+        dec, rep = hk.smallest_eig(N, beta, K, method=hk.HK_INVERSE, digits=45, flags=hk.HK_FLAG_NO_WORK_COUNT)
+        res_p = [(rep["status"], dec, rep["verified"], rep["factorizations"])]
+        log("plain: %s in %.1f s (%d factorisations, %d solves)" % (dec, time.time() - t0, rep["factorizations"],
+                                                                    rep["solves"]))
+    else:
+        res_p, rep_p = hk.eig_batched(plain, digits=45, panel=args.panel)
     torch.cuda.synchronize()
     t_plain = time.time() - t0
     t0 = time.time()
@@ -130,9 +146,12 @@ def learned_gain(args):
                   "fixed precision",
         "value": n / t_learned, "unit": "instances/s", "n_gpus": 1, "higher_is_better": True,
         "data": "synthetic", "dtype": "int32 (method), float32 (network)",
-        "config": {"workload": "%d held-out instances, seed %d, N uniform in [%d, %d], beta = p/q, p, q in 1..8, "
-                               "beta in [1/2, 3]; plain precision 1024 + 20.48 (N - 50) bits" %
-                               (n, args.seed, args.n_lo, args.n_hi)},
+        "config": {"workload": ("N=1500 beta=3/2, plain: inverse iteration + bracket at 24576 bits" if single else
+                                "%d held-out instances, seed %d, N uniform in [%d, %d], beta = p/q, p, q in 1..8, "
+                                "beta in [1/2, 3]; plain: batched Secant + bracket at 1024 + 20.48 (N - 50) bits" %
+                                (n, args.seed, args.n_lo, args.n_hi))},
+        "lambda_plain": res_p[0][1] if single else None,
+        "lambda_learned": res_l[0]["lambda_dec"] if single else None,
         "plain_instances_per_s": n / t_plain, "speedup": t_plain / t_learned,
         "t_plain_s": t_plain, "t_learned_s": t_learned,
         "accepted_learned": sum(r["path"] == 1 for r in res_l), "fallback_plain": sum(r["path"] == 0 for r in res_l),
@@ -158,11 +177,11 @@ def main():
     ap.add_argument("--mode", default="plain", choices=["plain", "learned"],
                     help="learned: batched + learned form against the batched plain form")
     ap.add_argument("--model", default=None, help="network file (default: the package's trained one)")
-    ap.add_argument("--instances", type=int, default=32)
+    ap.add_argument("--instances", type=int, default=64)
     ap.add_argument("--seed", type=int, default=4242)
-    ap.add_argument("--n-lo", type=int, default=100)
-    ap.add_argument("--n-hi", type=int, default=250)
-    ap.add_argument("--panel", type=int, default=0, help="learned mode: panel width (0: tuned or 4)")
+    ap.add_argument("--n-lo", type=int, default=50)
+    ap.add_argument("--n-hi", type=int, default=400)
+    ap.add_argument("--panel", type=int, default=0, help="panel width (0: tuned here / tuned or 4 in learned mode)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the method has no multi-GPU path in this "
@@ -182,19 +201,25 @@ def main():
     import tempfile
     tune_path = os.path.join(tempfile.gettempdir(), "hk_tune_%d.txt" % os.getpid())
     os.environ["HK_TUNE_CACHE"] = tune_path
-    panel = hk.autotune([(N, beta, K)], cache_path=tune_path)
-    log("tuned panel width %d" % panel)
+    if args.panel > 0:
+        panel = args.panel
+        log("panel width %d (given)" % panel)
+    else:
+        panel = hk.autotune([(N, beta, K)], cache_path=tune_path)
+        log("tuned panel width %d" % panel)
+    pflag = hk.HK_FLAG_PANEL(panel)
     # untimed: work count (deterministic) and warmup
-    dec, rep = hk.smallest_eig(N, beta, K, method=method, digits=45, ws=ws)
+    dec, rep = hk.smallest_eig(N, beta, K, method=method, digits=45, ws=ws, flags=pflag)
     macs_per_step = rep["limb_macs"]
     log("work per step: %.4e limb-MACs over %d factorisations; lambda_1 = %s"
         % (macs_per_step, rep["factorizations"], dec))
     for _ in range(max(0, args.warmup - 1)):
-        hk.smallest_eig(N, beta, K, method=method, digits=45, ws=ws, flags=hk.HK_FLAG_NO_WORK_COUNT)
+        hk.smallest_eig(N, beta, K, method=method, digits=45, ws=ws, flags=hk.HK_FLAG_NO_WORK_COUNT | pflag)
     torch.cuda.synchronize()
     t0 = time.time()
     for _ in range(args.steps):
-        dec, r = hk.smallest_eig(N, beta, K, method=method, digits=45, ws=ws, flags=hk.HK_FLAG_NO_WORK_COUNT)
+        dec, r = hk.smallest_eig(N, beta, K, method=method, digits=45, ws=ws,
+                                 flags=hk.HK_FLAG_NO_WORK_COUNT | pflag)
         assert r["verified"] == 1
     torch.cuda.synchronize()
     dt = time.time() - t0
@@ -204,7 +229,7 @@ def main():
     # bracketed by HIP events on the library's stream (stream launches instead
     # of the graph replay, the kernels are the same)
     _, r = hk.smallest_eig(N, beta, K, method=method, digits=45, ws=ws,
-                           flags=hk.HK_FLAG_NO_WORK_COUNT | hk.HK_FLAG_TIME_UPDATES)
+                           flags=hk.HK_FLAG_NO_WORK_COUNT | hk.HK_FLAG_TIME_UPDATES | pflag)
     torch.cuda.synchronize()
     upd_ms, upd_n = r["update_ms"], r["update_launches"]
     achieved = macs_per_step / (upd_ms * 1e-3) if upd_ms > 0 else 0.0

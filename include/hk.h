@@ -68,6 +68,9 @@ enum { HK_INVERSE = 0, HK_SECANT = 1 };
 /* flags or-ed into the method argument of hk_smallest_eig */
 enum { HK_FLAG_NO_WORK_COUNT = 0x100,   /* skip the limb-MAC count (report 0)    */
        HK_FLAG_TIME_UPDATES = 0x200 };  /* time every trailing-update launch      */
+/* panel width p in 1..64 forced for hk_smallest_eig: or HK_FLAG_PANEL(p)
+   into the method argument (0: the tuned width, else 4) */
+#define HK_FLAG_PANEL(p) (((p) & 0xff) << 16)
 
 typedef struct hk_matrix_s* hk_matrix;
 

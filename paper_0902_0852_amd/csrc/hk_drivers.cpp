@@ -617,6 +617,8 @@ hk_status hk_smallest_eig(int N, hk_rational beta, int prec_bits, int method, in
   cx.s = s;
   cx.count_macs = !(flags & HK_FLAG_NO_WORK_COUNT);
   if (flags & HK_FLAG_TIME_UPDATES) hk_set_timing(m, 1);
+  const int forced_panel = (flags >> 16) & 0xff;
+  if (forced_panel > 0) hk_set_panel(m, forced_panel);
   MP lam;
   int solves = 0;
   if (method == HK_SECANT) {

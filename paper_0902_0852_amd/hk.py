@@ -16,6 +16,11 @@ LIB_PATH = os.path.join(_HERE, "libhk.so")
 
 HK_INVERSE, HK_SECANT = 0, 1
 HK_FLAG_NO_WORK_COUNT, HK_FLAG_TIME_UPDATES = 0x100, 0x200
+
+
+def HK_FLAG_PANEL(p):
+    """Panel width forced for smallest_eig (or-ed into flags)."""
+    return (p & 0xff) << 16
 STATUS = {0: "HK_OK", 1: "HK_EINVAL", 2: "HK_ENOTSPD", 3: "HK_EPRECISION", 4: "HK_ENOCONV",
           5: "HK_EVERIFY", 6: "HK_EDEVICE", 7: "HK_ENOMEM"}
 
