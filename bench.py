@@ -182,6 +182,8 @@ def main():
     ap.add_argument("--n-lo", type=int, default=50)
     ap.add_argument("--n-hi", type=int, default=400)
     ap.add_argument("--panel", type=int, default=0, help="panel width (0: tuned here / tuned or 4 in learned mode)")
+    ap.add_argument("--lookahead", type=int, default=-1, choices=[-1, 0, 1],
+                    help="with --panel: look-ahead off / on (-1: chosen by size)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the method has no multi-GPU path in this "
@@ -202,12 +204,16 @@ def main():
     tune_path = os.path.join(tempfile.gettempdir(), "hk_tune_%d.txt" % os.getpid())
     os.environ["HK_TUNE_CACHE"] = tune_path
     if args.panel > 0:
-        panel = args.panel
-        log("panel width %d (given)" % panel)
+        panel, la = args.panel, args.lookahead
+        log("panel width %d, look-ahead %s (given)" % (panel, la))
     else:
-        panel = hk.autotune([(N, beta, K)], cache_path=tune_path)
-        log("tuned panel width %d" % panel)
+        panel, la = hk.autotune([(N, beta, K)], cache_path=tune_path)
+        log("tuned panel width %d, look-ahead %d" % (panel, la))
     pflag = hk.HK_FLAG_PANEL(panel)
+    if la == 1:
+        pflag |= hk.HK_FLAG_LOOKAHEAD_ON
+    elif la == 0:
+        pflag |= hk.HK_FLAG_LOOKAHEAD_OFF
     # untimed: work count (deterministic) and warmup
     dec, rep = hk.smallest_eig(N, beta, K, method=method, digits=45, ws=ws, flags=pflag)
     macs_per_step = rep["limb_macs"]
@@ -243,7 +249,7 @@ def main():
         "config": {"workload": "lambda_1 of the Hankel moment matrix, %s, %s driver, verified "
                                "to 45 digits" % (cfg["desc"], args.method),
                    "N": N, "beta": "%d/%d" % beta, "prec_bits": K, "method": args.method,
-                   "panel": panel},
+                   "panel": panel, "lookahead": la},
         "lambda_solves_per_s": args.steps / dt,
         "lambda_1": dec,
         "roofline": {"bound": "alu", "kernel": "k_update (trailing + in-panel update)",

@@ -71,6 +71,8 @@ enum { HK_FLAG_NO_WORK_COUNT = 0x100,   /* skip the limb-MAC count (report 0)   
 /* panel width p in 1..64 forced for hk_smallest_eig: or HK_FLAG_PANEL(p)
    into the method argument (0: the tuned width, else 4) */
 #define HK_FLAG_PANEL(p) (((p) & 0xff) << 16)
+/* look-ahead forced on / off for hk_smallest_eig (see hk_set_lookahead) */
+enum { HK_FLAG_LOOKAHEAD_ON = 0x1000000, HK_FLAG_LOOKAHEAD_OFF = 0x2000000 };
 
 typedef struct hk_matrix_s* hk_matrix;
 
@@ -110,8 +112,9 @@ size_t hk_workspace_bytes(int N, hk_rational beta, int prec_bits, int flags);
    (round to nearest, ties to even), and uploads them to dev_ws.  The matrix
    itself is expanded from them at every hk_factor.  On success *out is a new
    handle bound to dev_ws (which must stay alive until hk_matrix_destroy).
-   Its panel width is 4, or the one hk_autotune stored for this shape in the
-   tuning cache named by the environment variable HK_TUNE_CACHE. */
+   Its panel width (4) and look-ahead (by size) are the ones hk_autotune
+   stored for this shape in the tuning cache named by the environment
+   variable HK_TUNE_CACHE, when there is such an entry. */
 hk_status hk_build_matrix(int N, hk_rational beta, int prec_bits, void* dev_ws,
                           size_t ws_bytes, hipStream_t s, hk_matrix* out);
 
@@ -155,6 +158,15 @@ hk_status hk_matrix_info(hk_matrix m, hk_info* out);
 
 /* Tuning: columns per trailing update (panel width, >= 1). */
 hk_status hk_set_panel(hk_matrix m, int panel);
+/* Look-ahead ("The LDL^T Determinant Algorithm", parallel version: the next
+   panel's columns are updated first): mode 1 splits every trailing update
+   into the next panel's columns, on the critical path, and the rest, on a
+   second stream concurrently with the next panel; 0 keeps one trailing
+   update per panel; -1 (default) takes the tuned setting, else on when
+   N x widest column >= 100000 digits.  The environment variable
+   HK_LOOKAHEAD=0/1 overrides every setting.  The digits are the same
+   either way (exact updates). */
+hk_status hk_set_lookahead(hk_matrix m, int mode);
 /* Timing: when on, every launch of the update kernel in hk_factor (the
    in-panel and the trailing ones) is bracketed by HIP events on s and
    hk_info reports their count and summed duration. */
@@ -224,11 +236,12 @@ hk_status hk_eig_batched(const hk_instance* inst, int count, int digits, int pan
                          size_t ws_bytes, hipStream_t s, hk_result* out, hk_batch_report* rep);
 
 /* Times one batched factorisation of the given batch for each panel width
-   in {1, 2, 4, 8, 16}, stores the fastest in *best_panel and appends it to
-   the text cache file cache_path (NULL: no file) under the batch-shape key
+   in {1, 2, 4, 8, 16}, without and with look-ahead, stores the fastest in
+   *best_panel and *best_lookahead (may be NULL) and appends them to the text
+   cache file cache_path (NULL: no file) under the batch-shape key
    (architecture, count, N bucket, K bucket).  Synchronises s. */
 hk_status hk_autotune(const hk_instance* inst, int count, void* dev_ws, size_t ws_bytes,
-                      hipStream_t s, const char* cache_path, int* best_panel);
+                      hipStream_t s, const char* cache_path, int* best_panel, int* best_lookahead);
 
 /* ---- precision-proposal network -----------------------------------------
    A float32 MLP 3 -> 64 -> 64 -> 64 -> 2 with ReLU on the hidden layers

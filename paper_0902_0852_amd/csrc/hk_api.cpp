@@ -7,6 +7,7 @@
 #include <chrono>
 #include <climits>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -26,6 +27,17 @@ static hk_status fail(hk_status st, const std::string& msg) { g_err = msg; retur
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 static int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+// Whether the trailing update leaves the critical path (look-ahead):
+// HK_LOOKAHEAD=0/1 forces it; else the setting (0/1, from the caller or the
+// tuning cache); else on when a panel carries enough update work
+// (N x widest column >= 100000 digits), where the second stream pays off.
+bool use_lookahead(int setting, int maxN, int maxW) {
+  const char* v = getenv("HK_LOOKAHEAD");
+  if (v && (v[0] == '0' || v[0] == '1')) return v[0] == '1';
+  if (setting == 0 || setting == 1) return setting == 1;
+  return (int64_t)maxN * maxW >= 100000;
+}
 
 bool make_plan(int N, int64_t bnum, int64_t bden, int K, Plan& P, std::string& err) {
   if (N < 1 || N > 100000) { err = "N out of range"; return false; }
@@ -201,9 +213,11 @@ void mp_to_digits(const MP& v, int32_t* out, int n) { to_digits(v, out, n); }
 // place): expansion, then per panel of b columns the in-panel updates,
 // finalisations and divisions column by column, then the trailing update.
 // With evs != NULL every update launch is bracketed by HIP events.
-hipError_t enqueue_factor(const BatchView& B, int b, hipStream_t s,
+hipError_t enqueue_factor(const BatchView& B, int b, hipStream_t s, hipStream_t s2,
                           std::vector<std::pair<hipEvent_t, hipEvent_t>>* evs,
                           std::vector<hipEvent_t>* pool, size_t* evi, int* n_update) {
+  // one pool of (timing-capable) events for both the per-launch timing and
+  // the look-ahead fork/join points
   auto get_ev = [&]() -> hipEvent_t {
     if (*evi >= pool->size()) {
       hipEvent_t e;
@@ -212,27 +226,48 @@ hipError_t enqueue_factor(const BatchView& B, int b, hipStream_t s,
     }
     return (*pool)[(*evi)++];
   };
-  auto timed_update = [&](int pc, int j, int rd) -> hipError_t {
+  auto timed_update = [&](int pc, int j, int rd, hipStream_t st) -> hipError_t {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (evs) { e0 = get_ev(); e1 = get_ev(); }
     hipError_t e = hipSuccess;
-    if (e0 && e1) e = hipEventRecord(e0, s);
-    if (e == hipSuccess) e = launch_update(B, pc, b, j, rd, s);
-    if (e == hipSuccess && e0 && e1) { e = hipEventRecord(e1, s); evs->push_back({e0, e1}); }
+    if (e0 && e1) e = hipEventRecord(e0, st);
+    if (e == hipSuccess) e = launch_update(B, pc, b, j, rd, st);
+    if (e == hipSuccess && e0 && e1) { e = hipEventRecord(e1, st); evs->push_back({e0, e1}); }
     if (n_update) (*n_update)++;
     return e;
   };
+  const bool la = s2 != nullptr && pool != nullptr;
+  hipEvent_t far_prev = nullptr;
   hipError_t e = launch_expand(B, s);
   int Pidx = 0;
   for (int pc = 0; pc < B.maxN && e == hipSuccess; pc += b, Pidx++) {
     for (int j = 0; j < b && pc + j < B.maxN && e == hipSuccess; j++) {
       const int c = pc + j;
-      if (j > 0) e = timed_update(pc, j, Pidx & 1);
+      if (j > 0) e = timed_update(pc, j, Pidx & 1, s);
       if (e == hipSuccess) e = launch_finalize(B, c, (Pidx + (j > 0 ? 1 : 0)) & 1, s);
       if (e == hipSuccess) e = launch_divide(B, c, s);
     }
-    if (e == hipSuccess && pc + b < B.maxN) e = timed_update(pc, 0, Pidx & 1);
+    if (e != hipSuccess || pc + b >= B.maxN) continue;
+    if (!la) {
+      e = timed_update(pc, 0, Pidx & 1, s);
+      continue;
+    }
+    // look-ahead: the rest of the trailing update leaves the critical path
+    hipEvent_t fork = get_ev();
+    if (!fork) return hipErrorOutOfMemory;
+    e = hipEventRecord(fork, s);                       // this panel's C and L are final
+    if (e == hipSuccess) e = hipStreamWaitEvent(s2, fork, 0);
+    if (e == hipSuccess) e = timed_update(pc, UPD_FAR, Pidx & 1, s2);
+    // the next panel's columns: their update by the previous panel is on s2
+    if (e == hipSuccess && far_prev) e = hipStreamWaitEvent(s, far_prev, 0);
+    if (e == hipSuccess) e = timed_update(pc, UPD_NEAR, Pidx & 1, s);
+    if (e == hipSuccess) {
+      far_prev = get_ev();
+      if (!far_prev) return hipErrorOutOfMemory;
+      e = hipEventRecord(far_prev, s2);
+    }
   }
+  if (e == hipSuccess && far_prev) e = hipStreamWaitEvent(s, far_prev, 0);
   return e;
 }
 
@@ -282,8 +317,9 @@ hk_status hk_build_matrix(int N, hk_rational beta, int prec_bits, void* dev_ws, 
   if (st == HK_OK) {
     // a panel width tuned for this shape (hk_autotune, cache named by HK_TUNE_CACHE)
     const hk_instance one = {N, beta, prec_bits};
-    const int p = hk::tuned_panel(&one, 1);
-    if (p > 0) (*out)->panel = p;
+    const hk::Schedule sc = hk::tuned_schedule(&one, 1);
+    if (sc.panel > 0) (*out)->panel = sc.panel;
+    (*out)->lookahead = sc.lookahead;
   }
   return st;
 }
@@ -347,9 +383,12 @@ extern "C" {
 hk_status hk_matrix_destroy(hk_matrix m) {
   if (!m) return HK_OK;
   for (auto& e : m->ev) (void)hipEventDestroy(e);
+  for (auto& e : m->gev) (void)hipEventDestroy(e);
   if (m->gexec) (void)hipGraphExecDestroy(m->gexec);
   if (m->graph) (void)hipGraphDestroy(m->graph);
   if (m->gcap) (void)hipStreamDestroy(m->gcap);
+  if (m->gcap2) (void)hipStreamDestroy(m->gcap2);
+  if (m->s2) (void)hipStreamDestroy(m->s2);
   delete m;
   return HK_OK;
 }
@@ -357,6 +396,11 @@ hk_status hk_matrix_destroy(hk_matrix m) {
 hk_status hk_set_panel(hk_matrix m, int panel) {
   if (!m || panel < 1 || panel > 64) return fail(HK_EINVAL, "panel must be in [1, 64]");
   m->panel = panel;
+  return HK_OK;
+}
+hk_status hk_set_lookahead(hk_matrix m, int mode) {
+  if (!m || mode < -1 || mode > 1) return fail(HK_EINVAL, "look-ahead mode must be -1, 0 or 1");
+  m->lookahead = mode;
   return HK_OK;
 }
 hk_status hk_set_timing(hk_matrix m, int on) {
@@ -411,9 +455,12 @@ hk_status hk_factor(hk_matrix m, hk_mpf shift, int inertia_mode, hipStream_t s, 
     size_t evi = 0;
     HK_HIP(launch_fill32(D.flags, 16, 0, s));
     HK_HIP(launch_fill32(D.flags + 1, 1, INT_MAX, s));
-    HK_HIP(enqueue_factor(m->B, b, s, &evs, &m->ev, &evi, &m->n_update));
+    const bool la = use_lookahead(m->lookahead, P.N, P.maxW);
+    if (!m->s2 && la) HK_HIP(hipStreamCreateWithFlags(&m->s2, hipStreamNonBlocking));
+    HK_HIP(enqueue_factor(m->B, b, s, la ? m->s2 : nullptr, &evs, &m->ev, &evi, &m->n_update));
   } else {
-    if (!m->gexec || m->gpanel != b) {
+    const bool la = use_lookahead(m->lookahead, P.N, P.maxW);
+    if (!m->gexec || m->gpanel != b || m->gla != (int)la) {
       if (m->gexec) { (void)hipGraphExecDestroy(m->gexec); m->gexec = nullptr; }
       if (m->graph) { (void)hipGraphDestroy(m->graph); m->graph = nullptr; }
       if (!m->gcap) HK_HIP(hipStreamCreateWithFlags(&m->gcap, hipStreamNonBlocking));
@@ -421,7 +468,9 @@ hk_status hk_factor(hk_matrix m, hk_mpf shift, int inertia_mode, hipStream_t s, 
       int nu = 0;
       hipError_t e = launch_fill32(D.flags, 16, 0, m->gcap);
       if (e == hipSuccess) e = launch_fill32(D.flags + 1, 1, INT_MAX, m->gcap);
-      if (e == hipSuccess) e = enqueue_factor(m->B, b, m->gcap, nullptr, nullptr, nullptr, &nu);
+      size_t evi = 0;
+      if (e == hipSuccess && !m->gcap2 && la) e = hipStreamCreateWithFlags(&m->gcap2, hipStreamNonBlocking);
+      if (e == hipSuccess) e = enqueue_factor(m->B, b, m->gcap, la ? m->gcap2 : nullptr, nullptr, &m->gev, &evi, &nu);
       hipGraph_t g = nullptr;
       const hipError_t e2 = hipStreamEndCapture(m->gcap, &g);
       m->graph = g;
@@ -429,6 +478,7 @@ hk_status hk_factor(hk_matrix m, hk_mpf shift, int inertia_mode, hipStream_t s, 
       if (e == hipSuccess) e = hipGraphInstantiate(&m->gexec, m->graph, nullptr, nullptr, 0);
       if (e != hipSuccess) return fail(HK_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
       m->gpanel = b;
+      m->gla = (int)la;
       m->g_nupdate = nu;
     }
     HK_HIP(hipGraphLaunch(m->gexec, s));

@@ -31,6 +31,8 @@ Batch::~Batch() {
   if (exec) (void)hipGraphExecDestroy(exec);
   if (graph) (void)hipGraphDestroy(graph);
   if (cap) (void)hipStreamDestroy(cap);
+  if (cap2) (void)hipStreamDestroy(cap2);
+  for (hipEvent_t ev : events) (void)hipEventDestroy(ev);
   for (auto m : mats) hk_matrix_destroy(m);
 }
 
@@ -117,19 +119,23 @@ hk_status build_batch(Batch& bt, const hk_instance* inst, int count, void* ws, s
 
 // capture (once per panel width) the launch sequence of one factorisation
 static hk_status ensure_graph(Batch& bt) {
-  if (bt.exec && bt.captured_panel == bt.panel) return HK_OK;
+  int maxW = 0;
+  for (const Plan* p : bt.B.plans) maxW = std::max(maxW, p->maxW);
+  const bool la = use_lookahead(bt.lookahead, bt.maxN, maxW);
+  if (bt.exec && bt.captured_panel == bt.panel && bt.captured_la == (int)la) return HK_OK;
   if (bt.exec) { (void)hipGraphExecDestroy(bt.exec); bt.exec = nullptr; }
   if (bt.graph) { (void)hipGraphDestroy(bt.graph); bt.graph = nullptr; }
   hipError_t e = hipSuccess;
   if (!bt.cap) e = hipStreamCreateWithFlags(&bt.cap, hipStreamNonBlocking);
+  if (e == hipSuccess && !bt.cap2 && la) e = hipStreamCreateWithFlags(&bt.cap2, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipStreamBeginCapture(bt.cap, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_reset_flags, dim3((bt.count * 16 + 255) / 256), dim3(256), 0, bt.cap, bt.flags,
                        bt.count);
     e = hipGetLastError();
     size_t evi = 0;
-    std::vector<hipEvent_t> pool;
-    if (e == hipSuccess) e = enqueue_factor(bt.B, bt.panel, bt.cap, nullptr, &pool, &evi, nullptr);
+    if (e == hipSuccess)
+      e = enqueue_factor(bt.B, bt.panel, bt.cap, la ? bt.cap2 : nullptr, nullptr, &bt.events, &evi, nullptr);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(bt.cap, &g);
     if (e == hipSuccess) e = e2;
@@ -138,6 +144,7 @@ static hk_status ensure_graph(Batch& bt) {
   if (e == hipSuccess) e = hipGraphInstantiate(&bt.exec, bt.graph, nullptr, nullptr, 0);
   if (e != hipSuccess) return dfail_b(HK_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
   bt.captured_panel = bt.panel;
+  bt.captured_la = (int)la;
   return HK_OK;
 }
 
@@ -207,17 +214,20 @@ static std::string tune_key(const hk_instance* inst, int count) {
   return os.str();
 }
 
-static int cached_panel(const std::string& key) {
+static Schedule cached_schedule(const std::string& key) {
+  Schedule sc;
   const char* path = getenv("HK_TUNE_CACHE");
-  if (!path) return 0;
+  if (!path) return sc;
   std::ifstream f(path);
   std::string line;
-  int best = 0;
   while (std::getline(f, line)) {
-    size_t bar = line.find(" | panel=");
-    if (bar != std::string::npos && line.substr(0, bar) == key) best = atoi(line.c_str() + bar + 9);
+    const size_t bar = line.find(" | panel=");
+    if (bar == std::string::npos || line.substr(0, bar) != key) continue;
+    sc.panel = atoi(line.c_str() + bar + 9);
+    const size_t la = line.find(" la=", bar);
+    sc.lookahead = la == std::string::npos ? -1 : atoi(line.c_str() + la + 4);
   }
-  return best;
+  return sc;
 }
 
 // the paper's Secant iteration is reused from hk_drivers.cpp through this
@@ -238,7 +248,7 @@ size_t batch_bytes(const hk_instance* inst, int count) {
   return total;
 }
 
-int tuned_panel(const hk_instance* inst, int count) { return cached_panel(tune_key(inst, count)); }
+Schedule tuned_schedule(const hk_instance* inst, int count) { return cached_schedule(tune_key(inst, count)); }
 
 }  // namespace hk
 
@@ -254,8 +264,11 @@ hk_status hk_eig_batched(const hk_instance* inst, int count, int digits, int pan
   Batch bt;
   hk_status st = build_batch(bt, inst, count, dev_ws, ws_bytes, s);
   if (st != HK_OK) return st;
-  bt.panel = panel > 0 ? panel : tuned_panel(inst, count);
-  if (bt.panel <= 0) bt.panel = 4;
+  {
+    const Schedule sc = tuned_schedule(inst, count);
+    bt.panel = panel > 0 ? panel : (sc.panel > 0 ? sc.panel : 4);
+    bt.lookahead = sc.lookahead;
+  }
   auto t1 = std::chrono::steady_clock::now();
   std::vector<SecantRun*> sm(count);
   for (int i = 0; i < count; i++) {
@@ -326,7 +339,7 @@ hk_status hk_eig_batched(const hk_instance* inst, int count, int digits, int pan
 }
 
 hk_status hk_autotune(const hk_instance* inst, int count, void* dev_ws, size_t ws_bytes,
-                      hipStream_t s, const char* cache_path, int* best_panel) {
+                      hipStream_t s, const char* cache_path, int* best_panel, int* best_lookahead) {
   if (!inst || count < 1 || !best_panel) return dfail_b(HK_EINVAL, "bad arguments");
   Batch bt;
   hk_status st = build_batch(bt, inst, count, dev_ws, ws_bytes, s);
@@ -336,22 +349,26 @@ hk_status hk_autotune(const hk_instance* inst, int count, void* dev_ws, size_t w
   std::vector<BEval> ev;
   const int cand[] = {1, 2, 4, 8, 16};
   double best_ms = 1e300;
-  int best = 4;
-  for (int b : cand) {
-    bt.panel = b;
-    st = factor_batch(bt, x, act, s, ev, false);   // capture + warm up
-    if (st != HK_OK) return st;
-    auto t0 = std::chrono::steady_clock::now();
-    st = factor_batch(bt, x, act, s, ev, false);
-    if (st != HK_OK) return st;
-    const double ms = 1e3 * std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    if (ms < best_ms) { best_ms = ms; best = b; }
+  int best = 4, best_la = 0;
+  for (int la = 0; la <= 1; la++) {
+    for (int b : cand) {
+      bt.panel = b;
+      bt.lookahead = la;
+      st = factor_batch(bt, x, act, s, ev, false);   // capture + warm up
+      if (st != HK_OK) return st;
+      auto t0 = std::chrono::steady_clock::now();
+      st = factor_batch(bt, x, act, s, ev, false);
+      if (st != HK_OK) return st;
+      const double ms = 1e3 * std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      if (ms < best_ms) { best_ms = ms; best = b; best_la = la; }
+    }
   }
   *best_panel = best;
+  if (best_lookahead) *best_lookahead = best_la;
   if (cache_path) {
     std::ofstream f(cache_path, std::ios::app);
     if (!f) return dfail_b(HK_EINVAL, "cannot write the tuning cache");
-    f << tune_key(inst, count) << " | panel=" << best << " ms=" << best_ms << "\n";
+    f << tune_key(inst, count) << " | panel=" << best << " la=" << best_la << " ms=" << best_ms << "\n";
   }
   return HK_OK;
 }

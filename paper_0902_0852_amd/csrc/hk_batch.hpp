@@ -11,6 +11,7 @@ namespace hk {
 
 struct Batch {
   int count = 0, maxN = 0, ld = 0, panel = 4;
+  int lookahead = -1, captured_la = -1;   // -1: chosen by size
   std::vector<hk_matrix> mats;
   std::vector<InstDesc> hdesc;
   InstDesc* ddesc = nullptr;
@@ -18,7 +19,8 @@ struct Batch {
   int32_t* piv = nullptr;
   SweepArgs* sargs = nullptr;   // per-instance solve arguments (batched inverse iteration)
   BatchView B;
-  hipStream_t cap = nullptr;
+  hipStream_t cap = nullptr, cap2 = nullptr;   // capture streams (critical path, look-ahead)
+  std::vector<hipEvent_t> events;              // fork/join points of the captured graph
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int captured_panel = 0;

@@ -619,6 +619,8 @@ hk_status hk_smallest_eig(int N, hk_rational beta, int prec_bits, int method, in
   if (flags & HK_FLAG_TIME_UPDATES) hk_set_timing(m, 1);
   const int forced_panel = (flags >> 16) & 0xff;
   if (forced_panel > 0) hk_set_panel(m, forced_panel);
+  if (flags & HK_FLAG_LOOKAHEAD_ON) hk_set_lookahead(m, 1);
+  if (flags & HK_FLAG_LOOKAHEAD_OFF) hk_set_lookahead(m, 0);
   MP lam;
   int solves = 0;
   if (method == HK_SECANT) {

@@ -62,8 +62,11 @@ struct Plan {
 };
 
 bool make_plan(int N, int64_t bnum, int64_t bden, int K, Plan& P, std::string& err);
-// panel width from the tuning cache (HK_TUNE_CACHE) for this batch shape, else 0
-int tuned_panel(const hk_instance* inst, int count);
+bool use_lookahead(int setting, int maxN, int maxW);
+// panel width (0: none) and look-ahead (-1: none) from the tuning cache
+// named by HK_TUNE_CACHE for this batch shape
+struct Schedule { int panel = 0, lookahead = -1; };
+Schedule tuned_schedule(const hk_instance* inst, int count);
 
 bool reduce_beta(int64_t num, int64_t den, uint32_t* p, uint32_t* q);
 double log2_mu(int n, uint32_t p, uint32_t q);
@@ -119,13 +122,21 @@ hipError_t launch_fill32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_fill64(int64_t* p, int64_t n, hipStream_t s);
 hipError_t launch_expand(const BatchView& B, hipStream_t s);
 // j = 0: trailing update after the panel [pc, pc + b); j > 0: in-panel
-// (left-looking) update of column pc + j by columns [pc, pc + j)
+// (left-looking) update of column pc + j by columns [pc, pc + j);
+// UPD_NEAR / UPD_FAR: the trailing update split into the next panel's columns
+// [pc + b, pc + 2b) and the rest (look-ahead)
+constexpr int UPD_NEAR = -1, UPD_FAR = -2;
 hipError_t launch_update(const BatchView& B, int pc, int b, int j, int rd, hipStream_t s);
 hipError_t launch_finalize(const BatchView& B, int c, int rd, hipStream_t s);
 hipError_t launch_divide(const BatchView& B, int c, hipStream_t s);
 hipError_t launch_gather_pivots_b(const BatchView& B, int32_t* out, int ld, hipStream_t s);
 int64_t update_items(const Plan& P, int pc, int b, int j);
-hipError_t enqueue_factor(const BatchView& B, int b, hipStream_t s,
+// One factorisation of every instance of B, enqueued on s.  With a second
+// stream s2 (may be null) the trailing update of each panel is split: the
+// next panel's columns are updated on s, on the critical path, the rest on
+// s2 concurrently with the next panel (look-ahead); s2 is joined into s at
+// the end.  evs: optional HIP-event pairs around every update launch.
+hipError_t enqueue_factor(const BatchView& B, int b, hipStream_t s, hipStream_t s2,
                           std::vector<std::pair<hipEvent_t, hipEvent_t>>* evs,
                           std::vector<hipEvent_t>* pool, size_t* evi, int* n_update);
 hipError_t launch_bits(const Plan& P, const DevPtrs& D, hipStream_t s);
@@ -187,12 +198,14 @@ struct hk_matrix_s {
   int gbits = 0;            // solve guard bits from the actual largest moment
   hk::InstDesc desc_host;
   hk::BatchView B;          // this matrix as a batch of one
-  std::vector<hipEvent_t> ev;
+  std::vector<hipEvent_t> ev;    // per-launch timing and eager look-ahead points
+  std::vector<hipEvent_t> gev;   // look-ahead points of the captured graph
   // the launch sequence of one factorisation, captured once per panel width
   // and replayed by hk_factor when per-launch timing is off
-  hipStream_t gcap = nullptr;
+  hipStream_t gcap = nullptr, gcap2 = nullptr, s2 = nullptr;   // capture streams; look-ahead stream
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
-  int gpanel = 0, g_nupdate = 0;
+  int gpanel = 0, gla = -1, g_nupdate = 0;
+  int lookahead = -1;       // -1: chosen by size, 0 / 1: off / on
 };
 

@@ -190,15 +190,18 @@ __device__ __forceinline__ void apply_block(const int64_t* acc, int32_t* Ap, int
 // (column pc+j, k in [pc, pc+j)); false if the instance has nothing to do
 __host__ __device__ inline bool update_range(int N, int pc, int b, int j, int& k0, int& k1, int& c_lo,
                                             int& c_hi) {
-  if (j == 0) {
-    const int bb = min(b, N - pc);
-    if (bb <= 0 || pc + bb >= N) return false;
-    k0 = pc; k1 = pc + bb; c_lo = pc + bb; c_hi = N;
-  } else {
+  if (j > 0) {
     if (pc + j >= N) return false;
     k0 = pc; k1 = pc + j; c_lo = pc + j; c_hi = pc + j + 1;
+    return true;
   }
-  return true;
+  const int bb = min(b, N - pc);
+  if (bb <= 0 || pc + bb >= N) return false;
+  k0 = pc; k1 = pc + bb;
+  if (j == UPD_NEAR) { c_lo = pc + bb; c_hi = min(N, pc + 2 * bb); }
+  else if (j == UPD_FAR) { c_lo = min(N, pc + 2 * bb); c_hi = N; }
+  else { c_lo = pc + bb; c_hi = N; }
+  return c_lo < c_hi;
 }
 
 // Rank-(k1-k0) update of the columns [c_lo, c_hi) of every instance:

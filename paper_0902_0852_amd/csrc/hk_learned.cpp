@@ -75,8 +75,11 @@ hk_status run_entries(std::vector<Entry>& E, const hk_instance* inst, int digits
   Batch bt;
   hk_status st = build_batch(bt, bi.data(), n, ws, ws_bytes, s);
   if (st != HK_OK) return st;
-  bt.panel = panel > 0 ? panel : tuned_panel(bi.data(), n);
-  if (bt.panel <= 0) bt.panel = 4;
+  {
+    const Schedule sc = tuned_schedule(bi.data(), n);
+    bt.panel = panel > 0 ? panel : (sc.panel > 0 ? sc.panel : 4);
+    bt.lookahead = sc.lookahead;
+  }
   std::vector<MP> x(n);
   std::vector<int> act(n, 1);
   for (int j = 0; j < n; j++) x[j] = E[j].sigma;
@@ -129,7 +132,10 @@ extern "C" {
 
 size_t hk_learned_workspace_bytes(const hk_instance* inst, int count, const int* bits_hat) {
   if (!inst || !bits_hat || count < 1) return 0;
-  std::vector<hk_instance> first;
+  // pass 0: every instance at b and 1.25 b; escalations: at most every
+  // instance once more, at a precision <= 1.25^3 b (capped by prec_bits);
+  // fallback: one instance at a time at prec_bits
+  std::vector<hk_instance> first, later;
   for (int i = 0; i < count; i++) {
     const int b = even_bits(bits_hat[i]);
     const int b2 = even_bits(1.25 * b);
@@ -139,12 +145,19 @@ size_t hk_learned_workspace_bytes(const hk_instance* inst, int count, const int*
     first.push_back(a);
     a.prec_bits = b2;
     first.push_back(a);
+    a.prec_bits = std::min(inst[i].prec_bits, even_bits(1.25 * even_bits(1.25 * b2)));
+    later.push_back(a);
   }
-  size_t need = batch_bytes(inst, count);
-  if (need == 0) return 0;
-  if (!first.empty()) need = std::max(need, batch_bytes(first.data(), (int)first.size()));
-  for (int i = 0; i < count; i++)
-    need = std::max(need, hk_workspace_bytes(inst[i].N, inst[i].beta, inst[i].prec_bits, 0));
+  size_t need = 0;
+  if (!first.empty()) {
+    need = std::max(batch_bytes(first.data(), (int)first.size()), batch_bytes(later.data(), (int)later.size()));
+    if (need == 0) return 0;
+  }
+  for (int i = 0; i < count; i++) {
+    const size_t one = hk_workspace_bytes(inst[i].N, inst[i].beta, inst[i].prec_bits, 0);
+    if (one == 0) return 0;
+    need = std::max(need, one);
+  }
   return need;
 }
 
@@ -164,8 +177,11 @@ hk_status hk_bracket_batched(const hk_instance* inst, int count, const char* con
   Batch bt;
   hk_status st = build_batch(bt, inst, count, dev_ws, ws_bytes, s);
   if (st != HK_OK) return st;
-  bt.panel = panel > 0 ? panel : tuned_panel(inst, count);
-  if (bt.panel <= 0) bt.panel = 4;
+  {
+    const Schedule sc = tuned_schedule(inst, count);
+    bt.panel = panel > 0 ? panel : (sc.panel > 0 ? sc.panel : 4);
+    bt.lookahead = sc.lookahead;
+  }
   std::vector<int> act(count, 1);
   std::vector<BEval> elo, ehi;
   st = factor_batch(bt, xlo, act, s, elo, false);

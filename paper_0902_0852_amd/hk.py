@@ -21,6 +21,9 @@ HK_FLAG_NO_WORK_COUNT, HK_FLAG_TIME_UPDATES = 0x100, 0x200
 def HK_FLAG_PANEL(p):
     """Panel width forced for smallest_eig (or-ed into flags)."""
     return (p & 0xff) << 16
+
+
+HK_FLAG_LOOKAHEAD_ON, HK_FLAG_LOOKAHEAD_OFF = 0x1000000, 0x2000000
 STATUS = {0: "HK_OK", 1: "HK_EINVAL", 2: "HK_ENOTSPD", 3: "HK_EPRECISION", 4: "HK_ENOCONV",
           5: "HK_EVERIFY", 6: "HK_EDEVICE", 7: "HK_ENOMEM"}
 
@@ -86,7 +89,7 @@ _lib = None
 # every symbol that include/hk.h declares
 EXPORTS = ["hk_workspace_bytes", "hk_build_matrix", "hk_factor", "hk_solve", "hk_smallest_eig",
            "hk_matrix_destroy", "hk_last_error", "hk_matrix_info", "hk_set_panel", "hk_set_timing",
-           "hk_factor_export", "hk_factor_limb_macs", "hk_vec_import", "hk_vec_export",
+           "hk_factor_export", "hk_factor_limb_macs", "hk_vec_import", "hk_vec_export", "hk_set_lookahead",
            "hk_batch_workspace_bytes", "hk_eig_batched", "hk_autotune",
            "hk_mlp_nparams", "hk_mlp_cache_floats", "hk_mlp_forward", "hk_mlp_backward", "hk_mlp_mse",
            "hk_mlp_adam_step", "hk_mlp_propose", "hk_bracket_batched", "hk_learned_workspace_bytes",
@@ -120,6 +123,8 @@ def lib():
         L.hk_set_panel.argtypes = [P, I]
         L.hk_set_timing.restype = I
         L.hk_set_timing.argtypes = [P, I]
+        L.hk_set_lookahead.restype = I
+        L.hk_set_lookahead.argtypes = [P, I]
         L.hk_factor_export.restype = I64
         L.hk_factor_export.argtypes = [P, I, I, I, P, P, P, I64, P]
         L.hk_factor_limb_macs.restype = I
@@ -133,7 +138,7 @@ def lib():
         L.hk_eig_batched.restype = I
         L.hk_eig_batched.argtypes = [P, I, I, I, P, SZ, P, P, ctypes.POINTER(BatchReport)]
         L.hk_autotune.restype = I
-        L.hk_autotune.argtypes = [P, I, P, SZ, P, ctypes.c_char_p, ctypes.POINTER(I)]
+        L.hk_autotune.argtypes = [P, I, P, SZ, P, ctypes.c_char_p, ctypes.POINTER(I), ctypes.POINTER(I)]
         F = ctypes.c_float
         L.hk_mlp_nparams.restype = I
         L.hk_mlp_nparams.argtypes = []
@@ -247,6 +252,9 @@ class Matrix:
 
     def set_timing(self, on):
         _check(lib().hk_set_timing(self.h, 1 if on else 0))
+
+    def set_lookahead(self, mode):
+        _check(lib().hk_set_lookahead(self.h, mode))
 
     def info(self):
         inf = Info()
@@ -402,16 +410,17 @@ def eig_batched(insts, digits=45, panel=0, stream=None, ws=None):
 
 
 def autotune(insts, cache_path=None, stream=None, ws=None):
+    """(panel width, look-ahead) fastest for this batch shape."""
     import torch
     L = lib()
     arr = _instances(insts)
     nbytes = L.hk_batch_workspace_bytes(ctypes.cast(arr, ctypes.c_void_p), len(insts))
     ws = ws if ws is not None else torch.empty(nbytes, dtype=torch.uint8, device="cuda")
-    best = ctypes.c_int(0)
+    best, best_la = ctypes.c_int(0), ctypes.c_int(0)
     _check(L.hk_autotune(ctypes.cast(arr, ctypes.c_void_p), len(insts), ctypes.c_void_p(ws.data_ptr()),
                          ws.numel(), _stream(stream),
-                         cache_path.encode() if cache_path else None, ctypes.byref(best)))
-    return best.value
+                         cache_path.encode() if cache_path else None, ctypes.byref(best), ctypes.byref(best_la)))
+    return best.value, best_la.value
 
 
 # ---- precision-proposal network (float32 device tensors) ----------------

@@ -137,3 +137,48 @@ def test_graph_replays_equal_eager_and_oracle(hk):
     m.set_panel(2)          # recapture at another width
     m.factor(shifts[0])
     compare(m, ref[shifts[0]], N)
+
+
+@pytest.mark.parametrize("panel", [1, 3, 8])
+def test_lookahead_on_off_equal_oracle(hk, panel):
+    """The look-ahead schedule (next panel's columns first, the rest of the
+    trailing update on a second stream) gives the same digits as one trailing
+    update per panel, eager and through graph replays."""
+    N, beta, K = 97, (5, 3), 768
+    X = moments(N, beta, K)
+    ref = oracle.factor_from_moments(X, N, K, 0)
+    m = hk.Matrix(N, beta, K)
+    m.set_panel(panel)
+    for la in (1, 0, 1):
+        for timing in (1, 0, 0):
+            log("look-ahead %d panel %d timing %d" % (la, panel, timing))
+            m.set_lookahead(la)
+            m.set_timing(timing)
+            m.factor(0)
+            compare(m, ref, N)
+
+
+EDGE = [
+    # degenerate and boundary sizes: one entry, two entries, one full tile,
+    # one tile plus one row, the smallest precision
+    (1, (1, 1), 64, 0, 4),
+    (1, (3, 2), 128, 1, 1),
+    (2, (1, 2), 96, 0, 2),
+    (64, (2, 1), 64 * 9, 0, 4),
+    (65, (1, 1), 640, 0, 3),
+    (12, (1, 1), 64, 0, 1),
+]
+
+
+@pytest.mark.parametrize("N,beta,K,xn,panel", EDGE)
+def test_edge_sizes_vs_oracle(hk, N, beta, K, xn, panel):
+    log("edge N=%d beta=%s K=%d x=%d*2^-(K/2) panel=%d" % (N, beta, K, xn, panel))
+    X = moments(N, beta, K)
+    xf = xn << (K - K // 2)
+    of = oracle.factor_from_moments(X, N, K, xf)
+    m = hk.Matrix(N, beta, K)
+    m.set_panel(panel)
+    st, nneg, fb = m.factor(xf, inertia_mode=1, raise_on_error=False)
+    assert (nneg, fb) == (of.n_negative, of.first_nonpos)
+    if fb < 0 or fb == N - 1:
+        compare(m, of, N)
