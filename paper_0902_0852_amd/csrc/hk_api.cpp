@@ -244,8 +244,7 @@ hipError_t enqueue_factor(const BatchView& B, int b, hipStream_t s, hipStream_t 
     for (int j = 0; j < b && pc + j < B.maxN && e == hipSuccess; j++) {
       const int c = pc + j;
       if (j > 0) e = timed_update(pc, j, Pidx & 1, s);
-      if (e == hipSuccess) e = launch_finalize(B, c, (Pidx + (j > 0 ? 1 : 0)) & 1, s);
-      if (e == hipSuccess) e = launch_divide(B, c, s);
+      if (e == hipSuccess) e = launch_fdiv(B, c, (Pidx + (j > 0 ? 1 : 0)) & 1, s);
     }
     if (e != hipSuccess || pc + b >= B.maxN) continue;
     if (!la) {

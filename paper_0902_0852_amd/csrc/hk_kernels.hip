@@ -444,62 +444,31 @@ __device__ FinOut wave_finalize(const int32_t* Ap, int64_t as, int W, const int6
   return f;
 }
 
-// Column c after all its updates: C = RNE(A / 2^h) for every row (balanced
-// digits for the update, standard magnitude digits for the division); the
-// pivot row also stores |d| 2^sh normalised for the division.  One 64-lane
-// workgroup per (instance, row).
-__global__ void __launch_bounds__(64) k_finalize(const InstDesc* __restrict__ desc, int count, int c,
-                                                 int rd) {
-  extern __shared__ int64_t smem[];
-  int bid = blockIdx.x, inst = -1;
-  for (int i = 0; i < count; i++) {
-    const int n = max(0, desc[i].N - c);
-    if (bid < n) { inst = i; break; }
-    bid -= n;
-  }
-  if (inst < 0) return;
-  const InstDesc I = desc[inst];
-  if (!I.active) return;
-  const int N = I.N;
-  const int r = c + bid;
-  const ColInfo cc = I.cols[c];
-  const int lr = r - c;
-  int32_t* dg = (int32_t*)smem;
-  int32_t* ob = dg + (cc.W + 48);
-  int64_t* ca = (int64_t*)(ob + (cc.W + 48));
-  int64_t* cb = ca + (cc.W / WB + 8);
-  uint32_t* Srow = I.S + cc.soff + (int64_t)lr * cc.CW;
-  const FinOut f = wave_finalize(I.A + cc.aoff + lr, cc.R, cc.W,
-                                 I.Kc + cc.koff + (int64_t)rd * cc.nb * cc.R + lr, cc.R, I.h,
-                                 I.C + cc.coff + (int64_t)lr * cc.CW, Srow, cc.CW, I.flags, dg, ob, ca, cb);
-  if (threadIdx.x != 0) return;
-  const int64_t ti = tri_index(N, c, r);
-  I.nC[ti] = f.nbal;
-  I.nCs[ti] = f.neg ? -f.nstd : f.nstd;
-  I.b32C[ti] = (f.bits + 31) / 32;
-  if (r == c) {
-    if (f.nstd == 0 || f.neg) {
-      atomicMin(&I.flags[1], c);
-      if (f.nstd > 0 && f.neg) atomicAdd(&I.flags[2], 1);
-    }
-    if (f.nstd > 0) {
-      const int sh = 28 - (31 - __clz(f.topv));
-      uint32_t* Dp = I.D + cc.doff;
-      uint32_t carry = 0;
-      for (int i = 0; i < f.nstd; i++) {
-        const uint64_t x = ((uint64_t)Srow[i] << sh) | carry;
-        Dp[i] = (uint32_t)(x & (RADIX - 1));
-        carry = (uint32_t)(x >> DB);
-      }
-      I.dinfo[4 * c] = f.nstd;
-      I.dinfo[4 * c + 1] = sh;
-      I.dinfo[4 * c + 2] = f.neg;
-    } else {
-      I.dinfo[4 * c] = 0;
-      I.dinfo[4 * c + 1] = 0;
-      I.dinfo[4 * c + 2] = 0;
-    }
-  }
+// Quotient digits taken per pass over the remainder, zero positions kept
+// below position 0, and 64-position groups of divisor digits held in
+// registers by the bulk pass (larger divisors read them from LDS).
+constexpr int DQ = 8;
+constexpr int DOFF = DQ + 4;
+constexpr int DNIR = 4;
+
+// One bulk step of divide_entry for remainder position b + rel: subtract
+// sum_s q[s] dd[rel + s + 1 - DQ] and split the result into a digit in
+// [0, 2^29) and a carry for the position above (carry-save: the carry is
+// passed to the next lane, so no position needs a second writer).
+__device__ __forceinline__ void divide_bulk(int64_t* rem, int b, int rel, bool act, const int32_t* q,
+                                            const int32_t* ddv, int64_t& carry, int top_group,
+                                            int top_lane, int64_t& hi_top) {
+  const int lane = threadIdx.x & 63;
+  int64_t x = act ? rem[b + rel] : 0;
+#pragma unroll
+  for (int s = 0; s < DQ; s++) x += (int64_t)(-q[s]) * (int64_t)ddv[s];
+  const int64_t lo = x & (RADIX - 1);
+  const int64_t hi = x >> DB;
+  int64_t hin = __shfl_up(hi, 1);
+  if (lane == 0) hin = carry;
+  carry = __shfl(hi, 63);
+  if (act) rem[b + rel] = lo + hin;
+  if (top_group) hi_top = __shfl(hi, top_lane);
 }
 
 // out = RNE(+-|num| 2^h / |d|) for one 64-lane workgroup: schoolbook long
@@ -509,12 +478,17 @@ __global__ void __launch_bounds__(64) k_finalize(const InstDesc* __restrict__ de
 // quotient digit is estimated from the top three remainder digits against the
 // top three divisor digits in float64 (error < 1/2 + 2^-20), so quotient
 // digits are signed and the remainder stays within (1/2 + eps) |d|; the final
-// remainder decides the rounding (ties to even).  Writes `cap` balanced
+// remainder decides the rounding (ties to even).  The top DQ + 4 remainder
+// positions live in registers of every lane (identical in all lanes), where
+// DQ quotient digits are found one after another; then one pass over the
+// positions below subtracts all DQ multiples of the divisor at once, one
+// position per lane, with carry-save normalisation.  Writes `cap` balanced
 // digits to out[j * os] (zero filled) and returns the digit count.
-__device__ int divide_entry(int64_t* smem, const uint32_t* Sr, int ns, int negN,
+template <bool BLK = true>
+__device__ __forceinline__ int divide_entry(int64_t* smem, const uint32_t* Sr, int ns, int negN,
                             const uint32_t* Dp, int nd, int sh, int negd, int h, int32_t* out,
                             int64_t os, int cap, int32_t* out2, int64_t os2, int32_t* flags) {
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63;
   if (nd == 0) {
     for (int j = lane; j < cap; j += 64) { out[(int64_t)j * os] = 0; if (out2) out2[(int64_t)j * os2] = 0; }
     if (lane == 0) atomicOr(&flags[0], 4);
@@ -526,11 +500,11 @@ __device__ int divide_entry(int64_t* smem, const uint32_t* Sr, int ns, int negN,
     for (int j = lane; j < cap; j += 64) { out[(int64_t)j * os] = 0; if (out2) out2[(int64_t)j * os2] = 0; }
     return 0;
   }
-  int64_t* rem = smem;                       // nu + 3
+  int64_t* rem = smem + DOFF;                // positions -DOFF .. nu + 2
   int64_t* dd = rem + (nu + 3);              // nd + 1 (dd[nd] = 0)
   int64_t* qd = dd + (nd + 1);               // nu - nd + 2
   for (int i = lane; i <= nd; i += 64) dd[i] = i < nd ? (int64_t)Dp[i] : 0;
-  for (int s = lane; s < nu + 3; s += 64) {
+  for (int s = lane - DOFF; s < nu + 3; s += 64) {
     int64_t x = 0;
     if (s >= Sq && s < nu) {
       const int i = s - Sq;
@@ -540,68 +514,104 @@ __device__ int divide_entry(int64_t* smem, const uint32_t* Sr, int ns, int negN,
     }
     rem[s] = x;
   }
-  const int jmax = nu - nd;
+  const int jmax = __builtin_amdgcn_readfirstlane(nu - nd);
   for (int j = lane; j <= jmax + 1; j += 64) qd[j] = 0;
-  __syncthreads();
+  lds_sync<BLK>();
   const double R = (double)RADIX;
   const double D3 = (double)dd[nd - 1] * R * R + (nd >= 2 ? (double)dd[nd - 2] * R : 0.0) +
                     (nd >= 3 ? (double)dd[nd - 3] : 0.0);
-  const int64_t d1 = dd[nd - 1], d2 = nd >= 2 ? dd[nd - 2] : 0;
-  // The top of the remainder window, positions t-2 .. t+1 (t = j + nd), is
-  // kept in registers of every lane (w0 .. w3, identical in all lanes); the
-  // digits below t-2 live in LDS and take the bulk of each subtraction.
-  int t = jmax + nd;
-  int64_t w0 = t - 2 >= 0 ? rem[t - 2] : 0, w1 = rem[t - 1], w2 = rem[t], w3 = rem[t + 1];
-  int since = 0;
   const double invD = R / D3;   // quotient estimates by one multiply
-  for (int j = jmax; j >= 0; j--) {
-    t = j + nd;
-    w2 += w3 << DB;
-    w3 = 0;
-    int64_t cy = w0 >> DB;
-    w0 -= cy << DB;
-    w1 += cy;
-    cy = w1 >> DB;
-    w1 -= cy << DB;
-    w2 += cy;
-    const double T = (double)w2 * R * R + (double)w1 * R + (double)w0;
-    const int64_t qq = (int64_t)rint(T * invD);
-    if (lane == 0) qd[j] = qq;
-    w1 -= qq * d1;
-    w0 -= qq * d2;
-    // |qq| < 2^30 and divisor digits < 2^29: one 32 x 32 -> 64 multiply each
-    const int32_t q32 = (int32_t)qq;
-    if (qq != 0)
-      for (int i = lane; i < nd - 2; i += 64) rem[j + i] -= (int64_t)q32 * (int64_t)(int32_t)dd[i];
-    __syncthreads();
-    if (j == 0) break;
-    if (++since == 12) {
-      since = 0;
-      // one carry step on the LDS digits that stay below the next window
-      for (int s = j - 1 + lane; s <= t - 5; s += 64) {
-        const int64_t x = rem[s];
-        const int64_t c2 = x >> DB;
-        if (c2) {
-          atomicAdd((unsigned long long*)&rem[s], (unsigned long long)(-(c2 << DB)));
-          atomicAdd((unsigned long long*)&rem[s + 1], (unsigned long long)c2);
-        }
-      }
-      __syncthreads();
+  // top divisor digits for the register window: DT[m] = dd[nd - 1 - m]
+  int32_t DT[DQ + 2];
+#pragma unroll
+  for (int m = 0; m < DQ + 2; m++) DT[m] = nd - 1 - m >= 0 ? (int32_t)dd[nd - 1 - m] : 0;
+  // bulk positions of a pass: b + rel, rel = lane + 64 i in [0, nd - 3); the
+  // divisor digit that q[s] meets there is dd[rel + s + 1 - DQ], the same in
+  // every pass
+  const int nbulk = nd - 3;
+  const int NI = nbulk > 0 ? (nbulk + 63) / 64 : 0;
+  const int top_group = nbulk > 0 ? (nbulk - 1) / 64 : -1, top_lane = nbulk > 0 ? (nbulk - 1) & 63 : 0;
+  int32_t DDL[DNIR][DQ];
+#pragma unroll
+  for (int i = 0; i < DNIR; i++)
+#pragma unroll
+    for (int s = 0; s < DQ; s++) {
+      const int k = lane + 64 * i + s + 1 - DQ;
+      DDL[i][s] = (i < NI && k >= 0 && k < nd) ? (int32_t)dd[k] : 0;
     }
-    // slide the window down by one position
-    w3 = w2;
-    w2 = w1;
-    w1 = w0;
-    w0 = t - 3 >= 0 ? rem[t - 3] : 0;
+  // register window: W[x] holds remainder position T + 1 - x
+  int T = __builtin_amdgcn_readfirstlane(nu);
+  int64_t W[DQ + 4];
+#pragma unroll
+  for (int x = 0; x < DQ + 4; x++) W[x] = rem[T + 1 - x];
+  int j0 = jmax;
+  while (true) {
+    const int Qe = min(DQ, j0 + 1);
+    int32_t q[DQ];
+#pragma unroll
+    for (int s = 0; s < DQ; s++) {
+      q[s] = 0;
+      if (s < Qe) {
+        // quotient digit j0 - s: fold position t + 1 into t, carry t - 2 and
+        // t - 1 upward, estimate from t, t - 1, t - 2
+        W[s + 1] += W[s] << DB;
+        W[s] = 0;
+        int64_t cy = W[s + 3] >> DB;
+        W[s + 3] &= RADIX - 1;
+        W[s + 2] += cy;
+        cy = W[s + 2] >> DB;
+        W[s + 2] &= RADIX - 1;
+        W[s + 1] += cy;
+        // |W[s+1]| < 2^31 here, so the top two positions fit one int64
+        const int64_t top2 = (W[s + 1] << DB) + W[s + 2];
+        const double Tv = fma((double)top2, R, (double)(int32_t)W[s + 3]);
+        // |q| < 2^30 and divisor digits < 2^29: one 32 x 32 -> 64 multiply-add each
+        const int32_t qq = (int32_t)rint(Tv * invD);
+        q[s] = qq;
+#pragma unroll
+        for (int x = s + 2; x < DQ + 4; x++) W[x] += (int64_t)(-qq) * (int64_t)DT[x - s - 2];
+      }
+    }
+    {  // quotient digits j0 .. j0 - Qe + 1 to LDS, one lane each
+      int32_t v = q[0];
+#pragma unroll
+      for (int s = 1; s < DQ; s++) v = lane == s ? q[s] : v;
+      if (lane < Qe) qd[j0 - lane] = v;
+    }
+    // every position below the window: subtract the DQ multiples at once
+    const int b = j0 - DQ + 1;
+    int64_t carry = 0, hi_top = 0;
+#pragma unroll
+    for (int i = 0; i < DNIR; i++)
+      if (i < NI) divide_bulk(rem, b, lane + 64 * i, lane + 64 * i < nbulk, q, DDL[i], carry, i == top_group,
+                              top_lane, hi_top);
+    for (int i = DNIR; i < NI; i++) {
+      int32_t ddv[DQ];
+#pragma unroll
+      for (int s = 0; s < DQ; s++) {
+        const int k = lane + 64 * i + s + 1 - DQ;
+        ddv[s] = k < nd ? (int32_t)dd[k] : 0;
+      }
+      divide_bulk(rem, b, lane + 64 * i, lane + 64 * i < nbulk, q, ddv, carry, i == top_group, top_lane,
+                  hi_top);
+    }
+    W[DQ + 3] += hi_top;
+    lds_sync<BLK>();
+    if (j0 - DQ < 0) break;
+    T -= DQ;
+    j0 -= DQ;
+#pragma unroll
+    for (int x = 0; x < 4; x++) W[x] = W[x + DQ];
+#pragma unroll
+    for (int x = 4; x < DQ + 4; x++) W[x] = rem[T + 1 - x];
   }
-  // final remainder: window back to LDS (positions nd-2 .. nd+1)
+  // final remainder: window back to LDS (positions T - DQ - 2 .. T + 1,
+  // which cover nd - 2 .. nd + 1; those above nd are zero)
   if (lane == 0) {
-    if (nd - 2 >= 0) rem[nd - 2] = w0;
-    rem[nd - 1] = w1;
-    rem[nd] = w2;
-    rem[nd + 1] = w3;
+#pragma unroll
+    for (int x = 0; x < DQ + 4; x++) rem[T + 1 - x] = W[x];
   }
-  __syncthreads();
+  lds_sync<BLK>();
   if (lane == 0) {
     rem[nd] += rem[nd + 1] << DB;
     rem[nd + 1] = 0;
@@ -641,7 +651,7 @@ __device__ int divide_entry(int64_t* smem, const uint32_t* Sr, int ns, int negN,
     }
     qd[0] += adj;
   }
-  __syncthreads();
+  lds_sync<BLK>();
   // quotient digits -> balanced digits (one carry step suffices: |q| <= 2^30)
   const int nq = jmax + 2;
   int mytop = -1;
@@ -672,14 +682,28 @@ __device__ int divide_entry(int64_t* smem, const uint32_t* Sr, int ns, int negN,
   return wave_max(mytop) + 1;
 }
 
-// L_c[r] = RNE(C_c[r] 2^h / d_c), one row per 64-lane workgroup; written in
-// the column layout (for the trailing update and forward solves) and in the
-// row layout L^T (for backward solves).  Rows of every instance.
-__global__ void __launch_bounds__(64) k_divide(const InstDesc* __restrict__ desc, int count, int c) {
+// |d| 2^sh as standard digits, top digit in [2^28, 2^29): every output digit
+// takes its own input digit shifted up and the top bits of the one below
+__device__ __forceinline__ void normalise_divisor(const uint32_t* S, int n, int sh, uint32_t* out) {
+  for (int i = threadIdx.x & 63; i < n; i += 64) {
+    const uint32_t lo = i > 0 && sh > 0 ? S[i - 1] >> (DB - sh) : 0u;
+    out[i] = ((S[i] << sh) | lo) & (uint32_t)(RADIX - 1);
+  }
+}
+
+// Column c in one launch: C = RNE(A / 2^h) for every row r in [c, N) and
+// L = RNE(C 2^h / d) for r > c.  One 128-lane workgroup per (instance, row):
+// wavefront 0 finalises row r while wavefront 1 finalises the pivot row c
+// into LDS (the workgroup of row c writes the pivot out, with its normalised
+// divisor digits and the inertia flags), then wavefront 0 divides row r by
+// the pivot.  LDS: two finalisation regions of fin_bytes, the pivot's digits
+// (piv_bytes), the division.
+__global__ void __launch_bounds__(128) k_fdiv(const InstDesc* __restrict__ desc, int count, int c, int rd,
+                                              int fin_bytes, int piv_bytes) {
   extern __shared__ int64_t smem[];
   int bid = blockIdx.x, inst = -1;
   for (int i = 0; i < count; i++) {
-    const int n = max(0, desc[i].N - c - 1);
+    const int n = max(0, desc[i].N - c);
     if (bid < n) { inst = i; break; }
     bid -= n;
   }
@@ -687,17 +711,70 @@ __global__ void __launch_bounds__(64) k_divide(const InstDesc* __restrict__ desc
   const InstDesc I = desc[inst];
   if (!I.active) return;
   const int N = I.N;
-  const int r = c + 1 + bid;
+  const int r = c + bid, lr = r - c;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const ColInfo cc = I.cols[c];
+  const int W = cc.W;
+  char* base = (char*)smem;
+  int32_t* dg = (int32_t*)(base + wave * fin_bytes);
+  int32_t* ob = dg + (W + 48);
+  int64_t* ca = (int64_t*)(ob + (W + 48));
+  int64_t* cb = ca + (W / WB + 8);
+  int32_t* pC = (int32_t*)(base + 2 * fin_bytes);
+  uint32_t* pS = (uint32_t*)(pC + cc.CW);
+  uint32_t* pD = pS + cc.CW;
+  int* pinfo = (int*)(pD + cc.CW);           // pivot: standard digits, shift, sign
+  int64_t* dsm = (int64_t*)(base + 2 * fin_bytes + piv_bytes);
+  const int64_t* Kc = I.Kc + cc.koff + (int64_t)rd * cc.nb * cc.R;
+  uint32_t* Srow = I.S + cc.soff + (int64_t)lr * cc.CW;
+  FinOut f;
+  f.nstd = 0;
+  f.neg = 0;
+  if (wave == 0) {
+    f = wave_finalize<false>(I.A + cc.aoff + lr, cc.R, W, Kc + lr, cc.R, I.h,
+                             I.C + cc.coff + (int64_t)lr * cc.CW, Srow, cc.CW, I.flags, dg, ob, ca, cb);
+    const int64_t ti = tri_index(N, c, r);
+    if (lane == 0) {
+      I.nC[ti] = f.nbal;
+      I.nCs[ti] = f.neg ? -f.nstd : f.nstd;
+      I.b32C[ti] = (f.bits + 31) / 32;
+    }
+    if (r == c) {
+      const int sh = f.nstd > 0 ? 28 - (31 - __clz(f.topv)) : 0;
+      if (lane == 0) {
+        if (f.nstd == 0 || f.neg) {
+          atomicMin(&I.flags[1], c);
+          if (f.nstd > 0 && f.neg) atomicAdd(&I.flags[2], 1);
+        }
+        I.dinfo[4 * c] = f.nstd;
+        I.dinfo[4 * c + 1] = sh;
+        I.dinfo[4 * c + 2] = f.nstd > 0 ? f.neg : 0;
+      }
+      // this wavefront's own standard digits, written above by other lanes
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      normalise_divisor(Srow, f.nstd, sh, I.D + cc.doff);
+    }
+  } else if (r != c) {
+    const FinOut p = wave_finalize<false>(I.A + cc.aoff, cc.R, W, Kc, cc.R, I.h, pC, pS, cc.CW, I.flags,
+                                          dg, ob, ca, cb);
+    const int sh = p.nstd > 0 ? 28 - (31 - __clz(p.topv)) : 0;
+    lds_sync<false>();
+    normalise_divisor(pS, p.nstd, sh, pD);
+    if (lane == 0) {
+      pinfo[0] = p.nstd;
+      pinfo[1] = sh;
+      pinfo[2] = p.nstd > 0 ? p.neg : 0;
+    }
+  }
+  __syncthreads();
+  if (r == c || wave != 0) return;
   const ColInfo cr = I.cols[r];
-  const int64_t ti = tri_index(N, c, r);
-  const int nsg = I.nCs[ti];
-  const int lr = r - c;
-  const int n = divide_entry(smem, I.S + cc.soff + (int64_t)lr * cc.CW, nsg < 0 ? -nsg : nsg, nsg < 0,
-                             I.D + cc.doff, I.dinfo[4 * c], I.dinfo[4 * c + 1], I.dinfo[4 * c + 2], I.h,
-                             I.L + cc.loff + lr, cc.R, cc.LW, I.LT + cr.ltoff + c, cr.PT, I.flags);
-  if (threadIdx.x == 0) {
-    I.nL[ti] = n;
+  const int n = divide_entry<false>(dsm, Srow, f.nstd, f.neg, pD, pinfo[0], pinfo[1], pinfo[2], I.h,
+                                    I.L + cc.loff + lr, cc.R, cc.LW, I.LT + cr.ltoff + c, cr.PT, I.flags);
+  if (lane == 0) {
+    I.nL[tri_index(N, c, r)] = n;
     if (n > cc.LW - 2 * WB) atomicOr(&I.flags[0], 8);
   }
 }
@@ -1151,32 +1228,27 @@ hipError_t launch_update(const BatchView& B, int pc, int b, int j, int rd, hipSt
 static size_t fin_shm(int W) {
   return sizeof(int32_t) * 2 * (size_t)(W + 48) + sizeof(int64_t) * 2 * (size_t)(W / WB + 8);
 }
-hipError_t launch_finalize(const BatchView& B, int c, int rd, hipStream_t s) {
-  int64_t rows = 0;
-  int W = 0;
-  for (const Plan* p : B.plans)
-    if (c < p->N) { rows += p->N - c; W = std::max(W, p->cols[c].W); }
-  if (rows <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_finalize, dim3((unsigned)rows), dim3(64), fin_shm(W), s, B.ddesc,
-                     (int)B.plans.size(), c, rd);
-  return hipGetLastError();
-}
-// LDS of divide_entry: remainder nu + 3, divisor nd + 1, quotient nu - nd + 2
+// LDS of divide_entry: remainder DOFF + nu + 3, divisor nd + 1, quotient
+// nu - nd + 2
 static size_t divide_shm(int h, int num_cap, int den_cap) {
   const int Sq = (h + 28) / DB + 1;
   const int nu_max = Sq + num_cap + 1;
-  return sizeof(int64_t) * (size_t)((nu_max + 3) + (den_cap + 3) + (nu_max + 3));
+  return sizeof(int64_t) * (size_t)((DOFF + nu_max + 3) + (den_cap + 3) + (nu_max + 3));
 }
-hipError_t launch_divide(const BatchView& B, int c, hipStream_t s) {
+hipError_t launch_fdiv(const BatchView& B, int c, int rd, hipStream_t s) {
   int64_t rows = 0;
-  size_t shm = 0;
+  size_t fin = 0, piv = 0, div = 0;
   for (const Plan* p : B.plans)
-    if (c + 1 < p->N) {
-      rows += p->N - c - 1;
-      shm = std::max(shm, divide_shm(p->h, p->cols[c].CW, p->cols[c].W + 2));
+    if (c < p->N) {
+      const ColInfo& cc = p->cols[c];
+      rows += p->N - c;
+      fin = std::max(fin, fin_shm(cc.W));
+      piv = std::max(piv, (sizeof(uint32_t) * (3 * (size_t)cc.CW + 4) + 7) / 8 * 8);
+      div = std::max(div, divide_shm(p->h, cc.CW, cc.W + 2));
     }
   if (rows <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_divide, dim3((unsigned)rows), dim3(64), shm, s, B.ddesc, (int)B.plans.size(), c);
+  hipLaunchKernelGGL(k_fdiv, dim3((unsigned)rows), dim3(128), 2 * fin + piv + div, s, B.ddesc,
+                     (int)B.plans.size(), c, rd, (int)fin, (int)piv);
   return hipGetLastError();
 }
 hipError_t launch_gather_pivots_b(const BatchView& B, int32_t* out, int ld, hipStream_t s) {
