@@ -182,8 +182,9 @@ def main():
     ap.add_argument("--n-lo", type=int, default=50)
     ap.add_argument("--n-hi", type=int, default=400)
     ap.add_argument("--panel", type=int, default=0, help="panel width (0: tuned here / tuned or 4 in learned mode)")
-    ap.add_argument("--lookahead", type=int, default=-1, choices=[-1, 0, 1],
-                    help="with --panel: look-ahead off / on (-1: chosen by size)")
+    ap.add_argument("--lookahead", type=int, default=-1, choices=[-1, 0, 1, 2],
+                    help="with --panel: look-ahead mode 0 none, 1 second stream, 2 one launch per column "
+                         "(-1: chosen by size)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the method has no multi-GPU path in this "
@@ -210,10 +211,8 @@ def main():
         panel, la = hk.autotune([(N, beta, K)], cache_path=tune_path)
         log("tuned panel width %d, look-ahead %d" % (panel, la))
     pflag = hk.HK_FLAG_PANEL(panel)
-    if la == 1:
-        pflag |= hk.HK_FLAG_LOOKAHEAD_ON
-    elif la == 0:
-        pflag |= hk.HK_FLAG_LOOKAHEAD_OFF
+    pflag |= {0: hk.HK_FLAG_LOOKAHEAD_OFF, 1: hk.HK_FLAG_LOOKAHEAD_ON,
+              2: hk.HK_FLAG_LOOKAHEAD_FUSED}.get(la, 0)
     # untimed: work count (deterministic) and warmup
     dec, rep = hk.smallest_eig(N, beta, K, method=method, digits=45, ws=ws, flags=pflag)
     macs_per_step = rep["limb_macs"]

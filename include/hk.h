@@ -71,8 +71,9 @@ enum { HK_FLAG_NO_WORK_COUNT = 0x100,   /* skip the limb-MAC count (report 0)   
 /* panel width p in 1..64 forced for hk_smallest_eig: or HK_FLAG_PANEL(p)
    into the method argument (0: the tuned width, else 4) */
 #define HK_FLAG_PANEL(p) (((p) & 0xff) << 16)
-/* look-ahead forced on / off for hk_smallest_eig (see hk_set_lookahead) */
-enum { HK_FLAG_LOOKAHEAD_ON = 0x1000000, HK_FLAG_LOOKAHEAD_OFF = 0x2000000 };
+/* look-ahead mode forced for hk_smallest_eig (see hk_set_lookahead): 1, 0, 2 */
+enum { HK_FLAG_LOOKAHEAD_ON = 0x1000000, HK_FLAG_LOOKAHEAD_OFF = 0x2000000,
+       HK_FLAG_LOOKAHEAD_FUSED = 0x4000000 };
 
 typedef struct hk_matrix_s* hk_matrix;
 
@@ -161,11 +162,15 @@ hk_status hk_set_panel(hk_matrix m, int panel);
 /* Look-ahead ("The LDL^T Determinant Algorithm", parallel version: the next
    panel's columns are updated first): mode 1 splits every trailing update
    into the next panel's columns, on the critical path, and the rest, on a
-   second stream concurrently with the next panel; 0 keeps one trailing
-   update per panel; -1 (default) takes the tuned setting, else on when
-   N x widest column >= 100000 digits.  The environment variable
-   HK_LOOKAHEAD=0/1 overrides every setting.  The digits are the same
-   either way (exact updates). */
+   second stream concurrently with the next panel; mode 2 takes one launch
+   per column (panel width 1) in which each row's workgroup applies the
+   previous column's update to its own entry and the pivot's before
+   finalising and dividing, while further workgroups of the same launch
+   update the columns beyond; 0 keeps one trailing update per panel;
+   -1 (default) takes the tuned setting, else 1 when N x widest column
+   >= 100000 digits and 2 below.  The environment variable HK_LOOKAHEAD=0/1/2
+   overrides every setting.  The digits are the same in every mode (exact
+   updates).  HK_EINVAL for another mode. */
 hk_status hk_set_lookahead(hk_matrix m, int mode);
 /* Timing: when on, every launch of the update kernel in hk_factor (the
    in-panel and the trailing ones) is bracketed by HIP events on s and
@@ -236,7 +241,8 @@ hk_status hk_eig_batched(const hk_instance* inst, int count, int digits, int pan
                          size_t ws_bytes, hipStream_t s, hk_result* out, hk_batch_report* rep);
 
 /* Times one batched factorisation of the given batch for each panel width
-   in {1, 2, 4, 8, 16}, without and with look-ahead, stores the fastest in
+   in {1, 2, 4, 8, 16} under look-ahead modes 0 and 1, and once under mode 2
+   (width 1), stores the fastest in
    *best_panel and *best_lookahead (may be NULL) and appends them to the text
    cache file cache_path (NULL: no file) under the batch-shape key
    (architecture, count, N bucket, K bucket).  Synchronises s. */

@@ -28,15 +28,17 @@ static hk_status fail(hk_status st, const std::string& msg) { g_err = msg; retur
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 static int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
-// Whether the trailing update leaves the critical path (look-ahead):
-// HK_LOOKAHEAD=0/1 forces it; else the setting (0/1, from the caller or the
-// tuning cache); else on when a panel carries enough update work
-// (N x widest column >= 100000 digits), where the second stream pays off.
-bool use_lookahead(int setting, int maxN, int maxW) {
+// How the trailing update leaves the critical path (look-ahead mode): 0 none,
+// 1 the rest of each panel's update on a second stream, 2 one launch per
+// column with the next column's update inside it (panel width 1).
+// HK_LOOKAHEAD=0/1/2 forces it; else the setting (from the caller or the
+// tuning cache); else 1 when a panel carries enough update work
+// (N x widest column >= 100000 digits), 2 below that.
+int lookahead_mode(int setting, int maxN, int maxW) {
   const char* v = getenv("HK_LOOKAHEAD");
-  if (v && (v[0] == '0' || v[0] == '1')) return v[0] == '1';
-  if (setting == 0 || setting == 1) return setting == 1;
-  return (int64_t)maxN * maxW >= 100000;
+  if (v && v[0] >= '0' && v[0] <= '2' && v[1] == 0) return v[0] - '0';
+  if (setting >= 0 && setting <= 2) return setting;
+  return (int64_t)maxN * maxW >= 100000 ? 1 : 2;
 }
 
 bool make_plan(int N, int64_t bnum, int64_t bden, int K, Plan& P, std::string& err) {
@@ -213,7 +215,7 @@ void mp_to_digits(const MP& v, int32_t* out, int n) { to_digits(v, out, n); }
 // place): expansion, then per panel of b columns the in-panel updates,
 // finalisations and divisions column by column, then the trailing update.
 // With evs != NULL every update launch is bracketed by HIP events.
-hipError_t enqueue_factor(const BatchView& B, int b, hipStream_t s, hipStream_t s2,
+hipError_t enqueue_factor(const BatchView& B, int b, int mode, hipStream_t s, hipStream_t s2,
                           std::vector<std::pair<hipEvent_t, hipEvent_t>>* evs,
                           std::vector<hipEvent_t>* pool, size_t* evi, int* n_update) {
   // one pool of (timing-capable) events for both the per-launch timing and
@@ -236,9 +238,21 @@ hipError_t enqueue_factor(const BatchView& B, int b, hipStream_t s, hipStream_t 
     if (n_update) (*n_update)++;
     return e;
   };
-  const bool la = s2 != nullptr && pool != nullptr;
-  hipEvent_t far_prev = nullptr;
   hipError_t e = launch_expand(B, s);
+  if (mode == 2) {
+    // one launch per column; the update work rides in every launch
+    for (int c = 0; c < B.maxN && e == hipSuccess; c++) {
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (evs) { e0 = get_ev(); e1 = get_ev(); }
+      if (e0 && e1) e = hipEventRecord(e0, s);
+      if (e == hipSuccess) e = launch_column(B, c, s);
+      if (e == hipSuccess && e0 && e1) { e = hipEventRecord(e1, s); evs->push_back({e0, e1}); }
+      if (n_update) (*n_update)++;
+    }
+    return e;
+  }
+  const bool la = mode == 1 && s2 != nullptr && pool != nullptr;
+  hipEvent_t far_prev = nullptr;
   int Pidx = 0;
   for (int pc = 0; pc < B.maxN && e == hipSuccess; pc += b, Pidx++) {
     for (int j = 0; j < b && pc + j < B.maxN && e == hipSuccess; j++) {
@@ -398,7 +412,7 @@ hk_status hk_set_panel(hk_matrix m, int panel) {
   return HK_OK;
 }
 hk_status hk_set_lookahead(hk_matrix m, int mode) {
-  if (!m || mode < -1 || mode > 1) return fail(HK_EINVAL, "look-ahead mode must be -1, 0 or 1");
+  if (!m || mode < -1 || mode > 2) return fail(HK_EINVAL, "look-ahead mode must be -1, 0, 1 or 2");
   m->lookahead = mode;
   return HK_OK;
 }
@@ -454,12 +468,12 @@ hk_status hk_factor(hk_matrix m, hk_mpf shift, int inertia_mode, hipStream_t s, 
     size_t evi = 0;
     HK_HIP(launch_fill32(D.flags, 16, 0, s));
     HK_HIP(launch_fill32(D.flags + 1, 1, INT_MAX, s));
-    const bool la = use_lookahead(m->lookahead, P.N, P.maxW);
-    if (!m->s2 && la) HK_HIP(hipStreamCreateWithFlags(&m->s2, hipStreamNonBlocking));
-    HK_HIP(enqueue_factor(m->B, b, s, la ? m->s2 : nullptr, &evs, &m->ev, &evi, &m->n_update));
+    const int la = lookahead_mode(m->lookahead, P.N, P.maxW);
+    if (!m->s2 && la == 1) HK_HIP(hipStreamCreateWithFlags(&m->s2, hipStreamNonBlocking));
+    HK_HIP(enqueue_factor(m->B, b, la, s, la == 1 ? m->s2 : nullptr, &evs, &m->ev, &evi, &m->n_update));
   } else {
-    const bool la = use_lookahead(m->lookahead, P.N, P.maxW);
-    if (!m->gexec || m->gpanel != b || m->gla != (int)la) {
+    const int la = lookahead_mode(m->lookahead, P.N, P.maxW);
+    if (!m->gexec || m->gpanel != b || m->gla != la) {
       if (m->gexec) { (void)hipGraphExecDestroy(m->gexec); m->gexec = nullptr; }
       if (m->graph) { (void)hipGraphDestroy(m->graph); m->graph = nullptr; }
       if (!m->gcap) HK_HIP(hipStreamCreateWithFlags(&m->gcap, hipStreamNonBlocking));
@@ -468,8 +482,9 @@ hk_status hk_factor(hk_matrix m, hk_mpf shift, int inertia_mode, hipStream_t s, 
       hipError_t e = launch_fill32(D.flags, 16, 0, m->gcap);
       if (e == hipSuccess) e = launch_fill32(D.flags + 1, 1, INT_MAX, m->gcap);
       size_t evi = 0;
-      if (e == hipSuccess && !m->gcap2 && la) e = hipStreamCreateWithFlags(&m->gcap2, hipStreamNonBlocking);
-      if (e == hipSuccess) e = enqueue_factor(m->B, b, m->gcap, la ? m->gcap2 : nullptr, nullptr, &m->gev, &evi, &nu);
+      if (e == hipSuccess && !m->gcap2 && la == 1) e = hipStreamCreateWithFlags(&m->gcap2, hipStreamNonBlocking);
+      if (e == hipSuccess)
+        e = enqueue_factor(m->B, b, la, m->gcap, la == 1 ? m->gcap2 : nullptr, nullptr, &m->gev, &evi, &nu);
       hipGraph_t g = nullptr;
       const hipError_t e2 = hipStreamEndCapture(m->gcap, &g);
       m->graph = g;
@@ -477,7 +492,7 @@ hk_status hk_factor(hk_matrix m, hk_mpf shift, int inertia_mode, hipStream_t s, 
       if (e == hipSuccess) e = hipGraphInstantiate(&m->gexec, m->graph, nullptr, nullptr, 0);
       if (e != hipSuccess) return fail(HK_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
       m->gpanel = b;
-      m->gla = (int)la;
+      m->gla = la;
       m->g_nupdate = nu;
     }
     HK_HIP(hipGraphLaunch(m->gexec, s));

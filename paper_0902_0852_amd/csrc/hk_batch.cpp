@@ -121,13 +121,13 @@ hk_status build_batch(Batch& bt, const hk_instance* inst, int count, void* ws, s
 static hk_status ensure_graph(Batch& bt) {
   int maxW = 0;
   for (const Plan* p : bt.B.plans) maxW = std::max(maxW, p->maxW);
-  const bool la = use_lookahead(bt.lookahead, bt.maxN, maxW);
-  if (bt.exec && bt.captured_panel == bt.panel && bt.captured_la == (int)la) return HK_OK;
+  const int la = lookahead_mode(bt.lookahead, bt.maxN, maxW);
+  if (bt.exec && bt.captured_panel == bt.panel && bt.captured_la == la) return HK_OK;
   if (bt.exec) { (void)hipGraphExecDestroy(bt.exec); bt.exec = nullptr; }
   if (bt.graph) { (void)hipGraphDestroy(bt.graph); bt.graph = nullptr; }
   hipError_t e = hipSuccess;
   if (!bt.cap) e = hipStreamCreateWithFlags(&bt.cap, hipStreamNonBlocking);
-  if (e == hipSuccess && !bt.cap2 && la) e = hipStreamCreateWithFlags(&bt.cap2, hipStreamNonBlocking);
+  if (e == hipSuccess && !bt.cap2 && la == 1) e = hipStreamCreateWithFlags(&bt.cap2, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipStreamBeginCapture(bt.cap, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_reset_flags, dim3((bt.count * 16 + 255) / 256), dim3(256), 0, bt.cap, bt.flags,
@@ -135,7 +135,8 @@ static hk_status ensure_graph(Batch& bt) {
     e = hipGetLastError();
     size_t evi = 0;
     if (e == hipSuccess)
-      e = enqueue_factor(bt.B, bt.panel, bt.cap, la ? bt.cap2 : nullptr, nullptr, &bt.events, &evi, nullptr);
+      e = enqueue_factor(bt.B, bt.panel, la, bt.cap, la == 1 ? bt.cap2 : nullptr, nullptr, &bt.events, &evi,
+                         nullptr);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(bt.cap, &g);
     if (e == hipSuccess) e = e2;
@@ -144,7 +145,7 @@ static hk_status ensure_graph(Batch& bt) {
   if (e == hipSuccess) e = hipGraphInstantiate(&bt.exec, bt.graph, nullptr, nullptr, 0);
   if (e != hipSuccess) return dfail_b(HK_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
   bt.captured_panel = bt.panel;
-  bt.captured_la = (int)la;
+  bt.captured_la = la;
   return HK_OK;
 }
 
@@ -350,8 +351,9 @@ hk_status hk_autotune(const hk_instance* inst, int count, void* dev_ws, size_t w
   const int cand[] = {1, 2, 4, 8, 16};
   double best_ms = 1e300;
   int best = 4, best_la = 0;
-  for (int la = 0; la <= 1; la++) {
+  for (int la = 0; la <= 2; la++) {
     for (int b : cand) {
+      if (la == 2 && b != 1) continue;   // one column per launch: no panels
       bt.panel = b;
       bt.lookahead = la;
       st = factor_batch(bt, x, act, s, ev, false);   // capture + warm up

@@ -621,6 +621,7 @@ hk_status hk_smallest_eig(int N, hk_rational beta, int prec_bits, int method, in
   if (forced_panel > 0) hk_set_panel(m, forced_panel);
   if (flags & HK_FLAG_LOOKAHEAD_ON) hk_set_lookahead(m, 1);
   if (flags & HK_FLAG_LOOKAHEAD_OFF) hk_set_lookahead(m, 0);
+  if (flags & HK_FLAG_LOOKAHEAD_FUSED) hk_set_lookahead(m, 2);
   MP lam;
   int solves = 0;
   if (method == HK_SECANT) {

@@ -62,7 +62,7 @@ struct Plan {
 };
 
 bool make_plan(int N, int64_t bnum, int64_t bden, int K, Plan& P, std::string& err);
-bool use_lookahead(int setting, int maxN, int maxW);
+int lookahead_mode(int setting, int maxN, int maxW);
 // panel width (0: none) and look-ahead (-1: none) from the tuning cache
 // named by HK_TUNE_CACHE for this batch shape
 struct Schedule { int panel = 0, lookahead = -1; };
@@ -128,6 +128,7 @@ hipError_t launch_expand(const BatchView& B, hipStream_t s);
 constexpr int UPD_NEAR = -1, UPD_FAR = -2;
 hipError_t launch_update(const BatchView& B, int pc, int b, int j, int rd, hipStream_t s);
 hipError_t launch_fdiv(const BatchView& B, int c, int rd, hipStream_t s);
+hipError_t launch_column(const BatchView& B, int c, hipStream_t s);
 hipError_t launch_gather_pivots_b(const BatchView& B, int32_t* out, int ld, hipStream_t s);
 int64_t update_items(const Plan& P, int pc, int b, int j);
 // One factorisation of every instance of B, enqueued on s.  With a second
@@ -135,7 +136,7 @@ int64_t update_items(const Plan& P, int pc, int b, int j);
 // next panel's columns are updated on s, on the critical path, the rest on
 // s2 concurrently with the next panel (look-ahead); s2 is joined into s at
 // the end.  evs: optional HIP-event pairs around every update launch.
-hipError_t enqueue_factor(const BatchView& B, int b, hipStream_t s, hipStream_t s2,
+hipError_t enqueue_factor(const BatchView& B, int b, int mode, hipStream_t s, hipStream_t s2,
                           std::vector<std::pair<hipEvent_t, hipEvent_t>>* evs,
                           std::vector<hipEvent_t>* pool, size_t* evi, int* n_update);
 hipError_t launch_bits(const Plan& P, const DevPtrs& D, hipStream_t s);
@@ -205,6 +206,6 @@ struct hk_matrix_s {
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   int gpanel = 0, gla = -1, g_nupdate = 0;
-  int lookahead = -1;       // -1: chosen by size, 0 / 1: off / on
+  int lookahead = -1;       // -1: chosen by size, else the look-ahead mode 0 / 1 / 2
 };
 

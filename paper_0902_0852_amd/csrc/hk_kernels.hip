@@ -208,11 +208,11 @@ __host__ __device__ inline bool update_range(int N, int pc, int b, int j, int& k
 //   A_rc -= sum_{k0 <= k < k1} C_k[c] L_k[r]      (exact)
 // One wavefront per (instance, column, 64-row tile, 16-digit output block).
 // C_k[c] digits are wavefront-uniform; L_k[r] digits are per lane.
-__global__ void __launch_bounds__(256) k_update(const InstDesc* __restrict__ desc, int count, int pc,
-                                                int b, int j, int rd) {
-  const int wave = uni(threadIdx.x >> 6);
+// One item (wavefront), numbered `it` across the columns and instances of
+// the launch.
+__device__ __forceinline__ void update_item(const InstDesc* __restrict__ desc, int count, int pc, int b, int j,
+                                            int rd, int it) {
   const int lane = threadIdx.x & 63;
-  int it = blockIdx.x * 4 + wave;
   int inst = -1, k0 = 0, k1 = 0, c_lo = 0, c_hi = 0;
   for (int i = 0; i < count; i++) {
     int a0, a1, b0, b1;
@@ -262,6 +262,11 @@ __global__ void __launch_bounds__(256) k_update(const InstDesc* __restrict__ des
   apply_block(acc, I.A + cc.aoff + (int64_t)(WB * q) * cc.R + lr, cc.R,
               q > 0 ? Kcol + ((int64_t)rd * cc.nb + q) * cc.R + lr : nullptr,
               q + 1 < cc.nb ? Kcol + ((int64_t)(rd ^ 1) * cc.nb + q + 1) * cc.R + lr : nullptr, I.flags);
+}
+
+__global__ void __launch_bounds__(256) k_update(const InstDesc* __restrict__ desc, int count, int pc,
+                                                int b, int j, int rd) {
+  update_item(desc, count, pc, b, j, rd, blockIdx.x * 4 + uni(threadIdx.x >> 6));
 }
 
 struct FinOut {
@@ -333,7 +338,8 @@ __device__ int64_t wave_resolve(int32_t* x, int nblk, int64_t* cin, int64_t* cou
 template <bool BLK = true>
 __device__ FinOut wave_finalize(const int32_t* Ap, int64_t as, int W, const int64_t* Kp, int64_t ks,
                                 int h, int32_t* Cr, uint32_t* Sr, int cap, int32_t* flags,
-                                int32_t* dg, int32_t* ob, int64_t* ca, int64_t* cb) {
+                                int32_t* dg, int32_t* ob, int64_t* ca, int64_t* cb,
+                                const int64_t* Psub = nullptr) {
   const int lane = threadIdx.x & 63;
   const int nb = W / WB;
   // 1. load, block-local balanced normalisation, carries between blocks
@@ -345,6 +351,7 @@ __device__ FinOut wave_finalize(const int32_t* Ap, int64_t as, int W, const int6
 #pragma unroll
     for (int m = 0; m < WB; m++) {
       v += a[m];
+      if (Psub) v -= Psub[q * WB + m];
       const int32_t d = balanced29(v);
       dg[q * WB + m] = d;
       v = (v - d) >> DB;
@@ -444,12 +451,12 @@ __device__ FinOut wave_finalize(const int32_t* Ap, int64_t as, int W, const int6
   return f;
 }
 
-// Quotient digits taken per pass over the remainder, zero positions kept
-// below position 0, and 64-position groups of divisor digits held in
-// registers by the bulk pass (larger divisors read them from LDS).
+// Quotient digits taken per pass over the remainder and zero positions kept
+// below position 0.  divide_entry's DNIR is the number of 64-position groups
+// of divisor digits its bulk pass holds in registers (larger divisors read
+// the rest from LDS).
 constexpr int DQ = 8;
 constexpr int DOFF = DQ + 4;
-constexpr int DNIR = 4;
 
 // One bulk step of divide_entry for remainder position b + rel: subtract
 // sum_s q[s] dd[rel + s + 1 - DQ] and split the result into a digit in
@@ -484,7 +491,7 @@ __device__ __forceinline__ void divide_bulk(int64_t* rem, int b, int rel, bool a
 // positions below subtracts all DQ multiples of the divisor at once, one
 // position per lane, with carry-save normalisation.  Writes `cap` balanced
 // digits to out[j * os] (zero filled) and returns the digit count.
-template <bool BLK = true>
+template <bool BLK = true, int DNIR = 4>
 __device__ __forceinline__ int divide_entry(int64_t* smem, const uint32_t* Sr, int ns, int negN,
                             const uint32_t* Dp, int nd, int sh, int negd, int h, int32_t* out,
                             int64_t os, int cap, int32_t* out2, int64_t os2, int32_t* flags) {
@@ -772,6 +779,187 @@ __global__ void __launch_bounds__(128) k_fdiv(const InstDesc* __restrict__ desc,
   if (r == c || wave != 0) return;
   const ColInfo cr = I.cols[r];
   const int n = divide_entry<false>(dsm, Srow, f.nstd, f.neg, pD, pinfo[0], pinfo[1], pinfo[2], I.h,
+                                    I.L + cc.loff + lr, cc.R, cc.LW, I.LT + cr.ltoff + c, cr.PT, I.flags);
+  if (lane == 0) {
+    I.nL[tri_index(N, c, r)] = n;
+    if (n > cc.LW - 2 * WB) atomicOr(&I.flags[0], 8);
+  }
+}
+
+// Product digits per lane and pass of near_product, and the digits a pass covers.
+constexpr int PBD = 8;
+constexpr int PPASS = 64 * PBD;
+
+__device__ __forceinline__ void renorm_pbd(int64_t* acc) {
+#pragma unroll
+  for (int m = 0; m < PBD; m++) {
+    const int64_t hc = acc[m] >> DB;
+    acc[m] -= hc << DB;
+    acc[m + 1] += hc;
+  }
+}
+
+// P[0..W) = the digits of the exact product Lr * Cp by one wavefront, lazily
+// normalised (|P[s]| < 2^36).  Lr: nL balanced digits in LDS, zero padded to
+// a multiple of 8; Cp: nC balanced digits in LDS.  Lane l forms the output
+// digits [8 l, 8 l + 8) of each pass of 512 by operand scanning over Lr, with
+// the eight C digits it meets held in a ring of registers (one new digit per
+// step), then adds its carry into the digit above in a second phase.
+// A product wider than W digits sets bit 1 of flags[0], like an update that
+// overflows its entry.
+template <bool BLK>
+__device__ void near_product(const int32_t* Lr, int nL, const int32_t* Cp, int nC, int W, int64_t* P,
+                             int32_t* flags) {
+  const int lane = threadIdx.x & 63;
+  if (lane == 0 && nL > 0 && nC > 0 && nL + nC - 1 > W) atomicOr(&flags[0], 1);
+  for (int s = lane; s < W; s += 64) P[s] = 0;
+  lds_sync<BLK>();
+  if (nL <= 0 || nC <= 0) return;
+  const int nL8 = (nL + PBD - 1) / PBD * PBD;
+  for (int p0 = 0; p0 < W; p0 += PPASS) {
+    const int s0 = p0 + PBD * lane;
+    int64_t acc[PBD + 1];
+    int32_t ring[PBD];   // ring[(s0 + b - a) & 7] = C[s0 + b - a]
+#pragma unroll
+    for (int m = 0; m <= PBD; m++) acc[m] = 0;
+#pragma unroll
+    for (int b = 0; b < PBD; b++) ring[b] = s0 + b < nC ? Cp[s0 + b] : 0;
+    int cnt = 0;
+    for (int a0 = 0; a0 < nL8; a0 += PBD) {
+#pragma unroll
+      for (int u = 0; u < PBD; u++) {
+        const int a = a0 + u;
+        const int32_t la = Lr[a];
+#pragma unroll
+        for (int b = 0; b < PBD; b++) acc[b] += (int64_t)la * (int64_t)ring[(b - u) & (PBD - 1)];
+        const int idx = s0 - a - 1;
+        ring[(PBD - 1 - u) & (PBD - 1)] = idx >= 0 && idx < nC ? Cp[idx] : 0;
+      }
+      cnt += PBD;
+      if (cnt >= 96) { renorm_pbd(acc); cnt = 0; }
+    }
+    renorm_pbd(acc);
+#pragma unroll
+    for (int b = 0; b < PBD; b++)
+      if (s0 + b < W) P[s0 + b] += acc[b];
+    lds_sync<BLK>();
+    if (s0 + PBD < W) P[s0 + PBD] += acc[PBD];
+    else if (s0 < W && acc[PBD] != 0) atomicOr(&flags[0], 1);
+    lds_sync<BLK>();
+  }
+}
+
+// One launch per column c (the in-kernel look-ahead schedule, rank-1
+// updates): workgroups [0, n_near) handle the rows r in [c, N) of column c
+// like k_fdiv, each first subtracting the update of its entry, and of the
+// pivot entry, by column c - 1 (L_{c-1}[r] C_{c-1}[c], formed in LDS) while
+// loading the accumulator; the remaining workgroups apply the update by
+// column c - 1 to the columns [c + 1, N), two items each.  The next launch
+// finds every column it needs complete.  LDS: the pivot's digits
+// (piv_bytes), then either the two product + finalisation regions
+// (fin_bytes each) or the division.  Three waves per SIMD (at most 168
+// registers, two divisor groups in registers) keep the update workgroups of
+// the launch from starving for occupancy.
+__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3)))
+k_column(const InstDesc* __restrict__ desc, int count, int c, int n_near, int fin_bytes, int piv_bytes) {
+  if ((int)blockIdx.x >= n_near) {
+    if (c > 0)
+      update_item(desc, count, c - 1, 1, UPD_FAR, (c - 1) & 1,
+                  ((int)blockIdx.x - n_near) * 2 + uni(threadIdx.x >> 6));
+    return;
+  }
+  extern __shared__ int64_t smem[];
+  int bid = blockIdx.x, inst = -1;
+  for (int i = 0; i < count; i++) {
+    const int n = max(0, desc[i].N - c);
+    if (bid < n) { inst = i; break; }
+    bid -= n;
+  }
+  if (inst < 0) return;
+  const InstDesc I = desc[inst];
+  if (!I.active) return;
+  const int N = I.N;
+  const int r = c + bid, lr = r - c;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const ColInfo cc = I.cols[c];
+  const int W = cc.W;
+  char* base = (char*)smem;
+  int32_t* pC = (int32_t*)base;
+  uint32_t* pS = (uint32_t*)(pC + cc.CW);
+  uint32_t* pD = pS + cc.CW;
+  int* pinfo = (int*)(pD + cc.CW);           // pivot: standard digits, shift, sign
+  char* wbase = base + piv_bytes + wave * fin_bytes;
+  int32_t* dg = (int32_t*)wbase;
+  int32_t* ob = dg + (W + 48);
+  int64_t* ca = (int64_t*)(ob + (W + 48));
+  int64_t* cb = ca + (W / WB + 8);
+  int64_t* Pd = cb + (W / WB + 8);           // product digits, W
+  int64_t* dsm = (int64_t*)(base + piv_bytes);
+  // pending carries of column c: left by the update by column c - 2
+  const int64_t* Kc = I.Kc + cc.koff + (int64_t)((c + 1) & 1) * cc.nb * cc.R;
+  uint32_t* Srow = I.S + cc.soff + (int64_t)lr * cc.CW;
+  // the row this wavefront finalises
+  const int fr = wave == 0 ? r : c;
+  const bool work = wave == 0 || r != c;
+  const int64_t* Psub = nullptr;
+  if (work && c > 0) {
+    const ColInfo ck = I.cols[c - 1];
+    int32_t* Lr = (int32_t*)(Pd + W);          // L_{c-1}[fr], LW + 8
+    int32_t* Cp = Lr + (ck.LW + 8);            // C_{c-1}[c], CW
+    const int nL = min(I.nL[tri_index(N, c - 1, fr)], ck.LW);
+    const int nC = min(I.nC[tri_index(N, c - 1, c)], ck.CW);
+    const int nL8 = (nL + PBD - 1) / PBD * PBD;
+    for (int a = lane; a < nL8; a += 64)
+      Lr[a] = a < nL ? I.L[ck.loff + (int64_t)a * ck.R + (fr - (c - 1))] : 0;
+    for (int a = lane; a < nC; a += 64) Cp[a] = I.C[ck.coff + (int64_t)ck.CW + a];
+    lds_sync<false>();
+    near_product<false>(Lr, nL, Cp, nC, W, Pd, I.flags);
+    Psub = Pd;
+  }
+  FinOut f;
+  f.nstd = 0;
+  f.neg = 0;
+  if (wave == 0) {
+    f = wave_finalize<false>(I.A + cc.aoff + lr, cc.R, W, Kc + lr, cc.R, I.h,
+                             I.C + cc.coff + (int64_t)lr * cc.CW, Srow, cc.CW, I.flags, dg, ob, ca, cb, Psub);
+    const int64_t ti = tri_index(N, c, r);
+    if (lane == 0) {
+      I.nC[ti] = f.nbal;
+      I.nCs[ti] = f.neg ? -f.nstd : f.nstd;
+      I.b32C[ti] = (f.bits + 31) / 32;
+    }
+    if (r == c) {
+      const int sh = f.nstd > 0 ? 28 - (31 - __clz(f.topv)) : 0;
+      if (lane == 0) {
+        if (f.nstd == 0 || f.neg) {
+          atomicMin(&I.flags[1], c);
+          if (f.nstd > 0 && f.neg) atomicAdd(&I.flags[2], 1);
+        }
+        I.dinfo[4 * c] = f.nstd;
+        I.dinfo[4 * c + 1] = sh;
+        I.dinfo[4 * c + 2] = f.nstd > 0 ? f.neg : 0;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      normalise_divisor(Srow, f.nstd, sh, I.D + cc.doff);
+    }
+  } else if (work) {
+    const FinOut p = wave_finalize<false>(I.A + cc.aoff, cc.R, W, Kc, cc.R, I.h, pC, pS, cc.CW, I.flags,
+                                          dg, ob, ca, cb, Psub);
+    const int sh = p.nstd > 0 ? 28 - (31 - __clz(p.topv)) : 0;
+    lds_sync<false>();
+    normalise_divisor(pS, p.nstd, sh, pD);
+    if (lane == 0) {
+      pinfo[0] = p.nstd;
+      pinfo[1] = sh;
+      pinfo[2] = p.nstd > 0 ? p.neg : 0;
+    }
+  }
+  __syncthreads();
+  if (r == c || wave != 0) return;
+  const ColInfo cr = I.cols[r];
+  const int n = divide_entry<false, 2>(dsm, Srow, f.nstd, f.neg, pD, pinfo[0], pinfo[1], pinfo[2], I.h,
                                     I.L + cc.loff + lr, cc.R, cc.LW, I.LT + cr.ltoff + c, cr.PT, I.flags);
   if (lane == 0) {
     I.nL[tri_index(N, c, r)] = n;
@@ -1249,6 +1437,27 @@ hipError_t launch_fdiv(const BatchView& B, int c, int rd, hipStream_t s) {
   if (rows <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fdiv, dim3((unsigned)rows), dim3(128), 2 * fin + piv + div, s, B.ddesc,
                      (int)B.plans.size(), c, rd, (int)fin, (int)piv);
+  return hipGetLastError();
+}
+hipError_t launch_column(const BatchView& B, int c, hipStream_t s) {
+  int64_t rows = 0, items = 0;
+  size_t fin = 0, piv = 0, div = 0;
+  for (const Plan* p : B.plans) {
+    if (c < p->N) {
+      const ColInfo& cc = p->cols[c];
+      const int Lw = c > 0 ? p->cols[c - 1].LW + 8 : 0, Cw = c > 0 ? p->cols[c - 1].CW : 0;
+      rows += p->N - c;
+      fin = std::max(fin, fin_shm(cc.W) + sizeof(int64_t) * (size_t)cc.W + sizeof(int32_t) * (size_t)(Lw + Cw));
+      piv = std::max(piv, (sizeof(uint32_t) * (3 * (size_t)cc.CW + 4) + 7) / 8 * 8);
+      div = std::max(div, divide_shm(p->h, cc.CW, cc.W + 2));
+    }
+    if (c > 0) items += update_items(*p, c - 1, 1, UPD_FAR);
+  }
+  fin = (fin + 7) / 8 * 8;
+  if (rows <= 0 && items <= 0) return hipSuccess;
+  const int64_t blocks = rows + (items + 1) / 2;
+  hipLaunchKernelGGL(k_column, dim3((unsigned)blocks), dim3(128), piv + std::max(2 * fin, div), s, B.ddesc,
+                     (int)B.plans.size(), c, (int)rows, (int)fin, (int)piv);
   return hipGetLastError();
 }
 hipError_t launch_gather_pivots_b(const BatchView& B, int32_t* out, int ld, hipStream_t s) {

@@ -23,7 +23,7 @@ def HK_FLAG_PANEL(p):
     return (p & 0xff) << 16
 
 
-HK_FLAG_LOOKAHEAD_ON, HK_FLAG_LOOKAHEAD_OFF = 0x1000000, 0x2000000
+HK_FLAG_LOOKAHEAD_ON, HK_FLAG_LOOKAHEAD_OFF, HK_FLAG_LOOKAHEAD_FUSED = 0x1000000, 0x2000000, 0x4000000
 STATUS = {0: "HK_OK", 1: "HK_EINVAL", 2: "HK_ENOTSPD", 3: "HK_EPRECISION", 4: "HK_ENOCONV",
           5: "HK_EVERIFY", 6: "HK_EDEVICE", 7: "HK_ENOMEM"}
 

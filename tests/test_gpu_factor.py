@@ -56,14 +56,16 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("la", [0, 2])
 @pytest.mark.parametrize("N,beta,K,xn,panel", CASES)
-def test_parity_vs_oracle(hk, N, beta, K, xn, panel):
-    log("parity N=%d beta=%s K=%d x=%d*2^-(K/2) panel=%d" % (N, beta, K, xn, panel))
+def test_parity_vs_oracle(hk, N, beta, K, xn, panel, la):
+    log("parity N=%d beta=%s K=%d x=%d*2^-(K/2) panel=%d look-ahead %d" % (N, beta, K, xn, panel, la))
     X = moments(N, beta, K)
     xf = xn << (K - K // 2)
     of = oracle.factor_from_moments(X, N, K, xf)
     m = hk.Matrix(N, beta, K)
     m.set_panel(panel)
+    m.set_lookahead(la)
     st, nneg, fb = m.factor(xf)
     compare(m, of, N)
 
@@ -140,16 +142,17 @@ def test_graph_replays_equal_eager_and_oracle(hk):
 
 
 @pytest.mark.parametrize("panel", [1, 3, 8])
-def test_lookahead_on_off_equal_oracle(hk, panel):
-    """The look-ahead schedule (next panel's columns first, the rest of the
-    trailing update on a second stream) gives the same digits as one trailing
+def test_lookahead_modes_equal_oracle(hk, panel):
+    """The look-ahead schedules (1: next panel's columns first, the rest of
+    the trailing update on a second stream; 2: one launch per column with the
+    previous column's update inside it) give the same digits as one trailing
     update per panel, eager and through graph replays."""
     N, beta, K = 97, (5, 3), 768
     X = moments(N, beta, K)
     ref = oracle.factor_from_moments(X, N, K, 0)
     m = hk.Matrix(N, beta, K)
     m.set_panel(panel)
-    for la in (1, 0, 1):
+    for la in (1, 0, 2, 1, 2):
         for timing in (1, 0, 0):
             log("look-ahead %d panel %d timing %d" % (la, panel, timing))
             m.set_lookahead(la)
@@ -170,14 +173,16 @@ EDGE = [
 ]
 
 
+@pytest.mark.parametrize("la", [0, 2])
 @pytest.mark.parametrize("N,beta,K,xn,panel", EDGE)
-def test_edge_sizes_vs_oracle(hk, N, beta, K, xn, panel):
-    log("edge N=%d beta=%s K=%d x=%d*2^-(K/2) panel=%d" % (N, beta, K, xn, panel))
+def test_edge_sizes_vs_oracle(hk, N, beta, K, xn, panel, la):
+    log("edge N=%d beta=%s K=%d x=%d*2^-(K/2) panel=%d look-ahead %d" % (N, beta, K, xn, panel, la))
     X = moments(N, beta, K)
     xf = xn << (K - K // 2)
     of = oracle.factor_from_moments(X, N, K, xf)
     m = hk.Matrix(N, beta, K)
     m.set_panel(panel)
+    m.set_lookahead(la)
     st, nneg, fb = m.factor(xf, inertia_mode=1, raise_on_error=False)
     assert (nneg, fb) == (of.n_negative, of.first_nonpos)
     if fb < 0 or fb == N - 1:
