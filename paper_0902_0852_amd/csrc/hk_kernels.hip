@@ -298,7 +298,7 @@ __device__ __forceinline__ void lds_sync() {
 // q+1 in the next round; rounds repeat until no carry is left inside the
 // number (at most nblk rounds).  cin[0] may hold a carry into block 0.
 // Returns the total carry out of the top block.
-template <bool BAL, bool BLK = true>
+template <bool BAL, bool BLK = true, int FB = WB>
 __device__ int64_t wave_resolve(int32_t* x, int nblk, int64_t* cin, int64_t* cout) {
   const int lane = threadIdx.x & 63;
   int64_t top = cin[nblk];   // carry already out of the top block
@@ -308,10 +308,10 @@ __device__ int64_t wave_resolve(int32_t* x, int nblk, int64_t* cin, int64_t* cou
       const int64_t c = cin[q];
       int64_t v = c;
       if (c != 0) {
-        for (int m = 0; m < WB; m++) {
-          v += x[q * WB + m];
+        for (int m = 0; m < FB; m++) {
+          v += x[q * FB + m];
           const int32_t d = BAL ? balanced29(v) : (int32_t)(v & (RADIX - 1));
-          x[q * WB + m] = d;
+          x[q * FB + m] = d;
           v = (v - d) >> DB;
         }
       }
@@ -333,27 +333,39 @@ __device__ int64_t wave_resolve(int32_t* x, int nblk, int64_t* cin, int64_t* cou
 // Kp[q ks] for q >= 1) is normalised block by block in parallel,
 // its sign taken from the top digit, its magnitude converted to standard
 // digits, shifted right by h bits with round-to-nearest-even, and written as
-// balanced digits (Cr) and standard magnitude digits (Sr), cap each.  LDS:
-// dg and ob of W + 48 int32, ca and cb of W/16 + 8 int64.
-template <bool BLK = true>
+// balanced digits (Cr) and standard magnitude digits (Sr), cap each.  Each
+// lane normalises blocks of FB digits (a divisor of 16) one digit after
+// another; the carries between blocks are then resolved in rounds.  LDS:
+// dg and ob of W + 48 int32, ca and cb of W/FB + 8 int64.
+template <bool BLK = true, int FB = WB, bool PRE = false>
 __device__ FinOut wave_finalize(const int32_t* Ap, int64_t as, int W, const int64_t* Kp, int64_t ks,
                                 int h, int32_t* Cr, uint32_t* Sr, int cap, int32_t* flags,
                                 int32_t* dg, int32_t* ob, int64_t* ca, int64_t* cb,
-                                const int64_t* Psub = nullptr) {
+                                const int64_t* Psub = nullptr, uint32_t* Sl = nullptr) {
   const int lane = threadIdx.x & 63;
-  const int nb = W / WB;
-  // 1. load, block-local balanced normalisation, carries between blocks
+  const int nb = W / FB;
+  // 1. load, block-local balanced normalisation, carries between blocks (the
+  // pending carries Kp belong to the 16-digit blocks of the update).  PRE:
+  // the caller has already put the digits in dg and the carries in cb.
   for (int q = lane; q < nb; q += 64) {
-    int32_t a[WB];
+    int32_t a[FB];
+    const int q16 = q * FB / WB;
+    int64_t v = 0;
+    if constexpr (PRE) {
 #pragma unroll
-    for (int m = 0; m < WB; m++) a[m] = Ap[(int64_t)(q * WB + m) * as];
-    int64_t v = q > 0 ? Kp[(int64_t)q * ks] : 0;
+      for (int m = 0; m < FB; m++) a[m] = dg[q * FB + m];
+      if (q16 > 0 && q * FB == q16 * WB) v = cb[q16];
+    } else {
 #pragma unroll
-    for (int m = 0; m < WB; m++) {
+      for (int m = 0; m < FB; m++) a[m] = Ap[(int64_t)(q * FB + m) * as];
+      if (q16 > 0 && q * FB == q16 * WB) v = Kp[(int64_t)q16 * ks];
+    }
+#pragma unroll
+    for (int m = 0; m < FB; m++) {
       v += a[m];
-      if (Psub) v -= Psub[q * WB + m];
+      if (Psub) v -= Psub[q * FB + m];
       const int32_t d = balanced29(v);
-      dg[q * WB + m] = d;
+      dg[q * FB + m] = d;
       v = (v - d) >> DB;
     }
     ca[q + 1] = v;
@@ -361,7 +373,7 @@ __device__ FinOut wave_finalize(const int32_t* Ap, int64_t as, int W, const int6
   if (lane == 0) ca[0] = 0;
   lds_sync<BLK>();
   // carries out of block q were stored in ca[q+1]: the carry into block q
-  if (wave_resolve<true, BLK>(dg, nb, ca, cb) != 0 && lane == 0) atomicOr(&flags[0], 2);
+  if (wave_resolve<true, BLK, FB>(dg, nb, ca, cb) != 0 && lane == 0) atomicOr(&flags[0], 2);
   // 2. sign: the top nonzero digit
   int mytop = -1;
   for (int s = lane; s < W; s += 64) if (dg[s] != 0) mytop = s;
@@ -372,23 +384,23 @@ __device__ FinOut wave_finalize(const int32_t* Ap, int64_t as, int W, const int6
   for (int q = lane; q < nb; q += 64) {
     int64_t v = 0;
 #pragma unroll
-    for (int m = 0; m < WB; m++) {
-      const int64_t x = (int64_t)(neg ? -dg[q * WB + m] : dg[q * WB + m]) + v;
+    for (int m = 0; m < FB; m++) {
+      const int64_t x = (int64_t)(neg ? -dg[q * FB + m] : dg[q * FB + m]) + v;
       const int32_t u = (int32_t)(x & (RADIX - 1));
-      dg[q * WB + m] = u;
+      dg[q * FB + m] = u;
       v = x >> DB;
     }
     ca[q + 1] = v;
   }
   if (lane == 0) ca[0] = 0;
   lds_sync<BLK>();
-  wave_resolve<false, BLK>(dg, nb, ca, cb);
+  wave_resolve<false, BLK, FB>(dg, nb, ca, cb);
   // 4. shift right by h bits; round to nearest, ties to even
   const int hq = h / DB, hb = h % DB;
   const int hbit_digit = (h - 1) / DB, hbit = (h - 1) % DB;
   const int nout = W - hq + 1;                 // output digits incl. a carry digit
-  const int nbo = (nout + WB - 1) / WB;
-  for (int i = lane; i < nbo * WB; i += 64) {
+  const int nbo = (nout + FB - 1) / FB;
+  for (int i = lane; i < nbo * FB; i += 64) {
     uint32_t o = 0;
     if (i < nout) {
       const int s = hq + i;
@@ -407,41 +419,47 @@ __device__ FinOut wave_finalize(const int32_t* Ap, int64_t as, int W, const int6
   const int inc = half && (sticky || (ob[0] & 1));
   for (int q = lane; q <= nbo; q += 64) ca[q] = (q == 0) ? inc : 0;
   lds_sync<BLK>();
-  if (wave_resolve<false, BLK>(ob, nbo, ca, cb) != 0 && lane == 0) atomicOr(&flags[0], 16);
+  if (wave_resolve<false, BLK, FB>(ob, nbo, ca, cb) != 0 && lane == 0) atomicOr(&flags[0], 16);
   // 5. standard digits out; balanced copy with the sign
   int ts = -1;
-  for (int i = lane; i < nbo * WB; i += 64) {
+  for (int i = lane; i < nbo * FB; i += 64) {
     const int32_t u = i < nout ? ob[i] : 0;
-    if (i < cap) Sr[i] = (uint32_t)u;
+    if (i < cap) {
+      Sr[i] = (uint32_t)u;
+      if (Sl) Sl[i] = (uint32_t)u;
+    }
     if (u != 0) { ts = i; if (i >= cap) atomicOr(&flags[0], 16); }
   }
-  for (int i = nbo * WB + lane; i < cap; i += 64) Sr[i] = 0;
+  for (int i = nbo * FB + lane; i < cap; i += 64) {
+    Sr[i] = 0;
+    if (Sl) Sl[i] = 0;
+  }
   const int stop = wave_max(ts);
   const uint32_t topv = stop >= 0 ? (uint32_t)ob[stop] : 0u;
   lds_sync<BLK>();
   for (int q = lane; q < nbo; q += 64) {
     int64_t v = 0;
 #pragma unroll
-    for (int m = 0; m < WB; m++) {
-      v += ob[q * WB + m];
+    for (int m = 0; m < FB; m++) {
+      v += ob[q * FB + m];
       const int32_t d = balanced29(v);
-      ob[q * WB + m] = d;
+      ob[q * FB + m] = d;
       v = (v - d) >> DB;
     }
     ca[q + 1] = v;
   }
   if (lane == 0) ca[0] = 0;
   lds_sync<BLK>();
-  const int64_t extra = wave_resolve<true, BLK>(ob, nbo, ca, cb);   // 0 or 1: one more digit
+  const int64_t extra = wave_resolve<true, BLK, FB>(ob, nbo, ca, cb);   // 0 or 1: one more digit
   int tb = -1;
   for (int i = lane; i < cap; i += 64) {
-    int32_t d = i < nbo * WB ? ob[i] : 0;
-    if (i == nbo * WB) d = (int32_t)extra;
+    int32_t d = i < nbo * FB ? ob[i] : 0;
+    if (i == nbo * FB) d = (int32_t)extra;
     d = neg ? -d : d;
     Cr[i] = d;
     if (d != 0) tb = i;
   }
-  if (extra != 0 && nbo * WB >= cap && lane == 0) atomicOr(&flags[0], 16);
+  if (extra != 0 && nbo * FB >= cap && lane == 0) atomicOr(&flags[0], 16);
   FinOut f;
   f.nbal = wave_max(tb) + 1;
   f.nstd = stop + 1;
@@ -689,6 +707,10 @@ __device__ __forceinline__ int divide_entry(int64_t* smem, const uint32_t* Sr, i
   return wave_max(mytop) + 1;
 }
 
+// Digits per lane-serial block in the column finalisations (short serial
+// chains, more lanes busy).
+constexpr int FIN_FB = 4;
+
 // |d| 2^sh as standard digits, top digit in [2^28, 2^29): every output digit
 // takes its own input digit shifted up and the top bits of the one below
 __device__ __forceinline__ void normalise_divisor(const uint32_t* S, int n, int sh, uint32_t* out) {
@@ -726,7 +748,7 @@ __global__ void __launch_bounds__(128) k_fdiv(const InstDesc* __restrict__ desc,
   int32_t* dg = (int32_t*)(base + wave * fin_bytes);
   int32_t* ob = dg + (W + 48);
   int64_t* ca = (int64_t*)(ob + (W + 48));
-  int64_t* cb = ca + (W / WB + 8);
+  int64_t* cb = ca + (W / FIN_FB + 8);
   int32_t* pC = (int32_t*)(base + 2 * fin_bytes);
   uint32_t* pS = (uint32_t*)(pC + cc.CW);
   uint32_t* pD = pS + cc.CW;
@@ -738,7 +760,7 @@ __global__ void __launch_bounds__(128) k_fdiv(const InstDesc* __restrict__ desc,
   f.nstd = 0;
   f.neg = 0;
   if (wave == 0) {
-    f = wave_finalize<false>(I.A + cc.aoff + lr, cc.R, W, Kc + lr, cc.R, I.h,
+    f = wave_finalize<false, FIN_FB>(I.A + cc.aoff + lr, cc.R, W, Kc + lr, cc.R, I.h,
                              I.C + cc.coff + (int64_t)lr * cc.CW, Srow, cc.CW, I.flags, dg, ob, ca, cb);
     const int64_t ti = tri_index(N, c, r);
     if (lane == 0) {
@@ -764,7 +786,7 @@ __global__ void __launch_bounds__(128) k_fdiv(const InstDesc* __restrict__ desc,
       normalise_divisor(Srow, f.nstd, sh, I.D + cc.doff);
     }
   } else if (r != c) {
-    const FinOut p = wave_finalize<false>(I.A + cc.aoff, cc.R, W, Kc, cc.R, I.h, pC, pS, cc.CW, I.flags,
+    const FinOut p = wave_finalize<false, FIN_FB>(I.A + cc.aoff, cc.R, W, Kc, cc.R, I.h, pC, pS, cc.CW, I.flags,
                                           dg, ob, ca, cb);
     const int sh = p.nstd > 0 ? 28 - (31 - __clz(p.topv)) : 0;
     lds_sync<false>();
@@ -786,13 +808,10 @@ __global__ void __launch_bounds__(128) k_fdiv(const InstDesc* __restrict__ desc,
   }
 }
 
-// Product digits per lane and pass of near_product, and the digits a pass covers.
-constexpr int PBD = 8;
-constexpr int PPASS = 64 * PBD;
-
-__device__ __forceinline__ void renorm_pbd(int64_t* acc) {
+template <int PB>
+__device__ __forceinline__ void renorm_pb(int64_t* acc) {
 #pragma unroll
-  for (int m = 0; m < PBD; m++) {
+  for (int m = 0; m < PB; m++) {
     const int64_t hc = acc[m] >> DB;
     acc[m] -= hc << DB;
     acc[m + 1] += hc;
@@ -802,12 +821,14 @@ __device__ __forceinline__ void renorm_pbd(int64_t* acc) {
 // P[0..W) = the digits of the exact product Lr * Cp by one wavefront, lazily
 // normalised (|P[s]| < 2^36).  Lr: nL balanced digits in LDS, zero padded to
 // a multiple of 8; Cp: nC balanced digits in LDS.  Lane l forms the output
-// digits [8 l, 8 l + 8) of each pass of 512 by operand scanning over Lr, with
-// the eight C digits it meets held in a ring of registers (one new digit per
-// step), then adds its carry into the digit above in a second phase.
-// A product wider than W digits sets bit 1 of flags[0], like an update that
-// overflows its entry.
-template <bool BLK>
+// digits [PB l, PB l + PB) of each pass of 64 PB by operand scanning over Lr
+// (PB a power of two up to 8),
+// with the PB digits of C it meets held in a ring of registers (one new digit
+// per step), then adds its carry into the digit above in a second phase.
+// PB = 2 covers W <= 128 in one pass with every lane busy; PB = 8 suits wide
+// entries.  A product wider than W digits sets bit 1 of flags[0], like an
+// update that overflows its entry.
+template <int PB, bool BLK>
 __device__ void near_product(const int32_t* Lr, int nL, const int32_t* Cp, int nC, int W, int64_t* P,
                              int32_t* flags) {
   const int lane = threadIdx.x & 63;
@@ -815,36 +836,42 @@ __device__ void near_product(const int32_t* Lr, int nL, const int32_t* Cp, int n
   for (int s = lane; s < W; s += 64) P[s] = 0;
   lds_sync<BLK>();
   if (nL <= 0 || nC <= 0) return;
-  const int nL8 = (nL + PBD - 1) / PBD * PBD;
-  for (int p0 = 0; p0 < W; p0 += PPASS) {
-    const int s0 = p0 + PBD * lane;
-    int64_t acc[PBD + 1];
-    int32_t ring[PBD];   // ring[(s0 + b - a) & 7] = C[s0 + b - a]
+  const int nL8 = (nL + 7) / 8 * 8;
+  for (int p0 = 0; p0 < W; p0 += 64 * PB) {
+    const int s0 = p0 + PB * lane;
+    int64_t acc[PB + 1];
+    int32_t ring[PB];   // ring[(s0 + b - a) mod PB] = C[s0 + b - a]
 #pragma unroll
-    for (int m = 0; m <= PBD; m++) acc[m] = 0;
+    for (int m = 0; m <= PB; m++) acc[m] = 0;
 #pragma unroll
-    for (int b = 0; b < PBD; b++) ring[b] = s0 + b < nC ? Cp[s0 + b] : 0;
+    for (int b = 0; b < PB; b++) ring[b] = s0 + b < nC ? Cp[s0 + b] : 0;
     int cnt = 0;
-    for (int a0 = 0; a0 < nL8; a0 += PBD) {
+    for (int a0 = 0; a0 < nL8; a0 += 8) {
+      // eight steps: their L digits and the C digits entering the ring are
+      // read up front so the LDS reads overlap
+      int32_t la[8], cn[8];
 #pragma unroll
-      for (int u = 0; u < PBD; u++) {
-        const int a = a0 + u;
-        const int32_t la = Lr[a];
-#pragma unroll
-        for (int b = 0; b < PBD; b++) acc[b] += (int64_t)la * (int64_t)ring[(b - u) & (PBD - 1)];
-        const int idx = s0 - a - 1;
-        ring[(PBD - 1 - u) & (PBD - 1)] = idx >= 0 && idx < nC ? Cp[idx] : 0;
+      for (int u = 0; u < 8; u++) {
+        la[u] = Lr[a0 + u];
+        const int idx = s0 - (a0 + u) - 1;
+        cn[u] = idx >= 0 && idx < nC ? Cp[idx] : 0;
       }
-      cnt += PBD;
-      if (cnt >= 96) { renorm_pbd(acc); cnt = 0; }
-    }
-    renorm_pbd(acc);
 #pragma unroll
-    for (int b = 0; b < PBD; b++)
+      for (int u = 0; u < 8; u++) {
+#pragma unroll
+        for (int b = 0; b < PB; b++) acc[b] += (int64_t)la[u] * (int64_t)ring[(b - u) & (PB - 1)];
+        ring[(PB - 1 - u) & (PB - 1)] = cn[u];
+      }
+      cnt += 8;
+      if (cnt >= 96) { renorm_pb<PB>(acc); cnt = 0; }
+    }
+    renorm_pb<PB>(acc);
+#pragma unroll
+    for (int b = 0; b < PB; b++)
       if (s0 + b < W) P[s0 + b] += acc[b];
     lds_sync<BLK>();
-    if (s0 + PBD < W) P[s0 + PBD] += acc[PBD];
-    else if (s0 < W && acc[PBD] != 0) atomicOr(&flags[0], 1);
+    if (s0 + PB < W) P[s0 + PB] += acc[PB];
+    else if (s0 < W && acc[PB] != 0) atomicOr(&flags[0], 1);
     lds_sync<BLK>();
   }
 }
@@ -887,13 +914,14 @@ k_column(const InstDesc* __restrict__ desc, int count, int c, int n_near, int fi
   int32_t* pC = (int32_t*)base;
   uint32_t* pS = (uint32_t*)(pC + cc.CW);
   uint32_t* pD = pS + cc.CW;
-  int* pinfo = (int*)(pD + cc.CW);           // pivot: standard digits, shift, sign
+  uint32_t* oS = pD + cc.CW;                 // this row's standard digits
+  int* pinfo = (int*)(oS + cc.CW);           // pivot: standard digits, shift, sign
   char* wbase = base + piv_bytes + wave * fin_bytes;
   int32_t* dg = (int32_t*)wbase;
   int32_t* ob = dg + (W + 48);
   int64_t* ca = (int64_t*)(ob + (W + 48));
-  int64_t* cb = ca + (W / WB + 8);
-  int64_t* Pd = cb + (W / WB + 8);           // product digits, W
+  int64_t* cb = ca + (W / FIN_FB + 8);
+  int64_t* Pd = cb + (W / FIN_FB + 8);           // product digits, W
   int64_t* dsm = (int64_t*)(base + piv_bytes);
   // pending carries of column c: left by the update by column c - 2
   const int64_t* Kc = I.Kc + cc.koff + (int64_t)((c + 1) & 1) * cc.nb * cc.R;
@@ -902,26 +930,36 @@ k_column(const InstDesc* __restrict__ desc, int count, int c, int n_near, int fi
   const int fr = wave == 0 ? r : c;
   const bool work = wave == 0 || r != c;
   const int64_t* Psub = nullptr;
+  if (work) {
+    // the accumulator digits and pending carries of entry (fr, c), read into
+    // LDS together with the update's operands so the loads overlap
+    const int flr = fr - c;
+    for (int s2 = lane; s2 < W; s2 += 64) dg[s2] = I.A[cc.aoff + (int64_t)s2 * cc.R + flr];
+    for (int q = lane; q < cc.nb; q += 64) cb[q] = q > 0 ? Kc[(int64_t)q * cc.R + flr] : 0;
+  }
   if (work && c > 0) {
     const ColInfo ck = I.cols[c - 1];
     int32_t* Lr = (int32_t*)(Pd + W);          // L_{c-1}[fr], LW + 8
     int32_t* Cp = Lr + (ck.LW + 8);            // C_{c-1}[c], CW
     const int nL = min(I.nL[tri_index(N, c - 1, fr)], ck.LW);
     const int nC = min(I.nC[tri_index(N, c - 1, c)], ck.CW);
-    const int nL8 = (nL + PBD - 1) / PBD * PBD;
+    const int nL8 = (nL + 7) / 8 * 8;
     for (int a = lane; a < nL8; a += 64)
       Lr[a] = a < nL ? I.L[ck.loff + (int64_t)a * ck.R + (fr - (c - 1))] : 0;
     for (int a = lane; a < nC; a += 64) Cp[a] = I.C[ck.coff + (int64_t)ck.CW + a];
     lds_sync<false>();
-    near_product<false>(Lr, nL, Cp, nC, W, Pd, I.flags);
+    if (W <= 128) near_product<2, false>(Lr, nL, Cp, nC, W, Pd, I.flags);
+    else near_product<8, false>(Lr, nL, Cp, nC, W, Pd, I.flags);
     Psub = Pd;
   }
+  if (work) lds_sync<false>();
   FinOut f;
   f.nstd = 0;
   f.neg = 0;
   if (wave == 0) {
-    f = wave_finalize<false>(I.A + cc.aoff + lr, cc.R, W, Kc + lr, cc.R, I.h,
-                             I.C + cc.coff + (int64_t)lr * cc.CW, Srow, cc.CW, I.flags, dg, ob, ca, cb, Psub);
+    f = wave_finalize<false, FIN_FB, true>(I.A + cc.aoff + lr, cc.R, W, Kc + lr, cc.R, I.h,
+                                           I.C + cc.coff + (int64_t)lr * cc.CW, Srow, cc.CW, I.flags, dg, ob,
+                                           ca, cb, Psub, oS);
     const int64_t ti = tri_index(N, c, r);
     if (lane == 0) {
       I.nC[ti] = f.nbal;
@@ -945,8 +983,8 @@ k_column(const InstDesc* __restrict__ desc, int count, int c, int n_near, int fi
       normalise_divisor(Srow, f.nstd, sh, I.D + cc.doff);
     }
   } else if (work) {
-    const FinOut p = wave_finalize<false>(I.A + cc.aoff, cc.R, W, Kc, cc.R, I.h, pC, pS, cc.CW, I.flags,
-                                          dg, ob, ca, cb, Psub);
+    const FinOut p = wave_finalize<false, FIN_FB, true>(I.A + cc.aoff, cc.R, W, Kc, cc.R, I.h, pC, pS, cc.CW,
+                                                        I.flags, dg, ob, ca, cb, Psub);
     const int sh = p.nstd > 0 ? 28 - (31 - __clz(p.topv)) : 0;
     lds_sync<false>();
     normalise_divisor(pS, p.nstd, sh, pD);
@@ -959,7 +997,7 @@ k_column(const InstDesc* __restrict__ desc, int count, int c, int n_near, int fi
   __syncthreads();
   if (r == c || wave != 0) return;
   const ColInfo cr = I.cols[r];
-  const int n = divide_entry<false, 2>(dsm, Srow, f.nstd, f.neg, pD, pinfo[0], pinfo[1], pinfo[2], I.h,
+  const int n = divide_entry<false, 2>(dsm, oS, f.nstd, f.neg, pD, pinfo[0], pinfo[1], pinfo[2], I.h,
                                     I.L + cc.loff + lr, cc.R, cc.LW, I.LT + cr.ltoff + c, cr.PT, I.flags);
   if (lane == 0) {
     I.nL[tri_index(N, c, r)] = n;
@@ -1412,9 +1450,9 @@ hipError_t launch_update(const BatchView& B, int pc, int b, int j, int rd, hipSt
                      (int)B.plans.size(), pc, b, j, rd);
   return hipGetLastError();
 }
-// LDS of wave_finalize for W digits
-static size_t fin_shm(int W) {
-  return sizeof(int32_t) * 2 * (size_t)(W + 48) + sizeof(int64_t) * 2 * (size_t)(W / WB + 8);
+// LDS of wave_finalize for W digits in blocks of FB
+static size_t fin_shm(int W, int FB = WB) {
+  return sizeof(int32_t) * 2 * (size_t)(W + 48) + sizeof(int64_t) * 2 * (size_t)(W / FB + 8);
 }
 // LDS of divide_entry: remainder DOFF + nu + 3, divisor nd + 1, quotient
 // nu - nd + 2
@@ -1430,7 +1468,7 @@ hipError_t launch_fdiv(const BatchView& B, int c, int rd, hipStream_t s) {
     if (c < p->N) {
       const ColInfo& cc = p->cols[c];
       rows += p->N - c;
-      fin = std::max(fin, fin_shm(cc.W));
+      fin = std::max(fin, fin_shm(cc.W, FIN_FB));
       piv = std::max(piv, (sizeof(uint32_t) * (3 * (size_t)cc.CW + 4) + 7) / 8 * 8);
       div = std::max(div, divide_shm(p->h, cc.CW, cc.W + 2));
     }
@@ -1447,8 +1485,8 @@ hipError_t launch_column(const BatchView& B, int c, hipStream_t s) {
       const ColInfo& cc = p->cols[c];
       const int Lw = c > 0 ? p->cols[c - 1].LW + 8 : 0, Cw = c > 0 ? p->cols[c - 1].CW : 0;
       rows += p->N - c;
-      fin = std::max(fin, fin_shm(cc.W) + sizeof(int64_t) * (size_t)cc.W + sizeof(int32_t) * (size_t)(Lw + Cw));
-      piv = std::max(piv, (sizeof(uint32_t) * (3 * (size_t)cc.CW + 4) + 7) / 8 * 8);
+      fin = std::max(fin, fin_shm(cc.W, FIN_FB) + sizeof(int64_t) * (size_t)cc.W + sizeof(int32_t) * (size_t)(Lw + Cw));
+      piv = std::max(piv, (sizeof(uint32_t) * (4 * (size_t)cc.CW + 4) + 7) / 8 * 8);
       div = std::max(div, divide_shm(p->h, cc.CW, cc.W + 2));
     }
     if (c > 0) items += update_items(*p, c - 1, 1, UPD_FAR);
