@@ -9,10 +9,13 @@ beta = 7/4, K = 2048 fractional bits.
 Printed value: algorithmic 32-bit limb MACs per second of the whole job (the
 schoolbook count of every factorisation's trailing update, sum over updates
 of ceil(bits(C)/32) * ceil(bits(L)/32), divided by the wall time of the timed
-steps).  Also printed: lambda_1 solves/s, a roofline record for the update
-kernel (achieved limb MACs/s from HIP events around every update launch on
-the library's stream, against one 32-bit multiply per lane per clock on 256
-CUs at 2.4 GHz), and the CPU oracle timed on the host cores.
+steps).  Also printed: lambda_1 solves/s, a roofline record for the kernel
+that carries the update work (k_update, or k_column in look-ahead mode 2,
+where each column's launch holds its update as well as the finalisation and
+division of the column; achieved limb MACs/s from HIP events around every
+such launch on the library's stream, against one 32-bit multiply per lane
+per clock on 256 CUs at 2.4 GHz), and the CPU oracle timed on the host
+cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2]
 """
@@ -37,8 +40,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 PROFILE_TAG = {"c2": "N200_beta7-4_K2048", "c3b1": "N500_beta1_K6144"}
 
 
-def measured_traffic(cfg_name):
-    """HBM bytes per k_update launch from the committed rocprofv3 counter
+def measured_traffic(cfg_name, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary of this workload, or None when there is none or the kernel
     source has changed since the counters were taken."""
     import hashlib
@@ -46,7 +49,7 @@ def measured_traffic(cfg_name):
     tag = PROFILE_TAG.get(cfg_name)
     if tag is None:
         return None, None
-    path = os.path.join(HERE, "profiles", "k_update_%s_secant.txt" % tag)
+    path = os.path.join(HERE, "profiles", "%s_%s_secant.txt" % (kernel, tag))
     try:
         txt = open(path).read()
     except OSError:
@@ -206,7 +209,12 @@ def main():
     os.environ["HK_TUNE_CACHE"] = tune_path
     if args.panel > 0:
         panel, la = args.panel, args.lookahead
-        log("panel width %d, look-ahead %s (given)" % (panel, la))
+        if la < 0:   # the mode the library picks for this size
+            m = hk.Matrix(N, beta, K)
+            m.set_panel(panel)
+            la = m.info().lookahead
+            del m
+        log("panel width %d, look-ahead %d (given)" % (panel, la))
     else:
         panel, la = hk.autotune([(N, beta, K)], cache_path=tune_path)
         log("tuned panel width %d, look-ahead %d" % (panel, la))
@@ -238,7 +246,10 @@ def main():
     torch.cuda.synchronize()
     upd_ms, upd_n = r["update_ms"], r["update_launches"]
     achieved = macs_per_step / (upd_ms * 1e-3) if upd_ms > 0 else 0.0
-    traffic, traffic_src = measured_traffic(args.config)
+    kernel = "k_column" if la == 2 else "k_update"
+    kdesc = ("k_column (one column: its rows' update by the previous column, finalisation and division; "
+             "the update of the columns beyond)" if la == 2 else "k_update (trailing + in-panel update)")
+    traffic, traffic_src = measured_traffic(args.config, kernel)
     out = {
         "metric": "multiprecision limb-MACs/s (whole job) and % int-mul peak of the update kernel; "
                   "lambda_min solves/s at 1e-40 rel",
@@ -251,7 +262,7 @@ def main():
                    "panel": panel, "lookahead": la},
         "lambda_solves_per_s": args.steps / dt,
         "lambda_1": dec,
-        "roofline": {"bound": "alu", "kernel": "k_update (trailing + in-panel update)",
+        "roofline": {"bound": "alu", "kernel": kdesc,
                      "achieved": achieved / 1e12, "peak": PEAK_INT_MUL / 1e12,
                      "unit": "Tlimb-MAC/s", "frac": achieved / PEAK_INT_MUL,
                      "launches": upd_n,

@@ -86,8 +86,11 @@ typedef struct {
   int panel;              /* columns per trailing update (rank of the update) */
   size_t ws_bytes;        /* bytes of workspace in use                        */
   size_t vec_bytes;       /* bytes of one device vector (hk_solve operands)   */
-  int n_update_launches;  /* update-kernel launches of the last hk_factor     */
+  int n_update_launches;  /* launches that carry the update work in the last
+                             hk_factor (k_update, or k_column in look-ahead
+                             mode 2)                                          */
   double update_ms;       /* summed device time of those launches (timing on) */
+  int lookahead;          /* look-ahead mode hk_factor uses (0, 1, 2)         */
 } hk_info;
 
 typedef struct {

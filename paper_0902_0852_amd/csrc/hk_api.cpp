@@ -430,6 +430,7 @@ hk_status hk_matrix_info(hk_matrix m, hk_info* o) {
   o->panel = m->panel; o->ws_bytes = P.total;
   o->vec_bytes = sizeof(int32_t) * (size_t)P.N * P.VW;
   o->n_update_launches = m->n_update; o->update_ms = m->update_ms;
+  o->lookahead = lookahead_mode(m->lookahead, P.N, P.maxW);
   return HK_OK;
 }
 

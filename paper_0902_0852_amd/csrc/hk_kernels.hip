@@ -15,6 +15,7 @@
 // each item normalises its 16 digits and hands its carry to block q+1
 // through a double-buffered int64 carry plane (read buffer rd, write rd^1),
 // so no atomics and no cross-item ordering are needed.
+#include <climits>
 #include <cstring>
 
 #include "hk_internal.hpp"
@@ -229,14 +230,24 @@ __device__ __forceinline__ void update_item(const InstDesc* __restrict__ desc, i
   if (!I.active) return;
   const int N = I.N;
   it += sload(I.itemStart + c_lo);
-  int lo = c_lo, hi = c_hi - 1;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (sload(I.itemStart + mid) <= it) lo = mid; else hi = mid - 1;
+  // the column of the item: the last c in [c_lo, c_hi) with itemStart[c] <= it
+  // (itemStart is nondecreasing), found by the whole wavefront reading 64
+  // evenly spaced starts at once and narrowing to the interval the ballot
+  // picks: one round for up to 64 columns, two up to 4096
+  int lo = c_lo, n = c_hi - c_lo, start = 0;
+  while (n > 1) {
+    const int step = (n + 63) / 64;
+    const int k = lane * step;
+    const int v = k < n ? I.itemStart[lo + k] : INT_MAX;
+    const uint64_t m = __ballot(v <= it);
+    const int last = 63 - __clzll((long long)m);
+    lo = uni(lo + last * step);
+    n = min(step, c_hi - lo);
   }
   const int c = uni(lo);
+  start = sload(I.itemStart + c);
   const ColInfo cc = sload(I.cols + c);
-  const int rem = it - I.itemStart[c];
+  const int rem = it - start;
   const int T = cc.R >> 6;
   const int q = uni(rem / T);
   const int t = uni(rem - q * T);
@@ -545,7 +556,7 @@ __device__ __forceinline__ int divide_entry(int64_t* smem, const uint32_t* Sr, i
   const double R = (double)RADIX;
   const double D3 = (double)dd[nd - 1] * R * R + (nd >= 2 ? (double)dd[nd - 2] * R : 0.0) +
                     (nd >= 3 ? (double)dd[nd - 3] : 0.0);
-  const double invD = R / D3;   // quotient estimates by one multiply
+  const double ninvD = -R / D3;   // (negated) quotient estimates by one multiply
   // top divisor digits for the register window: DT[m] = dd[nd - 1 - m]
   int32_t DT[DQ + 2];
 #pragma unroll
@@ -577,24 +588,22 @@ __device__ __forceinline__ int divide_entry(int64_t* smem, const uint32_t* Sr, i
     for (int s = 0; s < DQ; s++) {
       q[s] = 0;
       if (s < Qe) {
-        // quotient digit j0 - s: fold position t + 1 into t, carry t - 2 and
-        // t - 1 upward, estimate from t, t - 1, t - 2
+        // quotient digit j0 - s: fold position t + 1 into t, carry t - 1
+        // upward, estimate from t, t - 1 and the lazy t - 2 (|W| < 2^63 there:
+        // converting it to double costs at most 2^10 of its units)
         W[s + 1] += W[s] << DB;
         W[s] = 0;
-        int64_t cy = W[s + 3] >> DB;
-        W[s + 3] &= RADIX - 1;
-        W[s + 2] += cy;
-        cy = W[s + 2] >> DB;
+        const int64_t cy = W[s + 2] >> DB;
         W[s + 2] &= RADIX - 1;
         W[s + 1] += cy;
-        // |W[s+1]| < 2^31 here, so the top two positions fit one int64
-        const int64_t top2 = (W[s + 1] << DB) + W[s + 2];
-        const double Tv = fma((double)top2, R, (double)(int32_t)W[s + 3]);
-        // |q| < 2^30 and divisor digits < 2^29: one 32 x 32 -> 64 multiply-add each
-        const int32_t qq = (int32_t)rint(Tv * invD);
-        q[s] = qq;
+        // |W[s+1]| < 2^31 here
+        const double Tv = fma((double)(int32_t)W[s + 1], R * R, fma((double)(int32_t)W[s + 2], R, (double)W[s + 3]));
+        // -q, with |q| < 2^30 and divisor digits < 2^29: one 32 x 32 -> 64
+        // multiply-add each
+        const int32_t nq = (int32_t)rint(Tv * ninvD);
+        q[s] = -nq;
 #pragma unroll
-        for (int x = s + 2; x < DQ + 4; x++) W[x] += (int64_t)(-qq) * (int64_t)DT[x - s - 2];
+        for (int x = s + 2; x < DQ + 4; x++) W[x] += (int64_t)nq * (int64_t)DT[x - s - 2];
       }
     }
     {  // quotient digits j0 .. j0 - Qe + 1 to LDS, one lane each
@@ -930,23 +939,51 @@ k_column(const InstDesc* __restrict__ desc, int count, int c, int n_near, int fi
   const int fr = wave == 0 ? r : c;
   const bool work = wave == 0 || r != c;
   const int64_t* Psub = nullptr;
+  // the accumulator digits and pending carries of entry (fr, c), and the
+  // operands of its update by column c - 1 (digits up to their capacities,
+  // which are zero filled), all requested before the first store to LDS so
+  // that their latencies overlap
+  const int flr = fr - c;
+  const bool upd = work && c > 0;
+  const ColInfo ck = I.cols[c > 0 ? c - 1 : 0];
+  const int32_t* Lsrc = I.L + ck.loff + (fr - (c - 1));
+  const int32_t* Csrc = I.C + ck.coff + (int64_t)ck.CW;
+  int32_t* Lr = (int32_t*)(Pd + W);            // L_{c-1}[fr], LW + 8
+  int32_t* Cp = Lr + (ck.LW + 8);              // C_{c-1}[c], CW
+  constexpr int U = 4;
+  int32_t av[U], lv[U], cv[U];
+  int64_t kv = 0;
+  int nL = 0, nC = 0;
   if (work) {
-    // the accumulator digits and pending carries of entry (fr, c), read into
-    // LDS together with the update's operands so the loads overlap
-    const int flr = fr - c;
-    for (int s2 = lane; s2 < W; s2 += 64) dg[s2] = I.A[cc.aoff + (int64_t)s2 * cc.R + flr];
-    for (int q = lane; q < cc.nb; q += 64) cb[q] = q > 0 ? Kc[(int64_t)q * cc.R + flr] : 0;
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int x = lane + 64 * u;
+      av[u] = x < W ? I.A[cc.aoff + (int64_t)x * cc.R + flr] : 0;
+      lv[u] = upd && x < ck.LW ? Lsrc[(int64_t)x * ck.R] : 0;
+      cv[u] = upd && x < ck.CW ? Csrc[x] : 0;
+    }
+    kv = lane > 0 && lane < cc.nb ? Kc[(int64_t)lane * cc.R + flr] : 0;
+    if (upd) {
+      nL = min(I.nL[tri_index(N, c - 1, fr)], ck.LW);
+      nC = min(I.nC[tri_index(N, c - 1, c)], ck.CW);
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int x = lane + 64 * u;
+      if (x < W) dg[x] = av[u];
+      if (upd && x < ck.LW) Lr[x] = lv[u];
+      if (upd && x < ck.CW) Cp[x] = cv[u];
+    }
+    if (lane < cc.nb) cb[lane] = kv;
+    for (int x = lane + 64 * U; x < W; x += 64) dg[x] = I.A[cc.aoff + (int64_t)x * cc.R + flr];
+    for (int q = lane + 64; q < cc.nb; q += 64) cb[q] = Kc[(int64_t)q * cc.R + flr];
+    if (upd) {
+      for (int x = lane + 64 * U; x < ck.LW; x += 64) Lr[x] = Lsrc[(int64_t)x * ck.R];
+      for (int x = lane + 64 * U; x < ck.CW; x += 64) Cp[x] = Csrc[x];
+      for (int x = ck.LW + lane; x < ck.LW + 8; x += 64) Lr[x] = 0;
+    }
   }
-  if (work && c > 0) {
-    const ColInfo ck = I.cols[c - 1];
-    int32_t* Lr = (int32_t*)(Pd + W);          // L_{c-1}[fr], LW + 8
-    int32_t* Cp = Lr + (ck.LW + 8);            // C_{c-1}[c], CW
-    const int nL = min(I.nL[tri_index(N, c - 1, fr)], ck.LW);
-    const int nC = min(I.nC[tri_index(N, c - 1, c)], ck.CW);
-    const int nL8 = (nL + 7) / 8 * 8;
-    for (int a = lane; a < nL8; a += 64)
-      Lr[a] = a < nL ? I.L[ck.loff + (int64_t)a * ck.R + (fr - (c - 1))] : 0;
-    for (int a = lane; a < nC; a += 64) Cp[a] = I.C[ck.coff + (int64_t)ck.CW + a];
+  if (upd) {
     lds_sync<false>();
     if (W <= 128) near_product<2, false>(Lr, nL, Cp, nC, W, Pd, I.flags);
     else near_product<8, false>(Lr, nL, Cp, nC, W, Pd, I.flags);

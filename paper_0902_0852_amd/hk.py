@@ -49,7 +49,7 @@ class Info(ctypes.Structure):
                 ("vec_digits", ctypes.c_int), ("solve_guard_bits", ctypes.c_int),
                 ("panel", ctypes.c_int), ("ws_bytes", ctypes.c_size_t),
                 ("vec_bytes", ctypes.c_size_t), ("n_update_launches", ctypes.c_int),
-                ("update_ms", ctypes.c_double)]
+                ("update_ms", ctypes.c_double), ("lookahead", ctypes.c_int)]
 
 
 class Report(ctypes.Structure):
