@@ -487,10 +487,24 @@ __device__ FinOut wave_finalize(const int32_t* Ap, int64_t as, int W, const int6
 constexpr int DQ = 8;
 constexpr int DOFF = DQ + 4;
 
+// 64-bit lane moves: the value of lane i - 1 (lane 0: 0) by a DPP wave
+// shift, and the value of one (uniform) lane
+__device__ __forceinline__ int64_t lane_shr1(int64_t v) {
+  const int32_t lo = __builtin_amdgcn_update_dpp(0, (int32_t)v, 0x138, 0xf, 0xf, false);
+  const int32_t hi = __builtin_amdgcn_update_dpp(0, (int32_t)(v >> 32), 0x138, 0xf, 0xf, false);
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+__device__ __forceinline__ int64_t lane_read(int64_t v, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int32_t)v, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int32_t)(v >> 32), l);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // One bulk step of divide_entry for remainder position b + rel: subtract
 // sum_s q[s] dd[rel + s + 1 - DQ] and split the result into a digit in
-// [0, 2^29) and a carry for the position above (carry-save: the carry is
-// passed to the next lane, so no position needs a second writer).
+// [0, 2^29) and a carry for the position above (carry-save: the carry moves
+// one lane up by a DPP shift, the top lane's to the next group's lane 0, so
+// no position needs a second writer).
 __device__ __forceinline__ void divide_bulk(int64_t* rem, int b, int rel, bool act, const int32_t* q,
                                             const int32_t* ddv, int64_t& carry, int top_group,
                                             int top_lane, int64_t& hi_top) {
@@ -500,11 +514,11 @@ __device__ __forceinline__ void divide_bulk(int64_t* rem, int b, int rel, bool a
   for (int s = 0; s < DQ; s++) x += (int64_t)(-q[s]) * (int64_t)ddv[s];
   const int64_t lo = x & (RADIX - 1);
   const int64_t hi = x >> DB;
-  int64_t hin = __shfl_up(hi, 1);
+  int64_t hin = lane_shr1(hi);
   if (lane == 0) hin = carry;
-  carry = __shfl(hi, 63);
+  carry = lane_read(hi, 63);
   if (act) rem[b + rel] = lo + hin;
-  if (top_group) hi_top = __shfl(hi, top_lane);
+  if (top_group) hi_top = lane_read(hi, top_lane);
 }
 
 // out = RNE(+-|num| 2^h / |d|) for one 64-lane workgroup: schoolbook long
@@ -525,6 +539,8 @@ __device__ __forceinline__ int divide_entry(int64_t* smem, const uint32_t* Sr, i
                             const uint32_t* Dp, int nd, int sh, int negd, int h, int32_t* out,
                             int64_t os, int cap, int32_t* out2, int64_t os2, int32_t* flags) {
   const int lane = threadIdx.x & 63;
+  nd = __builtin_amdgcn_readfirstlane(nd);
+  ns = __builtin_amdgcn_readfirstlane(ns);
   if (nd == 0) {
     for (int j = lane; j < cap; j += 64) { out[(int64_t)j * os] = 0; if (out2) out2[(int64_t)j * os2] = 0; }
     if (lane == 0) atomicOr(&flags[0], 4);
@@ -566,7 +582,8 @@ __device__ __forceinline__ int divide_entry(int64_t* smem, const uint32_t* Sr, i
   // every pass
   const int nbulk = nd - 3;
   const int NI = nbulk > 0 ? (nbulk + 63) / 64 : 0;
-  const int top_group = nbulk > 0 ? (nbulk - 1) / 64 : -1, top_lane = nbulk > 0 ? (nbulk - 1) & 63 : 0;
+  const int top_group = __builtin_amdgcn_readfirstlane(nbulk > 0 ? (nbulk - 1) / 64 : -1);
+  const int top_lane = __builtin_amdgcn_readfirstlane(nbulk > 0 ? (nbulk - 1) & 63 : 0);
   int32_t DDL[DNIR][DQ];
 #pragma unroll
   for (int i = 0; i < DNIR; i++)
@@ -950,7 +967,7 @@ k_column(const InstDesc* __restrict__ desc, int count, int c, int n_near, int fi
   const int32_t* Csrc = I.C + ck.coff + (int64_t)ck.CW;
   int32_t* Lr = (int32_t*)(Pd + W);            // L_{c-1}[fr], LW + 8
   int32_t* Cp = Lr + (ck.LW + 8);              // C_{c-1}[c], CW
-  constexpr int U = 4;
+  constexpr int U = 8;
   int32_t av[U], lv[U], cv[U];
   int64_t kv = 0;
   int nL = 0, nC = 0;

@@ -19,16 +19,19 @@ def _db():
     return json.load(open(GOLD)) if os.path.exists(GOLD) else {}
 
 
-@pytest.mark.parametrize("name", ["N200_b7_4_K2048", "N500_b1_K6144", "N500_b2_K6144",
-                                  "N500_b3_2_K6144", "N500_b1_2_K6144"])
-def test_fullsize_digests(hk, name):
+@pytest.mark.parametrize("name,la", [("N200_b7_4_K2048", -1), ("N500_b1_K6144", -1), ("N500_b2_K6144", -1),
+                                     ("N500_b3_2_K6144", -1), ("N500_b1_2_K6144", -1),
+                                     ("N200_b7_4_K2048", 0), ("N500_b1_K6144", 2), ("N500_b1_2_K6144", 2)])
+def test_fullsize_digests(hk, name, la):
+    """la: the look-ahead mode (-1: the one chosen by size)."""
     db = _db()
     if name not in db:
         pytest.skip("digest not generated")
     g = db[name]
     N, beta, K = g["N"], tuple(g["beta"]), g["K"]
-    log("full-size parity %s" % name)
+    log("full-size parity %s look-ahead %d" % (name, la))
     m = hk.Matrix(N, beta, K)
+    m.set_lookahead(la)
     m.factor(0)
     bad = []
     step = 50
