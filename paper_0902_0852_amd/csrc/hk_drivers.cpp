@@ -54,11 +54,17 @@ hk_status pivots_host(hk_matrix m, hipStream_t s, std::vector<MP>& out) {
   return HK_OK;
 }
 
+// R = prod_k t_k with t_k = floor(2^F dn_k / dold_k) and the running product
+// floored to F fractional bits after every factor.  Written as
+// t_k = 2^F + e_k, e_k = floor(2^F (dn_k - dold_k) / dold_k), and
+// floor(R t_k / 2^F) = R + floor(R e_k / 2^F): the same values, but the
+// pivots of nearby shifts differ only in their low digits, so e_k is short
+// and so are its division and product.
 MP pivot_ratio(const std::vector<MP>& dn, const std::vector<MP>& dold, int64_t F) {
   MP R = one_shl(F);
   for (size_t k = 0; k < dn.size(); k++) {
-    MP t = floor_div(shl(dn[k], F), dold[k]);
-    R = floor_shr(mul(R, t), F);
+    const MP e = floor_div(shl(sub(dn[k], dold[k]), F), dold[k]);
+    if (!e.is_zero()) R = add(R, floor_shr(mul(R, e), F));
   }
   return R;
 }
