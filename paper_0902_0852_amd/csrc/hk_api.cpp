@@ -136,6 +136,7 @@ bool make_plan(int N, int64_t bnum, int64_t bden, int K, Plan& P, std::string& e
   P.o_md = take(sizeof(uint32_t) * (size_t)(P.VW + 4));
   P.o_mdinfo = take(sizeof(int32_t) * 4);
   P.o_dots = take(sizeof(int64_t) * 4 * DOT_PARTS * (size_t)(2 * P.VW + 8));
+  P.o_sargs = take(sizeof(SweepArgs));
   P.o_desc = take(sizeof(InstDesc));
   P.total = o;
   return true;
@@ -174,6 +175,7 @@ DevPtrs dev_ptrs(const Plan& P, char* ws) {
   D.md = (uint32_t*)(ws + P.o_md);
   D.mdinfo = (int32_t*)(ws + P.o_mdinfo);
   D.dots = (int64_t*)(ws + P.o_dots);
+  D.sargs = (SweepArgs*)(ws + P.o_sargs);
   D.desc = (InstDesc*)(ws + P.o_desc);
   return D;
 }
@@ -399,6 +401,8 @@ hk_status hk_matrix_destroy(hk_matrix m) {
   for (auto& e : m->gev) (void)hipEventDestroy(e);
   if (m->gexec) (void)hipGraphExecDestroy(m->gexec);
   if (m->graph) (void)hipGraphDestroy(m->graph);
+  if (m->sgexec) (void)hipGraphExecDestroy(m->sgexec);
+  if (m->sgraph) (void)hipGraphDestroy(m->sgraph);
   if (m->gcap) (void)hipStreamDestroy(m->gcap);
   if (m->gcap2) (void)hipStreamDestroy(m->gcap2);
   if (m->s2) (void)hipStreamDestroy(m->s2);

@@ -1,7 +1,7 @@
 // Inverse iteration for every instance of a batch at once (not in the
 // paper): each instance on its own factorisation of M - sigma I, all of them
 // stepped together.  One iteration (right-hand side into the accumulators,
-// forward substitution column by column, diagonal division, second
+// forward substitution one launch per column, diagonal division, second
 // initialisation, backward substitution, the exact dots <v,y> and <v,v>, the
 // row of largest |y|, v <- RNE(y 2^K / max|y|)) is a fixed launch sequence
 // in which every launch covers all instances; it is captured once as a HIP
@@ -51,34 +51,11 @@ MP lazy64_to_mp(const int64_t* d, int n) {
   return sub(a, b);
 }
 
-// one inverse-iteration step for every instance, in launch order: right-hand
-// side, forward sweep column by column, diagonal, second right-hand side,
-// backward sweep, dots, largest row, normalisation
-hipError_t enqueue_iteration(const SweepArgs* da, const SweepShape& sh, int b, hipStream_t s) {
-  const int N = sh.maxN;
-  hipError_t e = launch_vinit_b(da, sh, 0, s);
-  int P = 0;
-  for (int k0 = 0; k0 < N && e == hipSuccess; k0 += b, P++) {
-    const int bb = std::min(b, N - k0);
-    for (int j = 0; j < bb && e == hipSuccess; j++) {
-      const int k = k0 + j;
-      if (j > 0) e = launch_vupdate_b(da, sh, 0, k0, k, k, k + 1, P & 1, s);
-      if (e == hipSuccess) e = launch_vfinalize_b(da, sh, k, (P + (j > 0 ? 1 : 0)) & 1, 0, s);
-    }
-    if (e == hipSuccess && k0 + bb < N) e = launch_vupdate_b(da, sh, 0, k0, k0 + bb, k0 + bb, -1, P & 1, s);
-  }
-  if (e == hipSuccess) e = launch_vdivide_b(da, sh, s);
-  if (e == hipSuccess) e = launch_vinit_b(da, sh, 1, s);
-  P = 0;
-  for (int k_hi = N; k_hi > 0 && e == hipSuccess; k_hi -= b, P++) {
-    const int k_lo = std::max(0, k_hi - b);
-    for (int j = 0; j < k_hi - k_lo && e == hipSuccess; j++) {
-      const int k = k_hi - 1 - j;
-      if (j > 0) e = launch_vupdate_b(da, sh, 1, k + 1, k_hi, k, k + 1, P & 1, s);
-      if (e == hipSuccess) e = launch_vfinalize_b(da, sh, k, (P + (j > 0 ? 1 : 0)) & 1, 1, s);
-    }
-    if (e == hipSuccess && k_lo > 0) e = launch_vupdate_b(da, sh, 1, k_lo, k_hi, 0, k_lo, P & 1, s);
-  }
+// one inverse-iteration step for every instance, in launch order: the solve
+// (right-hand side, forward sweep one launch per column, diagonal, second
+// right-hand side, backward sweep), dots, largest row, normalisation
+hipError_t enqueue_iteration(const SweepArgs* da, const SweepShape& sh, hipStream_t s) {
+  hipError_t e = enqueue_solve(da, sh, s);
   if (e == hipSuccess) e = launch_vdots_b(da, sh, s);
   if (e == hipSuccess) e = launch_vmax_b(da, sh, s);
   if (e == hipSuccess) e = launch_vscale_b(da, sh, s);
@@ -134,7 +111,7 @@ hk_status batch_inverse(Batch& bt, const std::vector<MP>& sigma, const std::vect
   e = hipStreamCreateWithFlags(&gh.cap, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipStreamBeginCapture(gh.cap, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    hipError_t ec = enqueue_iteration(da, sh, std::max(1, bt.panel), gh.cap);
+    hipError_t ec = enqueue_iteration(da, sh, gh.cap);
     const hipError_t e2 = hipStreamEndCapture(gh.cap, &gh.g);
     e = ec != hipSuccess ? ec : e2;
   }

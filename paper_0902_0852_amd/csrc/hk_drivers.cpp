@@ -527,34 +527,32 @@ hk_status hk_solve(hk_matrix m, const void* dev_rhs, void* dev_x, hipStream_t s)
   if (!m->factored) return dfail(HK_EINVAL, "no valid factorisation");
   const Plan& P = m->P;
   const DevPtrs& D = m->D;
-  const int N = P.N, h = P.h, b = m->panel;
-  hipError_t e = launch_fill32(D.flags, 16, 0, s);
-  // forward: acc = b 2^(h+g); z_k = RNE(acc_k / 2^h) column by column
-  if (e == hipSuccess) e = launch_vinit(P, D, (const int32_t*)dev_rhs, h + m->gbits, s);
-  int Pidx = 0;
-  for (int k0 = 0; k0 < N && e == hipSuccess; k0 += b, Pidx++) {
-    const int bb = std::min(b, N - k0);
-    for (int j = 0; j < bb && e == hipSuccess; j++) {
-      const int k = k0 + j;
-      if (j > 0) e = launch_vupdate(P, D, 0, k0, k, k, k + 1, Pidx & 1, s);
-      if (e == hipSuccess) e = launch_vfinalize(P, D, k, (Pidx + (j > 0 ? 1 : 0)) & 1, nullptr, s);
+  // the batched sweeps with one instance: forward (acc = b 2^(h+g), z_k =
+  // RNE(acc_k / 2^h) column by column), w_k = RNE(z_k 2^h / d_k), backward
+  // (acc = w 2^h, y_k = RNE(acc_k / 2^h), last row first)
+  // The launch sequence depends only on the plan, so it is captured once as a
+  // HIP graph and replayed; the operands travel in the uploaded arguments.
+  m->sweep = make_sweep_args(P, D, 1, m->gbits);
+  m->sweep.v = (int32_t*)dev_rhs;
+  m->sweep.y = (int32_t*)dev_x;
+  hipError_t e = hipSuccess;
+  if (!m->sgexec) {
+    const SweepShape sh = sweep_shape({&P});
+    if (!m->gcap) e = hipStreamCreateWithFlags(&m->gcap, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(m->gcap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      hipError_t ec = launch_fill32(D.flags, 16, 0, m->gcap);
+      if (ec == hipSuccess) ec = enqueue_solve(D.sargs, sh, m->gcap);
+      hipGraph_t g = nullptr;
+      const hipError_t e2 = hipStreamEndCapture(m->gcap, &g);
+      m->sgraph = g;
+      e = ec != hipSuccess ? ec : e2;
     }
-    if (e == hipSuccess && k0 + bb < N) e = launch_vupdate(P, D, 0, k0, k0 + bb, k0 + bb, N, Pidx & 1, s);
+    if (e == hipSuccess) e = hipGraphInstantiate(&m->sgexec, m->sgraph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return dfail(HK_EDEVICE, std::string("solve graph: ") + hipGetErrorString(e));
   }
-  // diagonal: w_k = RNE(z_k 2^h / d_k)
-  if (e == hipSuccess) e = launch_vdivide(P, D, s);
-  // backward: acc = w 2^h; y_k = RNE(acc_k / 2^h), last row first
-  if (e == hipSuccess) e = launch_vinit(P, D, D.wb, h, s);
-  Pidx = 0;
-  for (int k_hi = N; k_hi > 0 && e == hipSuccess; k_hi -= b, Pidx++) {
-    const int k_lo = std::max(0, k_hi - b);
-    for (int j = 0; j < k_hi - k_lo && e == hipSuccess; j++) {
-      const int k = k_hi - 1 - j;
-      if (j > 0) e = launch_vupdate(P, D, 1, k + 1, k_hi, k, k + 1, Pidx & 1, s);
-      if (e == hipSuccess) e = launch_vfinalize(P, D, k, (Pidx + (j > 0 ? 1 : 0)) & 1, (int32_t*)dev_x, s);
-    }
-    if (e == hipSuccess && k_lo > 0) e = launch_vupdate(P, D, 1, k_lo, k_hi, 0, k_lo, Pidx & 1, s);
-  }
+  e = hipMemcpyAsync(D.sargs, &m->sweep, sizeof(SweepArgs), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipGraphLaunch(m->sgexec, s);
   int32_t fl[16];
   if (e == hipSuccess) e = hipMemcpyAsync(fl, D.flags, sizeof fl, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);

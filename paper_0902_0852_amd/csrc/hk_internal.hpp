@@ -57,7 +57,7 @@ struct Plan {
   // byte offsets in the workspace
   size_t o_cols, o_items, o_A, o_K, o_C, o_L, o_S, o_D, o_dinfo, o_nC, o_nCs, o_nL,
       o_X, o_xs, o_flags, o_b32C, o_b32L, o_vec, o_LT, o_acc, o_kca, o_ub, o_us, o_wb, o_nU,
-      o_nUs, o_dv1, o_dv2, o_md, o_mdinfo, o_dots, o_desc, total;
+      o_nUs, o_dv1, o_dv2, o_md, o_mdinfo, o_dots, o_desc, o_sargs, total;
   int64_t ntri;
 };
 
@@ -85,6 +85,7 @@ hk_status build_matrix_impl(int N, hk_rational beta, int prec_bits, void* dev_ws
 
 // kernel launchers (hk_kernels.hip)
 struct InstDesc;
+struct SweepArgs;
 struct DevPtrs {
   ColInfo* cols; int32_t* itemStart;
   int32_t* A; int64_t* Kc; int32_t* C; int32_t* L; uint32_t* S; uint32_t* D; int32_t* dinfo;
@@ -94,6 +95,7 @@ struct DevPtrs {
   int32_t* nU; int32_t* nUs; int32_t* dv1; int32_t* dv2; uint32_t* md;
   int32_t* mdinfo; int64_t* dots;
   InstDesc* desc;
+  SweepArgs* sargs;   // the solve arguments of this matrix (hk_solve)
 };
 DevPtrs dev_ptrs(const Plan& P, char* ws);
 
@@ -140,12 +142,6 @@ hipError_t enqueue_factor(const BatchView& B, int b, int mode, hipStream_t s, hi
                           std::vector<std::pair<hipEvent_t, hipEvent_t>>* evs,
                           std::vector<hipEvent_t>* pool, size_t* evi, int* n_update);
 hipError_t launch_bits(const Plan& P, const DevPtrs& D, hipStream_t s);
-hipError_t launch_vinit(const Plan& P, const DevPtrs& D, const int32_t* src, int Sbits, hipStream_t s);
-hipError_t launch_vupdate(const Plan& P, const DevPtrs& D, int bwd, int k0, int k1, int i_lo,
-                          int i_hi, int rd, hipStream_t s);
-hipError_t launch_vfinalize(const Plan& P, const DevPtrs& D, int k, int rd, int32_t* out,
-                            hipStream_t s);
-hipError_t launch_vdivide(const Plan& P, const DevPtrs& D, hipStream_t s);
 
 // Everything the solve and inverse-iteration kernels need of one instance;
 // the batched launches take a device array of these (one per instance).
@@ -159,20 +155,23 @@ struct SweepArgs {
 };
 SweepArgs make_sweep_args(const Plan& P, const DevPtrs& D, int panel, int gbits);
 // launch shapes of a batch (maxima over its instances)
-struct SweepShape { int count = 0, maxN = 0, maxVA = 0, maxVW = 0; int64_t maxVAN = 0;
+struct SweepShape { int count = 0, maxN = 0, maxVA = 0, maxVW = 0, maxLW = 0; int64_t maxVAN = 0;
                     size_t shm_div = 0, shm_scale = 0; };
 SweepShape sweep_shape(const std::vector<const Plan*>& plans);
 // Batched inverse-iteration steps (hk_kernels.hip):
 //   vinit_b  stage 0: acc = v 2^(h+g); stage 1: acc = w 2^h
-//   vupdate_b, vfinalize_b  one column step of the forward (bwd 0) or backward (bwd 1) substitution
+//   vcol_b   one column step of the forward (bwd 0) or backward (bwd 1) substitution
 //   vdivide_b w = RNE(z 2^h / d) per row
 //   vdots_b  exact <v, y> and <v, v> as lazy int64 digits (dots)
 //   vmax_b   the row of largest |y|: its magnitude normalised (md, mdinfo = nd, sh, row)
 //   vscale_b v = RNE(y 2^K / max|y|)
 hipError_t launch_vinit_b(const SweepArgs* args, const SweepShape& sh, int stage, hipStream_t s);
-hipError_t launch_vupdate_b(const SweepArgs* args, const SweepShape& sh, int bwd, int k0, int k1, int i_lo,
-                            int i_hi, int rd, hipStream_t s);
-hipError_t launch_vfinalize_b(const SweepArgs* args, const SweepShape& sh, int k, int rd, int bwd, hipStream_t s);
+// one launch per column step j of a sweep (forward: column j, backward:
+// column maxN - 1 - j), with the previous column's update folded in
+hipError_t launch_vcol_b(const SweepArgs* args, const SweepShape& sh, int bwd, int j, hipStream_t s);
+// a whole solve (forward sweep, diagonal, backward sweep) of every instance:
+// rhs in SweepArgs::v, result in SweepArgs::y
+hipError_t enqueue_solve(const SweepArgs* args, const SweepShape& sh, hipStream_t s);
 hipError_t launch_vdivide_b(const SweepArgs* args, const SweepShape& sh, hipStream_t s);
 hipError_t launch_vdots_b(const SweepArgs* args, const SweepShape& sh, hipStream_t s);
 hipError_t launch_vmax_b(const SweepArgs* args, const SweepShape& sh, hipStream_t s);
@@ -206,6 +205,9 @@ struct hk_matrix_s {
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   int gpanel = 0, gla = -1, g_nupdate = 0;
+  hk::SweepArgs sweep;        // host copy of the solve arguments (kept alive for the upload)
+  hipGraph_t sgraph = nullptr;   // one captured solve, replayed by hk_solve
+  hipGraphExec_t sgexec = nullptr;
   int lookahead = -1;       // -1: chosen by size, else the look-ahead mode 0 / 1 / 2
 };
 

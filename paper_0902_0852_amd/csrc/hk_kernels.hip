@@ -1077,28 +1077,6 @@ __global__ void __launch_bounds__(64) k_vscale(int K, const uint32_t* __restrict
 // sum_s acc[s Npad + i] 2^(29 s) plus pending block carries), the same lazy
 // format and double-buffered carries as the matrix columns.
 
-// acc_i = src_i * 2^Sbits (src: N rows of VW balanced digits); carries cleared
-__global__ void k_vinit(int32_t* __restrict__ acc, int64_t* __restrict__ kc,
-                        const int32_t* __restrict__ src, int N, int Npad, int VA, int nbA, int VW,
-                        int Sbits) {
-  const int Sq = Sbits / DB, Sb = Sbits % DB;
-  const int64_t n = (int64_t)VA * Npad;
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int s = (int)(idx / Npad), i = (int)(idx - (int64_t)s * Npad);
-    int64_t v = 0;
-    if (i < N) {
-      const int j = s - Sq;
-      if (j >= 0 && j < VW) v += (((int64_t)src[(int64_t)i * VW + j]) << Sb) & (RADIX - 1);
-      if (j - 1 >= 0 && j - 1 < VW) v += (((int64_t)src[(int64_t)i * VW + j - 1]) << Sb) >> DB;
-    }
-    acc[idx] = (int32_t)v;
-  }
-  const int64_t nk = (int64_t)2 * nbA * Npad;
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < nk;
-       idx += (int64_t)gridDim.x * blockDim.x)
-    kc[idx] = 0;
-}
 
 // acc_i -= sum_{k0 <= k < k1} V_k[i] u_k for rows i in [i_lo, i_hi):
 //   forward (bwd = 0): V_k[i] = L_k[i] (column layout), rows i > k;
@@ -1155,70 +1133,8 @@ __device__ __forceinline__ void vupdate_item(const ColInfo* __restrict__ cols, i
               q + 1 < nbA ? kc + ((int64_t)(rd ^ 1) * nbA + q + 1) * Npad + i : nullptr, flags);
 }
 
-__global__ void __launch_bounds__(256) k_vupdate(const ColInfo* __restrict__ cols, int N, int bwd,
-                                                 int k0, int k1, int i_lo, int i_hi, int rd,
-                                                 int32_t* __restrict__ acc, int64_t* __restrict__ kc,
-                                                 int Npad, int nbA, const int32_t* __restrict__ ub,
-                                                 const int32_t* __restrict__ nU, int VW,
-                                                 const int32_t* __restrict__ Lb,
-                                                 const int32_t* __restrict__ LTb,
-                                                 const int32_t* __restrict__ nLw, int LWT,
-                                                 int32_t* __restrict__ flags) {
-  const int wave = uni(threadIdx.x >> 6);
-  const int T = (i_hi - i_lo + 63) / 64;
-  const int it = blockIdx.x * 4 + wave;
-  if (it >= T * nbA) return;
-  vupdate_item(cols, N, bwd, k0, k1, i_lo, i_hi, rd, it, acc, kc, Npad, nbA, ub, nU, VW, Lb, LTb, nLw, LWT,
-               flags);
-}
 
-// u_k = RNE(acc_k / 2^h) -> ub row k (balanced) and us row k (standard
-// magnitude), widths nU[k] and signed nUs[k]; optionally copied to out row k.
-// One 64-lane workgroup.
-__global__ void __launch_bounds__(64) k_vfinalize(int k, int rd, int h, const int32_t* __restrict__ acc,
-                                                  const int64_t* __restrict__ kc, int Npad, int VA,
-                                                  int nbA, int32_t* __restrict__ ub,
-                                                  uint32_t* __restrict__ us, int32_t* __restrict__ nU,
-                                                  int32_t* __restrict__ nUs, int VW,
-                                                  int32_t* __restrict__ out,
-                                                  int32_t* __restrict__ flags) {
-  extern __shared__ int64_t smem[];
-  int32_t* dg = (int32_t*)smem;
-  int32_t* ob = dg + (VA + 48);
-  int64_t* ca = (int64_t*)(ob + (VA + 48));
-  int64_t* cb = ca + (VA / WB + 8);
-  const FinOut f = wave_finalize(acc + k, Npad, VA, kc + (int64_t)rd * nbA * Npad + k, Npad, h,
-                                 ub + (int64_t)k * VW, us + (int64_t)k * VW, VW, flags, dg, ob, ca, cb);
-  if (threadIdx.x == 0) {
-    nU[k] = f.nbal;
-    nUs[k] = f.neg ? -f.nstd : f.nstd;
-    if (f.nbal > VW - WB) atomicOr(&flags[0], 32);
-  }
-  if (out) {
-    __syncthreads();
-    for (int j = threadIdx.x; j < VW; j += 64) out[(int64_t)k * VW + j] = ub[(int64_t)k * VW + j];
-  }
-}
 
-// u_k = RNE(acc_k / 2^h) of one instance by one wavefront (the batched
-// solves), with the counts and the optional copy of k_vfinalize.
-__device__ void sweep_finalize(const SweepArgs& a, int k, int rd, int64_t* smem) {
-  int32_t* dg = (int32_t*)smem;
-  int32_t* ob = dg + (a.VA + 48);
-  int64_t* ca = (int64_t*)(ob + (a.VA + 48));
-  int64_t* cb = ca + (a.VA / WB + 8);
-  const FinOut f = wave_finalize<false>(a.acc + k, a.Npad, a.VA, a.kc + (int64_t)rd * a.nbA * a.Npad + k,
-                                        a.Npad, a.h, a.ub + (int64_t)k * a.VW, a.us + (int64_t)k * a.VW, a.VW,
-                                        a.flags, dg, ob, ca, cb);
-  if ((threadIdx.x & 63) == 0) {
-    a.nU[k] = f.nbal;
-    a.nUs[k] = f.neg ? -f.nstd : f.nstd;
-    if (f.nbal > a.VW - WB) atomicOr(&a.flags[0], 32);
-  }
-  // each lane copies the digits it wrote itself
-  if (a.out)
-    for (int j = threadIdx.x & 63; j < a.VW; j += 64) a.out[(int64_t)k * a.VW + j] = a.ub[(int64_t)k * a.VW + j];
-}
 
 // ---------------------------------------------- batched inverse iteration
 // One SweepArgs per instance; blockIdx.y (or blockIdx.x for one-workgroup
@@ -1258,33 +1174,104 @@ __global__ void __launch_bounds__(64) k_vdivide_b(const SweepArgs* __restrict__ 
                    a.VW, nullptr, 0, a.flags);
 }
 
-// One column step of the solves for every instance of a batch (blockIdx.y):
-// the update of rows [i_lo, i_hi) (i_hi < 0: the instance's N) by columns
-// [k0, k1), both clipped to the instance's N, with the item layout of
-// k_vupdate.
-__global__ void __launch_bounds__(256) k_vupdate_b(const SweepArgs* __restrict__ args, int bwd, int k0, int k1,
-                                                   int i_lo, int i_hi, int rd) {
+
+// One column step of a substitution sweep for every instance (blockIdx.y),
+// with the previous column's update folded in, so a sweep is one launch per
+// column.  Forward (bwd = 0): column k, previous column p = k - 1; backward
+// (bwd = 1): column k, p = k + 1 (rows below are done first).  The first
+// wavefront of workgroup 0 subtracts the product V_p[k] u_p from acc_k while
+// normalising it (V = L, or L^T backward; the accumulator, its carries and
+// the operands read into LDS in one batch) and finalises u_k; every other
+// wavefront is an update item (vupdate_item) applying column p to the rows beyond k
+// (forward [k + 1, N), backward [0, k)).  Carry planes: the update at step j
+// reads plane (j - 1) & 1 and writes j & 1, so row k finds its carries in
+// plane (j + 1) & 1.  LDS (workgroup 0): finalisation, product digits, V and
+// u rows.
+__global__ void __launch_bounds__(256) k_vcol_b(const SweepArgs* __restrict__ args, int bwd, int k, int j,
+                                                int fin_bytes) {
+  extern __shared__ int64_t smem[];
   const SweepArgs& a = args[blockIdx.y];
   const int N = a.N;
-  const int k1e = min(k1, N), ihe = i_hi < 0 ? N : min(i_hi, N);
-  if (k1e <= k0 || ihe <= i_lo) return;
-  const int wave = uni(threadIdx.x >> 6);
-  const int T = (ihe - i_lo + 63) / 64;
-  const int it = blockIdx.x * 4 + wave;
-  if (it >= T * a.nbA) return;
-  vupdate_item(a.cols, N, bwd, k0, k1e, i_lo, ihe, rd, it, a.acc, a.kc, a.Npad, a.nbA, a.ub, a.nU, a.VW, a.L,
-               a.LT, a.nL, a.LWT, a.flags);
+  if (k >= N) return;
+  const int wave = uni(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int p = bwd ? k + 1 : k - 1;
+  const bool has_p = p >= 0 && p < N;
+  if (blockIdx.x > 0 || wave > 0) {
+    if (!has_p) return;
+    const int it = (int)blockIdx.x * 4 + wave - 1;
+    const int i_lo = bwd ? 0 : k + 1, i_hi = bwd ? k : N;
+    if (i_hi <= i_lo) return;
+    const int T = (i_hi - i_lo + 63) / 64;
+    if (it >= T * a.nbA) return;
+    vupdate_item(a.cols, N, bwd, p, p + 1, i_lo, i_hi, (j - 1) & 1, it, a.acc, a.kc, a.Npad, a.nbA, a.ub, a.nU,
+                 a.VW, a.L, a.LT, a.nL, a.LWT, a.flags);
+    return;
+  }
+  const int VA = a.VA;
+  int32_t* dg = (int32_t*)smem;
+  int32_t* ob = dg + (VA + 48);
+  int64_t* ca = (int64_t*)(ob + (VA + 48));
+  int64_t* cb = ca + (VA / FIN_FB + 8);
+  int64_t* Pd = cb + (VA / FIN_FB + 8);        // product digits, VA
+  const int rd = (j + 1) & 1;
+  const int64_t* Kc = a.kc + (int64_t)rd * a.nbA * a.Npad + k;
+  // the operands of the row's update by column p: V digits (stride P) and u_p
+  const ColInfo cp = a.cols[has_p ? p : k];
+  const int32_t* Vsrc = bwd ? a.LT + cp.ltoff + k : a.L + cp.loff + 1;
+  const int Vstride = bwd ? cp.PT : cp.R;
+  const int Vcap = bwd ? min(a.cols[k].LW, a.LWT) : cp.LW;
+  int32_t* Lr = (int32_t*)(Pd + VA);           // Vcap + 8
+  int32_t* Up = Lr + (Vcap + 8);               // VW
+  constexpr int U = 4;
+  int32_t av[U], lv[U], uv[U];
+  int64_t kv = 0;
+  int nL = 0, nC = 0;
+#pragma unroll
+  for (int u = 0; u < U; u++) {
+    const int x = lane + 64 * u;
+    av[u] = x < VA ? a.acc[(int64_t)x * a.Npad + k] : 0;
+    lv[u] = has_p && x < Vcap ? Vsrc[(int64_t)x * Vstride] : 0;
+    uv[u] = has_p && x < a.VW ? a.ub[(int64_t)p * a.VW + x] : 0;
+  }
+  kv = lane > 0 && lane < a.nbA ? Kc[(int64_t)lane * a.Npad] : 0;
+  if (has_p) {
+    nL = min(a.nL[bwd ? tri_index(N, k, p) : tri_index(N, p, k)], Vcap - 2 * WB);
+    nL = min(nL, a.LWT - 2 * WB);
+    nC = min(a.nU[p], a.VW - WB);
+  }
+#pragma unroll
+  for (int u = 0; u < U; u++) {
+    const int x = lane + 64 * u;
+    if (x < VA) dg[x] = av[u];
+    if (has_p && x < Vcap) Lr[x] = lv[u];
+    if (has_p && x < a.VW) Up[x] = uv[u];
+  }
+  if (lane < a.nbA) cb[lane] = kv;
+  for (int x = lane + 64 * U; x < VA; x += 64) dg[x] = a.acc[(int64_t)x * a.Npad + k];
+  for (int q = lane + 64; q < a.nbA; q += 64) cb[q] = Kc[(int64_t)q * a.Npad];
+  const int64_t* Psub = nullptr;
+  if (has_p) {
+    for (int x = lane + 64 * U; x < Vcap; x += 64) Lr[x] = Vsrc[(int64_t)x * Vstride];
+    for (int x = lane + 64 * U; x < a.VW; x += 64) Up[x] = a.ub[(int64_t)p * a.VW + x];
+    for (int x = Vcap + lane; x < Vcap + 8; x += 64) Lr[x] = 0;
+    lds_sync<false>();
+    if (VA <= 128) near_product<2, false>(Lr, nL, Up, nC, VA, Pd, a.flags);
+    else near_product<8, false>(Lr, nL, Up, nC, VA, Pd, a.flags);
+    Psub = Pd;
+  }
+  lds_sync<false>();
+  const FinOut f = wave_finalize<false, FIN_FB, true>(a.acc + k, a.Npad, VA, Kc, a.Npad, a.h, a.ub + (int64_t)k * a.VW,
+                                                      a.us + (int64_t)k * a.VW, a.VW, a.flags, dg, ob, ca, cb, Psub);
+  if (lane == 0) {
+    a.nU[k] = f.nbal;
+    a.nUs[k] = f.neg ? -f.nstd : f.nstd;
+    if (f.nbal > a.VW - WB) atomicOr(&a.flags[0], 32);
+  }
+  // the backward sweep's result; each lane copies the digits it wrote itself
+  if (bwd && a.y)
+    for (int x = lane; x < a.VW; x += 64) a.y[(int64_t)k * a.VW + x] = a.ub[(int64_t)k * a.VW + x];
 }
 
-// u_k = RNE(acc_k / 2^h) for every instance (blockIdx.x) with k < N; the
-// backward sweep also copies it to y
-__global__ void __launch_bounds__(64) k_vfinalize_b(const SweepArgs* __restrict__ args, int k, int rd, int bwd) {
-  extern __shared__ int64_t smem[];
-  SweepArgs a = args[blockIdx.x];
-  if (k >= a.N) return;
-  a.out = bwd ? a.y : nullptr;
-  sweep_finalize(a, k, rd, smem);
-}
 
 // <v, y> (which = 0) and <v, v> (which = 1) exactly, split over DOT_PARTS
 // workgroups per dot (each a subset of the rows; the host adds the parts):
@@ -1408,20 +1395,6 @@ __global__ void __launch_bounds__(64) k_vscale_b(const SweepArgs* __restrict__ a
                    a.mdinfo[1], 0, a.K, a.v + (int64_t)i * a.VW, 1, a.VW, nullptr, 0, a.flags);
 }
 
-// w_k = RNE(z_k 2^h / d_k) for every k (one 64-lane workgroup each)
-__global__ void __launch_bounds__(64) k_vdivide(const ColInfo* __restrict__ cols, int h,
-                                                const uint32_t* __restrict__ us,
-                                                const int32_t* __restrict__ nUs,
-                                                const uint32_t* __restrict__ Dd,
-                                                const int32_t* __restrict__ dinfo, int VW,
-                                                int32_t* __restrict__ wb, int32_t* __restrict__ flags) {
-  extern __shared__ int64_t smem[];
-  const int k = blockIdx.x;
-  const int nsg = nUs[k];
-  divide_entry(smem, us + (int64_t)k * VW, nsg < 0 ? -nsg : nsg, nsg < 0, Dd + cols[k].doff,
-               dinfo[4 * k], dinfo[4 * k + 1], dinfo[4 * k + 2], h, wb + (int64_t)k * VW, 1, VW,
-               nullptr, 0, flags);
-}
 
 // exact ceil(bits/32) of every L entry (for the algorithmic work count)
 __global__ void k_bitsL(const ColInfo* __restrict__ cols, int N, const int32_t* __restrict__ Lb,
@@ -1557,28 +1530,6 @@ hipError_t launch_gather_pivots_b(const BatchView& B, int32_t* out, int ld, hipS
                      B.maxN, ld, out);
   return hipGetLastError();
 }
-hipError_t launch_vinit(const Plan& P, const DevPtrs& D, const int32_t* src, int Sbits, hipStream_t s) {
-  const int64_t n = (int64_t)P.VA * P.Npad;
-  hipLaunchKernelGGL(k_vinit, dim3(blocks_for(n, 256)), dim3(256), 0, s, D.acc, D.kca, src, P.N,
-                     P.Npad, P.VA, P.VA / WB, P.VW, Sbits);
-  return hipGetLastError();
-}
-hipError_t launch_vupdate(const Plan& P, const DevPtrs& D, int bwd, int k0, int k1, int i_lo,
-                          int i_hi, int rd, hipStream_t s) {
-  if (i_hi <= i_lo || k1 <= k0) return hipSuccess;
-  const int T = (i_hi - i_lo + 63) / 64;
-  const int64_t items = (int64_t)T * (P.VA / WB);
-  hipLaunchKernelGGL(k_vupdate, dim3((int)((items + 3) / 4)), dim3(256), 0, s, D.cols, P.N, bwd, k0,
-                     k1, i_lo, i_hi, rd, D.acc, D.kca, P.Npad, P.VA / WB, D.ub, D.nU, P.VW, D.L, D.LT,
-                     D.nL, P.LWT, D.flags);
-  return hipGetLastError();
-}
-hipError_t launch_vfinalize(const Plan& P, const DevPtrs& D, int k, int rd, int32_t* out,
-                            hipStream_t s) {
-  hipLaunchKernelGGL(k_vfinalize, dim3(1), dim3(64), fin_shm(P.VA), s, k, rd, P.h, D.acc, D.kca, P.Npad, P.VA,
-                     P.VA / WB, D.ub, D.us, D.nU, D.nUs, P.VW, out, D.flags);
-  return hipGetLastError();
-}
 SweepArgs make_sweep_args(const Plan& P, const DevPtrs& D, int panel, int gbits) {
   SweepArgs a;
   memset(&a, 0, sizeof a);
@@ -1598,6 +1549,7 @@ SweepShape sweep_shape(const std::vector<const Plan*>& plans) {
     sh.maxVA = std::max(sh.maxVA, p->VA);
     sh.maxVW = std::max(sh.maxVW, p->VW);
     sh.maxVAN = std::max(sh.maxVAN, (int64_t)p->VA * p->Npad);
+    sh.maxLW = std::max(sh.maxLW, std::max(p->LWT, p->maxW + 32));
     sh.shm_div = std::max(sh.shm_div, divide_shm(p->h, p->VW, p->maxW + 2));
     sh.shm_scale = std::max(sh.shm_scale, divide_shm(p->K, p->VW, p->VW + 2));
   }
@@ -1608,19 +1560,24 @@ hipError_t launch_vinit_b(const SweepArgs* args, const SweepShape& sh, int stage
   hipLaunchKernelGGL(k_vinit_b, dim3(bx, sh.count), dim3(256), 0, s, args, stage);
   return hipGetLastError();
 }
-hipError_t launch_vupdate_b(const SweepArgs* args, const SweepShape& sh, int bwd, int k0, int k1, int i_lo,
-                            int i_hi, int rd, hipStream_t s) {
-  // rows of the widest instance bound the item count
-  const int rows = (i_hi < 0 ? sh.maxN : std::min(i_hi, sh.maxN)) - i_lo;
-  if (rows <= 0 || k1 <= k0) return hipSuccess;
-  const int64_t items = (int64_t)((rows + 63) / 64) * (sh.maxVA / WB);
-  hipLaunchKernelGGL(k_vupdate_b, dim3((unsigned)((items + 3) / 4), sh.count), dim3(256), 0, s, args, bwd, k0, k1,
-                     i_lo, i_hi, rd);
+hipError_t launch_vcol_b(const SweepArgs* args, const SweepShape& sh, int bwd, int j, hipStream_t s) {
+  const int k = bwd ? sh.maxN - 1 - j : j;
+  // far rows of the widest instance bound the item count
+  const int rows = bwd ? k : sh.maxN - k - 1;
+  const int64_t items = j > 0 && rows > 0 ? (int64_t)((rows + 63) / 64) * (sh.maxVA / WB) : 0;
+  const size_t fin = (fin_shm(sh.maxVA, FIN_FB) + sizeof(int64_t) * (size_t)sh.maxVA +
+                      sizeof(int32_t) * (size_t)(sh.maxLW + 8 + sh.maxVW) + 7) / 8 * 8;
+  hipLaunchKernelGGL(k_vcol_b, dim3((unsigned)((items + 1 + 3) / 4), sh.count), dim3(256), fin, s, args, bwd, k,
+                     j, (int)fin);
   return hipGetLastError();
 }
-hipError_t launch_vfinalize_b(const SweepArgs* args, const SweepShape& sh, int k, int rd, int bwd, hipStream_t s) {
-  hipLaunchKernelGGL(k_vfinalize_b, dim3(sh.count), dim3(64), fin_shm(sh.maxVA), s, args, k, rd, bwd);
-  return hipGetLastError();
+hipError_t enqueue_solve(const SweepArgs* args, const SweepShape& sh, hipStream_t s) {
+  hipError_t e = launch_vinit_b(args, sh, 0, s);
+  for (int j = 0; j < sh.maxN && e == hipSuccess; j++) e = launch_vcol_b(args, sh, 0, j, s);
+  if (e == hipSuccess) e = launch_vdivide_b(args, sh, s);
+  if (e == hipSuccess) e = launch_vinit_b(args, sh, 1, s);
+  for (int j = 0; j < sh.maxN && e == hipSuccess; j++) e = launch_vcol_b(args, sh, 1, j, s);
+  return e;
 }
 hipError_t launch_vdivide_b(const SweepArgs* args, const SweepShape& sh, hipStream_t s) {
   hipLaunchKernelGGL(k_vdivide_b, dim3(sh.maxN, sh.count), dim3(64), sh.shm_div, s, args);
@@ -1636,11 +1593,6 @@ hipError_t launch_vmax_b(const SweepArgs* args, const SweepShape& sh, hipStream_
 }
 hipError_t launch_vscale_b(const SweepArgs* args, const SweepShape& sh, hipStream_t s) {
   hipLaunchKernelGGL(k_vscale_b, dim3(sh.maxN, sh.count), dim3(64), sh.shm_scale, s, args);
-  return hipGetLastError();
-}
-hipError_t launch_vdivide(const Plan& P, const DevPtrs& D, hipStream_t s) {
-  hipLaunchKernelGGL(k_vdivide, dim3(P.N), dim3(64), divide_shm(P.h, P.VW, P.maxW + 2), s, D.cols, P.h, D.us,
-                     D.nUs, D.D, D.dinfo, P.VW, D.wb, D.flags);
   return hipGetLastError();
 }
 hipError_t launch_vscale(const Plan& P, const DevPtrs& D, const uint32_t* md, int nd, int sh,
