@@ -746,93 +746,6 @@ __device__ __forceinline__ void normalise_divisor(const uint32_t* S, int n, int 
   }
 }
 
-// Column c in one launch: C = RNE(A / 2^h) for every row r in [c, N) and
-// L = RNE(C 2^h / d) for r > c.  One 128-lane workgroup per (instance, row):
-// wavefront 0 finalises row r while wavefront 1 finalises the pivot row c
-// into LDS (the workgroup of row c writes the pivot out, with its normalised
-// divisor digits and the inertia flags), then wavefront 0 divides row r by
-// the pivot.  LDS: two finalisation regions of fin_bytes, the pivot's digits
-// (piv_bytes), the division.
-__global__ void __launch_bounds__(128) k_fdiv(const InstDesc* __restrict__ desc, int count, int c, int rd,
-                                              int fin_bytes, int piv_bytes) {
-  extern __shared__ int64_t smem[];
-  int bid = blockIdx.x, inst = -1;
-  for (int i = 0; i < count; i++) {
-    const int n = max(0, desc[i].N - c);
-    if (bid < n) { inst = i; break; }
-    bid -= n;
-  }
-  if (inst < 0) return;
-  const InstDesc I = desc[inst];
-  if (!I.active) return;
-  const int N = I.N;
-  const int r = c + bid, lr = r - c;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const ColInfo cc = I.cols[c];
-  const int W = cc.W;
-  char* base = (char*)smem;
-  int32_t* dg = (int32_t*)(base + wave * fin_bytes);
-  int32_t* ob = dg + (W + 48);
-  int64_t* ca = (int64_t*)(ob + (W + 48));
-  int64_t* cb = ca + (W / FIN_FB + 8);
-  int32_t* pC = (int32_t*)(base + 2 * fin_bytes);
-  uint32_t* pS = (uint32_t*)(pC + cc.CW);
-  uint32_t* pD = pS + cc.CW;
-  int* pinfo = (int*)(pD + cc.CW);           // pivot: standard digits, shift, sign
-  int64_t* dsm = (int64_t*)(base + 2 * fin_bytes + piv_bytes);
-  const int64_t* Kc = I.Kc + cc.koff + (int64_t)rd * cc.nb * cc.R;
-  uint32_t* Srow = I.S + cc.soff + (int64_t)lr * cc.CW;
-  FinOut f;
-  f.nstd = 0;
-  f.neg = 0;
-  if (wave == 0) {
-    f = wave_finalize<false, FIN_FB>(I.A + cc.aoff + lr, cc.R, W, Kc + lr, cc.R, I.h,
-                             I.C + cc.coff + (int64_t)lr * cc.CW, Srow, cc.CW, I.flags, dg, ob, ca, cb);
-    const int64_t ti = tri_index(N, c, r);
-    if (lane == 0) {
-      I.nC[ti] = f.nbal;
-      I.nCs[ti] = f.neg ? -f.nstd : f.nstd;
-      I.b32C[ti] = (f.bits + 31) / 32;
-    }
-    if (r == c) {
-      const int sh = f.nstd > 0 ? 28 - (31 - __clz(f.topv)) : 0;
-      if (lane == 0) {
-        if (f.nstd == 0 || f.neg) {
-          atomicMin(&I.flags[1], c);
-          if (f.nstd > 0 && f.neg) atomicAdd(&I.flags[2], 1);
-        }
-        I.dinfo[4 * c] = f.nstd;
-        I.dinfo[4 * c + 1] = sh;
-        I.dinfo[4 * c + 2] = f.nstd > 0 ? f.neg : 0;
-      }
-      // this wavefront's own standard digits, written above by other lanes
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      normalise_divisor(Srow, f.nstd, sh, I.D + cc.doff);
-    }
-  } else if (r != c) {
-    const FinOut p = wave_finalize<false, FIN_FB>(I.A + cc.aoff, cc.R, W, Kc, cc.R, I.h, pC, pS, cc.CW, I.flags,
-                                          dg, ob, ca, cb);
-    const int sh = p.nstd > 0 ? 28 - (31 - __clz(p.topv)) : 0;
-    lds_sync<false>();
-    normalise_divisor(pS, p.nstd, sh, pD);
-    if (lane == 0) {
-      pinfo[0] = p.nstd;
-      pinfo[1] = sh;
-      pinfo[2] = p.nstd > 0 ? p.neg : 0;
-    }
-  }
-  __syncthreads();
-  if (r == c || wave != 0) return;
-  const ColInfo cr = I.cols[r];
-  const int n = divide_entry<false>(dsm, Srow, f.nstd, f.neg, pD, pinfo[0], pinfo[1], pinfo[2], I.h,
-                                    I.L + cc.loff + lr, cc.R, cc.LW, I.LT + cr.ltoff + c, cr.PT, I.flags);
-  if (lane == 0) {
-    I.nL[tri_index(N, c, r)] = n;
-    if (n > cc.LW - 2 * WB) atomicOr(&I.flags[0], 8);
-  }
-}
 
 template <int PB>
 __device__ __forceinline__ void renorm_pb(int64_t* acc) {
@@ -902,21 +815,25 @@ __device__ void near_product(const int32_t* Lr, int nL, const int32_t* Cp, int n
   }
 }
 
-// One launch per column c (the in-kernel look-ahead schedule, rank-1
-// updates): workgroups [0, n_near) handle the rows r in [c, N) of column c
-// like k_fdiv, each first subtracting the update of its entry, and of the
-// pivot entry, by column c - 1 (L_{c-1}[r] C_{c-1}[c], formed in LDS) while
-// loading the accumulator; the remaining workgroups apply the update by
-// column c - 1 to the columns [c + 1, N), two items each.  The next launch
-// finds every column it needs complete.  LDS: the pivot's digits
-// (piv_bytes), then either the two product + finalisation regions
-// (fin_bytes each) or the division.  Three waves per SIMD (at most 168
-// registers, two divisor groups in registers) keep the update workgroups of
-// the launch from starving for occupancy.
-__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3)))
-k_column(const InstDesc* __restrict__ desc, int count, int c, int n_near, int fin_bytes, int piv_bytes) {
+// One column c in one launch: C = RNE(A / 2^h) for every row r in [c, N) and
+// L = RNE(C 2^h / d) for r > c.  Workgroups [0, n_near) are the rows: one
+// 128-lane workgroup per (instance, row); wavefront 0 finalises row r while
+// wavefront 1 finalises the pivot row c into LDS (the workgroup of row c
+// writes the pivot out, with its normalised divisor digits and the inertia
+// flags), then wavefront 0 divides row r by the pivot.  With upd (the
+// in-kernel look-ahead schedule, rank-1 updates), both first subtract the
+// update of their entry by column c - 1 (L_{c-1}[r] C_{c-1}[c], formed in
+// LDS) while normalising, and the remaining workgroups apply the update by
+// column c - 1 to the columns [c + 1, N), two items each; the next launch
+// finds every column it needs complete.  The accumulator, its carries
+// (plane rd) and the update's operands are read into LDS in one batch of
+// loads.  LDS: the pivot's digits (piv_bytes), then either the two product +
+// finalisation regions (fin_bytes each) or the division.
+template <int DNIR>
+__device__ __forceinline__ void column_step(const InstDesc* __restrict__ desc, int count, int c, int n_near,
+                                            int rd, int upd, int fin_bytes, int piv_bytes) {
   if ((int)blockIdx.x >= n_near) {
-    if (c > 0)
+    if (upd && c > 0)
       update_item(desc, count, c - 1, 1, UPD_FAR, (c - 1) & 1,
                   ((int)blockIdx.x - n_near) * 2 + uni(threadIdx.x >> 6));
     return;
@@ -949,8 +866,7 @@ k_column(const InstDesc* __restrict__ desc, int count, int c, int n_near, int fi
   int64_t* cb = ca + (W / FIN_FB + 8);
   int64_t* Pd = cb + (W / FIN_FB + 8);           // product digits, W
   int64_t* dsm = (int64_t*)(base + piv_bytes);
-  // pending carries of column c: left by the update by column c - 2
-  const int64_t* Kc = I.Kc + cc.koff + (int64_t)((c + 1) & 1) * cc.nb * cc.R;
+  const int64_t* Kc = I.Kc + cc.koff + (int64_t)rd * cc.nb * cc.R;
   uint32_t* Srow = I.S + cc.soff + (int64_t)lr * cc.CW;
   // the row this wavefront finalises
   const int fr = wave == 0 ? r : c;
@@ -961,7 +877,7 @@ k_column(const InstDesc* __restrict__ desc, int count, int c, int n_near, int fi
   // which are zero filled), all requested before the first store to LDS so
   // that their latencies overlap
   const int flr = fr - c;
-  const bool upd = work && c > 0;
+  const bool updr = upd && work && c > 0;
   const ColInfo ck = I.cols[c > 0 ? c - 1 : 0];
   const int32_t* Lsrc = I.L + ck.loff + (fr - (c - 1));
   const int32_t* Csrc = I.C + ck.coff + (int64_t)ck.CW;
@@ -976,11 +892,11 @@ k_column(const InstDesc* __restrict__ desc, int count, int c, int n_near, int fi
     for (int u = 0; u < U; u++) {
       const int x = lane + 64 * u;
       av[u] = x < W ? I.A[cc.aoff + (int64_t)x * cc.R + flr] : 0;
-      lv[u] = upd && x < ck.LW ? Lsrc[(int64_t)x * ck.R] : 0;
-      cv[u] = upd && x < ck.CW ? Csrc[x] : 0;
+      lv[u] = updr && x < ck.LW ? Lsrc[(int64_t)x * ck.R] : 0;
+      cv[u] = updr && x < ck.CW ? Csrc[x] : 0;
     }
     kv = lane > 0 && lane < cc.nb ? Kc[(int64_t)lane * cc.R + flr] : 0;
-    if (upd) {
+    if (updr) {
       nL = min(I.nL[tri_index(N, c - 1, fr)], ck.LW);
       nC = min(I.nC[tri_index(N, c - 1, c)], ck.CW);
     }
@@ -988,19 +904,19 @@ k_column(const InstDesc* __restrict__ desc, int count, int c, int n_near, int fi
     for (int u = 0; u < U; u++) {
       const int x = lane + 64 * u;
       if (x < W) dg[x] = av[u];
-      if (upd && x < ck.LW) Lr[x] = lv[u];
-      if (upd && x < ck.CW) Cp[x] = cv[u];
+      if (updr && x < ck.LW) Lr[x] = lv[u];
+      if (updr && x < ck.CW) Cp[x] = cv[u];
     }
     if (lane < cc.nb) cb[lane] = kv;
     for (int x = lane + 64 * U; x < W; x += 64) dg[x] = I.A[cc.aoff + (int64_t)x * cc.R + flr];
     for (int q = lane + 64; q < cc.nb; q += 64) cb[q] = Kc[(int64_t)q * cc.R + flr];
-    if (upd) {
+    if (updr) {
       for (int x = lane + 64 * U; x < ck.LW; x += 64) Lr[x] = Lsrc[(int64_t)x * ck.R];
       for (int x = lane + 64 * U; x < ck.CW; x += 64) Cp[x] = Csrc[x];
       for (int x = ck.LW + lane; x < ck.LW + 8; x += 64) Lr[x] = 0;
     }
   }
-  if (upd) {
+  if (updr) {
     lds_sync<false>();
     if (W <= 128) near_product<2, false>(Lr, nL, Cp, nC, W, Pd, I.flags);
     else near_product<8, false>(Lr, nL, Cp, nC, W, Pd, I.flags);
@@ -1051,12 +967,26 @@ k_column(const InstDesc* __restrict__ desc, int count, int c, int n_near, int fi
   __syncthreads();
   if (r == c || wave != 0) return;
   const ColInfo cr = I.cols[r];
-  const int n = divide_entry<false, 2>(dsm, oS, f.nstd, f.neg, pD, pinfo[0], pinfo[1], pinfo[2], I.h,
+  const int n = divide_entry<false, DNIR>(dsm, oS, f.nstd, f.neg, pD, pinfo[0], pinfo[1], pinfo[2], I.h,
                                     I.L + cc.loff + lr, cc.R, cc.LW, I.LT + cr.ltoff + c, cr.PT, I.flags);
   if (lane == 0) {
     I.nL[tri_index(N, c, r)] = n;
     if (n > cc.LW - 2 * WB) atomicOr(&I.flags[0], 8);
   }
+}
+
+// The in-kernel look-ahead schedule: three waves per SIMD (at most 168
+// registers, two divisor groups in registers) keep the update workgroups of
+// the launch from starving for occupancy.
+__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3)))
+k_column(const InstDesc* __restrict__ desc, int count, int c, int n_near, int fin_bytes, int piv_bytes) {
+  column_step<2>(desc, count, c, n_near, (c + 1) & 1, 1, fin_bytes, piv_bytes);
+}
+
+// Finalisation and division alone (the update came from k_update launches).
+__global__ void __launch_bounds__(128) k_fdiv(const InstDesc* __restrict__ desc, int count, int c, int rd,
+                                              int n_near, int fin_bytes, int piv_bytes) {
+  column_step<4>(desc, count, c, n_near, rd, 0, fin_bytes, piv_bytes);
 }
 
 // v_i = RNE(y_i 2^K / m) with the common divisor m (standard digits of m 2^sh
@@ -1495,13 +1425,14 @@ hipError_t launch_fdiv(const BatchView& B, int c, int rd, hipStream_t s) {
     if (c < p->N) {
       const ColInfo& cc = p->cols[c];
       rows += p->N - c;
-      fin = std::max(fin, fin_shm(cc.W, FIN_FB));
-      piv = std::max(piv, (sizeof(uint32_t) * (3 * (size_t)cc.CW + 4) + 7) / 8 * 8);
+      fin = std::max(fin, fin_shm(cc.W, FIN_FB) + sizeof(int64_t) * (size_t)cc.W);
+      piv = std::max(piv, (sizeof(uint32_t) * (4 * (size_t)cc.CW + 4) + 7) / 8 * 8);
       div = std::max(div, divide_shm(p->h, cc.CW, cc.W + 2));
     }
+  fin = (fin + 7) / 8 * 8;
   if (rows <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fdiv, dim3((unsigned)rows), dim3(128), 2 * fin + piv + div, s, B.ddesc,
-                     (int)B.plans.size(), c, rd, (int)fin, (int)piv);
+  hipLaunchKernelGGL(k_fdiv, dim3((unsigned)rows), dim3(128), piv + std::max(2 * fin, div), s, B.ddesc,
+                     (int)B.plans.size(), c, rd, (int)rows, (int)fin, (int)piv);
   return hipGetLastError();
 }
 hipError_t launch_column(const BatchView& B, int c, hipStream_t s) {
