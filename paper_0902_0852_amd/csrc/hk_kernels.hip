@@ -36,6 +36,20 @@ __device__ __forceinline__ int wave_max(int v) {
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// 64-bit lane moves: the value of lane i - 1 (lane 0: 0) by a DPP wave
+// shift, and the value of one (uniform) lane
+__device__ __forceinline__ int64_t lane_shr1(int64_t v) {
+  const int32_t lo = __builtin_amdgcn_update_dpp(0, (int32_t)v, 0x138, 0xf, 0xf, false);
+  const int32_t hi = __builtin_amdgcn_update_dpp(0, (int32_t)(v >> 32), 0x138, 0xf, 0xf, false);
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+__device__ __forceinline__ int64_t lane_read(int64_t v, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int32_t)v, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int32_t)(v >> 32), l);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+
 // wavefront-uniform operand digits are read through the constant address
 // space so that they arrive by scalar loads into SGPRs
 typedef const __attribute__((address_space(4))) int32_t cint32_t;
@@ -480,25 +494,188 @@ __device__ FinOut wave_finalize(const int32_t* Ap, int64_t as, int W, const int6
   return f;
 }
 
+// Carries between the register blocks of one number: lane l holds digits
+// [R l, R l + R) (l < nbl), already normalised within its block; c is
+// the carry entering the block.  Each round every block absorbs its carry
+// (balanced or standard digits) and hands its own to the lane above by a DPP
+// wave shift, until no carry crosses a boundary below the top block.
+// Returns the total carry out of the top block.
+template <bool BAL, int R>
+__device__ __forceinline__ int64_t reg_resolve(int64_t* d, int64_t c, int nbl) {
+  const int lane = threadIdx.x & 63;
+  int64_t top = 0;
+  for (int round = 0; round <= 64; round++) {
+    if (!__any(c != 0)) break;
+    int64_t v = c;
+    if (c != 0) {
+      v = 0;
+      int64_t t = c;
+#pragma unroll
+      for (int m = 0; m < R; m++) {
+        t += d[m];
+        const int64_t nd = BAL ? (int64_t)balanced29(t) : (t & (RADIX - 1));
+        d[m] = nd;
+        t = (t - nd) >> DB;
+      }
+      v = t;
+    }
+    top += lane_read(v, nbl - 1);
+    c = lane_shr1(lane < nbl - 1 ? v : 0);
+  }
+  return top;
+}
+
+// wave_finalize with the number in registers (W and the W - h/29 + 1 output
+// digits at most 64 R): the same
+// steps (block normalisation, sign, magnitude, shift by h with RNE, standard
+// and balanced outputs) and the same results and flags, but every carry
+// moves between lanes by DPP shifts instead of LDS rounds.  Inputs as in
+// wave_finalize's PRE form (lazy digits in dg, pending 16-block carries in
+// cb, optional subtrahend Psub); ob (W + 48 int32) is scratch for the shift.
+template <bool BLK, int R>
+__device__ __forceinline__ FinOut wave_finalize_reg(int W, int h, int32_t* Cr, uint32_t* Sr, int cap, int32_t* flags,
+                                    const int32_t* dg, int32_t* ob, const int64_t* cb,
+                                    const int64_t* Psub, uint32_t* Sl) {
+  const int lane = threadIdx.x & 63;
+  const int nbl = W / R;
+  const bool own = lane < nbl;
+  int64_t d[R];
+  // 1. load, block normalisation to balanced digits, carries between blocks
+  {
+    int64_t t = 0;
+    const int s0 = R * lane;
+    if (own && s0 >= WB && s0 % WB == 0) t = cb[s0 / WB];
+#pragma unroll
+    for (int m = 0; m < R; m++) {
+      int64_t x = own ? (int64_t)dg[s0 + m] : 0;
+      if (Psub && own) x -= Psub[s0 + m];
+      t += x;
+      d[m] = balanced29(t);
+      t = (t - d[m]) >> DB;
+    }
+    const int64_t top = lane_read(t, nbl - 1) + reg_resolve<true, R>(d, lane_shr1(lane < nbl - 1 ? t : 0), nbl);
+    if (top != 0 && lane == 0) atomicOr(&flags[0], 2);
+  }
+  // 2. sign: the top nonzero digit
+  int mytop = -1, mysign = 0;
+#pragma unroll
+  for (int m = 0; m < R; m++)
+    if (own && d[m] != 0) {
+      mytop = R * lane + m;
+      mysign = d[m] < 0;
+    }
+  const int top = wave_max(mytop);
+  const bool neg = top >= 0 && __builtin_amdgcn_readlane(mysign, top / R) != 0;
+  // 3. magnitude as standard digits
+  {
+    int64_t t = 0;
+#pragma unroll
+    for (int m = 0; m < R; m++) {
+      t += neg ? -d[m] : d[m];
+      d[m] = t & (RADIX - 1);
+      t >>= DB;
+    }
+    (void)reg_resolve<false, R>(d, lane_shr1(lane < nbl - 1 ? t : 0), nbl);
+  }
+  // 4. shift right by h bits through LDS; round to nearest, ties to even
+  uint32_t* ls = (uint32_t*)ob;
+#pragma unroll
+  for (int m = 0; m < R; m++) if (own) ls[R * lane + m] = (uint32_t)d[m];
+  for (int x = W + lane; x < W + R + 2; x += 64) ls[x] = 0;
+  lds_sync<BLK>();
+  const int hq = h / DB, hb = h % DB;
+  const int hbit_digit = (h - 1) / DB, hbit = (h - 1) % DB;
+  const int nout = W - hq + 1;
+  const int nbo = (nout + R - 1) / R;
+  int64_t o[R];
+#pragma unroll
+  for (int m = 0; m < R; m++) {
+    const int i = R * lane + m;
+    uint32_t v = 0;
+    if (i < nout) {
+      const int s2 = hq + i;
+      const uint32_t lo = s2 < W ? ls[s2] : 0u;
+      const uint32_t hi = s2 + 1 < W ? ls[s2 + 1] : 0u;
+      v = (lo >> hb) | (hb ? ((hi << (DB - hb)) & (uint32_t)(RADIX - 1)) : 0u);
+    }
+    o[m] = v;
+  }
+  int st = 0;
+#pragma unroll
+  for (int m = 0; m < R; m++) if (own && R * lane + m < hbit_digit && d[m] != 0) st = 1;
+  const uint32_t hd = ls[hbit_digit];
+  const int sticky = __any(st) || (hbit > 0 && (hd & ((1u << hbit) - 1)));
+  const int half = (hd >> hbit) & 1;
+  const int inc = half && (sticky || (lane_read(o[0], 0) & 1));
+  if (reg_resolve<false, R>(o, lane == 0 ? inc : 0, nbo) != 0 && lane == 0) atomicOr(&flags[0], 16);
+  // 5. standard digits out; balanced copy with the sign
+  int ts = -1;
+  uint32_t tv = 0;
+#pragma unroll
+  for (int m = 0; m < R; m++) {
+    const int i = R * lane + m;
+    if (lane >= nbo) continue;
+    const uint32_t u = i < nout ? (uint32_t)o[m] : 0u;
+    if (i < cap) {
+      Sr[i] = u;
+      if (Sl) Sl[i] = u;
+    }
+    if (u != 0) {
+      ts = i;
+      tv = u;
+      if (i >= cap) atomicOr(&flags[0], 16);
+    }
+  }
+  for (int i = nbo * R + lane; i < cap; i += 64) {
+    Sr[i] = 0;
+    if (Sl) Sl[i] = 0;
+  }
+  const int stop = wave_max(ts);
+  const uint32_t topv = stop >= 0 ? (uint32_t)__builtin_amdgcn_readlane((int32_t)tv, stop / R) : 0u;
+  {
+    int64_t t = 0;
+#pragma unroll
+    for (int m = 0; m < R; m++) {
+      t += lane < nbo ? o[m] : 0;
+      o[m] = balanced29(t);
+      t = (t - o[m]) >> DB;
+    }
+    const int64_t extra = lane_read(t, nbo - 1) + reg_resolve<true, R>(o, lane_shr1(lane < nbo - 1 ? t : 0), nbo);
+    int tb = -1;
+#pragma unroll
+    for (int m = 0; m < R; m++) {
+      const int i = R * lane + m;
+      if (lane >= nbo) continue;
+      const int32_t v = (int32_t)(neg ? -o[m] : o[m]);
+      if (i < cap) {
+        Cr[i] = v;
+        if (v != 0) tb = i;
+      } else if (v != 0) {
+        atomicOr(&flags[0], 16);
+      }
+    }
+    for (int i = nbo * R + lane; i < cap; i += 64) {
+      const int32_t v = i == nbo * R ? (int32_t)(neg ? -extra : extra) : 0;
+      Cr[i] = v;
+      if (v != 0) tb = i;
+    }
+    if (extra != 0 && nbo * R >= cap && lane == 0) atomicOr(&flags[0], 16);
+    FinOut f;
+    f.nbal = wave_max(tb) + 1;
+    f.nstd = stop + 1;
+    f.neg = neg ? 1 : 0;
+    f.bits = stop < 0 ? 0 : DB * stop + (32 - __clz(topv));
+    f.topv = topv;
+    return f;
+  }
+}
+
 // Quotient digits taken per pass over the remainder and zero positions kept
 // below position 0.  divide_entry's DNIR is the number of 64-position groups
 // of divisor digits its bulk pass holds in registers (larger divisors read
 // the rest from LDS).
 constexpr int DQ = 8;
 constexpr int DOFF = DQ + 4;
-
-// 64-bit lane moves: the value of lane i - 1 (lane 0: 0) by a DPP wave
-// shift, and the value of one (uniform) lane
-__device__ __forceinline__ int64_t lane_shr1(int64_t v) {
-  const int32_t lo = __builtin_amdgcn_update_dpp(0, (int32_t)v, 0x138, 0xf, 0xf, false);
-  const int32_t hi = __builtin_amdgcn_update_dpp(0, (int32_t)(v >> 32), 0x138, 0xf, 0xf, false);
-  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
-}
-__device__ __forceinline__ int64_t lane_read(int64_t v, int l) {
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int32_t)v, l);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int32_t)(v >> 32), l);
-  return (int64_t)(((uint64_t)hi << 32) | lo);
-}
 
 // One bulk step of divide_entry for remainder position b + rel: subtract
 // sum_s q[s] dd[rel + s + 1 - DQ] and split the result into a digit in
@@ -737,6 +914,20 @@ __device__ __forceinline__ int divide_entry(int64_t* smem, const uint32_t* Sr, i
 // chains, more lanes busy).
 constexpr int FIN_FB = 4;
 
+// The finalisation of the column and solve kernels (digits already in dg,
+// carries in cb): in registers, 2 or 8 digits a lane, while the number and
+// the shifted result both fit 64 lanes, else through LDS.
+__device__ __forceinline__ FinOut finalize_pre(int W, int h, int32_t* Cr, uint32_t* Sr, int cap, int32_t* flags,
+                                               int32_t* dg, int32_t* ob, int64_t* ca, int64_t* cb,
+                                               const int64_t* Psub, uint32_t* Sl = nullptr) {
+  const int nout = W - h / DB + 1;
+  if (W <= 64 * 2 && nout <= 64 * 2) return wave_finalize_reg<false, 2>(W, h, Cr, Sr, cap, flags, dg, ob, cb, Psub, Sl);
+  if (W <= 64 * 8 && nout <= 64 * 8) return wave_finalize_reg<false, 8>(W, h, Cr, Sr, cap, flags, dg, ob, cb, Psub, Sl);
+  return wave_finalize<false, FIN_FB, true>(nullptr, 0, W, nullptr, 0, h, Cr, Sr, cap, flags, dg, ob, ca, cb,
+                                            Psub, Sl);
+}
+
+
 // |d| 2^sh as standard digits, top digit in [2^28, 2^29): every output digit
 // takes its own input digit shifted up and the top bits of the one below
 __device__ __forceinline__ void normalise_divisor(const uint32_t* S, int n, int sh, uint32_t* out) {
@@ -927,9 +1118,8 @@ __device__ __forceinline__ void column_step(const InstDesc* __restrict__ desc, i
   f.nstd = 0;
   f.neg = 0;
   if (wave == 0) {
-    f = wave_finalize<false, FIN_FB, true>(I.A + cc.aoff + lr, cc.R, W, Kc + lr, cc.R, I.h,
-                                           I.C + cc.coff + (int64_t)lr * cc.CW, Srow, cc.CW, I.flags, dg, ob,
-                                           ca, cb, Psub, oS);
+    f = finalize_pre(W, I.h, I.C + cc.coff + (int64_t)lr * cc.CW, Srow, cc.CW, I.flags, dg, ob, ca, cb, Psub,
+                     oS);
     const int64_t ti = tri_index(N, c, r);
     if (lane == 0) {
       I.nC[ti] = f.nbal;
@@ -953,8 +1143,7 @@ __device__ __forceinline__ void column_step(const InstDesc* __restrict__ desc, i
       normalise_divisor(Srow, f.nstd, sh, I.D + cc.doff);
     }
   } else if (work) {
-    const FinOut p = wave_finalize<false, FIN_FB, true>(I.A + cc.aoff, cc.R, W, Kc, cc.R, I.h, pC, pS, cc.CW,
-                                                        I.flags, dg, ob, ca, cb, Psub);
+    const FinOut p = finalize_pre(W, I.h, pC, pS, cc.CW, I.flags, dg, ob, ca, cb, Psub);
     const int sh = p.nstd > 0 ? 28 - (31 - __clz(p.topv)) : 0;
     lds_sync<false>();
     normalise_divisor(pS, p.nstd, sh, pD);
@@ -1190,8 +1379,8 @@ __global__ void __launch_bounds__(256) k_vcol_b(const SweepArgs* __restrict__ ar
     Psub = Pd;
   }
   lds_sync<false>();
-  const FinOut f = wave_finalize<false, FIN_FB, true>(a.acc + k, a.Npad, VA, Kc, a.Npad, a.h, a.ub + (int64_t)k * a.VW,
-                                                      a.us + (int64_t)k * a.VW, a.VW, a.flags, dg, ob, ca, cb, Psub);
+  const FinOut f = finalize_pre(VA, a.h, a.ub + (int64_t)k * a.VW, a.us + (int64_t)k * a.VW, a.VW, a.flags, dg,
+                                ob, ca, cb, Psub);
   if (lane == 0) {
     a.nU[k] = f.nbal;
     a.nUs[k] = f.neg ? -f.nstd : f.nstd;
