@@ -675,27 +675,39 @@ __device__ __forceinline__ FinOut wave_finalize_reg(int W, int h, int32_t* Cr, u
 // of divisor digits its bulk pass holds in registers (larger divisors read
 // the rest from LDS).
 constexpr int DQ = 8;
+static_assert(DQ == 8, "bulk_sum pairs the DQ products as s and s + 4");
 constexpr int DOFF = DQ + 4;
 
-// One bulk step of divide_entry for remainder position b + rel: subtract
-// sum_s q[s] dd[rel + s + 1 - DQ] and split the result into a digit in
-// [0, 2^29) and a carry for the position above (carry-save: the carry moves
-// one lane up by a DPP shift, the top lane's to the next group's lane 0, so
-// no position needs a second writer).
-__device__ __forceinline__ void divide_bulk(int64_t* rem, int b, int rel, bool act, const int32_t* q,
-                                            const int32_t* ddv, int64_t& carry, int top_group,
-                                            int top_lane, int64_t& hi_top) {
-  const int lane = threadIdx.x & 63;
-  int64_t x = act ? rem[b + rel] : 0;
+// The bulk subtraction of divide_entry at remainder position b + rel:
+// x - sum_s q[s] dd[rel + s + 1 - DQ], the DQ products summed in four
+// independent chains (the empty asm statements keep the compiler from
+// folding them back into one dependent chain of multiply-adds).
+__device__ __forceinline__ int64_t bulk_sum(int64_t x, const int32_t* q, const int32_t* ddv) {
+  int64_t a[4];
 #pragma unroll
-  for (int s = 0; s < DQ; s++) x += (int64_t)(-q[s]) * (int64_t)ddv[s];
+  for (int k = 0; k < 4; k++) {
+    a[k] = (int64_t)(-q[k]) * (int64_t)ddv[k];
+    a[k] += (int64_t)(-q[k + 4]) * (int64_t)ddv[k + 4];
+    asm volatile("" : "+v"(a[k]));
+  }
+  return x + ((a[0] + a[1]) + (a[2] + a[3]));
+}
+
+// Carry-save split of one 64-position group of bulk sums: the digit in
+// [0, 2^29) plus the carry of the position below, moved one lane up by a DPP
+// wave shift whose vacated lane 0 is filled, by a DPP wave rotation, with the
+// top lane of the previous group's carries (prev; zero for the first group),
+// so no carry passes through a scalar register.  Returns the new remainder
+// value of this lane's position; prev becomes this group's carries.
+__device__ __forceinline__ int64_t bulk_split(int64_t x, int64_t& prev) {
   const int64_t lo = x & (RADIX - 1);
   const int64_t hi = x >> DB;
-  int64_t hin = lane_shr1(hi);
-  if (lane == 0) hin = carry;
-  carry = lane_read(hi, 63);
-  if (act) rem[b + rel] = lo + hin;
-  if (top_group) hi_top = lane_read(hi, top_lane);
+  const int32_t f0 = __builtin_amdgcn_update_dpp(0, (int32_t)prev, 0x13C, 0xf, 0xf, false);
+  const int32_t f1 = __builtin_amdgcn_update_dpp(0, (int32_t)(prev >> 32), 0x13C, 0xf, 0xf, false);
+  const int32_t h0 = __builtin_amdgcn_update_dpp(f0, (int32_t)hi, 0x138, 0xf, 0xf, false);
+  const int32_t h1 = __builtin_amdgcn_update_dpp(f1, (int32_t)(hi >> 32), 0x138, 0xf, 0xf, false);
+  prev = hi;
+  return lo + (int64_t)(((uint64_t)(uint32_t)h1 << 32) | (uint32_t)h0);
 }
 
 // out = RNE(+-|num| 2^h / |d|) for one 64-lane workgroup: schoolbook long
@@ -806,13 +818,28 @@ __device__ __forceinline__ int divide_entry(int64_t* smem, const uint32_t* Sr, i
       for (int s = 1; s < DQ; s++) v = lane == s ? q[s] : v;
       if (lane < Qe) qd[j0 - lane] = v;
     }
-    // every position below the window: subtract the DQ multiples at once
+    // every position below the window: subtract the DQ multiples at once.
+    // The register groups load and sum independently (no branch between
+    // them), then split in order, the carries passing upward.
     const int b = j0 - DQ + 1;
-    int64_t carry = 0, hi_top = 0;
+    int64_t prev = 0, htop = 0;
+    {
+      int64_t xv[DNIR];
 #pragma unroll
-    for (int i = 0; i < DNIR; i++)
-      if (i < NI) divide_bulk(rem, b, lane + 64 * i, lane + 64 * i < nbulk, q, DDL[i], carry, i == top_group,
-                              top_lane, hi_top);
+      for (int i = 0; i < DNIR; i++) {
+        const int rel = lane + 64 * i;
+        xv[i] = rel < nbulk ? rem[b + rel] : 0;
+      }
+#pragma unroll
+      for (int i = 0; i < DNIR; i++) xv[i] = bulk_sum(xv[i], q, DDL[i]);
+#pragma unroll
+      for (int i = 0; i < DNIR; i++) {
+        const int rel = lane + 64 * i;
+        const int64_t v = bulk_split(xv[i], prev);
+        if (rel < nbulk) rem[b + rel] = v;
+        if (i == top_group) htop = prev;
+      }
+    }
     for (int i = DNIR; i < NI; i++) {
       int32_t ddv[DQ];
 #pragma unroll
@@ -820,10 +847,14 @@ __device__ __forceinline__ int divide_entry(int64_t* smem, const uint32_t* Sr, i
         const int k = lane + 64 * i + s + 1 - DQ;
         ddv[s] = k < nd ? (int32_t)dd[k] : 0;
       }
-      divide_bulk(rem, b, lane + 64 * i, lane + 64 * i < nbulk, q, ddv, carry, i == top_group, top_lane,
-                  hi_top);
+      const int rel = lane + 64 * i;
+      const int64_t x = bulk_sum(rel < nbulk ? rem[b + rel] : 0, q, ddv);
+      const int64_t v = bulk_split(x, prev);
+      if (rel < nbulk) rem[b + rel] = v;
+      if (i == top_group) htop = prev;
     }
-    W[DQ + 3] += hi_top;
+    // the top bulk position's carry enters the window's lowest position
+    if (top_group >= 0) W[DQ + 3] += lane_read(htop, top_lane);
     lds_sync<BLK>();
     if (j0 - DQ < 0) break;
     T -= DQ;
@@ -1030,6 +1061,9 @@ __device__ __forceinline__ void column_step(const InstDesc* __restrict__ desc, i
     return;
   }
   extern __shared__ int64_t smem[];
+  // the row chain is the launch's critical path: its waves take the SIMDs'
+  // issue slots ahead of update waves that share them
+  __builtin_amdgcn_s_setprio(3);
   int bid = blockIdx.x, inst = -1;
   for (int i = 0; i < count; i++) {
     const int n = max(0, desc[i].N - c);
@@ -1326,6 +1360,7 @@ __global__ void __launch_bounds__(256) k_vcol_b(const SweepArgs* __restrict__ ar
                  a.VW, a.L, a.LT, a.nL, a.LWT, a.flags);
     return;
   }
+  __builtin_amdgcn_s_setprio(3);   // the sweep's critical path (see column_step)
   const int VA = a.VA;
   int32_t* dg = (int32_t*)smem;
   int32_t* ob = dg + (VA + 48);
