@@ -122,6 +122,18 @@ size_t hk_workspace_bytes(int N, hk_rational beta, int prec_bits, int flags);
 hk_status hk_build_matrix(int N, hk_rational beta, int prec_bits, void* dev_ws,
                           size_t ws_bytes, hipStream_t s, hk_matrix* out);
 
+/* Host only (no device work): the same 2N-1 correctly rounded moments
+   X_n = RNE(2^K mu_n) that hk_build_matrix uploads (Introduction: the matrix
+   definition; "Properties of M": the moments of exp(-x^beta)).  Each X_n is
+   a nonnegative integer written as little-endian base-2^32 words:
+   words[off[n] .. off[n+1]) for n = 0..2N-2; off (caller-owned, 2N entries)
+   is always filled, off[2N-1] being the total word count.  With words NULL,
+   or cap (its length in words) below that total, only off is written and
+   the call returns HK_EINVAL; call again with a large enough buffer.
+   HK_EPRECISION if the rounding stays undecided (never seen in practice). */
+hk_status hk_moments_host(int N, hk_rational beta, int prec_bits, uint32_t* words, int64_t cap,
+                          int64_t* off);
+
 /* LDL^T of M - xI, x = shift (a dyadic with at most K fractional bits),
    in the paper's submatrix order and fixed-point format ("The LDL^T
    Determinant Algorithm"; parallel variant's formats): for each column pc,

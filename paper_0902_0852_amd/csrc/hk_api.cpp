@@ -326,6 +326,22 @@ size_t hk_workspace_bytes(int N, hk_rational beta, int prec_bits, int flags) {
   return P.total;
 }
 
+hk_status hk_moments_host(int N, hk_rational beta, int prec_bits, uint32_t* words, int64_t cap,
+                          int64_t* off) {
+  if (!off) return fail(HK_EINVAL, "off is NULL");
+  if (N < 1 || prec_bits < 64 || (prec_bits & 1)) return fail(HK_EINVAL, "need N >= 1 and even prec_bits >= 64");
+  uint32_t p = 0, q = 0;
+  if (!reduce_beta(beta.num, beta.den, &p, &q)) return fail(HK_EINVAL, "beta must be num/den with num, den >= 1");
+  std::vector<MP> X;
+  if (!build_moments(N, p, q, prec_bits, X)) return fail(HK_EPRECISION, "moment rounding undecided");
+  int64_t total = 0;
+  for (size_t n = 0; n < X.size(); n++) { off[n] = total; total += (int64_t)X[n].d.size(); }
+  off[X.size()] = total;
+  if (!words || cap < total) return fail(HK_EINVAL, "words buffer too small: need " + std::to_string(total));
+  for (size_t n = 0; n < X.size(); n++) std::copy(X[n].d.begin(), X[n].d.end(), words + off[n]);
+  return HK_OK;
+}
+
 hk_status hk_build_matrix(int N, hk_rational beta, int prec_bits, void* dev_ws, size_t ws_bytes,
                           hipStream_t s, hk_matrix* out) {
   const hk_status st = hk::build_matrix_impl(N, beta, prec_bits, dev_ws, ws_bytes, s, out, nullptr);

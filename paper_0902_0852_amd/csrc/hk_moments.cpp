@@ -24,7 +24,7 @@ namespace {
 
 // In-place magnitude arithmetic for the long series below (little-endian
 // base-2^32 words, no leading zeros kept): x = floor(x m / 2^sh) with m below
-// 2^64, x = floor(x / d) with d below 2^32, acc += x.
+// 2^64, x = floor(x / d) with d below 2^32.
 void mul64_shr(std::vector<uint32_t>& x, uint64_t m, int64_t sh) {
   uint64_t carry = 0;
   for (size_t i = 0; i < x.size(); i++) {
@@ -45,9 +45,7 @@ void mul64_shr(std::vector<uint32_t>& x, uint64_t m, int64_t sh) {
   x.resize(n);
   while (!x.empty() && x.back() == 0) x.pop_back();
 }
-void div32(std::vector<uint32_t>& x, uint32_t d) {
-  // quotient digits by the precomputed reciprocal floor((2^64 - 1) / d): the
-  // estimate is at most two below the true digit, fixed up by the remainder
+uint32_t div32_rem(std::vector<uint32_t>& x, uint32_t d) {
   const uint64_t inv = ~0ULL / d;
   uint64_t rem = 0;
   for (size_t i = x.size(); i-- > 0;) {
@@ -59,23 +57,9 @@ void div32(std::vector<uint32_t>& x, uint32_t d) {
     rem = rr;
   }
   while (!x.empty() && x.back() == 0) x.pop_back();
+  return (uint32_t)rem;
 }
-void add_into(std::vector<uint32_t>& acc, const std::vector<uint32_t>& x) {
-  if (acc.size() < x.size()) acc.resize(x.size(), 0u);
-  uint64_t c = 0;
-  size_t i = 0;
-  for (; i < x.size(); i++) {
-    const uint64_t v = (uint64_t)acc[i] + x[i] + c;
-    acc[i] = (uint32_t)v;
-    c = v >> 32;
-  }
-  for (; c && i < acc.size(); i++) {
-    const uint64_t v = (uint64_t)acc[i] + c;
-    acc[i] = (uint32_t)v;
-    c = v >> 32;
-  }
-  if (c) acc.push_back((uint32_t)c);
-}
+void div32(std::vector<uint32_t>& x, uint32_t d) { (void)div32_rem(x, d); }
 // the factors of an exact product grouped into multipliers below 2^64
 std::vector<uint64_t> group64(const std::vector<uint64_t>& f) {
   std::vector<uint64_t> g;
@@ -122,72 +106,209 @@ struct SeriesPlan {
   }
 };
 
-struct Series { MP sum, first; uint64_t n = 0; };
+// A series sum_k tau_k with tau_0 given at scale 2^W and
+// tau_k = tau_{k-1} prod(mm) / (2^(a p) den_k), den_k = den0 + k dstep.
+// Each term is carried as x 2^e with at most P = W significant bits while
+// the terms grow (their relative errors are what later terms inherit), and
+// with absolute unit no finer than 2^elo once they shrink; the sum is kept
+// at unit 2^U, about 32 bits finer than its own size relative to P.  The
+// error of every term is tracked: with d the bound in units of its 2^e,
+//   d_k <= d_{k-1} rho_k 2^(e_{k-1} - e_k) + 2
+// (one floor in the shift, one in the division; rho_k the exact ratio,
+// rounded up), and err bounds |acc 2^U - 2^W sum_k tau_k| in units of 2^U,
+// including the tail dropped once a term is zero and the ratio below 1/2.
+struct FSeries { MP acc; int64_t U = 0; double err = 0; uint64_t n = 0; };
 
-// S = 2^W sum_k T^k p^{k+1} / prod_{j<=k} (r + j p), floor chain
-Series series_S(const SeriesPlan& sp, uint32_t r) {
-  const uint32_t p = sp.p;
-  std::vector<uint64_t> fs(p, sp.u);
-  fs.push_back(p);
-  const std::vector<uint64_t> ms = group64(fs);
-  Series out;
-  out.first = divmod_small(shl(MP::from_u64(p), sp.W), r, nullptr);
-  std::vector<uint32_t> t = out.first.d, S = out.first.d;
+int64_t bitlen_w(const std::vector<uint32_t>& x) {
+  return x.empty() ? 0 : 32 * (int64_t)(x.size() - 1) + (32 - __builtin_clz(x.back()));
+}
+// x = x m (m below 2^64)
+void mul_in(std::vector<uint32_t>& x, uint64_t m) {
+  uint64_t carry = 0;
+  for (size_t i = 0; i < x.size(); i++) {
+    const unsigned __int128 v = (unsigned __int128)x[i] * m + carry;
+    x[i] = (uint32_t)v;
+    carry = (uint64_t)(v >> 32);
+  }
+  while (carry) { x.push_back((uint32_t)carry); carry >>= 32; }
+}
+// x = floor(floor(x / 2^sh) / d), d below 2^32, in one pass from the top
+// (the quotient digits by the reciprocal of div32)
+// (quotient digits go to the scratch vector q, which then swaps with x)
+void shr_div_in(std::vector<uint32_t>& x, int64_t sh, uint32_t d, std::vector<uint32_t>& q) {
+  const size_t ws = (size_t)(sh >> 5);
+  const int bs = (int)(sh & 31);
+  if (ws >= x.size()) { x.clear(); return; }
+  const size_t n = x.size() - ws;
+  q.resize(n);
+  const uint64_t inv = ~0ULL / d;
+  uint64_t rem = 0;
+  for (size_t i = n; i-- > 0;) {
+    uint64_t w = x[i + ws];
+    if (bs) w = (w >> bs) | (i + ws + 1 < x.size() ? (uint64_t)x[i + ws + 1] << (32 - bs) : 0);
+    const uint64_t cur = (rem << 32) | (uint32_t)w;
+    uint64_t qd = (uint64_t)(((unsigned __int128)cur * inv) >> 64);
+    uint64_t rr = cur - qd * d;
+    while (rr >= d) { rr -= d; qd++; }
+    q[i] = (uint32_t)qd;
+    rem = rr;
+  }
+  x.swap(q);
+  while (!x.empty() && x.back() == 0) x.pop_back();
+}
+// acc += floor(x 2^s) (exact for s >= 0), the shifted words formed on the fly
+void add_scaled(std::vector<uint32_t>& acc, const std::vector<uint32_t>& x, int64_t s) {
+  if (x.empty()) return;
+  if (s >= 0) {
+    const size_t ws = (size_t)(s >> 5);
+    const int bs = (int)(s & 31);
+    const size_t need = ws + x.size() + 1;
+    if (acc.size() < need) acc.resize(need, 0u);
+    uint64_t c = 0;
+    uint32_t prev = 0;
+    size_t i = 0;
+    for (; i <= x.size(); i++) {
+      const uint32_t cur = i < x.size() ? x[i] : 0u;
+      const uint32_t w = bs ? (cur << bs) | (prev >> (32 - bs)) : cur;
+      prev = cur;
+      const uint64_t v = (uint64_t)acc[ws + i] + w + c;
+      acc[ws + i] = (uint32_t)v;
+      c = v >> 32;
+    }
+    for (size_t j = ws + i; c; j++) {
+      if (j == acc.size()) acc.push_back(0u);
+      const uint64_t v = (uint64_t)acc[j] + c;
+      acc[j] = (uint32_t)v;
+      c = v >> 32;
+    }
+  } else {
+    const int64_t sh = -s;
+    const size_t ws = (size_t)(sh >> 5);
+    const int bs = (int)(sh & 31);
+    if (ws >= x.size()) return;
+    const size_t n = x.size() - ws;
+    if (acc.size() < n + 1) acc.resize(n + 1, 0u);
+    uint64_t c = 0;
+    size_t i = 0;
+    for (; i < n; i++) {
+      uint64_t w = x[i + ws];
+      if (bs) w = (w >> bs) | (i + ws + 1 < x.size() ? (uint64_t)x[i + ws + 1] << (32 - bs) : 0);
+      const uint64_t v = (uint64_t)acc[i] + (uint32_t)w + c;
+      acc[i] = (uint32_t)v;
+      c = v >> 32;
+    }
+    for (size_t j = i; c; j++) {
+      if (j == acc.size()) acc.push_back(0u);
+      const uint64_t v = (uint64_t)acc[j] + c;
+      acc[j] = (uint32_t)v;
+      c = v >> 32;
+    }
+  }
+  while (!acc.empty() && acc.back() == 0) acc.pop_back();
+}
+
+// log2 of sum_k tau_k by the terms' logarithms (double precision): places
+// the sum's unit
+double log2_series(double log2_tau0, double lrho_num, double den0, double dstep) {
+  double lt = log2_tau0, top = lt, sum = 1.0;   // sum of 2^(l - top)
+  for (uint64_t k = 1; k < 100000000ULL; k++) {
+    lt += lrho_num - std::log2(den0 + (double)k * dstep);
+    if (lt > top) { sum = sum * std::exp2(top - lt) + 1.0; top = lt; }
+    else sum += std::exp2(lt - top);
+    if (lt < top - 80 && lrho_num < std::log2(den0 + (double)k * dstep)) break;
+  }
+  return top + std::log2(sum);
+}
+
+FSeries float_series(const SeriesPlan& sp, const std::vector<uint64_t>& mm, std::vector<uint32_t> x,
+                     double d0, uint64_t den0, uint64_t dstep) {
+  const int64_t P = sp.W;
+  double mprod = 1.0;
+  for (uint64_t m : mm) mprod *= (double)m;
+  const double lrho_num = std::log2(mprod) - (double)sp.ap;
+  const double l2 = log2_series((double)bitlen_w(x) - 1.0, lrho_num, (double)den0, (double)dstep);
+  FSeries out;
+  out.U = (int64_t)std::floor(l2) - P - 32;
+  const int64_t elo = out.U - 16;
+  const double up = 1.0 + 1e-12;
+  std::vector<uint32_t> acc, qs;
+  int64_t e = 0;
+  double d = d0, err = 0.0;
+  add_scaled(acc, x, e - out.U);
+  err += d * std::ldexp(1.0, (int)std::max<int64_t>(-2000, e - out.U)) + 1.0;
   out.n = 1;
   for (uint64_t k = 1;; k++) {
-    const uint64_t den = (uint64_t)r + k * (uint64_t)p;
-    sp.step(t, ms);
-    if (den <= 0xffffffffULL) div32(t, (uint32_t)den);
-    else { MP q, rr; divmod_mag(from_words(t), MP::from_u64(den), q, rr); t = q.d; }
-    add_into(S, t);
+    const uint64_t den = den0 + k * dstep;
+    const double rho = mprod * up / (std::ldexp(1.0, (int)sp.ap) * (double)den) * up;
+    for (uint64_t m : mm) mul_in(x, m);
+    int64_t en = e - sp.ap + std::max<int64_t>(0, bitlen_w(x) - P);
+    if (rho < 1.0 && en < elo) en = elo;
+    if (en < e - sp.ap) en = e - sp.ap;
+    if (den <= 0xffffffffULL) {
+      shr_div_in(x, en - (e - sp.ap), (uint32_t)den, qs);
+    } else {
+      mul64_shr(x, 1, en - (e - sp.ap));
+      MP q, rr;
+      divmod_mag(from_words(x), MP::from_u64(den), q, rr);
+      x = q.d;
+    }
+    d = d * rho * std::ldexp(1.0, (int)std::max<int64_t>(-2000, e - en)) * up + 2.0;
+    e = en;
+    add_scaled(acc, x, e - out.U);
+    const double unit = std::ldexp(1.0, (int)std::max<int64_t>(-2000, std::min<int64_t>(2000, e - out.U)));
+    err += d * unit * up + (e < out.U ? 1.0 : 0.0);
     out.n++;
-    if (t.empty() && (double)den > 2.0 * p * sp.Tval) break;
+    if (x.empty() && rho < 0.5) {
+      err += (d + 2.0) * unit;
+      break;
+    }
   }
-  out.sum = from_words(S);
+  out.acc = from_words(acc);
+  out.err = err * (1.0 + 1e-9) + 4.0;
   return out;
 }
 
-// E = 2^W e^T, floor chain (the same for every r)
-Series series_E(const SeriesPlan& sp) {
-  const std::vector<uint64_t> me = group64(std::vector<uint64_t>(sp.p, sp.u));
-  Series out;
-  std::vector<uint32_t> e = shl(MP::from_u64(1), sp.W).d, E = e;
-  out.n = 1;
-  for (uint64_t k = 1;; k++) {
-    sp.step(e, me);
-    if (k <= 0xffffffffULL) div32(e, (uint32_t)k);
-    add_into(E, e);
-    out.n++;
-    if (e.empty() && (double)k > 2.0 * sp.Tval) break;
-  }
-  out.sum = from_words(E);
-  return out;
+// S = 2^W sum_k T^k p^{k+1} / prod_{j<=k} (r + j p)
+FSeries series_S(const SeriesPlan& sp, uint32_t r) {
+  std::vector<uint64_t> fs(sp.p, sp.u);
+  fs.push_back(sp.p);
+  const MP first = divmod_small(shl(MP::from_u64(sp.p), sp.W), r, nullptr);
+  return float_series(sp, group64(fs), first.d, 1.0, r, sp.p);
+}
+
+// E = 2^W e^T (the same for every r)
+FSeries series_E(const SeriesPlan& sp) {
+  return float_series(sp, group64(std::vector<uint64_t>(sp.p, sp.u)), shl(MP::from_u64(1), sp.W).d, 0.0, 0, 1);
+}
+
+// MP upper bound of a nonnegative double
+MP mp_ceil(double v) {
+  int ex = 0;
+  const double m = std::frexp(v, &ex);                    // v = m 2^ex, m in [0.5, 1)
+  const uint64_t mi = (uint64_t)std::ceil(std::ldexp(m, 53));
+  return ex >= 53 ? shl(MP::from_u64(mi), ex - 53) : add(shr_mag(MP::from_u64(mi), 53 - ex), MP::from_u64(1));
 }
 
 // Gamma(s) = gamma(s, T) + Gamma(s, T) with the lower part T^s e^{-T} S and
 // the upper part below e^{-T}: 2^F Gamma(r/p) from the two series
-GammaApprox gamma_from(const SeriesPlan& sp, uint32_t r, const Series& Ss, const Series& Es, int64_t F) {
-  const MP& Sm = Ss.sum;
-  const MP& Em = Es.sum;
-  const int64_t W = sp.W;
-  // error bounds of the truncated floor chains (units of 2^-W), each step
-  // losing < 2 units (shift and division):
-  //   |dS| <= 2 n^2 + 2 n (S / t0 + 1),  |dE| <= 2 n^2 + 2 n (E / 2^W + 1)
-  // plus the dropped tails (each below one unit once a term is 0 and the
-  // ratio is below 1/2)
-  MP nSq = MP::from_u64(2 * Ss.n), nEq = MP::from_u64(2 * Es.n);
-  MP errS = add(mul(nSq, nSq), mul(nSq, add(floor_div(Sm, Ss.first), MP::from_u64(2))));
-  MP errE = add(mul(nEq, nEq), mul(nEq, add(shr_mag(Em, W), MP::from_u64(2))));
-  // T^s = u^r / 2^(a r)
-  MP ur = pow_small(sp.u, r);
-  const int64_t ar = (int64_t)sp.a * r;
-  MP num = shl(mul(ur, Sm), F);
+GammaApprox gamma_from(const SeriesPlan& sp, uint32_t r, const FSeries& Ss, const FSeries& Es, int64_t F) {
   GammaApprox g;
-  g.G = shr_mag(floor_div(num, Em), ar);
-  // err <= T^s 2^F (errS E + S errE) / E^2 + 2^(F+W) / E + 2
-  MP e1 = ceil_div(mul(shl(ur, F), add(mul(errS, Em), mul(Sm, errE))), mul(Em, Em));
+  const int64_t D = F + Ss.U - Es.U;           // S / E = (Sacc / Eacc) 2^(U_S - U_E)
+  const MP errS = mp_ceil(Ss.err), errE = mp_ceil(Es.err);
+  const MP Elo = sub(Es.acc, errE);
+  if (D < 0 || Elo.sign() <= 0 || F + sp.W - Es.U < 0) {
+    g.G = MP();
+    g.err = shl(MP::from_u64(1), F + 64);     // undecidable: the caller widens
+    return g;
+  }
+  // T^s = u^r / 2^(a r)
+  const MP ur = pow_small(sp.u, r);
+  const int64_t ar = (int64_t)sp.a * r;
+  g.G = shr_mag(floor_div(shl(mul(ur, Ss.acc), D), Es.acc), ar);
+  // err <= T^s 2^F (errS E + S errE) / (E (E - errE)) + 2^F e^{-T} + 3
+  MP e1 = ceil_div(mul(shl(ur, D), add(mul(errS, Es.acc), mul(Ss.acc, errE))), mul(Es.acc, Elo));
   e1 = add(shr_mag(e1, ar), MP::from_u64(1));
-  MP e2 = ceil_div(shl(MP::from_u64(1), F + W), Em);
+  const MP e2 = ceil_div(shl(MP::from_u64(1), F + sp.W - Es.U), Elo);
   g.err = add(add(e1, e2), MP::from_u64(3));
   return g;
 }
@@ -239,8 +360,8 @@ bool build_moments(int N, uint32_t p, uint32_t q, int K, std::vector<MP>& X) {
       std::vector<bool> need(p, false);
       for (int n = 0; n <= nmax; n++) need[((uint64_t)q * (n + 1)) % p] = true;
       const SeriesPlan sp(p, F);
-      std::vector<Series> S(p);
-      Series E;
+      std::vector<FSeries> S(p);
+      FSeries E;
       std::vector<std::thread> th;
       bool any = false;
       for (uint32_t r = 1; r < p; r++)
@@ -251,40 +372,64 @@ bool build_moments(int N, uint32_t p, uint32_t q, int K, std::vector<MP>& X) {
         if (need[r]) { gam[r] = gamma_from(sp, r, S[r], E, F); have[r] = true; }
     }
     // per residue r: lower and upper bounds of Y(m) = G prod_{j<m} (r + j p) / p^m,
-    // stepped in m by one floor and one ceiling multiply-divide each
-    std::vector<MP> ylo(p), yhi(p);
-    std::vector<uint64_t> ym(p, 0);
-    for (uint32_t r = 1; r < p; r++)
-      if (have[r]) { ylo[r] = sub(gam[r].G, gam[r].err); yhi[r] = add(gam[r].G, gam[r].err); }
-    MP fact = MP::from_u64(1);   // running (fm - 1)!
-    uint64_t fm = 1;
+    // stepped in m by one floor and one ceiling multiply-divide each; the
+    // residues' chains (and the exact factorial chain of r = 0) are
+    // independent and run on threads of their own
     X.assign(nmax + 1, MP());
-    bool ok = true;
-    for (int n = 0; n <= nmax && ok; n++) {
-      uint64_t a = (uint64_t)q * (uint64_t)(n + 1);
-      uint64_t m = a / p, r = a % p;
+    std::vector<int> okr(p, 1);
+    auto chain = [&](uint32_t r) {
       if (r == 0) {
-        while (fm < m) { fact = mul_small(fact, (uint32_t)fm); fm++; }
-        X[n] = rne_div(shl(mul_small(fact, q), K), MP::from_u64(p));
-        continue;
+        MP fact = MP::from_u64(1);   // running (fm - 1)!
+        uint64_t fm = 1;
+        for (int n = 0; n <= nmax; n++) {
+          const uint64_t a = (uint64_t)q * (uint64_t)(n + 1);
+          if (a % p != 0) continue;
+          const uint64_t m = a / p;
+          while (fm < m) { fact = mul_small(fact, (uint32_t)fm); fm++; }
+          X[n] = rne_div(shl(mul_small(fact, q), K), MP::from_u64(p));
+        }
+        return;
       }
-      if (ylo[r].sign() < 0) { ok = false; break; }
-      while (ym[r] < m) {
-        const uint64_t f = r + ym[r] * p;
-        if (f > 0xffffffffULL) { ok = false; break; }
-        uint32_t rem = 0;
-        ylo[r] = divmod_small(mul_small(ylo[r], (uint32_t)f), p, nullptr);
-        yhi[r] = divmod_small(mul_small(yhi[r], (uint32_t)f), p, &rem);
-        if (rem) yhi[r] = inc_mag(yhi[r]);
-        ym[r]++;
+      MP ylo = sub(gam[r].G, gam[r].err), yhi = add(gam[r].G, gam[r].err);
+      if (ylo.sign() < 0) { okr[r] = 0; return; }
+      uint64_t ym = 0;
+      for (int n = 0; n <= nmax; n++) {
+        const uint64_t a = (uint64_t)q * (uint64_t)(n + 1);
+        if (a % p != r) continue;
+        const uint64_t m = a / p;
+        while (ym < m) {
+          const uint64_t f = r + ym * p;
+          if (f > 0xffffffffULL) { okr[r] = 0; return; }
+          mul_in(ylo.d, f);
+          div32(ylo.d, p);
+          mul_in(yhi.d, f);
+          const bool exact = div32_rem(yhi.d, p) == 0;
+          if (!exact) yhi = inc_mag(yhi);
+          ym++;
+        }
+        // X_n = RNE(2^K q Y(m) / (p 2^F))
+        MP lo = rne_q_over_p2s(ylo, q, p, F - K);
+        MP hi = rne_q_over_p2s(yhi, q, p, F - K);
+        if (cmp(lo, hi) != 0) { okr[r] = 0; return; }
+        X[n] = lo;
       }
-      if (!ok) break;
-      // X_n = RNE(2^K q Y(m) / (p 2^F))
-      MP lo = rne_q_over_p2s(ylo[r], q, p, F - K);
-      MP hi = rne_q_over_p2s(yhi[r], q, p, F - K);
-      if (cmp(lo, hi) != 0) { ok = false; break; }
-      X[n] = lo;
+    };
+    {
+      std::vector<bool> used(p, false);
+      for (int n = 0; n <= nmax; n++) used[((uint64_t)q * (n + 1)) % p] = true;
+      std::vector<uint32_t> rs;
+      for (uint32_t r = 0; r < p; r++)
+        if (used[r] && (r == 0 || have[r])) rs.push_back(r);
+      if (rs.size() == 1) {
+        chain(rs[0]);
+      } else {
+        std::vector<std::thread> th;
+        for (uint32_t r : rs) th.emplace_back(chain, r);
+        for (auto& t : th) t.join();
+      }
     }
+    bool ok = true;
+    for (uint32_t r = 0; r < p; r++) ok = ok && okr[r];
     if (ok) return true;
   }
   return false;

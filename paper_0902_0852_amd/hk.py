@@ -93,7 +93,7 @@ EXPORTS = ["hk_workspace_bytes", "hk_build_matrix", "hk_factor", "hk_solve", "hk
            "hk_batch_workspace_bytes", "hk_eig_batched", "hk_autotune",
            "hk_mlp_nparams", "hk_mlp_cache_floats", "hk_mlp_forward", "hk_mlp_backward", "hk_mlp_mse",
            "hk_mlp_adam_step", "hk_mlp_propose", "hk_bracket_batched", "hk_learned_workspace_bytes",
-           "hk_eig_learned"]
+           "hk_eig_learned", "hk_moments_host"]
 
 
 def lib():
@@ -107,6 +107,8 @@ def lib():
         L.hk_workspace_bytes.argtypes = [I, Rational, I, I]
         L.hk_build_matrix.restype = I
         L.hk_build_matrix.argtypes = [I, Rational, I, P, SZ, P, ctypes.POINTER(P)]
+        L.hk_moments_host.restype = I
+        L.hk_moments_host.argtypes = [I, Rational, I, P, I64, P]
         L.hk_factor.restype = I
         L.hk_factor.argtypes = [P, MPF, I, P, ctypes.POINTER(I), ctypes.POINTER(I)]
         L.hk_solve.restype = I
@@ -219,6 +221,26 @@ def _io_to_ints(slen, off, dig, n):
         nd = -s if s < 0 else s
         v = int.from_bytes(raw[4 * o:4 * (o + nd)], "little") if nd else 0
         out.append(-v if s < 0 else v)
+    return out
+
+
+def moments_host(N, beta, K):
+    """The 2N - 1 fixed-point moments X_n = RNE(2^K mu_n) as Python ints,
+    computed by the library on the host (hk_moments_host)."""
+    L = lib()
+    off = (ctypes.c_int64 * (2 * N))()
+    st = L.hk_moments_host(N, _rational(beta), K, None, 0, off)
+    total = off[2 * N - 1]
+    if st != 1 or total <= 0:   # 1: HK_EINVAL, the expected answer of the sizing call
+        _check(st)
+    words = (ctypes.c_uint32 * max(1, total))()
+    _check(L.hk_moments_host(N, _rational(beta), K, words, total, off))
+    out = []
+    for n in range(2 * N - 1):
+        v = 0
+        for i in range(off[n + 1] - 1, off[n] - 1, -1):
+            v = (v << 32) | words[i]
+        out.append(v)
     return out
 
 
