@@ -185,12 +185,17 @@ __device__ __forceinline__ void accum_block(int64_t* acc, int& cnt, const int32_
 // A's 16 digits of block q (stride as) -= acc, with the pending carry into
 // this block (kin, NULL for block 0) folded in; the carry out goes to kout
 // (NULL for the top block, where it must vanish).
+// All 16 digits (and the carry) are loaded before the first store, so the
+// loads are in flight together rather than one after another.
 __device__ __forceinline__ void apply_block(const int64_t* acc, int32_t* Ap, int64_t as,
                                             const int64_t* kin, int64_t* kout, int32_t* flags) {
+  int32_t a[WB];
+#pragma unroll
+  for (int m = 0; m < WB; m++) a[m] = Ap[(int64_t)m * as];
   int64_t v = kin ? *kin : 0;
 #pragma unroll
   for (int m = 0; m < WB; m++) {
-    v += (int64_t)Ap[(int64_t)m * as] - acc[m];
+    v += (int64_t)a[m] - acc[m];
     const int32_t d = balanced29(v);
     Ap[(int64_t)m * as] = d;
     v = (v - d) >> DB;
@@ -744,30 +749,22 @@ __device__ __forceinline__ int divide_entry(int64_t* smem, const uint32_t* Sr, i
   int64_t* rem = smem + DOFF;                // positions -DOFF .. nu + 2
   int64_t* dd = rem + (nu + 3);              // nd + 1 (dd[nd] = 0)
   int64_t* qd = dd + (nd + 1);               // nu - nd + 2
-  for (int i = lane; i <= nd; i += 64) dd[i] = i < nd ? (int64_t)Dp[i] : 0;
-  for (int s = lane - DOFF; s < nu + 3; s += 64) {
-    int64_t x = 0;
-    if (s >= Sq && s < nu) {
-      const int i = s - Sq;
-      const uint64_t a = i < ns ? (uint64_t)Sr[i] : 0;
-      const uint64_t b = (i >= 1 && i - 1 < ns) ? (uint64_t)Sr[i - 1] : 0;
-      x = (int64_t)(((a << Sb) | (Sb ? (b >> (DB - Sb)) : 0)) & (RADIX - 1));
-    }
-    rem[s] = x;
-  }
-  const int jmax = __builtin_amdgcn_readfirstlane(nu - nd);
-  for (int j = lane; j <= jmax + 1; j += 64) qd[j] = 0;
-  lds_sync<BLK>();
+  // the divisor's registers come straight from Dp, so their loads overlap
+  // the fill of the remainder and of dd (the divisor digits that the bulk
+  // passes beyond the register groups read)
+  // (loads from clamped indices, then selects: no branch between the loads)
   const double R = (double)RADIX;
-  const double D3 = (double)dd[nd - 1] * R * R + (nd >= 2 ? (double)dd[nd - 2] * R : 0.0) +
-                    (nd >= 3 ? (double)dd[nd - 3] : 0.0);
-  const double ninvD = -R / D3;   // (negated) quotient estimates by one multiply
-  // top divisor digits for the register window: DT[m] = dd[nd - 1 - m]
+  const uint32_t d1 = Dp[nd - 1], d2 = Dp[max(nd - 2, 0)], d3 = Dp[max(nd - 3, 0)];
+  const double D3 = (double)d1 * R * R + (nd >= 2 ? (double)d2 * R : 0.0) + (nd >= 3 ? (double)d3 : 0.0);
+  // top divisor digits for the register window: DT[m] = Dp[nd - 1 - m]
   int32_t DT[DQ + 2];
 #pragma unroll
-  for (int m = 0; m < DQ + 2; m++) DT[m] = nd - 1 - m >= 0 ? (int32_t)dd[nd - 1 - m] : 0;
+  for (int m = 0; m < DQ + 2; m++) {
+    const int32_t v = (int32_t)Dp[max(nd - 1 - m, 0)];
+    DT[m] = nd - 1 - m >= 0 ? v : 0;
+  }
   // bulk positions of a pass: b + rel, rel = lane + 64 i in [0, nd - 3); the
-  // divisor digit that q[s] meets there is dd[rel + s + 1 - DQ], the same in
+  // divisor digit that q[s] meets there is Dp[rel + s + 1 - DQ], the same in
   // every pass
   const int nbulk = nd - 3;
   const int NI = nbulk > 0 ? (nbulk + 63) / 64 : 0;
@@ -779,8 +776,25 @@ __device__ __forceinline__ int divide_entry(int64_t* smem, const uint32_t* Sr, i
 #pragma unroll
     for (int s = 0; s < DQ; s++) {
       const int k = lane + 64 * i + s + 1 - DQ;
-      DDL[i][s] = (i < NI && k >= 0 && k < nd) ? (int32_t)dd[k] : 0;
+      const int32_t v = (int32_t)Dp[min(max(k, 0), nd - 1)];
+      DDL[i][s] = (i < NI && k >= 0 && k < nd) ? v : 0;
     }
+  for (int i = lane; i <= nd; i += 64) {
+    const int64_t v = (int64_t)Dp[min(i, nd - 1)];
+    dd[i] = i < nd ? v : 0;
+  }
+  for (int s = lane - DOFF; s < nu + 3; s += 64) {
+    const int i = s - Sq;
+    const uint64_t a = (uint64_t)Sr[min(max(i, 0), ns - 1)];
+    const uint64_t b = (uint64_t)Sr[min(max(i - 1, 0), ns - 1)];
+    const uint64_t av = i >= 0 && i < ns ? a : 0, bv = i >= 1 && i - 1 < ns ? b : 0;
+    const int64_t x = (int64_t)(((av << Sb) | (Sb ? (bv >> (DB - Sb)) : 0)) & (RADIX - 1));
+    rem[s] = s >= Sq && s < nu ? x : 0;
+  }
+  const int jmax = __builtin_amdgcn_readfirstlane(nu - nd);
+  for (int j = lane; j <= jmax + 1; j += 64) qd[j] = 0;
+  const double ninvD = -R / D3;   // (negated) quotient estimates by one multiply
+  lds_sync<BLK>();
   // register window: W[x] holds remainder position T + 1 - x
   int T = __builtin_amdgcn_readfirstlane(nu);
   int64_t W[DQ + 4];
@@ -1078,6 +1092,10 @@ __device__ __forceinline__ void column_step(const InstDesc* __restrict__ desc, i
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const ColInfo cc = I.cols[c];
   const int W = cc.W;
+  // this row's L^T placement, used only by the division at the end: loaded
+  // now so that its latency hides behind the row's first phases
+  const int64_t cr_ltoff = I.cols[r].ltoff;
+  const int cr_PT = I.cols[r].PT;
   char* base = (char*)smem;
   int32_t* pC = (int32_t*)base;
   uint32_t* pS = (uint32_t*)(pC + cc.CW);
@@ -1189,9 +1207,8 @@ __device__ __forceinline__ void column_step(const InstDesc* __restrict__ desc, i
   }
   __syncthreads();
   if (r == c || wave != 0) return;
-  const ColInfo cr = I.cols[r];
   const int n = divide_entry<false, DNIR>(dsm, oS, f.nstd, f.neg, pD, pinfo[0], pinfo[1], pinfo[2], I.h,
-                                    I.L + cc.loff + lr, cc.R, cc.LW, I.LT + cr.ltoff + c, cr.PT, I.flags);
+                                    I.L + cc.loff + lr, cc.R, cc.LW, I.LT + cr_ltoff + c, cr_PT, I.flags);
   if (lane == 0) {
     I.nL[tri_index(N, c, r)] = n;
     if (n > cc.LW - 2 * WB) atomicOr(&I.flags[0], 8);
