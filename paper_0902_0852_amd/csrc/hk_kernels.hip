@@ -36,6 +36,16 @@ __device__ __forceinline__ int wave_max(int v) {
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Device memory through global-address-space pointers: loads and stores
+// become global_* instructions, which the compiler never has to order against
+// LDS traffic (flat ones count against the LDS wait counter as well).
+#define GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ GLOBAL T* gp(T* p) { return (GLOBAL T*)p; }
+__device__ __forceinline__ void gor(GLOBAL int32_t* f, int32_t v) {
+  __hip_atomic_fetch_or(f, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // 64-bit lane moves: the value of lane i - 1 (lane 0: 0) by a DPP wave
 // shift, and the value of one (uniform) lane
 __device__ __forceinline__ int64_t lane_shr1(int64_t v) {
@@ -187,8 +197,9 @@ __device__ __forceinline__ void accum_block(int64_t* acc, int& cnt, const int32_
 // (NULL for the top block, where it must vanish).
 // All 16 digits (and the carry) are loaded before the first store, so the
 // loads are in flight together rather than one after another.
-__device__ __forceinline__ void apply_block(const int64_t* acc, int32_t* Ap, int64_t as,
-                                            const int64_t* kin, int64_t* kout, int32_t* flags) {
+__device__ __forceinline__ void apply_block(const int64_t* acc, GLOBAL int32_t* Ap, int64_t as,
+                                            const GLOBAL int64_t* kin, GLOBAL int64_t* kout,
+                                            GLOBAL int32_t* flags) {
   int32_t a[WB];
 #pragma unroll
   for (int m = 0; m < WB; m++) a[m] = Ap[(int64_t)m * as];
@@ -202,7 +213,7 @@ __device__ __forceinline__ void apply_block(const int64_t* acc, int32_t* Ap, int
   }
   v -= acc[WB];
   if (kout) *kout = v;
-  else if (v != 0) atomicOr(&flags[0], 1);
+  else if (v != 0) gor(flags, 1);
 }
 
 // column and panel ranges of one update launch for an instance of size N:
@@ -257,7 +268,7 @@ __device__ __forceinline__ void update_item(const InstDesc* __restrict__ desc, i
   while (n > 1) {
     const int step = (n + 63) / 64;
     const int k = lane * step;
-    const int v = k < n ? I.itemStart[lo + k] : INT_MAX;
+    const int v = k < n ? gp(I.itemStart)[lo + k] : INT_MAX;
     const uint64_t m = __ballot(v <= it);
     const int last = 63 - __clzll((long long)m);
     lo = uni(lo + last * step);
@@ -281,7 +292,7 @@ __device__ __forceinline__ void update_item(const InstDesc* __restrict__ desc, i
   for (int k = k0; k < k1; k++) {
     const ColInfo kk = sload(I.cols + k);
     const int nC = min(sload(I.nC + tri_index(N, k, c)), kk.CW - WB);
-    const int nLl = active ? I.nL[tri_index(N, k, rr)] : 0;
+    const int nLl = active ? gp(I.nL)[tri_index(N, k, rr)] : 0;
     const int nL = min(uni(wave_max(nLl)), kk.LW - 2 * WB);
     accum_block(acc, cnt, uptr(I.C + kk.coff + (int64_t)(c - k) * kk.CW), nC, uptr(I.L + kk.loff),
                 (int64_t)kk.LW * kk.R * 4, rr - k, kk.R, nL, q);
@@ -289,9 +300,9 @@ __device__ __forceinline__ void update_item(const InstDesc* __restrict__ desc, i
   if (!active) return;
   const int lr = r - c;
   int64_t* Kcol = I.Kc + cc.koff;
-  apply_block(acc, I.A + cc.aoff + (int64_t)(WB * q) * cc.R + lr, cc.R,
-              q > 0 ? Kcol + ((int64_t)rd * cc.nb + q) * cc.R + lr : nullptr,
-              q + 1 < cc.nb ? Kcol + ((int64_t)(rd ^ 1) * cc.nb + q + 1) * cc.R + lr : nullptr, I.flags);
+  apply_block(acc, gp(I.A + cc.aoff + (int64_t)(WB * q) * cc.R + lr), cc.R,
+              q > 0 ? gp(Kcol + ((int64_t)rd * cc.nb + q) * cc.R + lr) : nullptr,
+              q + 1 < cc.nb ? gp(Kcol + ((int64_t)(rd ^ 1) * cc.nb + q + 1) * cc.R + lr) : nullptr, gp(I.flags));
 }
 
 __global__ void __launch_bounds__(256) k_update(const InstDesc* __restrict__ desc, int count, int pc,
@@ -367,9 +378,9 @@ __device__ int64_t wave_resolve(int32_t* x, int nblk, int64_t* cin, int64_t* cou
 // lane normalises blocks of FB digits (a divisor of 16) one digit after
 // another; the carries between blocks are then resolved in rounds.  LDS:
 // dg and ob of W + 48 int32, ca and cb of W/FB + 8 int64.
-template <bool BLK = true, int FB = WB, bool PRE = false>
+template <bool BLK = true, int FB = WB, bool PRE = false, typename CT, typename ST>
 __device__ FinOut wave_finalize(const int32_t* Ap, int64_t as, int W, const int64_t* Kp, int64_t ks,
-                                int h, int32_t* Cr, uint32_t* Sr, int cap, int32_t* flags,
+                                int h, CT Cr, ST Sr, int cap, GLOBAL int32_t* flags,
                                 int32_t* dg, int32_t* ob, int64_t* ca, int64_t* cb,
                                 const int64_t* Psub = nullptr, uint32_t* Sl = nullptr) {
   const int lane = threadIdx.x & 63;
@@ -403,7 +414,7 @@ __device__ FinOut wave_finalize(const int32_t* Ap, int64_t as, int W, const int6
   if (lane == 0) ca[0] = 0;
   lds_sync<BLK>();
   // carries out of block q were stored in ca[q+1]: the carry into block q
-  if (wave_resolve<true, BLK, FB>(dg, nb, ca, cb) != 0 && lane == 0) atomicOr(&flags[0], 2);
+  if (wave_resolve<true, BLK, FB>(dg, nb, ca, cb) != 0 && lane == 0) gor(flags, 2);
   // 2. sign: the top nonzero digit
   int mytop = -1;
   for (int s = lane; s < W; s += 64) if (dg[s] != 0) mytop = s;
@@ -449,7 +460,7 @@ __device__ FinOut wave_finalize(const int32_t* Ap, int64_t as, int W, const int6
   const int inc = half && (sticky || (ob[0] & 1));
   for (int q = lane; q <= nbo; q += 64) ca[q] = (q == 0) ? inc : 0;
   lds_sync<BLK>();
-  if (wave_resolve<false, BLK, FB>(ob, nbo, ca, cb) != 0 && lane == 0) atomicOr(&flags[0], 16);
+  if (wave_resolve<false, BLK, FB>(ob, nbo, ca, cb) != 0 && lane == 0) gor(flags, 16);
   // 5. standard digits out; balanced copy with the sign
   int ts = -1;
   for (int i = lane; i < nbo * FB; i += 64) {
@@ -458,7 +469,7 @@ __device__ FinOut wave_finalize(const int32_t* Ap, int64_t as, int W, const int6
       Sr[i] = (uint32_t)u;
       if (Sl) Sl[i] = (uint32_t)u;
     }
-    if (u != 0) { ts = i; if (i >= cap) atomicOr(&flags[0], 16); }
+    if (u != 0) { ts = i; if (i >= cap) gor(flags, 16); }
   }
   for (int i = nbo * FB + lane; i < cap; i += 64) {
     Sr[i] = 0;
@@ -489,7 +500,7 @@ __device__ FinOut wave_finalize(const int32_t* Ap, int64_t as, int W, const int6
     Cr[i] = d;
     if (d != 0) tb = i;
   }
-  if (extra != 0 && nbo * FB >= cap && lane == 0) atomicOr(&flags[0], 16);
+  if (extra != 0 && nbo * FB >= cap && lane == 0) gor(flags, 16);
   FinOut f;
   f.nbal = wave_max(tb) + 1;
   f.nstd = stop + 1;
@@ -537,8 +548,8 @@ __device__ __forceinline__ int64_t reg_resolve(int64_t* d, int64_t c, int nbl) {
 // moves between lanes by DPP shifts instead of LDS rounds.  Inputs as in
 // wave_finalize's PRE form (lazy digits in dg, pending 16-block carries in
 // cb, optional subtrahend Psub); ob (W + 48 int32) is scratch for the shift.
-template <bool BLK, int R>
-__device__ __forceinline__ FinOut wave_finalize_reg(int W, int h, int32_t* Cr, uint32_t* Sr, int cap, int32_t* flags,
+template <bool BLK, int R, typename CT, typename ST>
+__device__ __forceinline__ FinOut wave_finalize_reg(int W, int h, CT Cr, ST Sr, int cap, GLOBAL int32_t* flags,
                                     const int32_t* dg, int32_t* ob, const int64_t* cb,
                                     const int64_t* Psub, uint32_t* Sl) {
   const int lane = threadIdx.x & 63;
@@ -559,7 +570,7 @@ __device__ __forceinline__ FinOut wave_finalize_reg(int W, int h, int32_t* Cr, u
       t = (t - d[m]) >> DB;
     }
     const int64_t top = lane_read(t, nbl - 1) + reg_resolve<true, R>(d, lane_shr1(lane < nbl - 1 ? t : 0), nbl);
-    if (top != 0 && lane == 0) atomicOr(&flags[0], 2);
+    if (top != 0 && lane == 0) gor(flags, 2);
   }
   // 2. sign: the top nonzero digit
   int mytop = -1, mysign = 0;
@@ -612,7 +623,7 @@ __device__ __forceinline__ FinOut wave_finalize_reg(int W, int h, int32_t* Cr, u
   const int sticky = __any(st) || (hbit > 0 && (hd & ((1u << hbit) - 1)));
   const int half = (hd >> hbit) & 1;
   const int inc = half && (sticky || (lane_read(o[0], 0) & 1));
-  if (reg_resolve<false, R>(o, lane == 0 ? inc : 0, nbo) != 0 && lane == 0) atomicOr(&flags[0], 16);
+  if (reg_resolve<false, R>(o, lane == 0 ? inc : 0, nbo) != 0 && lane == 0) gor(flags, 16);
   // 5. standard digits out; balanced copy with the sign
   int ts = -1;
   uint32_t tv = 0;
@@ -628,7 +639,7 @@ __device__ __forceinline__ FinOut wave_finalize_reg(int W, int h, int32_t* Cr, u
     if (u != 0) {
       ts = i;
       tv = u;
-      if (i >= cap) atomicOr(&flags[0], 16);
+      if (i >= cap) gor(flags, 16);
     }
   }
   for (int i = nbo * R + lane; i < cap; i += 64) {
@@ -656,7 +667,7 @@ __device__ __forceinline__ FinOut wave_finalize_reg(int W, int h, int32_t* Cr, u
         Cr[i] = v;
         if (v != 0) tb = i;
       } else if (v != 0) {
-        atomicOr(&flags[0], 16);
+        gor(flags, 16);
       }
     }
     for (int i = nbo * R + lane; i < cap; i += 64) {
@@ -664,7 +675,7 @@ __device__ __forceinline__ FinOut wave_finalize_reg(int W, int h, int32_t* Cr, u
       Cr[i] = v;
       if (v != 0) tb = i;
     }
-    if (extra != 0 && nbo * R >= cap && lane == 0) atomicOr(&flags[0], 16);
+    if (extra != 0 && nbo * R >= cap && lane == 0) gor(flags, 16);
     FinOut f;
     f.nbal = wave_max(tb) + 1;
     f.nstd = stop + 1;
@@ -730,14 +741,14 @@ __device__ __forceinline__ int64_t bulk_split(int64_t x, int64_t& prev) {
 // digits to out[j * os] (zero filled) and returns the digit count.
 template <bool BLK = true, int DNIR = 4>
 __device__ __forceinline__ int divide_entry(int64_t* smem, const uint32_t* Sr, int ns, int negN,
-                            const uint32_t* Dp, int nd, int sh, int negd, int h, int32_t* out,
-                            int64_t os, int cap, int32_t* out2, int64_t os2, int32_t* flags) {
+                            const uint32_t* Dp, int nd, int sh, int negd, int h, GLOBAL int32_t* out,
+                            int64_t os, int cap, GLOBAL int32_t* out2, int64_t os2, GLOBAL int32_t* flags) {
   const int lane = threadIdx.x & 63;
   nd = __builtin_amdgcn_readfirstlane(nd);
   ns = __builtin_amdgcn_readfirstlane(ns);
   if (nd == 0) {
     for (int j = lane; j < cap; j += 64) { out[(int64_t)j * os] = 0; if (out2) out2[(int64_t)j * os2] = 0; }
-    if (lane == 0) atomicOr(&flags[0], 4);
+    if (lane == 0) gor(flags, 4);
     return 0;
   }
   const int Sbits = h + sh, Sq = Sbits / DB, Sb = Sbits % DB;
@@ -949,7 +960,7 @@ __device__ __forceinline__ int divide_entry(int64_t* smem, const uint32_t* Sr, i
       const int64_t x = j <= jmax ? qd[j] : 0;
       int64_t o = balanced29(x);
       if (j - 1 <= jmax) { const int64_t y = qd[j - 1]; o += (y - balanced29(y)) >> DB; }
-      if (o != 0) atomicOr(&flags[0], 8);
+      if (o != 0) gor(flags, 8);
     }
   }
   return wave_max(mytop) + 1;
@@ -962,12 +973,15 @@ constexpr int FIN_FB = 4;
 // The finalisation of the column and solve kernels (digits already in dg,
 // carries in cb): in registers, 2 or 8 digits a lane, while the number and
 // the shifted result both fit 64 lanes, else through LDS.
-__device__ __forceinline__ FinOut finalize_pre(int W, int h, int32_t* Cr, uint32_t* Sr, int cap, int32_t* flags,
+template <typename CT, typename ST>
+__device__ __forceinline__ FinOut finalize_pre(int W, int h, CT Cr, ST Sr, int cap, GLOBAL int32_t* flags,
                                                int32_t* dg, int32_t* ob, int64_t* ca, int64_t* cb,
                                                const int64_t* Psub, uint32_t* Sl = nullptr) {
   const int nout = W - h / DB + 1;
-  if (W <= 64 * 2 && nout <= 64 * 2) return wave_finalize_reg<false, 2>(W, h, Cr, Sr, cap, flags, dg, ob, cb, Psub, Sl);
-  if (W <= 64 * 8 && nout <= 64 * 8) return wave_finalize_reg<false, 8>(W, h, Cr, Sr, cap, flags, dg, ob, cb, Psub, Sl);
+  if (W <= 64 * 2 && nout <= 64 * 2)
+    return wave_finalize_reg<false, 2>(W, h, Cr, Sr, cap, flags, dg, ob, cb, Psub, Sl);
+  if (W <= 64 * 8 && nout <= 64 * 8)
+    return wave_finalize_reg<false, 8>(W, h, Cr, Sr, cap, flags, dg, ob, cb, Psub, Sl);
   return wave_finalize<false, FIN_FB, true>(nullptr, 0, W, nullptr, 0, h, Cr, Sr, cap, flags, dg, ob, ca, cb,
                                             Psub, Sl);
 }
@@ -975,7 +989,8 @@ __device__ __forceinline__ FinOut finalize_pre(int W, int h, int32_t* Cr, uint32
 
 // |d| 2^sh as standard digits, top digit in [2^28, 2^29): every output digit
 // takes its own input digit shifted up and the top bits of the one below
-__device__ __forceinline__ void normalise_divisor(const uint32_t* S, int n, int sh, uint32_t* out) {
+template <typename SP, typename OP>
+__device__ __forceinline__ void normalise_divisor(SP S, int n, int sh, OP out) {
   for (int i = threadIdx.x & 63; i < n; i += 64) {
     const uint32_t lo = i > 0 && sh > 0 ? S[i - 1] >> (DB - sh) : 0u;
     out[i] = ((S[i] << sh) | lo) & (uint32_t)(RADIX - 1);
@@ -1080,7 +1095,7 @@ __device__ __forceinline__ void column_step(const InstDesc* __restrict__ desc, i
   __builtin_amdgcn_s_setprio(3);
   int bid = blockIdx.x, inst = -1;
   for (int i = 0; i < count; i++) {
-    const int n = max(0, desc[i].N - c);
+    const int n = max(0, gp(desc)[i].N - c);
     if (bid < n) { inst = i; break; }
     bid -= n;
   }
@@ -1094,8 +1109,8 @@ __device__ __forceinline__ void column_step(const InstDesc* __restrict__ desc, i
   const int W = cc.W;
   // this row's L^T placement, used only by the division at the end: loaded
   // now so that its latency hides behind the row's first phases
-  const int64_t cr_ltoff = I.cols[r].ltoff;
-  const int cr_PT = I.cols[r].PT;
+  const int64_t cr_ltoff = gp(I.cols)[r].ltoff;
+  const int cr_PT = gp(I.cols)[r].PT;
   char* base = (char*)smem;
   int32_t* pC = (int32_t*)base;
   uint32_t* pS = (uint32_t*)(pC + cc.CW);
@@ -1109,8 +1124,10 @@ __device__ __forceinline__ void column_step(const InstDesc* __restrict__ desc, i
   int64_t* cb = ca + (W / FIN_FB + 8);
   int64_t* Pd = cb + (W / FIN_FB + 8);           // product digits, W
   int64_t* dsm = (int64_t*)(base + piv_bytes);
-  const int64_t* Kc = I.Kc + cc.koff + (int64_t)rd * cc.nb * cc.R;
-  uint32_t* Srow = I.S + cc.soff + (int64_t)lr * cc.CW;
+  const GLOBAL int64_t* Kc = gp(I.Kc + cc.koff + (int64_t)rd * cc.nb * cc.R);
+  GLOBAL uint32_t* Srow = gp(I.S + cc.soff + (int64_t)lr * cc.CW);
+  const GLOBAL int32_t* Ag = gp(I.A + cc.aoff);
+  GLOBAL int32_t* flg = gp(I.flags);
   // the row this wavefront finalises
   const int fr = wave == 0 ? r : c;
   const bool work = wave == 0 || r != c;
@@ -1122,8 +1139,8 @@ __device__ __forceinline__ void column_step(const InstDesc* __restrict__ desc, i
   const int flr = fr - c;
   const bool updr = upd && work && c > 0;
   const ColInfo ck = I.cols[c > 0 ? c - 1 : 0];
-  const int32_t* Lsrc = I.L + ck.loff + (fr - (c - 1));
-  const int32_t* Csrc = I.C + ck.coff + (int64_t)ck.CW;
+  const GLOBAL int32_t* Lsrc = gp(I.L + ck.loff + (fr - (c - 1)));
+  const GLOBAL int32_t* Csrc = gp(I.C + ck.coff + (int64_t)ck.CW);
   int32_t* Lr = (int32_t*)(Pd + W);            // L_{c-1}[fr], LW + 8
   int32_t* Cp = Lr + (ck.LW + 8);              // C_{c-1}[c], CW
   constexpr int U = 8;
@@ -1134,14 +1151,14 @@ __device__ __forceinline__ void column_step(const InstDesc* __restrict__ desc, i
 #pragma unroll
     for (int u = 0; u < U; u++) {
       const int x = lane + 64 * u;
-      av[u] = x < W ? I.A[cc.aoff + (int64_t)x * cc.R + flr] : 0;
+      av[u] = x < W ? Ag[(int64_t)x * cc.R + flr] : 0;
       lv[u] = updr && x < ck.LW ? Lsrc[(int64_t)x * ck.R] : 0;
       cv[u] = updr && x < ck.CW ? Csrc[x] : 0;
     }
     kv = lane > 0 && lane < cc.nb ? Kc[(int64_t)lane * cc.R + flr] : 0;
     if (updr) {
-      nL = min(I.nL[tri_index(N, c - 1, fr)], ck.LW);
-      nC = min(I.nC[tri_index(N, c - 1, c)], ck.CW);
+      nL = min(gp(I.nL)[tri_index(N, c - 1, fr)], ck.LW);
+      nC = min(gp(I.nC)[tri_index(N, c - 1, c)], ck.CW);
     }
 #pragma unroll
     for (int u = 0; u < U; u++) {
@@ -1151,7 +1168,7 @@ __device__ __forceinline__ void column_step(const InstDesc* __restrict__ desc, i
       if (updr && x < ck.CW) Cp[x] = cv[u];
     }
     if (lane < cc.nb) cb[lane] = kv;
-    for (int x = lane + 64 * U; x < W; x += 64) dg[x] = I.A[cc.aoff + (int64_t)x * cc.R + flr];
+    for (int x = lane + 64 * U; x < W; x += 64) dg[x] = Ag[(int64_t)x * cc.R + flr];
     for (int q = lane + 64; q < cc.nb; q += 64) cb[q] = Kc[(int64_t)q * cc.R + flr];
     if (updr) {
       for (int x = lane + 64 * U; x < ck.LW; x += 64) Lr[x] = Lsrc[(int64_t)x * ck.R];
@@ -1170,32 +1187,33 @@ __device__ __forceinline__ void column_step(const InstDesc* __restrict__ desc, i
   f.nstd = 0;
   f.neg = 0;
   if (wave == 0) {
-    f = finalize_pre(W, I.h, I.C + cc.coff + (int64_t)lr * cc.CW, Srow, cc.CW, I.flags, dg, ob, ca, cb, Psub,
+    f = finalize_pre(W, I.h, gp(I.C + cc.coff + (int64_t)lr * cc.CW), Srow, cc.CW, flg, dg, ob, ca, cb, Psub,
                      oS);
     const int64_t ti = tri_index(N, c, r);
     if (lane == 0) {
-      I.nC[ti] = f.nbal;
-      I.nCs[ti] = f.neg ? -f.nstd : f.nstd;
-      I.b32C[ti] = (f.bits + 31) / 32;
+      gp(I.nC)[ti] = f.nbal;
+      gp(I.nCs)[ti] = f.neg ? -f.nstd : f.nstd;
+      gp(I.b32C)[ti] = (f.bits + 31) / 32;
     }
     if (r == c) {
       const int sh = f.nstd > 0 ? 28 - (31 - __clz(f.topv)) : 0;
       if (lane == 0) {
         if (f.nstd == 0 || f.neg) {
-          atomicMin(&I.flags[1], c);
-          if (f.nstd > 0 && f.neg) atomicAdd(&I.flags[2], 1);
+          __hip_atomic_fetch_min(flg + 1, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (f.nstd > 0 && f.neg) __hip_atomic_fetch_add(flg + 2, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        I.dinfo[4 * c] = f.nstd;
-        I.dinfo[4 * c + 1] = sh;
-        I.dinfo[4 * c + 2] = f.nstd > 0 ? f.neg : 0;
+        GLOBAL int32_t* di = gp(I.dinfo);
+        di[4 * c] = f.nstd;
+        di[4 * c + 1] = sh;
+        di[4 * c + 2] = f.nstd > 0 ? f.neg : 0;
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      normalise_divisor(Srow, f.nstd, sh, I.D + cc.doff);
+      normalise_divisor(Srow, f.nstd, sh, gp(I.D + cc.doff));
     }
   } else if (work) {
-    const FinOut p = finalize_pre(W, I.h, pC, pS, cc.CW, I.flags, dg, ob, ca, cb, Psub);
+    const FinOut p = finalize_pre(W, I.h, pC, pS, cc.CW, flg, dg, ob, ca, cb, Psub);
     const int sh = p.nstd > 0 ? 28 - (31 - __clz(p.topv)) : 0;
     lds_sync<false>();
     normalise_divisor(pS, p.nstd, sh, pD);
@@ -1208,10 +1226,10 @@ __device__ __forceinline__ void column_step(const InstDesc* __restrict__ desc, i
   __syncthreads();
   if (r == c || wave != 0) return;
   const int n = divide_entry<false, DNIR>(dsm, oS, f.nstd, f.neg, pD, pinfo[0], pinfo[1], pinfo[2], I.h,
-                                    I.L + cc.loff + lr, cc.R, cc.LW, I.LT + cr_ltoff + c, cr_PT, I.flags);
+                                    gp(I.L + cc.loff + lr), cc.R, cc.LW, gp(I.LT + cr_ltoff + c), cr_PT, flg);
   if (lane == 0) {
-    I.nL[tri_index(N, c, r)] = n;
-    if (n > cc.LW - 2 * WB) atomicOr(&I.flags[0], 8);
+    gp(I.nL)[tri_index(N, c, r)] = n;
+    if (n > cc.LW - 2 * WB) gor(flg, 8);
   }
 }
 
@@ -1239,7 +1257,7 @@ __global__ void __launch_bounds__(64) k_vscale(int K, const uint32_t* __restrict
   const int i = blockIdx.x;
   const int nsg = nUs[i];
   divide_entry(smem, us + (int64_t)i * VW, nsg < 0 ? -nsg : nsg, nsg < 0, md, nd, sh, 0, K,
-               out + (int64_t)i * VW, 1, VW, nullptr, 0, flags);
+               gp(out + (int64_t)i * VW), 1, VW, nullptr, 0, gp(flags));
 }
 
 // ---------------------------------------------------------------- solves
@@ -1298,9 +1316,9 @@ __device__ __forceinline__ void vupdate_item(const ColInfo* __restrict__ cols, i
     accum_block(a, cnt, ub + (int64_t)k * VW, nC, Lp, nbytes, lo, P, nL, q);
   }
   if (!active) return;
-  apply_block(a, acc + (int64_t)(WB * q) * Npad + i, Npad,
-              q > 0 ? kc + ((int64_t)rd * nbA + q) * Npad + i : nullptr,
-              q + 1 < nbA ? kc + ((int64_t)(rd ^ 1) * nbA + q + 1) * Npad + i : nullptr, flags);
+  apply_block(a, gp(acc + (int64_t)(WB * q) * Npad + i), Npad,
+              q > 0 ? gp(kc + ((int64_t)rd * nbA + q) * Npad + i) : nullptr,
+              q + 1 < nbA ? gp(kc + ((int64_t)(rd ^ 1) * nbA + q + 1) * Npad + i) : nullptr, gp(flags));
 }
 
 
@@ -1340,8 +1358,8 @@ __global__ void __launch_bounds__(64) k_vdivide_b(const SweepArgs* __restrict__ 
   if (k >= a.N) return;
   const int nsg = a.nUs[k];
   divide_entry(smem, a.us + (int64_t)k * a.VW, nsg < 0 ? -nsg : nsg, nsg < 0, a.Dd + a.cols[k].doff,
-                   a.dinfo[4 * k], a.dinfo[4 * k + 1], a.dinfo[4 * k + 2], a.h, a.wb + (int64_t)k * a.VW, 1,
-                   a.VW, nullptr, 0, a.flags);
+                   a.dinfo[4 * k], a.dinfo[4 * k + 1], a.dinfo[4 * k + 2], a.h, gp(a.wb + (int64_t)k * a.VW), 1,
+                   a.VW, nullptr, 0, gp(a.flags));
 }
 
 
@@ -1385,10 +1403,12 @@ __global__ void __launch_bounds__(256) k_vcol_b(const SweepArgs* __restrict__ ar
   int64_t* cb = ca + (VA / FIN_FB + 8);
   int64_t* Pd = cb + (VA / FIN_FB + 8);        // product digits, VA
   const int rd = (j + 1) & 1;
-  const int64_t* Kc = a.kc + (int64_t)rd * a.nbA * a.Npad + k;
+  const GLOBAL int64_t* Kc = gp(a.kc + (int64_t)rd * a.nbA * a.Npad + k);
+  const GLOBAL int32_t* accg = gp(a.acc + k);
+  const GLOBAL int32_t* ubg = gp(a.ub);
   // the operands of the row's update by column p: V digits (stride P) and u_p
   const ColInfo cp = a.cols[has_p ? p : k];
-  const int32_t* Vsrc = bwd ? a.LT + cp.ltoff + k : a.L + cp.loff + 1;
+  const GLOBAL int32_t* Vsrc = gp(bwd ? a.LT + cp.ltoff + k : a.L + cp.loff + 1);
   const int Vstride = bwd ? cp.PT : cp.R;
   const int Vcap = bwd ? min(a.cols[k].LW, a.LWT) : cp.LW;
   int32_t* Lr = (int32_t*)(Pd + VA);           // Vcap + 8
@@ -1400,15 +1420,15 @@ __global__ void __launch_bounds__(256) k_vcol_b(const SweepArgs* __restrict__ ar
 #pragma unroll
   for (int u = 0; u < U; u++) {
     const int x = lane + 64 * u;
-    av[u] = x < VA ? a.acc[(int64_t)x * a.Npad + k] : 0;
+    av[u] = x < VA ? accg[(int64_t)x * a.Npad] : 0;
     lv[u] = has_p && x < Vcap ? Vsrc[(int64_t)x * Vstride] : 0;
-    uv[u] = has_p && x < a.VW ? a.ub[(int64_t)p * a.VW + x] : 0;
+    uv[u] = has_p && x < a.VW ? ubg[(int64_t)p * a.VW + x] : 0;
   }
   kv = lane > 0 && lane < a.nbA ? Kc[(int64_t)lane * a.Npad] : 0;
   if (has_p) {
-    nL = min(a.nL[bwd ? tri_index(N, k, p) : tri_index(N, p, k)], Vcap - 2 * WB);
+    nL = min(gp(a.nL)[bwd ? tri_index(N, k, p) : tri_index(N, p, k)], Vcap - 2 * WB);
     nL = min(nL, a.LWT - 2 * WB);
-    nC = min(a.nU[p], a.VW - WB);
+    nC = min(gp(a.nU)[p], a.VW - WB);
   }
 #pragma unroll
   for (int u = 0; u < U; u++) {
@@ -1418,12 +1438,12 @@ __global__ void __launch_bounds__(256) k_vcol_b(const SweepArgs* __restrict__ ar
     if (has_p && x < a.VW) Up[x] = uv[u];
   }
   if (lane < a.nbA) cb[lane] = kv;
-  for (int x = lane + 64 * U; x < VA; x += 64) dg[x] = a.acc[(int64_t)x * a.Npad + k];
+  for (int x = lane + 64 * U; x < VA; x += 64) dg[x] = accg[(int64_t)x * a.Npad];
   for (int q = lane + 64; q < a.nbA; q += 64) cb[q] = Kc[(int64_t)q * a.Npad];
   const int64_t* Psub = nullptr;
   if (has_p) {
     for (int x = lane + 64 * U; x < Vcap; x += 64) Lr[x] = Vsrc[(int64_t)x * Vstride];
-    for (int x = lane + 64 * U; x < a.VW; x += 64) Up[x] = a.ub[(int64_t)p * a.VW + x];
+    for (int x = lane + 64 * U; x < a.VW; x += 64) Up[x] = ubg[(int64_t)p * a.VW + x];
     for (int x = Vcap + lane; x < Vcap + 8; x += 64) Lr[x] = 0;
     lds_sync<false>();
     if (VA <= 128) near_product<2, false>(Lr, nL, Up, nC, VA, Pd, a.flags);
@@ -1431,16 +1451,16 @@ __global__ void __launch_bounds__(256) k_vcol_b(const SweepArgs* __restrict__ ar
     Psub = Pd;
   }
   lds_sync<false>();
-  const FinOut f = finalize_pre(VA, a.h, a.ub + (int64_t)k * a.VW, a.us + (int64_t)k * a.VW, a.VW, a.flags, dg,
-                                ob, ca, cb, Psub);
+  const FinOut f = finalize_pre(VA, a.h, gp(a.ub + (int64_t)k * a.VW), gp(a.us + (int64_t)k * a.VW), a.VW,
+                                gp(a.flags), dg, ob, ca, cb, Psub);
   if (lane == 0) {
-    a.nU[k] = f.nbal;
-    a.nUs[k] = f.neg ? -f.nstd : f.nstd;
-    if (f.nbal > a.VW - WB) atomicOr(&a.flags[0], 32);
+    gp(a.nU)[k] = f.nbal;
+    gp(a.nUs)[k] = f.neg ? -f.nstd : f.nstd;
+    if (f.nbal > a.VW - WB) gor(gp(a.flags), 32);
   }
   // the backward sweep's result; each lane copies the digits it wrote itself
   if (bwd && a.y)
-    for (int x = lane; x < a.VW; x += 64) a.y[(int64_t)k * a.VW + x] = a.ub[(int64_t)k * a.VW + x];
+    for (int x = lane; x < a.VW; x += 64) gp(a.y)[(int64_t)k * a.VW + x] = gp(a.ub)[(int64_t)k * a.VW + x];
 }
 
 
@@ -1563,7 +1583,7 @@ __global__ void __launch_bounds__(64) k_vscale_b(const SweepArgs* __restrict__ a
   if (i >= a.N) return;
   const int nsg = a.nUs[i];
   divide_entry(smem, a.us + (int64_t)i * a.VW, nsg < 0 ? -nsg : nsg, nsg < 0, a.md, a.mdinfo[0],
-                   a.mdinfo[1], 0, a.K, a.v + (int64_t)i * a.VW, 1, a.VW, nullptr, 0, a.flags);
+                   a.mdinfo[1], 0, a.K, gp(a.v + (int64_t)i * a.VW), 1, a.VW, nullptr, 0, gp(a.flags));
 }
 
 
