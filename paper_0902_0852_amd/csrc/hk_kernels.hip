@@ -758,25 +758,41 @@ __device__ __forceinline__ int divide_entry(int64_t* smem, const uint32_t* Sr, i
     return 0;
   }
   int64_t* rem = smem + DOFF;                // positions -DOFF .. nu + 2
-  int64_t* dd = rem + (nu + 3);              // nd + 1 (dd[nd] = 0)
-  int64_t* qd = dd + (nd + 1);               // nu - nd + 2
-  // the divisor's registers come straight from Dp, so their loads overlap
-  // the fill of the remainder and of dd (the divisor digits that the bulk
-  // passes beyond the register groups read)
-  // (loads from clamped indices, then selects: no branch between the loads)
+  // the divisor digits with zeros around them: DPAD below, up to the
+  // register groups' reach above, so that every register of the divisor
+  // below is one unconditional LDS read
+  static_assert(DNIR >= 1 && DNIR <= 4, "divide_shm sizes the divisor padding for at most 4 groups");
+  constexpr int DPAD = 16, DHI = 64 * DNIR + 16;
+  int64_t* dd = rem + (nu + 3) + DPAD;       // dd[-DPAD .. nd + DHI)
+  int64_t* qd = dd + nd + DHI;               // nu - nd + 2
+  // (the loads of a fill are issued unconditionally from clamped indices and
+  // pinned by an empty asm statement, so the compiler cannot sink each one
+  // into a branch of its own with a wait behind it)
+  for (int i = lane; i < nd; i += 64) dd[i] = (int64_t)Dp[i];
+  for (int i = lane - DPAD; i < 0; i += 64) dd[i] = 0;
+  for (int i = nd + lane; i < nd + DHI; i += 64) dd[i] = 0;
+  for (int s = lane - DOFF; s < Sq; s += 64) rem[s] = 0;
+  for (int s = nu + lane; s < nu + 3; s += 64) rem[s] = 0;
+  for (int s = Sq + lane; s < nu; s += 64) {
+    const int i = s - Sq;                    // 0 .. ns
+    uint32_t a = Sr[min(i, ns - 1)], b = Sr[max(i - 1, 0)];
+    asm volatile("" : "+v"(a), "+v"(b));
+    const uint64_t av = i < ns ? a : 0u, bv = i >= 1 ? b : 0u;
+    rem[s] = (int64_t)(((av << Sb) | (Sb ? (bv >> (DB - Sb)) : 0)) & (RADIX - 1));
+  }
+  const int jmax = __builtin_amdgcn_readfirstlane(nu - nd);
+  for (int j = lane; j <= jmax + 1; j += 64) qd[j] = 0;
+  lds_sync<BLK>();
   const double R = (double)RADIX;
-  const uint32_t d1 = Dp[nd - 1], d2 = Dp[max(nd - 2, 0)], d3 = Dp[max(nd - 3, 0)];
-  const double D3 = (double)d1 * R * R + (nd >= 2 ? (double)d2 * R : 0.0) + (nd >= 3 ? (double)d3 : 0.0);
-  // top divisor digits for the register window: DT[m] = Dp[nd - 1 - m]
+  const double D3 = (double)dd[nd - 1] * R * R + (double)dd[nd - 2] * R + (double)dd[nd - 3];
+  const double ninvD = -R / D3;   // (negated) quotient estimates by one multiply
+  // top divisor digits for the register window: DT[m] = dd[nd - 1 - m]
   int32_t DT[DQ + 2];
 #pragma unroll
-  for (int m = 0; m < DQ + 2; m++) {
-    const int32_t v = (int32_t)Dp[max(nd - 1 - m, 0)];
-    DT[m] = nd - 1 - m >= 0 ? v : 0;
-  }
+  for (int m = 0; m < DQ + 2; m++) DT[m] = (int32_t)dd[nd - 1 - m];
   // bulk positions of a pass: b + rel, rel = lane + 64 i in [0, nd - 3); the
-  // divisor digit that q[s] meets there is Dp[rel + s + 1 - DQ], the same in
-  // every pass
+  // divisor digit that q[s] meets there is dd[rel + s + 1 - DQ], the same in
+  // every pass (zero beyond the divisor, so groups past the last are inert)
   const int nbulk = nd - 3;
   const int NI = nbulk > 0 ? (nbulk + 63) / 64 : 0;
   const int top_group = __builtin_amdgcn_readfirstlane(nbulk > 0 ? (nbulk - 1) / 64 : -1);
@@ -785,27 +801,7 @@ __device__ __forceinline__ int divide_entry(int64_t* smem, const uint32_t* Sr, i
 #pragma unroll
   for (int i = 0; i < DNIR; i++)
 #pragma unroll
-    for (int s = 0; s < DQ; s++) {
-      const int k = lane + 64 * i + s + 1 - DQ;
-      const int32_t v = (int32_t)Dp[min(max(k, 0), nd - 1)];
-      DDL[i][s] = (i < NI && k >= 0 && k < nd) ? v : 0;
-    }
-  for (int i = lane; i <= nd; i += 64) {
-    const int64_t v = (int64_t)Dp[min(i, nd - 1)];
-    dd[i] = i < nd ? v : 0;
-  }
-  for (int s = lane - DOFF; s < nu + 3; s += 64) {
-    const int i = s - Sq;
-    const uint64_t a = (uint64_t)Sr[min(max(i, 0), ns - 1)];
-    const uint64_t b = (uint64_t)Sr[min(max(i - 1, 0), ns - 1)];
-    const uint64_t av = i >= 0 && i < ns ? a : 0, bv = i >= 1 && i - 1 < ns ? b : 0;
-    const int64_t x = (int64_t)(((av << Sb) | (Sb ? (bv >> (DB - Sb)) : 0)) & (RADIX - 1));
-    rem[s] = s >= Sq && s < nu ? x : 0;
-  }
-  const int jmax = __builtin_amdgcn_readfirstlane(nu - nd);
-  for (int j = lane; j <= jmax + 1; j += 64) qd[j] = 0;
-  const double ninvD = -R / D3;   // (negated) quotient estimates by one multiply
-  lds_sync<BLK>();
+    for (int s = 0; s < DQ; s++) DDL[i][s] = (int32_t)dd[lane + 64 * i + s + 1 - DQ];
   // register window: W[x] holds remainder position T + 1 - x
   int T = __builtin_amdgcn_readfirstlane(nu);
   int64_t W[DQ + 4];
@@ -1672,12 +1668,12 @@ hipError_t launch_update(const BatchView& B, int pc, int b, int j, int rd, hipSt
 static size_t fin_shm(int W, int FB = WB) {
   return sizeof(int32_t) * 2 * (size_t)(W + 48) + sizeof(int64_t) * 2 * (size_t)(W / FB + 8);
 }
-// LDS of divide_entry: remainder DOFF + nu + 3, divisor nd + 1, quotient
-// nu - nd + 2
+// LDS of divide_entry: remainder DOFF + nu + 3, divisor nd with 16 zeros
+// below and 64 DNIR + 16 above (DNIR <= 4), quotient nu - nd + 2
 static size_t divide_shm(int h, int num_cap, int den_cap) {
   const int Sq = (h + 28) / DB + 1;
   const int nu_max = Sq + num_cap + 1;
-  return sizeof(int64_t) * (size_t)((DOFF + nu_max + 3) + (den_cap + 3) + (nu_max + 3));
+  return sizeof(int64_t) * (size_t)((DOFF + nu_max + 3) + (16 + den_cap + 64 * 4 + 16) + (nu_max + 3));
 }
 hipError_t launch_fdiv(const BatchView& B, int c, int rd, hipStream_t s) {
   int64_t rows = 0;
