@@ -1035,12 +1035,20 @@ __device__ void near_product(const int32_t* Lr, int nL, const int32_t* Cp, int n
     for (int a0 = 0; a0 < nL8; a0 += 8) {
       // eight steps: their L digits and the C digits entering the ring are
       // read up front so the LDS reads overlap
+      // (C digits from clamped indices, pinned together by an empty asm
+      // statement and masked afterwards: no branch and wait per read)
       int32_t la[8], cn[8];
 #pragma unroll
       for (int u = 0; u < 8; u++) {
         la[u] = Lr[a0 + u];
+        cn[u] = Cp[min(max(s0 - (a0 + u) - 1, 0), nC - 1)];
+      }
+      asm volatile("" : "+v"(cn[0]), "+v"(cn[1]), "+v"(cn[2]), "+v"(cn[3]), "+v"(cn[4]), "+v"(cn[5]),
+                   "+v"(cn[6]), "+v"(cn[7]));
+#pragma unroll
+      for (int u = 0; u < 8; u++) {
         const int idx = s0 - (a0 + u) - 1;
-        cn[u] = idx >= 0 && idx < nC ? Cp[idx] : 0;
+        cn[u] = idx >= 0 && idx < nC ? cn[u] : 0;
       }
 #pragma unroll
       for (int u = 0; u < 8; u++) {
