@@ -46,6 +46,13 @@ __device__ __forceinline__ void gor(GLOBAL int32_t* f, int32_t v) {
   __hip_atomic_fetch_or(f, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// An empty asm statement that takes v in a register: loads issued before it
+// cannot be sunk by the compiler into a branch of their own (each followed by
+// a wait) when their value is masked afterwards; a batch of loads from
+// clamped indices, pinned, then masked, costs one LDS round trip.
+template <typename T>
+__device__ __forceinline__ void pin(T& v) { asm volatile("" : "+v"(v)); }
+
 // 64-bit lane moves: the value of lane i - 1 (lane 0: 0) by a DPP wave
 // shift, and the value of one (uniform) lane
 __device__ __forceinline__ int64_t lane_shr1(int64_t v) {
@@ -558,13 +565,30 @@ __device__ __forceinline__ FinOut wave_finalize_reg(int W, int h, CT Cr, ST Sr, 
   int64_t d[R];
   // 1. load, block normalisation to balanced digits, carries between blocks
   {
-    int64_t t = 0;
     const int s0 = R * lane;
-    if (own && s0 >= WB && s0 % WB == 0) t = cb[s0 / WB];
+    const int sl = own ? s0 : 0;
+    int64_t kv = cb[sl / WB];
+    int32_t gv[R];
+    int64_t pv[R];
+#pragma unroll
+    for (int m = 0; m < R; m++) gv[m] = dg[sl + m];
+    if (Psub) {
+#pragma unroll
+      for (int m = 0; m < R; m++) pv[m] = Psub[sl + m];
+    } else {
+#pragma unroll
+      for (int m = 0; m < R; m++) pv[m] = 0;
+    }
+    pin(kv);
 #pragma unroll
     for (int m = 0; m < R; m++) {
-      int64_t x = own ? (int64_t)dg[s0 + m] : 0;
-      if (Psub && own) x -= Psub[s0 + m];
+      pin(gv[m]);
+      pin(pv[m]);
+    }
+    int64_t t = own && s0 >= WB && s0 % WB == 0 ? kv : 0;
+#pragma unroll
+    for (int m = 0; m < R; m++) {
+      const int64_t x = own ? (int64_t)gv[m] - pv[m] : 0;
       t += x;
       d[m] = balanced29(t);
       t = (t - d[m]) >> DB;
@@ -604,17 +628,19 @@ __device__ __forceinline__ FinOut wave_finalize_reg(int W, int h, CT Cr, ST Sr, 
   const int nout = W - hq + 1;
   const int nbo = (nout + R - 1) / R;
   int64_t o[R];
+  uint32_t lv[R + 1];
+#pragma unroll
+  for (int m = 0; m <= R; m++) lv[m] = ls[min(hq + R * lane + m, W - 1)];
+#pragma unroll
+  for (int m = 0; m <= R; m++) pin(lv[m]);
 #pragma unroll
   for (int m = 0; m < R; m++) {
     const int i = R * lane + m;
-    uint32_t v = 0;
-    if (i < nout) {
-      const int s2 = hq + i;
-      const uint32_t lo = s2 < W ? ls[s2] : 0u;
-      const uint32_t hi = s2 + 1 < W ? ls[s2 + 1] : 0u;
-      v = (lo >> hb) | (hb ? ((hi << (DB - hb)) & (uint32_t)(RADIX - 1)) : 0u);
-    }
-    o[m] = v;
+    const int s2 = hq + i;
+    const uint32_t lo = s2 < W ? lv[m] : 0u;
+    const uint32_t hi = s2 + 1 < W ? lv[m + 1] : 0u;
+    const uint32_t v = (lo >> hb) | (hb ? ((hi << (DB - hb)) & (uint32_t)(RADIX - 1)) : 0u);
+    o[m] = i < nout ? v : 0u;
   }
   int st = 0;
 #pragma unroll
@@ -847,12 +873,11 @@ __device__ __forceinline__ int divide_entry(int64_t* smem, const uint32_t* Sr, i
     {
       int64_t xv[DNIR];
 #pragma unroll
-      for (int i = 0; i < DNIR; i++) {
-        const int rel = lane + 64 * i;
-        xv[i] = rel < nbulk ? rem[b + rel] : 0;
-      }
+      for (int i = 0; i < DNIR; i++) xv[i] = rem[b + min(lane + 64 * i, max(nbulk - 1, 0))];
 #pragma unroll
-      for (int i = 0; i < DNIR; i++) xv[i] = bulk_sum(xv[i], q, DDL[i]);
+      for (int i = 0; i < DNIR; i++) pin(xv[i]);
+#pragma unroll
+      for (int i = 0; i < DNIR; i++) xv[i] = bulk_sum(lane + 64 * i < nbulk ? xv[i] : 0, q, DDL[i]);
 #pragma unroll
       for (int i = 0; i < DNIR; i++) {
         const int rel = lane + 64 * i;
@@ -862,14 +887,16 @@ __device__ __forceinline__ int divide_entry(int64_t* smem, const uint32_t* Sr, i
       }
     }
     for (int i = DNIR; i < NI; i++) {
+      // (dd[nd] is zero, so the divisor digit index clamps to nd)
       int32_t ddv[DQ];
 #pragma unroll
-      for (int s = 0; s < DQ; s++) {
-        const int k = lane + 64 * i + s + 1 - DQ;
-        ddv[s] = k < nd ? (int32_t)dd[k] : 0;
-      }
+      for (int s = 0; s < DQ; s++) ddv[s] = (int32_t)dd[min(lane + 64 * i + s + 1 - DQ, nd)];
       const int rel = lane + 64 * i;
-      const int64_t x = bulk_sum(rel < nbulk ? rem[b + rel] : 0, q, ddv);
+      int64_t xr = rem[b + min(rel, max(nbulk - 1, 0))];
+      pin(xr);
+#pragma unroll
+      for (int s = 0; s < DQ; s++) pin(ddv[s]);
+      const int64_t x = bulk_sum(rel < nbulk ? xr : 0, q, ddv);
       const int64_t v = bulk_split(x, prev);
       if (rel < nbulk) rem[b + rel] = v;
       if (i == top_group) htop = prev;
@@ -937,14 +964,14 @@ __device__ __forceinline__ int divide_entry(int64_t* smem, const uint32_t* Sr, i
   int mytop = -1;
   const int sgn = (negN ^ negd) ? -1 : 1;
   for (int j = lane; j < cap; j += 64) {
+    // (qd[jmax + 1] is zero: the digits below nq are loaded unconditionally)
+    int64_t x = qd[min(j, nq - 1)], y = qd[max(min(j, nq) - 1, 0)];
+    pin(x);
+    pin(y);
     int64_t o = 0;
     if (j < nq) {
-      const int64_t x = j <= jmax ? qd[j] : 0;
       o = balanced29(x);
-      if (j >= 1 && j - 1 <= jmax) {
-        const int64_t y = qd[j - 1];
-        o += (y - balanced29(y)) >> DB;
-      }
+      if (j >= 1) o += (y - balanced29(y)) >> DB;
     }
     const int32_t od = (int32_t)(sgn * o);
     out[(int64_t)j * os] = od;
