@@ -36,6 +36,27 @@ __device__ __forceinline__ int wave_max(int v) {
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// wave_max for values that are -1 or increase with the lane among the lanes
+// where they are not: the value of the highest such lane (one ballot and one
+// lane read instead of six cross-lane shuffles)
+__device__ __forceinline__ int wave_max_mono(int v) {
+  const uint64_t m = __ballot(v >= 0);
+  return m == 0 ? -1 : __builtin_amdgcn_readlane(v, 63 - __clzll((long long)m));
+}
+
+// wave_max for v = -1 or lane + 64 k (a lane's last index of a loop over
+// j = lane, lane + 64, ...; k <= kmax): the highest k that any lane reached,
+// then the highest such lane, by ballots
+__device__ __forceinline__ int wave_max_strided(int v, int kmax) {
+  const int lane = threadIdx.x & 63;
+  const int k = v >= 0 ? (v - lane) >> 6 : -1;
+  for (int kk = kmax; kk >= 0; kk--) {
+    const uint64_t m = __ballot(k == kk);
+    if (m) return 64 * kk + 63 - __clzll((long long)m);
+  }
+  return -1;
+}
+
 // Device memory through global-address-space pointers: loads and stores
 // become global_* instructions, which the compiler never has to order against
 // LDS traffic (flat ones count against the LDS wait counter as well).
@@ -604,7 +625,7 @@ __device__ __forceinline__ FinOut wave_finalize_reg(int W, int h, CT Cr, ST Sr, 
       mytop = R * lane + m;
       mysign = d[m] < 0;
     }
-  const int top = wave_max(mytop);
+  const int top = wave_max_mono(mytop);
   const bool neg = top >= 0 && __builtin_amdgcn_readlane(mysign, top / R) != 0;
   // 3. magnitude as standard digits
   {
@@ -672,7 +693,7 @@ __device__ __forceinline__ FinOut wave_finalize_reg(int W, int h, CT Cr, ST Sr, 
     Sr[i] = 0;
     if (Sl) Sl[i] = 0;
   }
-  const int stop = wave_max(ts);
+  const int stop = wave_max_mono(ts);
   const uint32_t topv = stop >= 0 ? (uint32_t)__builtin_amdgcn_readlane((int32_t)tv, stop / R) : 0u;
   {
     int64_t t = 0;
@@ -696,14 +717,11 @@ __device__ __forceinline__ FinOut wave_finalize_reg(int W, int h, CT Cr, ST Sr, 
         gor(flags, 16);
       }
     }
-    for (int i = nbo * R + lane; i < cap; i += 64) {
-      const int32_t v = i == nbo * R ? (int32_t)(neg ? -extra : extra) : 0;
-      Cr[i] = v;
-      if (v != 0) tb = i;
-    }
+    for (int i = nbo * R + lane; i < cap; i += 64) Cr[i] = i == nbo * R ? (int32_t)(neg ? -extra : extra) : 0;
     if (extra != 0 && nbo * R >= cap && lane == 0) gor(flags, 16);
     FinOut f;
-    f.nbal = wave_max(tb) + 1;
+    // the extra digit, when it is there and fits, is the top one
+    f.nbal = extra != 0 && nbo * R < cap ? nbo * R + 1 : wave_max_mono(tb) + 1;
     f.nstd = stop + 1;
     f.neg = neg ? 1 : 0;
     f.bits = stop < 0 ? 0 : DB * stop + (32 - __clz(topv));
@@ -986,7 +1004,7 @@ __device__ __forceinline__ int divide_entry(int64_t* smem, const uint32_t* Sr, i
       if (o != 0) gor(flags, 8);
     }
   }
-  return wave_max(mytop) + 1;
+  return wave_max_strided(mytop, (cap - 1) >> 6) + 1;
 }
 
 // Digits per lane-serial block in the column finalisations (short serial
