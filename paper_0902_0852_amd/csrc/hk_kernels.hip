@@ -930,30 +930,45 @@ __device__ __forceinline__ int divide_entry(int64_t* smem, const uint32_t* Sr, i
 #pragma unroll
     for (int x = 4; x < DQ + 4; x++) W[x] = rem[T + 1 - x];
   }
-  // final remainder: window back to LDS (positions T - DQ - 2 .. T + 1,
-  // which cover nd - 2 .. nd + 1; those above nd are zero)
-  if (lane == 0) {
+  // final remainder: its top positions nd + 1 .. nd - 2 are the window
+  // entries j0 .. j0 + 3 (T = nd + j0 after the last pass), folded and
+  // carried in registers by every lane alike; the rounding decision follows
+  // from remainder / divisor in float64 unless that is within 1e-6 of a tie,
+  // when the whole remainder goes back to LDS for an exact comparison
+  int64_t r1 = 0, r0 = 0, rm1 = 0, rm2 = 0;
 #pragma unroll
-    for (int x = 0; x < DQ + 4; x++) rem[T + 1 - x] = W[x];
+  for (int x = 0; x < DQ + 4; x++) {
+    r1 = x == j0 ? W[x] : r1;
+    r0 = x == j0 + 1 ? W[x] : r0;
+    rm1 = x == j0 + 2 ? W[x] : rm1;
+    rm2 = x == j0 + 3 ? W[x] : rm2;
   }
-  lds_sync<BLK>();
-  if (lane == 0) {
-    rem[nd] += rem[nd + 1] << DB;
-    rem[nd + 1] = 0;
-    for (int s = nd - 2; s < nd; s++) {
-      if (s < 0) continue;
-      const int64_t cy = rem[s] >> DB;
-      rem[s] -= cy << DB;
-      rem[s + 1] += cy;
+  r0 += r1 << DB;
+  if (nd >= 2) {
+    const int64_t cy = rm2 >> DB;
+    rm2 -= cy << DB;
+    rm1 += cy;
+  }
+  {
+    const int64_t cy = rm1 >> DB;
+    rm1 -= cy << DB;
+    r0 += cy;
+  }
+  const double Tr = (double)r0 * R * R + (double)rm1 * R + (nd >= 2 ? (double)rm2 : 0.0);
+  const double f = Tr * R / D3;   // remainder / divisor
+  const double af = fabs(f);
+  int adj = af > 0.5 ? (f > 0 ? 1 : -1) : 0;
+  if (uni(fabs(2.0 * af - 1.0) <= 1e-6)) {
+    if (lane == 0) {
+#pragma unroll
+      for (int x = 0; x < DQ + 4; x++) rem[T + 1 - x] = W[x];
+      rem[nd + 1] = 0;
+      rem[nd] = r0;
+      rem[nd - 1] = rm1;
+      if (nd >= 2) rem[nd - 2] = rm2;
     }
-    const double T = (double)rem[nd] * R * R + (nd >= 1 ? (double)rem[nd - 1] * R : 0.0) +
-                     (nd >= 2 ? (double)rem[nd - 2] : 0.0);
-    const double f = T * R / D3;   // remainder / divisor
-    int adj = 0;
-    const double af = fabs(f);
-    if (fabs(2.0 * af - 1.0) > 1e-6) {
-      adj = af > 0.5 ? (f > 0 ? 1 : -1) : 0;
-    } else {
+    lds_sync<BLK>();
+    if (lane == 0) {
       // exact comparison of 2 rem with +d and -d
       int64_t v1 = 0, v2 = 0;
       int nz1 = 0, nz2 = 0;
@@ -969,23 +984,26 @@ __device__ __forceinline__ int divide_entry(int64_t* smem, const uint32_t* Sr, i
       const int s1 = v1 < 0 ? -1 : ((v1 == 0 && !nz1) ? 0 : 1);
       const int s2 = v2 < 0 ? -1 : ((v2 == 0 && !nz2) ? 0 : 1);
       const int odd = (int)(qd[0] & 1);
+      adj = 0;
       if (s1 > 0) adj = 1;
       else if (s1 == 0) adj = odd ? 1 : 0;
       else if (s2 < 0) adj = -1;
       else if (s2 == 0) adj = odd ? -1 : 0;
     }
-    qd[0] += adj;
+    adj = uni(adj);
   }
-  lds_sync<BLK>();
   // quotient digits -> balanced digits (one carry step suffices: |q| <= 2^30)
   const int nq = jmax + 2;
   int mytop = -1;
   const int sgn = (negN ^ negd) ? -1 : 1;
   for (int j = lane; j < cap; j += 64) {
-    // (qd[jmax + 1] is zero: the digits below nq are loaded unconditionally)
+    // (qd[jmax + 1] is zero: the digits below nq are loaded unconditionally;
+    // the rounding adjustment belongs to digit 0)
     int64_t x = qd[min(j, nq - 1)], y = qd[max(min(j, nq) - 1, 0)];
     pin(x);
     pin(y);
+    x += j == 0 ? adj : 0;
+    y += j == 1 ? adj : 0;
     int64_t o = 0;
     if (j < nq) {
       o = balanced29(x);
@@ -998,9 +1016,12 @@ __device__ __forceinline__ int divide_entry(int64_t* smem, const uint32_t* Sr, i
   }
   if (nq > cap && lane == 0) {
     for (int j = cap; j < nq; j++) {
-      const int64_t x = j <= jmax ? qd[j] : 0;
+      const int64_t x = (j <= jmax ? qd[j] : 0) + (j == 0 ? adj : 0);
       int64_t o = balanced29(x);
-      if (j - 1 <= jmax) { const int64_t y = qd[j - 1]; o += (y - balanced29(y)) >> DB; }
+      if (j - 1 <= jmax) {
+        const int64_t y = qd[j - 1] + (j == 1 ? adj : 0);
+        o += (y - balanced29(y)) >> DB;
+      }
       if (o != 0) gor(flags, 8);
     }
   }
