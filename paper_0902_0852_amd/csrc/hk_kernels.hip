@@ -770,6 +770,30 @@ __device__ __forceinline__ int64_t bulk_split(int64_t x, int64_t& prev) {
   return lo + (int64_t)(((uint64_t)(uint32_t)h1 << 32) | (uint32_t)h0);
 }
 
+// The bulk pass over the first G 64-position groups, whose divisor digits sit
+// in registers (DDL): all loads first, then the sums, then the splits in
+// order with the carries passing upward.
+template <int G>
+__device__ __forceinline__ void bulk_groups(int64_t* rem, int b, int nbulk, const int32_t* q,
+                                            int32_t (*DDL)[DQ], int top_group, int64_t& prev,
+                                            int64_t& htop) {
+  const int lane = threadIdx.x & 63;
+  int64_t xv[G];
+#pragma unroll
+  for (int i = 0; i < G; i++) xv[i] = rem[b + min(lane + 64 * i, max(nbulk - 1, 0))];
+#pragma unroll
+  for (int i = 0; i < G; i++) pin(xv[i]);
+#pragma unroll
+  for (int i = 0; i < G; i++) xv[i] = bulk_sum(lane + 64 * i < nbulk ? xv[i] : 0, q, DDL[i]);
+#pragma unroll
+  for (int i = 0; i < G; i++) {
+    const int rel = lane + 64 * i;
+    const int64_t v = bulk_split(xv[i], prev);
+    if (rel < nbulk) rem[b + rel] = v;
+    if (i == top_group) htop = prev;
+  }
+}
+
 // out = RNE(+-|num| 2^h / |d|) for one 64-lane workgroup: schoolbook long
 // division in radix 2^29 with a lazily normalised int64 remainder in LDS.
 // num: standard digits Sr[0..ns) of its magnitude, sign negN; divisor:
@@ -888,22 +912,8 @@ __device__ __forceinline__ int divide_entry(int64_t* smem, const uint32_t* Sr, i
     // them), then split in order, the carries passing upward.
     const int b = j0 - DQ + 1;
     int64_t prev = 0, htop = 0;
-    {
-      int64_t xv[DNIR];
-#pragma unroll
-      for (int i = 0; i < DNIR; i++) xv[i] = rem[b + min(lane + 64 * i, max(nbulk - 1, 0))];
-#pragma unroll
-      for (int i = 0; i < DNIR; i++) pin(xv[i]);
-#pragma unroll
-      for (int i = 0; i < DNIR; i++) xv[i] = bulk_sum(lane + 64 * i < nbulk ? xv[i] : 0, q, DDL[i]);
-#pragma unroll
-      for (int i = 0; i < DNIR; i++) {
-        const int rel = lane + 64 * i;
-        const int64_t v = bulk_split(xv[i], prev);
-        if (rel < nbulk) rem[b + rel] = v;
-        if (i == top_group) htop = prev;
-      }
-    }
+    if (NI <= 1) bulk_groups<1>(rem, b, nbulk, q, DDL, top_group, prev, htop);
+    else bulk_groups<DNIR>(rem, b, nbulk, q, DDL, top_group, prev, htop);
     for (int i = DNIR; i < NI; i++) {
       // (dd[nd] is zero, so the divisor digit index clamps to nd)
       int32_t ddv[DQ];
@@ -996,23 +1006,24 @@ __device__ __forceinline__ int divide_entry(int64_t* smem, const uint32_t* Sr, i
   const int nq = jmax + 2;
   int mytop = -1;
   const int sgn = (negN ^ negd) ? -1 : 1;
-  for (int j = lane; j < cap; j += 64) {
-    // (qd[jmax + 1] is zero: the digits below nq are loaded unconditionally;
-    // the rounding adjustment belongs to digit 0)
-    int64_t x = qd[min(j, nq - 1)], y = qd[max(min(j, nq) - 1, 0)];
+  const int nqc = min(nq, cap);
+  for (int j = lane; j < nqc; j += 64) {
+    // (the rounding adjustment belongs to digit 0)
+    int64_t x = qd[j], y = qd[max(j - 1, 0)];
     pin(x);
     pin(y);
     x += j == 0 ? adj : 0;
     y += j == 1 ? adj : 0;
-    int64_t o = 0;
-    if (j < nq) {
-      o = balanced29(x);
-      if (j >= 1) o += (y - balanced29(y)) >> DB;
-    }
+    int64_t o = balanced29(x);
+    if (j >= 1) o += (y - balanced29(y)) >> DB;
     const int32_t od = (int32_t)(sgn * o);
     out[(int64_t)j * os] = od;
     if (out2) out2[(int64_t)j * os2] = od;
     if (od != 0) mytop = j;
+  }
+  for (int j = nqc + lane; j < cap; j += 64) {
+    out[(int64_t)j * os] = 0;
+    if (out2) out2[(int64_t)j * os2] = 0;
   }
   if (nq > cap && lane == 0) {
     for (int j = cap; j < nq; j++) {
