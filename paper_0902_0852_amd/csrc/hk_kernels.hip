@@ -908,8 +908,9 @@ __device__ __forceinline__ int divide_entry(int64_t* smem, const uint32_t* Sr, i
       if (lane < Qe) qd[j0 - lane] = v;
     }
     // every position below the window: subtract the DQ multiples at once.
-    // The register groups load and sum independently (no branch between
-    // them), then split in order, the carries passing upward.
+    // The register groups (only the first when the divisor needs no more)
+    // load and sum independently, then split in order, the carries passing
+    // upward; groups beyond them take their divisor digits from LDS.
     const int b = j0 - DQ + 1;
     int64_t prev = 0, htop = 0;
     if (NI <= 1) bulk_groups<1>(rem, b, nbulk, q, DDL, top_group, prev, htop);
