@@ -132,81 +132,6 @@ void mul_in(std::vector<uint32_t>& x, uint64_t m) {
   }
   while (carry) { x.push_back((uint32_t)carry); carry >>= 32; }
 }
-// x = floor(floor(x / 2^sh) / d), d below 2^32, in one pass from the top
-// (the quotient digits by the reciprocal of div32)
-// (quotient digits go to the scratch vector q, which then swaps with x)
-void shr_div_in(std::vector<uint32_t>& x, int64_t sh, uint32_t d, std::vector<uint32_t>& q) {
-  const size_t ws = (size_t)(sh >> 5);
-  const int bs = (int)(sh & 31);
-  if (ws >= x.size()) { x.clear(); return; }
-  const size_t n = x.size() - ws;
-  q.resize(n);
-  const uint64_t inv = ~0ULL / d;
-  uint64_t rem = 0;
-  for (size_t i = n; i-- > 0;) {
-    uint64_t w = x[i + ws];
-    if (bs) w = (w >> bs) | (i + ws + 1 < x.size() ? (uint64_t)x[i + ws + 1] << (32 - bs) : 0);
-    const uint64_t cur = (rem << 32) | (uint32_t)w;
-    uint64_t qd = (uint64_t)(((unsigned __int128)cur * inv) >> 64);
-    uint64_t rr = cur - qd * d;
-    while (rr >= d) { rr -= d; qd++; }
-    q[i] = (uint32_t)qd;
-    rem = rr;
-  }
-  x.swap(q);
-  while (!x.empty() && x.back() == 0) x.pop_back();
-}
-// acc += floor(x 2^s) (exact for s >= 0), the shifted words formed on the fly
-void add_scaled(std::vector<uint32_t>& acc, const std::vector<uint32_t>& x, int64_t s) {
-  if (x.empty()) return;
-  if (s >= 0) {
-    const size_t ws = (size_t)(s >> 5);
-    const int bs = (int)(s & 31);
-    const size_t need = ws + x.size() + 1;
-    if (acc.size() < need) acc.resize(need, 0u);
-    uint64_t c = 0;
-    uint32_t prev = 0;
-    size_t i = 0;
-    for (; i <= x.size(); i++) {
-      const uint32_t cur = i < x.size() ? x[i] : 0u;
-      const uint32_t w = bs ? (cur << bs) | (prev >> (32 - bs)) : cur;
-      prev = cur;
-      const uint64_t v = (uint64_t)acc[ws + i] + w + c;
-      acc[ws + i] = (uint32_t)v;
-      c = v >> 32;
-    }
-    for (size_t j = ws + i; c; j++) {
-      if (j == acc.size()) acc.push_back(0u);
-      const uint64_t v = (uint64_t)acc[j] + c;
-      acc[j] = (uint32_t)v;
-      c = v >> 32;
-    }
-  } else {
-    const int64_t sh = -s;
-    const size_t ws = (size_t)(sh >> 5);
-    const int bs = (int)(sh & 31);
-    if (ws >= x.size()) return;
-    const size_t n = x.size() - ws;
-    if (acc.size() < n + 1) acc.resize(n + 1, 0u);
-    uint64_t c = 0;
-    size_t i = 0;
-    for (; i < n; i++) {
-      uint64_t w = x[i + ws];
-      if (bs) w = (w >> bs) | (i + ws + 1 < x.size() ? (uint64_t)x[i + ws + 1] << (32 - bs) : 0);
-      const uint64_t v = (uint64_t)acc[i] + (uint32_t)w + c;
-      acc[i] = (uint32_t)v;
-      c = v >> 32;
-    }
-    for (size_t j = i; c; j++) {
-      if (j == acc.size()) acc.push_back(0u);
-      const uint64_t v = (uint64_t)acc[j] + c;
-      acc[j] = (uint32_t)v;
-      c = v >> 32;
-    }
-  }
-  while (!acc.empty() && acc.back() == 0) acc.pop_back();
-}
-
 // log2 of sum_k tau_k by the terms' logarithms (double precision): places
 // the sum's unit
 double log2_series(double log2_tau0, double lrho_num, double den0, double dstep) {
@@ -220,6 +145,94 @@ double log2_series(double log2_tau0, double lrho_num, double den0, double dstep)
   return top + std::log2(sum);
 }
 
+// The series sum as lazy base-2^32 words in uint64 (one carry pass at the
+// end): every term adds at most two 32-bit pieces per word, so 2^31 terms fit.
+struct LazyAcc {
+  std::vector<uint64_t> w;
+  void put(int64_t j, uint64_t v) {
+    if (j >= (int64_t)w.size()) w.resize((size_t)j + 64, 0);
+    w[(size_t)j] += v;
+  }
+  // += floor(x 2^s)
+  void add(const std::vector<uint32_t>& x, int64_t s) {
+    if (s >= 0) {
+      const int64_t ws = s >> 5;
+      const int bs = (int)(s & 31);
+      for (size_t i = 0; i < x.size(); i++) {
+        const uint64_t v = (uint64_t)x[i] << bs;
+        put(ws + (int64_t)i, v & 0xffffffffu);
+        if (v >> 32) put(ws + (int64_t)i + 1, v >> 32);
+      }
+    } else {
+      const int64_t sh = -s, ws = sh >> 5;
+      const int bs = (int)(sh & 31);
+      for (int64_t j = 0; j + ws < (int64_t)x.size(); j++) {
+        uint64_t v = x[(size_t)(j + ws)];
+        if (bs) v = (v >> bs) | ((size_t)(j + ws + 1) < x.size() ? ((uint64_t)x[(size_t)(j + ws + 1)] << (32 - bs)) : 0);
+        put(j, v & 0xffffffffu);
+      }
+    }
+  }
+  std::vector<uint32_t> words() const {
+    std::vector<uint32_t> out;
+    uint64_t c = 0;
+    for (uint64_t v : w) {
+      const unsigned __int128 t = (unsigned __int128)v + c;
+      out.push_back((uint32_t)t);
+      c = (uint64_t)(t >> 32);
+    }
+    while (c) { out.push_back((uint32_t)c); c >>= 32; }
+    while (!out.empty() && out.back() == 0) out.pop_back();
+    return out;
+  }
+};
+
+// x = floor(floor(x / 2^sh) / d), d below 2^32, in one pass from the top
+// (the quotient digits by the reciprocal of div32; q is scratch that then
+// swaps with x), each quotient digit also added to acc at the term's scale
+// 2^s (floor below the accumulator's unit)
+void shr_div_acc(std::vector<uint32_t>& x, int64_t sh, uint32_t d, std::vector<uint32_t>& q, LazyAcc& acc,
+                 int64_t s) {
+  const size_t ws = (size_t)(sh >> 5);
+  const int bs = (int)(sh & 31);
+  if (ws >= x.size()) { x.clear(); return; }
+  const size_t n = x.size() - ws;
+  q.resize(n);
+  const uint64_t inv = ~0ULL / d;
+  uint64_t rem = 0;
+  // placement of quotient digit i in acc: s >= 0 splits it over words
+  // i + as and i + as + 1; s < 0 forms word i - as from digits i and i + 1
+  const int64_t as = s >= 0 ? (s >> 5) : ((-s) >> 5);
+  const int abs_ = (int)(s >= 0 ? (s & 31) : ((-s) & 31));
+  if (s >= 0) {
+    const size_t need = (size_t)as + n + 2;
+    if (acc.w.size() < need) acc.w.resize(need + 64, 0);
+  }
+  uint32_t above = 0;                        // quotient digit i + 1
+  for (size_t i = n; i-- > 0;) {
+    uint64_t w = x[i + ws];
+    if (bs) w = (w >> bs) | (i + ws + 1 < x.size() ? (uint64_t)x[i + ws + 1] << (32 - bs) : 0);
+    const uint64_t cur = (rem << 32) | (uint32_t)w;
+    uint64_t qd = (uint64_t)(((unsigned __int128)cur * inv) >> 64);
+    uint64_t rr = cur - qd * d;
+    while (rr >= d) { rr -= d; qd++; }
+    q[i] = (uint32_t)qd;
+    rem = rr;
+    if (s >= 0) {
+      const uint64_t v = qd << abs_;
+      acc.w[i + (size_t)as] += v & 0xffffffffu;
+      acc.w[i + (size_t)as + 1] += v >> 32;
+    } else if ((int64_t)i >= as) {
+      uint64_t v = qd;
+      if (abs_) v = (v >> abs_) | ((uint64_t)above << (32 - abs_));
+      acc.put((int64_t)i - as, v & 0xffffffffu);
+    }
+    above = (uint32_t)qd;
+  }
+  x.swap(q);
+  while (!x.empty() && x.back() == 0) x.pop_back();
+}
+
 FSeries float_series(const SeriesPlan& sp, const std::vector<uint64_t>& mm, std::vector<uint32_t> x,
                      double d0, uint64_t den0, uint64_t dstep) {
   const int64_t P = sp.W;
@@ -231,10 +244,11 @@ FSeries float_series(const SeriesPlan& sp, const std::vector<uint64_t>& mm, std:
   out.U = (int64_t)std::floor(l2) - P - 32;
   const int64_t elo = out.U - 16;
   const double up = 1.0 + 1e-12;
-  std::vector<uint32_t> acc, qs;
+  LazyAcc acc;
+  std::vector<uint32_t> qs;
   int64_t e = 0;
   double d = d0, err = 0.0;
-  add_scaled(acc, x, e - out.U);
+  acc.add(x, e - out.U);
   err += d * std::ldexp(1.0, (int)std::max<int64_t>(-2000, e - out.U)) + 1.0;
   out.n = 1;
   for (uint64_t k = 1;; k++) {
@@ -245,16 +259,16 @@ FSeries float_series(const SeriesPlan& sp, const std::vector<uint64_t>& mm, std:
     if (rho < 1.0 && en < elo) en = elo;
     if (en < e - sp.ap) en = e - sp.ap;
     if (den <= 0xffffffffULL) {
-      shr_div_in(x, en - (e - sp.ap), (uint32_t)den, qs);
+      shr_div_acc(x, en - (e - sp.ap), (uint32_t)den, qs, acc, en - out.U);
     } else {
       mul64_shr(x, 1, en - (e - sp.ap));
       MP q, rr;
       divmod_mag(from_words(x), MP::from_u64(den), q, rr);
       x = q.d;
+      acc.add(x, en - out.U);
     }
     d = d * rho * std::ldexp(1.0, (int)std::max<int64_t>(-2000, e - en)) * up + 2.0;
     e = en;
-    add_scaled(acc, x, e - out.U);
     const double unit = std::ldexp(1.0, (int)std::max<int64_t>(-2000, std::min<int64_t>(2000, e - out.U)));
     err += d * unit * up + (e < out.U ? 1.0 : 0.0);
     out.n++;
@@ -263,7 +277,7 @@ FSeries float_series(const SeriesPlan& sp, const std::vector<uint64_t>& mm, std:
       break;
     }
   }
-  out.acc = from_words(acc);
+  out.acc = from_words(acc.words());
   out.err = err * (1.0 + 1e-9) + 4.0;
   return out;
 }
