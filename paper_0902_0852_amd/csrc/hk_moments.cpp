@@ -122,12 +122,20 @@ struct FSeries { MP acc; int64_t U = 0; double err = 0; uint64_t n = 0; };
 int64_t bitlen_w(const std::vector<uint32_t>& x) {
   return x.empty() ? 0 : 32 * (int64_t)(x.size() - 1) + (32 - __builtin_clz(x.back()));
 }
-// x = x m (m below 2^64)
+// x = x m (m below 2^64), two words (one 64-bit limb) per multiply
 void mul_in(std::vector<uint32_t>& x, uint64_t m) {
   uint64_t carry = 0;
-  for (size_t i = 0; i < x.size(); i++) {
-    const unsigned __int128 v = (unsigned __int128)x[i] * m + carry;
-    x[i] = (uint32_t)v;
+  const size_t n2 = x.size() / 2;
+  for (size_t i = 0; i < n2; i++) {
+    const uint64_t limb = (uint64_t)x[2 * i] | ((uint64_t)x[2 * i + 1] << 32);
+    const unsigned __int128 v = (unsigned __int128)limb * m + carry;
+    x[2 * i] = (uint32_t)v;
+    x[2 * i + 1] = (uint32_t)((uint64_t)v >> 32);
+    carry = (uint64_t)(v >> 64);
+  }
+  if (x.size() & 1) {
+    const unsigned __int128 v = (unsigned __int128)x.back() * m + carry;
+    x.back() = (uint32_t)v;
     carry = (uint64_t)(v >> 32);
   }
   while (carry) { x.push_back((uint32_t)carry); carry >>= 32; }
