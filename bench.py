@@ -12,10 +12,10 @@ of ceil(bits(C)/32) * ceil(bits(L)/32), divided by the wall time of the timed
 steps).  Also printed: lambda_1 solves/s, a roofline record for the kernel
 that carries the update work (k_update, or k_column in look-ahead mode 2,
 where each column's launch holds its update as well as the finalisation and
-division of the column; achieved limb MACs/s from HIP events around every
-such launch on the library's stream, against one 32-bit multiply per lane
-per clock on 256 CUs at 2.4 GHz), and the CPU oracle timed on the host
-cores.
+division of the column; achieved limb MACs/s from the start and end HIP
+events that every such launch records on the library's stream, against one
+32-bit multiply per lane per clock on 256 CUs at 2.4 GHz), and the CPU
+oracle timed on the host cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2]
 """
@@ -238,9 +238,9 @@ def main():
     dt = time.time() - t0
     ms_step = 1e3 * dt / args.steps
     value = macs_per_step * args.steps / dt
-    # the update kernel's own time: one more step with every update launch
-    # bracketed by HIP events on the library's stream (stream launches instead
-    # of the graph replay, the kernels are the same)
+    # the update kernel's own time: one more step in which every update
+    # launch records its start and end on HIP events of the library's stream
+    # (stream launches instead of the graph replay, the kernels are the same)
     _, r = hk.smallest_eig(N, beta, K, method=method, digits=45, ws=ws,
                            flags=hk.HK_FLAG_NO_WORK_COUNT | hk.HK_FLAG_TIME_UPDATES | pflag)
     torch.cuda.synchronize()

@@ -216,7 +216,8 @@ void mp_to_digits(const MP& v, int32_t* out, int n) { to_digits(v, out, n); }
 // The whole factorisation of every instance of B (shifts and flags already in
 // place): expansion, then per panel of b columns the in-panel updates,
 // finalisations and divisions column by column, then the trailing update.
-// With evs != NULL every update launch is bracketed by HIP events.
+// With evs != NULL every update launch records its own start and end on a
+// pair of HIP events.
 hipError_t enqueue_factor(const BatchView& B, int b, int mode, hipStream_t s, hipStream_t s2,
                           std::vector<std::pair<hipEvent_t, hipEvent_t>>* evs,
                           std::vector<hipEvent_t>* pool, size_t* evi, int* n_update) {
@@ -233,10 +234,8 @@ hipError_t enqueue_factor(const BatchView& B, int b, int mode, hipStream_t s, hi
   auto timed_update = [&](int pc, int j, int rd, hipStream_t st) -> hipError_t {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (evs) { e0 = get_ev(); e1 = get_ev(); }
-    hipError_t e = hipSuccess;
-    if (e0 && e1) e = hipEventRecord(e0, st);
-    if (e == hipSuccess) e = launch_update(B, pc, b, j, rd, st);
-    if (e == hipSuccess && e0 && e1) { e = hipEventRecord(e1, st); evs->push_back({e0, e1}); }
+    hipError_t e = launch_update(B, pc, b, j, rd, st, e0 && e1 ? e0 : nullptr, e0 && e1 ? e1 : nullptr);
+    if (e == hipSuccess && e0 && e1) evs->push_back({e0, e1});
     if (n_update) (*n_update)++;
     return e;
   };
@@ -246,9 +245,8 @@ hipError_t enqueue_factor(const BatchView& B, int b, int mode, hipStream_t s, hi
     for (int c = 0; c < B.maxN && e == hipSuccess; c++) {
       hipEvent_t e0 = nullptr, e1 = nullptr;
       if (evs) { e0 = get_ev(); e1 = get_ev(); }
-      if (e0 && e1) e = hipEventRecord(e0, s);
-      if (e == hipSuccess) e = launch_column(B, c, s);
-      if (e == hipSuccess && e0 && e1) { e = hipEventRecord(e1, s); evs->push_back({e0, e1}); }
+      if (e == hipSuccess) e = launch_column(B, c, s, e0 && e1 ? e0 : nullptr, e0 && e1 ? e1 : nullptr);
+      if (e == hipSuccess && e0 && e1) evs->push_back({e0, e1});
       if (n_update) (*n_update)++;
     }
     return e;

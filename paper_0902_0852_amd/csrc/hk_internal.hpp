@@ -128,9 +128,11 @@ hipError_t launch_expand(const BatchView& B, hipStream_t s);
 // UPD_NEAR / UPD_FAR: the trailing update split into the next panel's columns
 // [pc + b, pc + 2b) and the rest (look-ahead)
 constexpr int UPD_NEAR = -1, UPD_FAR = -2;
-hipError_t launch_update(const BatchView& B, int pc, int b, int j, int rd, hipStream_t s);
+hipError_t launch_update(const BatchView& B, int pc, int b, int j, int rd, hipStream_t s,
+                         hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 hipError_t launch_fdiv(const BatchView& B, int c, int rd, hipStream_t s);
-hipError_t launch_column(const BatchView& B, int c, hipStream_t s);
+hipError_t launch_column(const BatchView& B, int c, hipStream_t s, hipEvent_t t0 = nullptr,
+                         hipEvent_t t1 = nullptr);
 hipError_t launch_gather_pivots_b(const BatchView& B, int32_t* out, int ld, hipStream_t s);
 int64_t update_items(const Plan& P, int pc, int b, int j);
 // One factorisation of every instance of B, enqueued on s.  With a second

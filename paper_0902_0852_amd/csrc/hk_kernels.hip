@@ -16,6 +16,7 @@
 // through a double-buffered int64 carry plane (read buffer rd, write rd^1),
 // so no atomics and no cross-item ordering are needed.
 #include <climits>
+#include <hip/hip_ext.h>
 #include <cstring>
 
 #include "hk_internal.hpp"
@@ -1742,12 +1743,27 @@ int64_t update_items(const Plan& P, int pc, int b, int j) {
   if (!update_range(P.N, pc, b, j, k0, k1, c_lo, c_hi)) return 0;
   return (int64_t)P.itemStart[c_hi] - P.itemStart[c_lo];
 }
-hipError_t launch_update(const BatchView& B, int pc, int b, int j, int rd, hipStream_t s) {
+// With t0 and t1 (timing-capable events, both or neither) the launch's own
+// start and end are recorded on them (the dispatch packet's timestamps, as a
+// profiler sees the kernel), or, when nothing is launched, the current point
+// on both.
+static hipError_t mark_empty(hipEvent_t t0, hipEvent_t t1, hipStream_t s) {
+  hipError_t e = hipSuccess;
+  if (t0) e = hipEventRecord(t0, s);
+  if (e == hipSuccess && t1) e = hipEventRecord(t1, s);
+  return e;
+}
+hipError_t launch_update(const BatchView& B, int pc, int b, int j, int rd, hipStream_t s, hipEvent_t t0,
+                         hipEvent_t t1) {
   int64_t items = 0;
   for (const Plan* p : B.plans) items += update_items(*p, pc, b, j);
-  if (items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_update, dim3((unsigned)((items + 3) / 4)), dim3(256), 0, s, B.ddesc,
-                     (int)B.plans.size(), pc, b, j, rd);
+  if (items <= 0) return mark_empty(t0, t1, s);
+  if (t0 || t1)
+    hipExtLaunchKernelGGL(k_update, dim3((unsigned)((items + 3) / 4)), dim3(256), 0, s, t0, t1, 0, B.ddesc,
+                          (int)B.plans.size(), pc, b, j, rd);
+  else
+    hipLaunchKernelGGL(k_update, dim3((unsigned)((items + 3) / 4)), dim3(256), 0, s, B.ddesc,
+                       (int)B.plans.size(), pc, b, j, rd);
   return hipGetLastError();
 }
 // LDS of wave_finalize for W digits in blocks of FB
@@ -1778,7 +1794,7 @@ hipError_t launch_fdiv(const BatchView& B, int c, int rd, hipStream_t s) {
                      (int)B.plans.size(), c, rd, (int)rows, (int)fin, (int)piv);
   return hipGetLastError();
 }
-hipError_t launch_column(const BatchView& B, int c, hipStream_t s) {
+hipError_t launch_column(const BatchView& B, int c, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
   int64_t rows = 0, items = 0;
   size_t fin = 0, piv = 0, div = 0;
   for (const Plan* p : B.plans) {
@@ -1793,10 +1809,14 @@ hipError_t launch_column(const BatchView& B, int c, hipStream_t s) {
     if (c > 0) items += update_items(*p, c - 1, 1, UPD_FAR);
   }
   fin = (fin + 7) / 8 * 8;
-  if (rows <= 0 && items <= 0) return hipSuccess;
+  if (rows <= 0 && items <= 0) return mark_empty(t0, t1, s);
   const int64_t blocks = rows + (items + 1) / 2;
-  hipLaunchKernelGGL(k_column, dim3((unsigned)blocks), dim3(128), piv + std::max(2 * fin, div), s, B.ddesc,
-                     (int)B.plans.size(), c, (int)rows, (int)fin, (int)piv);
+  if (t0 || t1)
+    hipExtLaunchKernelGGL(k_column, dim3((unsigned)blocks), dim3(128), piv + std::max(2 * fin, div), s, t0, t1,
+                          0, B.ddesc, (int)B.plans.size(), c, (int)rows, (int)fin, (int)piv);
+  else
+    hipLaunchKernelGGL(k_column, dim3((unsigned)blocks), dim3(128), piv + std::max(2 * fin, div), s, B.ddesc,
+                       (int)B.plans.size(), c, (int)rows, (int)fin, (int)piv);
   return hipGetLastError();
 }
 hipError_t launch_gather_pivots_b(const BatchView& B, int32_t* out, int ld, hipStream_t s) {
