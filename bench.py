@@ -190,8 +190,8 @@ def main():
                          "(-1: chosen by size)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: the method has no multi-GPU path in this "
-              "build (one instance per GPU shards trivially; see DESIGN.md).", file=sys.stderr)
+        print("bench.py measures one GPU only: the method has no multi-GPU path "
+              "(independent instances would shard one per GPU).", file=sys.stderr)
         sys.exit(2)
     if args.mode == "learned":
         learned_gain(args)
