@@ -72,6 +72,33 @@ def pivot_ratio_fixed(d_new, d_old, F):
     return R
 
 
+class _Evaluator:
+    """P(x) through the pivots of the fixed-point LDL^T of M - xI; counts the
+    factorisations."""
+
+    def __init__(self, N, K, X, threads):
+        self.N, self.K, self.X, self.threads = N, K, X, threads
+        self.count = 0
+
+    def __call__(self, x):
+        f = factor_from_moments(self.X, self.N, self.K, x, threads=self.threads)
+        self.count += 1
+        if f.status != 0:
+            return None, f
+        return f.pivots(), f
+
+
+def _secant_point(xa, xb, R, ONE):
+    """xb - (xb - xa) r / (r - 1) with r = R / ONE, rounded RNE to the grid of
+    xa and xb (K fractional bits)."""
+    return rne_div(xb * (R - ONE) - (xb - xa) * R, R - ONE)
+
+
+def _ratio_bits(N, K):
+    """Fractional bits F of the pivot-product ratios."""
+    return K // 2 + 64 + N.bit_length()
+
+
 def secant(N, beta, K, tol_digits=45, max_iter=200, X=None, threads=0, trace=None):
     """Smallest eigenvalue by the Secant iteration; returns (Fraction, info).
 
@@ -82,24 +109,11 @@ def secant(N, beta, K, tol_digits=45, max_iter=200, X=None, threads=0, trace=Non
     variant of regula falsi) until the bracket is below the tolerance; the
     returned value is the bracket's lower end (a point with P > 0)."""
     X = moments(N, beta, K) if X is None else X
-    h = K // 2
-    F = h + 64 + N.bit_length()
+    F = _ratio_bits(N, K)
     ONE = 1 << F
     q = -(-K // 4)
     tol = Fraction(1, 10 ** tol_digits)
-    nfact = 0
-
-    def evaluate(x):
-        nonlocal nfact
-        f = factor_from_moments(X, N, K, x, threads=threads)
-        nfact += 1
-        if f.status != 0:
-            return None, f
-        return f.pivots(), f
-
-    def secant_point(xa, xb, R):
-        # xb - (xb - xa) * r / (r - 1), r = R / 2^F, rounded to K bits
-        return rne_div(xb * (R - ONE) - (xb - xa) * R, R - ONE)
+    evaluate = _Evaluator(N, K, X, threads)
 
     xs = [-(1 << (K - q)), 0]
     piv = []
@@ -114,7 +128,7 @@ def secant(N, beta, K, tol_digits=45, max_iter=200, X=None, threads=0, trace=Non
         R = pivot_ratio_fixed(piv[-1], piv[-2], F)
         if R >= ONE:
             raise PrecisionError("ratio >= 1: precision exhausted")
-        x2 = secant_point(x0, x1, R)
+        x2 = _secant_point(x0, x1, R, ONE)
         step = x2 - x1
         if trace is not None:
             trace.append(("secant", x2, R))
@@ -124,41 +138,60 @@ def secant(N, beta, K, tol_digits=45, max_iter=200, X=None, threads=0, trace=Non
             raise PrecisionError("step did not shrink")
         prev_step = step
         if Fraction(step) <= tol * x2:
-            return Fraction(x2, 1 << K), {"factorizations": nfact, "iterations": it + 1}
+            return Fraction(x2, 1 << K), {"factorizations": evaluate.count, "iterations": it + 1}
         d, f = evaluate(x2)
         if d is not None and f.first_nonpos < 0:
             xs.append(x2)
             piv.append(d)
             continue
         # crossed the computed root: bracket [x1, x2]
-        return _bracket(evaluate, secant_point, x1, piv[-1], x2, d, F, K, tol, nfact,
-                        max_iter - it, trace)
+        return _bracket(evaluate, x1, piv[-1], x2, d, F, K, tol, max_iter - it, trace)
     raise PrecisionError("no convergence")
 
 
-def _bracket(evaluate, secant_point, a, da, b, db, F, K, tol, nfact, budget, trace):
+def bracket_root(N, beta, K, a, b, tol_digits=45, max_iter=200, X=None, threads=0, trace=None):
+    """The bracketing phase of the root finder on its own, from a bracket
+    [a, b] of fixed-point shifts (K fractional bits) with P(a) > 0 >= P(b):
+    Illinois regula falsi until b - a <= 10^-tol_digits a; returns
+    (Fraction(a, 2^K), info) like secant()."""
+    X = moments(N, beta, K) if X is None else X
+    evaluate = _Evaluator(N, K, X, threads)
+    da, fa = evaluate(a)
+    if da is None or fa.first_nonpos >= 0:
+        raise NotSPDError("lower end not left of lambda_1")
+    db, fb = evaluate(b)
+    if db is not None and fb.first_nonpos < 0:
+        raise ValueError("upper end not right of lambda_1")
+    return _bracket(evaluate, a, da, b, db, _ratio_bits(N, K), K, Fraction(1, 10 ** tol_digits),
+                    max_iter, trace)
+
+
+def _bracket(evaluate, a, da, b, db, F, K, tol, budget, trace):
     """Illinois regula falsi on [a, b] with P(a) > 0 >= P(b); P known only
     through pivot lists (db may be None when a zero pivot stopped the
-    factorisation, then the midpoint is used)."""
+    factorisation, then the midpoint is used).  When the same end survives
+    two steps in a row, the function value kept for the other end is halved
+    (once more for every further step on that side), which restores
+    superlinear convergence where plain regula falsi would keep one end
+    fixed."""
     ONE = 1 << F
     scale_a = scale_b = 0       # Illinois halvings applied to P(a), P(b)
     side = 0
     for it in range(budget):
         if Fraction(b - a) <= tol * a:
-            return Fraction(a, 1 << K), {"factorizations": nfact, "iterations": it,
+            return Fraction(a, 1 << K), {"factorizations": evaluate.count, "iterations": it,
                                          "bracketed": True}
         c = None
         if db is not None:
             R = pivot_ratio_fixed(db, da, F)            # P(b)/P(a) <= 0
             R = (R >> scale_b) << scale_a if scale_b <= scale_a else R >> (scale_b - scale_a)
             if R != ONE:
-                c = secant_point(a, b, R)
+                c = _secant_point(a, b, R, ONE)
         if c is None or c <= a or c >= b:
             c = (a + b) // 2
         if trace is not None:
-            trace.append(("bracket", c, a, b))
+            trace.append(("bracket", c, a, b, scale_a, scale_b))
         dc, f = evaluate(c)
-        nfact += 1        # counted locally: the caller's count stops at the bracket
         if dc is not None and f.first_nonpos < 0:
             a, da = c, dc
             scale_a = 0

@@ -127,12 +127,14 @@ def log2_mu_estimate(n, p, q):
     return (math.lgamma(x) + math.log(q / p)) / math.log(2.0)
 
 
-def moments(N, beta, K):
-    """X_n = RNE(2^K mu_n), n = 0..2N-2, mu_n = (1/beta) Gamma((n+1)/beta)."""
+def moments(N, beta, K, guard=64):
+    """X_n = RNE(2^K mu_n), n = 0..2N-2, mu_n = (1/beta) Gamma((n+1)/beta).
+    Gamma is enclosed with `guard` bits beyond the ones the result needs; the
+    guard doubles until every rounding is decided (the result does not depend
+    on the starting guard)."""
     p, q = reduce_beta(beta)
     nmax = 2 * N - 2
     top = max(log2_mu_estimate(n, p, q) for n in range(0, nmax + 1))
-    guard = 64
     while True:
         F = K + max(0, int(math.ceil(top))) + guard
         out = []

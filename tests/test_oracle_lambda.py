@@ -10,8 +10,8 @@ import mpmath
 import pytest
 
 import oracle
-from oracle.drivers import (PrecisionError, inverse_iteration, rel_digits, secant,
-                            solve_guard_bits, verify)
+from oracle.drivers import (PrecisionError, bracket_root, inverse_iteration, rel_digits, secant,
+                            solve_guard_bits, to_fixed, verify)
 from oracle.moments import moments
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
@@ -46,40 +46,71 @@ def test_brute_force_eigsy(beta, N):
     assert mp_rel_digits(lam_i, lam_ref) > 44
 
 
+def exact_negative_pivots(X, N, K, x):
+    """Negative pivots of the exact-rational LDL^T of the dyadic-rounded
+    M - xI (Sylvester's inertia: the number of eigenvalues below x)."""
+    A = [[Fraction(X[r + c], 1 << K) for c in range(N)] for r in range(N)]
+    for i in range(N):
+        A[i][i] -= x
+    n = 0
+    for k in range(N):
+        d = A[k][k]
+        if d == 0:
+            raise ZeroDivisionError("singular leading block at this shift")
+        if d < 0:
+            n += 1
+        for c in range(k + 1, N):
+            for r in range(c, N):
+                A[r][c] -= A[r][k] * A[c][k] / d
+                A[c][r] = A[r][c]
+    return n
+
+
+def exact_bisection(X, N, K, steps=160):
+    """lambda_1 of the dyadic-rounded matrix bracketed by bisection on the
+    exact inertia: (lo, hi) with no eigenvalue below lo and one below hi."""
+    lo, hi = Fraction(0), Fraction(1, 3)      # (1/3: not a point where a pivot vanishes)
+    while exact_negative_pivots(X, N, K, hi) == 0:
+        hi *= 2
+    for _ in range(steps):
+        mid = (lo + hi) / 2
+        if exact_negative_pivots(X, N, K, mid) == 0:
+            lo = mid
+        else:
+            hi = mid
+    return lo, hi
+
+
 def test_sylvester_bisection_exact_rational():
     # exact-rational LDL^T of the dyadic-rounded M: count negative pivots at
     # rational x and bisect; must bracket the oracle's lambda
     N, K, beta = 8, 512, (7, 4)
     X = moments(N, beta, K)
-    A0 = [[Fraction(X[r + c], 1 << K) for c in range(N)] for r in range(N)]
-
-    def negs(x):
-        A = [row[:] for row in A0]
-        for i in range(N):
-            A[i][i] -= x
-        n = 0
-        for k in range(N):
-            d = A[k][k]
-            if d < 0:
-                n += 1
-            for c in range(k + 1, N):
-                for r in range(c, N):
-                    A[r][c] -= A[r][k] * A[c][k] / d
-                    A[c][r] = A[r][c]
-        return n
-
     lam, _ = inverse_iteration(N, beta, K)
-    lo, hi = Fraction(0), Fraction(1)
-    while negs(hi) == 0:
-        hi *= 2
-    for _ in range(120):
-        mid = (lo + hi) / 2
-        if negs(mid) == 0:
-            lo = mid
-        else:
-            hi = mid
+    lo, hi = exact_bisection(X, N, K, 120)
     assert lo <= lam * (1 + Fraction(1, 10 ** 30)) and lam <= hi * (1 + Fraction(1, 10 ** 30))
     assert rel_digits(lam, lo) > 30
+
+
+@pytest.mark.parametrize("N,beta,K,mult", [(8, (7, 4), 512, 4), (10, (3, 2), 768, 8), (12, (1, 1), 512, 3)])
+def test_bracket_phase_illinois(N, beta, K, mult):
+    """The bracketing phase on its own from [0, mult * lambda_1]: the
+    function values of the two ends have opposite signs and one end stays
+    put for consecutive steps, so the Illinois halving must act (a nonzero
+    scale in the trace).  It must land on the root that exact-rational
+    bisection of the same dyadic-rounded matrix gives (to the 40 digits the
+    fixed-point factorisation at this K resolves), and converge
+    superlinearly: plain regula falsi needs over 40 factorisations on the
+    first case, bisection about 160, the Illinois form at most 16."""
+    X = moments(N, beta, K)
+    lo, hi = exact_bisection(X, N, K)
+    b = to_fixed(hi * mult, K, "ceil")
+    trace = []
+    lam, info = bracket_root(N, beta, K, 0, b, X=X, trace=trace)
+    assert info["bracketed"] and info["factorizations"] <= 16
+    assert any(t[4] > 0 or t[5] > 0 for t in trace)
+    # the returned lower end has P > 0, and it lies within the tolerance
+    assert rel_digits(lam, lo) > 40
 
 
 def _parse(s):

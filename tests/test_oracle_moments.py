@@ -107,10 +107,12 @@ def test_reflection():
         assert a0 * b0 <= ref <= a1 * b1
 
 
-def test_rounding_stable_under_more_guard():
-    from oracle import moments as mm
-    X1 = moments(30, (7, 4), 512)
-    gamma_frac_bounds.cache_clear()
-    X2 = moments(30, (7, 4), 512)
+@pytest.mark.parametrize("beta", [(7, 4), (2, 7), (5, 3)])
+def test_rounding_stable_under_more_guard(beta):
+    # the Gamma enclosures at 64 and at 320 guard bits must decide every
+    # rounding the same way: each X_n is the correctly rounded value, so a
+    # bound that failed to enclose Gamma would show as a differing X_n
+    X1 = moments(30, beta, 512, guard=64)
+    X2 = moments(30, beta, 512, guard=320)
     assert X1 == X2
     assert all(x > 0 for x in X1)
