@@ -77,6 +77,11 @@ enum { HK_FLAG_LOOKAHEAD_ON = 0x1000000, HK_FLAG_LOOKAHEAD_OFF = 0x2000000,
 
 typedef struct hk_matrix_s* hk_matrix;
 
+/* Words of lambda_1's binary value in hk_report and hk_result: the computed
+   value (K fractional bits) rounded to nearest, ties to even, to at most
+   32 * HK_LAMBDA_WORDS significant bits (exact when it has fewer). */
+#define HK_LAMBDA_WORDS 16
+
 typedef struct {
   int N, K, h;            /* size, fractional bits of M, of C and L            */
   int digit_bits;         /* device digit radix 2^digit_bits (29)             */
@@ -105,6 +110,9 @@ typedef struct {
   double t_factor_s, t_solve_s, t_total_s;
   int update_launches;    /* update-kernel launches (HK_FLAG_TIME_UPDATES)    */
   double update_ms;       /* their summed device time                         */
+  hk_mpf lambda;          /* lambda_1 in binary (sign 0: none); its digits
+                             point at lambda_words of this same report       */
+  uint32_t lambda_words[HK_LAMBDA_WORDS];
 } hk_report;
 
 /* Bytes of device workspace needed for (N, beta, K).  flags: reserved, 0.
@@ -234,6 +242,9 @@ typedef struct {
   int path;               /* 0: plain method, checked by the inertia
                              bracket; 1: learned proposal, accepted by the
                              rerun at +25% bits (hk_eig_learned)         */
+  hk_mpf lambda;          /* lambda_1 in binary (sign 0: none); its digits
+                             point at lambda_words of this same result   */
+  uint32_t lambda_words[HK_LAMBDA_WORDS];
 } hk_result;
 
 typedef struct {
@@ -263,6 +274,37 @@ hk_status hk_eig_batched(const hk_instance* inst, int count, int digits, int pan
    (architecture, count, N bucket, K bucket).  Synchronises s. */
 hk_status hk_autotune(const hk_instance* inst, int count, void* dev_ws, size_t ws_bytes,
                       hipStream_t s, const char* cache_path, int* best_panel, int* best_lookahead);
+
+/* Batch handles: the instances of a batch laid out in dev_ws (at least
+   hk_batch_workspace_bytes(inst, count) bytes, alive until hk_batch_destroy)
+   and factored together at caller-given shifts by the same captured graph of
+   instance-batched launches hk_eig_batched replays.  The factors of
+   instance i stay in the workspace and are read through the borrowed handle
+   hk_batch_instance(b, i) with hk_factor_export / hk_factor_limb_macs
+   (never hk_matrix_destroy it: the batch owns it). */
+typedef struct hk_batch_s* hk_batch;
+
+/* Lays the batch out in dev_ws: every instance's moments (host) and
+   uploads.  The schedule starts as the tuned one (HK_TUNE_CACHE), else
+   panel 4 with the look-ahead mode chosen by size.  Synchronises s. */
+hk_status hk_batch_create(const hk_instance* inst, int count, void* dev_ws, size_t ws_bytes, hipStream_t s,
+                          hk_batch* out);
+/* panel width in 1..64 and look-ahead mode -1 (by size), 0, 1 or 2 (2
+   forces panel width 1); the digits are the same under every schedule. */
+hk_status hk_batch_set_schedule(hk_batch b, int panel, int lookahead);
+/* LDL^T of M_i - x_i I for every instance ("The LDL^T Determinant
+   Algorithm", as hk_factor) in one graph replay; shifts[i] is a dyadic with
+   at most K_i fractional bits (shifts NULL: all zero).  Per instance (arrays
+   of count, each may be NULL): status (HK_OK, HK_ENOTSPD for a pivot <= 0
+   before the last column, HK_EPRECISION for a width overflow), the number
+   of negative pivots and the first column with a pivot <= 0 (-1: none).  A
+   last pivot <= 0 is reported, not an error (inertia mode).  Returns the
+   first failing status.  Synchronises s. */
+hk_status hk_batch_factor(hk_batch b, const hk_mpf* shifts, hipStream_t s, hk_status* status, int* n_negative,
+                          int* first_bad_col);
+/* Instance i of the batch as a (borrowed) matrix handle; NULL if out of range. */
+hk_matrix hk_batch_instance(hk_batch b, int i);
+hk_status hk_batch_destroy(hk_batch b);
 
 /* ---- precision-proposal network -----------------------------------------
    A float32 MLP 3 -> 64 -> 64 -> 64 -> 2 with ReLU on the hidden layers

@@ -405,6 +405,21 @@ hk_status build_matrix_impl(int N, hk_rational beta, int prec_bits, void* dev_ws
   *out = m;
   return st;
 }
+// shift as an integer with K fractional bits
+bool shift_fixed(const hk_mpf& x, int K, MP& out) {
+  MP v;
+  if (x.sign != 0 && x.ndigits > 0 && x.digits) {
+    v.d.assign(x.digits, x.digits + x.ndigits);
+    v.trim();
+    v.neg = x.sign < 0 && !v.d.empty();
+  }
+  int64_t e = x.exp2 + K;
+  if (e >= 0) { out = shl(v, e); return true; }
+  if (!low_bits_zero(v, -e)) return false;
+  out = shr_mag(v, -e);
+  return true;
+}
+
 }  // namespace hk
 
 extern "C" {
@@ -450,21 +465,6 @@ hk_status hk_matrix_info(hk_matrix m, hk_info* o) {
   o->n_update_launches = m->n_update; o->update_ms = m->update_ms;
   o->lookahead = lookahead_mode(m->lookahead, P.N, P.maxW);
   return HK_OK;
-}
-
-// shift as an integer with K fractional bits
-static bool shift_fixed(const hk_mpf& x, int K, MP& out) {
-  MP v;
-  if (x.sign != 0 && x.ndigits > 0 && x.digits) {
-    v.d.assign(x.digits, x.digits + x.ndigits);
-    v.trim();
-    v.neg = x.sign < 0 && !v.d.empty();
-  }
-  int64_t e = x.exp2 + K;
-  if (e >= 0) { out = shl(v, e); return true; }
-  if (!low_bits_zero(v, -e)) return false;
-  out = shr_mag(v, -e);
-  return true;
 }
 
 hk_status hk_factor(hk_matrix m, hk_mpf shift, int inertia_mode, hipStream_t s, int* n_negative,

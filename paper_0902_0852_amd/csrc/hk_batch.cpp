@@ -324,6 +324,7 @@ hk_status hk_eig_batched(const hk_instance* inst, int count, int digits, int pan
       out[i].verified = okb ? 1 : 0;
       out[i].status = okb ? HK_OK : HK_EVERIFY;
       snprintf(out[i].lambda_dec, sizeof out[i].lambda_dec, "%s", dec[i].c_str());
+      lambda_mpf(lam[i], bt.mats[i]->P.K, &out[i].lambda, out[i].lambda_words);
     }
     if (first == HK_OK && out[i].status != HK_OK) first = out[i].status;
     secant_delete(sm[i]);
@@ -372,6 +373,74 @@ hk_status hk_autotune(const hk_instance* inst, int count, void* dev_ws, size_t w
     if (!f) return dfail_b(HK_EINVAL, "cannot write the tuning cache");
     f << tune_key(inst, count) << " | panel=" << best << " la=" << best_la << " ms=" << best_ms << "\n";
   }
+  return HK_OK;
+}
+
+}  // extern "C"
+
+// ---- batch handles: a batch factored at caller-given shifts, its factors
+// readable instance by instance ---------------------------------------------
+struct hk_batch_s {
+  hk::Batch bt;
+};
+
+extern "C" {
+
+hk_status hk_batch_create(const hk_instance* inst, int count, void* dev_ws, size_t ws_bytes, hipStream_t s,
+                          hk_batch* out) {
+  if (!inst || !out || count < 1) return dfail_b(HK_EINVAL, "bad arguments");
+  *out = nullptr;
+  hk_batch b = new (std::nothrow) hk_batch_s;
+  if (!b) return dfail_b(HK_ENOMEM, "host allocation failed");
+  hk_status st = build_batch(b->bt, inst, count, dev_ws, ws_bytes, s);
+  if (st != HK_OK) { delete b; return st; }
+  const Schedule sc = tuned_schedule(inst, count);
+  b->bt.panel = sc.panel > 0 ? sc.panel : 4;
+  b->bt.lookahead = sc.lookahead;
+  *out = b;
+  return HK_OK;
+}
+
+hk_status hk_batch_set_schedule(hk_batch b, int panel, int lookahead) {
+  if (!b || panel < 1 || panel > 64 || lookahead < -1 || lookahead > 2)
+    return dfail_b(HK_EINVAL, "panel must be in 1..64 and look-ahead in -1..2");
+  b->bt.panel = lookahead == 2 ? 1 : panel;
+  b->bt.lookahead = lookahead;
+  return HK_OK;
+}
+
+hk_status hk_batch_factor(hk_batch b, const hk_mpf* shifts, hipStream_t s, hk_status* status, int* n_negative,
+                          int* first_bad_col) {
+  if (!b) return dfail_b(HK_EINVAL, "null batch");
+  Batch& bt = b->bt;
+  std::vector<MP> x(bt.count);
+  std::vector<int> act(bt.count, 1);
+  for (int i = 0; i < bt.count && shifts; i++)
+    if (!shift_fixed(shifts[i], bt.mats[i]->P.K, x[i]))
+      return dfail_b(HK_EINVAL, "shift of instance " + std::to_string(i) + " has more than K fractional bits");
+  std::vector<BEval> ev;
+  hk_status st = factor_batch(bt, x, act, s, ev, false);
+  if (st != HK_OK) return st;
+  hk_status first = HK_OK;
+  for (int i = 0; i < bt.count; i++) {
+    // inertia mode: a last pivot <= 0 is reported, not an error
+    const hk_status si = ev[i].st;
+    if (status) status[i] = si;
+    if (n_negative) n_negative[i] = ev[i].nneg;
+    if (first_bad_col) first_bad_col[i] = ev[i].first_bad;
+    if (first == HK_OK && si != HK_OK) first = si;
+  }
+  if (first != HK_OK) g_err = "some instances failed";
+  return first;
+}
+
+hk_matrix hk_batch_instance(hk_batch b, int i) {
+  if (!b || i < 0 || i >= b->bt.count) { g_err = "bad instance index"; return nullptr; }
+  return b->bt.mats[i];
+}
+
+hk_status hk_batch_destroy(hk_batch b) {
+  delete b;
   return HK_OK;
 }
 

@@ -49,6 +49,9 @@ void decimal_bracket(const MP& lam, int K, int digits, MP& xlo, MP& xhi, std::st
 bool parse_decimal(const char* s, int digits, MP& D, int64_t& e);
 MP decimal_to_fixed(const MP& D, int64_t e, int K, bool ceil_mode);
 std::string decimal_string(const MP& lam, int K, int digits);
+// lambda with K fractional bits as an hk_mpf whose digits are words
+// (HK_LAMBDA_WORDS of them), rounded to nearest even beyond that
+void lambda_mpf(const MP& lam, int K, hk_mpf* out, uint32_t* words);
 // |a - b| <= 10^-tol |b| for values with the same number of fractional bits
 bool agree(const MP& a, const MP& b, int tol);
 // Inverse iteration of every active instance of bt on its current

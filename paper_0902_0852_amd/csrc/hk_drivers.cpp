@@ -332,6 +332,22 @@ bool parse_decimal(const char* str, int digits, MP& D, int64_t& e) {
   return true;
 }
 
+// lambda (K fractional bits) as an hk_mpf over the caller's words: rounded
+// to nearest, ties to even, to at most 32 HK_LAMBDA_WORDS significant bits
+void lambda_mpf(const MP& lam, int K, hk_mpf* out, uint32_t* words) {
+  memset(words, 0, sizeof(uint32_t) * HK_LAMBDA_WORDS);
+  out->sign = 0; out->ndigits = 0; out->exp2 = 0; out->digits = words;
+  if (lam.d.empty()) return;
+  const int64_t cap = 32 * (int64_t)HK_LAMBDA_WORDS;
+  int64_t drop = std::max<int64_t>(0, lam.bitlen() - cap);
+  MP v = rne_shr(lam, drop);
+  if (v.bitlen() > cap) { v = shr_mag(v, 1); drop += 1; }   // rounding carried into a new top bit (exact)
+  out->sign = lam.neg ? -1 : 1;
+  out->ndigits = (int32_t)v.d.size();
+  out->exp2 = drop - K;
+  for (size_t i = 0; i < v.d.size(); i++) words[i] = v.d[i];
+}
+
 std::string decimal_string(const MP& lam, int K, int digits) {
   MP xlo, xhi;
   std::string dec;
@@ -647,6 +663,7 @@ hk_status hk_smallest_eig(int N, hk_rational beta, int prec_bits, int method, in
     rep->verified = ok ? 1 : 0;
     rep->digits_verified = ok ? digits : 0;
     snprintf(rep->lambda_dec, sizeof rep->lambda_dec, "%s", dec.c_str());
+    if (st == HK_OK) lambda_mpf(lam, prec_bits, &rep->lambda, rep->lambda_words);
     rep->limb_macs = cx.limb_macs;
     rep->t_factor_s = cx.t_factor;
     rep->t_solve_s = cx.t_solve;

@@ -72,6 +72,9 @@ bool reduce_beta(int64_t num, int64_t den, uint32_t* p, uint32_t* q);
 double log2_mu(int n, uint32_t p, uint32_t q);
 bool build_moments(int N, uint32_t p, uint32_t q, int K, std::vector<MP>& X);
 
+// an hk_mpf as an integer with K fractional bits (false if it has more)
+bool shift_fixed(const hk_mpf& x, int K, MP& out);
+
 // conversions between host integers and device digits
 void mp_to_digits(const MP& v, int32_t* out, int n);          // balanced, zero padded
 MP digits_to_mp(const int32_t* d, int n, int64_t stride = 1);

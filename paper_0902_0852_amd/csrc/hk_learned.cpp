@@ -276,6 +276,7 @@ hk_status hk_eig_learned(const hk_instance* inst, int count, const int* bits_hat
         out[i].path = 1;
         out[i].bits_used = en.K;
         snprintf(out[i].lambda_dec, sizeof out[i].lambda_dec, "%s", decimal_string(en.lam, en.K, digits + 5).c_str());
+        lambda_mpf(en.lam, en.K, &out[i].lambda, out[i].lambda_words);
         continue;
       }
       // raise the precision once more, relative to this level
@@ -306,6 +307,9 @@ hk_status hk_eig_learned(const hk_instance* inst, int count, const int* bits_hat
       total_solves[i] += r.solves;
       nfact[i] += r.factorizations;
       snprintf(out[i].lambda_dec, sizeof out[i].lambda_dec, "%s", dec);
+      out[i].lambda = r.lambda;
+      memcpy(out[i].lambda_words, r.lambda_words, sizeof r.lambda_words);
+      out[i].lambda.digits = out[i].lambda_words;
     }
     out[i].solves = total_solves[i];
     out[i].factorizations = nfact[i];

@@ -191,8 +191,9 @@ inline MP inc_mag(MP a) {
 }
 
 // Long division of magnitudes: returns q = floor(|a|/|b|), r = |a| - q|b|.
-// Schoolbook in base 2^32 with a normalised divisor; the trial digit comes
-// from the top two remainder digits and is corrected with the third.
+// Knuth's Algorithm D (The Art of Computer Programming, vol. 2, 4.3.1) in
+// base 2^32 with a normalised divisor: the trial digit comes from the top
+// two remainder digits and is corrected with the third, then an add-back.
 inline void divmod_mag(const MP& a, const MP& b, MP& q, MP& r) {
   q = MP(); r = MP();
   if (cmp_mag(a, b) < 0) { r = a; r.neg = false; return; }

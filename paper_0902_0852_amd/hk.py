@@ -34,6 +34,22 @@ class HKError(RuntimeError):
         self.status = status
 
 
+LAMBDA_WORDS = 16   # HK_LAMBDA_WORDS
+
+
+def mpf_value(f):
+    """An hk_mpf as an exact Fraction (sign * sum d_i 2^(32 i) * 2^exp2)."""
+    from fractions import Fraction
+    if f.sign == 0:
+        return Fraction(0)
+    v = 0
+    for i in range(f.ndigits - 1, -1, -1):
+        v = (v << 32) | f.digits[i]
+    e = f.exp2
+    v = Fraction(v << e) if e >= 0 else Fraction(v, 1 << -e)
+    return -v if f.sign < 0 else v
+
+
 class Rational(ctypes.Structure):
     _fields_ = [("num", ctypes.c_int64), ("den", ctypes.c_int64)]
 
@@ -59,7 +75,8 @@ class Report(ctypes.Structure):
                 ("lambda_dec", ctypes.c_char * 192), ("limb_macs", ctypes.c_double),
                 ("t_factor_s", ctypes.c_double), ("t_solve_s", ctypes.c_double),
                 ("t_total_s", ctypes.c_double), ("update_launches", ctypes.c_int),
-                ("update_ms", ctypes.c_double)]
+                ("update_ms", ctypes.c_double), ("lambda_mpf", MPF),
+                ("lambda_words", ctypes.c_uint32 * LAMBDA_WORDS)]
 
 
 class Instance(ctypes.Structure):
@@ -69,7 +86,8 @@ class Instance(ctypes.Structure):
 class Result(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("factorizations", ctypes.c_int),
                 ("verified", ctypes.c_int), ("lambda_dec", ctypes.c_char * 192),
-                ("bits_used", ctypes.c_int), ("solves", ctypes.c_int), ("path", ctypes.c_int)]
+                ("bits_used", ctypes.c_int), ("solves", ctypes.c_int), ("path", ctypes.c_int),
+                ("lambda_mpf", MPF), ("lambda_words", ctypes.c_uint32 * LAMBDA_WORDS)]
 
 
 class MlpMeta(ctypes.Structure):
@@ -93,7 +111,8 @@ EXPORTS = ["hk_workspace_bytes", "hk_build_matrix", "hk_factor", "hk_solve", "hk
            "hk_batch_workspace_bytes", "hk_eig_batched", "hk_autotune",
            "hk_mlp_nparams", "hk_mlp_cache_floats", "hk_mlp_forward", "hk_mlp_backward", "hk_mlp_mse",
            "hk_mlp_adam_step", "hk_mlp_propose", "hk_bracket_batched", "hk_learned_workspace_bytes",
-           "hk_eig_learned", "hk_moments_host"]
+           "hk_eig_learned", "hk_moments_host", "hk_batch_create", "hk_batch_set_schedule",
+           "hk_batch_factor", "hk_batch_instance", "hk_batch_destroy"]
 
 
 def lib():
@@ -139,6 +158,16 @@ def lib():
         L.hk_batch_workspace_bytes.argtypes = [P, I]
         L.hk_eig_batched.restype = I
         L.hk_eig_batched.argtypes = [P, I, I, I, P, SZ, P, P, ctypes.POINTER(BatchReport)]
+        L.hk_batch_create.restype = I
+        L.hk_batch_create.argtypes = [P, I, P, SZ, P, ctypes.POINTER(P)]
+        L.hk_batch_set_schedule.restype = I
+        L.hk_batch_set_schedule.argtypes = [P, I, I]
+        L.hk_batch_factor.restype = I
+        L.hk_batch_factor.argtypes = [P, P, P, P, P, P]
+        L.hk_batch_instance.restype = P
+        L.hk_batch_instance.argtypes = [P, I]
+        L.hk_batch_destroy.restype = I
+        L.hk_batch_destroy.argtypes = [P]
         L.hk_autotune.restype = I
         L.hk_autotune.argtypes = [P, I, P, SZ, P, ctypes.c_char_p, ctypes.POINTER(I), ctypes.POINTER(I)]
         F = ctypes.c_float
@@ -248,48 +277,8 @@ def workspace_bytes(N, beta, K):
     return lib().hk_workspace_bytes(N, _rational(beta), K, 0)
 
 
-class Matrix:
-    """Owns a device workspace (a torch uint8 tensor) and an hk_matrix."""
-
-    def __init__(self, N, beta, K, stream=None, ws=None):
-        import torch
-        self.N, self.K = N, K
-        self.beta = beta
-        nbytes = workspace_bytes(N, beta, K)
-        if nbytes == 0:
-            raise HKError(1, lib().hk_last_error().decode())
-        self.ws = ws if ws is not None else torch.empty(nbytes, dtype=torch.uint8, device="cuda")
-        h = ctypes.c_void_p()
-        _check(lib().hk_build_matrix(N, _rational(beta), K, ctypes.c_void_p(self.ws.data_ptr()),
-                                     self.ws.numel(), _stream(stream), ctypes.byref(h)))
-        self.h = h
-
-    def __del__(self):
-        if getattr(self, "h", None) is not None and _lib is not None:
-            _lib.hk_matrix_destroy(self.h)
-            self.h = None
-
-    def set_panel(self, b):
-        _check(lib().hk_set_panel(self.h, b))
-
-    def set_timing(self, on):
-        _check(lib().hk_set_timing(self.h, 1 if on else 0))
-
-    def set_lookahead(self, mode):
-        _check(lib().hk_set_lookahead(self.h, mode))
-
-    def info(self):
-        inf = Info()
-        _check(lib().hk_matrix_info(self.h, ctypes.byref(inf)))
-        return inf
-
-    def factor(self, shift_fixed=0, inertia_mode=0, stream=None, raise_on_error=True):
-        f, keep = _mpf_fixed(shift_fixed, self.K)
-        nn, fb = ctypes.c_int(0), ctypes.c_int(0)
-        st = lib().hk_factor(self.h, f, inertia_mode, _stream(stream), ctypes.byref(nn), ctypes.byref(fb))
-        if raise_on_error:
-            _check(st)
-        return st, nn.value, fb.value
+class _Factors:
+    """Read-back of a factorisation held by an hk_matrix handle (self.h, self.N)."""
 
     def export(self, kind, c0=0, c1=None, stream=None):
         c1 = self.N if c1 is None else c1
@@ -339,6 +328,50 @@ class Matrix:
         v = ctypes.c_double()
         _check(lib().hk_factor_limb_macs(self.h, _stream(stream), ctypes.byref(v)))
         return v.value
+
+
+class Matrix(_Factors):
+    """Owns a device workspace (a torch uint8 tensor) and an hk_matrix."""
+
+    def __init__(self, N, beta, K, stream=None, ws=None):
+        import torch
+        self.N, self.K = N, K
+        self.beta = beta
+        nbytes = workspace_bytes(N, beta, K)
+        if nbytes == 0:
+            raise HKError(1, lib().hk_last_error().decode())
+        self.ws = ws if ws is not None else torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        h = ctypes.c_void_p()
+        _check(lib().hk_build_matrix(N, _rational(beta), K, ctypes.c_void_p(self.ws.data_ptr()),
+                                     self.ws.numel(), _stream(stream), ctypes.byref(h)))
+        self.h = h
+
+    def __del__(self):
+        if getattr(self, "h", None) is not None and _lib is not None:
+            _lib.hk_matrix_destroy(self.h)
+            self.h = None
+
+    def set_panel(self, b):
+        _check(lib().hk_set_panel(self.h, b))
+
+    def set_timing(self, on):
+        _check(lib().hk_set_timing(self.h, 1 if on else 0))
+
+    def set_lookahead(self, mode):
+        _check(lib().hk_set_lookahead(self.h, mode))
+
+    def info(self):
+        inf = Info()
+        _check(lib().hk_matrix_info(self.h, ctypes.byref(inf)))
+        return inf
+
+    def factor(self, shift_fixed=0, inertia_mode=0, stream=None, raise_on_error=True):
+        f, keep = _mpf_fixed(shift_fixed, self.K)
+        nn, fb = ctypes.c_int(0), ctypes.c_int(0)
+        st = lib().hk_factor(self.h, f, inertia_mode, _stream(stream), ctypes.byref(nn), ctypes.byref(fb))
+        if raise_on_error:
+            _check(st)
+        return st, nn.value, fb.value
 
     # device vectors
     def new_vec(self):
@@ -390,8 +423,9 @@ def smallest_eig(N, beta, K, method=HK_INVERSE, digits=45, shift_fixed=None, str
     st = L.hk_smallest_eig(N, _rational(beta), K, method | flags, digits, hint, ctypes.c_void_p(ws.data_ptr()),
                            ws.numel(), _stream(stream), out, 256, ctypes.byref(rep))
     _check(st)
-    d = {k: getattr(rep, k) for k, _ in Report._fields_}
+    d = {k: getattr(rep, k) for k, _ in Report._fields_ if not k.startswith("lambda_")}
     d["lambda_dec"] = rep.lambda_dec.decode()
+    d["lambda"] = mpf_value(rep.lambda_mpf)
     return out.value.decode(), d
 
 
@@ -425,10 +459,72 @@ def eig_batched(insts, digits=45, panel=0, stream=None, ws=None):
     res = [(r.status, r.lambda_dec.decode(), r.verified, r.factorizations) for r in out]
     d = {k: getattr(rep, k) for k, _ in BatchReport._fields_}
     d["bits_used"] = [r.bits_used for r in out]
+    d["lambda"] = [mpf_value(r.lambda_mpf) for r in out]
     d["status"] = st
     if st != 0 and all(r[0] == 0 for r in res):
         _check(st)
     return res, d
+
+
+class BatchMember(_Factors):
+    """Instance i of a Batch (a borrowed hk_matrix handle)."""
+
+    def __init__(self, batch, i, N):
+        self._batch = batch       # keeps the batch (and its workspace) alive
+        self.h = lib().hk_batch_instance(batch.h, i)
+        if not self.h:
+            raise HKError(1, lib().hk_last_error().decode())
+        self.N = N
+
+
+class Batch:
+    """A batch of (N, beta, K) instances in one device workspace, factored
+    together at caller-given shifts (hk_batch_create / hk_batch_factor)."""
+
+    def __init__(self, insts, stream=None, ws=None):
+        import torch
+        L = lib()
+        self.insts = list(insts)
+        self._arr = _instances(self.insts)
+        nbytes = L.hk_batch_workspace_bytes(ctypes.cast(self._arr, ctypes.c_void_p), len(self.insts))
+        if nbytes == 0:
+            raise HKError(1, L.hk_last_error().decode())
+        self.ws = ws if ws is not None else torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        h = ctypes.c_void_p()
+        _check(L.hk_batch_create(ctypes.cast(self._arr, ctypes.c_void_p), len(self.insts),
+                                 ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(), _stream(stream),
+                                 ctypes.byref(h)))
+        self.h = h
+
+    def __del__(self):
+        if getattr(self, "h", None) is not None and _lib is not None:
+            _lib.hk_batch_destroy(self.h)
+            self.h = None
+
+    def set_schedule(self, panel, lookahead=-1):
+        _check(lib().hk_batch_set_schedule(self.h, panel, lookahead))
+
+    def factor(self, shifts=None, stream=None):
+        """shifts: list of ints with K_i fractional bits (None: all zero).
+        Returns (status, n_negative, first_bad_col) per instance."""
+        n = len(self.insts)
+        keep = []
+        arr = None
+        if shifts is not None:
+            arr = (MPF * n)()
+            for i, (x, (_, _, K)) in enumerate(zip(shifts, self.insts)):
+                f, k = _mpf_fixed(x, K)
+                arr[i] = f
+                keep.append(k)
+        st = (ctypes.c_int * n)()
+        nn = (ctypes.c_int * n)()
+        fb = (ctypes.c_int * n)()
+        lib().hk_batch_factor(self.h, ctypes.cast(arr, ctypes.c_void_p) if arr is not None else None,
+                              _stream(stream), st, nn, fb)
+        return [(st[i], nn[i], fb[i]) for i in range(n)]
+
+    def member(self, i):
+        return BatchMember(self, i, self.insts[i][0])
 
 
 def autotune(insts, cache_path=None, stream=None, ws=None):
@@ -576,7 +672,7 @@ def eig_learned(insts, bits_hat, ln_sigma_hat, digits=40, panel=0, stream=None, 
                           ws.numel(), _stream(stream), ctypes.cast(out, ctypes.c_void_p), ctypes.byref(rep))
     res = [{"status": r.status, "lambda_dec": r.lambda_dec.decode(), "verified": r.verified,
             "factorizations": r.factorizations, "bits_used": r.bits_used, "solves": r.solves,
-            "path": r.path} for r in out]
+            "path": r.path, "lambda": mpf_value(r.lambda_mpf)} for r in out]
     d = {k: getattr(rep, k) for k, _ in BatchReport._fields_}
     d["status"] = st
     if st != 0 and all(r["status"] == 0 for r in res):

@@ -48,3 +48,62 @@ def test_autotune_writes_cache(hk, tmp_path):
     assert b in (1, 2, 4, 8, 16) and la in (0, 1, 2)
     txt = open(path).read()
     assert "panel=%d la=%d" % (b, la) in txt
+
+
+# ---- factor parity of the batched path -------------------------------------
+import hashlib  # noqa: E402
+import json  # noqa: E402
+import os  # noqa: E402
+
+from oracle.moments import moments  # noqa: E402
+from tests.golden.canon import canon_bytes, column_digest  # noqa: E402
+from tests.test_gpu_factor import compare  # noqa: E402
+
+BATCH_GOLD = os.path.join(os.path.dirname(__file__), "golden", "batch_digests.json")
+
+
+@pytest.mark.parametrize("panel,la", [(3, 1), (3, 0), (1, 2)])
+def test_batched_factors_equal_oracle_uneven(hk, panel, la):
+    # uneven instances, shifts of both signs: every digit of every instance
+    # against the oracle, under each schedule (second-stream look-ahead, none,
+    # one launch per column)
+    insts = [(40, (7, 4), 512), (97, (3, 2), 1024), (130, (1, 1), 1536), (70, (2, 7), 768), (5, (5, 3), 256)]
+    shifts = [3 << 256, -(5 << 512), 0, 7 << 384, -(1 << 128)]
+    log("batched factors, uneven, panel %d look-ahead %d" % (panel, la))
+    b = hk.Batch(insts)
+    b.set_schedule(panel, la)
+    res = b.factor(shifts)
+    for i, ((N, beta, K), xf) in enumerate(zip(insts, shifts)):
+        assert res[i] == (0, 0, -1), (i, res[i])
+        of = oracle.factor_from_moments(moments(N, beta, K), N, K, xf)
+        compare(b.member(i), of, N)
+
+
+@pytest.mark.parametrize("panel,la", [(2, 1), (1, 2)])
+def test_batched_factors_match_golden_batch(hk, panel, la):
+    # the seeded batch of ten uneven instances up to N = 400, K = 8192
+    # (tests/golden/make_batch_digests.py, oracle only): per-column digests
+    # of C and L, the pivots and the algorithmic work of every instance
+    db = json.load(open(BATCH_GOLD))
+    g = db["instances"]
+    insts = [(x["N"], tuple(x["beta"]), x["K"]) for x in g]
+    log("golden batch of %d, panel %d look-ahead %d" % (len(insts), panel, la))
+    b = hk.Batch(insts)
+    b.set_schedule(panel, la)
+    res = b.factor()
+    for i, x in enumerate(g):
+        assert res[i] == (0, 0, -1), (i, res[i])
+        m = b.member(i)
+        N = x["N"]
+        bad = []
+        for c0 in range(0, N, 50):
+            c1 = min(N, c0 + 50)
+            Cs = m.columns_C(c0, c1)
+            Ls = m.columns_L(c0, min(c1, N - 1))
+            for pc in range(c0, c1):
+                Lc = Ls[pc - c0] if pc < N - 1 else []
+                if column_digest(Cs[pc - c0], Lc) != x["columns"][pc]:
+                    bad.append(pc)
+        assert bad == [], (i, bad[:5])
+        assert hashlib.sha256(canon_bytes(m.pivots())).hexdigest() == x["pivots"]
+        assert m.limb_macs() == x["limb_macs"]

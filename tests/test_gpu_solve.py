@@ -26,6 +26,8 @@ def parse_dec(s):
     (70, (3, 2), 640, 11, 3, 3),
     (65, (1, 3), 768, 0, 8, 4),
     (130, (1, 2), 1024, 5, 4, 5),
+    (200, (7, 4), 2048, 0, 1, 6),      # the N = 200 workload, every digit
+    (200, (7, 4), 2048, -9, 4, 7),
 ])
 def test_solve_parity(hk, N, beta, K, xn, panel, seed):
     log("solve N=%d beta=%s K=%d panel=%d" % (N, beta, K, panel))

@@ -148,3 +148,70 @@ def test_inertia_counts_eigenvalues(beta, N):
             assert f.n_negative == 1 and f.first_nonpos == N - 1
         else:
             assert f.n_negative == want, (xf, want)
+
+
+# ---- constructed rounding ties (the shifts of tests/tie_cases.py) ----------
+from tests.tie_cases import (beta1_negative_last_pivot_shift, beta1_pivot_tie_shift, general_tie_shift,
+                             is_half, rne)
+
+
+@pytest.mark.parametrize("K,m", [(512, 1), (512, 3), (512, -1), (8192, 1), (16640, 3)])
+def test_beta1_pivot_ties(K, m):
+    # beta = 1, x_fix = m 2^(h-1): A_00 and A^(1)_11 are exact halves at h
+    # bits; the first two columns checked against exact rational arithmetic
+    N, h = 6, K // 2
+    xf = beta1_pivot_tie_shift(K, m)
+    f = oracle.factor(N, (1, 1), K, xf)
+    C0, C1, L0 = f.column_C(0), f.column_C(1), f.column_L(0)
+    a00 = Fraction((1 << K) - xf, 1 << h)
+    assert is_half(a00)
+    assert C0[0] == rne(a00) and C0[0] % 2 == 0
+    assert C0[1:] == [math.factorial(r) << h for r in range(1, N)]
+    assert L0 == [rne(Fraction(C0[i] << h, C0[0])) for i in range(1, N)]
+    a11 = Fraction((2 << K) - xf - C0[1] * L0[0], 1 << h)
+    assert is_half(a11)
+    assert C1[0] == rne(a11) and C1[0] % 2 == 0
+
+
+@pytest.mark.parametrize("beta,K,D,e", [((3, 2), 640, 1, 0), ((3, 2), 640, 1, 1), ((3, 2), 640, 1, 3),
+                                        ((5, 3), 640, 3, 0), ((2, 7), 1024, 5, 0), ((3, 2), 8192, 1, 0)])
+def test_general_division_ties(beta, K, D, e):
+    # x_fix = X_0 - 2^(K+1) D - e 2^(h-1): the pivot is 2^(h+1) D (e = 0, 1) or
+    # 2^(h+1) D + 2 (e = 3), and L_0[r] = RNE(C_0[r] 2^h / d_0) is a tie for
+    # every C_0[r] = D mod 2D when e < 3
+    N, h = 40, K // 2
+    X = moments(N, beta, K)
+    xf = general_tie_shift(X[0], K, D, e << (h - 1) if e else 0)
+    f = oracle.factor_from_moments(X, N, K, xf)
+    C0, L0 = f.column_C(0), f.column_L(0)
+    assert C0[0] == (D << (h + 1)) + (2 if e == 3 else 0)
+    assert C0[1:] == [rne(Fraction(X[r], 1 << h)) for r in range(1, N)]
+    q = [Fraction(C0[i] << h, C0[0]) for i in range(1, N)]
+    assert L0 == [rne(v) for v in q]
+    ties = sum(is_half(v) for v in q)
+    if e < 3:
+        assert ties >= 1 and ties == sum(c % (2 * D) == D for c in C0[1:])
+
+
+def test_beta1_negative_last_pivot_tie():
+    # N = 2, beta = 1, x just above the smaller eigenvalue (3 - 5^(1/2))/2 of
+    # [[1, 1], [1, 2]]: the last pivot is a negative exact half at h bits
+    K = 512
+    h = K // 2
+    X = moments(2, (1, 1), K)
+
+    def piv(xf):
+        return oracle.factor_from_moments(X, 2, K, xf).pivots()
+    xf = beta1_negative_last_pivot_shift(K, piv)
+    f = oracle.factor_from_moments(X, 2, K, xf)
+    d0, d1 = f.pivots()
+    assert d0 == rne(Fraction(X[0] - xf, 1 << h)) > 0
+    L01 = f.column_L(0)[0]
+    assert L01 == rne(Fraction(f.column_C(0)[1] << h, d0))
+    a11 = Fraction(X[2] - xf - f.column_C(0)[1] * L01, 1 << h)
+    assert a11 < 0 and is_half(a11)
+    assert d1 == rne(a11) and d1 % 2 == 0
+    assert f.n_negative == 1 and f.first_nonpos == 1
+    # x between the two eigenvalues of the 2 x 2 matrix
+    x = Fraction(xf, 1 << K)
+    assert (3 - 2.2360679775) / 2 < float(x) < 0.9
