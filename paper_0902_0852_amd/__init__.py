@@ -7,4 +7,4 @@ from .hk import (HK_INVERSE, HK_SECANT, HK_FLAG_NO_WORK_COUNT, HK_FLAG_TIME_UPDA
                  HK_FLAG_LOOKAHEAD_OFF, HK_FLAG_LOOKAHEAD_FUSED, EXPORTS, HKError, Matrix, lib, smallest_eig,  # noqa: F401
                  workspace_bytes, batch_workspace_bytes, eig_batched, autotune,
                  mlp_nparams, mlp_cache_floats, mlp_forward, mlp_backward, mlp_mse, mlp_adam_step,
-                 bracket_batched, mlp_meta, mlp_propose, eig_learned, moments_host)
+                 bracket_batched, mlp_meta, mlp_propose, eig_learned, moments_host, Batch, BatchMember, mpf_value)
