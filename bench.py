@@ -1,10 +1,11 @@
 """Benchmark: smallest eigenvalue of the Hankel moment matrix on one MI355X.
 
-One step = one pass of the whole hot path on one synthetic instance: moments
-(Gamma at the working precision) -> LDL^T factorisations (expansion, panel,
-trailing update) -> the eigenvalue iteration -> the inertia bracket at 45
-digits, i.e. one verified lambda_1.  The default workload is N = 200,
-beta = 7/4, K = 2048 fractional bits.
+One step = one pass of the whole hot path over the workload's synthetic
+instances: for each, moments (Gamma at the working precision) -> LDL^T
+factorisations (expansion, panel, trailing update) -> the eigenvalue
+iteration -> the inertia bracket at 45 digits, i.e. one verified lambda_1
+per instance.  The default workload is N = 500, K = 6144 fractional bits,
+beta = 1/2, 1, 3/2 and 2 (four separate runs, one step covers all four).
 
 Printed value: algorithmic 32-bit limb MACs per second of the whole job (the
 schoolbook count of every factorisation's trailing update, sum over updates
@@ -17,7 +18,7 @@ events that every such launch records on the library's stream, against one
 32-bit multiply per lane per clock on 256 CUs at 2.4 GHz), and the CPU
 oracle timed on the host cores.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c3]
 """
 import argparse
 import json
@@ -26,13 +27,15 @@ import sys
 import time
 
 CONFIGS = {
-    "c1": dict(N=32, beta=(1, 1), K=512, desc="N=32 beta=1 K=512"),
-    "c2": dict(N=200, beta=(7, 4), K=2048, desc="N=200 beta=7/4 K=2048"),
-    "c3b1": dict(N=500, beta=(1, 1), K=6144, desc="N=500 beta=1 K=6144"),
-    "c3b2": dict(N=500, beta=(2, 1), K=6144, desc="N=500 beta=2 K=6144"),
-    "c3b32": dict(N=500, beta=(3, 2), K=6144, desc="N=500 beta=3/2 K=6144"),
-    "c3b12": dict(N=500, beta=(1, 2), K=6144, desc="N=500 beta=1/2 K=6144"),
-    "c5": dict(N=1500, beta=(3, 2), K=24576, desc="N=1500 beta=3/2 K=24576"),
+    "c1": dict(runs=[(32, (1, 1), 512)], desc="N=32 beta=1 K=512"),
+    "c2": dict(runs=[(200, (7, 4), 2048)], desc="N=200 beta=7/4 K=2048"),
+    "c3": dict(runs=[(500, (1, 2), 6144), (500, (1, 1), 6144), (500, (3, 2), 6144), (500, (2, 1), 6144)],
+               desc="N=500 K=6144, beta = 1/2, 1, 3/2 and 2 (four runs)", cpu_run=3),
+    "c3b1": dict(runs=[(500, (1, 1), 6144)], desc="N=500 beta=1 K=6144"),
+    "c3b2": dict(runs=[(500, (2, 1), 6144)], desc="N=500 beta=2 K=6144"),
+    "c3b32": dict(runs=[(500, (3, 2), 6144)], desc="N=500 beta=3/2 K=6144"),
+    "c3b12": dict(runs=[(500, (1, 2), 6144)], desc="N=500 beta=1/2 K=6144"),
+    "c5": dict(runs=[(1500, (3, 2), 24576)], desc="N=1500 beta=3/2 K=24576"),
 }
 PEAK_INT_MUL = 256 * 64 * 2.4e9       # one 32x32 multiply per lane per clock
 HBM_PEAK = 8.0e12
@@ -67,34 +70,59 @@ def log(msg):
     sys.stderr.flush()
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(cfg, method, budget_s=20.0):
-    """The oracle (test infrastructure) on the same workload, bounded: full
-    verified lambda_1 runs (iteration + the two bracket factorisations) until
-    the budget is spent; work = factorisations x the limb MACs of one."""
+    """The oracle (test infrastructure) on the same workload, bounded.  For
+    a single small run: whole verified lambda_1 runs (iteration + the two
+    bracket factorisations) until the budget is spent, work = factorisations
+    x the limb MACs of one.  For N >= 500 (where the oracle needs minutes for
+    one whole factorisation): the first 64 columns of the factorisation at
+    x = 0 of the configuration's sample run, which carry about a third of its
+    update work; the rate is the same quantity, limb MACs per second."""
     import oracle
     from oracle.drivers import inverse_iteration, secant, verify
     from oracle.moments import moments
-    N, beta, K = cfg["N"], cfg["beta"], cfg["K"]
+    N, beta, K = cfg["runs"][cfg.get("cpu_run", 0)]
     X = moments(N, beta, K)                 # matrix generation excluded, as in the paper
+    info = {"cores": oracle.max_threads(), "kind": "oracle", "cpu": cpu_model(), "nproc": os.cpu_count()}
+    if N >= 500:
+        ncols = 64
+        t0 = time.time()
+        f = oracle.factor_from_moments(X, N, K, 0, ncols=ncols)
+        dt = time.time() - t0
+        info.update({"value": f.limb_macs / dt, "unit": "limb-MAC/s",
+                     "sample": "the first %d columns of the factorisation at x = 0 of N=%d beta=%d/%d K=%d "
+                               "(%.3e limb-MACs), moments excluded, %.1f s"
+                               % (ncols, N, beta[0], beta[1], K, f.limb_macs, dt)})
+        return info
     macs0 = oracle.factor_from_moments(X, N, K, 0).limb_macs
     t0 = time.time()
     nfact, n = 0, 0
     while True:
         if method == "secant":
-            lam, info = secant(N, beta, K, X=X)
+            lam, inf = secant(N, beta, K, X=X)
         else:
-            lam, info = inverse_iteration(N, beta, K, X=X)
+            lam, inf = inverse_iteration(N, beta, K, X=X)
         ok, _ = verify(N, beta, K, lam, X=X)
-        nfact += info["factorizations"] + 2
+        nfact += inf["factorizations"] + 2
         n += 1
         if time.time() - t0 > budget_s / 2 or n >= 12:
             break
     dt = time.time() - t0
-    return {"value": nfact * macs0 / dt, "unit": "limb-MAC/s", "cores": oracle.max_threads(),
-            "kind": "oracle",
-            "sample": "%d verified lambda_1 runs (%s driver, %d factorisations) of %s, "
-                      "moments excluded, %.1f s" % (n, method, nfact, cfg["desc"], dt),
-            "lambda_per_s": n / dt}
+    info.update({"value": nfact * macs0 / dt, "unit": "limb-MAC/s",
+                 "sample": "%d verified lambda_1 runs (%s driver, %d factorisations) of N=%d beta=%d/%d K=%d, "
+                           "moments excluded, %.1f s" % (n, method, nfact, N, beta[0], beta[1], K, dt),
+                 "lambda_per_s": n / dt})
+    return info
 
 
 def learned_gain(args):
@@ -109,9 +137,9 @@ def learned_gain(args):
     if single:
         # one large instance: the plain form is inverse iteration from 0 at the
         # fixed precision plus the inertia bracket (the faster plain driver)
-        cfg = CONFIGS["c5"]
-        insts = [(cfg["N"], cfg["beta"])]
-        plain = [(cfg["N"], cfg["beta"], cfg["K"])]
+        N5, beta5, K5 = CONFIGS["c5"]["runs"][0]
+        insts = [(N5, beta5)]
+        plain = [(N5, beta5, K5)]
     else:
         insts = learned.sample_instances(args.instances, args.seed, args.n_lo, args.n_hi)
         plain = [(N, b, learned.plain_bits(N)) for N, b in insts]
@@ -169,16 +197,34 @@ def learned_gain(args):
     print(json.dumps(out), flush=True)
 
 
+def peak_rates(args):
+    """Measured issue rates of the VALU multiply instructions (hk_mul_rate)
+    against the nominal one operation per lane per clock on 256 CUs at
+    2.4 GHz; the update kernel multiplies with v_mad_i64_i32."""
+    import paper_0902_0852_amd as hk
+    kinds = [("v_mad_i64_i32", hk.HK_RATE_MAD_I64_I32), ("v_mad_u64_u32", hk.HK_RATE_MAD_U64_U32),
+             ("v_mad_u32_u24", hk.HK_RATE_MAD_U32_U24), ("v_fma_f64", hk.HK_RATE_FMA_F64)]
+    out = {"metric": "measured VALU issue rate (lane operations/s)", "unit": "ops/s", "n_gpus": 1,
+           "nominal_per_s": PEAK_INT_MUL, "rates": {}}
+    for name, k in kinds:
+        rate, clk = hk.mul_rate(k)
+        out["rates"][name] = {"per_s": rate, "of_nominal": rate / PEAK_INT_MUL, "clock_hz": clk,
+                              "per_lane_per_clock": rate / (256 * 64 * clk) if clk > 0 else None}
+        log("%-14s %.4e ops/s = %.3f of nominal, clock %.3f GHz" % (name, rate, rate / PEAK_INT_MUL, clk / 1e9))
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
+    ap.add_argument("--config", default="c3", choices=sorted(CONFIGS))
     ap.add_argument("--method", default="secant", choices=["secant", "inverse"])
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--mode", default="plain", choices=["plain", "learned"],
-                    help="learned: batched + learned form against the batched plain form")
+    ap.add_argument("--mode", default="plain", choices=["plain", "learned", "peak"],
+                    help="learned: batched + learned form against the batched plain form; "
+                         "peak: measured issue rates of the multiply instructions")
     ap.add_argument("--model", default=None, help="network file (default: the package's trained one)")
     ap.add_argument("--instances", type=int, default=64)
     ap.add_argument("--seed", type=int, default=4242)
@@ -196,44 +242,58 @@ def main():
     if args.mode == "learned":
         learned_gain(args)
         return
+    if args.mode == "peak":
+        peak_rates(args)
+        return
     import torch
     import paper_0902_0852_amd as hk
     cfg = CONFIGS[args.config]
-    N, beta, K = cfg["N"], cfg["beta"], cfg["K"]
+    runs = cfg["runs"]
     method = hk.HK_SECANT if args.method == "secant" else hk.HK_INVERSE
-    ws = torch.empty(hk.workspace_bytes(N, beta, K), dtype=torch.uint8, device="cuda")
-    # untimed: the panel width tuned for this shape (hk_autotune; the library
+    ws = torch.empty(max(hk.workspace_bytes(N, beta, K) for N, beta, K in runs), dtype=torch.uint8, device="cuda")
+    # untimed: the schedule tuned for each shape (hk_autotune; the library
     # reads it back from the cache named by HK_TUNE_CACHE)
     import tempfile
     tune_path = os.path.join(tempfile.gettempdir(), "hk_tune_%d.txt" % os.getpid())
     os.environ["HK_TUNE_CACHE"] = tune_path
-    if args.panel > 0:
-        panel, la = args.panel, args.lookahead
-        if la < 0:   # the mode the library picks for this size
-            m = hk.Matrix(N, beta, K)
-            m.set_panel(panel)
-            la = m.info().lookahead
-            del m
-        log("panel width %d, look-ahead %d (given)" % (panel, la))
-    else:
-        panel, la = hk.autotune([(N, beta, K)], cache_path=tune_path)
-        log("tuned panel width %d, look-ahead %d" % (panel, la))
-    pflag = hk.HK_FLAG_PANEL(panel)
-    pflag |= {0: hk.HK_FLAG_LOOKAHEAD_OFF, 1: hk.HK_FLAG_LOOKAHEAD_ON,
-              2: hk.HK_FLAG_LOOKAHEAD_FUSED}.get(la, 0)
+    flags, scheds = [], []
+    for N, beta, K in runs:
+        if args.panel > 0:
+            panel, la = args.panel, args.lookahead
+            if la < 0:   # the mode the library picks for this size
+                m = hk.Matrix(N, beta, K, ws=ws)
+                m.set_panel(panel)
+                la = m.info().lookahead
+                del m
+        else:
+            panel, la = hk.autotune([(N, beta, K)], cache_path=tune_path)
+        pflag = hk.HK_FLAG_PANEL(panel)
+        pflag |= {0: hk.HK_FLAG_LOOKAHEAD_OFF, 1: hk.HK_FLAG_LOOKAHEAD_ON,
+                  2: hk.HK_FLAG_LOOKAHEAD_FUSED}.get(la, 0)
+        flags.append(pflag)
+        scheds.append((panel, la))
+        log("N=%d beta=%d/%d K=%d: panel width %d, look-ahead %d (%s)"
+            % (N, beta[0], beta[1], K, panel, la, "given" if args.panel > 0 else "tuned"))
+
+    def one_step(extra):
+        out = []
+        for (N, beta, K), fl in zip(runs, flags):
+            dec, r = hk.smallest_eig(N, beta, K, method=method, digits=45, ws=ws, flags=fl | extra)
+            assert r["verified"] == 1
+            out.append((dec, r))
+        return out
     # untimed: work count (deterministic) and warmup
-    dec, rep = hk.smallest_eig(N, beta, K, method=method, digits=45, ws=ws, flags=pflag)
-    macs_per_step = rep["limb_macs"]
+    res = one_step(0)
+    macs_per_step = sum(r["limb_macs"] for _, r in res)
+    lams = [dec for dec, _ in res]
     log("work per step: %.4e limb-MACs over %d factorisations; lambda_1 = %s"
-        % (macs_per_step, rep["factorizations"], dec))
+        % (macs_per_step, sum(r["factorizations"] for _, r in res), ", ".join(lams)))
     for _ in range(max(0, args.warmup - 1)):
-        hk.smallest_eig(N, beta, K, method=method, digits=45, ws=ws, flags=hk.HK_FLAG_NO_WORK_COUNT | pflag)
+        one_step(hk.HK_FLAG_NO_WORK_COUNT)
     torch.cuda.synchronize()
     t0 = time.time()
     for _ in range(args.steps):
-        dec, r = hk.smallest_eig(N, beta, K, method=method, digits=45, ws=ws,
-                                 flags=hk.HK_FLAG_NO_WORK_COUNT | pflag)
-        assert r["verified"] == 1
+        one_step(hk.HK_FLAG_NO_WORK_COUNT)
     torch.cuda.synchronize()
     dt = time.time() - t0
     ms_step = 1e3 * dt / args.steps
@@ -241,14 +301,20 @@ def main():
     # the update kernel's own time: one more step in which every update
     # launch records its start and end on HIP events of the library's stream
     # (stream launches instead of the graph replay, the kernels are the same)
-    _, r = hk.smallest_eig(N, beta, K, method=method, digits=45, ws=ws,
-                           flags=hk.HK_FLAG_NO_WORK_COUNT | hk.HK_FLAG_TIME_UPDATES | pflag)
+    res_t = one_step(hk.HK_FLAG_NO_WORK_COUNT | hk.HK_FLAG_TIME_UPDATES)
     torch.cuda.synchronize()
-    upd_ms, upd_n = r["update_ms"], r["update_launches"]
-    achieved = macs_per_step / (upd_ms * 1e-3) if upd_ms > 0 else 0.0
-    kernel = "k_column" if la == 2 else "k_update"
+    upd_ms = sum(r["update_ms"] for _, r in res_t)
+    upd_n = sum(r["update_launches"] for _, r in res_t)
+    bulk_ms = sum(r["bulk_ms"] for _, r in res_t)
+    bulk_n = sum(r["bulk_launches"] for _, r in res_t)
+    macs_bulk = sum(r["limb_macs_bulk"] for _, r in res)
+    fused = all(la == 2 for _, la in scheds)
+    kernel = "k_column" if fused else "k_update"
     kdesc = ("k_column (one column: its rows' update by the previous column, finalisation and division; "
-             "the update of the columns beyond)" if la == 2 else "k_update (trailing + in-panel update)")
+             "the update of the columns beyond)" if fused else
+             "k_update (the bulk of the trailing update: each panel's update of the columns beyond the next "
+             "panel under look-ahead, or its whole trailing update without)")
+    achieved = macs_bulk / (bulk_ms * 1e-3) if bulk_ms > 0 else 0.0
     traffic, traffic_src = measured_traffic(args.config, kernel)
     out = {
         "metric": "multiprecision limb-MACs/s (whole job) and % int-mul peak of the update kernel; "
@@ -258,20 +324,26 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
         "config": {"workload": "lambda_1 of the Hankel moment matrix, %s, %s driver, verified "
                                "to 45 digits" % (cfg["desc"], args.method),
-                   "N": N, "beta": "%d/%d" % beta, "prec_bits": K, "method": args.method,
-                   "panel": panel, "lookahead": la},
-        "lambda_solves_per_s": args.steps / dt,
-        "lambda_1": dec,
+                   "N": [N for N, _, _ in runs], "beta": ["%d/%d" % b for _, b, _ in runs],
+                   "prec_bits": [K for _, _, K in runs], "method": args.method,
+                   "panel": [p for p, _ in scheds], "lookahead": [la for _, la in scheds]},
+        "lambda_solves_per_s": len(runs) * args.steps / dt,
+        "lambda_1": lams,
         "roofline": {"bound": "alu", "kernel": kdesc,
                      "achieved": achieved / 1e12, "peak": PEAK_INT_MUL / 1e12,
                      "unit": "Tlimb-MAC/s", "frac": achieved / PEAK_INT_MUL,
-                     "launches": upd_n,
-                     "avg_launch_us": 1e3 * upd_ms / max(upd_n, 1),
-                     "limb_macs_per_launch": macs_per_step / max(upd_n, 1),
-                     "share_of_step": upd_ms / ms_step,
+                     "launches": bulk_n,
+                     "avg_launch_us": 1e3 * bulk_ms / max(bulk_n, 1),
+                     "limb_macs_per_launch": macs_bulk / max(bulk_n, 1),
+                     "work_share": macs_bulk / macs_per_step if macs_per_step else None,
+                     "time_share_of_step": bulk_ms / ms_step,
                      "traffic": traffic, "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + "
                                                           "WRITE_SIZE, copy-calibrated)",
-                     "traffic_source": traffic_src},
+                     "traffic_source": traffic_src,
+                     "all_update_launches": {"launches": upd_n, "ms_per_step": upd_ms,
+                                             "achieved": macs_per_step / (upd_ms * 1e-3) / 1e12 if upd_ms else 0,
+                                             "frac": macs_per_step / (upd_ms * 1e-3) / PEAK_INT_MUL
+                                             if upd_ms else 0}},
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, args.method)

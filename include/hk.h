@@ -67,7 +67,9 @@ typedef enum {
 enum { HK_INVERSE = 0, HK_SECANT = 1 };
 /* flags or-ed into the method argument of hk_smallest_eig */
 enum { HK_FLAG_NO_WORK_COUNT = 0x100,   /* skip the limb-MAC count (report 0)    */
-       HK_FLAG_TIME_UPDATES = 0x200 };  /* time every trailing-update launch      */
+       HK_FLAG_TIME_UPDATES = 0x200,    /* time every trailing-update launch      */
+       HK_FLAG_CERTIFY = 0x400 };       /* prove the inertia bracket (hk_certify
+                                           on both bracket factorisations)       */
 /* panel width p in 1..64 forced for hk_smallest_eig: or HK_FLAG_PANEL(p)
    into the method argument (0: the tuned width, else 4) */
 #define HK_FLAG_PANEL(p) (((p) & 0xff) << 16)
@@ -96,6 +98,12 @@ typedef struct {
                              mode 2)                                          */
   double update_ms;       /* summed device time of those launches (timing on) */
   int lookahead;          /* look-ahead mode hk_factor uses (0, 1, 2)         */
+  int n_bulk_launches;    /* of those, the bulk ones: k_update (the trailing
+                             update, or its columns beyond the next panel
+                             under look-ahead 1), or every k_column launch
+                             (mode 2); the rest are k_update_near launches
+                             (in-panel updates, the next panel's columns)     */
+  double bulk_ms;         /* summed device time of the bulk launches          */
 } hk_info;
 
 typedef struct {
@@ -110,6 +118,14 @@ typedef struct {
   double t_factor_s, t_solve_s, t_total_s;
   int update_launches;    /* update-kernel launches (HK_FLAG_TIME_UPDATES)    */
   double update_ms;       /* their summed device time                         */
+  int bulk_launches;      /* of those, the bulk launches (hk_info)            */
+  double bulk_ms;         /* their summed device time                         */
+  double limb_macs_bulk;  /* the share of limb_macs the bulk launches carry   */
+  int certified;          /* HK_FLAG_CERTIFY: 1 when the bracket is proved    */
+  double certify_margin_bits;  /* least log2(|pivot| / radius) of the two
+                             bracket factorisations (negative: short)         */
+  int certify_bits;       /* HK_FLAG_CERTIFY and not proved: the precision at
+                             which the margin would reach 16 bits             */
   hk_mpf lambda;          /* lambda_1 in binary (sign 0: none); its digits
                              point at lambda_words of this same report       */
   uint32_t lambda_words[HK_LAMBDA_WORDS];
@@ -180,6 +196,24 @@ hk_status hk_matrix_destroy(hk_matrix m);
 const char* hk_last_error(void);
 hk_status hk_matrix_info(hk_matrix m, hk_info* out);
 
+/* Rigorous inertia of the current factorisation of m (the sign checks of
+   "Interval Verification" made rigorous, in midpoint-radius form): the
+   fixed-point factors are the midpoints; a radius per entry bounds the
+   distance to the same quantity of the exact elimination of the true
+   matrix (exact moments, exact shift): 2^-(K+1) for the correctly rounded
+   moments, plus the rounding of every C and L entry carried through the
+   updates, each operation rounded up.  A pivot is certified when its
+   magnitude exceeds its radius; *certified = 1 when every pivot is (then
+   *n_negative is the exact inertia of M - xI), 0 when one is not, or a
+   pivot before the last is negative (later radii are then unbounded).
+   *min_margin_bits (may be NULL): the least log2(|pivot| / radius);
+   margin_bits (N doubles, may be NULL): per pivot.  The radii grow with the
+   elimination's cancellation, so certification needs K above what the
+   plain inertia check needs (a missing bit of margin costs two of K).
+   Overwrites the working triangle (the factors stay); synchronises s. */
+hk_status hk_certify(hk_matrix m, hipStream_t s, int* n_negative, int* certified, double* min_margin_bits,
+                     double* margin_bits);
+
 /* Tuning: columns per trailing update (panel width, >= 1). */
 hk_status hk_set_panel(hk_matrix m, int panel);
 /* Look-ahead ("The LDL^T Determinant Algorithm", parallel version: the next
@@ -220,6 +254,22 @@ hk_status hk_vec_import(hk_matrix m, int n, const int32_t* slen, const int64_t* 
 int64_t hk_vec_export(hk_matrix m, const void* dev_vec, int n, int32_t* slen, int64_t* off,
                       uint32_t* dig, int64_t dig_cap, hipStream_t s);
 
+/* ---- measurement ---------------------------------------------------------
+   Issue rate of one VALU instruction kind on the running GPU, measured:
+   every lane of a grid that fills every SIMD (8 waves each) runs 16
+   independent chains of 4096 steps of it, so the rate is the issue rate
+   rather than the latency.  It is the denominator of the update kernel's
+   fraction of the integer-multiply peak (the update multiplies 29-bit digits
+   with HK_RATE_MAD_I64_I32, int64 += int32 x int32).  dev_buf: device
+   buffer of at least hk_mul_rate_buffer_bytes() bytes (the chains' results
+   and per-wave clock samples).  *per_s: lane operations per second (one
+   timed launch after a warm-up launch); *clock_hz (may be NULL): the shader
+   clock during the timed launch, from each wave's cycle counter against
+   the constant-rate counter.  Synchronises s. */
+enum { HK_RATE_MAD_I64_I32 = 0, HK_RATE_MAD_U64_U32 = 1, HK_RATE_MAD_U32_U24 = 2, HK_RATE_FMA_F64 = 3 };
+size_t hk_mul_rate_buffer_bytes(void);
+hk_status hk_mul_rate(int kind, void* dev_buf, size_t buf_bytes, hipStream_t s, double* per_s, double* clock_hz);
+
 /* ---- batched form ------------------------------------------------------
    Many instances of uneven (N, beta, K) factored together: every kernel of
    the factorisation covers all instances of the batch in one launch (work
@@ -230,7 +280,15 @@ int64_t hk_vec_export(hk_matrix m, const void* dev_vec, int n, int32_t* slen, in
    lockstep, then the inertia bracket of "Interval Verification".  Callers
    that repeat the same batch shapes may tune the panel width once with
    hk_autotune. */
-typedef struct { int N; hk_rational beta; int prec_bits; } hk_instance;
+typedef struct {
+  int N;
+  hk_rational beta;
+  int prec_bits;
+  int method;                /* hk_eig_batched: HK_SECANT, or HK_INVERSE (0, what
+                                a zero-initialised instance asks for)       */
+  const hk_mpf* shift_hint;  /* HK_INVERSE: the shift of its factorisation
+                                (NULL: 0); ignored elsewhere                 */
+} hk_instance;
 
 typedef struct {
   hk_status status;
@@ -258,7 +316,12 @@ typedef struct {
 /* Device bytes for a batch (one buffer for all instances). 0 if invalid. */
 size_t hk_batch_workspace_bytes(const hk_instance* inst, int count);
 
-/* lambda_1 of every instance.  panel = 0 takes the width from the tuning
+/* lambda_1 of every instance by its method: HK_SECANT instances run the
+   paper's Secant iteration in lockstep (one batched factorisation per
+   step); HK_INVERSE instances are factored once at their shift hint (halved
+   while a pivot is <= 0, at most three times, then 0) and run inverse
+   iteration together; then the inertia bracket ("Interval Verification")
+   for all.  panel = 0 takes the width from the tuning
    cache named by the environment variable HK_TUNE_CACHE when it has an entry
    for this batch shape, else 4.  out[count] receives the per-instance
    results; the call returns HK_OK if every instance succeeded (otherwise the

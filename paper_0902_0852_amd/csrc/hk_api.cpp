@@ -219,8 +219,8 @@ void mp_to_digits(const MP& v, int32_t* out, int n) { to_digits(v, out, n); }
 // With evs != NULL every update launch records its own start and end on a
 // pair of HIP events.
 hipError_t enqueue_factor(const BatchView& B, int b, int mode, hipStream_t s, hipStream_t s2,
-                          std::vector<std::pair<hipEvent_t, hipEvent_t>>* evs,
-                          std::vector<hipEvent_t>* pool, size_t* evi, int* n_update) {
+                          std::vector<TimedLaunch>* evs, std::vector<hipEvent_t>* pool, size_t* evi,
+                          int* n_update, int* n_bulk) {
   // one pool of (timing-capable) events for both the per-launch timing and
   // the look-ahead fork/join points
   auto get_ev = [&]() -> hipEvent_t {
@@ -235,8 +235,9 @@ hipError_t enqueue_factor(const BatchView& B, int b, int mode, hipStream_t s, hi
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (evs) { e0 = get_ev(); e1 = get_ev(); }
     hipError_t e = launch_update(B, pc, b, j, rd, st, e0 && e1 ? e0 : nullptr, e0 && e1 ? e1 : nullptr);
-    if (e == hipSuccess && e0 && e1) evs->push_back({e0, e1});
+    if (e == hipSuccess && e0 && e1) evs->push_back({e0, e1, update_is_bulk(j)});
     if (n_update) (*n_update)++;
+    if (n_bulk && update_is_bulk(j)) (*n_bulk)++;
     return e;
   };
   hipError_t e = launch_expand(B, s);
@@ -246,8 +247,9 @@ hipError_t enqueue_factor(const BatchView& B, int b, int mode, hipStream_t s, hi
       hipEvent_t e0 = nullptr, e1 = nullptr;
       if (evs) { e0 = get_ev(); e1 = get_ev(); }
       if (e == hipSuccess) e = launch_column(B, c, s, e0 && e1 ? e0 : nullptr, e0 && e1 ? e1 : nullptr);
-      if (e == hipSuccess && e0 && e1) evs->push_back({e0, e1});
+      if (e == hipSuccess && e0 && e1) evs->push_back({e0, e1, true});
       if (n_update) (*n_update)++;
+      if (n_bulk) (*n_bulk)++;
     }
     return e;
   }
@@ -420,6 +422,39 @@ bool shift_fixed(const hk_mpf& x, int K, MP& out) {
   return true;
 }
 
+// the look-ahead mode hk_factor runs: the set or tuned one
+int effective_lookahead(const hk_matrix_s* m) { return lookahead_mode(m->lookahead, m->P.N, m->P.maxW); }
+
+hipError_t limb_macs_split(hk_matrix m, int b, int mode, hipStream_t s, double* total, double* bulk) {
+  const Plan& P = m->P;
+  hipError_t e = launch_bits(P, m->D, s);
+  std::vector<int32_t> bc(P.ntri), bl(P.ntri);
+  if (e == hipSuccess) e = hipMemcpyAsync(bc.data(), m->D.b32C, sizeof(int32_t) * P.ntri, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(bl.data(), m->D.b32L, sizeof(int32_t) * P.ntri, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  const int N = P.N;
+  if (mode == 2) b = 1;
+  double tot = 0, blk = 0;
+  for (int k = 0; k < N - 1; k++) {
+    // the panel of column k, and the first column of its bulk launch: the
+    // next panel's columns belong to the near launch in mode 1
+    const int pc = k / b * b, bb = std::min(b, N - pc);
+    const int c_bulk = mode == 2 ? k + 1 : (mode == 1 ? std::min(N, pc + 2 * bb) : pc + bb);
+    // sum_{c>k} nC(k,c) * sum_{r>=c} nL(k,r)
+    double suf = 0;
+    for (int r = N - 1; r > k; r--) {
+      suf += bl[tri_index(N, k, r)];
+      const double w = (double)bc[tri_index(N, k, r)] * suf;
+      tot += w;
+      if (r >= c_bulk) blk += w;
+    }
+  }
+  *total = tot;
+  *bulk = blk;
+  return hipSuccess;
+}
+
 }  // namespace hk
 
 extern "C" {
@@ -463,6 +498,7 @@ hk_status hk_matrix_info(hk_matrix m, hk_info* o) {
   o->panel = m->panel; o->ws_bytes = P.total;
   o->vec_bytes = sizeof(int32_t) * (size_t)P.N * P.VW;
   o->n_update_launches = m->n_update; o->update_ms = m->update_ms;
+  o->n_bulk_launches = m->n_bulk; o->bulk_ms = m->bulk_ms;
   o->lookahead = lookahead_mode(m->lookahead, P.N, P.maxW);
   return HK_OK;
 }
@@ -482,14 +518,18 @@ hk_status hk_factor(hk_matrix m, hk_mpf shift, int inertia_mode, hipStream_t s, 
   const int N = P.N, b = m->panel;
   m->n_update = 0;
   m->update_ms = 0;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> evs;
+  m->n_bulk = 0;
+  m->bulk_ms = 0;
+  std::vector<TimedLaunch> evs;
   if (m->timing) {
+    // launched one by one on s (per-launch timing)
     size_t evi = 0;
     HK_HIP(launch_fill32(D.flags, 16, 0, s));
     HK_HIP(launch_fill32(D.flags + 1, 1, INT_MAX, s));
-    const int la = lookahead_mode(m->lookahead, P.N, P.maxW);
+    const int la = effective_lookahead(m);
     if (!m->s2 && la == 1) HK_HIP(hipStreamCreateWithFlags(&m->s2, hipStreamNonBlocking));
-    HK_HIP(enqueue_factor(m->B, b, la, s, la == 1 ? m->s2 : nullptr, &evs, &m->ev, &evi, &m->n_update));
+    HK_HIP(enqueue_factor(m->B, b, la, s, la == 1 ? m->s2 : nullptr, m->timing ? &evs : nullptr, &m->ev, &evi,
+                          &m->n_update, &m->n_bulk));
   } else {
     const int la = lookahead_mode(m->lookahead, P.N, P.maxW);
     if (!m->gexec || m->gpanel != b || m->gla != la) {
@@ -497,13 +537,13 @@ hk_status hk_factor(hk_matrix m, hk_mpf shift, int inertia_mode, hipStream_t s, 
       if (m->graph) { (void)hipGraphDestroy(m->graph); m->graph = nullptr; }
       if (!m->gcap) HK_HIP(hipStreamCreateWithFlags(&m->gcap, hipStreamNonBlocking));
       HK_HIP(hipStreamBeginCapture(m->gcap, hipStreamCaptureModeThreadLocal));
-      int nu = 0;
+      int nu = 0, nbk = 0;
       hipError_t e = launch_fill32(D.flags, 16, 0, m->gcap);
       if (e == hipSuccess) e = launch_fill32(D.flags + 1, 1, INT_MAX, m->gcap);
       size_t evi = 0;
       if (e == hipSuccess && !m->gcap2 && la == 1) e = hipStreamCreateWithFlags(&m->gcap2, hipStreamNonBlocking);
       if (e == hipSuccess)
-        e = enqueue_factor(m->B, b, la, m->gcap, la == 1 ? m->gcap2 : nullptr, nullptr, &m->gev, &evi, &nu);
+        e = enqueue_factor(m->B, b, la, m->gcap, la == 1 ? m->gcap2 : nullptr, nullptr, &m->gev, &evi, &nu, &nbk);
       hipGraph_t g = nullptr;
       const hipError_t e2 = hipStreamEndCapture(m->gcap, &g);
       m->graph = g;
@@ -513,16 +553,19 @@ hk_status hk_factor(hk_matrix m, hk_mpf shift, int inertia_mode, hipStream_t s, 
       m->gpanel = b;
       m->gla = la;
       m->g_nupdate = nu;
+      m->g_nbulk = nbk;
     }
     HK_HIP(hipGraphLaunch(m->gexec, s));
     m->n_update = m->g_nupdate;
+    m->n_bulk = m->g_nbulk;
   }
   HK_HIP(hipMemcpyAsync(m->flags_host, D.flags, sizeof(int32_t) * 16, hipMemcpyDeviceToHost, s));
   HK_HIP(hipStreamSynchronize(s));
-  for (auto& pr : evs) {
+  for (auto& tl : evs) {
     float ms = 0;
-    HK_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
+    HK_HIP(hipEventElapsedTime(&ms, tl.t0, tl.t1));
     m->update_ms += ms;
+    if (tl.bulk) m->bulk_ms += ms;
   }
   m->factored = true;
   const int fb = m->flags_host[1] == INT_MAX ? -1 : m->flags_host[1];
@@ -588,23 +631,8 @@ int64_t hk_factor_export(hk_matrix m, int kind, int c0, int c1, int32_t* slen, i
 hk_status hk_factor_limb_macs(hk_matrix m, hipStream_t s, double* limb_macs) {
   if (!m || !limb_macs) return fail(HK_EINVAL, "null argument");
   if (!m->factored) return fail(HK_EINVAL, "no factorisation");
-  const Plan& P = m->P;
-  HK_HIP(launch_bits(P, m->D, s));
-  std::vector<int32_t> bc(P.ntri), bl(P.ntri);
-  HK_HIP(hipMemcpyAsync(bc.data(), m->D.b32C, sizeof(int32_t) * P.ntri, hipMemcpyDeviceToHost, s));
-  HK_HIP(hipMemcpyAsync(bl.data(), m->D.b32L, sizeof(int32_t) * P.ntri, hipMemcpyDeviceToHost, s));
-  HK_HIP(hipStreamSynchronize(s));
-  const int N = P.N;
-  double total = 0;
-  for (int k = 0; k < N - 1; k++) {
-    // sum_{c>k} nC(k,c) * sum_{r>=c} nL(k,r)
-    double suf = 0;
-    for (int r = N - 1; r > k; r--) {
-      suf += bl[tri_index(N, k, r)];
-      total += (double)bc[tri_index(N, k, r)] * suf;
-    }
-  }
-  *limb_macs = total;
+  double bulk = 0;
+  HK_HIP(limb_macs_split(m, m->panel, effective_lookahead(m), s, limb_macs, &bulk));
   return HK_OK;
 }
 

@@ -262,6 +262,9 @@ hk_status hk_eig_batched(const hk_instance* inst, int count, int digits, int pan
   auto t0 = std::chrono::steady_clock::now();
   if (!inst || !out || count < 1) return dfail_b(HK_EINVAL, "bad arguments");
   if (digits < 2 || digits > 150) return dfail_b(HK_EINVAL, "digits must be in [2, 150]");
+  for (int i = 0; i < count; i++)
+    if (inst[i].method != HK_INVERSE && inst[i].method != HK_SECANT)
+      return dfail_b(HK_EINVAL, "instance " + std::to_string(i) + ": unknown method");
   Batch bt;
   hk_status st = build_batch(bt, inst, count, dev_ws, ws_bytes, s);
   if (st != HK_OK) return st;
@@ -271,20 +274,21 @@ hk_status hk_eig_batched(const hk_instance* inst, int count, int digits, int pan
     bt.lookahead = sc.lookahead;
   }
   auto t1 = std::chrono::steady_clock::now();
-  std::vector<SecantRun*> sm(count);
+  std::vector<SecantRun*> sm(count, nullptr);
   for (int i = 0; i < count; i++) {
     const Plan& P = bt.mats[i]->P;
-    sm[i] = secant_new(P.N, P.K, P.h, digits, 200);
+    if (inst[i].method == HK_SECANT) sm[i] = secant_new(P.N, P.K, P.h, digits, 200);
     memset(&out[i], 0, sizeof(hk_result));
   }
-  std::vector<MP> x(count);
-  std::vector<int> act(count), inertia(count), nfact(count, 0);
+  std::vector<MP> x(count), lam(count);
+  std::vector<int> act(count), inertia(count), nfact(count, 0), done(count, 0);
   std::vector<BEval> ev;
+  // the paper's Secant iteration, every Secant instance in lockstep
   st = HK_OK;
   for (int round = 0; round < 400 && st == HK_OK; round++) {
     bool any = false;
     for (int i = 0; i < count; i++) {
-      act[i] = secant_next(sm[i], x[i], inertia[i]) ? 1 : 0;
+      act[i] = sm[i] && secant_next(sm[i], x[i], inertia[i]) ? 1 : 0;
       any |= act[i] != 0;
     }
     if (!any) break;
@@ -295,26 +299,71 @@ hk_status hk_eig_batched(const hk_instance* inst, int count, int digits, int pan
       secant_feed(sm[i], ev[i].st, ev[i].nneg, ev[i].first_bad, ev[i].piv);
     }
   }
-  // inertia bracket for every converged instance
-  std::vector<MP> lam(count), xlo(count), xhi(count);
-  std::vector<std::string> dec(count);
-  std::vector<int> done(count, 0);
   for (int i = 0; i < count && st == HK_OK; i++) {
+    if (!sm[i]) continue;
     hk_status si;
     std::string err;
-    if (secant_done(sm[i], lam[i], si, err)) {
-      done[i] = 1;
-      decimal_bracket(lam[i], bt.mats[i]->P.K, digits, xlo[i], xhi[i], dec[i]);
-    } else {
-      out[i].status = si;
+    if (secant_done(sm[i], lam[i], si, err)) done[i] = 1;
+    else out[i].status = si;
+  }
+  // inverse iteration (not in the paper) for the other instances: one
+  // factorisation at the shift hint (halved while a pivot is <= 0, at most
+  // three times, then 0) or at 0, then all of them stepped together
+  std::vector<int> inv(count, 0);
+  int ninv = 0;
+  for (int i = 0; i < count; i++) {
+    inv[i] = inst[i].method == HK_INVERSE;
+    ninv += inv[i];
+    x[i] = MP();
+    if (inv[i] && inst[i].shift_hint && !shift_fixed(*inst[i].shift_hint, bt.mats[i]->P.K, x[i]))
+      st = dfail_b(HK_EINVAL, "instance " + std::to_string(i) + ": shift hint has more than K fractional bits");
+  }
+  std::vector<int> solves(count, 0);
+  if (ninv > 0 && st == HK_OK) {
+    std::vector<int> ok(count, 0), halv(count, 0), a2 = inv;
+    for (int attempt = 0; attempt < 5 && st == HK_OK; attempt++) {
+      st = factor_batch(bt, x, a2, s, ev, false);
+      bool again = false;
+      for (int i = 0; i < count && st == HK_OK; i++) {
+        if (!a2[i]) continue;
+        nfact[i]++;
+        const bool above = ev[i].st == HK_ENOTSPD || (ev[i].st == HK_OK && ev[i].first_bad >= 0);
+        if (above && !x[i].is_zero()) {
+          x[i] = halv[i] < 3 ? shr_mag(x[i], 1) : MP();
+          halv[i]++;
+          again = true;
+        } else {
+          a2[i] = 0;
+          ok[i] = !above && ev[i].st == HK_OK;
+          if (!ok[i]) out[i].status = above ? HK_ENOTSPD : ev[i].st;
+        }
+      }
+      if (!again) break;
+    }
+    std::vector<MP> li;
+    std::vector<hk_status> ist;
+    std::vector<int> iters;
+    double ts = 0;
+    if (st == HK_OK) st = batch_inverse(bt, x, ok, digits, 400, s, li, ist, iters, ts);
+    for (int i = 0; i < count && st == HK_OK; i++) {
+      if (!ok[i]) continue;
+      solves[i] = iters[i];
+      if (ist[i] == HK_OK) { lam[i] = li[i]; done[i] = 1; }
+      else out[i].status = ist[i];
     }
   }
+  // the inertia bracket of "Interval Verification" for every converged instance
+  std::vector<MP> xlo(count), xhi(count);
+  std::vector<std::string> dec(count);
+  for (int i = 0; i < count && st == HK_OK; i++)
+    if (done[i]) decimal_bracket(lam[i], bt.mats[i]->P.K, digits, xlo[i], xhi[i], dec[i]);
   std::vector<BEval> elo, ehi;
   if (st == HK_OK) st = factor_batch(bt, xlo, done, s, elo, false);
   if (st == HK_OK) st = factor_batch(bt, xhi, done, s, ehi, false);
   hk_status first = st;
   for (int i = 0; i < count; i++) {
     out[i].factorizations = nfact[i] + (done[i] ? 2 : 0);
+    out[i].solves = solves[i];
     out[i].bits_used = bt.mats[i]->P.K;
     out[i].path = 0;
     if (st == HK_OK && done[i]) {
@@ -327,7 +376,7 @@ hk_status hk_eig_batched(const hk_instance* inst, int count, int digits, int pan
       lambda_mpf(lam[i], bt.mats[i]->P.K, &out[i].lambda, out[i].lambda_words);
     }
     if (first == HK_OK && out[i].status != HK_OK) first = out[i].status;
-    secant_delete(sm[i]);
+    if (sm[i]) secant_delete(sm[i]);
   }
   if (rep) {
     rep->panel = bt.panel;

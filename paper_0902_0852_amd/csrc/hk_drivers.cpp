@@ -105,8 +105,14 @@ struct DriverCtx {
   double t_factor = 0;
   double t_solve = 0;
   bool count_macs = true;
+  bool certify = false;       // rigorous inertia of the bracket factorisations
+  int certified = 0;
+  double certify_margin = 0;
   int upd_launches = 0;
   double upd_ms = 0;
+  int bulk_launches = 0;
+  double bulk_ms = 0;
+  double limb_macs_bulk = 0;
 };
 
 hk_status inverse_driver(DriverCtx& cx, const hk_mpf* shift_hint, int tol, int max_iter, MP& lam,
@@ -122,11 +128,19 @@ static Eval evaluate(DriverCtx& cx, const MP& x, int inertia_mode) {
   cx.nfact++;
   {
     hk_info inf;
-    if (hk_matrix_info(cx.m, &inf) == HK_OK) { cx.upd_launches += inf.n_update_launches; cx.upd_ms += inf.update_ms; }
+    if (hk_matrix_info(cx.m, &inf) == HK_OK) {
+      cx.upd_launches += inf.n_update_launches;
+      cx.upd_ms += inf.update_ms;
+      cx.bulk_launches += inf.n_bulk_launches;
+      cx.bulk_ms += inf.bulk_ms;
+    }
   }
   if (ev.st == HK_OK && cx.count_macs) {
-    double lm = 0;
-    if (hk_factor_limb_macs(cx.m, cx.s, &lm) == HK_OK) cx.limb_macs += lm;
+    double lm = 0, lb = 0;
+    if (limb_macs_split(cx.m, cx.m->panel, effective_lookahead(cx.m), cx.s, &lm, &lb) == hipSuccess) {
+      cx.limb_macs += lm;
+      cx.limb_macs_bulk += lb;
+    }
   }
   if (ev.st == HK_OK) {
     hk_status st = pivots_host(cx.m, cx.s, ev.piv);
@@ -396,10 +410,26 @@ hk_status verify_bracket(DriverCtx& cx, const MP& lam_fixed, int digits, std::st
   MP xhi = decimal_to_fixed(add(D, MP::from_u64(1)), e, K, true);
   Eval a = evaluate(cx, xlo, 1);
   if (a.st != HK_OK && a.st != HK_ENOTSPD) return a.st;
+  int ca = 0, cb = 0, na = 0, nb = 0;
+  double ma = -INFINITY, mb = -INFINITY;
+  if (cx.certify && a.st == HK_OK) {
+    const hk_status st = certify_factor(cx.m, cx.s, a.piv, &na, &ca, &ma, nullptr);
+    if (st != HK_OK) return st;
+  }
   Eval b = evaluate(cx, xhi, 1);
   if (b.st != HK_OK && b.st != HK_ENOTSPD) return b.st;
   ok = a.st == HK_OK && a.nneg == 0 && a.first_bad < 0 && b.st == HK_OK && b.nneg == 1 &&
        b.first_bad == cx.m->P.N - 1;
+  if (cx.certify && b.st == HK_OK) {
+    const hk_status st = certify_factor(cx.m, cx.s, b.piv, &nb, &cb, &mb, nullptr);
+    if (st != HK_OK) return st;
+  }
+  if (cx.certify) {
+    // proved: all pivots certified, none negative at the lower point, only
+    // the last one negative at the upper point
+    cx.certified = ok && ca && cb && na == 0 && nb == 1;
+    cx.certify_margin = std::min(ma, mb);
+  }
   return HK_OK;
 }
 
@@ -620,9 +650,12 @@ int64_t hk_vec_export(hk_matrix m, const void* dev_vec, int n, int32_t* slen, in
   return total;
 }
 
-hk_status hk_smallest_eig(int N, hk_rational beta, int prec_bits, int method, int digits,
-                          const hk_mpf* shift_hint, void* dev_ws, size_t ws_bytes, hipStream_t s,
-                          char* out_decimal, size_t out_len, hk_report* rep) {
+}  // extern "C"
+
+// hk_smallest_eig's body
+static hk_status smallest_eig_impl(int N, hk_rational beta, int prec_bits, int method, int digits,
+                                   const hk_mpf* shift_hint, void* dev_ws, size_t ws_bytes, hipStream_t s,
+                                   char* out_decimal, size_t out_len, hk_report* rep) {
   auto t0 = std::chrono::steady_clock::now();
   if (rep) { memset(rep, 0, sizeof(*rep)); rep->bits_used = prec_bits; }
   if (digits < 2 || digits > 150) return dfail(HK_EINVAL, "digits must be in [2, 150]");
@@ -636,6 +669,7 @@ hk_status hk_smallest_eig(int N, hk_rational beta, int prec_bits, int method, in
   cx.m = m;
   cx.s = s;
   cx.count_macs = !(flags & HK_FLAG_NO_WORK_COUNT);
+  cx.certify = (flags & HK_FLAG_CERTIFY) != 0;
   if (flags & HK_FLAG_TIME_UPDATES) hk_set_timing(m, 1);
   const int forced_panel = (flags >> 16) & 0xff;
   if (forced_panel > 0) hk_set_panel(m, forced_panel);
@@ -670,9 +704,28 @@ hk_status hk_smallest_eig(int N, hk_rational beta, int prec_bits, int method, in
     rep->t_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     rep->update_launches = cx.upd_launches;
     rep->update_ms = cx.upd_ms;
+    rep->certified = cx.certified;
+    rep->certify_margin_bits = cx.certify_margin;
+    // the precision at which the same bracket would be proved: radii scale
+    // as 2^-h, so each missing bit of margin costs two bits of K
+    rep->certify_bits = !cx.certify || cx.certified ? prec_bits
+        : !std::isfinite(cx.certify_margin) ? 0
+        : (int)(64 * std::ceil((prec_bits + 2.0 * (std::max(0.0, -cx.certify_margin) + 16.0)) / 64.0));
+    rep->bulk_launches = cx.bulk_launches;
+    rep->bulk_ms = cx.bulk_ms;
+    rep->limb_macs_bulk = cx.limb_macs_bulk;
   }
   hk_matrix_destroy(m);
   return st;
+}
+
+extern "C" {
+
+hk_status hk_smallest_eig(int N, hk_rational beta, int prec_bits, int method, int digits,
+                          const hk_mpf* shift_hint, void* dev_ws, size_t ws_bytes, hipStream_t s,
+                          char* out_decimal, size_t out_len, hk_report* rep) {
+  return smallest_eig_impl(N, beta, prec_bits, method, digits, shift_hint, dev_ws, ws_bytes, s, out_decimal,
+                           out_len, rep);
 }
 
 }  // extern "C"

@@ -131,6 +131,9 @@ hipError_t launch_expand(const BatchView& B, hipStream_t s);
 // UPD_NEAR / UPD_FAR: the trailing update split into the next panel's columns
 // [pc + b, pc + 2b) and the rest (look-ahead)
 constexpr int UPD_NEAR = -1, UPD_FAR = -2;
+// the launches of k_update (the bulk of the update work: j = 0 and UPD_FAR)
+// against those of k_update_near (in-panel and UPD_NEAR, critical path)
+inline bool update_is_bulk(int j) { return j == 0 || j == UPD_FAR; }
 hipError_t launch_update(const BatchView& B, int pc, int b, int j, int rd, hipStream_t s,
                          hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 hipError_t launch_fdiv(const BatchView& B, int c, int rd, hipStream_t s);
@@ -143,10 +146,21 @@ int64_t update_items(const Plan& P, int pc, int b, int j);
 // next panel's columns are updated on s, on the critical path, the rest on
 // s2 concurrently with the next panel (look-ahead); s2 is joined into s at
 // the end.  evs: optional HIP-event pairs around every update launch.
+struct TimedLaunch { hipEvent_t t0, t1; bool bulk; };
 hipError_t enqueue_factor(const BatchView& B, int b, int mode, hipStream_t s, hipStream_t s2,
-                          std::vector<std::pair<hipEvent_t, hipEvent_t>>* evs,
-                          std::vector<hipEvent_t>* pool, size_t* evi, int* n_update);
+                          std::vector<TimedLaunch>* evs, std::vector<hipEvent_t>* pool, size_t* evi,
+                          int* n_update, int* n_bulk = nullptr);
+// algorithmic limb MACs of the last factorisation of m: all of them, and the
+// share its bulk update launches carried under the schedule (panel b, look-
+// ahead mode) it ran with (mode 2: the column launches carry all of it)
+hipError_t limb_macs_split(hk_matrix m, int b, int mode, hipStream_t s, double* total, double* bulk);
+int effective_lookahead(const hk_matrix_s* m);
 hipError_t launch_bits(const Plan& P, const DevPtrs& D, hipStream_t s);
+// rigorous inertia of m's current factorisation (hk_certify.cpp): the exact
+// pivots piv (h fractional bits) with the radii of the midpoint-radius
+// enclosure; margins (N, may be NULL) get log2(|d_k| / radius_k)
+hk_status certify_factor(hk_matrix m, hipStream_t s, const std::vector<MP>& piv, int* n_negative,
+                         int* certified, double* min_margin, double* margins);
 
 // Everything the solve and inverse-iteration kernels need of one instance;
 // the batched launches take a device array of these (one per instance).
@@ -198,6 +212,8 @@ struct hk_matrix_s {
   int timing = 0;
   int n_update = 0;
   double update_ms = 0;
+  int n_bulk = 0;            // k_update launches (bulk) of the last hk_factor
+  double bulk_ms = 0;        // their summed device time (timing on)
   int32_t flags_host[16];
   int gbits = 0;            // solve guard bits from the actual largest moment
   hk::InstDesc desc_host;
@@ -209,7 +225,7 @@ struct hk_matrix_s {
   hipStream_t gcap = nullptr, gcap2 = nullptr, s2 = nullptr;   // capture streams; look-ahead stream
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
-  int gpanel = 0, gla = -1, g_nupdate = 0;
+  int gpanel = 0, gla = -1, g_nupdate = 0, g_nbulk = 0;
   hk::SweepArgs sweep;        // host copy of the solve arguments (kept alive for the upload)
   hipGraph_t sgraph = nullptr;   // one captured solve, replayed by hk_solve
   hipGraphExec_t sgexec = nullptr;

@@ -221,23 +221,31 @@ __device__ __forceinline__ void accum_block(int64_t* acc, int& cnt, const int32_
   }
 }
 
-// A's 16 digits of block q (stride as) -= acc, with the pending carry into
-// this block (kin, NULL for block 0) folded in; the carry out goes to kout
-// (NULL for the top block, where it must vanish).
-// All 16 digits (and the carry) are loaded before the first store, so the
-// loads are in flight together rather than one after another.
-__device__ __forceinline__ void apply_block(const int64_t* acc, GLOBAL int32_t* Ap, int64_t as,
-                                            const GLOBAL int64_t* kin, GLOBAL int64_t* kout,
+// A's 16 digits of block q -= acc, with the pending carry into this block
+// (kin, NULL for block 0) folded in; the carry out goes to kout (NULL for the
+// top block, where it must vanish).  The digits are addressed as in the
+// multiply loop: a buffer descriptor over the column's digit planes (Acol,
+// abytes), the lane's row as the vector offset and the digit plane as a
+// scalar offset, so no 64-bit address is held per digit.  All 16 digits
+// (and the carry) are loaded before the first store, so the loads are in
+// flight together rather than one after another.
+__device__ __forceinline__ void apply_block(const int64_t* acc, const int32_t* Acol, int64_t abytes, int lr,
+                                            int R, int q, const GLOBAL int64_t* kin, GLOBAL int64_t* kout,
                                             GLOBAL int32_t* flags) {
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)Acol, (short)0, (int)min(abytes, (int64_t)0x7fffffff), 0x00020000);
+  const int vo = lr * 4;
+  const int pb = R * 4;
+  const int sb = WB * q * pb;
   int32_t a[WB];
 #pragma unroll
-  for (int m = 0; m < WB; m++) a[m] = Ap[(int64_t)m * as];
+  for (int m = 0; m < WB; m++) a[m] = __builtin_amdgcn_raw_buffer_load_b32(rs, vo, sb + m * pb, 0);
   int64_t v = kin ? *kin : 0;
 #pragma unroll
   for (int m = 0; m < WB; m++) {
     v += (int64_t)a[m] - acc[m];
     const int32_t d = balanced29(v);
-    Ap[(int64_t)m * as] = d;
+    __builtin_amdgcn_raw_buffer_store_b32(d, rs, vo, sb + m * pb, 0);
     v = (v - d) >> DB;
   }
   v -= acc[WB];
@@ -329,13 +337,22 @@ __device__ __forceinline__ void update_item(const InstDesc* __restrict__ desc, i
   if (!active) return;
   const int lr = r - c;
   int64_t* Kcol = I.Kc + cc.koff;
-  apply_block(acc, gp(I.A + cc.aoff + (int64_t)(WB * q) * cc.R + lr), cc.R,
+  apply_block(acc, uptr(I.A + cc.aoff), (int64_t)cc.W * cc.R * 4, lr, cc.R, q,
               q > 0 ? gp(Kcol + ((int64_t)rd * cc.nb + q) * cc.R + lr) : nullptr,
               q + 1 < cc.nb ? gp(Kcol + ((int64_t)(rd ^ 1) * cc.nb + q + 1) * cc.R + lr) : nullptr, gp(I.flags));
 }
 
-__global__ void __launch_bounds__(256) k_update(const InstDesc* __restrict__ desc, int count, int pc,
+// The bulk of the update work: the trailing update of a panel (j = 0), or
+// its columns beyond the next panel (UPD_FAR, look-ahead).
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) k_update(const InstDesc* __restrict__ desc, int count, int pc,
                                                 int b, int j, int rd) {
+  update_item(desc, count, pc, b, j, rd, blockIdx.x * 4 + uni(threadIdx.x >> 6));
+}
+// The small launches on the critical path: the in-panel updates (j > 0) and
+// the next panel's columns (UPD_NEAR, look-ahead); the same items under a
+// symbol of their own, so that they time and profile apart from the bulk.
+__global__ void __launch_bounds__(256) k_update_near(const InstDesc* __restrict__ desc, int count, int pc,
+                                                     int b, int j, int rd) {
   update_item(desc, count, pc, b, j, rd, blockIdx.x * 4 + uni(threadIdx.x >> 6));
 }
 
@@ -1399,7 +1416,7 @@ __device__ __forceinline__ void vupdate_item(const ColInfo* __restrict__ cols, i
     accum_block(a, cnt, ub + (int64_t)k * VW, nC, Lp, nbytes, lo, P, nL, q);
   }
   if (!active) return;
-  apply_block(a, gp(acc + (int64_t)(WB * q) * Npad + i), Npad,
+  apply_block(a, uptr(acc), (int64_t)nbA * WB * Npad * 4, i, Npad, q,
               q > 0 ? gp(kc + ((int64_t)rd * nbA + q) * Npad + i) : nullptr,
               q + 1 < nbA ? gp(kc + ((int64_t)(rd ^ 1) * nbA + q + 1) * Npad + i) : nullptr, gp(flags));
 }
@@ -1758,11 +1775,12 @@ hipError_t launch_update(const BatchView& B, int pc, int b, int j, int rd, hipSt
   int64_t items = 0;
   for (const Plan* p : B.plans) items += update_items(*p, pc, b, j);
   if (items <= 0) return mark_empty(t0, t1, s);
+  auto kern = update_is_bulk(j) ? k_update : k_update_near;
   if (t0 || t1)
-    hipExtLaunchKernelGGL(k_update, dim3((unsigned)((items + 3) / 4)), dim3(256), 0, s, t0, t1, 0, B.ddesc,
+    hipExtLaunchKernelGGL(kern, dim3((unsigned)((items + 3) / 4)), dim3(256), 0, s, t0, t1, 0, B.ddesc,
                           (int)B.plans.size(), pc, b, j, rd);
   else
-    hipLaunchKernelGGL(k_update, dim3((unsigned)((items + 3) / 4)), dim3(256), 0, s, B.ddesc,
+    hipLaunchKernelGGL(kern, dim3((unsigned)((items + 3) / 4)), dim3(256), 0, s, B.ddesc,
                        (int)B.plans.size(), pc, b, j, rd);
   return hipGetLastError();
 }

@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhk.so")
 
 HK_INVERSE, HK_SECANT = 0, 1
-HK_FLAG_NO_WORK_COUNT, HK_FLAG_TIME_UPDATES = 0x100, 0x200
+HK_FLAG_NO_WORK_COUNT, HK_FLAG_TIME_UPDATES, HK_FLAG_CERTIFY = 0x100, 0x200, 0x400
 
 
 def HK_FLAG_PANEL(p):
@@ -65,7 +65,8 @@ class Info(ctypes.Structure):
                 ("vec_digits", ctypes.c_int), ("solve_guard_bits", ctypes.c_int),
                 ("panel", ctypes.c_int), ("ws_bytes", ctypes.c_size_t),
                 ("vec_bytes", ctypes.c_size_t), ("n_update_launches", ctypes.c_int),
-                ("update_ms", ctypes.c_double), ("lookahead", ctypes.c_int)]
+                ("update_ms", ctypes.c_double), ("lookahead", ctypes.c_int),
+                ("n_bulk_launches", ctypes.c_int), ("bulk_ms", ctypes.c_double)]
 
 
 class Report(ctypes.Structure):
@@ -75,12 +76,15 @@ class Report(ctypes.Structure):
                 ("lambda_dec", ctypes.c_char * 192), ("limb_macs", ctypes.c_double),
                 ("t_factor_s", ctypes.c_double), ("t_solve_s", ctypes.c_double),
                 ("t_total_s", ctypes.c_double), ("update_launches", ctypes.c_int),
-                ("update_ms", ctypes.c_double), ("lambda_mpf", MPF),
+                ("update_ms", ctypes.c_double), ("bulk_launches", ctypes.c_int),
+                ("bulk_ms", ctypes.c_double), ("limb_macs_bulk", ctypes.c_double), ("certified", ctypes.c_int),
+                ("certify_margin_bits", ctypes.c_double), ("certify_bits", ctypes.c_int), ("lambda_mpf", MPF),
                 ("lambda_words", ctypes.c_uint32 * LAMBDA_WORDS)]
 
 
 class Instance(ctypes.Structure):
-    _fields_ = [("N", ctypes.c_int), ("beta", Rational), ("prec_bits", ctypes.c_int)]
+    _fields_ = [("N", ctypes.c_int), ("beta", Rational), ("prec_bits", ctypes.c_int),
+                ("method", ctypes.c_int), ("shift_hint", ctypes.POINTER(MPF))]
 
 
 class Result(ctypes.Structure):
@@ -112,7 +116,7 @@ EXPORTS = ["hk_workspace_bytes", "hk_build_matrix", "hk_factor", "hk_solve", "hk
            "hk_mlp_nparams", "hk_mlp_cache_floats", "hk_mlp_forward", "hk_mlp_backward", "hk_mlp_mse",
            "hk_mlp_adam_step", "hk_mlp_propose", "hk_bracket_batched", "hk_learned_workspace_bytes",
            "hk_eig_learned", "hk_moments_host", "hk_batch_create", "hk_batch_set_schedule",
-           "hk_batch_factor", "hk_batch_instance", "hk_batch_destroy"]
+           "hk_batch_factor", "hk_batch_instance", "hk_batch_destroy", "hk_mul_rate_buffer_bytes", "hk_mul_rate", "hk_certify"]
 
 
 def lib():
@@ -148,6 +152,8 @@ def lib():
         L.hk_set_lookahead.argtypes = [P, I]
         L.hk_factor_export.restype = I64
         L.hk_factor_export.argtypes = [P, I, I, I, P, P, P, I64, P]
+        L.hk_certify.restype = I
+        L.hk_certify.argtypes = [P, P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(ctypes.c_double), P]
         L.hk_factor_limb_macs.restype = I
         L.hk_factor_limb_macs.argtypes = [P, P, ctypes.POINTER(ctypes.c_double)]
         L.hk_vec_import.restype = I
@@ -168,6 +174,10 @@ def lib():
         L.hk_batch_instance.argtypes = [P, I]
         L.hk_batch_destroy.restype = I
         L.hk_batch_destroy.argtypes = [P]
+        L.hk_mul_rate_buffer_bytes.restype = SZ
+        L.hk_mul_rate_buffer_bytes.argtypes = []
+        L.hk_mul_rate.restype = I
+        L.hk_mul_rate.argtypes = [I, P, SZ, P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         L.hk_autotune.restype = I
         L.hk_autotune.argtypes = [P, I, P, SZ, P, ctypes.c_char_p, ctypes.POINTER(I), ctypes.POINTER(I)]
         F = ctypes.c_float
@@ -324,6 +334,15 @@ class _Factors:
     def pivots(self):
         return self.export(2, 0, self.N)
 
+    def certify(self, stream=None):
+        """(n_negative, certified, min margin bits, per-pivot margins) of the
+        current factorisation (hk_certify)."""
+        nn, ok, mm = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        margins = np.zeros(self.N, np.float64)
+        _check(lib().hk_certify(self.h, _stream(stream), ctypes.byref(nn), ctypes.byref(ok), ctypes.byref(mm),
+                                margins.ctypes.data))
+        return nn.value, ok.value, mm.value, margins
+
     def limb_macs(self, stream=None):
         v = ctypes.c_double()
         _check(lib().hk_factor_limb_macs(self.h, _stream(stream), ctypes.byref(v)))
@@ -429,10 +448,10 @@ def smallest_eig(N, beta, K, method=HK_INVERSE, digits=45, shift_fixed=None, str
     return out.value.decode(), d
 
 
-def _instances(insts):
+def _instances(insts, method=HK_SECANT):
     arr = (Instance * len(insts))()
     for i, (N, beta, K) in enumerate(insts):
-        arr[i] = Instance(N, _rational(beta), K)
+        arr[i] = Instance(N, _rational(beta), K, method, None)
     return arr
 
 
@@ -441,12 +460,13 @@ def batch_workspace_bytes(insts):
     return lib().hk_batch_workspace_bytes(ctypes.cast(arr, ctypes.c_void_p), len(insts))
 
 
-def eig_batched(insts, digits=45, panel=0, stream=None, ws=None):
-    """lambda_1 of every (N, beta, K) instance in one batch; returns
-    (list of (status, decimal, verified, factorizations), report dict)."""
+def eig_batched(insts, digits=45, panel=0, stream=None, ws=None, method=HK_SECANT):
+    """lambda_1 of every (N, beta, K) instance in one batch (all by `method`,
+    inverse iteration from 0 for HK_INVERSE); returns (list of (status,
+    decimal, verified, factorizations), report dict)."""
     import torch
     L = lib()
-    arr = _instances(insts)
+    arr = _instances(insts, method)
     nbytes = L.hk_batch_workspace_bytes(ctypes.cast(arr, ctypes.c_void_p), len(insts))
     if nbytes == 0:
         raise HKError(1, L.hk_last_error().decode())
@@ -460,6 +480,7 @@ def eig_batched(insts, digits=45, panel=0, stream=None, ws=None):
     d = {k: getattr(rep, k) for k, _ in BatchReport._fields_}
     d["bits_used"] = [r.bits_used for r in out]
     d["lambda"] = [mpf_value(r.lambda_mpf) for r in out]
+    d["solves"] = [r.solves for r in out]
     d["status"] = st
     if st != 0 and all(r[0] == 0 for r in res):
         _check(st)
@@ -525,6 +546,21 @@ class Batch:
 
     def member(self, i):
         return BatchMember(self, i, self.insts[i][0])
+
+
+HK_RATE_MAD_I64_I32, HK_RATE_MAD_U64_U32, HK_RATE_MAD_U32_U24, HK_RATE_FMA_F64 = 0, 1, 2, 3
+
+
+def mul_rate(kind, stream=None):
+    """(lane operations per second, shader clock in Hz) of one VALU
+    instruction kind, measured on the current GPU (hk_mul_rate)."""
+    import torch
+    L = lib()
+    buf = torch.empty(L.hk_mul_rate_buffer_bytes(), dtype=torch.uint8, device="cuda")
+    r, clk = ctypes.c_double(), ctypes.c_double()
+    _check(L.hk_mul_rate(kind, ctypes.c_void_p(buf.data_ptr()), buf.numel(), _stream(stream),
+                         ctypes.byref(r), ctypes.byref(clk)))
+    return r.value, clk.value
 
 
 def autotune(insts, cache_path=None, stream=None, ws=None):
