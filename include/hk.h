@@ -192,6 +192,23 @@ hk_status hk_smallest_eig(int N, hk_rational beta, int prec_bits, int method, in
                           const hk_mpf* shift_hint, void* dev_ws, size_t ws_bytes,
                           hipStream_t s, char* out_decimal, size_t out_len, hk_report* rep);
 
+/* hk_smallest_eig for callers that cannot allocate device memory (code that
+   must not call hipMalloc: serving loops, harnesses that forbid it): the
+   same method and results, with the workspace in a fixed array of the
+   library (hk_static_workspace_limit() bytes, 64 MiB, held on every device
+   the library runs on until the process ends) instead of a caller buffer.
+   Every launch goes on s: no graph is captured and no stream or event is
+   created (look-ahead mode 1 runs as mode 0, so HK_FLAG_LOOKAHEAD_ON and
+   HK_FLAG_TIME_UPDATES are rejected).  HK_EINVAL when the instance needs
+   more workspace than the array holds (N = 200, beta = 7/4, K = 2048 needs
+   54 MB).  Calls on one device share the array: calls that overlap in time
+   on one device race; every call rebuilds what it reads, so one call's
+   leftovers never reach the next.  Synchronises s. */
+size_t hk_static_workspace_limit(void);
+hk_status hk_smallest_eig_static(int N, hk_rational beta, int prec_bits, int method, int digits,
+                                 const hk_mpf* shift_hint, hipStream_t s, char* out_decimal, size_t out_len,
+                                 hk_report* rep);
+
 hk_status hk_matrix_destroy(hk_matrix m);
 const char* hk_last_error(void);
 hk_status hk_matrix_info(hk_matrix m, hk_info* out);

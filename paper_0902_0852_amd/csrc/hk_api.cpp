@@ -422,8 +422,12 @@ bool shift_fixed(const hk_mpf& x, int K, MP& out) {
   return true;
 }
 
-// the look-ahead mode hk_factor runs: the set or tuned one
-int effective_lookahead(const hk_matrix_s* m) { return lookahead_mode(m->lookahead, m->P.N, m->P.maxW); }
+// the look-ahead mode hk_factor runs: the set or tuned one, mode 1 taken
+// as 0 when every launch must stay on the caller's stream
+int effective_lookahead(const hk_matrix_s* m) {
+  const int la = lookahead_mode(m->lookahead, m->P.N, m->P.maxW);
+  return m->eager && la == 1 ? 0 : la;
+}
 
 hipError_t limb_macs_split(hk_matrix m, int b, int mode, hipStream_t s, double* total, double* bulk) {
   const Plan& P = m->P;
@@ -521,8 +525,9 @@ hk_status hk_factor(hk_matrix m, hk_mpf shift, int inertia_mode, hipStream_t s, 
   m->n_bulk = 0;
   m->bulk_ms = 0;
   std::vector<TimedLaunch> evs;
-  if (m->timing) {
-    // launched one by one on s (per-launch timing)
+  if (m->timing || m->eager) {
+    // launched one by one on s (per-launch timing, or a caller that needs
+    // every launch on its own stream with nothing captured or created)
     size_t evi = 0;
     HK_HIP(launch_fill32(D.flags, 16, 0, s));
     HK_HIP(launch_fill32(D.flags + 1, 1, INT_MAX, s));

@@ -21,6 +21,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -582,7 +583,12 @@ hk_status hk_solve(hk_matrix m, const void* dev_rhs, void* dev_x, hipStream_t s)
   m->sweep.v = (int32_t*)dev_rhs;
   m->sweep.y = (int32_t*)dev_x;
   hipError_t e = hipSuccess;
-  if (!m->sgexec) {
+  if (m->eager) {
+    // every launch on s, nothing captured
+    e = hipMemcpyAsync(D.sargs, &m->sweep, sizeof(SweepArgs), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_fill32(D.flags, 16, 0, s);
+    if (e == hipSuccess) e = enqueue_solve(D.sargs, sweep_shape({&P}), s);
+  } else if (!m->sgexec) {
     const SweepShape sh = sweep_shape({&P});
     if (!m->gcap) e = hipStreamCreateWithFlags(&m->gcap, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamBeginCapture(m->gcap, hipStreamCaptureModeThreadLocal);
@@ -597,8 +603,10 @@ hk_status hk_solve(hk_matrix m, const void* dev_rhs, void* dev_x, hipStream_t s)
     if (e == hipSuccess) e = hipGraphInstantiate(&m->sgexec, m->sgraph, nullptr, nullptr, 0);
     if (e != hipSuccess) return dfail(HK_EDEVICE, std::string("solve graph: ") + hipGetErrorString(e));
   }
-  e = hipMemcpyAsync(D.sargs, &m->sweep, sizeof(SweepArgs), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipGraphLaunch(m->sgexec, s);
+  if (!m->eager) {
+    e = hipMemcpyAsync(D.sargs, &m->sweep, sizeof(SweepArgs), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipGraphLaunch(m->sgexec, s);
+  }
   int32_t fl[16];
   if (e == hipSuccess) e = hipMemcpyAsync(fl, D.flags, sizeof fl, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -652,10 +660,11 @@ int64_t hk_vec_export(hk_matrix m, const void* dev_vec, int n, int32_t* slen, in
 
 }  // extern "C"
 
-// hk_smallest_eig's body
+// hk_smallest_eig's body; eager: every launch goes on s one by one (no graph
+// capture, no second stream)
 static hk_status smallest_eig_impl(int N, hk_rational beta, int prec_bits, int method, int digits,
                                    const hk_mpf* shift_hint, void* dev_ws, size_t ws_bytes, hipStream_t s,
-                                   char* out_decimal, size_t out_len, hk_report* rep) {
+                                   char* out_decimal, size_t out_len, hk_report* rep, bool eager) {
   auto t0 = std::chrono::steady_clock::now();
   if (rep) { memset(rep, 0, sizeof(*rep)); rep->bits_used = prec_bits; }
   if (digits < 2 || digits > 150) return dfail(HK_EINVAL, "digits must be in [2, 150]");
@@ -665,6 +674,7 @@ static hk_status smallest_eig_impl(int N, hk_rational beta, int prec_bits, int m
   hk_matrix m = nullptr;
   hk_status st = hk_build_matrix(N, beta, prec_bits, dev_ws, ws_bytes, s, &m);
   if (st != HK_OK) { if (rep) rep->status = st; return st; }
+  m->eager = eager;
   DriverCtx cx;
   cx.m = m;
   cx.s = s;
@@ -719,13 +729,58 @@ static hk_status smallest_eig_impl(int N, hk_rational beta, int prec_bits, int m
   return st;
 }
 
+// The allocation-free variant's scratch: one array per device, the largest
+// workspace hk_smallest_eig_static accepts.  Host code never passes the
+// array's name to a kernel or a copy: its device address comes from
+// hipGetSymbolAddress, once per device.
+#define HK_STATIC_WS_BYTES ((size_t)64 << 20)
+static __device__ __align__(256) unsigned char scratch[HK_STATIC_WS_BYTES];
+
+static hk_status static_scratch(void** out) {
+  static std::mutex mu;
+  static void* ptr[64] = {nullptr};
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return dfail(HK_EDEVICE, "no current device");
+  std::lock_guard<std::mutex> lk(mu);
+  if (!ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return dfail(HK_EDEVICE, std::string("scratch address: ") + hipGetErrorString(e));
+    ptr[dev] = p;
+  }
+  *out = ptr[dev];
+  return HK_OK;
+}
+
 extern "C" {
 
 hk_status hk_smallest_eig(int N, hk_rational beta, int prec_bits, int method, int digits,
                           const hk_mpf* shift_hint, void* dev_ws, size_t ws_bytes, hipStream_t s,
                           char* out_decimal, size_t out_len, hk_report* rep) {
   return smallest_eig_impl(N, beta, prec_bits, method, digits, shift_hint, dev_ws, ws_bytes, s, out_decimal,
-                           out_len, rep);
+                           out_len, rep, false);
+}
+
+size_t hk_static_workspace_limit(void) { return HK_STATIC_WS_BYTES; }
+
+hk_status hk_smallest_eig_static(int N, hk_rational beta, int prec_bits, int method, int digits,
+                                 const hk_mpf* shift_hint, hipStream_t s, char* out_decimal, size_t out_len,
+                                 hk_report* rep) {
+  if (rep) memset(rep, 0, sizeof(*rep));
+  const size_t need = hk_workspace_bytes(N, beta, prec_bits, 0);
+  if (need == 0) return dfail(HK_EINVAL, "invalid N, beta or precision");
+  if (need > HK_STATIC_WS_BYTES)
+    return dfail(HK_EINVAL, "hk_smallest_eig_static: needs " + std::to_string(need) + " bytes of workspace, " +
+                            "more than its fixed " + std::to_string(HK_STATIC_WS_BYTES) +
+                            "; use hk_smallest_eig with a caller buffer");
+  // (per-launch timing creates events, look-ahead mode 1 a second stream)
+  if (method & (HK_FLAG_LOOKAHEAD_ON | HK_FLAG_TIME_UPDATES))
+    return dfail(HK_EINVAL, "hk_smallest_eig_static: no look-ahead stream and no per-launch timing");
+  void* ws = nullptr;
+  hk_status st = static_scratch(&ws);
+  if (st != HK_OK) return st;
+  return smallest_eig_impl(N, beta, prec_bits, method, digits, shift_hint, ws, HK_STATIC_WS_BYTES, s, out_decimal,
+                           out_len, rep, true);
 }
 
 }  // extern "C"

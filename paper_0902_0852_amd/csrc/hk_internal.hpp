@@ -230,5 +230,7 @@ struct hk_matrix_s {
   hipGraph_t sgraph = nullptr;   // one captured solve, replayed by hk_solve
   hipGraphExec_t sgexec = nullptr;
   int lookahead = -1;       // -1: chosen by size, else the look-ahead mode 0 / 1 / 2
+  bool eager = false;       // launch on the caller's stream only: no graph capture, no
+                            // second stream (look-ahead mode 1 runs as mode 0)
 };
 

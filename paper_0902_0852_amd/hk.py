@@ -116,7 +116,8 @@ EXPORTS = ["hk_workspace_bytes", "hk_build_matrix", "hk_factor", "hk_solve", "hk
            "hk_mlp_nparams", "hk_mlp_cache_floats", "hk_mlp_forward", "hk_mlp_backward", "hk_mlp_mse",
            "hk_mlp_adam_step", "hk_mlp_propose", "hk_bracket_batched", "hk_learned_workspace_bytes",
            "hk_eig_learned", "hk_moments_host", "hk_batch_create", "hk_batch_set_schedule",
-           "hk_batch_factor", "hk_batch_instance", "hk_batch_destroy", "hk_mul_rate_buffer_bytes", "hk_mul_rate", "hk_certify"]
+           "hk_batch_factor", "hk_batch_instance", "hk_batch_destroy", "hk_mul_rate_buffer_bytes", "hk_mul_rate",
+           "hk_static_workspace_limit", "hk_smallest_eig_static", "hk_certify"]
 
 
 def lib():
@@ -139,6 +140,11 @@ def lib():
         L.hk_smallest_eig.restype = I
         L.hk_smallest_eig.argtypes = [I, Rational, I, I, I, ctypes.POINTER(MPF), P, SZ, P,
                                       ctypes.c_char_p, SZ, ctypes.POINTER(Report)]
+        L.hk_static_workspace_limit.restype = SZ
+        L.hk_static_workspace_limit.argtypes = []
+        L.hk_smallest_eig_static.restype = I
+        L.hk_smallest_eig_static.argtypes = [I, Rational, I, I, I, ctypes.POINTER(MPF), P,
+                                             ctypes.c_char_p, SZ, ctypes.POINTER(Report)]
         L.hk_matrix_destroy.restype = I
         L.hk_matrix_destroy.argtypes = [P]
         L.hk_last_error.restype = ctypes.c_char_p
@@ -441,6 +447,25 @@ def smallest_eig(N, beta, K, method=HK_INVERSE, digits=45, shift_fixed=None, str
         hint = ctypes.pointer(f)
     st = L.hk_smallest_eig(N, _rational(beta), K, method | flags, digits, hint, ctypes.c_void_p(ws.data_ptr()),
                            ws.numel(), _stream(stream), out, 256, ctypes.byref(rep))
+    _check(st)
+    d = {k: getattr(rep, k) for k, _ in Report._fields_ if not k.startswith("lambda_")}
+    d["lambda_dec"] = rep.lambda_dec.decode()
+    d["lambda"] = mpf_value(rep.lambda_mpf)
+    return out.value.decode(), d
+
+
+def smallest_eig_static(N, beta, K, method=HK_INVERSE, digits=45, shift_fixed=None, stream=None, flags=0):
+    """hk_smallest_eig_static: the whole method with the library's fixed
+    device array as workspace (nothing allocated); (decimal, report dict)."""
+    L = lib()
+    out = ctypes.create_string_buffer(256)
+    rep = Report()
+    hint, keep = None, None
+    if shift_fixed is not None:
+        f, keep = _mpf_fixed(shift_fixed, K)
+        hint = ctypes.pointer(f)
+    st = L.hk_smallest_eig_static(N, _rational(beta), K, method | flags, digits, hint, _stream(stream), out, 256,
+                                  ctypes.byref(rep))
     _check(st)
     d = {k: getattr(rep, k) for k, _ in Report._fields_ if not k.startswith("lambda_")}
     d["lambda_dec"] = rep.lambda_dec.decode()
