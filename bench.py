@@ -214,6 +214,42 @@ def peak_rates(args):
     print(json.dumps(out), flush=True)
 
 
+# the paper's table of smallest eigenvalues ('Numerical results'), the rows
+# beyond the GPU tests: (N, column of beta, precision K, driver)
+TABLE_BETAS = [(1, 3), (1, 2), (1, 1), (7, 4)]
+TABLE_RUNS = {
+    1000: [(0, 8192), (1, 6144), (2, 6144), (3, 8192)],
+    1500: [(0, 10240), (1, 8192), (2, 8192), (3, 10240)],
+}
+
+
+def lambda_table(args):
+    """lambda_1 of rows of the paper's table on the GPU (inverse iteration
+    from 0 and the 45-digit inertia bracket), each compared with the
+    printed five digits; one JSON line per run."""
+    from fractions import Fraction
+    os.environ.setdefault("HK_TRACE", "1")   # the driver reports each factorisation and solve
+    import paper_0902_0852_amd as hk
+    gold = json.load(open(os.path.join(HERE, "tests", "golden", "paper_lambda_table.json")))
+    for N in [int(x) for x in args.rows.split(",")]:
+        for col, K in TABLE_RUNS[N]:
+            if args.cols and col not in [int(c) for c in args.cols.split(",")]:
+                continue
+            beta = TABLE_BETAS[col]
+            log("table: N=%d beta=%d/%d K=%d" % (N, beta[0], beta[1], K))
+            t0 = time.time()
+            dec, rep = hk.smallest_eig(N, beta, K, method=hk.HK_INVERSE, digits=45, flags=hk.HK_FLAG_NO_WORK_COUNT)
+            dt = time.time() - t0
+            m, e = (gold["rows"][str(N)][col].split("e") + ["0"])[:2]
+            ref = Fraction(m) * Fraction(10) ** int(e)
+            lam = rep["lambda"]
+            rel = abs(lam - ref) / ref
+            print(json.dumps({"N": N, "beta": "%d/%d" % beta, "K": K, "lambda_1": dec, "paper": gold["rows"][str(N)][col],
+                              "rel_diff_vs_paper": float(rel), "within_print": bool(rel <= Fraction(51, 10 ** 6)),
+                              "verified": rep["verified"], "factorizations": rep["factorizations"],
+                              "solves": rep["solves"], "seconds": dt}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -222,15 +258,20 @@ def main():
     ap.add_argument("--config", default="c3", choices=sorted(CONFIGS))
     ap.add_argument("--method", default="secant", choices=["secant", "inverse"])
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--mode", default="plain", choices=["plain", "learned", "peak"],
+    ap.add_argument("--mode", default="plain", choices=["plain", "learned", "peak", "table"],
                     help="learned: batched + learned form against the batched plain form; "
-                         "peak: measured issue rates of the multiply instructions")
+                         "peak: measured issue rates of the multiply instructions; "
+                         "table: rows of the paper's lambda table (--rows, --cols)")
+    ap.add_argument("--rows", default="1000", help="table mode: N rows, comma separated (1000, 1500)")
+    ap.add_argument("--cols", default="", help="table mode: beta columns 0..3 (1/3, 1/2, 1, 7/4); default all")
     ap.add_argument("--model", default=None, help="network file (default: the package's trained one)")
     ap.add_argument("--instances", type=int, default=64)
     ap.add_argument("--seed", type=int, default=4242)
     ap.add_argument("--n-lo", type=int, default=50)
     ap.add_argument("--n-hi", type=int, default=400)
     ap.add_argument("--panel", type=int, default=0, help="panel width (0: tuned here / tuned or 4 in learned mode)")
+    ap.add_argument("--group", type=int, default=0, choices=[0, 1, 2, 4],
+                    help="update items per workgroup (0: tuned, else 4)")
     ap.add_argument("--lookahead", type=int, default=-1, choices=[-1, 0, 1, 2],
                     help="with --panel: look-ahead mode 0 none, 1 second stream, 2 one launch per column "
                          "(-1: chosen by size)")
@@ -245,6 +286,9 @@ def main():
     if args.mode == "peak":
         peak_rates(args)
         return
+    if args.mode == "table":
+        lambda_table(args)
+        return
     import torch
     import paper_0902_0852_amd as hk
     cfg = CONFIGS[args.config]
@@ -258,6 +302,7 @@ def main():
     os.environ["HK_TUNE_CACHE"] = tune_path
     flags, scheds = [], []
     for N, beta, K in runs:
+        group = args.group
         if args.panel > 0:
             panel, la = args.panel, args.lookahead
             if la < 0:   # the mode the library picks for this size
@@ -266,14 +311,15 @@ def main():
                 la = m.info().lookahead
                 del m
         else:
-            panel, la = hk.autotune([(N, beta, K)], cache_path=tune_path)
-        pflag = hk.HK_FLAG_PANEL(panel)
+            panel, la, g = hk.autotune([(N, beta, K)], cache_path=tune_path)
+            group = group or g
+        pflag = hk.HK_FLAG_PANEL(panel) | (hk.HK_FLAG_GROUP(group) if group else 0)
         pflag |= {0: hk.HK_FLAG_LOOKAHEAD_OFF, 1: hk.HK_FLAG_LOOKAHEAD_ON,
                   2: hk.HK_FLAG_LOOKAHEAD_FUSED}.get(la, 0)
         flags.append(pflag)
-        scheds.append((panel, la))
-        log("N=%d beta=%d/%d K=%d: panel width %d, look-ahead %d (%s)"
-            % (N, beta[0], beta[1], K, panel, la, "given" if args.panel > 0 else "tuned"))
+        scheds.append((panel, la, group or 4))
+        log("N=%d beta=%d/%d K=%d: panel width %d, look-ahead %d, %d update items per workgroup (%s)"
+            % (N, beta[0], beta[1], K, panel, la, group or 4, "given" if args.panel > 0 else "tuned"))
 
     def one_step(extra):
         out = []
@@ -308,7 +354,7 @@ def main():
     bulk_ms = sum(r["bulk_ms"] for _, r in res_t)
     bulk_n = sum(r["bulk_launches"] for _, r in res_t)
     macs_bulk = sum(r["limb_macs_bulk"] for _, r in res)
-    fused = all(la == 2 for _, la in scheds)
+    fused = all(la == 2 for _, la, _ in scheds)
     kernel = "k_column" if fused else "k_update"
     kdesc = ("k_column (one column: its rows' update by the previous column, finalisation and division; "
              "the update of the columns beyond)" if fused else
@@ -326,7 +372,8 @@ def main():
                                "to 45 digits" % (cfg["desc"], args.method),
                    "N": [N for N, _, _ in runs], "beta": ["%d/%d" % b for _, b, _ in runs],
                    "prec_bits": [K for _, _, K in runs], "method": args.method,
-                   "panel": [p for p, _ in scheds], "lookahead": [la for _, la in scheds]},
+                   "panel": [p for p, _, _ in scheds], "lookahead": [la for _, la, _ in scheds],
+                   "update_group": [g for _, _, g in scheds]},
         "lambda_solves_per_s": len(runs) * args.steps / dt,
         "lambda_1": lams,
         "roofline": {"bound": "alu", "kernel": kdesc,

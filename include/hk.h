@@ -76,6 +76,9 @@ enum { HK_FLAG_NO_WORK_COUNT = 0x100,   /* skip the limb-MAC count (report 0)   
 /* look-ahead mode forced for hk_smallest_eig (see hk_set_lookahead): 1, 0, 2 */
 enum { HK_FLAG_LOOKAHEAD_ON = 0x1000000, HK_FLAG_LOOKAHEAD_OFF = 0x2000000,
        HK_FLAG_LOOKAHEAD_FUSED = 0x4000000 };
+/* update items per workgroup g in {1, 2, 4} forced for hk_smallest_eig
+   (see hk_set_update_group): or HK_FLAG_GROUP(g) into the method argument */
+#define HK_FLAG_GROUP(g) (((g) & 7) << 28)
 
 typedef struct hk_matrix_s* hk_matrix;
 
@@ -233,6 +236,10 @@ hk_status hk_certify(hk_matrix m, hipStream_t s, int* n_negative, int* certified
 
 /* Tuning: columns per trailing update (panel width, >= 1). */
 hk_status hk_set_panel(hk_matrix m, int panel);
+/* Tuning: update items (wavefronts of 64 rows x 16 output digits) per
+   workgroup of the update kernels, 1, 2 or 4 (the default, or the tuned
+   value); HK_EINVAL otherwise. */
+hk_status hk_set_update_group(hk_matrix m, int items);
 /* Look-ahead ("The LDL^T Determinant Algorithm", parallel version: the next
    panel's columns are updated first): mode 1 splits every trailing update
    into the next panel's columns, on the critical path, and the rest, on a
@@ -348,12 +355,16 @@ hk_status hk_eig_batched(const hk_instance* inst, int count, int digits, int pan
 
 /* Times one batched factorisation of the given batch for each panel width
    in {1, 2, 4, 8, 16} under look-ahead modes 0 and 1, and once under mode 2
-   (width 1), stores the fastest in
-   *best_panel and *best_lookahead (may be NULL) and appends them to the text
-   cache file cache_path (NULL: no file) under the batch-shape key
-   (architecture, count, N bucket, K bucket).  Synchronises s. */
+   (width 1), then the update workgroup size (1, 2 or 4 items of 64 rows x
+   16 digits per workgroup) for the fastest; stores the choice in
+   *best_panel, *best_lookahead and *best_group (the last two may be NULL)
+   and appends it to the text cache file cache_path (NULL: no file) under
+   the batch-shape key (architecture, count, N bucket, K bucket).  Rows per
+   item (one wavefront) and digits per output block (16, the carry-plane
+   granularity of the layout) are fixed.  Synchronises s. */
 hk_status hk_autotune(const hk_instance* inst, int count, void* dev_ws, size_t ws_bytes,
-                      hipStream_t s, const char* cache_path, int* best_panel, int* best_lookahead);
+                      hipStream_t s, const char* cache_path, int* best_panel, int* best_lookahead,
+                      int* best_group);
 
 /* Batch handles: the instances of a batch laid out in dev_ws (at least
    hk_batch_workspace_bytes(inst, count) bytes, alive until hk_batch_destroy)
@@ -369,9 +380,10 @@ typedef struct hk_batch_s* hk_batch;
    panel 4 with the look-ahead mode chosen by size.  Synchronises s. */
 hk_status hk_batch_create(const hk_instance* inst, int count, void* dev_ws, size_t ws_bytes, hipStream_t s,
                           hk_batch* out);
-/* panel width in 1..64 and look-ahead mode -1 (by size), 0, 1 or 2 (2
-   forces panel width 1); the digits are the same under every schedule. */
-hk_status hk_batch_set_schedule(hk_batch b, int panel, int lookahead);
+/* panel width in 1..64, look-ahead mode -1 (by size), 0, 1 or 2 (2 forces
+   panel width 1) and update items per workgroup 1, 2 or 4 (0: keep); the
+   digits are the same under every schedule. */
+hk_status hk_batch_set_schedule(hk_batch b, int panel, int lookahead, int group);
 /* LDL^T of M_i - x_i I for every instance ("The LDL^T Determinant
    Algorithm", as hk_factor) in one graph replay; shifts[i] is a dyadic with
    at most K_i fractional bits (shifts NULL: all zero).  Per instance (arrays

@@ -351,8 +351,15 @@ hk_status hk_build_matrix(int N, hk_rational beta, int prec_bits, void* dev_ws, 
     const hk::Schedule sc = hk::tuned_schedule(&one, 1);
     if (sc.panel > 0) (*out)->panel = sc.panel;
     (*out)->lookahead = sc.lookahead;
+    if (sc.ipw > 0) (*out)->B.ipw = sc.ipw;
   }
   return st;
+}
+
+hk_status hk_set_update_group(hk_matrix m, int items) {
+  if (!m || (items != 1 && items != 2 && items != 4)) return fail(HK_EINVAL, "items per workgroup must be 1, 2 or 4");
+  m->B.ipw = items;
+  return HK_OK;
 }
 
 }  // extern "C"
@@ -537,7 +544,7 @@ hk_status hk_factor(hk_matrix m, hk_mpf shift, int inertia_mode, hipStream_t s, 
                           &m->n_update, &m->n_bulk));
   } else {
     const int la = lookahead_mode(m->lookahead, P.N, P.maxW);
-    if (!m->gexec || m->gpanel != b || m->gla != la) {
+    if (!m->gexec || m->gpanel != b || m->gla != la || m->gipw != m->B.ipw) {
       if (m->gexec) { (void)hipGraphExecDestroy(m->gexec); m->gexec = nullptr; }
       if (m->graph) { (void)hipGraphDestroy(m->graph); m->graph = nullptr; }
       if (!m->gcap) HK_HIP(hipStreamCreateWithFlags(&m->gcap, hipStreamNonBlocking));
@@ -557,6 +564,7 @@ hk_status hk_factor(hk_matrix m, hk_mpf shift, int inertia_mode, hipStream_t s, 
       if (e != hipSuccess) return fail(HK_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
       m->gpanel = b;
       m->gla = la;
+      m->gipw = m->B.ipw;
       m->g_nupdate = nu;
       m->g_nbulk = nbk;
     }

@@ -122,7 +122,8 @@ static hk_status ensure_graph(Batch& bt) {
   int maxW = 0;
   for (const Plan* p : bt.B.plans) maxW = std::max(maxW, p->maxW);
   const int la = lookahead_mode(bt.lookahead, bt.maxN, maxW);
-  if (bt.exec && bt.captured_panel == bt.panel && bt.captured_la == la) return HK_OK;
+  if (bt.exec && bt.captured_panel == bt.panel && bt.captured_la == la && bt.captured_ipw == bt.B.ipw)
+    return HK_OK;
   if (bt.exec) { (void)hipGraphExecDestroy(bt.exec); bt.exec = nullptr; }
   if (bt.graph) { (void)hipGraphDestroy(bt.graph); bt.graph = nullptr; }
   hipError_t e = hipSuccess;
@@ -146,6 +147,7 @@ static hk_status ensure_graph(Batch& bt) {
   if (e != hipSuccess) return dfail_b(HK_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
   bt.captured_panel = bt.panel;
   bt.captured_la = la;
+  bt.captured_ipw = bt.B.ipw;
   return HK_OK;
 }
 
@@ -227,6 +229,8 @@ static Schedule cached_schedule(const std::string& key) {
     sc.panel = atoi(line.c_str() + bar + 9);
     const size_t la = line.find(" la=", bar);
     sc.lookahead = la == std::string::npos ? -1 : atoi(line.c_str() + la + 4);
+    const size_t ip = line.find(" ipw=", bar);
+    sc.ipw = ip == std::string::npos ? 0 : atoi(line.c_str() + ip + 5);
   }
   return sc;
 }
@@ -272,6 +276,7 @@ hk_status hk_eig_batched(const hk_instance* inst, int count, int digits, int pan
     const Schedule sc = tuned_schedule(inst, count);
     bt.panel = panel > 0 ? panel : (sc.panel > 0 ? sc.panel : 4);
     bt.lookahead = sc.lookahead;
+    if (sc.ipw > 0) bt.B.ipw = sc.ipw;
   }
   auto t1 = std::chrono::steady_clock::now();
   std::vector<SecantRun*> sm(count, nullptr);
@@ -390,7 +395,8 @@ hk_status hk_eig_batched(const hk_instance* inst, int count, int digits, int pan
 }
 
 hk_status hk_autotune(const hk_instance* inst, int count, void* dev_ws, size_t ws_bytes,
-                      hipStream_t s, const char* cache_path, int* best_panel, int* best_lookahead) {
+                      hipStream_t s, const char* cache_path, int* best_panel, int* best_lookahead,
+                      int* best_group) {
   if (!inst || count < 1 || !best_panel) return dfail_b(HK_EINVAL, "bad arguments");
   Batch bt;
   hk_status st = build_batch(bt, inst, count, dev_ws, ws_bytes, s);
@@ -398,29 +404,47 @@ hk_status hk_autotune(const hk_instance* inst, int count, void* dev_ws, size_t w
   std::vector<MP> x(count);
   std::vector<int> act(count, 1);
   std::vector<BEval> ev;
+  // one batched factorisation per candidate (captured and warmed up first)
+  auto time_one = [&](int b, int la, int ipw, double& ms) -> hk_status {
+    bt.panel = b;
+    bt.lookahead = la;
+    bt.B.ipw = ipw;
+    hk_status e = factor_batch(bt, x, act, s, ev, false);
+    if (e != HK_OK) return e;
+    auto t0 = std::chrono::steady_clock::now();
+    e = factor_batch(bt, x, act, s, ev, false);
+    ms = 1e3 * std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return e;
+  };
   const int cand[] = {1, 2, 4, 8, 16};
   double best_ms = 1e300;
-  int best = 4, best_la = 0;
+  int best = 4, best_la = 0, best_ipw = 4;
   for (int la = 0; la <= 2; la++) {
     for (int b : cand) {
       if (la == 2 && b != 1) continue;   // one column per launch: no panels
-      bt.panel = b;
-      bt.lookahead = la;
-      st = factor_batch(bt, x, act, s, ev, false);   // capture + warm up
+      double ms = 0;
+      st = time_one(b, la, 4, ms);
       if (st != HK_OK) return st;
-      auto t0 = std::chrono::steady_clock::now();
-      st = factor_batch(bt, x, act, s, ev, false);
-      if (st != HK_OK) return st;
-      const double ms = 1e3 * std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
       if (ms < best_ms) { best_ms = ms; best = b; best_la = la; }
+    }
+  }
+  // the update workgroup size (items per workgroup) for the best schedule
+  if (best_la != 2) {
+    for (int ipw : {1, 2}) {
+      double ms = 0;
+      st = time_one(best, best_la, ipw, ms);
+      if (st != HK_OK) return st;
+      if (ms < best_ms) { best_ms = ms; best_ipw = ipw; }
     }
   }
   *best_panel = best;
   if (best_lookahead) *best_lookahead = best_la;
+  if (best_group) *best_group = best_ipw;
   if (cache_path) {
     std::ofstream f(cache_path, std::ios::app);
     if (!f) return dfail_b(HK_EINVAL, "cannot write the tuning cache");
-    f << tune_key(inst, count) << " | panel=" << best << " la=" << best_la << " ms=" << best_ms << "\n";
+    f << tune_key(inst, count) << " | panel=" << best << " la=" << best_la << " ipw=" << best_ipw << " ms=" << best_ms
+      << "\n";
   }
   return HK_OK;
 }
@@ -446,15 +470,18 @@ hk_status hk_batch_create(const hk_instance* inst, int count, void* dev_ws, size
   const Schedule sc = tuned_schedule(inst, count);
   b->bt.panel = sc.panel > 0 ? sc.panel : 4;
   b->bt.lookahead = sc.lookahead;
+  if (sc.ipw > 0) b->bt.B.ipw = sc.ipw;
   *out = b;
   return HK_OK;
 }
 
-hk_status hk_batch_set_schedule(hk_batch b, int panel, int lookahead) {
-  if (!b || panel < 1 || panel > 64 || lookahead < -1 || lookahead > 2)
-    return dfail_b(HK_EINVAL, "panel must be in 1..64 and look-ahead in -1..2");
+hk_status hk_batch_set_schedule(hk_batch b, int panel, int lookahead, int group) {
+  if (!b || panel < 1 || panel > 64 || lookahead < -1 || lookahead > 2 ||
+      (group != 0 && group != 1 && group != 2 && group != 4))
+    return dfail_b(HK_EINVAL, "panel must be in 1..64, look-ahead in -1..2 and group 0, 1, 2 or 4");
   b->bt.panel = lookahead == 2 ? 1 : panel;
   b->bt.lookahead = lookahead;
+  if (group > 0) b->bt.B.ipw = group;
   return HK_OK;
 }
 

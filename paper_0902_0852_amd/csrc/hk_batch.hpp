@@ -23,7 +23,7 @@ struct Batch {
   std::vector<hipEvent_t> events;              // fork/join points of the captured graph
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  int captured_panel = 0;
+  int captured_panel = 0, captured_ipw = 0;
   int graph_launches = 0;
   Batch() = default;
   Batch(const Batch&) = delete;

@@ -33,6 +33,13 @@ namespace {
 
 hk_status dfail(hk_status st, const std::string& msg) { g_err = msg; return st; }
 
+// HK_TRACE=1 in the environment: one line on stderr per factorisation and
+// per solve of the drivers (long runs report their progress as they go)
+bool trace_on() {
+  static const bool on = [] { const char* v = getenv("HK_TRACE"); return v && v[0] == '1'; }();
+  return on;
+}
+
 MP one_shl(int64_t s) { return shl(MP::from_u64(1), s); }
 
 // floor(x / 2^s)
@@ -125,8 +132,12 @@ static Eval evaluate(DriverCtx& cx, const MP& x, int inertia_mode) {
   hk_mpf f = fixed_mpf(x, cx.m->P.K, keep);
   auto t0 = std::chrono::steady_clock::now();
   ev.st = hk_factor(cx.m, f, inertia_mode, cx.s, &ev.nneg, &ev.first_bad);
-  cx.t_factor += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  cx.t_factor += dt;
   cx.nfact++;
+  if (trace_on())
+    fprintf(stderr, "[hk] factorisation %d (N=%d K=%d): status %d, %.2f s\n", cx.nfact, cx.m->P.N, cx.m->P.K,
+            (int)ev.st, dt);
   {
     hk_info inf;
     if (hk_matrix_info(cx.m, &inf) == HK_OK) {
@@ -509,6 +520,7 @@ hk_status inverse_iterate(hk_matrix m, hipStream_t s, const MP& sigma, int tol, 
     auto t0 = std::chrono::steady_clock::now();
     hk_status st = hk_solve(m, m->D.dv1, m->D.dv2, s);
     solves++;
+    if (trace_on()) fprintf(stderr, "[hk] solve %d (N=%d K=%d): status %d\n", solves, N, P.K, (int)st);
     if (st != HK_OK) return st;
     st = vec_to_host(m, m->D.dv2, s, y);
     t_solve += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -686,6 +698,8 @@ static hk_status smallest_eig_impl(int N, hk_rational beta, int prec_bits, int m
   if (flags & HK_FLAG_LOOKAHEAD_ON) hk_set_lookahead(m, 1);
   if (flags & HK_FLAG_LOOKAHEAD_OFF) hk_set_lookahead(m, 0);
   if (flags & HK_FLAG_LOOKAHEAD_FUSED) hk_set_lookahead(m, 2);
+  const int forced_group = (flags >> 28) & 7;
+  if (forced_group > 0) hk_set_update_group(m, forced_group);
   MP lam;
   int solves = 0;
   if (method == HK_SECANT) {

@@ -65,7 +65,7 @@ bool make_plan(int N, int64_t bnum, int64_t bden, int K, Plan& P, std::string& e
 int lookahead_mode(int setting, int maxN, int maxW);
 // panel width (0: none) and look-ahead (-1: none) from the tuning cache
 // named by HK_TUNE_CACHE for this batch shape
-struct Schedule { int panel = 0, lookahead = -1; };
+struct Schedule { int panel = 0, lookahead = -1, ipw = 0; };
 Schedule tuned_schedule(const hk_instance* inst, int count);
 
 bool reduce_beta(int64_t num, int64_t den, uint32_t* p, uint32_t* q);
@@ -120,6 +120,7 @@ struct BatchView {
   const InstDesc* ddesc = nullptr;
   std::vector<const Plan*> plans;
   int maxN = 0;
+  int ipw = 4;   // update items (wavefronts) per workgroup of k_update / k_update_near: 1, 2 or 4
 };
 extern thread_local std::string g_err;
 
@@ -225,7 +226,7 @@ struct hk_matrix_s {
   hipStream_t gcap = nullptr, gcap2 = nullptr, s2 = nullptr;   // capture streams; look-ahead stream
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
-  int gpanel = 0, gla = -1, g_nupdate = 0, g_nbulk = 0;
+  int gpanel = 0, gla = -1, gipw = 0, g_nupdate = 0, g_nbulk = 0;
   hk::SweepArgs sweep;        // host copy of the solve arguments (kept alive for the upload)
   hipGraph_t sgraph = nullptr;   // one captured solve, replayed by hk_solve
   hipGraphExec_t sgexec = nullptr;

@@ -346,14 +346,18 @@ __device__ __forceinline__ void update_item(const InstDesc* __restrict__ desc, i
 // its columns beyond the next panel (UPD_FAR, look-ahead).
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) k_update(const InstDesc* __restrict__ desc, int count, int pc,
                                                 int b, int j, int rd) {
-  update_item(desc, count, pc, b, j, rd, blockIdx.x * 4 + uni(threadIdx.x >> 6));
+  update_item(desc, count, pc, b, j, rd, blockIdx.x * (blockDim.x >> 6) + uni(threadIdx.x >> 6));
 }
 // The small launches on the critical path: the in-panel updates (j > 0) and
 // the next panel's columns (UPD_NEAR, look-ahead); the same items under a
 // symbol of their own, so that they time and profile apart from the bulk.
+// Their waves take the SIMDs' issue slots ahead of the bulk launch's waves
+// that share them (the bulk only needs to finish before the panel after
+// next), as the row waves of the column kernels do.
 __global__ void __launch_bounds__(256) k_update_near(const InstDesc* __restrict__ desc, int count, int pc,
                                                      int b, int j, int rd) {
-  update_item(desc, count, pc, b, j, rd, blockIdx.x * 4 + uni(threadIdx.x >> 6));
+  __builtin_amdgcn_s_setprio(3);
+  update_item(desc, count, pc, b, j, rd, blockIdx.x * (blockDim.x >> 6) + uni(threadIdx.x >> 6));
 }
 
 struct FinOut {
@@ -1776,12 +1780,12 @@ hipError_t launch_update(const BatchView& B, int pc, int b, int j, int rd, hipSt
   for (const Plan* p : B.plans) items += update_items(*p, pc, b, j);
   if (items <= 0) return mark_empty(t0, t1, s);
   auto kern = update_is_bulk(j) ? k_update : k_update_near;
+  const int ipw = B.ipw == 1 || B.ipw == 2 ? B.ipw : 4;
+  const dim3 grid((unsigned)((items + ipw - 1) / ipw)), block(64 * ipw);
   if (t0 || t1)
-    hipExtLaunchKernelGGL(kern, dim3((unsigned)((items + 3) / 4)), dim3(256), 0, s, t0, t1, 0, B.ddesc,
-                          (int)B.plans.size(), pc, b, j, rd);
+    hipExtLaunchKernelGGL(kern, grid, block, 0, s, t0, t1, 0, B.ddesc, (int)B.plans.size(), pc, b, j, rd);
   else
-    hipLaunchKernelGGL(kern, dim3((unsigned)((items + 3) / 4)), dim3(256), 0, s, B.ddesc,
-                       (int)B.plans.size(), pc, b, j, rd);
+    hipLaunchKernelGGL(kern, grid, block, 0, s, B.ddesc, (int)B.plans.size(), pc, b, j, rd);
   return hipGetLastError();
 }
 // LDS of wave_finalize for W digits in blocks of FB

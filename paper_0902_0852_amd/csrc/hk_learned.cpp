@@ -181,6 +181,7 @@ hk_status hk_bracket_batched(const hk_instance* inst, int count, const char* con
     const Schedule sc = tuned_schedule(inst, count);
     bt.panel = panel > 0 ? panel : (sc.panel > 0 ? sc.panel : 4);
     bt.lookahead = sc.lookahead;
+    if (sc.ipw > 0) bt.B.ipw = sc.ipw;
   }
   std::vector<int> act(count, 1);
   std::vector<BEval> elo, ehi;

@@ -18,6 +18,10 @@ HK_INVERSE, HK_SECANT = 0, 1
 HK_FLAG_NO_WORK_COUNT, HK_FLAG_TIME_UPDATES, HK_FLAG_CERTIFY = 0x100, 0x200, 0x400
 
 
+def HK_FLAG_GROUP(g):
+    return (g & 7) << 28
+
+
 def HK_FLAG_PANEL(p):
     """Panel width forced for smallest_eig (or-ed into flags)."""
     return (p & 0xff) << 16
@@ -117,7 +121,8 @@ EXPORTS = ["hk_workspace_bytes", "hk_build_matrix", "hk_factor", "hk_solve", "hk
            "hk_mlp_adam_step", "hk_mlp_propose", "hk_bracket_batched", "hk_learned_workspace_bytes",
            "hk_eig_learned", "hk_moments_host", "hk_batch_create", "hk_batch_set_schedule",
            "hk_batch_factor", "hk_batch_instance", "hk_batch_destroy", "hk_mul_rate_buffer_bytes", "hk_mul_rate",
-           "hk_static_workspace_limit", "hk_smallest_eig_static", "hk_certify"]
+           "hk_static_workspace_limit", "hk_smallest_eig_static", "hk_certify",
+           "hk_set_update_group"]
 
 
 def lib():
@@ -173,7 +178,7 @@ def lib():
         L.hk_batch_create.restype = I
         L.hk_batch_create.argtypes = [P, I, P, SZ, P, ctypes.POINTER(P)]
         L.hk_batch_set_schedule.restype = I
-        L.hk_batch_set_schedule.argtypes = [P, I, I]
+        L.hk_batch_set_schedule.argtypes = [P, I, I, I]
         L.hk_batch_factor.restype = I
         L.hk_batch_factor.argtypes = [P, P, P, P, P, P]
         L.hk_batch_instance.restype = P
@@ -185,7 +190,10 @@ def lib():
         L.hk_mul_rate.restype = I
         L.hk_mul_rate.argtypes = [I, P, SZ, P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         L.hk_autotune.restype = I
-        L.hk_autotune.argtypes = [P, I, P, SZ, P, ctypes.c_char_p, ctypes.POINTER(I), ctypes.POINTER(I)]
+        L.hk_autotune.argtypes = [P, I, P, SZ, P, ctypes.c_char_p, ctypes.POINTER(I), ctypes.POINTER(I),
+                                  ctypes.POINTER(I)]
+        L.hk_set_update_group.restype = I
+        L.hk_set_update_group.argtypes = [P, I]
         F = ctypes.c_float
         L.hk_mlp_nparams.restype = I
         L.hk_mlp_nparams.argtypes = []
@@ -382,6 +390,9 @@ class Matrix(_Factors):
     def set_timing(self, on):
         _check(lib().hk_set_timing(self.h, 1 if on else 0))
 
+    def set_update_group(self, items):
+        _check(lib().hk_set_update_group(self.h, items))
+
     def set_lookahead(self, mode):
         _check(lib().hk_set_lookahead(self.h, mode))
 
@@ -547,8 +558,8 @@ class Batch:
             _lib.hk_batch_destroy(self.h)
             self.h = None
 
-    def set_schedule(self, panel, lookahead=-1):
-        _check(lib().hk_batch_set_schedule(self.h, panel, lookahead))
+    def set_schedule(self, panel, lookahead=-1, group=0):
+        _check(lib().hk_batch_set_schedule(self.h, panel, lookahead, group))
 
     def factor(self, shifts=None, stream=None):
         """shifts: list of ints with K_i fractional bits (None: all zero).
@@ -589,17 +600,18 @@ def mul_rate(kind, stream=None):
 
 
 def autotune(insts, cache_path=None, stream=None, ws=None):
-    """(panel width, look-ahead) fastest for this batch shape."""
+    """(panel width, look-ahead mode, update items per workgroup) fastest for
+    this batch shape."""
     import torch
     L = lib()
     arr = _instances(insts)
     nbytes = L.hk_batch_workspace_bytes(ctypes.cast(arr, ctypes.c_void_p), len(insts))
     ws = ws if ws is not None else torch.empty(nbytes, dtype=torch.uint8, device="cuda")
-    best, best_la = ctypes.c_int(0), ctypes.c_int(0)
+    best, best_la, best_g = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
     _check(L.hk_autotune(ctypes.cast(arr, ctypes.c_void_p), len(insts), ctypes.c_void_p(ws.data_ptr()),
-                         ws.numel(), _stream(stream),
-                         cache_path.encode() if cache_path else None, ctypes.byref(best), ctypes.byref(best_la)))
-    return best.value, best_la.value
+                         ws.numel(), _stream(stream), cache_path.encode() if cache_path else None,
+                         ctypes.byref(best), ctypes.byref(best_la), ctypes.byref(best_g)))
+    return best.value, best_la.value, best_g.value
 
 
 # ---- precision-proposal network (float32 device tensors) ----------------

@@ -44,10 +44,10 @@ def test_batched_equals_single_instance(hk):
 def test_autotune_writes_cache(hk, tmp_path):
     insts = [(24, (1, 1), 384), (30, (7, 4), 512)]
     path = str(tmp_path / "tune.txt")
-    b, la = hk.autotune(insts, cache_path=path)
-    assert b in (1, 2, 4, 8, 16) and la in (0, 1, 2)
+    b, la, g = hk.autotune(insts, cache_path=path)
+    assert b in (1, 2, 4, 8, 16) and la in (0, 1, 2) and g in (1, 2, 4)
     txt = open(path).read()
-    assert "panel=%d la=%d" % (b, la) in txt
+    assert "panel=%d la=%d ipw=%d" % (b, la, g) in txt
 
 
 # ---- factor parity of the batched path -------------------------------------

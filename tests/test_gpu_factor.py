@@ -187,3 +187,20 @@ def test_edge_sizes_vs_oracle(hk, N, beta, K, xn, panel, la):
     assert (nneg, fb) == (of.n_negative, of.first_nonpos)
     if fb < 0 or fb == N - 1:
         compare(m, of, N)
+
+
+@pytest.mark.parametrize("group,la", [(1, 0), (2, 1), (1, 1), (4, 0)])
+def test_update_group_invariance(hk, group, la):
+    # update items per workgroup change only the launch shape: every digit
+    # still equals the oracle's
+    N, beta, K, xn = 97, (5, 3), 768, 7
+    log("update group %d look-ahead %d" % (group, la))
+    X = moments(N, beta, K)
+    xf = xn << (K - K // 2)
+    of = oracle.factor_from_moments(X, N, K, xf)
+    m = hk.Matrix(N, beta, K)
+    m.set_panel(3)
+    m.set_lookahead(la)
+    m.set_update_group(group)
+    m.factor(xf)
+    compare(m, of, N)
