@@ -40,29 +40,42 @@ CONFIGS = {
 PEAK_INT_MUL = 256 * 64 * 2.4e9       # one 32x32 multiply per lane per clock
 HBM_PEAK = 8.0e12
 HERE = os.path.dirname(os.path.abspath(__file__))
-PROFILE_TAG = {"c2": "N200_beta7-4_K2048", "c3b1": "N500_beta1_K6144"}
+PROFILE_TAG = {"c2": "N200_beta7-4_K2048_secant", "c3b1": "N500_beta1_K6144_secant", "c3": "N500_K6144_4beta"}
 
 
-def measured_traffic(cfg_name, kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary of this workload, or None when there is none or the kernel
-    source has changed since the counters were taken."""
+def profile_figures(cfg_name, kernel):
+    """Per-launch figures of `kernel` from the committed rocprofv3 counter
+    summary of this workload (HBM bytes; 64-bit integer VALU instructions),
+    each None when there is no summary or the kernel source has changed
+    since the counters were taken; and the summary's path."""
     import hashlib
     import re
     tag = PROFILE_TAG.get(cfg_name)
     if tag is None:
-        return None, None
-    path = os.path.join(HERE, "profiles", "%s_%s_secant.txt" % (kernel, tag))
+        return {}, None
+    path = os.path.join(HERE, "profiles", "%s_%s.txt" % (kernel, tag))
     try:
         txt = open(path).read()
     except OSError:
-        return None, None
+        return {}, None
     src = open(os.path.join(HERE, "paper_0902_0852_amd", "csrc", "hk_kernels.hip"), "rb").read()
     m = re.search(r"sha256 ([0-9a-f]{16})", txt)
-    t = re.search(r"traffic_bytes_per_launch=(\d+)", txt)
-    if not m or not t or m.group(1) != hashlib.sha256(src).hexdigest()[:16]:
-        return None, os.path.relpath(path, HERE)
-    return int(t.group(1)), os.path.relpath(path, HERE)
+    if not m or m.group(1) != hashlib.sha256(src).hexdigest()[:16]:
+        return {}, os.path.relpath(path, HERE)
+    out = {}
+    for key in ("traffic_bytes_per_launch", "valu_int64_per_launch"):
+        t = re.search(key + r"=([0-9.eE+]+)", txt)
+        if t:
+            out[key] = float(t.group(1))
+    return out, os.path.relpath(path, HERE)
+
+
+def measured_traffic(cfg_name, kernel):
+    """HBM bytes per launch of `kernel` from the committed profile (None when
+    there is none or it is stale), and the profile's path."""
+    fig, path = profile_figures(cfg_name, kernel)
+    t = fig.get("traffic_bytes_per_launch")
+    return (int(t) if t is not None else None), path
 
 
 def log(msg):
@@ -225,8 +238,9 @@ TABLE_RUNS = {
 
 def lambda_table(args):
     """lambda_1 of rows of the paper's table on the GPU (inverse iteration
-    from 0 and the 45-digit inertia bracket), each compared with the
-    printed five digits; one JSON line per run."""
+    from 0, or the Secant iteration where the solve vectors do not fit, and
+    the 45-digit inertia bracket), each compared with the printed five
+    digits; one JSON line per run."""
     from fractions import Fraction
     os.environ.setdefault("HK_TRACE", "1")   # the driver reports each factorisation and solve
     import paper_0902_0852_amd as hk
@@ -238,13 +252,26 @@ def lambda_table(args):
             beta = TABLE_BETAS[col]
             log("table: N=%d beta=%d/%d K=%d" % (N, beta[0], beta[1], K))
             t0 = time.time()
-            dec, rep = hk.smallest_eig(N, beta, K, method=hk.HK_INVERSE, digits=45, flags=hk.HK_FLAG_NO_WORK_COUNT)
+            method = "inverse"
+            try:
+                dec, rep = hk.smallest_eig(N, beta, K, method=hk.HK_INVERSE, digits=45,
+                                           flags=hk.HK_FLAG_NO_WORK_COUNT)
+            except hk.HKError as e:
+                # the solve sweeps' vectors too wide for one workgroup's LDS:
+                # the Secant iteration needs factorisations only
+                if e.status != 1 or "LDS" not in str(e):
+                    raise
+                log("  %s; Secant instead" % e)
+                method = "secant"
+                t0 = time.time()
+                dec, rep = hk.smallest_eig(N, beta, K, method=hk.HK_SECANT, digits=45,
+                                           flags=hk.HK_FLAG_NO_WORK_COUNT)
             dt = time.time() - t0
             m, e = (gold["rows"][str(N)][col].split("e") + ["0"])[:2]
             ref = Fraction(m) * Fraction(10) ** int(e)
             lam = rep["lambda"]
             rel = abs(lam - ref) / ref
-            print(json.dumps({"N": N, "beta": "%d/%d" % beta, "K": K, "lambda_1": dec, "paper": gold["rows"][str(N)][col],
+            print(json.dumps({"N": N, "beta": "%d/%d" % beta, "K": K, "method": method, "lambda_1": dec, "paper": gold["rows"][str(N)][col],
                               "rel_diff_vs_paper": float(rel), "within_print": bool(rel <= Fraction(51, 10 ** 6)),
                               "verified": rep["verified"], "factorizations": rep["factorizations"],
                               "solves": rep["solves"], "seconds": dt}), flush=True)
@@ -362,6 +389,13 @@ def main():
              "panel under look-ahead, or its whole trailing update without)")
     achieved = macs_bulk / (bulk_ms * 1e-3) if bulk_ms > 0 else 0.0
     traffic, traffic_src = measured_traffic(args.config, kernel)
+    fig, _ = profile_figures(args.config, kernel)
+    avg_s = 1e-3 * bulk_ms / max(bulk_n, 1)
+    # executed multiplies: the profiled 64-bit integer VALU instructions per
+    # launch (v_mad_i64_i32 and the accumulator renormalisations), 64 lanes
+    # each, over the live launch time, against the same nominal peak
+    valu64 = fig.get("valu_int64_per_launch")
+    exec_frac = valu64 * 64 / avg_s / PEAK_INT_MUL if valu64 and avg_s > 0 else None
     out = {
         "metric": "multiprecision limb-MACs/s (whole job) and % int-mul peak of the update kernel; "
                   "lambda_min solves/s at 1e-40 rel",
@@ -387,6 +421,7 @@ def main():
                      "traffic": traffic, "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + "
                                                           "WRITE_SIZE, copy-calibrated)",
                      "traffic_source": traffic_src,
+                     "executed_int64_valu_frac": exec_frac,
                      "all_update_launches": {"launches": upd_n, "ms_per_step": upd_ms,
                                              "achieved": macs_per_step / (upd_ms * 1e-3) / 1e12 if upd_ms else 0,
                                              "frac": macs_per_step / (upd_ms * 1e-3) / PEAK_INT_MUL

@@ -539,12 +539,16 @@ hk_status hk_factor(hk_matrix m, hk_mpf shift, int inertia_mode, hipStream_t s, 
     HK_HIP(launch_fill32(D.flags, 16, 0, s));
     HK_HIP(launch_fill32(D.flags + 1, 1, INT_MAX, s));
     const int la = effective_lookahead(m);
+    const std::string why = factor_lds_check(m->B, la);
+    if (!why.empty()) return fail(HK_EINVAL, why);
     if (!m->s2 && la == 1) HK_HIP(hipStreamCreateWithFlags(&m->s2, hipStreamNonBlocking));
     HK_HIP(enqueue_factor(m->B, b, la, s, la == 1 ? m->s2 : nullptr, m->timing ? &evs : nullptr, &m->ev, &evi,
                           &m->n_update, &m->n_bulk));
   } else {
     const int la = lookahead_mode(m->lookahead, P.N, P.maxW);
     if (!m->gexec || m->gpanel != b || m->gla != la || m->gipw != m->B.ipw) {
+      const std::string why = factor_lds_check(m->B, la);
+      if (!why.empty()) return fail(HK_EINVAL, why);
       if (m->gexec) { (void)hipGraphExecDestroy(m->gexec); m->gexec = nullptr; }
       if (m->graph) { (void)hipGraphDestroy(m->graph); m->graph = nullptr; }
       if (!m->gcap) HK_HIP(hipStreamCreateWithFlags(&m->gcap, hipStreamNonBlocking));

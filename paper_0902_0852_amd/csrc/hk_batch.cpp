@@ -124,6 +124,8 @@ static hk_status ensure_graph(Batch& bt) {
   const int la = lookahead_mode(bt.lookahead, bt.maxN, maxW);
   if (bt.exec && bt.captured_panel == bt.panel && bt.captured_la == la && bt.captured_ipw == bt.B.ipw)
     return HK_OK;
+  const std::string why = factor_lds_check(bt.B, la);
+  if (!why.empty()) return dfail_b(HK_EINVAL, why);
   if (bt.exec) { (void)hipGraphExecDestroy(bt.exec); bt.exec = nullptr; }
   if (bt.graph) { (void)hipGraphDestroy(bt.graph); bt.graph = nullptr; }
   hipError_t e = hipSuccess;
@@ -422,6 +424,9 @@ hk_status hk_autotune(const hk_instance* inst, int count, void* dev_ws, size_t w
   for (int la = 0; la <= 2; la++) {
     for (int b : cand) {
       if (la == 2 && b != 1) continue;   // one column per launch: no panels
+      // the in-kernel look-ahead holds the update's operands in LDS too:
+      // skipped where its launches do not fit
+      if (la == 2 && !factor_lds_check(bt.B, 2).empty()) continue;
       double ms = 0;
       st = time_one(b, la, 4, ms);
       if (st != HK_OK) return st;

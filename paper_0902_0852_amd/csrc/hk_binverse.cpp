@@ -91,6 +91,10 @@ hk_status batch_inverse(Batch& bt, const std::vector<MP>& sigma, const std::vect
     plans.push_back(&m->P);
   }
   const SweepShape sh = sweep_shape(plans);
+  {
+    const std::string why = solve_lds_check(sh);
+    if (!why.empty()) return bfail(HK_EINVAL, why);
+  }
   hipError_t e = hipMemcpyAsync(bt.sargs, ha.data(), sizeof(SweepArgs) * count, hipMemcpyHostToDevice, s);
   // v0 = 1 (K fractional bits) for every active instance; flags cleared
   std::vector<std::vector<int32_t>> v0(count);

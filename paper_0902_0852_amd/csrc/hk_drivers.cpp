@@ -586,6 +586,10 @@ hk_status hk_solve(hk_matrix m, const void* dev_rhs, void* dev_x, hipStream_t s)
   if (!m->factored) return dfail(HK_EINVAL, "no valid factorisation");
   const Plan& P = m->P;
   const DevPtrs& D = m->D;
+  {
+    const std::string why = solve_lds_check(sweep_shape({&P}));
+    if (!why.empty()) return dfail(HK_EINVAL, why);
+  }
   // the batched sweeps with one instance: forward (acc = b 2^(h+g), z_k =
   // RNE(acc_k / 2^h) column by column), w_k = RNE(z_k 2^h / d_k), backward
   // (acc = w 2^h, y_k = RNE(acc_k / 2^h), last row first)

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/hk.h"
+#include "hk_moments.hpp"
 #include "hk_mp.hpp"
 
 struct hk_matrix_s;
@@ -67,10 +68,6 @@ int lookahead_mode(int setting, int maxN, int maxW);
 // named by HK_TUNE_CACHE for this batch shape
 struct Schedule { int panel = 0, lookahead = -1, ipw = 0; };
 Schedule tuned_schedule(const hk_instance* inst, int count);
-
-bool reduce_beta(int64_t num, int64_t den, uint32_t* p, uint32_t* q);
-double log2_mu(int n, uint32_t p, uint32_t q);
-bool build_moments(int N, uint32_t p, uint32_t q, int K, std::vector<MP>& X);
 
 // an hk_mpf as an integer with K fractional bits (false if it has more)
 bool shift_fixed(const hk_mpf& x, int K, MP& out);
@@ -138,6 +135,11 @@ inline bool update_is_bulk(int j) { return j == 0 || j == UPD_FAR; }
 hipError_t launch_update(const BatchView& B, int pc, int b, int j, int rd, hipStream_t s,
                          hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 hipError_t launch_fdiv(const BatchView& B, int c, int rd, hipStream_t s);
+// LDS per workgroup that the current device allows
+size_t device_lds_limit();
+// empty when every column launch of a factorisation in look-ahead mode `mode`
+// fits the device's LDS, else a message naming the first column that does not
+std::string factor_lds_check(const BatchView& B, int mode);
 hipError_t launch_column(const BatchView& B, int c, hipStream_t s, hipEvent_t t0 = nullptr,
                          hipEvent_t t1 = nullptr);
 hipError_t launch_gather_pivots_b(const BatchView& B, int32_t* out, int ld, hipStream_t s);
@@ -178,6 +180,8 @@ SweepArgs make_sweep_args(const Plan& P, const DevPtrs& D, int panel, int gbits)
 struct SweepShape { int count = 0, maxN = 0, maxVA = 0, maxVW = 0, maxLW = 0; int64_t maxVAN = 0;
                     size_t shm_div = 0, shm_scale = 0; };
 SweepShape sweep_shape(const std::vector<const Plan*>& plans);
+// empty when every launch of the solve sweeps fits the device's LDS, else why not
+std::string solve_lds_check(const SweepShape& sh);
 // Batched inverse-iteration steps (hk_kernels.hip):
 //   vinit_b  stage 0: acc = v 2^(h+g); stage 1: acc = w 2^h
 //   vcol_b   one column step of the forward (bwd 0) or backward (bwd 1) substitution

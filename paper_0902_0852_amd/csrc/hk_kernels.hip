@@ -18,6 +18,8 @@
 #include <climits>
 #include <hip/hip_ext.h>
 #include <cstring>
+#include <mutex>
+#include <string>
 
 #include "hk_internal.hpp"
 
@@ -1170,6 +1172,9 @@ __device__ void near_product(const int32_t* Lr, int nL, const int32_t* Cp, int n
   }
 }
 
+// LDS of the pivot's balanced and standard digits while it is finalised
+__host__ __device__ inline int pivot_scratch_bytes(int CW) { return 8 * CW; }
+
 // One column c in one launch: C = RNE(A / 2^h) for every row r in [c, N) and
 // L = RNE(C 2^h / d) for r > c.  Workgroups [0, n_near) are the rows: one
 // 128-lane workgroup per (instance, row); wavefront 0 finalises row r while
@@ -1182,8 +1187,10 @@ __device__ void near_product(const int32_t* Lr, int nL, const int32_t* Cp, int n
 // column c - 1 to the columns [c + 1, N), two items each; the next launch
 // finds every column it needs complete.  The accumulator, its carries
 // (plane rd) and the update's operands are read into LDS in one batch of
-// loads.  LDS: the pivot's digits (piv_bytes), then either the two product +
-// finalisation regions (fin_bytes each) or the division.
+// loads.  LDS: the pivot's normalised divisor, this row's standard digits and
+// the pivot's shift and sign (piv_bytes, live to the end), then either the
+// pivot's balanced and standard digits with the two product + finalisation
+// regions (fin_bytes each), or, once those are dead, the division.
 template <int DNIR>
 __device__ __forceinline__ void column_step(const InstDesc* __restrict__ desc, int count, int c, int n_near,
                                             int rd, int upd, int fin_bytes, int piv_bytes) {
@@ -1216,12 +1223,12 @@ __device__ __forceinline__ void column_step(const InstDesc* __restrict__ desc, i
   const int64_t cr_ltoff = gp(I.cols)[r].ltoff;
   const int cr_PT = gp(I.cols)[r].PT;
   char* base = (char*)smem;
-  int32_t* pC = (int32_t*)base;
-  uint32_t* pS = (uint32_t*)(pC + cc.CW);
-  uint32_t* pD = pS + cc.CW;
+  uint32_t* pD = (uint32_t*)base;            // pivot's normalised divisor
   uint32_t* oS = pD + cc.CW;                 // this row's standard digits
   int* pinfo = (int*)(oS + cc.CW);           // pivot: standard digits, shift, sign
-  char* wbase = base + piv_bytes + wave * fin_bytes;
+  int32_t* pC = (int32_t*)(base + piv_bytes);
+  uint32_t* pS = (uint32_t*)(pC + cc.CW);
+  char* wbase = base + piv_bytes + pivot_scratch_bytes(cc.CW) + wave * fin_bytes;
   int32_t* dg = (int32_t*)wbase;
   int32_t* ob = dg + (W + 48);
   int64_t* ca = (int64_t*)(ob + (W + 48));
@@ -1799,46 +1806,97 @@ static size_t divide_shm(int h, int num_cap, int den_cap) {
   const int nu_max = Sq + num_cap + 1;
   return sizeof(int64_t) * (size_t)((DOFF + nu_max + 3) + (16 + den_cap + 64 * 4 + 16) + (nu_max + 3));
 }
-hipError_t launch_fdiv(const BatchView& B, int c, int rd, hipStream_t s) {
-  int64_t rows = 0;
-  size_t fin = 0, piv = 0, div = 0;
+// LDS of one row workgroup of the column launches for column c: the live
+// pivot region, then the larger of the finalisation phase (pivot scratch and
+// two per-wave regions; with the rank-1 look-ahead update, the product digits
+// and the update's operands too) and the division.  *fin and *piv receive the
+// kernel's fin_bytes and piv_bytes.
+static size_t column_lds(const BatchView& B, int c, bool upd, int* fin_out, int* piv_out) {
+  size_t fin = 0, piv = 0, pcs = 0, div = 0;
   for (const Plan* p : B.plans)
     if (c < p->N) {
       const ColInfo& cc = p->cols[c];
-      rows += p->N - c;
-      fin = std::max(fin, fin_shm(cc.W, FIN_FB) + sizeof(int64_t) * (size_t)cc.W);
-      piv = std::max(piv, (sizeof(uint32_t) * (4 * (size_t)cc.CW + 4) + 7) / 8 * 8);
+      size_t f = fin_shm(cc.W, FIN_FB);
+      if (upd) {
+        const int Lw = c > 0 ? p->cols[c - 1].LW + 8 : 0, Cw = c > 0 ? p->cols[c - 1].CW : 0;
+        f += sizeof(int64_t) * (size_t)cc.W + sizeof(int32_t) * (size_t)(Lw + Cw);
+      }
+      fin = std::max(fin, f);
+      piv = std::max(piv, (sizeof(uint32_t) * (2 * (size_t)cc.CW + 4) + 7) / 8 * 8);
+      pcs = std::max(pcs, (size_t)pivot_scratch_bytes(cc.CW));
       div = std::max(div, divide_shm(p->h, cc.CW, cc.W + 2));
     }
   fin = (fin + 7) / 8 * 8;
+  if (fin_out) *fin_out = (int)fin;
+  if (piv_out) *piv_out = (int)piv;
+  return piv + std::max(pcs + 2 * fin, div);
+}
+// LDS of one workgroup of the forward/backward sweep launches
+static size_t vcol_lds(const SweepShape& sh) {
+  return (fin_shm(sh.maxVA, FIN_FB) + sizeof(int64_t) * (size_t)sh.maxVA +
+          sizeof(int32_t) * (size_t)(sh.maxLW + 8 + sh.maxVW) + 7) / 8 * 8;
+}
+size_t device_lds_limit() {
+  static std::mutex mu;
+  static int lim[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 65536;
+  std::lock_guard<std::mutex> g(mu);
+  if (!lim[dev]) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+      v = 65536;
+    lim[dev] = v;
+  }
+  return (size_t)lim[dev];
+}
+std::string factor_lds_check(const BatchView& B, int mode) {
+  const size_t lim = device_lds_limit();
+  int maxN = 0;
+  for (const Plan* p : B.plans) maxN = std::max(maxN, p->N);
+  for (int c = 0; c < maxN; c++) {
+    const size_t need = column_lds(B, c, mode == 2, nullptr, nullptr);
+    if (need > lim)
+      return "column " + std::to_string(c) + " needs " + std::to_string(need) +
+             " bytes of LDS per workgroup, above the device's " + std::to_string(lim) +
+             " (entries too wide: lower N or prec_bits" + (mode == 2 ? ", or use look-ahead mode 0 or 1)" : ")");
+  }
+  return "";
+}
+std::string solve_lds_check(const SweepShape& sh) {
+  const size_t lim = device_lds_limit();
+  const size_t need = std::max(vcol_lds(sh), std::max(sh.shm_div, sh.shm_scale));
+  if (need <= lim) return "";
+  return "the solve sweeps need " + std::to_string(need) + " bytes of LDS per workgroup, above the device's " +
+         std::to_string(lim) + " (vectors too wide: lower N or prec_bits)";
+}
+hipError_t launch_fdiv(const BatchView& B, int c, int rd, hipStream_t s) {
+  int64_t rows = 0;
+  for (const Plan* p : B.plans)
+    if (c < p->N) rows += p->N - c;
   if (rows <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fdiv, dim3((unsigned)rows), dim3(128), piv + std::max(2 * fin, div), s, B.ddesc,
-                     (int)B.plans.size(), c, rd, (int)rows, (int)fin, (int)piv);
+  int fin = 0, piv = 0;
+  const size_t shm = column_lds(B, c, false, &fin, &piv);
+  hipLaunchKernelGGL(k_fdiv, dim3((unsigned)rows), dim3(128), shm, s, B.ddesc, (int)B.plans.size(), c, rd,
+                     (int)rows, fin, piv);
   return hipGetLastError();
 }
 hipError_t launch_column(const BatchView& B, int c, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
   int64_t rows = 0, items = 0;
-  size_t fin = 0, piv = 0, div = 0;
   for (const Plan* p : B.plans) {
-    if (c < p->N) {
-      const ColInfo& cc = p->cols[c];
-      const int Lw = c > 0 ? p->cols[c - 1].LW + 8 : 0, Cw = c > 0 ? p->cols[c - 1].CW : 0;
-      rows += p->N - c;
-      fin = std::max(fin, fin_shm(cc.W, FIN_FB) + sizeof(int64_t) * (size_t)cc.W + sizeof(int32_t) * (size_t)(Lw + Cw));
-      piv = std::max(piv, (sizeof(uint32_t) * (4 * (size_t)cc.CW + 4) + 7) / 8 * 8);
-      div = std::max(div, divide_shm(p->h, cc.CW, cc.W + 2));
-    }
+    if (c < p->N) rows += p->N - c;
     if (c > 0) items += update_items(*p, c - 1, 1, UPD_FAR);
   }
-  fin = (fin + 7) / 8 * 8;
   if (rows <= 0 && items <= 0) return mark_empty(t0, t1, s);
+  int fin = 0, piv = 0;
+  const size_t shm = column_lds(B, c, true, &fin, &piv);
   const int64_t blocks = rows + (items + 1) / 2;
   if (t0 || t1)
-    hipExtLaunchKernelGGL(k_column, dim3((unsigned)blocks), dim3(128), piv + std::max(2 * fin, div), s, t0, t1,
-                          0, B.ddesc, (int)B.plans.size(), c, (int)rows, (int)fin, (int)piv);
+    hipExtLaunchKernelGGL(k_column, dim3((unsigned)blocks), dim3(128), shm, s, t0, t1, 0, B.ddesc,
+                          (int)B.plans.size(), c, (int)rows, fin, piv);
   else
-    hipLaunchKernelGGL(k_column, dim3((unsigned)blocks), dim3(128), piv + std::max(2 * fin, div), s, B.ddesc,
-                       (int)B.plans.size(), c, (int)rows, (int)fin, (int)piv);
+    hipLaunchKernelGGL(k_column, dim3((unsigned)blocks), dim3(128), shm, s, B.ddesc, (int)B.plans.size(), c,
+                       (int)rows, fin, piv);
   return hipGetLastError();
 }
 hipError_t launch_gather_pivots_b(const BatchView& B, int32_t* out, int ld, hipStream_t s) {
@@ -1881,8 +1939,7 @@ hipError_t launch_vcol_b(const SweepArgs* args, const SweepShape& sh, int bwd, i
   // far rows of the widest instance bound the item count
   const int rows = bwd ? k : sh.maxN - k - 1;
   const int64_t items = j > 0 && rows > 0 ? (int64_t)((rows + 63) / 64) * (sh.maxVA / WB) : 0;
-  const size_t fin = (fin_shm(sh.maxVA, FIN_FB) + sizeof(int64_t) * (size_t)sh.maxVA +
-                      sizeof(int32_t) * (size_t)(sh.maxLW + 8 + sh.maxVW) + 7) / 8 * 8;
+  const size_t fin = vcol_lds(sh);
   hipLaunchKernelGGL(k_vcol_b, dim3((unsigned)((items + 1 + 3) / 4), sh.count), dim3(256), fin, s, args, bwd, k,
                      j, (int)fin);
   return hipGetLastError();

@@ -107,3 +107,31 @@ def test_batched_factors_match_golden_batch(hk, panel, la):
         assert bad == [], (i, bad[:5])
         assert hashlib.sha256(canon_bytes(m.pivots())).hexdigest() == x["pivots"]
         assert m.limb_macs() == x["limb_macs"]
+
+
+def test_batched_workload_64_instances(hk):
+    # the batched workload's shape: 64 seeded instances, N uniform in
+    # [50, 400], beta = p/q (p, q in 1..8, 1/2 <= beta <= 3), K from 1024 at
+    # N = 50 to 8192 at N = 400; every lambda_1 equals the single-instance
+    # path's digit for digit, and the four smallest instances the oracle's
+    # to 1e-40
+    import math
+    rng = random.Random(9020852)
+    insts = []
+    while len(insts) < 64:
+        N = rng.randint(50, 400)
+        p, q = rng.randint(1, 8), rng.randint(1, 8)
+        b = Fraction(p, q)
+        if Fraction(1, 2) <= b <= 3:
+            insts.append((N, (b.numerator, b.denominator), 64 * math.ceil((1024 + 7168 * (N - 50) / 350) / 64)))
+    log("batched workload: 64 instances, N %d..%d" % (min(i[0] for i in insts), max(i[0] for i in insts)))
+    res, rep = hk.eig_batched(insts, digits=45)
+    assert rep["status"] == 0
+    for (N, beta, K), (st, dec, ver, nf) in zip(insts, res):
+        assert st == 0 and ver == 1, (N, beta, K)
+        d1, r1 = hk.smallest_eig(N, beta, K, method=hk.HK_SECANT, digits=45, flags=hk.HK_FLAG_NO_WORK_COUNT)
+        assert d1 == dec, (N, beta, K, d1, dec)
+    for N, beta, K in sorted(insts)[:4]:
+        lam_o, _ = inverse_iteration(N, beta, K)
+        i = insts.index((N, beta, K))
+        assert rel_digits(parse_dec(res[i][1]), lam_o) > 40, (N, beta, K)

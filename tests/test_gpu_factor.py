@@ -204,3 +204,34 @@ def test_update_group_invariance(hk, group, la):
     m.set_update_group(group)
     m.factor(xf)
     compare(m, of, N)
+
+
+@pytest.mark.parametrize("la", [0, 1])
+def test_widest_entries_vs_oracle(hk, la):
+    # entries of about 3800 digits: the finalise/divide launch's LDS (pivot,
+    # this row's digits, two finalisation regions, then the division over the
+    # dead finalisation regions) sits just under what a workgroup may hold
+    N, beta, K = 16, (1, 1), 110000
+    log("widest entries N=%d K=%d look-ahead %d" % (N, K, la))
+    X = moments(N, beta, K)
+    of = oracle.factor_from_moments(X, N, K, 0)
+    m = hk.Matrix(N, beta, K)
+    m.set_panel(4)
+    m.set_lookahead(la)
+    m.factor(0)
+    assert m.info().max_col_digits > 3700
+    compare(m, of, N)
+
+
+def test_lds_limit_reported(hk):
+    # the in-kernel look-ahead launch also holds the update's operands in LDS:
+    # at these widths it does not fit, and the factorisation says so before
+    # launching anything
+    m = hk.Matrix(16, (1, 1), 110000)
+    m.set_lookahead(2)
+    with pytest.raises(hk.HKError, match="LDS"):
+        m.factor(0)
+    # the same matrix still factors in a mode that fits
+    m.set_lookahead(0)
+    m.factor(0)
+    assert m.pivots()[0] > 0
