@@ -16,7 +16,7 @@
 #include <thread>
 #include <vector>
 
-#include "hk_internal.hpp"
+#include "hk_moments.hpp"
 
 namespace hk {
 
