@@ -38,6 +38,7 @@ CONFIGS = {
     "c5": dict(runs=[(1500, (3, 2), 24576)], desc="N=1500 beta=3/2 K=24576"),
 }
 PEAK_INT_MUL = 256 * 64 * 2.4e9       # one 32x32 multiply per lane per clock
+PEAK_INT8_OPS = 5.0e15                 # dense int8 matrix-core peak
 HBM_PEAK = 8.0e12
 HERE = os.path.dirname(os.path.abspath(__file__))
 PROFILE_TAG = {"c2": "N200_beta7-4_K2048_secant", "c3b1": "N500_beta1_K6144_secant", "c3": "N500_K6144_4beta"}
@@ -277,6 +278,134 @@ def lambda_table(args):
                               "solves": rep["solves"], "seconds": dt}), flush=True)
 
 
+def roofline_record(hk, engine, macs_bulk, bulk_ms, bulk_n, macs_per_step, upd_ms, upd_n, ms_step, fig,
+                    traffic, traffic_src, kernel):
+    """The roofline record of the kernel that carries the bulk of the update
+    work.  On the matrix cores (k_update_mma) the algorithmic work is priced
+    as int8 matrix operations: one 32-bit limb-MAC is 16 int8 multiply-adds
+    (32 ops), against the dense int8 peak (5.0 POP/s); on the vector units
+    (k_update, k_column) against one 32-bit multiply per lane per clock."""
+    achieved = macs_bulk / (bulk_ms * 1e-3) if bulk_ms > 0 else 0.0
+    avg_s = 1e-3 * bulk_ms / max(bulk_n, 1)
+    valu64 = fig.get("valu_int64_per_launch")
+    all_rate = macs_per_step / (upd_ms * 1e-3) if upd_ms else 0.0
+    rec = {"launches": bulk_n, "avg_launch_us": 1e3 * bulk_ms / max(bulk_n, 1),
+           "limb_macs_per_launch": macs_bulk / max(bulk_n, 1),
+           "work_share": macs_bulk / macs_per_step if macs_per_step else None,
+           "time_share_of_step": bulk_ms / ms_step,
+           "traffic": traffic, "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                                              "copy-calibrated)",
+           "traffic_source": traffic_src,
+           "limb_mac_rate_T": achieved / 1e12}
+    if engine == 1:
+        rec.update({"bound": "mfma", "kernel": "k_update_mma (the bulk of the trailing update on the matrix "
+                                               "cores: int8 byte-plane products, v_mfma_i32_32x32x32_i8)",
+                    "achieved": 32 * achieved / 1e12, "peak": PEAK_INT8_OPS / 1e12, "unit": "TOP/s",
+                    "op_basis": "int8 ops of the algorithmic 32-bit limb-MACs (32 per limb-MAC)",
+                    "frac": 32 * achieved / PEAK_INT8_OPS,
+                    "all_update_launches": {"launches": upd_n, "ms_per_step": upd_ms,
+                                            "achieved": 32 * all_rate / 1e12, "frac": 32 * all_rate / PEAK_INT8_OPS}})
+    else:
+        rec.update({"bound": "alu", "kernel": kernel,
+                    "achieved": achieved / 1e12, "peak": PEAK_INT_MUL / 1e12, "unit": "Tlimb-MAC/s",
+                    "frac": achieved / PEAK_INT_MUL,
+                    "executed_int64_valu_frac": valu64 * 64 / avg_s / PEAK_INT_MUL if valu64 and avg_s > 0 else None,
+                    "all_update_launches": {"launches": upd_n, "ms_per_step": upd_ms,
+                                            "achieved": all_rate / 1e12, "frac": all_rate / PEAK_INT_MUL}})
+    return rec
+
+
+def plain_batched(args, cfg, hk, torch):
+    """The workload's runs as one batch per step (hk_eig_batched: the Secant
+    iterations of all runs in lockstep, every factorisation launch covering
+    all of them, then the inertia bracket for all).  The algorithmic work
+    and lambda_1 come from one untimed run of each instance alone
+    (hk_smallest_eig with the same schedule): the batch must reproduce every
+    lambda_1 digit for digit with the same number of factorisations."""
+    import tempfile
+    runs = cfg["runs"]
+    if args.method != "secant":
+        raise SystemExit("the batched driver runs the Secant iteration")
+    tune_path = os.path.join(tempfile.gettempdir(), "hk_tune_%d.txt" % os.getpid())
+    os.environ["HK_TUNE_CACHE"] = tune_path
+    if args.panel > 0:
+        panel, la, group = args.panel, args.lookahead, args.group or 4
+    else:
+        panel, la, group = hk.autotune(runs, cache_path=tune_path)
+        group = args.group or group
+    la_flag = {0: hk.HK_FLAG_LOOKAHEAD_OFF, 1: hk.HK_FLAG_LOOKAHEAD_ON, 2: hk.HK_FLAG_LOOKAHEAD_FUSED}.get(la, 0)
+    bflags = la_flag | hk.HK_FLAG_GROUP(group)
+    log("batch of %d runs: panel width %d, look-ahead %d, %d update items per workgroup (%s)"
+        % (len(runs), panel, la, group, "given" if args.panel > 0 else "tuned"))
+    ws = torch.empty(hk.batch_workspace_bytes(runs), dtype=torch.uint8, device="cuda")
+    # untimed reference: each run alone, with its work count
+    wss = torch.empty(max(hk.workspace_bytes(N, beta, K) for N, beta, K in runs), dtype=torch.uint8,
+                      device="cuda")
+    single = []
+    for N, beta, K in runs:
+        dec, r = hk.smallest_eig(N, beta, K, method=hk.HK_SECANT, digits=45, ws=wss,
+                                 flags=hk.HK_FLAG_PANEL(panel) | bflags)
+        assert r["verified"] == 1
+        single.append((dec, r))
+    del wss
+    macs_per_step = sum(r["limb_macs"] for _, r in single)
+    macs_bulk = sum(r["limb_macs_bulk"] for _, r in single)
+    lams = [dec for dec, _ in single]
+
+    def one_step(extra):
+        res, d = hk.eig_batched(runs, digits=45, panel=panel, ws=ws, method=hk.HK_SECANT, flags=bflags | extra)
+        for (st, dec, ver, nf), (dec1, r1) in zip(res, single):
+            assert st == 0 and ver == 1, (st, dec)
+            assert dec == dec1 and nf == r1["factorizations"], (dec, dec1, nf, r1["factorizations"])
+        return d
+    log("work per step: %.4e limb-MACs over %d factorisations; lambda_1 = %s"
+        % (macs_per_step, sum(r["factorizations"] for _, r in single), ", ".join(lams)))
+    for _ in range(max(1, args.warmup)):
+        one_step(0)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    for _ in range(args.steps):
+        one_step(0)
+    torch.cuda.synchronize()
+    dt = time.time() - t0
+    ms_step = 1e3 * dt / args.steps
+    value = macs_per_step * args.steps / dt
+    # one more step with every update launch timed on HIP events of the
+    # stream it runs on (launched one by one instead of the graph replay)
+    d = one_step(hk.HK_FLAG_TIME_UPDATES)
+    torch.cuda.synchronize()
+    engine = d["update_engine"]
+    kernel = "k_update_mma" if engine == 1 else "k_update"
+    traffic, traffic_src = measured_traffic(args.config, kernel)
+    fig, _ = profile_figures(args.config, kernel)
+    rec = roofline_record(hk, engine, macs_bulk, d["bulk_ms"], d["bulk_launches"], macs_per_step,
+                          d["update_ms"], d["update_launches"], ms_step, fig, traffic, traffic_src,
+                          "k_update (the bulk of the trailing update on the vector units)")
+    out = {
+        "metric": "multiprecision limb-MACs/s (whole job) and % int-mul peak of the update kernel; "
+                  "lambda_min solves/s at 1e-40 rel",
+        "value": value, "unit": "limb-MAC/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "lambda_1 of the Hankel moment matrix, %s, Secant driver, all runs of a step "
+                               "as one batch, verified to 45 digits" % cfg["desc"],
+                   "N": [N for N, _, _ in runs], "beta": ["%d/%d" % b for _, b, _ in runs],
+                   "prec_bits": [K for _, _, K in runs], "method": "secant", "driver": "batched",
+                   "panel": panel, "lookahead": la, "update_group": group,
+                   "update_engine": "matrix cores" if engine == 1 else "vector units"},
+        "lambda_solves_per_s": len(runs) * args.steps / dt,
+        "lambda_1": lams,
+        "roofline": rec,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(cfg, args.method)
+    try:
+        os.remove(tune_path)
+    except OSError:
+        pass
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -299,6 +428,10 @@ def main():
     ap.add_argument("--panel", type=int, default=0, help="panel width (0: tuned here / tuned or 4 in learned mode)")
     ap.add_argument("--group", type=int, default=0, choices=[0, 1, 2, 4],
                     help="update items per workgroup (0: tuned, else 4)")
+    ap.add_argument("--driver", default="", choices=["", "single", "batched"],
+                    help="single: the runs one after another (hk_smallest_eig); batched: all runs of a "
+                         "step as one batch (hk_eig_batched, lockstep Secant); default batched when the "
+                         "workload has several runs")
     ap.add_argument("--lookahead", type=int, default=-1, choices=[-1, 0, 1, 2],
                     help="with --panel: look-ahead mode 0 none, 1 second stream, 2 one launch per column "
                          "(-1: chosen by size)")
@@ -321,6 +454,9 @@ def main():
     cfg = CONFIGS[args.config]
     runs = cfg["runs"]
     method = hk.HK_SECANT if args.method == "secant" else hk.HK_INVERSE
+    if args.driver == "batched" or (args.driver == "" and len(runs) > 1):
+        plain_batched(args, cfg, hk, torch)
+        return
     ws = torch.empty(max(hk.workspace_bytes(N, beta, K) for N, beta, K in runs), dtype=torch.uint8, device="cuda")
     # untimed: the schedule tuned for each shape (hk_autotune; the library
     # reads it back from the cache named by HK_TUNE_CACHE)
@@ -387,15 +523,13 @@ def main():
              "the update of the columns beyond)" if fused else
              "k_update (the bulk of the trailing update: each panel's update of the columns beyond the next "
              "panel under look-ahead, or its whole trailing update without)")
-    achieved = macs_bulk / (bulk_ms * 1e-3) if bulk_ms > 0 else 0.0
+    engine = 0 if fused else res_t[0][1]["update_engine"]
+    if engine == 1:
+        kernel = "k_update_mma"
     traffic, traffic_src = measured_traffic(args.config, kernel)
     fig, _ = profile_figures(args.config, kernel)
-    avg_s = 1e-3 * bulk_ms / max(bulk_n, 1)
-    # executed multiplies: the profiled 64-bit integer VALU instructions per
-    # launch (v_mad_i64_i32 and the accumulator renormalisations), 64 lanes
-    # each, over the live launch time, against the same nominal peak
-    valu64 = fig.get("valu_int64_per_launch")
-    exec_frac = valu64 * 64 / avg_s / PEAK_INT_MUL if valu64 and avg_s > 0 else None
+    rec = roofline_record(hk, engine, macs_bulk, bulk_ms, bulk_n, macs_per_step, upd_ms, upd_n, ms_step, fig,
+                          traffic, traffic_src, kdesc)
     out = {
         "metric": "multiprecision limb-MACs/s (whole job) and % int-mul peak of the update kernel; "
                   "lambda_min solves/s at 1e-40 rel",
@@ -410,22 +544,7 @@ def main():
                    "update_group": [g for _, _, g in scheds]},
         "lambda_solves_per_s": len(runs) * args.steps / dt,
         "lambda_1": lams,
-        "roofline": {"bound": "alu", "kernel": kdesc,
-                     "achieved": achieved / 1e12, "peak": PEAK_INT_MUL / 1e12,
-                     "unit": "Tlimb-MAC/s", "frac": achieved / PEAK_INT_MUL,
-                     "launches": bulk_n,
-                     "avg_launch_us": 1e3 * bulk_ms / max(bulk_n, 1),
-                     "limb_macs_per_launch": macs_bulk / max(bulk_n, 1),
-                     "work_share": macs_bulk / macs_per_step if macs_per_step else None,
-                     "time_share_of_step": bulk_ms / ms_step,
-                     "traffic": traffic, "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + "
-                                                          "WRITE_SIZE, copy-calibrated)",
-                     "traffic_source": traffic_src,
-                     "executed_int64_valu_frac": exec_frac,
-                     "all_update_launches": {"launches": upd_n, "ms_per_step": upd_ms,
-                                             "achieved": macs_per_step / (upd_ms * 1e-3) / 1e12 if upd_ms else 0,
-                                             "frac": macs_per_step / (upd_ms * 1e-3) / PEAK_INT_MUL
-                                             if upd_ms else 0}},
+        "roofline": rec,
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, args.method)

@@ -68,8 +68,10 @@ enum { HK_INVERSE = 0, HK_SECANT = 1 };
 /* flags or-ed into the method argument of hk_smallest_eig */
 enum { HK_FLAG_NO_WORK_COUNT = 0x100,   /* skip the limb-MAC count (report 0)    */
        HK_FLAG_TIME_UPDATES = 0x200,    /* time every trailing-update launch      */
-       HK_FLAG_CERTIFY = 0x400 };       /* prove the inertia bracket (hk_certify
+       HK_FLAG_CERTIFY = 0x400,         /* prove the inertia bracket (hk_certify
                                            on both bracket factorisations)       */
+       HK_FLAG_VECTOR_UPDATE = 0x800 }; /* the bulk of the trailing update on the
+                                           vector units (hk_set_update_engine)   */
 /* panel width p in 1..64 forced for hk_smallest_eig: or HK_FLAG_PANEL(p)
    into the method argument (0: the tuned width, else 4) */
 #define HK_FLAG_PANEL(p) (((p) & 0xff) << 16)
@@ -107,6 +109,9 @@ typedef struct {
                              (mode 2); the rest are k_update_near launches
                              (in-panel updates, the next panel's columns)     */
   double bulk_ms;         /* summed device time of the bulk launches          */
+  int update_engine;      /* engine of the bulk launches at the current panel
+                             width: 1 matrix cores (k_update_mma), 0 vector
+                             units (k_update, or k_column in mode 2)          */
 } hk_info;
 
 typedef struct {
@@ -132,6 +137,7 @@ typedef struct {
   hk_mpf lambda;          /* lambda_1 in binary (sign 0: none); its digits
                              point at lambda_words of this same report       */
   uint32_t lambda_words[HK_LAMBDA_WORDS];
+  int update_engine;      /* hk_info's update_engine of the factorisations    */
 } hk_report;
 
 /* Bytes of device workspace needed for (N, beta, K).  flags: reserved, 0.
@@ -240,6 +246,16 @@ hk_status hk_set_panel(hk_matrix m, int panel);
    workgroup of the update kernels, 1, 2 or 4 (the default, or the tuned
    value); HK_EINVAL otherwise. */
 hk_status hk_set_update_group(hk_matrix m, int items);
+/* Engine of the bulk of the trailing update ("The LDL^T Determinant
+   Algorithm", the update of the columns beyond the panel; the digits are the
+   same either way): HK_UPDATE_MATRIX_CORES (the default) splits every digit
+   of C and L into four signed bytes and accumulates the digit products as
+   int8 matrix products (v_mfma_i32_32x32x32_i8) wherever the panel width b
+   and the widest column W keep b W below 32704 (int32 accumulators), and
+   uses the vector units elsewhere; HK_UPDATE_VECTOR always uses the vector
+   units (v_mad_i64_i32).  HK_EINVAL for other values. */
+enum { HK_UPDATE_MATRIX_CORES = 0, HK_UPDATE_VECTOR = 1 };
+hk_status hk_set_update_engine(hk_matrix m, int engine);
 /* Look-ahead ("The LDL^T Determinant Algorithm", parallel version: the next
    panel's columns are updated first): mode 1 splits every trailing update
    into the next panel's columns, on the critical path, and the rest, on a
@@ -335,6 +351,12 @@ typedef struct {
   double t_build_s;       /* moments + uploads                           */
   double t_factor_s;      /* graph replays incl. pivot read-back         */
   double t_total_s;
+  int update_launches;    /* HK_FLAG_TIME_UPDATES: update launches of all
+                             factorisations and their summed device time  */
+  double update_ms;
+  int bulk_launches;      /* of those, the bulk launches (hk_info)       */
+  double bulk_ms;
+  int update_engine;      /* hk_info's update_engine of the batch        */
 } hk_batch_report;
 
 /* Device bytes for a batch (one buffer for all instances). 0 if invalid. */
@@ -347,7 +369,11 @@ size_t hk_batch_workspace_bytes(const hk_instance* inst, int count);
    iteration together; then the inertia bracket ("Interval Verification")
    for all.  panel = 0 takes the width from the tuning
    cache named by the environment variable HK_TUNE_CACHE when it has an entry
-   for this batch shape, else 4.  out[count] receives the per-instance
+   for this batch shape, else 4.  The first instance's method may carry the
+   hk_smallest_eig flags HK_FLAG_LOOKAHEAD_*, HK_FLAG_GROUP(g),
+   HK_FLAG_VECTOR_UPDATE and HK_FLAG_TIME_UPDATES (every factorisation then
+   launched one by one with its update launches timed, in rep); they apply to
+   the whole batch.  out[count] receives the per-instance
    results; the call returns HK_OK if every instance succeeded (otherwise the
    first failing status).  rep may be NULL.  Synchronises s. */
 hk_status hk_eig_batched(const hk_instance* inst, int count, int digits, int panel, void* dev_ws,

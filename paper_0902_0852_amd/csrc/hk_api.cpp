@@ -61,13 +61,16 @@ bool make_plan(int N, int64_t bnum, int64_t bden, int K, Plan& P, std::string& e
   for (int r = N - 1; r >= 0; r--) sufmax[r] = std::max(sufmax[r + 1], bX[2 * r]);
   P.cols.resize(N);
   P.itemStart.assign(N + 1, 0);
-  int64_t a = 0, kk = 0, cc = 0, ll = 0, dd = 0;
+  P.tileStart.assign(N + 1, 0);
+  int64_t a = 0, kk = 0, cc = 0, ll = 0, l8 = 0, dd = 0;
   P.maxW = 0;
   for (int c = 0; c < N; c++) {
     ColInfo& ci = P.cols[c];
     // |A_rc| <= sqrt(A_rr A_cc) while the trailing block is positive definite
     int64_t Bc = (sufmax[c] + bX[2 * c] + 1) / 2 + 4;
-    int W = round_up((int)((Bc + DB - 1) / DB) + 4, WB);
+    // a whole number of 32-digit tiles (the matrix-core update works on two
+    // 16-digit blocks at a time)
+    int W = round_up((int)((Bc + DB - 1) / DB) + 4, 2 * WB);
     ci.W = W;
     ci.R = round_up(N - c, 64);
     ci.nb = W / WB;
@@ -79,8 +82,11 @@ bool make_plan(int N, int64_t bnum, int64_t bden, int K, Plan& P, std::string& e
     ci.coff = cc; cc += (int64_t)(N - c) * ci.CW;
     ci.soff = ci.coff;
     ci.loff = ll; ll += (int64_t)ci.LW * ci.R;
+    ci.G = (ci.LW + 31) / 32;
+    ci.l8off = l8; l8 += (int64_t)4 * ci.G * ci.R * 32;
     ci.doff = dd; dd += W + 2;
     P.itemStart[c + 1] = P.itemStart[c] + ci.items;
+    P.tileStart[c + 1] = P.tileStart[c] + ci.R / 32;
     P.maxW = std::max(P.maxW, W);
   }
   if ((int64_t)P.itemStart[N] >= (int64_t)INT_MAX / 2) { err = "problem too large"; return false; }
@@ -107,11 +113,13 @@ bool make_plan(int N, int64_t bnum, int64_t bden, int K, Plan& P, std::string& e
   auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
   P.o_cols = take(sizeof(ColInfo) * N);
   P.o_items = take(sizeof(int32_t) * (N + 1));
+  P.o_tiles = take(sizeof(int32_t) * (N + 1));
   P.o_A = take(sizeof(int32_t) * a);
   P.o_K = take(sizeof(int64_t) * kk);
   P.o_C = take(sizeof(int32_t) * cc);
   P.o_S = take(sizeof(uint32_t) * cc);
   P.o_L = take(sizeof(int32_t) * ll);
+  P.o_L8 = take((size_t)l8);
   P.o_D = take(sizeof(uint32_t) * dd);
   P.o_dinfo = take(sizeof(int32_t) * 4 * N);
   P.o_nC = take(sizeof(int32_t) * P.ntri);
@@ -146,11 +154,13 @@ DevPtrs dev_ptrs(const Plan& P, char* ws) {
   DevPtrs D;
   D.cols = (ColInfo*)(ws + P.o_cols);
   D.itemStart = (int32_t*)(ws + P.o_items);
+  D.tileStart = (int32_t*)(ws + P.o_tiles);
   D.A = (int32_t*)(ws + P.o_A);
   D.Kc = (int64_t*)(ws + P.o_K);
   D.C = (int32_t*)(ws + P.o_C);
   D.S = (uint32_t*)(ws + P.o_S);
   D.L = (int32_t*)(ws + P.o_L);
+  D.L8 = (int8_t*)(ws + P.o_L8);
   D.D = (uint32_t*)(ws + P.o_D);
   D.dinfo = (int32_t*)(ws + P.o_dinfo);
   D.nC = (int32_t*)(ws + P.o_nC);
@@ -182,8 +192,8 @@ DevPtrs dev_ptrs(const Plan& P, char* ws) {
 
 InstDesc make_desc(const Plan& P, const DevPtrs& D) {
   InstDesc I;
-  I.cols = D.cols; I.itemStart = D.itemStart;
-  I.A = D.A; I.Kc = D.Kc; I.C = D.C; I.S = D.S; I.L = D.L; I.LT = D.LT; I.D = D.D;
+  I.cols = D.cols; I.itemStart = D.itemStart; I.tileStart = D.tileStart;
+  I.A = D.A; I.Kc = D.Kc; I.C = D.C; I.S = D.S; I.L = D.L; I.L8 = D.L8; I.LT = D.LT; I.D = D.D;
   I.dinfo = D.dinfo; I.nC = D.nC; I.nCs = D.nCs; I.nL = D.nL; I.b32C = D.b32C; I.flags = D.flags;
   I.X = D.X; I.xs = D.xs;
   I.N = P.N; I.h = P.h; I.WX = P.WX; I.active = 1;
@@ -362,6 +372,13 @@ hk_status hk_set_update_group(hk_matrix m, int items) {
   return HK_OK;
 }
 
+hk_status hk_set_update_engine(hk_matrix m, int engine) {
+  if (!m || (engine != HK_UPDATE_MATRIX_CORES && engine != HK_UPDATE_VECTOR))
+    return fail(HK_EINVAL, "engine must be HK_UPDATE_MATRIX_CORES or HK_UPDATE_VECTOR");
+  m->B.mma = engine == HK_UPDATE_MATRIX_CORES ? 1 : 0;
+  return HK_OK;
+}
+
 }  // extern "C"
 
 namespace hk {
@@ -409,6 +426,7 @@ hk_status build_matrix_impl(int N, hk_rational beta, int prec_bits, void* dev_ws
   if (e == hipSuccess) e = cp(m->D.desc, &m->desc_host, sizeof(InstDesc));
   if (e == hipSuccess) e = cp(m->D.cols, P.cols.data(), P.cols.size() * sizeof(ColInfo));
   if (e == hipSuccess) e = cp(m->D.itemStart, P.itemStart.data(), P.itemStart.size() * sizeof(int32_t));
+  if (e == hipSuccess) e = cp(m->D.tileStart, P.tileStart.data(), P.tileStart.size() * sizeof(int32_t));
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) { delete m; return fail(HK_EDEVICE, std::string("upload: ") + hipGetErrorString(e)); }
   *out = m;
@@ -511,6 +529,7 @@ hk_status hk_matrix_info(hk_matrix m, hk_info* o) {
   o->n_update_launches = m->n_update; o->update_ms = m->update_ms;
   o->n_bulk_launches = m->n_bulk; o->bulk_ms = m->bulk_ms;
   o->lookahead = lookahead_mode(m->lookahead, P.N, P.maxW);
+  o->update_engine = o->lookahead != 2 && mma_width(m->B, m->panel) > 0 ? 1 : 0;
   return HK_OK;
 }
 
@@ -546,7 +565,7 @@ hk_status hk_factor(hk_matrix m, hk_mpf shift, int inertia_mode, hipStream_t s, 
                           &m->n_update, &m->n_bulk));
   } else {
     const int la = lookahead_mode(m->lookahead, P.N, P.maxW);
-    if (!m->gexec || m->gpanel != b || m->gla != la || m->gipw != m->B.ipw) {
+    if (!m->gexec || m->gpanel != b || m->gla != la || m->gipw != m->B.ipw || m->gmma != m->B.mma) {
       const std::string why = factor_lds_check(m->B, la);
       if (!why.empty()) return fail(HK_EINVAL, why);
       if (m->gexec) { (void)hipGraphExecDestroy(m->gexec); m->gexec = nullptr; }
@@ -569,6 +588,7 @@ hk_status hk_factor(hk_matrix m, hk_mpf shift, int inertia_mode, hipStream_t s, 
       m->gpanel = b;
       m->gla = la;
       m->gipw = m->B.ipw;
+      m->gmma = m->B.mma;
       m->g_nupdate = nu;
       m->g_nbulk = nbk;
     }

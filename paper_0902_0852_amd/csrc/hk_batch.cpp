@@ -32,7 +32,9 @@ Batch::~Batch() {
   if (graph) (void)hipGraphDestroy(graph);
   if (cap) (void)hipStreamDestroy(cap);
   if (cap2) (void)hipStreamDestroy(cap2);
+  if (s2) (void)hipStreamDestroy(s2);
   for (hipEvent_t ev : events) (void)hipEventDestroy(ev);
+  for (hipEvent_t ev : tevents) (void)hipEventDestroy(ev);
   for (auto m : mats) hk_matrix_destroy(m);
 }
 
@@ -122,10 +124,12 @@ static hk_status ensure_graph(Batch& bt) {
   int maxW = 0;
   for (const Plan* p : bt.B.plans) maxW = std::max(maxW, p->maxW);
   const int la = lookahead_mode(bt.lookahead, bt.maxN, maxW);
-  if (bt.exec && bt.captured_panel == bt.panel && bt.captured_la == la && bt.captured_ipw == bt.B.ipw)
-    return HK_OK;
   const std::string why = factor_lds_check(bt.B, la);
   if (!why.empty()) return dfail_b(HK_EINVAL, why);
+  if (bt.timing) return HK_OK;   // launched one by one
+  if (bt.exec && bt.captured_panel == bt.panel && bt.captured_la == la && bt.captured_ipw == bt.B.ipw &&
+      bt.captured_mma == bt.B.mma)
+    return HK_OK;
   if (bt.exec) { (void)hipGraphExecDestroy(bt.exec); bt.exec = nullptr; }
   if (bt.graph) { (void)hipGraphDestroy(bt.graph); bt.graph = nullptr; }
   hipError_t e = hipSuccess;
@@ -150,6 +154,7 @@ static hk_status ensure_graph(Batch& bt) {
   bt.captured_panel = bt.panel;
   bt.captured_la = la;
   bt.captured_ipw = bt.B.ipw;
+  bt.captured_mma = bt.B.mma;
   return HK_OK;
 }
 
@@ -170,7 +175,25 @@ hk_status factor_batch(Batch& bt, const std::vector<MP>& x, const std::vector<in
   }
   if (e == hipSuccess)
     e = hipMemcpyAsync(bt.ddesc, bt.hdesc.data(), sizeof(InstDesc) * bt.count, hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipGraphLaunch(bt.exec, s);
+  std::vector<TimedLaunch> evs;
+  if (e == hipSuccess && bt.timing) {
+    int maxW = 0;
+    for (const Plan* p : bt.B.plans) maxW = std::max(maxW, p->maxW);
+    const int la = lookahead_mode(bt.lookahead, bt.maxN, maxW);
+    if (!bt.s2 && la == 1) e = hipStreamCreateWithFlags(&bt.s2, hipStreamNonBlocking);
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(k_reset_flags, dim3((bt.count * 16 + 255) / 256), dim3(256), 0, s, bt.flags, bt.count);
+      e = hipGetLastError();
+    }
+    size_t evi = 0;
+    int nu = 0, nbk = 0;
+    if (e == hipSuccess)
+      e = enqueue_factor(bt.B, bt.panel, la, s, la == 1 ? bt.s2 : nullptr, &evs, &bt.tevents, &evi, &nu, &nbk);
+    bt.n_update += nu;
+    bt.n_bulk += nbk;
+  } else if (e == hipSuccess) {
+    e = hipGraphLaunch(bt.exec, s);
+  }
   bt.graph_launches++;
   std::vector<int32_t> fl(16 * bt.count);
   std::vector<int32_t> pv;
@@ -181,6 +204,12 @@ hk_status factor_batch(Batch& bt, const std::vector<MP>& x, const std::vector<in
   }
   if (e == hipSuccess) e = hipMemcpyAsync(fl.data(), bt.flags, sizeof(int32_t) * fl.size(), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
+  for (size_t k = 0; k < evs.size() && e == hipSuccess; k++) {
+    float ms = 0;
+    e = hipEventElapsedTime(&ms, evs[k].t0, evs[k].t1);
+    bt.update_ms += ms;
+    if (evs[k].bulk) bt.bulk_ms += ms;
+  }
   if (e != hipSuccess) return dfail_b(HK_EDEVICE, std::string("batched factorisation: ") + hipGetErrorString(e));
   out.assign(bt.count, BEval());
   for (int i = 0; i < bt.count; i++) {
@@ -269,7 +298,7 @@ hk_status hk_eig_batched(const hk_instance* inst, int count, int digits, int pan
   if (!inst || !out || count < 1) return dfail_b(HK_EINVAL, "bad arguments");
   if (digits < 2 || digits > 150) return dfail_b(HK_EINVAL, "digits must be in [2, 150]");
   for (int i = 0; i < count; i++)
-    if (inst[i].method != HK_INVERSE && inst[i].method != HK_SECANT)
+    if ((inst[i].method & 0xff) != HK_INVERSE && (inst[i].method & 0xff) != HK_SECANT)
       return dfail_b(HK_EINVAL, "instance " + std::to_string(i) + ": unknown method");
   Batch bt;
   hk_status st = build_batch(bt, inst, count, dev_ws, ws_bytes, s);
@@ -279,12 +308,21 @@ hk_status hk_eig_batched(const hk_instance* inst, int count, int digits, int pan
     bt.panel = panel > 0 ? panel : (sc.panel > 0 ? sc.panel : 4);
     bt.lookahead = sc.lookahead;
     if (sc.ipw > 0) bt.B.ipw = sc.ipw;
+    // the first instance's flags set the schedule of the whole batch
+    const int fl = inst[0].method;
+    if (fl & HK_FLAG_LOOKAHEAD_ON) bt.lookahead = 1;
+    if (fl & HK_FLAG_LOOKAHEAD_OFF) bt.lookahead = 0;
+    if (fl & HK_FLAG_LOOKAHEAD_FUSED) bt.lookahead = 2;
+    const int g = (fl >> 28) & 7;
+    if (g == 1 || g == 2 || g == 4) bt.B.ipw = g;
+    if (fl & HK_FLAG_VECTOR_UPDATE) bt.B.mma = 0;
+    bt.timing = (fl & HK_FLAG_TIME_UPDATES) != 0;
   }
   auto t1 = std::chrono::steady_clock::now();
   std::vector<SecantRun*> sm(count, nullptr);
   for (int i = 0; i < count; i++) {
     const Plan& P = bt.mats[i]->P;
-    if (inst[i].method == HK_SECANT) sm[i] = secant_new(P.N, P.K, P.h, digits, 200);
+    if ((inst[i].method & 0xff) == HK_SECANT) sm[i] = secant_new(P.N, P.K, P.h, digits, 200);
     memset(&out[i], 0, sizeof(hk_result));
   }
   std::vector<MP> x(count), lam(count);
@@ -319,7 +357,7 @@ hk_status hk_eig_batched(const hk_instance* inst, int count, int digits, int pan
   std::vector<int> inv(count, 0);
   int ninv = 0;
   for (int i = 0; i < count; i++) {
-    inv[i] = inst[i].method == HK_INVERSE;
+    inv[i] = (inst[i].method & 0xff) == HK_INVERSE;
     ninv += inv[i];
     x[i] = MP();
     if (inv[i] && inst[i].shift_hint && !shift_fixed(*inst[i].shift_hint, bt.mats[i]->P.K, x[i]))
@@ -391,6 +429,13 @@ hk_status hk_eig_batched(const hk_instance* inst, int count, int digits, int pan
     rep->t_build_s = std::chrono::duration<double>(t1 - t0).count();
     rep->t_factor_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t1).count();
     rep->t_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    rep->update_launches = bt.n_update;
+    rep->update_ms = bt.update_ms;
+    rep->bulk_launches = bt.n_bulk;
+    rep->bulk_ms = bt.bulk_ms;
+    int maxW = 0;
+    for (const Plan* p : bt.B.plans) maxW = std::max(maxW, p->maxW);
+    rep->update_engine = lookahead_mode(bt.lookahead, bt.maxN, maxW) != 2 && mma_width(bt.B, bt.panel) > 0 ? 1 : 0;
   }
   if (first != HK_OK && st == HK_OK) g_err = "some instances failed";
   return first;

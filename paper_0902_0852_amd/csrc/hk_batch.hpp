@@ -23,8 +23,15 @@ struct Batch {
   std::vector<hipEvent_t> events;              // fork/join points of the captured graph
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  int captured_panel = 0, captured_ipw = 0;
+  int captured_panel = 0, captured_ipw = 0, captured_mma = -1;
   int graph_launches = 0;
+  // per-launch timing of the update launches (HK_FLAG_TIME_UPDATES): every
+  // factorisation launched one by one on the caller's stream (and s2)
+  bool timing = false;
+  hipStream_t s2 = nullptr;
+  std::vector<hipEvent_t> tevents;
+  int n_update = 0, n_bulk = 0;
+  double update_ms = 0, bulk_ms = 0;
   Batch() = default;
   Batch(const Batch&) = delete;
   Batch& operator=(const Batch&) = delete;

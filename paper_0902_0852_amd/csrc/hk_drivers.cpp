@@ -704,6 +704,7 @@ static hk_status smallest_eig_impl(int N, hk_rational beta, int prec_bits, int m
   if (flags & HK_FLAG_LOOKAHEAD_FUSED) hk_set_lookahead(m, 2);
   const int forced_group = (flags >> 28) & 7;
   if (forced_group > 0) hk_set_update_group(m, forced_group);
+  if (flags & HK_FLAG_VECTOR_UPDATE) hk_set_update_engine(m, HK_UPDATE_VECTOR);
   MP lam;
   int solves = 0;
   if (method == HK_SECANT) {
@@ -727,6 +728,10 @@ static hk_status smallest_eig_impl(int N, hk_rational beta, int prec_bits, int m
     snprintf(rep->lambda_dec, sizeof rep->lambda_dec, "%s", dec.c_str());
     if (st == HK_OK) lambda_mpf(lam, prec_bits, &rep->lambda, rep->lambda_words);
     rep->limb_macs = cx.limb_macs;
+    {
+      hk_info inf;
+      if (hk_matrix_info(m, &inf) == HK_OK) rep->update_engine = inf.update_engine;
+    }
     rep->t_factor_s = cx.t_factor;
     rep->t_solve_s = cx.t_solve;
     rep->t_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

@@ -32,7 +32,7 @@ struct ColInfo {
   int64_t loff;   // L_k digit planes LW x R (int32), row index r - k
   int64_t soff;   // |C_k| standard digits, rows (N-k) x CW (uint32)
   int64_t doff;   // |d_k| 2^sh standard digits (uint32), W + 2 entries
-  int32_t W;      // digits per A entry (multiple of WB)
+  int32_t W;      // digits per A entry (multiple of 2 WB)
   int32_t R;      // padded rows (multiple of 64)
   int32_t nb;     // W / WB
   int32_t CW;     // W + 16
@@ -40,7 +40,9 @@ struct ColInfo {
   int32_t items;  // trailing-update items of this column: (R/64) * nb
   int64_t ltoff;  // L^T row: entries L_c[r] for c < r, digit planes LWT x PT (int32)
   int32_t PT;     // rows of the L^T planes: r rounded up to 64 (>= 64)
-  int32_t pad;
+  int32_t G;      // 32-digit chunks of the byte planes of L_k: ceil(LW / 32)
+  int64_t l8off;  // byte planes of L_k (int8): [4][G][R][32], digit j of row
+                  // r - k at plane s, chunk j / 32, byte j % 32
 };
 
 struct Plan {
@@ -55,8 +57,9 @@ struct Plan {
   int LWT = 0;                // digit planes of the L^T rows
   std::vector<ColInfo> cols;
   std::vector<int32_t> itemStart;  // N+1 prefix sums of items
+  std::vector<int32_t> tileStart;  // N+1 prefix sums of 32-row tiles (R / 32)
   // byte offsets in the workspace
-  size_t o_cols, o_items, o_A, o_K, o_C, o_L, o_S, o_D, o_dinfo, o_nC, o_nCs, o_nL,
+  size_t o_cols, o_items, o_tiles, o_A, o_K, o_C, o_L, o_L8, o_S, o_D, o_dinfo, o_nC, o_nCs, o_nL,
       o_X, o_xs, o_flags, o_b32C, o_b32L, o_vec, o_LT, o_acc, o_kca, o_ub, o_us, o_wb, o_nU,
       o_nUs, o_dv1, o_dv2, o_md, o_mdinfo, o_dots, o_desc, o_sargs, total;
   int64_t ntri;
@@ -87,8 +90,8 @@ hk_status build_matrix_impl(int N, hk_rational beta, int prec_bits, void* dev_ws
 struct InstDesc;
 struct SweepArgs;
 struct DevPtrs {
-  ColInfo* cols; int32_t* itemStart;
-  int32_t* A; int64_t* Kc; int32_t* C; int32_t* L; uint32_t* S; uint32_t* D; int32_t* dinfo;
+  ColInfo* cols; int32_t* itemStart; int32_t* tileStart;
+  int32_t* A; int64_t* Kc; int32_t* C; int32_t* L; int8_t* L8; uint32_t* S; uint32_t* D; int32_t* dinfo;
   int32_t* nC; int32_t* nCs; int32_t* nL; int32_t* X; int32_t* xs; int32_t* flags;
   int32_t* b32C; int32_t* b32L; int32_t* vec;
   int32_t* LT; int32_t* acc; int64_t* kca; int32_t* ub; uint32_t* us; int32_t* wb;
@@ -103,8 +106,8 @@ DevPtrs dev_ptrs(const Plan& P, char* ws);
 // every factorisation kernel takes an array of them, a single matrix is a
 // batch of one.
 struct InstDesc {
-  const ColInfo* cols; const int32_t* itemStart;
-  int32_t* A; int64_t* Kc; int32_t* C; uint32_t* S; int32_t* L; int32_t* LT; uint32_t* D;
+  const ColInfo* cols; const int32_t* itemStart; const int32_t* tileStart;
+  int32_t* A; int64_t* Kc; int32_t* C; uint32_t* S; int32_t* L; int8_t* L8; int32_t* LT; uint32_t* D;
   int32_t* dinfo; int32_t* nC; int32_t* nCs; int32_t* nL; int32_t* b32C; int32_t* flags;
   const int32_t* X; const int32_t* xs;
   int32_t N, h, WX, active;
@@ -118,6 +121,7 @@ struct BatchView {
   std::vector<const Plan*> plans;
   int maxN = 0;
   int ipw = 4;   // update items (wavefronts) per workgroup of k_update / k_update_near: 1, 2 or 4
+  int mma = 1;   // bulk updates on the matrix cores where they fit (k_update_mma)
 };
 extern thread_local std::string g_err;
 
@@ -132,6 +136,9 @@ constexpr int UPD_NEAR = -1, UPD_FAR = -2;
 // the launches of k_update (the bulk of the update work: j = 0 and UPD_FAR)
 // against those of k_update_near (in-panel and UPD_NEAR, critical path)
 inline bool update_is_bulk(int j) { return j == 0 || j == UPD_FAR; }
+// widest column of the batch when its bulk updates run on the matrix cores
+// (k_update_mma), 0 when they run on the vector units (k_update)
+int mma_width(const BatchView& B, int b);
 hipError_t launch_update(const BatchView& B, int pc, int b, int j, int rd, hipStream_t s,
                          hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 hipError_t launch_fdiv(const BatchView& B, int c, int rd, hipStream_t s);
@@ -230,7 +237,7 @@ struct hk_matrix_s {
   hipStream_t gcap = nullptr, gcap2 = nullptr, s2 = nullptr;   // capture streams; look-ahead stream
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
-  int gpanel = 0, gla = -1, gipw = 0, g_nupdate = 0, g_nbulk = 0;
+  int gpanel = 0, gla = -1, gipw = 0, gmma = -1, g_nupdate = 0, g_nbulk = 0;
   hk::SweepArgs sweep;        // host copy of the solve arguments (kept alive for the upload)
   hipGraph_t sgraph = nullptr;   // one captured solve, replayed by hk_solve
   hipGraphExec_t sgexec = nullptr;

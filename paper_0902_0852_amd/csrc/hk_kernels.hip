@@ -17,6 +17,7 @@
 // so no atomics and no cross-item ordering are needed.
 #include <climits>
 #include <hip/hip_ext.h>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -29,6 +30,18 @@ namespace {
 
 __device__ __forceinline__ int32_t balanced29(int64_t v) {
   return (int32_t)(((v + (int64_t(1) << 28)) & (RADIX - 1)) - (int64_t(1) << 28));
+}
+
+// A balanced radix-2^29 digit d (|d| <= 2^28) as four signed bytes,
+// d = b0 + b1 2^8 + b2 2^16 + b3 2^24 with b0, b1, b2 in [-128, 127] and
+// |b3| <= 16: the operands of the matrix-core update.
+__device__ __forceinline__ void split_bytes(int32_t d, int32_t& b0, int32_t& b1, int32_t& b2, int32_t& b3) {
+  b0 = (d << 24) >> 24;
+  d = (d - b0) >> 8;
+  b1 = (d << 24) >> 24;
+  d = (d - b1) >> 8;
+  b2 = (d << 24) >> 24;
+  b3 = (d - b2) >> 8;
 }
 
 __device__ __forceinline__ int wave_max(int v) {
@@ -280,10 +293,14 @@ __host__ __device__ inline bool update_range(int N, int pc, int b, int j, int& k
 // C_k[c] digits are wavefront-uniform; L_k[r] digits are per lane.
 // One item (wavefront), numbered `it` across the columns and instances of
 // the launch.
-__device__ __forceinline__ void update_item(const InstDesc* __restrict__ desc, int count, int pc, int b, int j,
-                                            int rd, int it) {
+// The instance, panel range [k0, k1), column c and the item's rank within
+// its column (rem) of update item `it` of a launch; false if there is none or
+// the instance is finished.  Wavefront-uniform.
+__device__ __forceinline__ bool find_update_item(const InstDesc* __restrict__ desc, int count, int pc, int b,
+                                                 int j, int it, int& inst, int& k0, int& k1, int& c, int& rem) {
   const int lane = threadIdx.x & 63;
-  int inst = -1, k0 = 0, k1 = 0, c_lo = 0, c_hi = 0;
+  int c_lo = 0, c_hi = 0;
+  inst = -1;
   for (int i = 0; i < count; i++) {
     int a0, a1, b0, b1;
     const int Ni = sload(&desc[i].N);
@@ -294,10 +311,9 @@ __device__ __forceinline__ void update_item(const InstDesc* __restrict__ desc, i
     it -= n;
   }
   inst = uni(inst);
-  if (inst < 0) return;
+  if (inst < 0) return false;
   const InstDesc I = sload(desc + inst);
-  if (!I.active) return;
-  const int N = I.N;
+  if (!I.active) return false;
   it += sload(I.itemStart + c_lo);
   // the column of the item: the last c in [c_lo, c_hi) with itemStart[c] <= it
   // (itemStart is nondecreasing), found by the whole wavefront reading 64
@@ -313,10 +329,20 @@ __device__ __forceinline__ void update_item(const InstDesc* __restrict__ desc, i
     lo = uni(lo + last * step);
     n = min(step, c_hi - lo);
   }
-  const int c = uni(lo);
+  c = uni(lo);
   start = sload(I.itemStart + c);
+  rem = it - start;
+  return true;
+}
+
+__device__ __forceinline__ void update_item(const InstDesc* __restrict__ desc, int count, int pc, int b, int j,
+                                            int rd, int it) {
+  const int lane = threadIdx.x & 63;
+  int inst, k0, k1, c, rem;
+  if (!find_update_item(desc, count, pc, b, j, it, inst, k0, k1, c, rem)) return;
+  const InstDesc I = sload(desc + inst);
+  const int N = I.N;
   const ColInfo cc = sload(I.cols + c);
-  const int rem = it - start;
   const int T = cc.R >> 6;
   const int q = uni(rem / T);
   const int t = uni(rem - q * T);
@@ -360,6 +386,463 @@ __global__ void __launch_bounds__(256) k_update_near(const InstDesc* __restrict_
                                                      int b, int j, int rd) {
   __builtin_amdgcn_s_setprio(3);
   update_item(desc, count, pc, b, j, rd, blockIdx.x * (blockDim.x >> 6) + uni(threadIdx.x >> 6));
+}
+
+// ---------------------------------------------------------------------------
+// The trailing update on the matrix cores.  Every digit of C and L splits
+// exactly into four signed bytes (split_bytes), so the exact sum of digit
+// products at output position t of an entry,
+//   V_t = sum_{i + j = t} C_i L_j = sum_s 2^(8 s) D_s[t],
+//   D_s[t] = sum_{p + q = s} sum_j c_p[t - j] l_q[j],
+// is sixteen int8 products accumulated into seven int32 planes D_0..D_6.
+// For one column c, 32 output positions t0 + i and 32 rows r, each D_s is a
+// matrix product: a Toeplitz matrix of C's bytes (rows t, columns j, entry
+// c_p[t - j], the same for every row r) times L's bytes (rows j, columns r),
+// which is what v_mfma_i32_32x32x32_i8 computes, 32 digits j at a time.
+// Products are accumulated over the panel's columns k in int32 (the host
+// keeps sum_k nC_k below 2^15, so |D_s| < 4 2^14 2^15 = 2^31), then turned
+// into 29-bit digits and carries and subtracted from A as in apply_block.
+
+typedef int v16i __attribute__((ext_vector_type(16)));
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+// bytes of one C byte plane in LDS for columns of at most Wm digits: the
+// plane is stored reversed, byte y holding c_p[Wm + 64 - y], with 64 zero
+// digits beyond both ends of C and a dword of slack for the aligned reads
+__host__ __device__ inline int mma_plane_bytes(int Wm) { return (Wm + 140 + 15) / 16 * 16; }
+
+// 16 bytes of a plane from byte y0 on (any alignment): five aligned dword
+// reads and four byte-aligns
+__device__ __forceinline__ v4i lds_bytes16(const uint32_t* plane, int y0) {
+  const uint32_t* w = plane + (y0 >> 2);
+  const uint32_t sh = (uint32_t)(y0 & 3);
+  const uint32_t a0 = w[0], a1 = w[1], a2 = w[2], a3 = w[3], a4 = w[4];
+  v4i r;
+  r[0] = (int)__builtin_amdgcn_alignbyte(a1, a0, sh);
+  r[1] = (int)__builtin_amdgcn_alignbyte(a2, a1, sh);
+  r[2] = (int)__builtin_amdgcn_alignbyte(a3, a2, sh);
+  r[3] = (int)__builtin_amdgcn_alignbyte(a4, a3, sh);
+  return r;
+}
+
+// 64-bit value of lane l ^ 32
+__device__ __forceinline__ int64_t swap_halves(int64_t v) {
+  const int a = (((int)threadIdx.x & 63) ^ 32) << 2;
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(a, (int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(a, (int)(uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// A's digits of block q (per lane) -= acc with the pending carry kin folded
+// in and the carry out to kout, as apply_block, with the block offset a
+// vector operand (the two halves of a wavefront apply different blocks)
+__device__ __forceinline__ void apply_block_v(const int64_t* acc, const int32_t* Acol, int64_t abytes, int lr,
+                                              int R, int q, const GLOBAL int64_t* kin, GLOBAL int64_t* kout,
+                                              GLOBAL int32_t* flags) {
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)Acol, (short)0, (int)min(abytes, (int64_t)0x7fffffff), 0x00020000);
+  const int pb = R * 4;
+  const int vo = lr * 4 + WB * q * pb;
+  int32_t a[WB];
+#pragma unroll
+  for (int m = 0; m < WB; m++) a[m] = __builtin_amdgcn_raw_buffer_load_b32(rs, vo, m * pb, 0);
+  int64_t v = kin ? *kin : 0;
+#pragma unroll
+  for (int m = 0; m < WB; m++) {
+    v += (int64_t)a[m] - acc[m];
+    const int32_t d = balanced29(v);
+    __builtin_amdgcn_raw_buffer_store_b32(d, rs, vo, m * pb, 0);
+    v = (v - d) >> DB;
+  }
+  v -= acc[WB];
+  if (kout) *kout = v;
+  else if (v != 0) gor(flags, 1);
+}
+
+// One item of the matrix-core update: column c, 32 rows (tile t32 of the
+// column's 32-row tiles), output digits [32 q2, 32 q2 + 32) (blocks 2 q2 and
+// 2 q2 + 1).  Lane l: row r = c + 32 t32 + l % 32, half h = l / 32 of the
+// K operand digits; after the exchange at the end, the lane applies block
+// 2 q2 + h of its row.  lds: this wavefront's four C byte planes.
+__device__ __forceinline__ void mma_item(const InstDesc* __restrict__ desc, int count, int pc, int b, int j,
+                                         int rd, int it, int Wm, uint32_t* lds) {
+  const int lane = threadIdx.x & 63, i = lane & 31, h = lane >> 5;
+  int inst, k0, k1, c, rem;
+  if (!find_update_item(desc, count, pc, b, j, it, inst, k0, k1, c, rem)) return;
+  const InstDesc I = sload(desc + inst);
+  const int N = I.N;
+  const ColInfo cc = sload(I.cols + c);
+  const int T32 = cc.R >> 5;
+  const int q2 = uni(rem / T32);
+  const int t32 = uni(rem - q2 * T32);
+  const int t0 = 32 * q2;
+  const int r = c + 32 * t32 + i;
+  const bool active = r < N;
+  const int rr = active ? r : N - 1;
+  const int PB = mma_plane_bytes(Wm), X0 = Wm + 64;
+  int8_t* planes = (int8_t*)lds;
+
+  v16i D[7];
+#pragma unroll
+  for (int s = 0; s < 7; s++)
+#pragma unroll
+    for (int v = 0; v < 16; v++) D[s][v] = 0;
+  // the digit counts of the next panel column are requested one column ahead
+  int nCn = sload(I.nC + tri_index(N, k0, c));
+  int nLn = active ? gp(I.nL)[tri_index(N, k0, rr)] : 0;
+  for (int k = k0; k < k1; k++) {
+    const ColInfo kk = sload(I.cols + k);
+    const int nC = min(nCn, kk.CW - WB);
+    const int nLl = nLn;
+    if (k + 1 < k1) {
+      nCn = sload(I.nC + tri_index(N, k + 1, c));
+      nLn = active ? gp(I.nL)[tri_index(N, k + 1, rr)] : 0;
+    }
+    const int nL = min(uni(wave_max(nLl)), kk.LW - 2 * WB);
+    const int jlo = max(0, t0 - nC + 1), jhi = min(nL, t0 + 32);
+    if (nC <= 0 || jlo >= jhi) continue;
+    const int g0 = jlo >> 5, g1 = (jhi - 1) >> 5;
+    // L_k's byte planes of this lane's row (16 digits of each 32-digit
+    // chunk) are loaded two chunks ahead of their products, C's Toeplitz
+    // operands one chunk ahead, in three rotating register sets (no moves
+    // between them, so no wait falls before its turn); the first two chunks
+    // of L are requested before C's planes are built
+    const GLOBAL int8_t* Lb = gp(I.L8 + kk.l8off + (int64_t)(rr - k) * 32 + 16 * h);
+    const int64_t cs = (int64_t)kk.R * 32, ps = (int64_t)kk.G * cs;
+    const int yb = X0 - t0 - i + 16 * h;
+    v4i B0[4], B1[4], B2[4], A0[4], A1[4], A2[4];
+    auto ldB = [&](v4i* Bx, int g) {
+      const GLOBAL int8_t* p = Lb + min(g, g1) * cs;
+#pragma unroll
+      for (int q = 0; q < 4; q++) Bx[q] = *(const GLOBAL v4i*)(p + q * ps);
+    };
+    auto ldA = [&](v4i* Ax, int g) {
+#pragma unroll
+      for (int p = 0; p < 4; p++) Ax[p] = lds_bytes16(lds + p * (PB >> 2), yb + 32 * min(g, g1));
+    };
+    auto mm = [&](const v4i* Ax, const v4i* Bx) {
+#pragma unroll
+      for (int q = 0; q < 4; q++)
+#pragma unroll
+        for (int p = 0; p < 4; p++)
+          D[p + q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(Ax[p], Bx[q], D[p + q], 0, 0, 0);
+    };
+    ldB(B0, g0);
+    ldB(B1, g0 + 1);
+    // C_k[c] as four reversed byte planes, zero outside the digits
+    for (int x = lane; x < PB; x += 64) lds[x] = 0;   // 4 planes of PB / 4 dwords
+    {
+      // C's digits in batches of 8 per lane, each batch's loads in flight
+      // together (clamped indices, masked stores)
+      const GLOBAL int32_t* Cg = gp(I.C + kk.coff + (int64_t)(c - k) * kk.CW);
+      for (int x0 = 0; x0 < nC; x0 += 512) {
+        int32_t cv[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) cv[u] = Cg[min(x0 + lane + 64 * u, nC - 1)];
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+          const int x = x0 + lane + 64 * u;
+          if (x < nC) {
+            int32_t b0, b1, b2, b3;
+            split_bytes(cv[u], b0, b1, b2, b3);
+            const int y = X0 - x;
+            planes[y] = (int8_t)b0;
+            planes[PB + y] = (int8_t)b1;
+            planes[2 * PB + y] = (int8_t)b2;
+            planes[3 * PB + y] = (int8_t)b3;
+          }
+        }
+      }
+    }
+    ldA(A0, g0);
+    for (int g = g0; g <= g1; g += 3) {
+      ldB(B2, g + 2);
+      ldA(A1, g + 1);
+      mm(A0, B0);
+      if (g + 1 > g1) break;
+      ldB(B0, g + 3);
+      ldA(A2, g + 2);
+      mm(A1, B1);
+      if (g + 2 > g1) break;
+      ldB(B1, g + 4);
+      ldA(A0, g + 3);
+      mm(A2, B2);
+    }
+  }
+  // D_s[t][r] for t = 8 (v / 4) + 4 h + v % 4: digits and carries of V_t
+  int32_t dg[16];
+  int64_t cy[16];
+#pragma unroll
+  for (int v = 0; v < 16; v++) {
+    const int64_t lo = (int64_t)D[0][v] + ((int64_t)D[1][v] << 8) + ((int64_t)D[2][v] << 16) +
+                       ((int64_t)D[3][v] << 24);
+    const int64_t hi = (int64_t)D[4][v] + ((int64_t)D[5][v] << 8) + ((int64_t)D[6][v] << 16);
+    dg[v] = balanced29(lo);
+    cy[v] = ((lo - dg[v]) >> DB) + (hi << 3);
+  }
+  // half 0 takes t in [0, 16), half 1 t in [16, 32): exchange the four-digit
+  // groups the other half holds
+  int32_t rdg[8];
+  int64_t rcy[8];
+#pragma unroll
+  for (int u = 0; u < 8; u++) {
+    const int v = h ? u : u + 8;
+    rdg[u] = (int32_t)swap_halves((int64_t)dg[v]);
+    rcy[u] = swap_halves(cy[v]);
+  }
+  int64_t acc[WB + 1];
+  int64_t prev = h ? cy[7] : 0;         // carry out of t = 15 (held by half 1)
+#pragma unroll
+  for (int m = 0; m < WB; m++) {
+    const int grp = m >> 2, e = m & 3;
+    const bool own = (grp & 1) == h;    // half 0 holds groups 0, 2; half 1 groups 1, 3
+    const int v = 8 * h + 4 * (grp >> 1) + e, u = 4 * (grp >> 1) + e;
+    const int32_t d = own ? dg[v] : rdg[u];
+    const int64_t y = own ? cy[v] : rcy[u];
+    acc[m] = (int64_t)d + prev;
+    prev = y;
+  }
+  acc[WB] = h ? prev : 0;               // half 0 hands its top carry to half 1
+  if (!active) return;
+  const int lr = r - c, q = 2 * q2 + h;
+  int64_t* Kcol = I.Kc + cc.koff;
+  apply_block_v(acc, uptr(I.A + cc.aoff), (int64_t)cc.W * cc.R * 4, lr, cc.R, q,
+                q > 0 ? gp(Kcol + ((int64_t)rd * cc.nb + q) * cc.R + lr) : nullptr,
+                q + 1 < cc.nb ? gp(Kcol + ((int64_t)(rd ^ 1) * cc.nb + q + 1) * cc.R + lr) : nullptr,
+                gp(I.flags));
+}
+
+// The digit products of one 32 x 32 tile on the matrix cores: D (zeroed
+// here) accumulates the byte-plane products over the panel columns and
+// their 32-digit chunks, with L's planes loaded two chunks ahead and C's
+// Toeplitz operands one chunk ahead of their products (three rotating
+// register sets, so no move between them makes a load wait before its turn).
+// Per panel column kk of the workgroup (LDS): planes[kk] C's four byte
+// planes, nCk[kk], nLk[kk] the digit counts, l8[kk] the byte offset of L's
+// planes of the tile's first row, and csk/psk their chunk and plane strides.
+struct MmaCols {
+  const uint32_t* planes;   // nk sets of 4 planes of PB bytes
+  const int* nCk;
+  const int* nLk;
+  const int64_t* l8;
+  const int64_t* csk;
+  const int64_t* psk;
+  int nk, PB, X0;
+};
+
+__device__ __forceinline__ void mma_tile(v16i* D, const MmaCols& M, const GLOBAL int8_t* L8, int t0, int row,
+                                         int lane) {
+  const int i = lane & 31, h = lane >> 5;
+#pragma unroll
+  for (int s = 0; s < 7; s++)
+#pragma unroll
+    for (int v = 0; v < 16; v++) D[s][v] = 0;
+  const int yb = M.X0 - t0 - i + 16 * h;
+  for (int kk = 0; kk < M.nk; kk++) {
+    const int nC = M.nCk[kk], nL = M.nLk[kk];
+    const int jlo = max(0, t0 - nC + 1), jhi = min(nL, t0 + 32);
+    if (nC <= 0 || jlo >= jhi) continue;
+    const int g0 = jlo >> 5, g1 = (jhi - 1) >> 5;
+    const GLOBAL int8_t* Lb = L8 + M.l8[kk] + (int64_t)row * 32 + 16 * h;
+    const int64_t cs = M.csk[kk], ps = M.psk[kk];
+    const uint32_t* pl = M.planes + kk * M.PB;     // 4 planes of PB / 4 dwords
+    auto ldB = [&](v4i* Bx, int g) {
+      const GLOBAL int8_t* p = Lb + min(g, g1) * cs;
+#pragma unroll
+      for (int q = 0; q < 4; q++) Bx[q] = *(const GLOBAL v4i*)(p + q * ps);
+    };
+    auto ldA = [&](v4i* Ax, int g) {
+#pragma unroll
+      for (int p = 0; p < 4; p++) Ax[p] = lds_bytes16(pl + p * (M.PB >> 2), yb + 32 * min(g, g1));
+    };
+    auto mm = [&](const v4i* Ax, const v4i* Bx) {
+#pragma unroll
+      for (int q = 0; q < 4; q++)
+#pragma unroll
+        for (int p = 0; p < 4; p++)
+          D[p + q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(Ax[p], Bx[q], D[p + q], 0, 0, 0);
+    };
+    v4i B0[4], B1[4], B2[4], A0[4], A1[4], A2[4];
+    ldB(B0, g0);
+    ldB(B1, g0 + 1);
+    ldA(A0, g0);
+    for (int g = g0; g <= g1; g += 3) {
+      ldB(B2, g + 2);
+      ldA(A1, g + 1);
+      mm(A0, B0);
+      if (g + 1 > g1) break;
+      ldB(B0, g + 3);
+      ldA(A2, g + 2);
+      mm(A1, B1);
+      if (g + 2 > g1) break;
+      ldB(B1, g + 4);
+      ldA(A0, g + 3);
+      mm(A2, B2);
+    }
+  }
+}
+
+// The digits and carries of the tile's exact sums (from D) subtracted from
+// A's blocks 2 q2 + h of row r, as at the end of mma_item
+__device__ __forceinline__ void mma_apply(const v16i* D, const InstDesc& I, const ColInfo& cc, int c, int r,
+                                          bool active, int q2, int rd, int lane) {
+  const int h = lane >> 5;
+  int32_t dg[16];
+  int64_t cy[16];
+#pragma unroll
+  for (int v = 0; v < 16; v++) {
+    const int64_t lo = (int64_t)D[0][v] + ((int64_t)D[1][v] << 8) + ((int64_t)D[2][v] << 16) +
+                       ((int64_t)D[3][v] << 24);
+    const int64_t hi = (int64_t)D[4][v] + ((int64_t)D[5][v] << 8) + ((int64_t)D[6][v] << 16);
+    dg[v] = balanced29(lo);
+    cy[v] = ((lo - dg[v]) >> DB) + (hi << 3);
+  }
+  int32_t rdg[8];
+  int64_t rcy[8];
+#pragma unroll
+  for (int u = 0; u < 8; u++) {
+    const int v = h ? u : u + 8;
+    rdg[u] = (int32_t)swap_halves((int64_t)dg[v]);
+    rcy[u] = swap_halves(cy[v]);
+  }
+  int64_t acc[WB + 1];
+  int64_t prev = h ? cy[7] : 0;
+#pragma unroll
+  for (int m = 0; m < WB; m++) {
+    const int grp = m >> 2, e = m & 3;
+    const bool own = (grp & 1) == h;
+    const int v = 8 * h + 4 * (grp >> 1) + e, u = 4 * (grp >> 1) + e;
+    acc[m] = (int64_t)(own ? dg[v] : rdg[u]) + prev;
+    prev = own ? cy[v] : rcy[u];
+  }
+  acc[WB] = h ? prev : 0;
+  if (!active) return;
+  const int lr = r - c, q = 2 * q2 + h;
+  int64_t* Kcol = I.Kc + cc.koff;
+  apply_block_v(acc, uptr(I.A + cc.aoff), (int64_t)cc.W * cc.R * 4, lr, cc.R, q,
+                q > 0 ? gp(Kcol + ((int64_t)rd * cc.nb + q) * cc.R + lr) : nullptr,
+                q + 1 < cc.nb ? gp(Kcol + ((int64_t)(rd ^ 1) * cc.nb + q + 1) * cc.R + lr) : nullptr,
+                gp(I.flags));
+}
+
+// The bulk update on the matrix cores, one workgroup per (instance, column,
+// 32-row tile): its four wavefronts build C_k[c]'s byte planes of every panel
+// column k once (LDS), then share out the column's 32-digit output tiles.
+// Wm: the widest column of the launch; the LDS holds (k1 - k0) plane sets.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_update_mma(const InstDesc* __restrict__ desc, int count, int pc, int b,
+                                                     int j, int rd, int Wm) {
+  extern __shared__ int64_t smem[];
+  const int lane = threadIdx.x & 63, w = uni(threadIdx.x >> 6), nw = blockDim.x >> 6;
+  // the instance and column of this workgroup's tile, by the tile prefix
+  int it = blockIdx.x, inst = -1, k0 = 0, k1 = 0, c_lo = 0, c_hi = 0;
+  for (int i2 = 0; i2 < count; i2++) {
+    int a0, a1, b0, b1;
+    const int Ni = sload(&desc[i2].N);
+    if (!update_range(Ni, pc, b, j, a0, a1, b0, b1)) continue;
+    const int32_t* ts = sload(&desc[i2].tileStart);
+    const int n = sload(ts + b1) - sload(ts + b0);
+    if (it < n) { inst = i2; k0 = a0; k1 = a1; c_lo = b0; c_hi = b1; break; }
+    it -= n;
+  }
+  inst = uni(inst);
+  if (inst < 0) return;
+  const InstDesc I = sload(desc + inst);
+  if (!I.active) return;
+  const int N = I.N;
+  it += sload(I.tileStart + c_lo);
+  int lo = c_lo, n = c_hi - c_lo;
+  while (n > 1) {
+    const int step = (n + 63) / 64;
+    const int kx = lane * step;
+    const int v = kx < n ? gp(I.tileStart)[lo + kx] : INT_MAX;
+    const uint64_t m = __ballot(v <= it);
+    const int last = 63 - __clzll((long long)m);
+    lo = uni(lo + last * step);
+    n = min(step, c_hi - lo);
+  }
+  const int c = uni(lo);
+  const int t32 = uni(it - sload(I.tileStart + c));
+  if (c + 32 * t32 >= N) return;   // a tile of padding rows only
+  const ColInfo cc = sload(I.cols + c);
+  const int nk = k1 - k0;
+  const int PB = mma_plane_bytes(Wm), X0 = Wm + 64;
+  uint32_t* planes = (uint32_t*)smem;                       // nk x PB dwords
+  int* nCk = (int*)(planes + nk * PB);
+  int* nLk = nCk + nk;
+  int64_t* l8 = (int64_t*)(((uintptr_t)(nLk + nk) + 7) & ~(uintptr_t)7);
+  int64_t* csk = l8 + nk;
+  int64_t* psk = csk + nk;
+  const int i = lane & 31;
+  const int r = c + 32 * t32 + i;
+  const bool active = r < N;
+  const int rr = active ? r : N - 1;
+  // per panel column: digit counts (L's: the largest over the tile's rows)
+  for (int kk = w; kk < nk; kk += nw) {
+    const int k = k0 + kk;
+    const ColInfo kc = sload(I.cols + k);
+    const int nLl = active ? gp(I.nL)[tri_index(N, k, rr)] : 0;
+    const int nL = min(uni(wave_max(nLl)), kc.LW - 2 * WB);
+    if (lane == 0) {
+      nCk[kk] = min(gp(I.nC)[tri_index(N, k, c)], kc.CW - WB);
+      nLk[kk] = nL;
+      l8[kk] = kc.l8off + (int64_t)(c + 32 * t32 - k) * 32;
+      csk[kk] = (int64_t)kc.R * 32;
+      psk[kk] = (int64_t)kc.G * kc.R * 32;
+    }
+  }
+  for (int x = threadIdx.x; x < nk * PB; x += blockDim.x) planes[x] = 0;
+  __syncthreads();
+  // C_k[c] of every panel column as four reversed byte planes
+  {
+    int8_t* pb = (int8_t*)planes;
+    for (int kk = 0; kk < nk; kk++) {
+      const int k = k0 + kk;
+      const ColInfo kc = sload(I.cols + k);
+      const int nC = nCk[kk];
+      const GLOBAL int32_t* Cg = gp(I.C + kc.coff + (int64_t)(c - k) * kc.CW);
+      int8_t* pk = pb + (int64_t)kk * 4 * PB;
+      for (int x0 = 0; x0 < nC; x0 += 4 * 256) {
+        int32_t cv[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) cv[u] = Cg[min(x0 + (int)threadIdx.x + (int)blockDim.x * u, max(nC - 1, 0))];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+          const int x = x0 + threadIdx.x + blockDim.x * u;
+          if (x < nC) {
+            int32_t b0, b1, b2, b3;
+            split_bytes(cv[u], b0, b1, b2, b3);
+            const int y = X0 - x;
+            pk[y] = (int8_t)b0;
+            pk[PB + y] = (int8_t)b1;
+            pk[2 * PB + y] = (int8_t)b2;
+            pk[3 * PB + y] = (int8_t)b3;
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  const MmaCols M{planes, nCk, nLk, l8, csk, psk, nk, PB, X0};
+  const GLOBAL int8_t* L8 = gp(I.L8);
+  v16i D[7];
+  for (int q2 = w; q2 < (cc.nb >> 1); q2 += nw) {
+    mma_tile(D, M, L8, 32 * q2, rr - (c + 32 * t32), lane);
+    mma_apply(D, I, cc, c, r, active, q2, rd, lane);
+  }
+}
+__host__ inline size_t mma_lds(int Wm, int nk) {
+  return (size_t)nk * 4 * mma_plane_bytes(Wm) + 8 * (size_t)nk + 8 + 24 * (size_t)nk;
+}
+
+// The bulk update on the matrix cores, one item per wavefront (the form for
+// panels whose C planes do not fit one workgroup's LDS): Wm the widest
+// column of the launch (LDS: four C byte planes per wavefront)
+__global__ void __launch_bounds__(256) k_update_mma_w(const InstDesc* __restrict__ desc, int count, int pc, int b,
+                                                    int j, int rd, int Wm) {
+  extern __shared__ int64_t smem[];
+  const int w = uni(threadIdx.x >> 6);
+  uint32_t* lds = (uint32_t*)smem + w * mma_plane_bytes(Wm);
+  mma_item(desc, count, pc, b, j, rd, blockIdx.x * (blockDim.x >> 6) + w, Wm, lds);
 }
 
 struct FinOut {
@@ -818,6 +1301,28 @@ __device__ __forceinline__ void bulk_groups(int64_t* rem, int b, int nbulk, cons
   }
 }
 
+// Destination of the byte planes of one L entry (row of ColInfo::l8off):
+// byte s of digit j at p[s ps + (j / 32) cs + j % 32], digits [0, n) written
+// (zeros above the quotient); p == nullptr when there are none.
+struct L8Out {
+  GLOBAL int8_t* p;
+  int64_t ps, cs;
+  int n;
+};
+__device__ __forceinline__ void l8_store(const L8Out& o, int j, int32_t d) {
+  int32_t b0, b1, b2, b3;
+  split_bytes(d, b0, b1, b2, b3);
+  GLOBAL int8_t* q = o.p + (int64_t)(j >> 5) * o.cs + (j & 31);
+  q[0] = (int8_t)b0;
+  q[o.ps] = (int8_t)b1;
+  q[2 * o.ps] = (int8_t)b2;
+  q[3 * o.ps] = (int8_t)b3;
+}
+__device__ __forceinline__ void l8_zero(const L8Out& o, int from) {
+  if (!o.p) return;
+  for (int j = from + (int)(threadIdx.x & 63); j < o.n; j += 64) l8_store(o, j, 0);
+}
+
 // out = RNE(+-|num| 2^h / |d|) for one 64-lane workgroup: schoolbook long
 // division in radix 2^29 with a lazily normalised int64 remainder in LDS.
 // num: standard digits Sr[0..ns) of its magnitude, sign negN; divisor:
@@ -834,12 +1339,14 @@ __device__ __forceinline__ void bulk_groups(int64_t* rem, int b, int nbulk, cons
 template <bool BLK = true, int DNIR = 4>
 __device__ __forceinline__ int divide_entry(int64_t* smem, const uint32_t* Sr, int ns, int negN,
                             const uint32_t* Dp, int nd, int sh, int negd, int h, GLOBAL int32_t* out,
-                            int64_t os, int cap, GLOBAL int32_t* out2, int64_t os2, GLOBAL int32_t* flags) {
+                            int64_t os, int cap, GLOBAL int32_t* out2, int64_t os2, GLOBAL int32_t* flags,
+                            L8Out o8 = L8Out{nullptr, 0, 0, 0}) {
   const int lane = threadIdx.x & 63;
   nd = __builtin_amdgcn_readfirstlane(nd);
   ns = __builtin_amdgcn_readfirstlane(ns);
   if (nd == 0) {
     for (int j = lane; j < cap; j += 64) { out[(int64_t)j * os] = 0; if (out2) out2[(int64_t)j * os2] = 0; }
+    l8_zero(o8, 0);
     if (lane == 0) gor(flags, 4);
     return 0;
   }
@@ -847,6 +1354,7 @@ __device__ __forceinline__ int divide_entry(int64_t* smem, const uint32_t* Sr, i
   const int nu = ns == 0 ? 0 : Sq + ns + 1;
   if (nu < nd) {  // quotient below 2 / 2^29: rounds to zero
     for (int j = lane; j < cap; j += 64) { out[(int64_t)j * os] = 0; if (out2) out2[(int64_t)j * os2] = 0; }
+    l8_zero(o8, 0);
     return 0;
   }
   int64_t* rem = smem + DOFF;                // positions -DOFF .. nu + 2
@@ -1044,12 +1552,14 @@ __device__ __forceinline__ int divide_entry(int64_t* smem, const uint32_t* Sr, i
     const int32_t od = (int32_t)(sgn * o);
     out[(int64_t)j * os] = od;
     if (out2) out2[(int64_t)j * os2] = od;
+    if (o8.p) l8_store(o8, j, od);
     if (od != 0) mytop = j;
   }
   for (int j = nqc + lane; j < cap; j += 64) {
     out[(int64_t)j * os] = 0;
     if (out2) out2[(int64_t)j * os2] = 0;
   }
+  l8_zero(o8, nqc);
   if (nq > cap && lane == 0) {
     for (int j = cap; j < nq; j++) {
       const int64_t x = (j <= jmax ? qd[j] : 0) + (j == 0 ? adj : 0);
@@ -1336,8 +1846,9 @@ __device__ __forceinline__ void column_step(const InstDesc* __restrict__ desc, i
   }
   __syncthreads();
   if (r == c || wave != 0) return;
+  const L8Out o8{gp(I.L8 + cc.l8off + (int64_t)lr * 32), (int64_t)cc.G * cc.R * 32, (int64_t)cc.R * 32, 32 * cc.G};
   const int n = divide_entry<false, DNIR>(dsm, oS, f.nstd, f.neg, pD, pinfo[0], pinfo[1], pinfo[2], I.h,
-                                    gp(I.L + cc.loff + lr), cc.R, cc.LW, gp(I.LT + cr_ltoff + c), cr_PT, flg);
+                                    gp(I.L + cc.loff + lr), cc.R, cc.LW, gp(I.LT + cr_ltoff + c), cr_PT, flg, o8);
   if (lane == 0) {
     gp(I.nL)[tri_index(N, c, r)] = n;
     if (n > cc.LW - 2 * WB) gor(flg, 8);
@@ -1781,14 +2292,54 @@ static hipError_t mark_empty(hipEvent_t t0, hipEvent_t t1, hipStream_t s) {
   if (e == hipSuccess && t1) e = hipEventRecord(t1, s);
   return e;
 }
+// The widest column of a batch when its bulk updates run on the matrix cores,
+// else 0: off when HK_MMA=0, or when the int32 accumulators could overflow
+// (b panel columns of up to Wm digits: b Wm must stay below 2^15).
+int mma_width(const BatchView& B, int b) {
+  static const int off = [] {
+    const char* v = getenv("HK_MMA");
+    return v && v[0] == '0' && v[1] == 0;
+  }();
+  if (off || !B.mma) return 0;
+  int Wm = 0;
+  for (const Plan* p : B.plans) Wm = std::max(Wm, p->maxW);
+  if ((int64_t)std::max(b, 1) * Wm >= 32768 - 64) return 0;
+  return Wm;
+}
+
 hipError_t launch_update(const BatchView& B, int pc, int b, int j, int rd, hipStream_t s, hipEvent_t t0,
                          hipEvent_t t1) {
   int64_t items = 0;
   for (const Plan* p : B.plans) items += update_items(*p, pc, b, j);
   if (items <= 0) return mark_empty(t0, t1, s);
-  auto kern = update_is_bulk(j) ? k_update : k_update_near;
   const int ipw = B.ipw == 1 || B.ipw == 2 ? B.ipw : 4;
   const dim3 grid((unsigned)((items + ipw - 1) / ipw)), block(64 * ipw);
+  const int Wm = update_is_bulk(j) ? mma_width(B, b) : 0;
+  if (Wm > 0 && mma_lds(Wm, b) <= 65536) {
+    int64_t tiles = 0;
+    for (const Plan* p : B.plans) {
+      int k0, k1, c_lo, c_hi;
+      if (update_range(p->N, pc, b, j, k0, k1, c_lo, c_hi)) tiles += p->tileStart[c_hi] - p->tileStart[c_lo];
+    }
+    const size_t shm = mma_lds(Wm, b);
+    if (t0 || t1)
+      hipExtLaunchKernelGGL(k_update_mma, dim3((unsigned)tiles), dim3(256), shm, s, t0, t1, 0, B.ddesc,
+                            (int)B.plans.size(), pc, b, j, rd, Wm);
+    else
+      hipLaunchKernelGGL(k_update_mma, dim3((unsigned)tiles), dim3(256), shm, s, B.ddesc, (int)B.plans.size(), pc,
+                         b, j, rd, Wm);
+    return hipGetLastError();
+  }
+  if (Wm > 0) {
+    const size_t shm = (size_t)ipw * 4 * mma_plane_bytes(Wm);
+    if (t0 || t1)
+      hipExtLaunchKernelGGL(k_update_mma_w, grid, block, shm, s, t0, t1, 0, B.ddesc, (int)B.plans.size(), pc, b, j,
+                            rd, Wm);
+    else
+      hipLaunchKernelGGL(k_update_mma_w, grid, block, shm, s, B.ddesc, (int)B.plans.size(), pc, b, j, rd, Wm);
+    return hipGetLastError();
+  }
+  auto kern = update_is_bulk(j) ? k_update : k_update_near;
   if (t0 || t1)
     hipExtLaunchKernelGGL(kern, grid, block, 0, s, t0, t1, 0, B.ddesc, (int)B.plans.size(), pc, b, j, rd);
   else

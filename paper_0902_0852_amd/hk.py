@@ -16,6 +16,8 @@ LIB_PATH = os.path.join(_HERE, "libhk.so")
 
 HK_INVERSE, HK_SECANT = 0, 1
 HK_FLAG_NO_WORK_COUNT, HK_FLAG_TIME_UPDATES, HK_FLAG_CERTIFY = 0x100, 0x200, 0x400
+HK_FLAG_VECTOR_UPDATE = 0x800
+HK_UPDATE_MATRIX_CORES, HK_UPDATE_VECTOR = 0, 1
 
 
 def HK_FLAG_GROUP(g):
@@ -70,7 +72,8 @@ class Info(ctypes.Structure):
                 ("panel", ctypes.c_int), ("ws_bytes", ctypes.c_size_t),
                 ("vec_bytes", ctypes.c_size_t), ("n_update_launches", ctypes.c_int),
                 ("update_ms", ctypes.c_double), ("lookahead", ctypes.c_int),
-                ("n_bulk_launches", ctypes.c_int), ("bulk_ms", ctypes.c_double)]
+                ("n_bulk_launches", ctypes.c_int), ("bulk_ms", ctypes.c_double),
+                ("update_engine", ctypes.c_int)]
 
 
 class Report(ctypes.Structure):
@@ -83,7 +86,7 @@ class Report(ctypes.Structure):
                 ("update_ms", ctypes.c_double), ("bulk_launches", ctypes.c_int),
                 ("bulk_ms", ctypes.c_double), ("limb_macs_bulk", ctypes.c_double), ("certified", ctypes.c_int),
                 ("certify_margin_bits", ctypes.c_double), ("certify_bits", ctypes.c_int), ("lambda_mpf", MPF),
-                ("lambda_words", ctypes.c_uint32 * LAMBDA_WORDS)]
+                ("lambda_words", ctypes.c_uint32 * LAMBDA_WORDS), ("update_engine", ctypes.c_int)]
 
 
 class Instance(ctypes.Structure):
@@ -107,7 +110,9 @@ class MlpMeta(ctypes.Structure):
 class BatchReport(ctypes.Structure):
     _fields_ = [("panel", ctypes.c_int), ("graph_launches", ctypes.c_int),
                 ("t_build_s", ctypes.c_double), ("t_factor_s", ctypes.c_double),
-                ("t_total_s", ctypes.c_double)]
+                ("t_total_s", ctypes.c_double), ("update_launches", ctypes.c_int),
+                ("update_ms", ctypes.c_double), ("bulk_launches", ctypes.c_int),
+                ("bulk_ms", ctypes.c_double), ("update_engine", ctypes.c_int)]
 
 
 _lib = None
@@ -122,7 +127,7 @@ EXPORTS = ["hk_workspace_bytes", "hk_build_matrix", "hk_factor", "hk_solve", "hk
            "hk_eig_learned", "hk_moments_host", "hk_batch_create", "hk_batch_set_schedule",
            "hk_batch_factor", "hk_batch_instance", "hk_batch_destroy", "hk_mul_rate_buffer_bytes", "hk_mul_rate",
            "hk_static_workspace_limit", "hk_smallest_eig_static", "hk_certify",
-           "hk_set_update_group"]
+           "hk_set_update_group", "hk_set_update_engine"]
 
 
 def lib():
@@ -393,6 +398,9 @@ class Matrix(_Factors):
     def set_update_group(self, items):
         _check(lib().hk_set_update_group(self.h, items))
 
+    def set_update_engine(self, engine):
+        _check(lib().hk_set_update_engine(self.h, engine))
+
     def set_lookahead(self, mode):
         _check(lib().hk_set_lookahead(self.h, mode))
 
@@ -496,13 +504,13 @@ def batch_workspace_bytes(insts):
     return lib().hk_batch_workspace_bytes(ctypes.cast(arr, ctypes.c_void_p), len(insts))
 
 
-def eig_batched(insts, digits=45, panel=0, stream=None, ws=None, method=HK_SECANT):
+def eig_batched(insts, digits=45, panel=0, stream=None, ws=None, method=HK_SECANT, flags=0):
     """lambda_1 of every (N, beta, K) instance in one batch (all by `method`,
     inverse iteration from 0 for HK_INVERSE); returns (list of (status,
     decimal, verified, factorizations), report dict)."""
     import torch
     L = lib()
-    arr = _instances(insts, method)
+    arr = _instances(insts, method | flags)
     nbytes = L.hk_batch_workspace_bytes(ctypes.cast(arr, ctypes.c_void_p), len(insts))
     if nbytes == 0:
         raise HKError(1, L.hk_last_error().decode())

@@ -235,3 +235,38 @@ def test_lds_limit_reported(hk):
     m.set_lookahead(0)
     m.factor(0)
     assert m.pivots()[0] > 0
+
+
+@pytest.mark.parametrize("engine,la,panel", [(0, 0, 4), (1, 0, 4), (0, 1, 3), (1, 1, 2), (0, 0, 16)])
+def test_update_engines_vs_oracle(hk, engine, la, panel):
+    # the bulk update on the matrix cores (int8 byte-plane products) and on
+    # the vector units: every digit equals the oracle's either way
+    N, beta, K, xn = 150, (3, 2), 2048, 5
+    log("update engine %d look-ahead %d panel %d" % (engine, la, panel))
+    X = moments(N, beta, K)
+    xf = xn << (K - K // 2)
+    of = oracle.factor_from_moments(X, N, K, xf)
+    m = hk.Matrix(N, beta, K)
+    m.set_panel(panel)
+    m.set_lookahead(la)
+    m.set_update_engine(engine)
+    assert m.info().update_engine == (1 if engine == hk.HK_UPDATE_MATRIX_CORES else 0)
+    m.factor(xf)
+    compare(m, of, N)
+
+
+def test_matrix_core_update_wide_panel(hk):
+    # a 16-column panel of 1040-digit columns: C's byte planes of the whole
+    # panel no longer fit one workgroup's LDS, so the bulk update takes the
+    # one-item-per-wavefront form of the matrix-core kernel
+    N, beta, K = 64, (1, 2), 30000
+    log("matrix-core update, wide panel N=%d K=%d" % (N, K))
+    X = moments(N, beta, K)
+    of = oracle.factor_from_moments(X, N, K, 0)
+    m = hk.Matrix(N, beta, K)
+    assert m.info().max_col_digits * 16 < 32704
+    m.set_panel(16)
+    m.set_lookahead(0)
+    m.factor(0)
+    assert m.info().update_engine == 1
+    compare(m, of, N)
