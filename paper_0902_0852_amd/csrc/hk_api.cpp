@@ -61,7 +61,6 @@ bool make_plan(int N, int64_t bnum, int64_t bden, int K, Plan& P, std::string& e
   for (int r = N - 1; r >= 0; r--) sufmax[r] = std::max(sufmax[r + 1], bX[2 * r]);
   P.cols.resize(N);
   P.itemStart.assign(N + 1, 0);
-  P.tileStart.assign(N + 1, 0);
   int64_t a = 0, kk = 0, cc = 0, ll = 0, l8 = 0, dd = 0;
   P.maxW = 0;
   for (int c = 0; c < N; c++) {
@@ -86,7 +85,6 @@ bool make_plan(int N, int64_t bnum, int64_t bden, int K, Plan& P, std::string& e
     ci.l8off = l8; l8 += (int64_t)4 * ci.G * ci.R * 32;
     ci.doff = dd; dd += W + 2;
     P.itemStart[c + 1] = P.itemStart[c] + ci.items;
-    P.tileStart[c + 1] = P.tileStart[c] + ci.R / 32;
     P.maxW = std::max(P.maxW, W);
   }
   if ((int64_t)P.itemStart[N] >= (int64_t)INT_MAX / 2) { err = "problem too large"; return false; }
@@ -113,7 +111,6 @@ bool make_plan(int N, int64_t bnum, int64_t bden, int K, Plan& P, std::string& e
   auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
   P.o_cols = take(sizeof(ColInfo) * N);
   P.o_items = take(sizeof(int32_t) * (N + 1));
-  P.o_tiles = take(sizeof(int32_t) * (N + 1));
   P.o_A = take(sizeof(int32_t) * a);
   P.o_K = take(sizeof(int64_t) * kk);
   P.o_C = take(sizeof(int32_t) * cc);
@@ -154,7 +151,6 @@ DevPtrs dev_ptrs(const Plan& P, char* ws) {
   DevPtrs D;
   D.cols = (ColInfo*)(ws + P.o_cols);
   D.itemStart = (int32_t*)(ws + P.o_items);
-  D.tileStart = (int32_t*)(ws + P.o_tiles);
   D.A = (int32_t*)(ws + P.o_A);
   D.Kc = (int64_t*)(ws + P.o_K);
   D.C = (int32_t*)(ws + P.o_C);
@@ -192,7 +188,7 @@ DevPtrs dev_ptrs(const Plan& P, char* ws) {
 
 InstDesc make_desc(const Plan& P, const DevPtrs& D) {
   InstDesc I;
-  I.cols = D.cols; I.itemStart = D.itemStart; I.tileStart = D.tileStart;
+  I.cols = D.cols; I.itemStart = D.itemStart;
   I.A = D.A; I.Kc = D.Kc; I.C = D.C; I.S = D.S; I.L = D.L; I.L8 = D.L8; I.LT = D.LT; I.D = D.D;
   I.dinfo = D.dinfo; I.nC = D.nC; I.nCs = D.nCs; I.nL = D.nL; I.b32C = D.b32C; I.flags = D.flags;
   I.X = D.X; I.xs = D.xs;
@@ -426,7 +422,6 @@ hk_status build_matrix_impl(int N, hk_rational beta, int prec_bits, void* dev_ws
   if (e == hipSuccess) e = cp(m->D.desc, &m->desc_host, sizeof(InstDesc));
   if (e == hipSuccess) e = cp(m->D.cols, P.cols.data(), P.cols.size() * sizeof(ColInfo));
   if (e == hipSuccess) e = cp(m->D.itemStart, P.itemStart.data(), P.itemStart.size() * sizeof(int32_t));
-  if (e == hipSuccess) e = cp(m->D.tileStart, P.tileStart.data(), P.tileStart.size() * sizeof(int32_t));
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) { delete m; return fail(HK_EDEVICE, std::string("upload: ") + hipGetErrorString(e)); }
   *out = m;

@@ -57,9 +57,8 @@ struct Plan {
   int LWT = 0;                // digit planes of the L^T rows
   std::vector<ColInfo> cols;
   std::vector<int32_t> itemStart;  // N+1 prefix sums of items
-  std::vector<int32_t> tileStart;  // N+1 prefix sums of 32-row tiles (R / 32)
   // byte offsets in the workspace
-  size_t o_cols, o_items, o_tiles, o_A, o_K, o_C, o_L, o_L8, o_S, o_D, o_dinfo, o_nC, o_nCs, o_nL,
+  size_t o_cols, o_items, o_A, o_K, o_C, o_L, o_L8, o_S, o_D, o_dinfo, o_nC, o_nCs, o_nL,
       o_X, o_xs, o_flags, o_b32C, o_b32L, o_vec, o_LT, o_acc, o_kca, o_ub, o_us, o_wb, o_nU,
       o_nUs, o_dv1, o_dv2, o_md, o_mdinfo, o_dots, o_desc, o_sargs, total;
   int64_t ntri;
@@ -90,7 +89,7 @@ hk_status build_matrix_impl(int N, hk_rational beta, int prec_bits, void* dev_ws
 struct InstDesc;
 struct SweepArgs;
 struct DevPtrs {
-  ColInfo* cols; int32_t* itemStart; int32_t* tileStart;
+  ColInfo* cols; int32_t* itemStart;
   int32_t* A; int64_t* Kc; int32_t* C; int32_t* L; int8_t* L8; uint32_t* S; uint32_t* D; int32_t* dinfo;
   int32_t* nC; int32_t* nCs; int32_t* nL; int32_t* X; int32_t* xs; int32_t* flags;
   int32_t* b32C; int32_t* b32L; int32_t* vec;
@@ -106,7 +105,7 @@ DevPtrs dev_ptrs(const Plan& P, char* ws);
 // every factorisation kernel takes an array of them, a single matrix is a
 // batch of one.
 struct InstDesc {
-  const ColInfo* cols; const int32_t* itemStart; const int32_t* tileStart;
+  const ColInfo* cols; const int32_t* itemStart;
   int32_t* A; int64_t* Kc; int32_t* C; uint32_t* S; int32_t* L; int8_t* L8; int32_t* LT; uint32_t* D;
   int32_t* dinfo; int32_t* nC; int32_t* nCs; int32_t* nL; int32_t* b32C; int32_t* flags;
   const int32_t* X; const int32_t* xs;
@@ -135,7 +134,7 @@ hipError_t launch_expand(const BatchView& B, hipStream_t s);
 constexpr int UPD_NEAR = -1, UPD_FAR = -2;
 // the launches of k_update (the bulk of the update work: j = 0 and UPD_FAR)
 // against those of k_update_near (in-panel and UPD_NEAR, critical path)
-inline bool update_is_bulk(int j) { return j == 0 || j == UPD_FAR; }
+__host__ __device__ inline bool update_is_bulk(int j) { return j == 0 || j == UPD_FAR; }
 // widest column of the batch when its bulk updates run on the matrix cores
 // (k_update_mma), 0 when they run on the vector units (k_update)
 int mma_width(const BatchView& B, int b);

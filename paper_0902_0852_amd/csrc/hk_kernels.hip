@@ -729,18 +729,35 @@ __device__ __forceinline__ void mma_apply(const v16i* D, const InstDesc& I, cons
 // 32-row tile): its four wavefronts build C_k[c]'s byte planes of every panel
 // column k once (LDS), then share out the column's 32-digit output tiles.
 // Wm: the widest column of the launch; the LDS holds (k1 - k0) plane sets.
+constexpr int MMA_RUN = 16;   // consecutive tiles per XCD turn
+
+// Number of (32-row tile, column) pairs with rows in them of an instance of
+// size N for the columns [c_lo, c_hi), tile t32 of column c covering rows
+// c + 32 t32 .. c + 32 t32 + 31: for tile index t32 the columns below
+// N - 32 t32.
+__host__ __device__ inline int mma_tile_count(int N, int c_lo, int c_hi, int t32) {
+  return max(0, min(c_hi, N - 32 * t32) - c_lo);
+}
+
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_update_mma(const InstDesc* __restrict__ desc, int count, int pc, int b,
-                                                     int j, int rd, int Wm) {
+                                                     int j, int rd, int Wm, int per_xcd) {
   extern __shared__ int64_t smem[];
   const int lane = threadIdx.x & 63, w = uni(threadIdx.x >> 6), nw = blockDim.x >> 6;
-  // the instance and column of this workgroup's tile, by the tile prefix
-  int it = blockIdx.x, inst = -1, k0 = 0, k1 = 0, c_lo = 0, c_hi = 0;
+  // Workgroups go round-robin to the chip's eight XCDs; each XCD takes runs
+  // of MMA_RUN consecutive pairs, enumerated tile-major (for tile index 0,
+  // every column, then tile index 1 ...), so that the workgroups one XCD
+  // runs together read the same rows of L from its own L2, while the runs
+  // alternate between the XCDs to spread the work evenly
+  const int q = (int)(blockIdx.x >> 3);
+  int it = ((q / MMA_RUN) * 8 + (int)(blockIdx.x & 7)) * MMA_RUN + q % MMA_RUN;
+  (void)per_xcd;
+  int inst = -1, k0 = 0, k1 = 0, c_lo = 0, c_hi = 0;
   for (int i2 = 0; i2 < count; i2++) {
     int a0, a1, b0, b1;
     const int Ni = sload(&desc[i2].N);
     if (!update_range(Ni, pc, b, j, a0, a1, b0, b1)) continue;
-    const int32_t* ts = sload(&desc[i2].tileStart);
-    const int n = sload(ts + b1) - sload(ts + b0);
+    int n = 0;
+    for (int t = 0; 32 * t < Ni - b0; t++) n += mma_tile_count(Ni, b0, b1, t);
     if (it < n) { inst = i2; k0 = a0; k1 = a1; c_lo = b0; c_hi = b1; break; }
     it -= n;
   }
@@ -749,20 +766,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
   const InstDesc I = sload(desc + inst);
   if (!I.active) return;
   const int N = I.N;
-  it += sload(I.tileStart + c_lo);
-  int lo = c_lo, n = c_hi - c_lo;
-  while (n > 1) {
-    const int step = (n + 63) / 64;
-    const int kx = lane * step;
-    const int v = kx < n ? gp(I.tileStart)[lo + kx] : INT_MAX;
-    const uint64_t m = __ballot(v <= it);
-    const int last = 63 - __clzll((long long)m);
-    lo = uni(lo + last * step);
-    n = min(step, c_hi - lo);
+  int t32 = 0;
+  for (;; t32++) {
+    const int n = mma_tile_count(N, c_lo, c_hi, t32);
+    if (it < n) break;
+    it -= n;
   }
-  const int c = uni(lo);
-  const int t32 = uni(it - sload(I.tileStart + c));
-  if (c + 32 * t32 >= N) return;   // a tile of padding rows only
+  t32 = uni(t32);
+  const int c = uni(c_lo + it);
   const ColInfo cc = sload(I.cols + c);
   const int nk = k1 - k0;
   const int PB = mma_plane_bytes(Wm), X0 = Wm + 64;
@@ -834,12 +845,17 @@ __host__ inline size_t mma_lds(int Wm, int nk) {
   return (size_t)nk * 4 * mma_plane_bytes(Wm) + 8 * (size_t)nk + 8 + 24 * (size_t)nk;
 }
 
-// The bulk update on the matrix cores, one item per wavefront (the form for
-// panels whose C planes do not fit one workgroup's LDS): Wm the widest
-// column of the launch (LDS: four C byte planes per wavefront)
+// The update on the matrix cores, one item per wavefront: the near launches
+// (few columns: one wavefront per 32 x 32 tile spreads them over the whole
+// chip), and the bulk where the panel's C planes do not fit one workgroup's
+// LDS.  Wm: the widest column of the launch (LDS: four C byte planes per
+// wavefront).
 __global__ void __launch_bounds__(256) k_update_mma_w(const InstDesc* __restrict__ desc, int count, int pc, int b,
                                                     int j, int rd, int Wm) {
   extern __shared__ int64_t smem[];
+  // the near launches (in-panel and next-panel columns) are on the critical
+  // path: their waves take the SIMDs' issue slots ahead of the bulk's
+  if (!update_is_bulk(j)) __builtin_amdgcn_s_setprio(3);
   const int w = uni(threadIdx.x >> 6);
   uint32_t* lds = (uint32_t*)smem + w * mma_plane_bytes(Wm);
   mma_item(desc, count, pc, b, j, rd, blockIdx.x * (blockDim.x >> 6) + w, Wm, lds);
@@ -2314,20 +2330,23 @@ hipError_t launch_update(const BatchView& B, int pc, int b, int j, int rd, hipSt
   if (items <= 0) return mark_empty(t0, t1, s);
   const int ipw = B.ipw == 1 || B.ipw == 2 ? B.ipw : 4;
   const dim3 grid((unsigned)((items + ipw - 1) / ipw)), block(64 * ipw);
-  const int Wm = update_is_bulk(j) ? mma_width(B, b) : 0;
-  if (Wm > 0 && mma_lds(Wm, b) <= 65536) {
+  const int Wm = mma_width(B, b);
+  if (Wm > 0 && update_is_bulk(j) && mma_lds(Wm, b) <= 65536) {
     int64_t tiles = 0;
     for (const Plan* p : B.plans) {
       int k0, k1, c_lo, c_hi;
-      if (update_range(p->N, pc, b, j, k0, k1, c_lo, c_hi)) tiles += p->tileStart[c_hi] - p->tileStart[c_lo];
+      if (update_range(p->N, pc, b, j, k0, k1, c_lo, c_hi))
+        for (int t = 0; 32 * t < p->N - c_lo; t++) tiles += mma_tile_count(p->N, c_lo, c_hi, t);
     }
+    if (tiles <= 0) return mark_empty(t0, t1, s);
+    const int per = (int)((tiles + 8 * MMA_RUN - 1) / (8 * MMA_RUN)) * MMA_RUN;
     const size_t shm = mma_lds(Wm, b);
     if (t0 || t1)
-      hipExtLaunchKernelGGL(k_update_mma, dim3((unsigned)tiles), dim3(256), shm, s, t0, t1, 0, B.ddesc,
-                            (int)B.plans.size(), pc, b, j, rd, Wm);
+      hipExtLaunchKernelGGL(k_update_mma, dim3(8u * per), dim3(256), shm, s, t0, t1, 0, B.ddesc,
+                            (int)B.plans.size(), pc, b, j, rd, Wm, per);
     else
-      hipLaunchKernelGGL(k_update_mma, dim3((unsigned)tiles), dim3(256), shm, s, B.ddesc, (int)B.plans.size(), pc,
-                         b, j, rd, Wm);
+      hipLaunchKernelGGL(k_update_mma, dim3(8u * per), dim3(256), shm, s, B.ddesc, (int)B.plans.size(), pc, b, j,
+                         rd, Wm, per);
     return hipGetLastError();
   }
   if (Wm > 0) {
