@@ -459,44 +459,85 @@ __device__ __forceinline__ void apply_block_v(const int64_t* acc, const int32_t*
   else if (v != 0) gor(flags, 1);
 }
 
-// One item of the matrix-core update: column c, 32 rows (tile t32 of the
-// column's 32-row tiles), output digits [32 q2, 32 q2 + 32) (blocks 2 q2 and
-// 2 q2 + 1).  Lane l: row r = c + 32 t32 + l % 32, half h = l / 32 of the
-// K operand digits; after the exchange at the end, the lane applies block
-// 2 q2 + h of its row.  lds: this wavefront's four C byte planes.
-__device__ __forceinline__ void mma_item(const InstDesc* __restrict__ desc, int count, int pc, int b, int j,
-                                         int rd, int it, int Wm, uint32_t* lds) {
+// The digits and carries of the tile's exact sums (from D) subtracted from
+// A's blocks 2 q2 + h of row r (lane l: row r, half h = l / 32)
+__device__ __forceinline__ void mma_apply(const v16i* D, const InstDesc& I, const ColInfo& cc, int c, int r,
+                                          bool active, int q2, int rd, int lane) {
+  const int h = lane >> 5;
+  int32_t dg[16];
+  int64_t cy[16];
+#pragma unroll
+  for (int v = 0; v < 16; v++) {
+    const int64_t lo = (int64_t)D[0][v] + ((int64_t)D[1][v] << 8) + ((int64_t)D[2][v] << 16) +
+                       ((int64_t)D[3][v] << 24);
+    const int64_t hi = (int64_t)D[4][v] + ((int64_t)D[5][v] << 8) + ((int64_t)D[6][v] << 16);
+    dg[v] = balanced29(lo);
+    cy[v] = ((lo - dg[v]) >> DB) + (hi << 3);
+  }
+  int32_t rdg[8];
+  int64_t rcy[8];
+#pragma unroll
+  for (int u = 0; u < 8; u++) {
+    const int v = h ? u : u + 8;
+    rdg[u] = (int32_t)swap_halves((int64_t)dg[v]);
+    rcy[u] = swap_halves(cy[v]);
+  }
+  int64_t acc[WB + 1];
+  int64_t prev = h ? cy[7] : 0;
+#pragma unroll
+  for (int m = 0; m < WB; m++) {
+    const int grp = m >> 2, e = m & 3;
+    const bool own = (grp & 1) == h;
+    const int v = 8 * h + 4 * (grp >> 1) + e, u = 4 * (grp >> 1) + e;
+    acc[m] = (int64_t)(own ? dg[v] : rdg[u]) + prev;
+    prev = own ? cy[v] : rcy[u];
+  }
+  acc[WB] = h ? prev : 0;
+  if (!active) return;
+  const int lr = r - c, q = 2 * q2 + h;
+  int64_t* Kcol = I.Kc + cc.koff;
+  apply_block_v(acc, uptr(I.A + cc.aoff), (int64_t)cc.W * cc.R * 4, lr, cc.R, q,
+                q > 0 ? gp(Kcol + ((int64_t)rd * cc.nb + q) * cc.R + lr) : nullptr,
+                q + 1 < cc.nb ? gp(Kcol + ((int64_t)(rd ^ 1) * cc.nb + q + 1) * cc.R + lr) : nullptr,
+                gp(I.flags));
+}
+
+// Where one item of the matrix-core update lies: column c, 32 rows (tile
+// t32 of the column's 32-row tiles), output digits [32 q2, 32 q2 + 32)
+// (blocks 2 q2 and 2 q2 + 1) of instance I.
+struct MmaItem {
+  InstDesc I;
+  ColInfo cc;
+  int k0, k1, c, q2, t32, r, rr;
+  bool active;
+};
+
+// The item's digit products by the panel columns k0 + kf, k0 + kf + ks, ...
+// into D (zeroed here).  Lane l: row r = c + 32 t32 + l % 32, half h = l / 32
+// of the K operand digits.  lds: this wavefront's four C byte planes.
+__device__ __forceinline__ void mma_accum(v16i* D, const MmaItem& T, int kf, int ks, int Wm, uint32_t* lds) {
   const int lane = threadIdx.x & 63, i = lane & 31, h = lane >> 5;
-  int inst, k0, k1, c, rem;
-  if (!find_update_item(desc, count, pc, b, j, it, inst, k0, k1, c, rem)) return;
-  const InstDesc I = sload(desc + inst);
-  const int N = I.N;
-  const ColInfo cc = sload(I.cols + c);
-  const int T32 = cc.R >> 5;
-  const int q2 = uni(rem / T32);
-  const int t32 = uni(rem - q2 * T32);
-  const int t0 = 32 * q2;
-  const int r = c + 32 * t32 + i;
-  const bool active = r < N;
-  const int rr = active ? r : N - 1;
+  const InstDesc& I = T.I;
+  const int N = I.N, c = T.c, k0 = T.k0, k1 = T.k1, rr = T.rr;
+  const bool active = T.active;
+  const int t0 = 32 * T.q2;
   const int PB = mma_plane_bytes(Wm), X0 = Wm + 64;
   int8_t* planes = (int8_t*)lds;
-
-  v16i D[7];
 #pragma unroll
   for (int s = 0; s < 7; s++)
 #pragma unroll
     for (int v = 0; v < 16; v++) D[s][v] = 0;
+  if (k0 + kf >= k1) return;
   // the digit counts of the next panel column are requested one column ahead
-  int nCn = sload(I.nC + tri_index(N, k0, c));
-  int nLn = active ? gp(I.nL)[tri_index(N, k0, rr)] : 0;
-  for (int k = k0; k < k1; k++) {
+  int nCn = sload(I.nC + tri_index(N, k0 + kf, c));
+  int nLn = active ? gp(I.nL)[tri_index(N, k0 + kf, rr)] : 0;
+  for (int k = k0 + kf; k < k1; k += ks) {
     const ColInfo kk = sload(I.cols + k);
     const int nC = min(nCn, kk.CW - WB);
     const int nLl = nLn;
-    if (k + 1 < k1) {
-      nCn = sload(I.nC + tri_index(N, k + 1, c));
-      nLn = active ? gp(I.nL)[tri_index(N, k + 1, rr)] : 0;
+    if (k + ks < k1) {
+      nCn = sload(I.nC + tri_index(N, k + ks, c));
+      nLn = active ? gp(I.nL)[tri_index(N, k + ks, rr)] : 0;
     }
     const int nL = min(uni(wave_max(nLl)), kk.LW - 2 * WB);
     const int jlo = max(0, t0 - nC + 1), jhi = min(nL, t0 + 32);
@@ -569,47 +610,22 @@ __device__ __forceinline__ void mma_item(const InstDesc* __restrict__ desc, int 
       mm(A2, B2);
     }
   }
-  // D_s[t][r] for t = 8 (v / 4) + 4 h + v % 4: digits and carries of V_t
-  int32_t dg[16];
-  int64_t cy[16];
-#pragma unroll
-  for (int v = 0; v < 16; v++) {
-    const int64_t lo = (int64_t)D[0][v] + ((int64_t)D[1][v] << 8) + ((int64_t)D[2][v] << 16) +
-                       ((int64_t)D[3][v] << 24);
-    const int64_t hi = (int64_t)D[4][v] + ((int64_t)D[5][v] << 8) + ((int64_t)D[6][v] << 16);
-    dg[v] = balanced29(lo);
-    cy[v] = ((lo - dg[v]) >> DB) + (hi << 3);
-  }
-  // half 0 takes t in [0, 16), half 1 t in [16, 32): exchange the four-digit
-  // groups the other half holds
-  int32_t rdg[8];
-  int64_t rcy[8];
-#pragma unroll
-  for (int u = 0; u < 8; u++) {
-    const int v = h ? u : u + 8;
-    rdg[u] = (int32_t)swap_halves((int64_t)dg[v]);
-    rcy[u] = swap_halves(cy[v]);
-  }
-  int64_t acc[WB + 1];
-  int64_t prev = h ? cy[7] : 0;         // carry out of t = 15 (held by half 1)
-#pragma unroll
-  for (int m = 0; m < WB; m++) {
-    const int grp = m >> 2, e = m & 3;
-    const bool own = (grp & 1) == h;    // half 0 holds groups 0, 2; half 1 groups 1, 3
-    const int v = 8 * h + 4 * (grp >> 1) + e, u = 4 * (grp >> 1) + e;
-    const int32_t d = own ? dg[v] : rdg[u];
-    const int64_t y = own ? cy[v] : rcy[u];
-    acc[m] = (int64_t)d + prev;
-    prev = y;
-  }
-  acc[WB] = h ? prev : 0;               // half 0 hands its top carry to half 1
-  if (!active) return;
-  const int lr = r - c, q = 2 * q2 + h;
-  int64_t* Kcol = I.Kc + cc.koff;
-  apply_block_v(acc, uptr(I.A + cc.aoff), (int64_t)cc.W * cc.R * 4, lr, cc.R, q,
-                q > 0 ? gp(Kcol + ((int64_t)rd * cc.nb + q) * cc.R + lr) : nullptr,
-                q + 1 < cc.nb ? gp(Kcol + ((int64_t)(rd ^ 1) * cc.nb + q + 1) * cc.R + lr) : nullptr,
-                gp(I.flags));
+}
+
+// The item of update launch item `it`; false if there is none
+__device__ __forceinline__ bool mma_find(const InstDesc* __restrict__ desc, int count, int pc, int b, int j, int it,
+                                         MmaItem& T) {
+  int inst, rem;
+  if (!find_update_item(desc, count, pc, b, j, it, inst, T.k0, T.k1, T.c, rem)) return false;
+  T.I = sload(desc + inst);
+  T.cc = sload(T.I.cols + T.c);
+  const int T32 = T.cc.R >> 5;
+  T.q2 = uni(rem / T32);
+  T.t32 = uni(rem - T.q2 * T32);
+  T.r = T.c + 32 * T.t32 + (int)(threadIdx.x & 31);
+  T.active = T.r < T.I.N;
+  T.rr = T.active ? T.r : T.I.N - 1;
+  return true;
 }
 
 // The digit products of one 32 x 32 tile on the matrix cores: D (zeroed
@@ -682,54 +698,12 @@ __device__ __forceinline__ void mma_tile(v16i* D, const MmaCols& M, const GLOBAL
   }
 }
 
-// The digits and carries of the tile's exact sums (from D) subtracted from
-// A's blocks 2 q2 + h of row r, as at the end of mma_item
-__device__ __forceinline__ void mma_apply(const v16i* D, const InstDesc& I, const ColInfo& cc, int c, int r,
-                                          bool active, int q2, int rd, int lane) {
-  const int h = lane >> 5;
-  int32_t dg[16];
-  int64_t cy[16];
-#pragma unroll
-  for (int v = 0; v < 16; v++) {
-    const int64_t lo = (int64_t)D[0][v] + ((int64_t)D[1][v] << 8) + ((int64_t)D[2][v] << 16) +
-                       ((int64_t)D[3][v] << 24);
-    const int64_t hi = (int64_t)D[4][v] + ((int64_t)D[5][v] << 8) + ((int64_t)D[6][v] << 16);
-    dg[v] = balanced29(lo);
-    cy[v] = ((lo - dg[v]) >> DB) + (hi << 3);
-  }
-  int32_t rdg[8];
-  int64_t rcy[8];
-#pragma unroll
-  for (int u = 0; u < 8; u++) {
-    const int v = h ? u : u + 8;
-    rdg[u] = (int32_t)swap_halves((int64_t)dg[v]);
-    rcy[u] = swap_halves(cy[v]);
-  }
-  int64_t acc[WB + 1];
-  int64_t prev = h ? cy[7] : 0;
-#pragma unroll
-  for (int m = 0; m < WB; m++) {
-    const int grp = m >> 2, e = m & 3;
-    const bool own = (grp & 1) == h;
-    const int v = 8 * h + 4 * (grp >> 1) + e, u = 4 * (grp >> 1) + e;
-    acc[m] = (int64_t)(own ? dg[v] : rdg[u]) + prev;
-    prev = own ? cy[v] : rcy[u];
-  }
-  acc[WB] = h ? prev : 0;
-  if (!active) return;
-  const int lr = r - c, q = 2 * q2 + h;
-  int64_t* Kcol = I.Kc + cc.koff;
-  apply_block_v(acc, uptr(I.A + cc.aoff), (int64_t)cc.W * cc.R * 4, lr, cc.R, q,
-                q > 0 ? gp(Kcol + ((int64_t)rd * cc.nb + q) * cc.R + lr) : nullptr,
-                q + 1 < cc.nb ? gp(Kcol + ((int64_t)(rd ^ 1) * cc.nb + q + 1) * cc.R + lr) : nullptr,
-                gp(I.flags));
-}
-
 // The bulk update on the matrix cores, one workgroup per (instance, column,
 // 32-row tile): its four wavefronts build C_k[c]'s byte planes of every panel
 // column k once (LDS), then share out the column's 32-digit output tiles.
 // Wm: the widest column of the launch; the LDS holds (k1 - k0) plane sets.
 constexpr int MMA_RUN = 16;   // consecutive tiles per XCD turn
+constexpr int MMA_SPLIT_ITEMS = 512;   // near launches up to this many items: k_update_mma_sk
 
 // Number of (32-row tile, column) pairs with rows in them of an instance of
 // size N for the columns [c_lo, c_hi), tile t32 of column c covering rows
@@ -846,19 +820,57 @@ __host__ inline size_t mma_lds(int Wm, int nk) {
 }
 
 // The update on the matrix cores, one item per wavefront: the near launches
-// (few columns: one wavefront per 32 x 32 tile spreads them over the whole
-// chip), and the bulk where the panel's C planes do not fit one workgroup's
-// LDS.  Wm: the widest column of the launch (LDS: four C byte planes per
-// wavefront).
+// with many items, and the bulk where the panel's C planes do not fit one
+// workgroup's LDS.  Wm: the widest column of the launch (LDS: four C byte
+// planes per wavefront).
 __global__ void __launch_bounds__(256) k_update_mma_w(const InstDesc* __restrict__ desc, int count, int pc, int b,
                                                     int j, int rd, int Wm) {
   extern __shared__ int64_t smem[];
-  // the near launches (in-panel and next-panel columns) are on the critical
-  // path: their waves take the SIMDs' issue slots ahead of the bulk's
-  if (!update_is_bulk(j)) __builtin_amdgcn_s_setprio(3);
   const int w = uni(threadIdx.x >> 6);
   uint32_t* lds = (uint32_t*)smem + w * mma_plane_bytes(Wm);
-  mma_item(desc, count, pc, b, j, rd, blockIdx.x * (blockDim.x >> 6) + w, Wm, lds);
+  if (!update_is_bulk(j)) __builtin_amdgcn_s_setprio(3);
+  MmaItem T;
+  if (!mma_find(desc, count, pc, b, j, blockIdx.x * (blockDim.x >> 6) + w, T)) return;
+  if (!T.I.active) return;
+  v16i D[7];
+  mma_accum(D, T, 0, 1, Wm, lds);
+  mma_apply(D, T.I, T.cc, T.c, T.r, T.active, T.q2, rd, (int)(threadIdx.x & 63));
+}
+
+// The near launches on the matrix cores (the in-panel columns and the next
+// panel's: few columns, on the critical path): one workgroup per item, its
+// four wavefronts splitting the panel columns k between them (k0 + w, k0 +
+// w + 4, ...), their int32 products summed by LDS atomic adds (exact, so
+// the order does not matter), and wavefront 0 applying the result.  The
+// waves take the SIMDs' issue slots ahead of the bulk launch's.  LDS: four
+// C byte planes per wavefront, then the 7 x 16 x 64 int32 sums.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_update_mma_sk(const InstDesc* __restrict__ desc, int count, int pc, int b,
+                                                     int j, int rd, int Wm) {
+  extern __shared__ int64_t smem[];
+  __builtin_amdgcn_s_setprio(3);
+  const int lane = threadIdx.x & 63, w = uni(threadIdx.x >> 6), nw = blockDim.x >> 6;
+  const int PB = mma_plane_bytes(Wm);
+  uint32_t* lds = (uint32_t*)smem + w * PB;
+  int32_t* sum = (int32_t*)((uint32_t*)smem + nw * PB);
+  MmaItem T;
+  if (!mma_find(desc, count, pc, b, j, blockIdx.x, T)) return;   // uniform over the workgroup
+  if (!T.I.active) return;
+  for (int x = threadIdx.x; x < 7 * 16 * 64; x += blockDim.x) sum[x] = 0;
+  __syncthreads();
+  v16i D[7];
+  mma_accum(D, T, w, nw, Wm, lds);
+#pragma unroll
+  for (int s = 0; s < 7; s++)
+#pragma unroll
+    for (int v = 0; v < 16; v++) __hip_atomic_fetch_add(sum + (s * 16 + v) * 64 + lane, D[s][v], __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_WORKGROUP);
+  __syncthreads();
+  if (w != 0) return;
+#pragma unroll
+  for (int s = 0; s < 7; s++)
+#pragma unroll
+    for (int v = 0; v < 16; v++) D[s][v] = sum[(s * 16 + v) * 64 + lane];
+  mma_apply(D, T.I, T.cc, T.c, T.r, T.active, T.q2, rd, lane);
 }
 
 struct FinOut {
@@ -2308,9 +2320,10 @@ static hipError_t mark_empty(hipEvent_t t0, hipEvent_t t1, hipStream_t s) {
   if (e == hipSuccess && t1) e = hipEventRecord(t1, s);
   return e;
 }
-// The widest column of a batch when its bulk updates run on the matrix cores,
-// else 0: off when HK_MMA=0, or when the int32 accumulators could overflow
-// (b panel columns of up to Wm digits: b Wm must stay below 2^15).
+// The widest column of a batch when its updates run on the matrix cores,
+// else 0: off when HK_MMA=0, when the int32 accumulators could overflow (b
+// panel columns of up to Wm digits: b Wm must stay below 2^15), or when the
+// near launches' LDS would exceed the device's.
 int mma_width(const BatchView& B, int b) {
   static const int off = [] {
     const char* v = getenv("HK_MMA");
@@ -2320,6 +2333,8 @@ int mma_width(const BatchView& B, int b) {
   int Wm = 0;
   for (const Plan* p : B.plans) Wm = std::max(Wm, p->maxW);
   if ((int64_t)std::max(b, 1) * Wm >= 32768 - 64) return 0;
+  // the near launches' LDS: four waves' C planes and the int32 sums
+  if ((size_t)16 * mma_plane_bytes(Wm) + 7 * 16 * 64 * sizeof(int32_t) > device_lds_limit()) return 0;
   return Wm;
 }
 
@@ -2347,6 +2362,20 @@ hipError_t launch_update(const BatchView& B, int pc, int b, int j, int rd, hipSt
     else
       hipLaunchKernelGGL(k_update_mma, dim3(8u * per), dim3(256), shm, s, B.ddesc, (int)B.plans.size(), pc, b, j,
                          rd, Wm, per);
+    return hipGetLastError();
+  }
+  // near launches small enough to leave most of the chip idle split their
+  // panel columns over four wavefronts per item; larger ones keep one
+  // wavefront per item (the split only adds waves to a launch that fills
+  // the chip already)
+  if (Wm > 0 && !update_is_bulk(j) && items <= MMA_SPLIT_ITEMS) {
+    const size_t shm = (size_t)16 * mma_plane_bytes(Wm) + 7 * 16 * 64 * sizeof(int32_t);
+    if (t0 || t1)
+      hipExtLaunchKernelGGL(k_update_mma_sk, dim3((unsigned)items), dim3(256), shm, s, t0, t1, 0, B.ddesc,
+                            (int)B.plans.size(), pc, b, j, rd, Wm);
+    else
+      hipLaunchKernelGGL(k_update_mma_sk, dim3((unsigned)items), dim3(256), shm, s, B.ddesc, (int)B.plans.size(), pc,
+                         b, j, rd, Wm);
     return hipGetLastError();
   }
   if (Wm > 0) {
