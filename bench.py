@@ -218,13 +218,19 @@ def peak_rates(args):
     import paper_0902_0852_amd as hk
     kinds = [("v_mad_i64_i32", hk.HK_RATE_MAD_I64_I32), ("v_mad_u64_u32", hk.HK_RATE_MAD_U64_U32),
              ("v_mad_u32_u24", hk.HK_RATE_MAD_U32_U24), ("v_fma_f64", hk.HK_RATE_FMA_F64)]
-    out = {"metric": "measured VALU issue rate (lane operations/s)", "unit": "ops/s", "n_gpus": 1,
-           "nominal_per_s": PEAK_INT_MUL, "rates": {}}
+    out = {"metric": "measured issue rate (VALU: lane operations/s; matrix cores: int8 multiply-adds/s)",
+           "unit": "ops/s", "n_gpus": 1, "nominal_per_s": PEAK_INT_MUL, "rates": {}}
     for name, k in kinds:
         rate, clk = hk.mul_rate(k)
         out["rates"][name] = {"per_s": rate, "of_nominal": rate / PEAK_INT_MUL, "clock_hz": clk,
                               "per_lane_per_clock": rate / (256 * 64 * clk) if clk > 0 else None}
         log("%-14s %.4e ops/s = %.3f of nominal, clock %.3f GHz" % (name, rate, rate / PEAK_INT_MUL, clk / 1e9))
+    rate, clk = hk.mul_rate(hk.HK_RATE_MFMA_I8)
+    out["rates"]["v_mfma_i32_32x32x32_i8"] = {"per_s": rate, "unit": "int8 multiply-adds/s",
+                                              "of_dense_peak": 2 * rate / PEAK_INT8_OPS, "clock_hz": clk,
+                                              "limb_macs_per_s": rate / 16 / (32 / 29) ** 2}
+    log("%-14s %.4e MAC/s = %.3f of the 5.0 POP/s dense peak, clock %.3f GHz; %.4e limb-MAC/s of 29-bit digits"
+        % ("mfma_i8", rate, 2 * rate / PEAK_INT8_OPS, clk / 1e9, rate / 16 / (32 / 29) ** 2))
     print(json.dumps(out), flush=True)
 
 

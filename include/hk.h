@@ -305,8 +305,11 @@ int64_t hk_vec_export(hk_matrix m, const void* dev_vec, int n, int32_t* slen, in
    and per-wave clock samples).  *per_s: lane operations per second (one
    timed launch after a warm-up launch); *clock_hz (may be NULL): the shader
    clock during the timed launch, from each wave's cycle counter against
-   the constant-rate counter.  Synchronises s. */
-enum { HK_RATE_MAD_I64_I32 = 0, HK_RATE_MAD_U64_U32 = 1, HK_RATE_MAD_U32_U24 = 2, HK_RATE_FMA_F64 = 3 };
+   the constant-rate counter.  HK_RATE_MFMA_I8: the matrix-core update's
+   instruction (v_mfma_i32_32x32x32_i8), four independent products per wave;
+   *per_s counts int8 multiply-adds.  Synchronises s. */
+enum { HK_RATE_MAD_I64_I32 = 0, HK_RATE_MAD_U64_U32 = 1, HK_RATE_MAD_U32_U24 = 2, HK_RATE_FMA_F64 = 3,
+       HK_RATE_MFMA_I8 = 4 };
 size_t hk_mul_rate_buffer_bytes(void);
 hk_status hk_mul_rate(int kind, void* dev_buf, size_t buf_bytes, hipStream_t s, double* per_s, double* clock_hz);
 

@@ -9,4 +9,5 @@ from .hk import (HK_INVERSE, HK_SECANT, HK_FLAG_NO_WORK_COUNT, HK_FLAG_TIME_UPDA
                  workspace_bytes, batch_workspace_bytes, eig_batched, autotune,
                  mlp_nparams, mlp_cache_floats, mlp_forward, mlp_backward, mlp_mse, mlp_adam_step,
                  bracket_batched, mlp_meta, mlp_propose, eig_learned, moments_host, Batch, BatchMember, mpf_value,
-                 mul_rate, smallest_eig_static, HK_RATE_MAD_I64_I32, HK_RATE_MAD_U64_U32, HK_RATE_MAD_U32_U24, HK_RATE_FMA_F64)
+                 mul_rate, smallest_eig_static, HK_RATE_MAD_I64_I32, HK_RATE_MAD_U64_U32, HK_RATE_MAD_U32_U24, HK_RATE_FMA_F64,
+                 HK_RATE_MFMA_I8)

@@ -1,6 +1,6 @@
-// Issue rate of the VALU multiply instructions the update kernel could use,
-// measured on the running GPU: the denominator of the update kernel's
-// fraction of the integer-multiply peak.  Every lane of a grid that fills
+// Issue rate of the multiply instructions the update kernels use or could
+// use, measured on the running GPU: the VALU multiplies, and the int8 matrix
+// product of the matrix-core update (multiply-adds per second).  Every lane of a grid that fills
 // every SIMD runs CH independent chains of one instruction kind (no chain
 // waits on another, so the rate is the issue rate, not the latency); the
 // chains' results are stored so that nothing is optimised away.  Each wave
@@ -72,6 +72,22 @@ __global__ void __launch_bounds__(256) k_rate(int64_t* out, int64_t* clk, uint32
     }
 #pragma unroll
     for (int j = 0; j < RATE_CH; j++) r ^= acc[j];
+  } else if constexpr (KIND == HK_RATE_MFMA_I8) {
+    // the matrix-core update's instruction: 32 x 32 x 32 int8 products into
+    // int32, four independent accumulators per wave
+    typedef int v16 __attribute__((ext_vector_type(16)));
+    typedef int v4 __attribute__((ext_vector_type(4)));
+    v16 c0 = {0}, c1 = {0}, c2 = {0}, c3 = {0};
+    const v4 a = {(int)m, (int)(m * 3u), (int)(m * 5u), (int)(m * 7u)};
+    const v4 b = {(int)(m ^ 1u), (int)(m ^ 2u), (int)(m ^ 3u), (int)(m ^ 4u)};
+    for (int i = 0; i < RATE_ITERS / 16; i++) {
+      c0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, c0, 0, 0, 0);
+      c1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(b, a, c1, 0, 0, 0);
+      c2 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, a, c2, 0, 0, 0);
+      c3 = __builtin_amdgcn_mfma_i32_32x32x32_i8(b, b, c3, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 16; v++) r ^= (int64_t)(c0[v] ^ c1[v] ^ c2[v] ^ c3[v]);
   } else {
     // HK_RATE_FMA_F64: the double-precision FMA, for comparison
     double acc[RATE_CH];
@@ -126,7 +142,7 @@ size_t hk_mul_rate_buffer_bytes(void) {
 }
 
 hk_status hk_mul_rate(int kind, void* dev_buf, size_t buf_bytes, hipStream_t s, double* per_s, double* clock_hz) {
-  if (!per_s || kind < HK_RATE_MAD_I64_I32 || kind > HK_RATE_FMA_F64) {
+  if (!per_s || kind < HK_RATE_MAD_I64_I32 || kind > HK_RATE_MFMA_I8) {
     g_err = "bad arguments";
     return HK_EINVAL;
   }
@@ -145,6 +161,8 @@ hk_status hk_mul_rate(int kind, void* dev_buf, size_t buf_bytes, hipStream_t s, 
         hipLaunchKernelGGL(k_rate<HK_RATE_MAD_U64_U32>, dim3(r.blocks), dim3(256), 0, s, out, clk, 7u); break;
       case HK_RATE_MAD_U32_U24:
         hipLaunchKernelGGL(k_rate<HK_RATE_MAD_U32_U24>, dim3(r.blocks), dim3(256), 0, s, out, clk, 7u); break;
+      case HK_RATE_MFMA_I8:
+        hipLaunchKernelGGL(k_rate<HK_RATE_MFMA_I8>, dim3(r.blocks), dim3(256), 0, s, out, clk, 7u); break;
       default:
         hipLaunchKernelGGL(k_rate<HK_RATE_FMA_F64>, dim3(r.blocks), dim3(256), 0, s, out, clk, 7u); break;
     }
@@ -166,7 +184,11 @@ hk_status hk_mul_rate(int kind, void* dev_buf, size_t buf_bytes, hipStream_t s, 
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   if (e != hipSuccess) { g_err = hipGetErrorString(e); return HK_EDEVICE; }
-  *per_s = (double)r.threads * RATE_CH * (double)RATE_ITERS / (1e-3 * (double)ms);
+  // per lane: RATE_CH chains of RATE_ITERS steps, or (matrix products) four
+  // chains of RATE_ITERS / 16 products of 32 x 32 x 32 multiply-adds a wave
+  const double per_lane = kind == HK_RATE_MFMA_I8 ? 4.0 * (RATE_ITERS / 16) * 32768.0 / 64.0
+                                                  : (double)RATE_CH * (double)RATE_ITERS;
+  *per_s = (double)r.threads * per_lane / (1e-3 * (double)ms);
   if (clock_hz) {
     int dev = 0, wall_khz = 0;
     if (hipGetDevice(&dev) != hipSuccess ||

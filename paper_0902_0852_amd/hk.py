@@ -592,7 +592,7 @@ class Batch:
         return BatchMember(self, i, self.insts[i][0])
 
 
-HK_RATE_MAD_I64_I32, HK_RATE_MAD_U64_U32, HK_RATE_MAD_U32_U24, HK_RATE_FMA_F64 = 0, 1, 2, 3
+HK_RATE_MAD_I64_I32, HK_RATE_MAD_U64_U32, HK_RATE_MAD_U32_U24, HK_RATE_FMA_F64, HK_RATE_MFMA_I8 = 0, 1, 2, 3, 4
 
 
 def mul_rate(kind, stream=None):
