@@ -98,10 +98,10 @@ def cpu_baseline(cfg, method, budget_s=20.0):
     """The oracle (test infrastructure) on the same workload, bounded.  For
     a single small run: whole verified lambda_1 runs (iteration + the two
     bracket factorisations) until the budget is spent, work = factorisations
-    x the limb MACs of one.  For N >= 500 (where the oracle needs minutes for
-    one whole factorisation): the first 64 columns of the factorisation at
-    x = 0 of the configuration's sample run, which carry about a third of its
-    update work; the rate is the same quantity, limb MACs per second."""
+    x the limb MACs of one.  For N >= 500: one whole factorisation at x = 0
+    of the configuration's sample run (about 10 s on 16 host threads at
+    N = 500, K = 6144); the rate is the same quantity, limb MACs per
+    second."""
     import oracle
     from oracle.drivers import inverse_iteration, secant, verify
     from oracle.moments import moments
@@ -109,14 +109,13 @@ def cpu_baseline(cfg, method, budget_s=20.0):
     X = moments(N, beta, K)                 # matrix generation excluded, as in the paper
     info = {"cores": oracle.max_threads(), "kind": "oracle", "cpu": cpu_model(), "nproc": os.cpu_count()}
     if N >= 500:
-        ncols = 64
         t0 = time.time()
-        f = oracle.factor_from_moments(X, N, K, 0, ncols=ncols)
+        f = oracle.factor_from_moments(X, N, K, 0)
         dt = time.time() - t0
         info.update({"value": f.limb_macs / dt, "unit": "limb-MAC/s",
-                     "sample": "the first %d columns of the factorisation at x = 0 of N=%d beta=%d/%d K=%d "
+                     "sample": "one whole factorisation at x = 0 of N=%d beta=%d/%d K=%d "
                                "(%.3e limb-MACs), moments excluded, %.1f s"
-                               % (ncols, N, beta[0], beta[1], K, f.limb_macs, dt)})
+                               % (N, beta[0], beta[1], K, f.limb_macs, dt)})
         return info
     macs0 = oracle.factor_from_moments(X, N, K, 0).limb_macs
     t0 = time.time()
@@ -334,16 +333,24 @@ def plain_batched(args, cfg, hk, torch):
         raise SystemExit("the batched driver runs the Secant iteration")
     tune_path = os.path.join(tempfile.gettempdir(), "hk_tune_%d.txt" % os.getpid())
     os.environ["HK_TUNE_CACHE"] = tune_path
+    # batches: the runs dealt round-robin after sorting by work (widest first)
+    nsplit = max(1, min(args.split, len(runs)))
+    order = sorted(range(len(runs)), key=lambda i: -hk.workspace_bytes(*runs[i]))
+    groups = [[order[k] for k in range(g, len(runs), nsplit)] for g in range(nsplit)]
     if args.panel > 0:
         panel, la, group = args.panel, args.lookahead, args.group or 4
     else:
-        panel, la, group = hk.autotune(runs, cache_path=tune_path)
+        panel, la, group = hk.autotune([runs[i] for i in groups[0]], cache_path=tune_path)
         group = args.group or group
     la_flag = {0: hk.HK_FLAG_LOOKAHEAD_OFF, 1: hk.HK_FLAG_LOOKAHEAD_ON, 2: hk.HK_FLAG_LOOKAHEAD_FUSED}.get(la, 0)
     bflags = la_flag | hk.HK_FLAG_GROUP(group)
     log("batch of %d runs: panel width %d, look-ahead %d, %d update items per workgroup (%s)"
         % (len(runs), panel, la, group, "given" if args.panel > 0 else "tuned"))
-    ws = torch.empty(hk.batch_workspace_bytes(runs), dtype=torch.uint8, device="cuda")
+    wsg = [torch.empty(hk.batch_workspace_bytes([runs[i] for i in g]), dtype=torch.uint8, device="cuda")
+           for g in groups]
+    streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in groups[1:]]
+    from concurrent.futures import ThreadPoolExecutor
+    pool = ThreadPoolExecutor(max_workers=len(groups)) if len(groups) > 1 else None
     # untimed reference: each run alone, with its work count
     wss = torch.empty(max(hk.workspace_bytes(N, beta, K) for N, beta, K in runs), dtype=torch.uint8,
                       device="cuda")
@@ -358,11 +365,23 @@ def plain_batched(args, cfg, hk, torch):
     macs_bulk = sum(r["limb_macs_bulk"] for _, r in single)
     lams = [dec for dec, _ in single]
 
-    def one_step(extra):
-        res, d = hk.eig_batched(runs, digits=45, panel=panel, ws=ws, method=hk.HK_SECANT, flags=bflags | extra)
-        for (st, dec, ver, nf), (dec1, r1) in zip(res, single):
+    def one_batch(gi, extra):
+        g = groups[gi]
+        res, d = hk.eig_batched([runs[i] for i in g], digits=45, panel=panel, ws=wsg[gi], stream=streams[gi],
+                                method=hk.HK_SECANT, flags=bflags | extra)
+        for (st, dec, ver, nf), i in zip(res, g):
+            dec1, r1 = single[i]
             assert st == 0 and ver == 1, (st, dec)
             assert dec == dec1 and nf == r1["factorizations"], (dec, dec1, nf, r1["factorizations"])
+        return d
+
+    def one_step(extra):
+        if pool is None:
+            return one_batch(0, extra)
+        ds = list(pool.map(lambda gi: one_batch(gi, extra), range(len(groups))))
+        d = dict(ds[0])
+        for k in ("update_launches", "update_ms", "bulk_launches", "bulk_ms"):
+            d[k] = sum(x[k] for x in ds)
         return d
     log("work per step: %.4e limb-MACs over %d factorisations; lambda_1 = %s"
         % (macs_per_step, sum(r["factorizations"] for _, r in single), ", ".join(lams)))
@@ -397,6 +416,7 @@ def plain_batched(args, cfg, hk, torch):
                                "as one batch, verified to 45 digits" % cfg["desc"],
                    "N": [N for N, _, _ in runs], "beta": ["%d/%d" % b for _, b, _ in runs],
                    "prec_bits": [K for _, _, K in runs], "method": "secant", "driver": "batched",
+                   "concurrent_batches": [[i for i in g] for g in groups],
                    "panel": panel, "lookahead": la, "update_group": group,
                    "update_engine": "matrix cores" if engine == 1 else "vector units"},
         "lambda_solves_per_s": len(runs) * args.steps / dt,
@@ -438,6 +458,9 @@ def main():
                     help="single: the runs one after another (hk_smallest_eig); batched: all runs of a "
                          "step as one batch (hk_eig_batched, lockstep Secant); default batched when the "
                          "workload has several runs")
+    ap.add_argument("--split", type=int, default=1,
+                    help="batched driver: the runs as this many batches launched concurrently, one host thread "
+                         "and one stream each")
     ap.add_argument("--lookahead", type=int, default=-1, choices=[-1, 0, 1, 2],
                     help="with --panel: look-ahead mode 0 none, 1 second stream, 2 one launch per column "
                          "(-1: chosen by size)")

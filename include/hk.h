@@ -385,12 +385,15 @@ hk_status hk_eig_batched(const hk_instance* inst, int count, int digits, int pan
 /* Times one batched factorisation of the given batch for each panel width
    in {1, 2, 4, 8, 16} under look-ahead modes 0 and 1, and once under mode 2
    (width 1), then the update workgroup size (1, 2 or 4 items of 64 rows x
-   16 digits per workgroup) for the fastest; stores the choice in
-   *best_panel, *best_lookahead and *best_group (the last two may be NULL)
-   and appends it to the text cache file cache_path (NULL: no file) under
-   the batch-shape key (architecture, count, N bucket, K bucket).  Rows per
-   item (one wavefront) and digits per output block (16, the carry-plane
-   granularity of the layout) are fixed.  Synchronises s. */
+   16 digits per workgroup) for the fastest, then the update engine (the
+   vector units against the matrix cores, see hk_set_update_engine); stores
+   the choice in *best_panel, *best_lookahead and *best_group (the last two
+   may be NULL) and appends it, engine included, to the text cache file
+   cache_path (NULL: no file) under the batch-shape key (architecture,
+   count, N bucket, K bucket), from which hk_build_matrix, hk_eig_batched,
+   hk_batch_create and hk_eig_learned take it.  Rows per item and digits
+   per output block (16, the carry-plane granularity of the layout) are
+   fixed.  Synchronises s. */
 hk_status hk_autotune(const hk_instance* inst, int count, void* dev_ws, size_t ws_bytes,
                       hipStream_t s, const char* cache_path, int* best_panel, int* best_lookahead,
                       int* best_group);

@@ -358,6 +358,7 @@ hk_status hk_build_matrix(int N, hk_rational beta, int prec_bits, void* dev_ws, 
     if (sc.panel > 0) (*out)->panel = sc.panel;
     (*out)->lookahead = sc.lookahead;
     if (sc.ipw > 0) (*out)->B.ipw = sc.ipw;
+    if (sc.mma >= 0) (*out)->B.mma = sc.mma;
   }
   return st;
 }

@@ -262,6 +262,8 @@ static Schedule cached_schedule(const std::string& key) {
     sc.lookahead = la == std::string::npos ? -1 : atoi(line.c_str() + la + 4);
     const size_t ip = line.find(" ipw=", bar);
     sc.ipw = ip == std::string::npos ? 0 : atoi(line.c_str() + ip + 5);
+    const size_t mm = line.find(" mma=", bar);
+    sc.mma = mm == std::string::npos ? -1 : atoi(line.c_str() + mm + 5);
   }
   return sc;
 }
@@ -308,6 +310,7 @@ hk_status hk_eig_batched(const hk_instance* inst, int count, int digits, int pan
     bt.panel = panel > 0 ? panel : (sc.panel > 0 ? sc.panel : 4);
     bt.lookahead = sc.lookahead;
     if (sc.ipw > 0) bt.B.ipw = sc.ipw;
+    if (sc.mma >= 0) bt.B.mma = sc.mma;
     // the first instance's flags set the schedule of the whole batch
     const int fl = inst[0].method;
     if (fl & HK_FLAG_LOOKAHEAD_ON) bt.lookahead = 1;
@@ -487,14 +490,25 @@ hk_status hk_autotune(const hk_instance* inst, int count, void* dev_ws, size_t w
       if (ms < best_ms) { best_ms = ms; best_ipw = ipw; }
     }
   }
+  // the update engine: the vector units against the matrix cores (where
+  // those apply at this panel width)
+  int best_mma = bt.B.mma;
+  if (best_la != 2 && mma_width(bt.B, best) > 0) {
+    bt.B.mma = 0;
+    double ms = 0;
+    st = time_one(best, best_la, best_ipw, ms);
+    if (st != HK_OK) return st;
+    if (ms < best_ms) { best_ms = ms; best_mma = 0; }
+    bt.B.mma = 1;
+  }
   *best_panel = best;
   if (best_lookahead) *best_lookahead = best_la;
   if (best_group) *best_group = best_ipw;
   if (cache_path) {
     std::ofstream f(cache_path, std::ios::app);
     if (!f) return dfail_b(HK_EINVAL, "cannot write the tuning cache");
-    f << tune_key(inst, count) << " | panel=" << best << " la=" << best_la << " ipw=" << best_ipw << " ms=" << best_ms
-      << "\n";
+    f << tune_key(inst, count) << " | panel=" << best << " la=" << best_la << " ipw=" << best_ipw
+      << " mma=" << best_mma << " ms=" << best_ms << "\n";
   }
   return HK_OK;
 }
@@ -521,6 +535,7 @@ hk_status hk_batch_create(const hk_instance* inst, int count, void* dev_ws, size
   b->bt.panel = sc.panel > 0 ? sc.panel : 4;
   b->bt.lookahead = sc.lookahead;
   if (sc.ipw > 0) b->bt.B.ipw = sc.ipw;
+  if (sc.mma >= 0) b->bt.B.mma = sc.mma;
   *out = b;
   return HK_OK;
 }

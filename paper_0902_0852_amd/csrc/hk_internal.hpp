@@ -68,7 +68,7 @@ bool make_plan(int N, int64_t bnum, int64_t bden, int K, Plan& P, std::string& e
 int lookahead_mode(int setting, int maxN, int maxW);
 // panel width (0: none) and look-ahead (-1: none) from the tuning cache
 // named by HK_TUNE_CACHE for this batch shape
-struct Schedule { int panel = 0, lookahead = -1, ipw = 0; };
+struct Schedule { int panel = 0, lookahead = -1, ipw = 0, mma = -1; };
 Schedule tuned_schedule(const hk_instance* inst, int count);
 
 // an hk_mpf as an integer with K fractional bits (false if it has more)

@@ -182,6 +182,7 @@ hk_status hk_bracket_batched(const hk_instance* inst, int count, const char* con
     bt.panel = panel > 0 ? panel : (sc.panel > 0 ? sc.panel : 4);
     bt.lookahead = sc.lookahead;
     if (sc.ipw > 0) bt.B.ipw = sc.ipw;
+    if (sc.mma >= 0) bt.B.mma = sc.mma;
   }
   std::vector<int> act(count, 1);
   std::vector<BEval> elo, ehi;
