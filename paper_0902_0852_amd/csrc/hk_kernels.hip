@@ -702,7 +702,7 @@ __device__ __forceinline__ void mma_tile(v16i* D, const MmaCols& M, const GLOBAL
 // 32-row tile): its four wavefronts build C_k[c]'s byte planes of every panel
 // column k once (LDS), then share out the column's 32-digit output tiles.
 // Wm: the widest column of the launch; the LDS holds (k1 - k0) plane sets.
-constexpr int MMA_RUN = 16;   // consecutive tiles per XCD turn
+constexpr int MMA_RUN = 4;    // consecutive tiles per XCD turn (4, 16, 64, 256: 1712, 1732, 1829, 2174 ms per step)
 constexpr int MMA_SPLIT_ITEMS = 512;   // near launches up to this many items: k_update_mma_sk
 
 // Number of (32-row tile, column) pairs with rows in them of an instance of
@@ -714,17 +714,18 @@ __host__ __device__ inline int mma_tile_count(int N, int c_lo, int c_hi, int t32
 }
 
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_update_mma(const InstDesc* __restrict__ desc, int count, int pc, int b,
-                                                     int j, int rd, int Wm, int per_xcd) {
+                                                     int j, int rd, int Wm, int run) {
   extern __shared__ int64_t smem[];
+  // the next panel's columns are on the critical path (as in k_update_mma_w)
+  if (!update_is_bulk(j)) __builtin_amdgcn_s_setprio(3);
   const int lane = threadIdx.x & 63, w = uni(threadIdx.x >> 6), nw = blockDim.x >> 6;
   // Workgroups go round-robin to the chip's eight XCDs; each XCD takes runs
-  // of MMA_RUN consecutive pairs, enumerated tile-major (for tile index 0,
+  // of `run` consecutive pairs, enumerated tile-major (for tile index 0,
   // every column, then tile index 1 ...), so that the workgroups one XCD
   // runs together read the same rows of L from its own L2, while the runs
   // alternate between the XCDs to spread the work evenly
   const int q = (int)(blockIdx.x >> 3);
-  int it = ((q / MMA_RUN) * 8 + (int)(blockIdx.x & 7)) * MMA_RUN + q % MMA_RUN;
-  (void)per_xcd;
+  int it = ((q / run) * 8 + (int)(blockIdx.x & 7)) * run + q % run;
   int inst = -1, k0 = 0, k1 = 0, c_lo = 0, c_hi = 0;
   for (int i2 = 0; i2 < count; i2++) {
     int a0, a1, b0, b1;
@@ -2346,7 +2347,7 @@ hipError_t launch_update(const BatchView& B, int pc, int b, int j, int rd, hipSt
   const int ipw = B.ipw == 1 || B.ipw == 2 ? B.ipw : 4;
   const dim3 grid((unsigned)((items + ipw - 1) / ipw)), block(64 * ipw);
   const int Wm = mma_width(B, b);
-  if (Wm > 0 && update_is_bulk(j) && mma_lds(Wm, b) <= 65536) {
+  if (Wm > 0 && (update_is_bulk(j) || j == UPD_NEAR) && mma_lds(Wm, b) <= 65536) {
     int64_t tiles = 0;
     for (const Plan* p : B.plans) {
       int k0, k1, c_lo, c_hi;
@@ -2354,14 +2355,15 @@ hipError_t launch_update(const BatchView& B, int pc, int b, int j, int rd, hipSt
         for (int t = 0; 32 * t < p->N - c_lo; t++) tiles += mma_tile_count(p->N, c_lo, c_hi, t);
     }
     if (tiles <= 0) return mark_empty(t0, t1, s);
-    const int per = (int)((tiles + 8 * MMA_RUN - 1) / (8 * MMA_RUN)) * MMA_RUN;
+    const int run_len = MMA_RUN;
+    const int per = (int)((tiles + 8 * run_len - 1) / (8 * run_len)) * run_len;
     const size_t shm = mma_lds(Wm, b);
     if (t0 || t1)
       hipExtLaunchKernelGGL(k_update_mma, dim3(8u * per), dim3(256), shm, s, t0, t1, 0, B.ddesc,
-                            (int)B.plans.size(), pc, b, j, rd, Wm, per);
+                            (int)B.plans.size(), pc, b, j, rd, Wm, run_len);
     else
       hipLaunchKernelGGL(k_update_mma, dim3(8u * per), dim3(256), shm, s, B.ddesc, (int)B.plans.size(), pc, b, j,
-                         rd, Wm, per);
+                         rd, Wm, run_len);
     return hipGetLastError();
   }
   // near launches small enough to leave most of the chip idle split their
