@@ -528,9 +528,12 @@ __device__ __forceinline__ void mma_accum(v16i* D, const MmaItem& T, int kf, int
 #pragma unroll
     for (int v = 0; v < 16; v++) D[s][v] = 0;
   if (k0 + kf >= k1) return;
-  // the digit counts of the next panel column are requested one column ahead
+  // the digit counts of the next panel column are requested one column
+  // ahead, and so are its first 512 digits of C (cvn, for column kpref)
   int nCn = sload(I.nC + tri_index(N, k0 + kf, c));
   int nLn = active ? gp(I.nL)[tri_index(N, k0 + kf, rr)] : 0;
+  int32_t cvn[8];
+  int kpref = -1;
   for (int k = k0 + kf; k < k1; k += ks) {
     const ColInfo kk = sload(I.cols + k);
     const int nC = min(nCn, kk.CW - WB);
@@ -578,8 +581,13 @@ __device__ __forceinline__ void mma_accum(v16i* D, const MmaItem& T, int kf, int
       const GLOBAL int32_t* Cg = gp(I.C + kk.coff + (int64_t)(c - k) * kk.CW);
       for (int x0 = 0; x0 < nC; x0 += 512) {
         int32_t cv[8];
+        if (x0 == 0 && kpref == k) {
 #pragma unroll
-        for (int u = 0; u < 8; u++) cv[u] = Cg[min(x0 + lane + 64 * u, nC - 1)];
+          for (int u = 0; u < 8; u++) cv[u] = cvn[u];
+        } else {
+#pragma unroll
+          for (int u = 0; u < 8; u++) cv[u] = Cg[min(x0 + lane + 64 * u, nC - 1)];
+        }
 #pragma unroll
         for (int u = 0; u < 8; u++) {
           const int x = x0 + lane + 64 * u;
@@ -594,6 +602,17 @@ __device__ __forceinline__ void mma_accum(v16i* D, const MmaItem& T, int kf, int
           }
         }
       }
+    }
+    // the next panel column's first digits of C, in flight during this
+    // column's products
+    if (k + ks < k1) {
+      const int kn = k + ks;
+      const ColInfo kc = sload(I.cols + kn);
+      const int nCx = min(nCn, kc.CW - WB);
+      const GLOBAL int32_t* Cn = gp(I.C + kc.coff + (int64_t)(c - kn) * kc.CW);
+#pragma unroll
+      for (int u = 0; u < 8; u++) cvn[u] = Cn[min(lane + 64 * u, max(nCx - 1, 0))];
+      kpref = kn;
     }
     ldA(A0, g0);
     for (int g = g0; g <= g1; g += 3) {
