@@ -292,6 +292,15 @@ hipError_t enqueue_factor(const BatchView& B, int b, int mode, hipStream_t s, hi
   return e;
 }
 
+int host_threads() {
+  static const int n = [] {
+    const char* v = getenv("HK_HOST_THREADS");
+    if (v && atoi(v) > 0) return std::min(atoi(v), 64);
+    return std::max(1, std::min(16, (int)std::thread::hardware_concurrency()));
+  }();
+  return n;
+}
+
 MP digits_to_mp(const int32_t* d, int n, int64_t stride) {
   // positive and negative digit parts packed separately, then subtracted
   std::vector<uint32_t> pw((size_t)(((int64_t)n * DB) / 32 + 3), 0u), nw(pw.size(), 0u);

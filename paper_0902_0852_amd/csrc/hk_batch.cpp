@@ -273,6 +273,7 @@ static Schedule cached_schedule(const std::string& key) {
 struct SecantRun;
 SecantRun* secant_new(int N, int K, int h, int tol, int max_eval);
 void secant_delete(SecantRun* r);
+void secant_threads(SecantRun* r, int threads);
 bool secant_next(SecantRun* r, MP& x, int& inertia);
 void secant_feed(SecantRun* r, hk_status st, int nneg, int first_bad, const std::vector<MP>& piv);
 bool secant_done(SecantRun* r, MP& lam, hk_status& st, std::string& err);
@@ -333,12 +334,17 @@ hk_status hk_eig_batched(const hk_instance* inst, int count, int digits, int pan
   std::vector<BEval> ev;
   // the paper's Secant iteration, every Secant instance in lockstep
   st = HK_OK;
+  // each round's Secant steps of the instances run side by side on the host,
+  // the host threads shared out among them
+  int nsec = 0;
+  for (int i = 0; i < count; i++) nsec += sm[i] ? 1 : 0;
+  const int ith = std::min(nsec, host_threads());
+  for (int i = 0; i < count; i++)
+    if (sm[i]) secant_threads(sm[i], host_threads() / std::max(1, ith));
   for (int round = 0; round < 400 && st == HK_OK; round++) {
+    parallel_for(count, ith, [&](int i) { act[i] = sm[i] && secant_next(sm[i], x[i], inertia[i]) ? 1 : 0; });
     bool any = false;
-    for (int i = 0; i < count; i++) {
-      act[i] = sm[i] && secant_next(sm[i], x[i], inertia[i]) ? 1 : 0;
-      any |= act[i] != 0;
-    }
+    for (int i = 0; i < count; i++) any |= act[i] != 0;
     if (!any) break;
     st = factor_batch(bt, x, act, s, ev, true);
     for (int i = 0; i < count && st == HK_OK; i++) {

@@ -67,13 +67,17 @@ hk_status pivots_host(hk_matrix m, hipStream_t s, std::vector<MP>& out) {
 // t_k = 2^F + e_k, e_k = floor(2^F (dn_k - dold_k) / dold_k), and
 // floor(R t_k / 2^F) = R + floor(R e_k / 2^F): the same values, but the
 // pivots of nearby shifts differ only in their low digits, so e_k is short
-// and so are its division and product.
-MP pivot_ratio(const std::vector<MP>& dn, const std::vector<MP>& dold, int64_t F) {
+// and so are its division and product.  The divisions are independent and
+// run on `threads` host threads; the product runs in k order.
+MP pivot_ratio(const std::vector<MP>& dn, const std::vector<MP>& dold, int64_t F, int threads) {
+  const int n = (int)dn.size();
+  std::vector<MP> e(n);
+  // a thread per 32 pivots at most: below that, starting it costs more
+  parallel_for(n, std::min(threads, n / 32),
+               [&](int k) { e[k] = floor_div(shl(sub(dn[k], dold[k]), F), dold[k]); });
   MP R = one_shl(F);
-  for (size_t k = 0; k < dn.size(); k++) {
-    const MP e = floor_div(shl(sub(dn[k], dold[k]), F), dold[k]);
-    if (!e.is_zero()) R = add(R, floor_shr(mul(R, e), F));
-  }
+  for (int k = 0; k < n; k++)
+    if (!e[k].is_zero()) R = add(R, floor_shr(mul(R, e[k]), F));
   return R;
 }
 
@@ -167,6 +171,7 @@ static Eval evaluate(DriverCtx& cx, const MP& x, int inertia_mode) {
 struct SecantMachine {
   enum Phase { START0, START1, ITER, BRACKET, DONE, FAILED } phase = START0;
   int K = 0, tol = 45, max_eval = 200, nevals = 0;
+  int threads = 1;  // host threads of the pivot ratio
   int64_t F = 0;
   MP ONE, lam;
   hk_status status = HK_OK;
@@ -184,6 +189,7 @@ struct SecantMachine {
 
   void init(int N, int K_, int h, int tol_, int max_eval_) {
     K = K_; tol = tol_; max_eval = max_eval_;
+    threads = host_threads();
     int nb = 0;
     for (int n = N; n; n >>= 1) nb++;
     F = h + 64 + nb;
@@ -207,7 +213,7 @@ struct SecantMachine {
     if (phase == ITER) {
       const MP& x0 = xs[xs.size() - 2];
       const MP& x1 = xs.back();
-      MP R = pivot_ratio(piv.back(), piv[piv.size() - 2], F);
+      MP R = pivot_ratio(piv.back(), piv[piv.size() - 2], F, threads);
       if (cmp(R, ONE) >= 0) { fail(HK_EPRECISION, "secant ratio >= 1: precision exhausted"); return false; }
       MP x2 = secant_point(x0, x1, R);
       MP step = sub(x2, x1);
@@ -230,7 +236,7 @@ struct SecantMachine {
     MP c;
     bool have_c = false;
     if (!db.empty()) {
-      MP Rb = pivot_ratio(db, da, F);
+      MP Rb = pivot_ratio(db, da, F, threads);
       if (scale_b <= scale_a) Rb = shl(floor_shr(Rb, scale_b), scale_a);
       else Rb = floor_shr(Rb, scale_b - scale_a);
       if (cmp(Rb, ONE) != 0) { c = secant_point(a, b, Rb); have_c = true; }
@@ -394,6 +400,7 @@ SecantRun* secant_new(int N, int K, int h, int tol, int max_eval) {
   return r;
 }
 void secant_delete(SecantRun* r) { delete r; }
+void secant_threads(SecantRun* r, int threads) { r->m.threads = std::max(1, threads); }
 bool secant_next(SecantRun* r, MP& x, int& inertia) { return r->m.next(x, inertia); }
 void secant_feed(SecantRun* r, hk_status st, int nneg, int first_bad, const std::vector<MP>& piv) {
   Eval ev;
@@ -525,8 +532,14 @@ hk_status inverse_iterate(hk_matrix m, hipStream_t s, const MP& sigma, int tol, 
     st = vec_to_host(m, m->D.dv2, s, y);
     t_solve += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (st != HK_OK) return st;
+    // v.y and v.v in exact integers: partial sums on host threads, then added
+    const int nt = std::max(1, std::min(host_threads(), N / 32));
+    std::vector<MP> pvy(nt), pvv(nt);
+    parallel_for(nt, nt, [&](int t) {
+      for (int i = t; i < N; i += nt) { pvy[t] = add(pvy[t], mul(v[i], y[i])); pvv[t] = add(pvv[t], mul(v[i], v[i])); }
+    });
     MP vy, vv;
-    for (int i = 0; i < N; i++) { vy = add(vy, mul(v[i], y[i])); vv = add(vv, mul(v[i], v[i])); }
+    for (int t = 0; t < nt; t++) { vy = add(vy, pvy[t]); vv = add(vv, pvv[t]); }
     if (vy.sign() <= 0) return dfail(HK_EPRECISION, "non-positive Rayleigh quotient");
     // lambda 2^F = sigma 2^(F-K) + vv 2^(g+F) / vy
     MP lamF = add(shl(sigma, F - K), floor_div(shl(vv, g + F), vy));

@@ -3,8 +3,10 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/hk.h"
@@ -77,6 +79,27 @@ bool shift_fixed(const hk_mpf& x, int K, MP& out);
 // conversions between host integers and device digits
 void mp_to_digits(const MP& v, int32_t* out, int n);          // balanced, zero padded
 MP digits_to_mp(const int32_t* d, int n, int64_t stride = 1);
+
+// host threads for the drivers' multiprecision arithmetic: HK_HOST_THREADS
+// if set, else the hardware's, at most 16
+int host_threads();
+
+// f(i) for every i in [0, n) on up to `threads` host threads, i dealt out
+// round-robin (costs that fall or rise with i stay balanced)
+template <class Fn>
+void parallel_for(int n, int threads, Fn&& f) {
+  threads = std::max(1, std::min(threads, n));
+  if (threads == 1) {
+    for (int i = 0; i < n; i++) f(i);
+    return;
+  }
+  std::vector<std::thread> th;
+  th.reserve(threads - 1);
+  for (int t = 1; t < threads; t++)
+    th.emplace_back([&, t] { for (int i = t; i < n; i += threads) f(i); });
+  for (int i = 0; i < n; i += threads) f(i);
+  for (auto& x : th) x.join();
+}
 
 __host__ __device__ inline int64_t tri_index(int N, int k, int r) {
   return (int64_t)k * N - (int64_t)k * (k - 1) / 2 + (r - k);
