@@ -221,11 +221,17 @@ hk_status factor_batch(Batch& bt, const std::vector<MP>& x, const std::vector<in
     ev.nneg = f[2];
     ev.st = f[0] ? HK_EPRECISION : ((ev.first_bad >= 0 && ev.first_bad < N - 1) ? HK_ENOTSPD : HK_OK);
     bt.mats[i]->factored = ev.st == HK_OK;
-    if (want_pivots && ev.st == HK_OK) {
-      ev.piv.resize(N);
-      for (int k = 0; k < N; k++)
-        ev.piv[k] = digits_to_mp(pv.data() + ((size_t)i * bt.maxN + k) * bt.ld, bt.ld, 1);
-    }
+    if (want_pivots && ev.st == HK_OK) ev.piv.resize(N);
+  }
+  if (want_pivots) {
+    // pivots to host integers, every instance's at once on the host threads
+    std::vector<std::pair<int, int>> jobs;
+    for (int i = 0; i < bt.count; i++)
+      for (int k = 0; k < (int)out[i].piv.size(); k++) jobs.emplace_back(i, k);
+    parallel_for((int)jobs.size(), std::min(host_threads(), (int)jobs.size() / 64), [&](int t) {
+      const int i = jobs[t].first, k = jobs[t].second;
+      out[i].piv[k] = digits_to_mp(pv.data() + ((size_t)i * bt.maxN + k) * bt.ld, bt.ld, 1);
+    });
   }
   return HK_OK;
 }
@@ -275,7 +281,7 @@ SecantRun* secant_new(int N, int K, int h, int tol, int max_eval);
 void secant_delete(SecantRun* r);
 void secant_threads(SecantRun* r, int threads);
 bool secant_next(SecantRun* r, MP& x, int& inertia);
-void secant_feed(SecantRun* r, hk_status st, int nneg, int first_bad, const std::vector<MP>& piv);
+void secant_feed(SecantRun* r, hk_status st, int nneg, int first_bad, std::vector<MP>&& piv);
 bool secant_done(SecantRun* r, MP& lam, hk_status& st, std::string& err);
 
 size_t batch_bytes(const hk_instance* inst, int count) {
@@ -350,7 +356,7 @@ hk_status hk_eig_batched(const hk_instance* inst, int count, int digits, int pan
     for (int i = 0; i < count && st == HK_OK; i++) {
       if (!act[i]) continue;
       nfact[i]++;
-      secant_feed(sm[i], ev[i].st, ev[i].nneg, ev[i].first_bad, ev[i].piv);
+      secant_feed(sm[i], ev[i].st, ev[i].nneg, ev[i].first_bad, std::move(ev[i].piv));
     }
   }
   for (int i = 0; i < count && st == HK_OK; i++) {

@@ -247,7 +247,7 @@ struct SecantMachine {
     inertia = 1;
     return true;
   }
-  void feed(const Eval& ev) {
+  void feed(Eval&& ev) {
     nevals++;
     const bool left = ev.st == HK_OK && ev.nneg == 0 && ev.first_bad < 0;
     if (phase == START0 || phase == START1) {
@@ -256,13 +256,13 @@ struct SecantMachine {
         else fail(ev.st, "factorisation failed");
         return;
       }
-      piv.push_back(ev.piv);
+      piv.push_back(std::move(ev.piv));
       phase = phase == START0 ? START1 : ITER;
       return;
     }
     if (ev.st != HK_OK && ev.st != HK_ENOTSPD) { fail(ev.st, "factorisation failed"); return; }
     if (phase == ITER) {
-      if (left) { xs.push_back(pending); piv.push_back(ev.piv); return; }
+      if (left) { xs.push_back(pending); piv.push_back(std::move(ev.piv)); return; }
       a = xs.back(); b = pending;
       da = piv.back();
       db = ev.st == HK_OK ? ev.piv : std::vector<MP>();
@@ -402,10 +402,10 @@ SecantRun* secant_new(int N, int K, int h, int tol, int max_eval) {
 void secant_delete(SecantRun* r) { delete r; }
 void secant_threads(SecantRun* r, int threads) { r->m.threads = std::max(1, threads); }
 bool secant_next(SecantRun* r, MP& x, int& inertia) { return r->m.next(x, inertia); }
-void secant_feed(SecantRun* r, hk_status st, int nneg, int first_bad, const std::vector<MP>& piv) {
+void secant_feed(SecantRun* r, hk_status st, int nneg, int first_bad, std::vector<MP>&& piv) {
   Eval ev;
-  ev.st = st; ev.nneg = nneg; ev.first_bad = first_bad; ev.piv = piv;
-  r->m.feed(ev);
+  ev.st = st; ev.nneg = nneg; ev.first_bad = first_bad; ev.piv = std::move(piv);
+  r->m.feed(std::move(ev));
 }
 bool secant_done(SecantRun* r, MP& lam, hk_status& st, std::string& err) {
   lam = r->m.lam;

@@ -94,22 +94,40 @@ inline MP add(const MP& a, const MP& b) {
 inline MP neg(MP a) { if (!a.d.empty()) a.neg = !a.neg; return a; }
 inline MP sub(const MP& a, const MP& b) { return add(a, neg(b)); }
 
+// 32-bit digit vectors as 64-bit limbs and back (leading zeros dropped)
+inline std::vector<uint64_t> limbs64(const std::vector<uint32_t>& d) {
+  std::vector<uint64_t> w((d.size() + 1) / 2, 0);
+  for (size_t i = 0; i < d.size(); i++) w[i >> 1] |= (uint64_t)d[i] << (32 * (i & 1));
+  while (!w.empty() && w.back() == 0) w.pop_back();
+  return w;
+}
+inline std::vector<uint32_t> digits32(const uint64_t* w, size_t n) {
+  std::vector<uint32_t> d(2 * n);
+  for (size_t i = 0; i < n; i++) { d[2 * i] = (uint32_t)w[i]; d[2 * i + 1] = (uint32_t)(w[i] >> 32); }
+  while (!d.empty() && d.back() == 0) d.pop_back();
+  return d;
+}
+
+// schoolbook product, 64-bit limbs with 128-bit partial products
 inline MP mul(const MP& a, const MP& b) {
   if (a.d.empty() || b.d.empty()) return MP();
-  MP r;
-  r.d.assign(a.d.size() + b.d.size(), 0u);
-  for (size_t i = 0; i < a.d.size(); i++) {
+  typedef unsigned __int128 u128;
+  const std::vector<uint64_t> A = limbs64(a.d), B = limbs64(b.d);
+  std::vector<uint64_t> R(A.size() + B.size(), 0);
+  for (size_t i = 0; i < A.size(); i++) {
     uint64_t c = 0;
-    const uint64_t ai = a.d[i];
-    for (size_t j = 0; j < b.d.size(); j++) {
-      uint64_t t = ai * b.d[j] + r.d[i + j] + c;
-      r.d[i + j] = (uint32_t)t;
-      c = t >> 32;
+    const uint64_t ai = A[i];
+    for (size_t j = 0; j < B.size(); j++) {
+      // at most (2^64 - 1)^2 + 2 (2^64 - 1) = 2^128 - 1
+      const u128 t = (u128)ai * B[j] + R[i + j] + c;
+      R[i + j] = (uint64_t)t;
+      c = (uint64_t)(t >> 64);
     }
-    r.d[i + b.d.size()] = (uint32_t)c;
+    R[i + B.size()] = c;
   }
-  r.neg = a.neg != b.neg;
-  r.trim();
+  MP r;
+  r.d = digits32(R.data(), R.size());
+  r.neg = a.neg != b.neg && !r.d.empty();
   return r;
 }
 inline MP mul_small(const MP& a, uint32_t m) {
@@ -192,9 +210,10 @@ inline MP inc_mag(MP a) {
 
 // Long division of magnitudes: returns q = floor(|a|/|b|), r = |a| - q|b|.
 // Knuth's Algorithm D (The Art of Computer Programming, vol. 2, 4.3.1) in
-// base 2^32 with a normalised divisor: the trial digit comes from the top
+// base 2^64 with a normalised divisor: the trial digit comes from the top
 // two remainder digits and is corrected with the third, then an add-back.
 inline void divmod_mag(const MP& a, const MP& b, MP& q, MP& r) {
+  typedef unsigned __int128 u128;
   q = MP(); r = MP();
   if (cmp_mag(a, b) < 0) { r = a; r.neg = false; return; }
   if (b.d.size() == 1) {
@@ -204,51 +223,64 @@ inline void divmod_mag(const MP& a, const MP& b, MP& q, MP& r) {
     r = MP::from_u64(rr);
     return;
   }
-  int sh = __builtin_clz(b.d.back());
-  MP bn = shl(b, sh); bn.neg = false;
-  MP an = shl(a, sh); an.neg = false;
-  size_t n = bn.d.size();
-  std::vector<uint32_t> rem(an.d.begin(), an.d.end());
-  rem.push_back(0);
-  size_t m = rem.size() - n;  // quotient digits
-  q.d.assign(m, 0u);
-  const uint64_t top = bn.d[n - 1], nxt = bn.d[n - 2];
-  for (size_t jj = m; jj-- > 0;) {
-    uint64_t hi2 = ((uint64_t)rem[jj + n] << 32) | rem[jj + n - 1];
-    uint64_t qh = hi2 / top, rh = hi2 % top;
-    while (qh > 0xffffffffULL || qh * nxt > ((rh << 32) | rem[jj + n - 2])) {
+  const std::vector<uint64_t> A = limbs64(a.d), B = limbs64(b.d);
+  const size_t n = B.size();
+  if (n == 1) {
+    std::vector<uint64_t> Q(A.size());
+    uint64_t rem = 0;
+    for (size_t i = A.size(); i-- > 0;) {
+      const u128 cur = ((u128)rem << 64) | A[i];
+      Q[i] = (uint64_t)(cur / B[0]);
+      rem = (uint64_t)(cur % B[0]);
+    }
+    q.d = digits32(Q.data(), Q.size());
+    r.d = digits32(&rem, 1);
+    return;
+  }
+  const int sh = __builtin_clzll(B[n - 1]);
+  std::vector<uint64_t> Bn(n), R(A.size() + 1);
+  for (size_t i = 0; i < n; i++) Bn[i] = (B[i] << sh) | (sh && i ? B[i - 1] >> (64 - sh) : 0);
+  R[A.size()] = sh ? A.back() >> (64 - sh) : 0;
+  for (size_t i = 0; i < A.size(); i++) R[i] = (A[i] << sh) | (sh && i ? A[i - 1] >> (64 - sh) : 0);
+  const size_t m = R.size() - n;  // quotient digits
+  std::vector<uint64_t> Q(m, 0);
+  const uint64_t top = Bn[n - 1], nxt = Bn[n - 2];
+  for (size_t j = m; j-- > 0;) {
+    const u128 num = ((u128)R[j + n] << 64) | R[j + n - 1];
+    u128 qh = num / top, rh = num % top;
+    while ((qh >> 64) != 0 || qh * nxt > ((rh << 64) | R[j + n - 2])) {
       qh--; rh += top;
-      if (rh > 0xffffffffULL) break;
+      if ((rh >> 64) != 0) break;
     }
-    // rem[jj .. jj+n] -= qh * bn
-    uint64_t carry = 0;
-    int64_t borrow = 0;
+    // R[j .. j+n] -= qd * Bn
+    uint64_t qd = (uint64_t)qh, carry = 0, borrow = 0;
     for (size_t i = 0; i < n; i++) {
-      uint64_t p = qh * bn.d[i] + carry;
-      carry = p >> 32;
-      int64_t t = (int64_t)rem[jj + i] - (int64_t)(uint32_t)p - borrow;
-      borrow = t < 0;
-      rem[jj + i] = (uint32_t)(t & 0xffffffffLL);
+      const u128 p = (u128)qd * Bn[i] + carry;
+      carry = (uint64_t)(p >> 64);
+      const uint64_t pl = (uint64_t)p, x = R[j + i];
+      const uint64_t t = x - pl;
+      const uint64_t t2 = t - borrow;
+      borrow = (uint64_t)(x < pl) + (uint64_t)(t < borrow);
+      R[j + i] = t2;
     }
-    int64_t t = (int64_t)rem[jj + n] - (int64_t)carry - borrow;
-    rem[jj + n] = (uint32_t)(t & 0xffffffffLL);
-    if (t < 0) {
-      qh--;
+    const uint64_t x = R[j + n];
+    const bool below = x < carry || x - carry < borrow;
+    R[j + n] = x - carry - borrow;
+    if (below) {
+      qd--;
       uint64_t c = 0;
       for (size_t i = 0; i < n; i++) {
-        uint64_t s2 = (uint64_t)rem[jj + i] + bn.d[i] + c;
-        rem[jj + i] = (uint32_t)s2;
-        c = s2 >> 32;
+        const u128 s2 = (u128)R[j + i] + Bn[i] + c;
+        R[j + i] = (uint64_t)s2;
+        c = (uint64_t)(s2 >> 64);
       }
-      rem[jj + n] += (uint32_t)c;
+      R[j + n] += c;
     }
-    q.d[jj] = (uint32_t)qh;
+    Q[j] = qd;
   }
-  q.trim();
-  MP rr;
-  rr.d.assign(rem.begin(), rem.begin() + n);
-  rr.trim();
-  r = shr_mag(rr, sh);
+  q.d = digits32(Q.data(), Q.size());
+  for (size_t i = 0; i < n; i++) R[i] = (R[i] >> sh) | (sh && i + 1 < n ? R[i + 1] << (64 - sh) : 0);
+  r.d = digits32(R.data(), n);
 }
 inline MP floor_div(const MP& a, const MP& b) {  // floor(a/b), b > 0
   MP q, r;
