@@ -196,7 +196,9 @@ hk_status hk_solve(hk_matrix factored, const void* dev_rhs, void* dev_x, hipStre
    one factorisation at shift_hint or 0; HK_SECANT: the paper's Secant
    iteration), then the inertia bracket at `digits` significant digits.
    lambda_1 is written to out_decimal (scientific notation, `digits`
-   digits).  rep may be NULL. */
+   digits).  rep may be NULL.  The drivers' host arithmetic (the Secant's
+   pivot ratio, the inverse iteration's dot products) runs on up to 16 host
+   threads; the environment variable HK_HOST_THREADS sets the number. */
 hk_status hk_smallest_eig(int N, hk_rational beta, int prec_bits, int method, int digits,
                           const hk_mpf* shift_hint, void* dev_ws, size_t ws_bytes,
                           hipStream_t s, char* out_decimal, size_t out_len, hk_report* rep);
