@@ -1638,6 +1638,8 @@ __device__ __forceinline__ FinOut finalize_pre(int W, int h, CT Cr, ST Sr, int c
     return wave_finalize_reg<false, 2>(W, h, Cr, Sr, cap, flags, dg, ob, cb, Psub, Sl);
   if (W <= 64 * 8 && nout <= 64 * 8)
     return wave_finalize_reg<false, 8>(W, h, Cr, Sr, cap, flags, dg, ob, cb, Psub, Sl);
+  if (W <= 64 * 16 && nout <= 64 * 16)
+    return wave_finalize_reg<false, 16>(W, h, Cr, Sr, cap, flags, dg, ob, cb, Psub, Sl);
   return wave_finalize<false, FIN_FB, true>(nullptr, 0, W, nullptr, 0, h, Cr, Sr, cap, flags, dg, ob, ca, cb,
                                             Psub, Sl);
 }
@@ -1675,7 +1677,7 @@ __device__ __forceinline__ void renorm_pb(int64_t* acc) {
 // entries.  A product wider than W digits sets bit 1 of flags[0], like an
 // update that overflows its entry.
 template <int PB, bool BLK>
-__device__ void near_product(const int32_t* Lr, int nL, const int32_t* Cp, int nC, int W, int64_t* P,
+__device__ __forceinline__ void near_product(const int32_t* Lr, int nL, const int32_t* Cp, int nC, int W, int64_t* P,
                              int32_t* flags) {
   const int lane = threadIdx.x & 63;
   if (lane == 0 && nL > 0 && nC > 0 && nL + nC - 1 > W) atomicOr(&flags[0], 1);
