@@ -1409,7 +1409,7 @@ __device__ __forceinline__ int divide_entry(int64_t* smem, const uint32_t* Sr, i
   // the divisor digits with zeros around them: DPAD below, up to the
   // register groups' reach above, so that every register of the divisor
   // below is one unconditional LDS read
-  static_assert(DNIR >= 1 && DNIR <= 4, "divide_shm sizes the divisor padding for at most 4 groups");
+  static_assert(DNIR >= 1 && DNIR <= 8, "divide_shm sizes the divisor padding for at most 8 groups");
   constexpr int DPAD = 16, DHI = 64 * DNIR + 16;
   int64_t* dd = rem + (nu + 3) + DPAD;       // dd[-DPAD .. nd + DHI)
   int64_t* qd = dd + nd + DHI;               // nu - nd + 2
@@ -1493,7 +1493,10 @@ __device__ __forceinline__ int divide_entry(int64_t* smem, const uint32_t* Sr, i
     // upward; groups beyond them take their divisor digits from LDS.
     const int b = j0 - DQ + 1;
     int64_t prev = 0, htop = 0;
+    // (as many register groups as the divisor has, in steps of powers of two)
     if (NI <= 1) bulk_groups<1>(rem, b, nbulk, q, DDL, top_group, prev, htop);
+    else if (DNIR > 2 && NI <= 2) bulk_groups<(DNIR > 2 ? 2 : DNIR)>(rem, b, nbulk, q, DDL, top_group, prev, htop);
+    else if (DNIR > 4 && NI <= 4) bulk_groups<(DNIR > 4 ? 4 : DNIR)>(rem, b, nbulk, q, DDL, top_group, prev, htop);
     else bulk_groups<DNIR>(rem, b, nbulk, q, DDL, top_group, prev, htop);
     for (int i = DNIR; i < NI; i++) {
       // (dd[nd] is zero, so the divisor digit index clamps to nd)
@@ -1916,7 +1919,7 @@ k_column(const InstDesc* __restrict__ desc, int count, int c, int n_near, int fi
 // Finalisation and division alone (the update came from k_update launches).
 __global__ void __launch_bounds__(128) k_fdiv(const InstDesc* __restrict__ desc, int count, int c, int rd,
                                               int n_near, int fin_bytes, int piv_bytes) {
-  column_step<4>(desc, count, c, n_near, rd, 0, fin_bytes, piv_bytes);
+  column_step<8>(desc, count, c, n_near, rd, 0, fin_bytes, piv_bytes);
 }
 
 // v_i = RNE(y_i 2^K / m) with the common divisor m (standard digits of m 2^sh
@@ -2422,11 +2425,11 @@ static size_t fin_shm(int W, int FB = WB) {
   return sizeof(int32_t) * 2 * (size_t)(W + 48) + sizeof(int64_t) * 2 * (size_t)(W / FB + 8);
 }
 // LDS of divide_entry: remainder DOFF + nu + 3, divisor nd with 16 zeros
-// below and 64 DNIR + 16 above (DNIR <= 4), quotient nu - nd + 2
+// below and 64 DNIR + 16 above (DNIR <= 8), quotient nu - nd + 2
 static size_t divide_shm(int h, int num_cap, int den_cap) {
   const int Sq = (h + 28) / DB + 1;
   const int nu_max = Sq + num_cap + 1;
-  return sizeof(int64_t) * (size_t)((DOFF + nu_max + 3) + (16 + den_cap + 64 * 4 + 16) + (nu_max + 3));
+  return sizeof(int64_t) * (size_t)((DOFF + nu_max + 3) + (16 + den_cap + 64 * 8 + 16) + (nu_max + 3));
 }
 // LDS of one row workgroup of the column launches for column c: the live
 // pivot region, then the larger of the finalisation phase (pivot scratch and
