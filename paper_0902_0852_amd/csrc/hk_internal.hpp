@@ -85,7 +85,8 @@ MP digits_to_mp(const int32_t* d, int n, int64_t stride = 1);
 int host_threads();
 
 // f(i) for every i in [0, n) on up to `threads` host threads, i dealt out
-// round-robin (costs that fall or rise with i stay balanced)
+// round-robin (costs that fall or rise with i stay balanced).  A thread the
+// system will not start leaves its share to the calling thread.
 template <class Fn>
 void parallel_for(int n, int threads, Fn&& f) {
   threads = std::max(1, std::min(threads, n));
@@ -95,9 +96,17 @@ void parallel_for(int n, int threads, Fn&& f) {
   }
   std::vector<std::thread> th;
   th.reserve(threads - 1);
-  for (int t = 1; t < threads; t++)
-    th.emplace_back([&, t] { for (int i = t; i < n; i += threads) f(i); });
-  for (int i = 0; i < n; i += threads) f(i);
+  int started = 1;
+  for (int t = 1; t < threads; t++, started++) {
+    try {
+      th.emplace_back([&, t] { for (int i = t; i < n; i += threads) f(i); });
+    } catch (...) {
+      break;
+    }
+  }
+  for (int t = 0; t < threads; t++)
+    if (t == 0 || t >= started)
+      for (int i = t; i < n; i += threads) f(i);
   for (auto& x : th) x.join();
 }
 
