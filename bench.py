@@ -346,7 +346,7 @@ def plain_batched(args, cfg, hk, torch):
     bflags = la_flag | hk.HK_FLAG_GROUP(group)
     log("batch of %d runs: panel width %d, look-ahead %d, %d update items per workgroup (%s)"
         % (len(runs), panel, la, group, "given" if args.panel > 0 else "tuned"))
-    wsg = [torch.empty(hk.batch_workspace_bytes([runs[i] for i in g]), dtype=torch.uint8, device="cuda")
+    wsg = [torch.empty(hk.batch_workspace_bytes([runs[i] for i in g], paired=not args.unpaired), dtype=torch.uint8, device="cuda")
            for g in groups]
     streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in groups[1:]]
     from concurrent.futures import ThreadPoolExecutor
@@ -417,6 +417,7 @@ def plain_batched(args, cfg, hk, torch):
                    "N": [N for N, _, _ in runs], "beta": ["%d/%d" % b for _, b, _ in runs],
                    "prec_bits": [K for _, _, K in runs], "method": "secant", "driver": "batched",
                    "concurrent_batches": [[i for i in g] for g in groups],
+                   "paired_factorisations": not args.unpaired,
                    "panel": panel, "lookahead": la, "update_group": group,
                    "update_engine": "matrix cores" if engine == 1 else "vector units"},
         "lambda_solves_per_s": len(runs) * args.steps / dt,
@@ -461,6 +462,9 @@ def main():
     ap.add_argument("--split", type=int, default=1,
                     help="batched driver: the runs as this many batches launched concurrently, one host thread "
                          "and one stream each")
+    ap.add_argument("--unpaired", action="store_true",
+                    help="batched driver: the batch workspace without the second copy of every run, so "
+                         "the Secant's start points and the bracket's ends are factored one at a time")
     ap.add_argument("--lookahead", type=int, default=-1, choices=[-1, 0, 1, 2],
                     help="with --panel: look-ahead mode 0 none, 1 second stream, 2 one launch per column "
                          "(-1: chosen by size)")

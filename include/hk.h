@@ -367,6 +367,11 @@ typedef struct {
 /* Device bytes for a batch (one buffer for all instances). 0 if invalid. */
 size_t hk_batch_workspace_bytes(const hk_instance* inst, int count);
 
+/* Device bytes with which hk_eig_batched pairs factorisations (about twice
+   hk_batch_workspace_bytes: a second copy of every instance's workspace).
+   0 if invalid. */
+size_t hk_batch_workspace_bytes_paired(const hk_instance* inst, int count);
+
 /* lambda_1 of every instance by its method: HK_SECANT instances run the
    paper's Secant iteration in lockstep (one batched factorisation per
    step); HK_INVERSE instances are factored once at their shift hint (halved
@@ -378,7 +383,12 @@ size_t hk_batch_workspace_bytes(const hk_instance* inst, int count);
    hk_smallest_eig flags HK_FLAG_LOOKAHEAD_*, HK_FLAG_GROUP(g),
    HK_FLAG_VECTOR_UPDATE and HK_FLAG_TIME_UPDATES (every factorisation then
    launched one by one with its update launches timed, in rep); they apply to
-   the whole batch.  out[count] receives the per-instance
+   the whole batch.  With ws_bytes of at least
+   hk_batch_workspace_bytes_paired(inst, count), the two start points of
+   every Secant instance and the two ends of every bracket are factored in
+   one launch sequence each (the second shift on a second copy of the
+   instance), two launch sequences fewer per call; the results are the same.
+   out[count] receives the per-instance
    results; the call returns HK_OK if every instance succeeded (otherwise the
    first failing status).  rep may be NULL.  Synchronises s. */
 hk_status hk_eig_batched(const hk_instance* inst, int count, int digits, int panel, void* dev_ws,

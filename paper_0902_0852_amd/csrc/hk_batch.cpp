@@ -35,7 +35,7 @@ Batch::~Batch() {
   if (s2) (void)hipStreamDestroy(s2);
   for (hipEvent_t ev : events) (void)hipEventDestroy(ev);
   for (hipEvent_t ev : tevents) (void)hipEventDestroy(ev);
-  for (auto m : mats) hk_matrix_destroy(m);
+  for (size_t i = (size_t)borrowed; i < mats.size(); i++) hk_matrix_destroy(mats[i]);
 }
 
 // per-batch layout: descriptors, flags, pivot rows, then one workspace per instance
@@ -281,8 +281,83 @@ SecantRun* secant_new(int N, int K, int h, int tol, int max_eval);
 void secant_delete(SecantRun* r);
 void secant_threads(SecantRun* r, int threads);
 bool secant_next(SecantRun* r, MP& x, int& inertia);
+bool secant_start_pair(SecantRun* r, MP& x0, MP& x1);
 void secant_feed(SecantRun* r, hk_status st, int nneg, int first_bad, std::vector<MP>&& piv);
 bool secant_done(SecantRun* r, MP& lam, hk_status& st, std::string& err);
+
+// the paired batch's own part: descriptors, flags, pivot rows and solve
+// arguments for 2 count instances, then a second workspace per instance (the
+// sizes of the batch's own)
+static bool twin_layout(const hk_instance* inst, int count, std::vector<size_t>& off2, size_t& total2) {
+  std::vector<size_t> off;
+  size_t total;
+  int maxN, ld;
+  if (!batch_layout(inst, count, off, total, maxN, ld)) return false;
+  size_t o = 0;
+  o = al256(o + sizeof(InstDesc) * 2 * count);
+  o = al256(o + sizeof(int32_t) * 16 * 2 * count);
+  o = al256(o + sizeof(int32_t) * (size_t)2 * count * maxN * ld);
+  o = al256(o + sizeof(SweepArgs) * 2 * count);
+  off2.resize(count);
+  for (int i = 0; i < count; i++) {
+    off2[i] = o;
+    o = al256(o + ((i + 1 < count ? off[i + 1] : total) - off[i]));
+  }
+  total2 = o;
+  return true;
+}
+
+size_t twin_bytes(const hk_instance* inst, int count) {
+  std::vector<size_t> off2;
+  size_t total2;
+  if (!inst || count < 1 || !twin_layout(inst, count, off2, total2)) return 0;
+  return total2;
+}
+
+hk_status build_twin(Batch& tw, Batch& bt, const hk_instance* inst, int count, void* ws, size_t ws_bytes,
+                     hipStream_t s) {
+  std::vector<size_t> off2;
+  size_t total2;
+  if (!twin_layout(inst, count, off2, total2)) return HK_EINVAL;
+  if (!ws || ws_bytes < total2) return dfail_b(HK_EINVAL, "paired workspace too small");
+  char* base = (char*)ws;
+  tw.count = 2 * count;
+  tw.maxN = bt.maxN;
+  tw.ld = bt.ld;
+  tw.ddesc = (InstDesc*)base;
+  tw.flags = (int32_t*)(base + al256(sizeof(InstDesc) * 2 * count));
+  tw.piv = (int32_t*)((char*)tw.flags + al256(sizeof(int32_t) * 16 * 2 * count));
+  tw.sargs = (SweepArgs*)((char*)tw.piv + al256(sizeof(int32_t) * (size_t)2 * count * tw.maxN * tw.ld));
+  tw.borrowed = count;
+  for (int i = 0; i < 2 * count; i++) {
+    hk_matrix m = nullptr;
+    if (i < count) {
+      m = bt.mats[i];
+    } else {
+      const int j = i - count;
+      std::vector<MP> X = bt.mats[j]->X;   // the moments are the batch's own
+      hk_status st = build_matrix_impl(inst[j].N, inst[j].beta, inst[j].prec_bits, base + off2[j],
+                                       ws_bytes - off2[j], s, &m, &X);
+      if (st != HK_OK) return st;
+    }
+    tw.mats.push_back(m);
+    InstDesc d = m->desc_host;
+    d.flags = tw.flags + 16 * i;
+    tw.hdesc.push_back(d);
+    tw.B.plans.push_back(&m->P);
+  }
+  tw.B.ddesc = tw.ddesc;
+  tw.B.maxN = tw.maxN;
+  tw.B.ipw = bt.B.ipw;
+  tw.B.mma = bt.B.mma;
+  tw.panel = bt.panel;
+  tw.lookahead = bt.lookahead;
+  tw.timing = bt.timing;
+  hipError_t e = hipMemcpyAsync(tw.ddesc, tw.hdesc.data(), sizeof(InstDesc) * 2 * count, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return dfail_b(HK_EDEVICE, hipGetErrorString(e));
+  return HK_OK;
+}
 
 size_t batch_bytes(const hk_instance* inst, int count) {
   std::vector<size_t> off;
@@ -300,6 +375,11 @@ Schedule tuned_schedule(const hk_instance* inst, int count) { return cached_sche
 extern "C" {
 
 size_t hk_batch_workspace_bytes(const hk_instance* inst, int count) { return batch_bytes(inst, count); }
+
+size_t hk_batch_workspace_bytes_paired(const hk_instance* inst, int count) {
+  const size_t a = batch_bytes(inst, count), b = twin_bytes(inst, count);
+  return a && b ? ((a + 255) & ~(size_t)255) + b : 0;
+}
 
 hk_status hk_eig_batched(const hk_instance* inst, int count, int digits, int panel, void* dev_ws,
                          size_t ws_bytes, hipStream_t s, hk_result* out, hk_batch_report* rep) {
@@ -328,6 +408,18 @@ hk_status hk_eig_batched(const hk_instance* inst, int count, int digits, int pan
     if (fl & HK_FLAG_VECTOR_UPDATE) bt.B.mma = 0;
     bt.timing = (fl & HK_FLAG_TIME_UPDATES) != 0;
   }
+  // with room for a second copy of every instance, the two start points of
+  // the Secant and the two ends of the bracket are factored together
+  Batch tw;
+  bool paired = false;
+  {
+    const size_t own = (batch_bytes(inst, count) + 255) & ~(size_t)255, t2 = twin_bytes(inst, count);
+    if (t2 > 0 && ws_bytes >= own + t2) {
+      st = build_twin(tw, bt, inst, count, (char*)dev_ws + own, ws_bytes - own, s);
+      if (st != HK_OK) return st;
+      paired = true;
+    }
+  }
   auto t1 = std::chrono::steady_clock::now();
   std::vector<SecantRun*> sm(count, nullptr);
   for (int i = 0; i < count; i++) {
@@ -347,6 +439,25 @@ hk_status hk_eig_batched(const hk_instance* inst, int count, int digits, int pan
   const int ith = std::min(nsec, host_threads());
   for (int i = 0; i < count; i++)
     if (sm[i]) secant_threads(sm[i], host_threads() / std::max(1, ith));
+  if (paired && nsec > 0) {
+    // round 0: both start points of every Secant instance in one factorisation
+    std::vector<MP> x2(2 * count), xb(count);
+    std::vector<int> a2(2 * count, 0);
+    for (int i = 0; i < count; i++)
+      if (sm[i] && secant_start_pair(sm[i], x2[i], xb[i])) { x2[count + i] = xb[i]; a2[i] = a2[count + i] = 1; }
+    st = factor_batch(tw, x2, a2, s, ev, true);
+    for (int i = 0; i < count && st == HK_OK; i++) {
+      if (!a2[i]) continue;
+      MP xs;
+      int inert = 0;
+      if (!secant_next(sm[i], xs, inert)) continue;
+      nfact[i]++;
+      secant_feed(sm[i], ev[i].st, ev[i].nneg, ev[i].first_bad, std::move(ev[i].piv));
+      if (!secant_next(sm[i], xs, inert) || cmp(xs, xb[i]) != 0) continue;
+      nfact[i]++;
+      secant_feed(sm[i], ev[count + i].st, ev[count + i].nneg, ev[count + i].first_bad, std::move(ev[count + i].piv));
+    }
+  }
   for (int round = 0; round < 400 && st == HK_OK; round++) {
     parallel_for(count, ith, [&](int i) { act[i] = sm[i] && secant_next(sm[i], x[i], inertia[i]) ? 1 : 0; });
     bool any = false;
@@ -418,8 +529,23 @@ hk_status hk_eig_batched(const hk_instance* inst, int count, int digits, int pan
   for (int i = 0; i < count && st == HK_OK; i++)
     if (done[i]) decimal_bracket(lam[i], bt.mats[i]->P.K, digits, xlo[i], xhi[i], dec[i]);
   std::vector<BEval> elo, ehi;
-  if (st == HK_OK) st = factor_batch(bt, xlo, done, s, elo, false);
-  if (st == HK_OK) st = factor_batch(bt, xhi, done, s, ehi, false);
+  bool anydone = false;
+  for (int i = 0; i < count; i++) anydone |= done[i] != 0;
+  if (paired && anydone && st == HK_OK) {
+    // both ends of every bracket in one factorisation
+    std::vector<MP> x2(2 * count);
+    std::vector<int> a2(2 * count, 0);
+    for (int i = 0; i < count; i++)
+      if (done[i]) { x2[i] = xlo[i]; x2[count + i] = xhi[i]; a2[i] = a2[count + i] = 1; }
+    st = factor_batch(tw, x2, a2, s, ev, false);
+    if (st == HK_OK) {
+      elo.assign(ev.begin(), ev.begin() + count);
+      ehi.assign(ev.begin() + count, ev.end());
+    }
+  } else {
+    if (st == HK_OK) st = factor_batch(bt, xlo, done, s, elo, false);
+    if (st == HK_OK) st = factor_batch(bt, xhi, done, s, ehi, false);
+  }
   hk_status first = st;
   for (int i = 0; i < count; i++) {
     out[i].factorizations = nfact[i] + (done[i] ? 2 : 0);
@@ -440,14 +566,14 @@ hk_status hk_eig_batched(const hk_instance* inst, int count, int digits, int pan
   }
   if (rep) {
     rep->panel = bt.panel;
-    rep->graph_launches = bt.graph_launches;
+    rep->graph_launches = bt.graph_launches + tw.graph_launches;
     rep->t_build_s = std::chrono::duration<double>(t1 - t0).count();
     rep->t_factor_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t1).count();
     rep->t_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    rep->update_launches = bt.n_update;
-    rep->update_ms = bt.update_ms;
-    rep->bulk_launches = bt.n_bulk;
-    rep->bulk_ms = bt.bulk_ms;
+    rep->update_launches = bt.n_update + tw.n_update;
+    rep->update_ms = bt.update_ms + tw.update_ms;
+    rep->bulk_launches = bt.n_bulk + tw.n_bulk;
+    rep->bulk_ms = bt.bulk_ms + tw.bulk_ms;
     int maxW = 0;
     for (const Plan* p : bt.B.plans) maxW = std::max(maxW, p->maxW);
     rep->update_engine = lookahead_mode(bt.lookahead, bt.maxN, maxW) != 2 && mma_width(bt.B, bt.panel) > 0 ? 1 : 0;

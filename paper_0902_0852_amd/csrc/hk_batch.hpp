@@ -13,6 +13,7 @@ struct Batch {
   int count = 0, maxN = 0, ld = 0, panel = 4;
   int lookahead = -1, captured_la = -1;   // -1: chosen by size
   std::vector<hk_matrix> mats;
+  int borrowed = 0;   // mats[0, borrowed) belong to another batch (a paired batch)
   std::vector<InstDesc> hdesc;
   InstDesc* ddesc = nullptr;
   int32_t* flags = nullptr;
@@ -44,6 +45,12 @@ struct BEval { hk_status st; int nneg, first_bad; std::vector<MP> piv; };
 // Lays the batch out in ws (moments on the host, then uploads).
 hk_status build_batch(Batch& bt, const hk_instance* inst, int count, void* ws, size_t ws_bytes,
                       hipStream_t s);
+// The paired batch of bt: 2 count instances, bt's own (borrowed) and a second
+// copy of each with its own workspace in ws (twin_bytes(inst, count) bytes),
+// so that two shifts of every instance are factored by one launch sequence.
+hk_status build_twin(Batch& tw, Batch& bt, const hk_instance* inst, int count, void* ws, size_t ws_bytes,
+                     hipStream_t s);
+size_t twin_bytes(const hk_instance* inst, int count);
 // One batched factorisation: instance i at shift x[i] (K_i fractional bits)
 // when act[i] != 0, replayed from the captured graph; synchronises s.
 hk_status factor_batch(Batch& bt, const std::vector<MP>& x, const std::vector<int>& act, hipStream_t s,

@@ -402,6 +402,13 @@ SecantRun* secant_new(int N, int K, int h, int tol, int max_eval) {
 void secant_delete(SecantRun* r) { delete r; }
 void secant_threads(SecantRun* r, int threads) { r->m.threads = std::max(1, threads); }
 bool secant_next(SecantRun* r, MP& x, int& inertia) { return r->m.next(x, inertia); }
+// both start points while the machine waits for the first
+bool secant_start_pair(SecantRun* r, MP& x0, MP& x1) {
+  if (r->m.phase != SecantMachine::START0) return false;
+  x0 = r->m.xs[0];
+  x1 = r->m.xs[1];
+  return true;
+}
 void secant_feed(SecantRun* r, hk_status st, int nneg, int first_bad, std::vector<MP>&& piv) {
   Eval ev;
   ev.st = st; ev.nneg = nneg; ev.first_bad = first_bad; ev.piv = std::move(piv);

@@ -121,7 +121,7 @@ _lib = None
 EXPORTS = ["hk_workspace_bytes", "hk_build_matrix", "hk_factor", "hk_solve", "hk_smallest_eig",
            "hk_matrix_destroy", "hk_last_error", "hk_matrix_info", "hk_set_panel", "hk_set_timing",
            "hk_factor_export", "hk_factor_limb_macs", "hk_vec_import", "hk_vec_export", "hk_set_lookahead",
-           "hk_batch_workspace_bytes", "hk_eig_batched", "hk_autotune",
+           "hk_batch_workspace_bytes", "hk_batch_workspace_bytes_paired", "hk_eig_batched", "hk_autotune",
            "hk_mlp_nparams", "hk_mlp_cache_floats", "hk_mlp_forward", "hk_mlp_backward", "hk_mlp_mse",
            "hk_mlp_adam_step", "hk_mlp_propose", "hk_bracket_batched", "hk_learned_workspace_bytes",
            "hk_eig_learned", "hk_moments_host", "hk_batch_create", "hk_batch_set_schedule",
@@ -178,6 +178,8 @@ def lib():
         L.hk_vec_export.argtypes = [P, P, I, P, P, P, I64, P]
         L.hk_batch_workspace_bytes.restype = SZ
         L.hk_batch_workspace_bytes.argtypes = [P, I]
+        L.hk_batch_workspace_bytes_paired.restype = SZ
+        L.hk_batch_workspace_bytes_paired.argtypes = [P, I]
         L.hk_eig_batched.restype = I
         L.hk_eig_batched.argtypes = [P, I, I, I, P, SZ, P, P, ctypes.POINTER(BatchReport)]
         L.hk_batch_create.restype = I
@@ -499,19 +501,25 @@ def _instances(insts, method=HK_SECANT):
     return arr
 
 
-def batch_workspace_bytes(insts):
+def batch_workspace_bytes(insts, paired=False):
+    """Device bytes of a batch; paired: the size with which eig_batched
+    factors the Secant's two start points and the bracket's two ends
+    together."""
     arr = _instances(insts)
-    return lib().hk_batch_workspace_bytes(ctypes.cast(arr, ctypes.c_void_p), len(insts))
+    f = lib().hk_batch_workspace_bytes_paired if paired else lib().hk_batch_workspace_bytes
+    return f(ctypes.cast(arr, ctypes.c_void_p), len(insts))
 
 
-def eig_batched(insts, digits=45, panel=0, stream=None, ws=None, method=HK_SECANT, flags=0):
+def eig_batched(insts, digits=45, panel=0, stream=None, ws=None, method=HK_SECANT, flags=0, paired=True):
     """lambda_1 of every (N, beta, K) instance in one batch (all by `method`,
     inverse iteration from 0 for HK_INVERSE); returns (list of (status,
-    decimal, verified, factorizations), report dict)."""
+    decimal, verified, factorizations), report dict).  Without ws, the
+    workspace is allocated here, of the paired size unless paired=False."""
     import torch
     L = lib()
     arr = _instances(insts, method | flags)
-    nbytes = L.hk_batch_workspace_bytes(ctypes.cast(arr, ctypes.c_void_p), len(insts))
+    f = L.hk_batch_workspace_bytes_paired if paired else L.hk_batch_workspace_bytes
+    nbytes = f(ctypes.cast(arr, ctypes.c_void_p), len(insts))
     if nbytes == 0:
         raise HKError(1, L.hk_last_error().decode())
     ws = ws if ws is not None else torch.empty(nbytes, dtype=torch.uint8, device="cuda")

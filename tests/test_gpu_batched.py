@@ -41,6 +41,24 @@ def test_batched_equals_single_instance(hk):
         assert st == 0 and d1 == dec
 
 
+def test_paired_factorisations_change_nothing(hk):
+    # with the paired workspace the Secant's start points and the bracket's
+    # ends go two to a launch sequence: two sequences fewer, identical results
+    # (a Secant and an inverse-iteration mix, uneven sizes, look-ahead 1)
+    insts = [(40, (1, 1), 640), (23, (7, 4), 512), (57, (3, 2), 768)]
+    log("paired against unpaired batched factorisations, %d instances" % len(insts))
+    for method in (hk.HK_SECANT, hk.HK_INVERSE):
+        r1, d1 = hk.eig_batched(insts, digits=45, panel=3, method=method,
+                                flags=hk.HK_FLAG_LOOKAHEAD_ON, paired=True)
+        r0, d0 = hk.eig_batched(insts, digits=45, panel=3, method=method,
+                                flags=hk.HK_FLAG_LOOKAHEAD_ON, paired=False)
+        assert r1 == r0, (method, r1, r0)
+        assert all(st == 0 and ver == 1 for st, _, ver, _ in r1)
+        fewer = 2 if method == hk.HK_SECANT else 1
+        assert d1["graph_launches"] == d0["graph_launches"] - fewer, (method, d1["graph_launches"],
+                                                                      d0["graph_launches"])
+
+
 def test_autotune_writes_cache(hk, tmp_path):
     insts = [(24, (1, 1), 384), (30, (7, 4), 512)]
     path = str(tmp_path / "tune.txt")
