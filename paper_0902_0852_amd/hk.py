@@ -514,12 +514,16 @@ def eig_batched(insts, digits=45, panel=0, stream=None, ws=None, method=HK_SECAN
     """lambda_1 of every (N, beta, K) instance in one batch (all by `method`,
     inverse iteration from 0 for HK_INVERSE); returns (list of (status,
     decimal, verified, factorizations), report dict).  Without ws, the
-    workspace is allocated here, of the paired size unless paired=False."""
+    workspace is allocated here, of the paired size unless paired=False or
+    that size would take more than half of the device's free memory."""
     import torch
     L = lib()
     arr = _instances(insts, method | flags)
-    f = L.hk_batch_workspace_bytes_paired if paired else L.hk_batch_workspace_bytes
-    nbytes = f(ctypes.cast(arr, ctypes.c_void_p), len(insts))
+    nbytes = L.hk_batch_workspace_bytes(ctypes.cast(arr, ctypes.c_void_p), len(insts))
+    if paired and ws is None and nbytes:
+        nb2 = L.hk_batch_workspace_bytes_paired(ctypes.cast(arr, ctypes.c_void_p), len(insts))
+        if nb2 <= torch.cuda.mem_get_info()[0] // 2:
+            nbytes = nb2
     if nbytes == 0:
         raise HKError(1, L.hk_last_error().decode())
     ws = ws if ws is not None else torch.empty(nbytes, dtype=torch.uint8, device="cuda")
